@@ -1,0 +1,204 @@
+/*
+ * rd.h -- C ABI of the MI355X sparse-block reaction-diffusion library (librd.so).
+ *
+ * The library advances reaction-diffusion fields by explicit FTCS time stepping
+ * on a sparse block grid fitted to a porous geometry: Stark & Sbalzarini, "An
+ * open-source pipeline for solving continuous reaction-diffusion models in
+ * image-based geometries of porous media" (arXiv 2304.11165).
+ *
+ *   PDE        du/dt = div(D grad u) + f(u)               section "Methods", eq. reaction_diffusion
+ *   scheme     forward Euler + centred 7-point differences section "Discretization and numerical methods"
+ *   walls      no-flux by the mirror rule inside the stencil (same section; appendix "Code examples")
+ *   storage    only blocks of B^3 voxels that hold an active voxel are stored
+ *              (section "Parallel implementation using OpenFPM")
+ *
+ * Per free active voxel p and species a, one step computes
+ *   c'_a(p) = c_a(p) + alpha_a * sum_{q in N6(p), q active} (c_a(q) - c_a(p))
+ *             - (beta_a + gamma_a * n_wall(p)) * c_a(p) + sum_b K_ab * c_b(p)
+ * with alpha_a = D_a dt/dx^2, gamma_a = k_R,a dt/dx (Robin wall uptake per wall
+ * face), beta_a = dt * (sum of first-order rates out of a), K_ab = dt * (rate of
+ * b -> a).  n_wall(p) counts in-box face neighbours that are not active; box
+ * faces are no-flux and not walls.  Dirichlet voxels (the active voxels of a box
+ * face plane flagged for a species) hold their value and act as active
+ * neighbours.
+ *
+ * Conventions
+ *   - Volumes are C-ordered (nz, ny, nx), x fastest.  Voxel (i,j,k) sits at
+ *     (i,j,k)*dx.  Face ids: 0:-x 1:+x 2:-y 3:+y 4:-z 5:+z.
+ *   - Host pointers are read only during the call.  Device pointers are
+ *     caller-owned (for example torch tensors); the library never frees them.
+ *   - All device work of a simulation is enqueued on the stream given to
+ *     rd_sim_bind (a hipStream_t passed as void*; NULL = the null stream).
+ *     rd_sim_step is asynchronous; functions that return host values
+ *     synchronise that stream.
+ *   - Every function returns rd_status; no C++ exception crosses the ABI.  After
+ *     a failure rd_last_error() gives a thread-local message.
+ *   - A handle must not be used from two threads at once.
+ */
+#ifndef RD_H
+#define RD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RD_OK = 0,
+    RD_ERR_ARG = 1,               /* bad argument value (id, face, pointer, ...) */
+    RD_ERR_SHAPE = 2,             /* bad volume shape or block edge */
+    RD_ERR_INCONSISTENT_SDF = 3,  /* sign(sdf) > 0 disagrees with image != 0 */
+    RD_ERR_UNSTABLE_DT = 4,       /* dt above the explicit stability bound */
+    RD_ERR_WORKSPACE = 5,         /* workspace missing or too small */
+    RD_ERR_HIP = 6,               /* a HIP runtime call failed */
+    RD_ERR_NONFINITE = 7,         /* a reduction met a NaN or an infinity */
+    RD_ERR_NOT_CONVERGED = 8,     /* iteration limit reached before the tolerance */
+    RD_ERR_STATE = 9              /* call out of order (e.g. step before bind) */
+} rd_status;
+
+typedef enum { RD_FP32 = 0, RD_BF16 = 1, RD_FP16 = 2 } rd_storage;
+
+/* Workspace features (rd_sim_workspace_bytes). */
+#define RD_WS_SOLVER 1u   /* vectors for rd_sim_steady_state */
+#define RD_WS_ADJOINT 2u  /* adjoint vectors + checkpoint slots for rd_sim_adjoint */
+
+typedef struct rd_geometry rd_geometry;
+typedef struct rd_sim rd_sim;
+typedef struct rd_batch rd_batch;
+
+const char *rd_status_string(rd_status s);
+const char *rd_last_error(void);
+
+/* ---- geometry (host only; no GPU needed) --------------------------------- */
+
+/* Build the active-block index of a voxel image.
+ *   image      host uint8 (nz,ny,nx); nonzero = active voxel (inside Omega, phi > 0)
+ *   sdf        host float (nz,ny,nx) signed distance (phi > 0 inside), or NULL.  If
+ *              given, (sdf > 0) must equal (image != 0) everywhere, else
+ *              RD_ERR_INCONSISTENT_SDF (section "Level-set method", eq. SDF; the
+ *              sparse grid holds the points with phi > 0, section "Generating
+ *              real-world geometries").
+ *   dx         grid spacing (> 0)
+ *   block_edge 4 or 8; a block is stored iff it holds an active voxel.
+ * Blocks are listed by ascending linear id l = (bz*NBy + by)*NBx + bx,
+ * NB = ceil(n / B); slots of a block past the box edge are inactive. */
+rd_status rd_geometry_create(const uint8_t *image, const float *sdf, int64_t nx, int64_t ny,
+                             int64_t nz, double dx, int block_edge, rd_geometry **out);
+/* Counts: active voxels, active blocks, porosity = active / (nx ny nz),
+ * fill = active voxels / (active blocks * B^3).  Any output may be NULL. */
+rd_status rd_geometry_stats(const rd_geometry *g, int64_t *n_active_vox, int64_t *n_active_blocks,
+                            double *porosity, double *fill);
+/* Copy the index out: block_id int64[nb] (linear ids, ascending) and nbr
+ * int32[nb*6] (list index of the face neighbour in order -x,+x,-y,+y,-z,+z, or -1
+ * if outside the box or not stored).  Either may be NULL. */
+rd_status rd_geometry_export_index(const rd_geometry *g, int64_t *block_id, int32_t *nbr);
+/* Copy the active bitmasks out: uint64[nb * ceil(B^3/64)]; slot (lz*B+ly)*B+lx is
+ * bit (slot % 64) of word slot/64 of its block. */
+rd_status rd_geometry_export_masks(const rd_geometry *g, uint64_t *masks);
+void rd_geometry_destroy(rd_geometry *g);
+
+/* ---- simulation ------------------------------------------------------------ */
+
+/* A simulation on geometry g (g must outlive the simulation).  storage selects the
+ * field element type in HBM; arithmetic is FP32 and reductions FP64 in every case. */
+rd_status rd_sim_create(const rd_geometry *g, rd_storage storage, rd_sim **out);
+/* Add a species with diffusion coefficient D >= 0 (at most 4 species); *id receives
+ * its index (0, 1, ...).  Must precede rd_sim_bind. */
+rd_status rd_sim_add_species(rd_sim *sim, double D, int *id);
+/* First-order reaction from -> to at rate >= 0 (to = -1: decay), evaluated at the
+ * old time level (law of mass action, section "Methods"). */
+rd_status rd_sim_add_reaction(rd_sim *sim, int from, int to, double rate);
+/* Wall uptake of a species: flux k * c out through every wall face (k >= 0); the
+ * per-face form of the surface-restricted sink of section "Application example 2". */
+rd_status rd_sim_set_robin(rd_sim *sim, int species, double k);
+/* Hold the active voxels of box face `face` at `value` for a species. */
+rd_status rd_sim_set_dirichlet(rd_sim *sim, int species, int face, double value);
+/* Remove every Dirichlet face of a species. */
+rd_status rd_sim_clear_dirichlet(rd_sim *sim, int species);
+/* Launch shape: steps fused per graph node group (>= 1) and whether rd_sim_step
+ * replays a captured hipGraph (1) or launches directly (0).  Results are bitwise
+ * identical for every choice. */
+rd_status rd_sim_set_launch(rd_sim *sim, int graph_steps, int use_graph);
+
+/* Rounding of BF16 / FP16 stores (no effect with FP32 storage).  stochastic = 0:
+ * round to nearest even (default).  stochastic = 1: round up with probability equal
+ * to the fraction of the storage spacing, drawn from a counter-based hash of (slot,
+ * species, step, seed); unbiased, so small increments are not lost near fronts and
+ * steady states.  Results stay deterministic for a given seed. */
+rd_status rd_sim_set_rounding(rd_sim *sim, int stochastic, uint64_t seed);
+/* Device bytes the caller must provide to rd_sim_bind for the given features
+ * (bitwise OR of RD_WS_*) and, with RD_WS_ADJOINT, checkpoint_slots stored states. */
+rd_status rd_sim_workspace_bytes(const rd_sim *sim, uint32_t features, int64_t checkpoint_slots,
+                                 size_t *bytes);
+/* Attach a caller-owned device workspace (>= the size above, 256-byte aligned) and
+ * the stream all work goes to.  Uploads the block index, zeroes the fields and
+ * synchronises.  May be called again to move to another workspace (fields reset). */
+rd_status rd_sim_bind(rd_sim *sim, void *dev_workspace, size_t bytes, uint32_t features,
+                      int64_t checkpoint_slots, void *stream);
+/* Scatter a dense device field float32 (nz,ny,nx) into species s; inactive voxels are
+ * ignored and Dirichlet voxels take their held value. */
+rd_status rd_sim_set_field(rd_sim *sim, int species, const float *dev_dense);
+/* Gather species s into a dense device float32 (nz,ny,nx); inactive voxels -> 0. */
+rd_status rd_sim_get_field(const rd_sim *sim, int species, float *dev_dense);
+/* Advance n_steps FTCS steps of size dt (asynchronous).  RD_ERR_UNSTABLE_DT if
+ * dt > 2 / lambda_max with the Gershgorin bound
+ * lambda_max = 12 D_max/dx^2 + max_a(total rate out of a) + 6 max_a(k_R,a)/dx
+ * (the 3-D form of the paper's eq. diffusion_stability_condition). */
+rd_status rd_sim_step(rd_sim *sim, double dt, int64_t n_steps);
+/* Steps taken since bind / the last set_field. */
+rd_status rd_sim_steps_taken(const rd_sim *sim, int64_t *n);
+/* FP64 balance terms of species s for the current field (synchronises):
+ *   mass   = sum over free voxels of c dx^3
+ *   inflow = sum over Dirichlet voxels q and free active neighbours p of D (c_q - c_p) dx
+ *   uptake = sum over free voxels of k_R n_wall c dx^2
+ * With them one step satisfies M' - M = dt (inflow - uptake + reactions).
+ * RD_ERR_NONFINITE if the field holds a NaN or infinity.  Outputs may be NULL. */
+rd_status rd_sim_reduce(rd_sim *sim, int species, double *mass, double *dirichlet_inflow,
+                        double *robin_uptake);
+/* All balance terms: out[0] mass, out[1..6] inflow per face, out[7] uptake,
+ * out[8] reaction total (sum over free voxels of the reaction rate, times dx^3). */
+rd_status rd_sim_balance(rd_sim *sim, int species, double out[9]);
+
+/* Steady state of species 0 (single-species, no reactions or Robin) with a unit
+ * drop along `axis` (Dirichlet 1 on the low face plane, 0 on the high one,
+ * no-flux elsewhere), solved by conjugate gradients with the stencil as operator
+ * and FP64 dot products.  Stops at rel. residual <= rel_tol, at stagnation (no 10%
+ * decrease of the best residual over 20 checks of 50 iterations) or at max_iters.
+ * tau = psi D A / (Q L): psi active fraction, A box cross-section, L = (n-1) dx,
+ * Q the inflow at the inlet plane (eq. tortuosity, tau = D_f / D_eff); +inf if
+ * Q <= 0.  Needs RD_WS_SOLVER.  Leaves the steady field in species 0. */
+rd_status rd_sim_steady_state(rd_sim *sim, int axis, double rel_tol, int64_t max_iters,
+                              double *tau, double *rel_residual, int64_t *iters);
+
+/* Gradient of L = 1/2 sum_free (c^N - c*)^2 for a single-species diffusion-decay
+ * simulation, run from the current field for n_steps of size dt, with respect to
+ * D and the decay rate.  dev_target: dense float32 (nz,ny,nx) c*.  States are
+ * checkpointed every `checkpoint_every` steps and recomputed per segment (needs
+ * RD_WS_ADJOINT with checkpoint_slots >= ceil(n_steps/checkpoint_every) + 1 +
+ * checkpoint_every).  On return species 0 holds c^N.  Outputs: loss, dL/dD, dL/dk. */
+rd_status rd_sim_adjoint(rd_sim *sim, const float *dev_target, int64_t n_steps, double dt,
+                         int checkpoint_every, double *loss, double *dL_dD, double *dL_drate);
+void rd_sim_destroy(rd_sim *sim);
+
+/* ---- batches of geometries ------------------------------------------------- */
+
+/* Many geometries stepped together: their block lists are concatenated and one
+ * launch per step covers every geometry.  Single species, D = 1, pure diffusion;
+ * used for per-geometry tortuosity.  The geometries must outlive the batch. */
+rd_status rd_batch_create(const rd_geometry *const *geoms, int n, rd_storage storage,
+                          rd_batch **out);
+rd_status rd_batch_workspace_bytes(const rd_batch *b, size_t *bytes);
+rd_status rd_batch_bind(rd_batch *b, void *dev_workspace, size_t bytes, void *stream);
+/* Per-geometry tortuosity along `axis` by batched conjugate gradients (one launch
+ * per kernel stage for the whole batch); converged geometries stop updating.
+ * tau[n], rel_residual[n], iters[n] are host arrays (any may be NULL). */
+rd_status rd_batch_tortuosity(rd_batch *b, int axis, double rel_tol, int64_t max_iters,
+                              double *tau, double *rel_residual, int64_t *iters);
+void rd_batch_destroy(rd_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RD_H */

@@ -1,0 +1,609 @@
+// rd_api.cpp -- the C ABI: validation, workspace layout, launch driver, reductions.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+
+#include "rd_host.h"
+#include "rd_sim.h"
+
+static thread_local std::string g_last_error;
+
+rd_status rd_fail(rd_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+#define HIPCHK(expr)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return rd_fail(RD_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+#define LAUNCHCHK(expr)                                                                      \
+    do {                                                                                     \
+        int e_ = (expr);                                                                     \
+        if (e_ != 0)                                                                         \
+            return rd_fail(RD_ERR_HIP, std::string(#expr) + ": " +                           \
+                                           hipGetErrorString((hipError_t)e_));               \
+    } while (0)
+
+extern "C" const char *rd_status_string(rd_status s)
+{
+    switch (s) {
+    case RD_OK: return "ok";
+    case RD_ERR_ARG: return "bad argument";
+    case RD_ERR_SHAPE: return "bad shape";
+    case RD_ERR_INCONSISTENT_SDF: return "sdf sign disagrees with image";
+    case RD_ERR_UNSTABLE_DT: return "time step above the stability bound";
+    case RD_ERR_WORKSPACE: return "workspace missing or too small";
+    case RD_ERR_HIP: return "HIP runtime error";
+    case RD_ERR_NONFINITE: return "non-finite value in field";
+    case RD_ERR_NOT_CONVERGED: return "not converged";
+    case RD_ERR_STATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+extern "C" const char *rd_last_error(void) { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+
+extern "C" rd_status rd_geometry_create(const uint8_t *image, const float *sdf, int64_t nx,
+                                        int64_t ny, int64_t nz, double dx, int block_edge,
+                                        rd_geometry **out)
+{
+    if (!out) return rd_fail(RD_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!image) return rd_fail(RD_ERR_ARG, "image is NULL");
+    if (nx <= 0 || ny <= 0 || nz <= 0) return rd_fail(RD_ERR_SHAPE, "non-positive extent");
+    if (nx > 65535L * 8 || ny > 65535L * 8 || nz > 65535L * 8 || nx * ny > ((int64_t)1 << 40))
+        return rd_fail(RD_ERR_SHAPE, "volume too large");
+    if (nx >= INT32_MAX || ny >= INT32_MAX || nz >= INT32_MAX)
+        return rd_fail(RD_ERR_SHAPE, "extent does not fit int32");
+    if (block_edge != 4 && block_edge != 8) return rd_fail(RD_ERR_SHAPE, "block_edge must be 4 or 8");
+    if (!(dx > 0.0) || !isfinite(dx)) return rd_fail(RD_ERR_ARG, "dx must be positive");
+    const int64_t N = nx * ny * nz;
+    if (sdf) {
+        for (int64_t i = 0; i < N; ++i) {
+            const bool in = image[i] != 0;
+            if ((sdf[i] > 0.0f) != in) {
+                const int64_t x = i % nx, y = (i / nx) % ny, z = i / (nx * ny);
+                return rd_fail(RD_ERR_INCONSISTENT_SDF,
+                               "sdf > 0 disagrees with image at (x,y,z) = (" + std::to_string(x) +
+                                   "," + std::to_string(y) + "," + std::to_string(z) + ")");
+            }
+        }
+    }
+    rd_geometry *g = new (std::nothrow) rd_geometry();
+    if (!g) return rd_fail(RD_ERR_ARG, "out of host memory");
+    g->dx = dx;
+    rd_status s;
+    try {
+        s = rd_geometry_build(image, nx, ny, nz, block_edge, g);
+    } catch (const std::bad_alloc &) {
+        s = rd_fail(RD_ERR_ARG, "out of host memory");
+    }
+    if (s != RD_OK) {
+        delete g;
+        return s;
+    }
+    *out = g;
+    return RD_OK;
+}
+
+extern "C" rd_status rd_geometry_stats(const rd_geometry *g, int64_t *n_active_vox,
+                                       int64_t *n_active_blocks, double *porosity, double *fill)
+{
+    if (!g) return rd_fail(RD_ERR_ARG, "geometry is NULL");
+    const int64_t nb = g->nb();
+    const double slots = (double)nb * g->B * g->B * g->B;
+    if (n_active_vox) *n_active_vox = g->n_active;
+    if (n_active_blocks) *n_active_blocks = nb;
+    if (porosity) *porosity = (double)g->n_active / ((double)g->nx * g->ny * g->nz);
+    if (fill) *fill = nb ? (double)g->n_active / slots : 0.0;
+    return RD_OK;
+}
+
+extern "C" rd_status rd_geometry_export_index(const rd_geometry *g, int64_t *block_id, int32_t *nbr)
+{
+    if (!g) return rd_fail(RD_ERR_ARG, "geometry is NULL");
+    const int64_t nb = g->nb();
+    if (block_id) memcpy(block_id, g->block_id.data(), sizeof(int64_t) * nb);
+    if (nbr)
+        for (int64_t b = 0; b < nb; ++b)
+            for (int f = 0; f < 6; ++f) nbr[b * 6 + f] = g->info[b].nbr[f];
+    return RD_OK;
+}
+
+extern "C" rd_status rd_geometry_export_masks(const rd_geometry *g, uint64_t *masks)
+{
+    if (!g || !masks) return rd_fail(RD_ERR_ARG, "NULL argument");
+    const int own = g->B == 8 ? 8 : 1, MW = mask_words(g->B);
+    for (int64_t b = 0; b < g->nb(); ++b)
+        for (int w = 0; w < own; ++w) masks[b * own + w] = g->mask[b * MW + w];
+    return RD_OK;
+}
+
+extern "C" void rd_geometry_destroy(rd_geometry *g) { delete g; }
+
+// ---------------------------------------------------------------------------
+// simulation set-up
+// ---------------------------------------------------------------------------
+
+extern "C" rd_status rd_sim_create(const rd_geometry *g, rd_storage storage, rd_sim **out)
+{
+    if (!out) return rd_fail(RD_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!g) return rd_fail(RD_ERR_ARG, "geometry is NULL");
+    if (storage != RD_FP32 && storage != RD_BF16 && storage != RD_FP16)
+        return rd_fail(RD_ERR_ARG, "unknown storage type");
+    rd_sim *s = new (std::nothrow) rd_sim();
+    if (!s) return rd_fail(RD_ERR_ARG, "out of host memory");
+    s->g = g;
+    s->storage = storage;
+    *out = s;
+    return RD_OK;
+}
+
+extern "C" rd_status rd_sim_add_species(rd_sim *sim, double D, int *id)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    if (sim->ws) return rd_fail(RD_ERR_STATE, "species must be added before rd_sim_bind");
+    if (sim->S >= RD_MAX_SPECIES) return rd_fail(RD_ERR_ARG, "at most 4 species");
+    if (!(D >= 0.0) || !isfinite(D)) return rd_fail(RD_ERR_ARG, "D must be finite and >= 0");
+    sim->D[sim->S] = D;
+    if (id) *id = sim->S;
+    sim->S++;
+    return RD_OK;
+}
+
+extern "C" rd_status rd_sim_add_reaction(rd_sim *sim, int from, int to, double rate)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    if (from < 0 || from >= sim->S) return rd_fail(RD_ERR_ARG, "bad 'from' species");
+    if (to < -1 || to >= sim->S || to == from) return rd_fail(RD_ERR_ARG, "bad 'to' species");
+    if (!(rate >= 0.0) || !isfinite(rate)) return rd_fail(RD_ERR_ARG, "rate must be finite and >= 0");
+    sim->reactions.push_back({from, to, rate});
+    sim->invalidate_graphs();
+    return RD_OK;
+}
+
+extern "C" rd_status rd_sim_set_robin(rd_sim *sim, int species, double k)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    if (species < 0 || species >= sim->S) return rd_fail(RD_ERR_ARG, "bad species");
+    if (!(k >= 0.0) || !isfinite(k)) return rd_fail(RD_ERR_ARG, "k must be finite and >= 0");
+    sim->robin[species] = k;
+    sim->invalidate_graphs();
+    return RD_OK;
+}
+
+extern "C" rd_status rd_sim_set_dirichlet(rd_sim *sim, int species, int face, double value)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    if (species < 0 || species >= sim->S) return rd_fail(RD_ERR_ARG, "bad species");
+    if (face < 0 || face > 5) return rd_fail(RD_ERR_ARG, "face must be 0..5");
+    if (!isfinite(value)) return rd_fail(RD_ERR_ARG, "value must be finite");
+    sim->dir[species] |= 1u << face;
+    sim->dirval[species][face] = value;
+    sim->invalidate_graphs();
+    if (sim->ws) return sim->apply_dirichlet(species);
+    return RD_OK;
+}
+
+extern "C" rd_status rd_sim_clear_dirichlet(rd_sim *sim, int species)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    if (species < 0 || species >= sim->S) return rd_fail(RD_ERR_ARG, "bad species");
+    sim->dir[species] = 0;
+    sim->invalidate_graphs();
+    return RD_OK;
+}
+
+extern "C" rd_status rd_sim_set_launch(rd_sim *sim, int graph_steps, int use_graph)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    if (graph_steps < 1 || graph_steps > 4096) return rd_fail(RD_ERR_ARG, "graph_steps in 1..4096");
+    sim->graph_steps = graph_steps;
+    sim->use_graph = use_graph != 0;
+    sim->invalidate_graphs();
+    return RD_OK;
+}
+
+extern "C" rd_status rd_sim_set_rounding(rd_sim *sim, int stochastic, uint64_t seed)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    sim->sround = stochastic != 0;
+    sim->seed = (uint32_t)(seed ^ (seed >> 32));
+    sim->invalidate_graphs();
+    return RD_OK;
+}
+
+extern "C" rd_status rd_sim_workspace_bytes(const rd_sim *sim, uint32_t features,
+                                            int64_t checkpoint_slots, size_t *bytes)
+{
+    if (!sim || !bytes) return rd_fail(RD_ERR_ARG, "NULL argument");
+    if (sim->S < 1) return rd_fail(RD_ERR_STATE, "add a species first");
+    if (checkpoint_slots < 0) return rd_fail(RD_ERR_ARG, "checkpoint_slots < 0");
+    *bytes = sim_layout(*sim, features, checkpoint_slots).total;
+    return RD_OK;
+}
+
+extern "C" rd_status rd_sim_bind(rd_sim *sim, void *dev_workspace, size_t bytes, uint32_t features,
+                                 int64_t checkpoint_slots, void *stream)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    if (sim->S < 1) return rd_fail(RD_ERR_STATE, "add a species first");
+    if (!dev_workspace) return rd_fail(RD_ERR_WORKSPACE, "workspace is NULL");
+    if (((uintptr_t)dev_workspace) % 256) return rd_fail(RD_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    if (checkpoint_slots < 0) return rd_fail(RD_ERR_ARG, "checkpoint_slots < 0");
+    const SimLayout L = sim_layout(*sim, features, checkpoint_slots);
+    if (bytes < L.total)
+        return rd_fail(RD_ERR_WORKSPACE, "workspace has " + std::to_string(bytes) + " bytes, needs " +
+                                             std::to_string(L.total));
+    sim->invalidate_graphs();
+    sim->ws = (char *)dev_workspace;
+    sim->ws_bytes = bytes;
+    sim->L = L;
+    sim->features = features;
+    sim->cp_slots = checkpoint_slots;
+    sim->stream = (hipStream_t)stream;
+    return sim->upload();
+}
+
+// ---------------------------------------------------------------------------
+// rd_sim methods
+// ---------------------------------------------------------------------------
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+SimLayout sim_layout(const rd_sim &s, uint32_t features, int64_t cp_slots)
+{
+    SimLayout L{};
+    const rd_geometry &g = *s.g;
+    const int64_t nb = g.nb();
+    const int64_t NS = (int64_t)g.B * g.B * g.B;
+    const size_t es = s.storage == RD_FP32 ? 4 : 2;
+    size_t off = 0;
+    L.info = off; off = align256(off + sizeof(BlockInfo) * (size_t)std::max<int64_t>(nb, 1));
+    L.mask = off; off = align256(off + 8 * (size_t)mask_words(g.B) * (size_t)std::max<int64_t>(nb, 1));
+    L.geom = off; off = align256(off + sizeof(GeomInfo));
+    L.field_elems = nb * NS;
+    for (int p = 0; p < 2; ++p) {
+        L.field[p] = off;
+        off = align256(off + es * (size_t)L.field_elems * s.S);
+    }
+    L.nparts = (int)std::max<int64_t>(1, nb);  // one partial row per workgroup (upper bound)
+    L.part = off; off = align256(off + sizeof(double) * RD_NRED * (size_t)L.nparts);
+    L.res = off; off = align256(off + sizeof(double) * 64);
+    if (features & RD_WS_SOLVER) {
+        for (int v = 0; v < 3; ++v) {
+            L.solver[v] = off;
+            off = align256(off + es * (size_t)L.field_elems);
+        }
+        L.scal = off; off = align256(off + sizeof(double) * 64);
+    }
+    if (features & RD_WS_ADJOINT) {
+        for (int v = 0; v < 2; ++v) {
+            L.lam[v] = off;
+            off = align256(off + 4 * (size_t)L.field_elems);
+        }
+        L.target = off; off = align256(off + 4 * (size_t)L.field_elems);
+        L.cp = off;
+        L.cp_stride = align256(es * (size_t)L.field_elems);
+        off += L.cp_stride * (size_t)cp_slots;
+    }
+    L.total = off;
+    return L;
+}
+
+void rd_sim::invalidate_graphs()
+{
+    for (auto &e : graphs) hipGraphExecDestroy(e.exec);
+    graphs.clear();
+}
+
+rd_sim::~rd_sim()
+{
+    invalidate_graphs();
+    if (cap_stream) hipStreamDestroy(cap_stream);
+    if (host_res) hipHostFree(host_res);
+}
+
+rd_status rd_sim::upload()
+{
+    const rd_geometry &G = *g;
+    const int64_t nb = G.nb();
+    HIPCHK(hipMemcpyAsync(ws + L.info, G.info.data(), sizeof(BlockInfo) * nb, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(ws + L.mask, G.mask.data(), 8 * mask_words(G.B) * nb, hipMemcpyHostToDevice, stream));
+    GeomInfo gi{(int32_t)G.nx, (int32_t)G.ny, (int32_t)G.nz, 0};
+    geom_host = gi;
+    HIPCHK(hipMemcpyAsync(ws + L.geom, &geom_host, sizeof(GeomInfo), hipMemcpyHostToDevice, stream));
+    const size_t es = storage == RD_FP32 ? 4 : 2;
+    for (int p = 0; p < 2; ++p)
+        LAUNCHCHK(rd_launch_fill_u32(ws + L.field[p], 0u, (int64_t)(es * L.field_elems * S / 4), stream));
+    LAUNCHCHK(rd_launch_fill_u32(ws + L.res, 0u, 64 * 2, stream));  // results + step counter
+    if (!host_res) HIPCHK(hipHostMalloc((void **)&host_res, 64 * sizeof(double), hipHostMallocDefault));
+    cur = 0;
+    steps_taken = 0;
+    for (int s = 0; s < S; ++s) {
+        rd_status st = apply_dirichlet(s);
+        if (st != RD_OK) return st;
+    }
+    HIPCHK(hipStreamSynchronize(stream));
+    return RD_OK;
+}
+
+// Write the held Dirichlet values into the current buffer of species s (a scatter
+// of the current field through a temporary is avoided: a dedicated pass over the
+// blocks sets only the face voxels).
+rd_status rd_sim::apply_dirichlet(int s)
+{
+    if (!ws || !dir[s]) return RD_OK;
+    float dv[6];
+    for (int f = 0; f < 6; ++f) dv[f] = (float)dirval[s][f];
+    LAUNCHCHK(rd_launch_set_dirichlet(storage, g->B, (const BlockInfo *)(ws + L.info),
+                                      (const uint64_t *)(ws + L.mask), (const GeomInfo *)(ws + L.geom),
+                                      (int)g->nb(), field_ptr(cur, s), dir[s], dv, stream));
+    return RD_OK;
+}
+
+void *rd_sim::field_ptr(int buf, int s) const
+{
+    const size_t es = storage == RD_FP32 ? 4 : 2;
+    return ws + L.field[buf] + es * (size_t)L.field_elems * s;
+}
+
+StepArgs rd_sim::step_args(double dt, int in_buf) const
+{
+    StepArgs a{};
+    a.info = (const BlockInfo *)(ws + L.info);
+    a.mask = (const uint64_t *)(ws + L.mask);
+    a.geom = (const GeomInfo *)(ws + L.geom);
+    a.cin = field_ptr(in_buf, 0);
+    a.cout = field_ptr(1 - in_buf, 0);
+    a.sstride = L.field_elems;
+    a.nb = (int32_t)g->nb();
+    a.S = S;
+    a.xcd_chunk = 0;
+    const double dx = g->dx;
+    for (int s = 0; s < S; ++s) {
+        SpeciesCoef &c = a.coef[s];
+        double out_rate = 0.0;
+        for (const Reaction &r : reactions)
+            if (r.from == s) out_rate += r.rate;
+        c.alpha = (float)(D[s] * dt / (dx * dx));
+        c.beta = (float)(dt * out_rate);
+        c.gamma = (float)(robin[s] * dt / dx);
+        c.dir = dir[s];
+        for (int b = 0; b < RD_MAX_SPECIES; ++b) c.K[b] = 0.0f;
+        for (const Reaction &r : reactions)
+            if (r.to == s) c.K[r.from] = (float)((double)c.K[r.from] + dt * r.rate);
+    }
+    return a;
+}
+
+double rd_sim::lambda_max() const
+{
+    const double dx = g->dx;
+    double dmax = 0.0, rmax = 0.0, kmax = 0.0;
+    for (int s = 0; s < S; ++s) {
+        dmax = std::max(dmax, D[s]);
+        kmax = std::max(kmax, robin[s]);
+        double out_rate = 0.0;
+        for (const Reaction &r : reactions)
+            if (r.from == s) out_rate += r.rate;
+        rmax = std::max(rmax, out_rate);
+    }
+    return 12.0 * dmax / (dx * dx) + rmax + 6.0 * kmax / dx;
+}
+
+rd_status rd_sim::check_dt(double dt) const
+{
+    if (!(dt > 0.0) || !isfinite(dt)) return rd_fail(RD_ERR_ARG, "dt must be positive");
+    const double lm = lambda_max();
+    if (lm > 0.0 && dt > 2.0 / lm * (1.0 + 1e-12))
+        return rd_fail(RD_ERR_UNSTABLE_DT, "dt = " + std::to_string(dt) + " exceeds 2/lambda_max = " +
+                                               std::to_string(2.0 / lm));
+    return RD_OK;
+}
+
+uint32_t *rd_sim::step_counter() const { return (uint32_t *)(ws + L.res + 384); }
+
+rd_status rd_sim::launch_steps(double dt, int64_t n)
+{
+    const bool sr = sround && storage != RD_FP32;
+    for (int64_t i = 0; i < n; ++i) {
+        StepArgs a = step_args(dt, cur);
+        a.xcd_chunk = xcd_chunk(a.nb);
+        a.sround = sr ? 1 : 0;
+        a.seed = seed;
+        a.ctr = step_counter();
+        a.ctr_off = (uint32_t)i;
+        LAUNCHCHK(rd_launch_step(storage, g->B, a, stream));
+        cur = 1 - cur;
+    }
+    // the device step counter advances once per batch of launches, so graph replay
+    // and direct launches see the same counter values
+    if (sr && n > 0) LAUNCHCHK(rd_launch_add_u32(step_counter(), (uint32_t)n, stream));
+    return RD_OK;
+}
+
+int rd_sim::xcd_chunk(int nb) const
+{
+    if (!xcd_map) return 0;
+    const int bpw = g->B == 8 ? 1 : 4;
+    const int groups = (nb + bpw - 1) / bpw;
+    if (groups < 64) return 0;
+    return (groups + 7) / 8;
+}
+
+rd_status rd_sim::step(double dt, int64_t n)
+{
+    if (!ws) return rd_fail(RD_ERR_STATE, "bind a workspace first");
+    if (n < 0) return rd_fail(RD_ERR_ARG, "n_steps < 0");
+    rd_status st = check_dt(dt);
+    if (st != RD_OK) return st;
+    if (n == 0) return RD_OK;
+    if (g->nb() == 0) {  // nothing is stored, nothing changes
+        steps_taken += n;
+        return RD_OK;
+    }
+    int64_t left = n;
+    // a graph holds an even number of steps so the buffer parity it was captured for
+    // is the same at every replay
+    const int gs = graph_steps + (graph_steps & 1);
+    if (use_graph && left >= gs) {
+        GraphEntry *ge = nullptr;
+        for (auto &e : graphs)
+            if (e.dt == dt && e.parity == cur && e.steps == gs) ge = &e;
+        if (!ge) {
+            if (!cap_stream) HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+            hipStream_t user = stream;
+            stream = cap_stream;
+            const int cur0 = cur;
+            HIPCHK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+            rd_status ls = launch_steps(dt, gs);
+            hipGraph_t graph = nullptr;
+            hipError_t ce = hipStreamEndCapture(cap_stream, &graph);
+            stream = user;
+            cur = cur0;
+            if (ls != RD_OK) {
+                if (graph) hipGraphDestroy(graph);
+                return ls;
+            }
+            HIPCHK(ce);
+            GraphEntry e{};
+            e.dt = dt;
+            e.parity = cur0;
+            e.steps = gs;
+            hipError_t ie = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            HIPCHK(ie);
+            graphs.push_back(e);
+            ge = &graphs.back();
+        }
+        while (left >= gs) {
+            HIPCHK(hipGraphLaunch(ge->exec, stream));
+            left -= gs;
+            steps_taken += gs;
+        }
+    }
+    st = launch_steps(dt, left);
+    steps_taken += left;
+    return st;
+}
+
+rd_status rd_sim::balance(int s, double out[RD_NRED])
+{
+    if (!ws) return rd_fail(RD_ERR_STATE, "bind a workspace first");
+    if (s < 0 || s >= S) return rd_fail(RD_ERR_ARG, "bad species");
+    ReduceArgs a{};
+    a.info = (const BlockInfo *)(ws + L.info);
+    a.mask = (const uint64_t *)(ws + L.mask);
+    a.geom = (const GeomInfo *)(ws + L.geom);
+    a.c = field_ptr(cur, 0);
+    a.sstride = L.field_elems;
+    a.nb = (int32_t)g->nb();
+    a.S = S;
+    a.s = s;
+    a.dx = g->dx;
+    a.D = D[s];
+    a.kR = robin[s];
+    a.dir = dir[s];
+    for (const Reaction &r : reactions) {
+        if (r.from == s) a.rate_out += r.rate;
+        if (r.to == s) a.rate_in[r.from] += r.rate;
+    }
+    a.partial = (double *)(ws + L.part);
+    const int bpw = g->B == 8 ? 1 : 4;
+    const int nparts = (a.nb + bpw - 1) / bpw;  // 0 for an empty geometry: sums are 0
+    double *res = (double *)(ws + L.res);
+    LAUNCHCHK(rd_launch_reduce(storage, g->B, a, nparts, stream));
+    LAUNCHCHK(rd_launch_finish_reduce(a.partial, nparts, RD_NRED, res, stream));
+    HIPCHK(hipMemcpyAsync(host_res, res, sizeof(double) * RD_NRED, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    for (int l = 0; l < RD_NRED; ++l) out[l] = host_res[l];
+    if (out[9] != 0.0) return rd_fail(RD_ERR_NONFINITE, "field holds " + std::to_string((int64_t)out[9]) +
+                                                            " non-finite values");
+    return RD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI wrappers of the methods
+// ---------------------------------------------------------------------------
+
+extern "C" rd_status rd_sim_set_field(rd_sim *sim, int species, const float *dev_dense)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    if (!sim->ws) return rd_fail(RD_ERR_STATE, "bind a workspace first");
+    if (species < 0 || species >= sim->S) return rd_fail(RD_ERR_ARG, "bad species");
+    if (!dev_dense) return rd_fail(RD_ERR_ARG, "field pointer is NULL");
+    float dv[6];
+    for (int f = 0; f < 6; ++f) dv[f] = (float)sim->dirval[species][f];
+    LAUNCHCHK(rd_launch_scatter(sim->storage, sim->g->B, (const BlockInfo *)(sim->ws + sim->L.info),
+                                (const uint64_t *)(sim->ws + sim->L.mask),
+                                (const GeomInfo *)(sim->ws + sim->L.geom), (int)sim->g->nb(),
+                                dev_dense, sim->field_ptr(sim->cur, species), sim->dir[species], dv,
+                                sim->stream));
+    sim->steps_taken = 0;
+    return RD_OK;
+}
+
+extern "C" rd_status rd_sim_get_field(const rd_sim *sim, int species, float *dev_dense)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    if (!sim->ws) return rd_fail(RD_ERR_STATE, "bind a workspace first");
+    if (species < 0 || species >= sim->S) return rd_fail(RD_ERR_ARG, "bad species");
+    if (!dev_dense) return rd_fail(RD_ERR_ARG, "field pointer is NULL");
+    const rd_geometry &G = *sim->g;
+    LAUNCHCHK(rd_launch_gather(sim->storage, G.B, (const BlockInfo *)(sim->ws + sim->L.info),
+                               (const uint64_t *)(sim->ws + sim->L.mask),
+                               (const GeomInfo *)(sim->ws + sim->L.geom), (int)G.nb(),
+                               sim->field_ptr(sim->cur, species), dev_dense, G.nx * G.ny * G.nz,
+                               sim->stream));
+    return RD_OK;
+}
+
+extern "C" rd_status rd_sim_step(rd_sim *sim, double dt, int64_t n_steps)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    return sim->step(dt, n_steps);
+}
+
+extern "C" rd_status rd_sim_steps_taken(const rd_sim *sim, int64_t *n)
+{
+    if (!sim || !n) return rd_fail(RD_ERR_ARG, "NULL argument");
+    *n = sim->steps_taken;
+    return RD_OK;
+}
+
+extern "C" rd_status rd_sim_balance(rd_sim *sim, int species, double out[9])
+{
+    if (!sim || !out) return rd_fail(RD_ERR_ARG, "NULL argument");
+    double r[RD_NRED];
+    rd_status st = sim->balance(species, r);
+    for (int l = 0; l < 9; ++l) out[l] = r[l];
+    return st;
+}
+
+extern "C" rd_status rd_sim_reduce(rd_sim *sim, int species, double *mass, double *dirichlet_inflow,
+                                   double *robin_uptake)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    double r[RD_NRED];
+    rd_status st = sim->balance(species, r);
+    if (mass) *mass = r[0];
+    if (dirichlet_inflow) *dirichlet_inflow = r[1] + r[2] + r[3] + r[4] + r[5] + r[6];
+    if (robin_uptake) *robin_uptake = r[7];
+    return st;
+}
+
+extern "C" void rd_sim_destroy(rd_sim *sim) { delete sim; }

@@ -1,0 +1,29 @@
+// rd_host.h -- host-side objects behind the C ABI handles.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/rd.h"
+#include "rd_internal.h"
+
+// Thread-local error detail; returns the status so call sites can `return fail(...)`.
+rd_status rd_fail(rd_status s, const std::string &msg);
+
+struct rd_geometry {
+    int64_t nx = 0, ny = 0, nz = 0;
+    double dx = 1.0;
+    int B = 8;
+    int64_t NBx = 0, NBy = 0, NBz = 0;
+    int64_t n_active = 0;
+    std::vector<int64_t> block_id;   // [nb], ascending linear id
+    std::vector<BlockInfo> info;     // [nb]
+    std::vector<uint64_t> mask;      // [nb * mask_words(B)]
+    int64_t nb() const { return (int64_t)block_id.size(); }
+};
+
+// Builds the index (geometry.cpp).
+rd_status rd_geometry_build(const uint8_t *image, int64_t nx, int64_t ny, int64_t nz, int B,
+                            rd_geometry *g);

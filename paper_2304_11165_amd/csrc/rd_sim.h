@@ -1,0 +1,83 @@
+// rd_sim.h -- the simulation handle behind rd_sim*.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "rd_host.h"
+
+struct Reaction {
+    int from, to;
+    double rate;
+};
+
+// Byte offsets of every array inside the caller's workspace.
+struct SimLayout {
+    size_t info, mask, geom;
+    size_t field[2];
+    int64_t field_elems;  // nb * B^3
+    int nparts;
+    size_t part, res;
+    size_t solver[3], scal;
+    size_t lam[2], target, cp, cp_stride;
+    size_t total;
+};
+
+struct GraphEntry {
+    double dt;
+    int parity;
+    int steps;
+    hipGraphExec_t exec;
+};
+
+SimLayout sim_layout(const struct rd_sim &s, uint32_t features, int64_t cp_slots);
+
+struct rd_sim {
+    const rd_geometry *g = nullptr;
+    rd_storage storage = RD_FP32;
+    int S = 0;
+    double D[RD_MAX_SPECIES] = {0, 0, 0, 0};
+    double robin[RD_MAX_SPECIES] = {0, 0, 0, 0};
+    uint32_t dir[RD_MAX_SPECIES] = {0, 0, 0, 0};
+    double dirval[RD_MAX_SPECIES][6] = {};
+    std::vector<Reaction> reactions;
+
+    int graph_steps = 32;
+    bool use_graph = true;
+    bool xcd_map = false;
+    bool sround = false;  // stochastic rounding on store (BF16 / FP16 storage)
+    uint32_t seed = 0;
+
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    uint32_t features = 0;
+    int64_t cp_slots = 0;
+    SimLayout L{};
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    GeomInfo geom_host{};
+    double *host_res = nullptr;  // pinned
+    std::vector<GraphEntry> graphs;
+
+    int cur = 0;  // buffer holding the current field
+    int64_t steps_taken = 0;
+
+    ~rd_sim();
+    void invalidate_graphs();
+    rd_status upload();
+    rd_status apply_dirichlet(int s);
+    void *field_ptr(int buf, int s) const;
+    StepArgs step_args(double dt, int in_buf) const;
+    double lambda_max() const;
+    rd_status check_dt(double dt) const;
+    int xcd_chunk(int nb) const;
+    uint32_t *step_counter() const;
+    rd_status launch_steps(double dt, int64_t n);
+    rd_status step(double dt, int64_t n);
+    rd_status balance(int s, double out[RD_NRED]);
+};
+
+int rd_launch_set_dirichlet(int storage, int B, const BlockInfo *info, const uint64_t *mask,
+                            const GeomInfo *geom, int nb, void *field, uint32_t dir,
+                            const float dv[6], void *stream);

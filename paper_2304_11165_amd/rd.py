@@ -1,0 +1,354 @@
+"""Thin Python binding of librd.so (argument marshalling only).
+
+Every computation happens in the HIP library; this module only converts NumPy /
+torch objects into pointers and sizes, allocates the caller-owned device
+workspace with torch, and passes torch's stream handle.  There is no fallback:
+if librd.so is missing the import fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librd.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_2304_11165_amd.build.build() "
+                      "(or __graft_entry__.build()) first")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+P = ctypes.c_void_p
+i64, i32, u32, f64, ci = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double, ctypes.c_int
+sz = ctypes.c_size_t
+
+RD_OK = 0
+STATUS = ["RD_OK", "RD_ERR_ARG", "RD_ERR_SHAPE", "RD_ERR_INCONSISTENT_SDF", "RD_ERR_UNSTABLE_DT",
+          "RD_ERR_WORKSPACE", "RD_ERR_HIP", "RD_ERR_NONFINITE", "RD_ERR_NOT_CONVERGED",
+          "RD_ERR_STATE"]
+STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2}
+RD_WS_SOLVER = 1
+RD_WS_ADJOINT = 2
+
+_SIGS = {
+    "rd_status_string": ([ci], ctypes.c_char_p),
+    "rd_last_error": ([], ctypes.c_char_p),
+    "rd_geometry_create": ([P, P, i64, i64, i64, f64, ci, P], ci),
+    "rd_geometry_stats": ([P, P, P, P, P], ci),
+    "rd_geometry_export_index": ([P, P, P], ci),
+    "rd_geometry_export_masks": ([P, P], ci),
+    "rd_geometry_destroy": ([P], None),
+    "rd_sim_create": ([P, ci, P], ci),
+    "rd_sim_add_species": ([P, f64, P], ci),
+    "rd_sim_add_reaction": ([P, ci, ci, f64], ci),
+    "rd_sim_set_robin": ([P, ci, f64], ci),
+    "rd_sim_set_dirichlet": ([P, ci, ci, f64], ci),
+    "rd_sim_clear_dirichlet": ([P, ci], ci),
+    "rd_sim_set_launch": ([P, ci, ci], ci),
+    "rd_sim_set_rounding": ([P, ci, ctypes.c_uint64], ci),
+    "rd_sim_workspace_bytes": ([P, u32, i64, P], ci),
+    "rd_sim_bind": ([P, P, sz, u32, i64, P], ci),
+    "rd_sim_set_field": ([P, ci, P], ci),
+    "rd_sim_get_field": ([P, ci, P], ci),
+    "rd_sim_step": ([P, f64, i64], ci),
+    "rd_sim_steps_taken": ([P, P], ci),
+    "rd_sim_reduce": ([P, ci, P, P, P], ci),
+    "rd_sim_balance": ([P, ci, P], ci),
+    "rd_sim_steady_state": ([P, ci, f64, i64, P, P, P], ci),
+    "rd_sim_adjoint": ([P, P, i64, f64, ci, P, P, P], ci),
+    "rd_sim_destroy": ([P], None),
+    "rd_batch_create": ([P, ci, ci, P], ci),
+    "rd_batch_workspace_bytes": ([P, P], ci),
+    "rd_batch_bind": ([P, P, sz, P], ci),
+    "rd_batch_tortuosity": ([P, ci, f64, i64, P, P, P], ci),
+    "rd_batch_destroy": ([P], None),
+}
+
+EXPORTED = sorted(_SIGS)
+
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)  # AttributeError here means the library lacks a declared symbol
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+class RDError(RuntimeError):
+    def __init__(self, status, func):
+        self.status = status
+        self.name = STATUS[status] if 0 <= status < len(STATUS) else str(status)
+        detail = _lib.rd_last_error().decode()
+        super().__init__(f"{func}: {self.name}: {detail}")
+
+
+def _check(status, func):
+    if status != RD_OK:
+        raise RDError(status, func)
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data_as(P)
+
+
+def _stream_handle(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ---------------------------------------------------------------------------
+# same-name functions
+# ---------------------------------------------------------------------------
+
+def rd_geometry_create(image, sdf=None, dx=1.0, block_edge=8):
+    img = np.ascontiguousarray(image, dtype=np.uint8)
+    if img.ndim != 3:
+        raise ValueError("image must be (nz, ny, nx)")
+    nz, ny, nx = img.shape
+    s = None
+    if sdf is not None:
+        s = np.ascontiguousarray(sdf, dtype=np.float32)
+        if s.shape != img.shape:
+            raise ValueError("sdf shape differs from image")
+    h = P()
+    _check(_lib.rd_geometry_create(_np_ptr(img), _np_ptr(s), nx, ny, nz, float(dx),
+                                   int(block_edge), ctypes.byref(h)), "rd_geometry_create")
+    return h
+
+
+def rd_geometry_stats(h):
+    na, nb, por, fill = i64(), i64(), f64(), f64()
+    _check(_lib.rd_geometry_stats(h, ctypes.byref(na), ctypes.byref(nb), ctypes.byref(por),
+                                  ctypes.byref(fill)), "rd_geometry_stats")
+    return na.value, nb.value, por.value, fill.value
+
+
+def rd_geometry_export_index(h):
+    nb = rd_geometry_stats(h)[1]
+    ids = np.zeros(nb, dtype=np.int64)
+    nbr = np.zeros((nb, 6), dtype=np.int32)
+    _check(_lib.rd_geometry_export_index(h, _np_ptr(ids), _np_ptr(nbr)), "rd_geometry_export_index")
+    return ids, nbr
+
+
+def rd_geometry_export_masks(h, block_edge):
+    nb = rd_geometry_stats(h)[1]
+    words = max(1, block_edge ** 3 // 64)
+    m = np.zeros((nb, words), dtype=np.uint64)
+    _check(_lib.rd_geometry_export_masks(h, _np_ptr(m)), "rd_geometry_export_masks")
+    return m
+
+
+def rd_geometry_destroy(h):
+    _lib.rd_geometry_destroy(h)
+
+
+# ---------------------------------------------------------------------------
+# objects
+# ---------------------------------------------------------------------------
+
+class Geometry:
+    """Active-block index of a voxel image (host only)."""
+
+    def __init__(self, image, sdf=None, dx=1.0, block_edge=8):
+        self.shape = tuple(int(v) for v in np.asarray(image).shape)
+        self.dx = float(dx)
+        self.block_edge = int(block_edge)
+        self.handle = rd_geometry_create(image, sdf, dx, block_edge)
+
+    def stats(self):
+        na, nb, por, fill = rd_geometry_stats(self.handle)
+        return {"n_active": na, "n_blocks": nb, "porosity": por, "fill": fill}
+
+    def export_index(self):
+        return rd_geometry_export_index(self.handle)
+
+    def export_masks(self):
+        return rd_geometry_export_masks(self.handle, self.block_edge)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            rd_geometry_destroy(h)
+            self.handle = None
+
+
+class Sim:
+    """A reaction-diffusion simulation on one geometry (device work via librd)."""
+
+    def __init__(self, geometry, storage="fp32"):
+        self.geometry = geometry
+        self.storage = storage
+        self.handle = P()
+        _check(_lib.rd_sim_create(geometry.handle, STORAGE[storage], ctypes.byref(self.handle)),
+               "rd_sim_create")
+        self.n_species = 0
+        self.workspace = None
+        self.stream = None
+
+    # set-up ------------------------------------------------------------------
+    def add_species(self, D):
+        sid = ci()
+        _check(_lib.rd_sim_add_species(self.handle, float(D), ctypes.byref(sid)), "rd_sim_add_species")
+        self.n_species += 1
+        return sid.value
+
+    def add_reaction(self, src, dst, rate):
+        _check(_lib.rd_sim_add_reaction(self.handle, int(src), int(dst), float(rate)),
+               "rd_sim_add_reaction")
+
+    def set_robin(self, species, k):
+        _check(_lib.rd_sim_set_robin(self.handle, int(species), float(k)), "rd_sim_set_robin")
+
+    def set_dirichlet(self, species, face, value):
+        _check(_lib.rd_sim_set_dirichlet(self.handle, int(species), int(face), float(value)),
+               "rd_sim_set_dirichlet")
+
+    def clear_dirichlet(self, species):
+        _check(_lib.rd_sim_clear_dirichlet(self.handle, int(species)), "rd_sim_clear_dirichlet")
+
+    def set_launch(self, graph_steps=32, use_graph=True):
+        _check(_lib.rd_sim_set_launch(self.handle, int(graph_steps), int(bool(use_graph))),
+               "rd_sim_set_launch")
+
+    def set_rounding(self, stochastic, seed=0):
+        _check(_lib.rd_sim_set_rounding(self.handle, int(bool(stochastic)), int(seed)),
+               "rd_sim_set_rounding")
+
+    def workspace_bytes(self, features=0, checkpoint_slots=0):
+        n = sz()
+        _check(_lib.rd_sim_workspace_bytes(self.handle, int(features), int(checkpoint_slots),
+                                           ctypes.byref(n)), "rd_sim_workspace_bytes")
+        return n.value
+
+    def bind(self, features=0, checkpoint_slots=0, device="cuda", stream=None):
+        import torch
+
+        nbytes = self.workspace_bytes(features, checkpoint_slots)
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        _check(_lib.rd_sim_bind(self.handle, ctypes.c_void_p(self.workspace.data_ptr()),
+                                self.workspace.numel(), int(features), int(checkpoint_slots),
+                                _stream_handle(self.stream)), "rd_sim_bind")
+        return self
+
+    # fields ------------------------------------------------------------------
+    def set_field(self, species, dense):
+        import torch
+
+        nz, ny, nx = self.geometry.shape
+        t = torch.as_tensor(dense, dtype=torch.float32, device=self.workspace.device)
+        t = t.reshape(nz, ny, nx).contiguous()
+        _check(_lib.rd_sim_set_field(self.handle, int(species), ctypes.c_void_p(t.data_ptr())),
+               "rd_sim_set_field")
+        self._keep = t  # lives until the stream has consumed it
+        return self
+
+    def get_field(self, species, out=None):
+        import torch
+
+        nz, ny, nx = self.geometry.shape
+        if out is None:
+            out = torch.empty((nz, ny, nx), dtype=torch.float32, device=self.workspace.device)
+        _check(_lib.rd_sim_get_field(self.handle, int(species), ctypes.c_void_p(out.data_ptr())),
+               "rd_sim_get_field")
+        return out
+
+    # time stepping --------------------------------------------------------------
+    def step(self, dt, n_steps=1):
+        _check(_lib.rd_sim_step(self.handle, float(dt), int(n_steps)), "rd_sim_step")
+        return self
+
+    def steps_taken(self):
+        n = i64()
+        _check(_lib.rd_sim_steps_taken(self.handle, ctypes.byref(n)), "rd_sim_steps_taken")
+        return n.value
+
+    def reduce(self, species):
+        m, f, r = f64(), f64(), f64()
+        _check(_lib.rd_sim_reduce(self.handle, int(species), ctypes.byref(m), ctypes.byref(f),
+                                  ctypes.byref(r)), "rd_sim_reduce")
+        return m.value, f.value, r.value
+
+    def balance(self, species):
+        out = np.zeros(9)
+        _check(_lib.rd_sim_balance(self.handle, int(species), _np_ptr(out)), "rd_sim_balance")
+        return {"mass": out[0], "inflow": out[1:7].copy(), "uptake": out[7], "react": out[8]}
+
+    def steady_state(self, axis, rel_tol=1e-8, max_iters=100000):
+        tau, rel, it = f64(), f64(), i64()
+        st = _lib.rd_sim_steady_state(self.handle, int(axis), float(rel_tol), int(max_iters),
+                                      ctypes.byref(tau), ctypes.byref(rel), ctypes.byref(it))
+        if st not in (RD_OK, 8):  # RD_ERR_NOT_CONVERGED still returns the values reached
+            _check(st, "rd_sim_steady_state")
+        return {"tau": tau.value, "rel_residual": rel.value, "iters": it.value,
+                "converged": st == RD_OK}
+
+    def adjoint(self, target, n_steps, dt, checkpoint_every):
+        import torch
+
+        nz, ny, nx = self.geometry.shape
+        t = torch.as_tensor(target, dtype=torch.float32, device=self.workspace.device)
+        t = t.reshape(nz, ny, nx).contiguous()
+        L, gD, gk = f64(), f64(), f64()
+        _check(_lib.rd_sim_adjoint(self.handle, ctypes.c_void_p(t.data_ptr()), int(n_steps),
+                                   float(dt), int(checkpoint_every), ctypes.byref(L),
+                                   ctypes.byref(gD), ctypes.byref(gk)), "rd_sim_adjoint")
+        return L.value, gD.value, gk.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            _lib.rd_sim_destroy(h)
+            self.handle = None
+
+
+class Batch:
+    """Many geometries stepped together (single species, pure diffusion)."""
+
+    def __init__(self, geometries, storage="fp32"):
+        self.geometries = list(geometries)
+        arr = (P * len(self.geometries))(*[g.handle for g in self.geometries])
+        self._arr = arr
+        self.handle = P()
+        _check(_lib.rd_batch_create(arr, len(self.geometries), STORAGE[storage],
+                                    ctypes.byref(self.handle)), "rd_batch_create")
+        self.workspace = None
+
+    def bind(self, device="cuda", stream=None):
+        import torch
+
+        n = sz()
+        _check(_lib.rd_batch_workspace_bytes(self.handle, ctypes.byref(n)), "rd_batch_workspace_bytes")
+        self.workspace = torch.empty(max(n.value, 256), dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        _check(_lib.rd_batch_bind(self.handle, ctypes.c_void_p(self.workspace.data_ptr()),
+                                  self.workspace.numel(), _stream_handle(self.stream)),
+               "rd_batch_bind")
+        return self
+
+    def tortuosity(self, axis=0, rel_tol=1e-8, max_iters=100000):
+        n = len(self.geometries)
+        tau, rel, it = np.zeros(n), np.zeros(n), np.zeros(n, dtype=np.int64)
+        st = _lib.rd_batch_tortuosity(self.handle, int(axis), float(rel_tol), int(max_iters),
+                                      _np_ptr(tau), _np_ptr(rel), _np_ptr(it))
+        if st not in (RD_OK, 8):
+            _check(st, "rd_batch_tortuosity")
+        return tau, rel, it
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            _lib.rd_batch_destroy(h)
+            self.handle = None
+
+
+def stability_dt_max(D_max, dx=1.0, rate_max=0.0, robin_max=0.0):
+    """2 / lambda_max of the step (the bound rd_sim_step enforces)."""
+    lam = 12.0 * D_max / dx ** 2 + rate_max + 6.0 * robin_max / dx
+    return math.inf if lam == 0 else 2.0 / lam

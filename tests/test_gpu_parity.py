@@ -1,0 +1,223 @@
+"""GPU (HIP, through the C ABI) vs the FP64 oracle, element by element.
+
+Tolerance: relative L2 over active voxels <= 1e-5 for FP32 storage after the
+workload's steps (FP32 rounding of ~1e-7 per step, damped by diffusion).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_common import fields, make_gpu, rel_l2, round_to_storage
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def rd():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2304_11165_amd import rd as rdmod
+
+    return rdmod
+
+
+def _run_both(rd, oracle_mod, img, D, dt, n, B=8, dx=1.0, robin=None, dirichlet=None,
+              reactions=None, init=None, storage="fp32", graph=True):
+    g, s = make_gpu(rd, img, D, dx, robin, dirichlet, reactions, storage, B, graph=graph)
+    prob = oracle_mod.Problem(img, D, dx=dx, robin=robin, dirichlet=dirichlet, reactions=reactions)
+    c0 = prob.initial()
+    if init is not None:
+        c0 = prob.apply_dirichlet(round_to_storage(init, storage))
+        for sp in range(len(D)):
+            s.set_field(sp, c0[sp].astype(np.float32))
+    s.step(dt, n)
+    got = fields(s, len(D))
+    ref = prob.run(c0, dt, n)
+    return got, ref, prob, s
+
+
+def test_slab_closed_form_and_oracle(rd, oracle_mod):
+    N = 37  # ragged: not a multiple of 4 or 8
+    img = W.slab_box(N, ny=5, nz=3)
+    for B in (4, 8):
+        got, ref, _, _ = _run_both(rd, oracle_mod, img, [1.0], 0.1, 400, B=B, dirichlet={(0, 0): 1.0})
+        act = img != 0
+        assert rel_l2(got[0], ref[0], act) < TOL
+        i = np.arange(N)
+        u = np.ones(N)
+        for m in range(N - 1):
+            th = (2 * m + 1) * math.pi / (2 * N - 1)
+            a = -np.sin(th * i[1:]).sum() / ((2 * N - 1) / 4.0)
+            u += a * (1 - 4 * 0.1 * math.sin(th / 2) ** 2) ** 400 * np.sin(th * i)
+        np.testing.assert_allclose(got[0, 1, 2], u, atol=2e-6)
+
+
+def test_spheres64_full_config(rd, oracle_mod):
+    """64^3 disjoint-sphere packing, D = 1, dt = 0.1, 1000 steps, c = 1 on x = 0."""
+    w = W.workload("spheres64")
+    img, sdf = W.workload_geometry("spheres64")
+    g, s = make_gpu(rd, img, w.species_D, w.dx, dirichlet=w.dirichlet, B=8, sdf=sdf)
+    s.step(w.dt, w.steps)
+    got8 = fields(s, 1)
+    prob = oracle_mod.Problem(img, w.species_D, dirichlet=w.dirichlet)
+    ref = prob.run(prob.initial(), w.dt, w.steps)
+    act = img != 0
+    err = rel_l2(got8[0], ref[0], act)
+    print(f"spheres64 rel L2 = {err:.3e}")
+    assert err < TOL
+    assert np.all(got8[0][~act] == 0)
+    # B = 4, direct launches and graph replay: bitwise identical
+    _, s4 = make_gpu(rd, img, w.species_D, w.dx, dirichlet=w.dirichlet, B=4, graph=False)
+    s4.step(w.dt, w.steps)
+    np.testing.assert_array_equal(fields(s4, 1), got8)
+
+
+def test_soil_reduced_two_species(rd, oracle_mod):
+    """Soil recipe at 96^3: A, B with D = (1, 0.4), A -> B at 0.01, Robin on B."""
+    w = W.workload("soil512", small=True)
+    img, _ = W.workload_geometry("soil512", small=True)
+    got, ref, prob, s = _run_both(rd, oracle_mod, img, w.species_D, w.dt, 1500, B=8,
+                                  robin=w.robin, dirichlet=w.dirichlet, reactions=w.reactions)
+    act = img != 0
+    for sp in range(2):
+        err = rel_l2(got[sp], ref[sp], act)
+        print(f"soil96 species {sp} rel L2 = {err:.3e}")
+        assert err < TOL
+    # FP64 balance terms of the GPU field agree with the oracle's on the same field
+    for sp in range(2):
+        b = s.balance(sp)
+        m, infl, up, re = prob.balance(got, sp)
+        assert b["mass"] == pytest.approx(m, rel=1e-10)
+        np.testing.assert_allclose(b["inflow"], infl, rtol=1e-9, atol=1e-9)
+        assert b["uptake"] == pytest.approx(up, rel=1e-10, abs=1e-12)
+        assert b["react"] == pytest.approx(re, rel=1e-10, abs=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_tiny_geometries(rd, oracle_mod, seed):
+    """Edge cases: sizes not a multiple of B, isolated voxels, thin walls, random
+    stable parameters and random initial fields."""
+    rng = np.random.default_rng(100 + seed)
+    img = W.random_tiny_geometry(seed)
+    S = int(rng.integers(1, 4))
+    D = list(rng.uniform(0.1, 1.0, S))
+    dx = float(rng.uniform(0.5, 2.0))
+    robin = {int(rng.integers(0, S)): float(rng.uniform(0, 0.2))}
+    reactions = [(0, -1, float(rng.uniform(0, 0.05)))]
+    if S > 1:
+        reactions.append((0, 1, float(rng.uniform(0, 0.05))))
+    dirichlet = {(int(rng.integers(0, S)), int(rng.integers(0, 6))): float(rng.uniform(0, 1))}
+    lam = 12 * max(D) / dx ** 2 + sum(r[2] for r in reactions) + 6 * max(robin.values()) / dx
+    dt = 1.9 / lam
+    init = rng.uniform(0, 1, (S,) + img.shape)
+    for B in (4, 8):
+        got, ref, _, _ = _run_both(rd, oracle_mod, img, D, dt, 60, B=B, dx=dx, robin=robin,
+                                   dirichlet=dirichlet, reactions=reactions, init=init)
+        assert np.abs(got - ref).max() < 2e-5, (seed, B)
+
+
+def test_empty_and_single_voxel(rd, oracle_mod):
+    img = np.zeros((9, 10, 11), np.uint8)
+    g, s = make_gpu(rd, img, [1.0])
+    s.step(0.1, 5)
+    assert np.all(fields(s, 1) == 0)
+    assert s.balance(0)["mass"] == 0.0
+    img[4, 5, 6] = 1
+    got, ref, _, _ = _run_both(rd, oracle_mod, img, [1.0], 0.1, 50, robin={0: 0.1},
+                               init=np.ones((1,) + img.shape))
+    assert got[0, 4, 5, 6] == pytest.approx(ref[0, 4, 5, 6], rel=1e-5)
+    assert ref[0, 4, 5, 6] == pytest.approx((1 - 0.1 * 0.1 * 6) ** 50, rel=1e-12)
+
+
+def test_mass_conservation_fp32(rd, oracle_mod):
+    img, _ = W.boolean_spheres(48, 0.5, 3.0, 6.0, seed=11)
+    rng = np.random.default_rng(11)
+    init = rng.uniform(0, 1, (1,) + img.shape)
+    g, s = make_gpu(rd, img, [1.0])
+    s.set_field(0, (init[0] * (img != 0)).astype(np.float32))
+    m0 = s.balance(0)["mass"]
+    s.step(0.15, 2000)
+    m1 = s.balance(0)["mass"]
+    drift = abs(m1 - m0) / m0 / 2000
+    print(f"FP32 normalised mass drift per step = {drift:.3e} (paper, FP32 on A100: 7.91e-10)")
+    assert drift < 1e-8
+
+
+def test_deterministic_and_resume(rd, oracle_mod):
+    w = W.workload("soil512", small=True)
+    img, _ = W.workload_geometry("soil512", small=True)
+    runs = []
+    for _ in range(2):
+        _, s = make_gpu(rd, img, w.species_D, robin=w.robin, dirichlet=w.dirichlet,
+                        reactions=w.reactions)
+        s.step(w.dt, 300)
+        runs.append(fields(s, 2))
+    np.testing.assert_array_equal(runs[0], runs[1])
+    # interrupt after 100 steps, save with get_field, restore with set_field
+    _, s = make_gpu(rd, img, w.species_D, robin=w.robin, dirichlet=w.dirichlet,
+                    reactions=w.reactions)
+    s.step(w.dt, 100)
+    saved = [s.get_field(i).clone() for i in range(2)]
+    _, s2 = make_gpu(rd, img, w.species_D, robin=w.robin, dirichlet=w.dirichlet,
+                     reactions=w.reactions)
+    for i in range(2):
+        s2.set_field(i, saved[i])
+    s2.step(w.dt, 200)
+    np.testing.assert_array_equal(fields(s2, 2), runs[0])
+
+
+def test_error_paths(rd):
+    img = np.ones((8, 8, 8), np.uint8)
+    _, s = make_gpu(rd, img, [1.0])
+    with pytest.raises(rd.RDError) as e:
+        s.step(0.2, 1)  # 2/lambda_max = 1/6
+    assert e.value.name == "RD_ERR_UNSTABLE_DT"
+    with pytest.raises(rd.RDError):
+        s.get_field(3)
+    bad = np.zeros((8, 8, 8), np.float32)
+    bad[2, 3, 4] = np.nan
+    s.set_field(0, bad)
+    with pytest.raises(rd.RDError) as e:
+        s.balance(0)
+    assert e.value.name == "RD_ERR_NONFINITE"
+
+
+@pytest.mark.parametrize("storage", ["bf16", "fp16"])
+def test_reduced_storage_error_reported(rd, oracle_mod, storage):
+    """BF16 / FP16 storage with FP32 arithmetic on the 64^3 packing (1000 steps).
+
+    Parity unpinned: the error against the FP64 oracle is measured and reported.
+    Round-to-nearest storage loses increments below half a storage spacing, so the
+    front stalls; stochastic rounding is unbiased and must stay within a few
+    storage spacings (bounds: BF16 spacing 2^-8, FP16 2^-11 in [0.5, 1))."""
+    w = W.workload("spheres64")
+    img, sdf = W.workload_geometry("spheres64")
+    prob = oracle_mod.Problem(img, w.species_D, dirichlet=w.dirichlet)
+    ref = prob.run(prob.initial(), w.dt, w.steps)
+    act = img != 0
+    errs = {}
+    for sr in (0, 1):
+        g, s = make_gpu(rd, img, w.species_D, dirichlet=w.dirichlet, storage=storage)
+        s.set_rounding(sr, seed=1234)
+        s.step(w.dt, w.steps)
+        errs[sr] = rel_l2(fields(s, 1)[0], ref[0], act)
+    print(f"spheres64 {storage}: rel L2 vs FP64 nearest = {errs[0]:.3e}, stochastic = {errs[1]:.3e}")
+    bound = {"bf16": 2 ** -8, "fp16": 2 ** -11}[storage] * 4
+    assert errs[1] < bound
+    assert errs[1] < errs[0]
+
+
+def test_stochastic_rounding_graph_equals_direct(rd):
+    img, _ = W.boolean_spheres(40, 0.5, 3.0, 6.0, seed=3)
+    out = []
+    for graph in (True, False):
+        g, s = make_gpu(rd, img, [1.0], dirichlet={(0, 0): 1.0}, storage="bf16", graph=graph)
+        s.set_rounding(1, seed=99)
+        s.step(0.1, 77)
+        out.append(fields(s, 1))
+    np.testing.assert_array_equal(out[0], out[1])
