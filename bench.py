@@ -44,7 +44,7 @@ def log(msg, quiet=False):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def build_sim(rd, geom, w, storage, graph_steps):
+def build_sim(rd, geom, w, storage, graph_steps, xcd_map=False):
     s = rd.Sim(geom, storage)
     for d in w.species_D:
         s.add_species(d)
@@ -54,7 +54,7 @@ def build_sim(rd, geom, w, storage, graph_steps):
         s.set_robin(sp, k)
     for (sp, f), v in w.dirichlet.items():
         s.set_dirichlet(sp, f, v)
-    s.set_launch(graph_steps, True)
+    s.set_launch(graph_steps, True, xcd_map)
     return s
 
 

@@ -117,10 +117,17 @@ rd_status rd_sim_set_robin(rd_sim *sim, int species, double k);
 rd_status rd_sim_set_dirichlet(rd_sim *sim, int species, int face, double value);
 /* Remove every Dirichlet face of a species. */
 rd_status rd_sim_clear_dirichlet(rd_sim *sim, int species);
-/* Launch shape: steps fused per graph node group (>= 1) and whether rd_sim_step
- * replays a captured hipGraph (1) or launches directly (0).  Results are bitwise
+/* Launch shape: steps per captured graph (>= 1), whether rd_sim_step
+ * replays a captured hipGraph (1) or launches directly (0), and whether workgroups
+ * are remapped so each of the 8 XCDs walks one contiguous range of the block list
+ * (xcd_map = 1; its L2 then holds most halo reads).  Results are bitwise
  * identical for every choice. */
-rd_status rd_sim_set_launch(rd_sim *sim, int graph_steps, int use_graph);
+rd_status rd_sim_set_launch(rd_sim *sim, int graph_steps, int use_graph, int xcd_map);
+/* Step kernel for B = 8: persistent = 1 (default) runs a fixed grid of
+ * wg_per_cu * (compute units) workgroups that walk the block list and prefetch the
+ * next block while computing the current one; persistent = 0 launches one
+ * workgroup per block.  Results are bitwise identical. */
+rd_status rd_sim_set_kernel(rd_sim *sim, int persistent, int wg_per_cu);
 
 /* Rounding of BF16 / FP16 stores (no effect with FP32 storage).  stochastic = 0:
  * round to nearest even (default).  stochastic = 1: round up with probability equal
@@ -172,14 +179,26 @@ rd_status rd_sim_balance(rd_sim *sim, int species, double out[9]);
 rd_status rd_sim_steady_state(rd_sim *sim, int axis, double rel_tol, int64_t max_iters,
                               double *tau, double *rel_residual, int64_t *iters);
 
-/* Gradient of L = 1/2 sum_free (c^N - c*)^2 for a single-species diffusion-decay
- * simulation, run from the current field for n_steps of size dt, with respect to
- * D and the decay rate.  dev_target: dense float32 (nz,ny,nx) c*.  States are
- * checkpointed every `checkpoint_every` steps and recomputed per segment (needs
- * RD_WS_ADJOINT with checkpoint_slots >= ceil(n_steps/checkpoint_every) + 1 +
- * checkpoint_every).  On return species 0 holds c^N.  Outputs: loss, dL/dD, dL/dk. */
-rd_status rd_sim_adjoint(rd_sim *sim, const float *dev_target, int64_t n_steps, double dt,
-                         int checkpoint_every, double *loss, double *dL_dD, double *dL_drate);
+/* Discrete adjoint of a single-species diffusion-decay simulation (optionally with
+ * Robin walls and Dirichlet faces), run from the current field for n_steps of size
+ * dt.  Gradients with respect to D and to the decay rate k (the sum of the rates of
+ * its decay reactions; 0 if none):
+ *   seed_mode 0: dev_seed is a target c* (dense float32 (nz,ny,nx));
+ *                L = 1/2 sum over free voxels of (c^N - c*)^2, returned in *loss;
+ *   seed_mode 1: dev_seed is dL/dc^N (dense float32); *loss = 0.
+ * The recursion lambda^n = J^T lambda^{n+1} uses the symmetry of the step's
+ * Jacobian J (mirror rule); dL/dD = sum_n dt/dx^2 <lambda^{n+1}, L c^n>,
+ * dL/dk = -sum_n dt <lambda^{n+1}, c^n>, accumulated in FP64.  States are
+ * checkpointed every `checkpoint_every` = k steps and recomputed per segment:
+ * needs RD_WS_ADJOINT with checkpoint_slots >= ceil(n_steps / k) + k - 1, and
+ * round-to-nearest storage.  On return species 0 holds c^N. */
+rd_status rd_sim_adjoint(rd_sim *sim, const float *dev_seed, int seed_mode, int64_t n_steps,
+                         double dt, int checkpoint_every, double *loss, double *dL_dD,
+                         double *dL_drate);
+/* Change a species' D, or the rate of reaction `index` (in order of addition), after
+ * binding (used between differentiable runs). */
+rd_status rd_sim_set_species_D(rd_sim *sim, int species, double D);
+rd_status rd_sim_set_reaction_rate(rd_sim *sim, int index, double rate);
 void rd_sim_destroy(rd_sim *sim);
 
 /* ---- batches of geometries ------------------------------------------------- */

@@ -129,10 +129,10 @@ class Problem:
 
     def apply_dirichlet(self, c):
         """Zero inactive voxels and write the Dirichlet values (in face order, the
-        last flagged face wins on shared edges)."""
+        highest flagged face wins on shared edges)."""
         c = np.array(c, dtype=np.float64, copy=True).reshape(self.S, self.nz, self.ny, self.nx)
         c[:, self.image == 0] = 0.0
-        for (s, f), v in self.dir_value.items():
+        for (s, f), v in sorted(self.dir_value.items()):
             m = self.face_plane(f) & (self.image != 0)
             c[s][m] = v
         return c

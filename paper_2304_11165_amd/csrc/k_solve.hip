@@ -1,0 +1,410 @@
+// k_solve.hip -- conjugate gradients for the steady state of pure diffusion on the
+// sparse block grid, for one geometry or a batch of concatenated geometries.
+//
+// Problem (the t -> infinity limit of the FTCS step with the same mirror rule):
+// on every free voxel p (active, not Dirichlet)
+//     (A x)_p = sum over active face neighbours q of (x_p - x_q) = b_p,
+// b_p = sum of the Dirichlet neighbours' held values.  A is the graph Laplacian of
+// the free voxels with Dirichlet contacts on the diagonal: symmetric positive
+// semi-definite, so plain CG applies.  Vectors live in the storage type T with FP32
+// arithmetic; every dot product is an FP64 per-block partial summed per geometry in
+// a fixed order.  Tortuosity follows from the steady flux (eq. tortuosity).
+#include <algorithm>
+
+#include "rd_device.h"
+#include "rd_solve.h"
+
+namespace {
+
+// Per-block sum of two FP64 values over the block's voxels, written to part[b*2 + k].
+// B = 8: one block spans the 4 waves; B = 4: one block is one wave.
+template <int B>
+__device__ __forceinline__ void block_sum2(double v0, double v1, double *part, int b, bool valid)
+{
+    __shared__ double sh[4][2];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    v0 = wave_sum(v0);
+    v1 = wave_sum(v1);
+    if constexpr (B == 8) {
+        if (lane == 0) {
+            sh[wave][0] = v0;
+            sh[wave][1] = v1;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0 && valid) {
+            part[(int64_t)b * 2 + 0] = ((sh[0][0] + sh[1][0]) + sh[2][0]) + sh[3][0];
+            part[(int64_t)b * 2 + 1] = ((sh[0][1] + sh[1][1]) + sh[2][1]) + sh[3][1];
+        }
+    } else {
+        if (lane == 0 && valid) {
+            part[(int64_t)b * 2 + 0] = v0;
+            part[(int64_t)b * 2 + 1] = v1;
+        }
+    }
+}
+
+struct VoxCtx {
+    bool act, fr;
+    unsigned nbm;     // active neighbours
+    unsigned dirnb;   // active neighbours that are Dirichlet voxels
+    int gx, gy, gz;
+};
+
+template <int B>
+__device__ __forceinline__ VoxCtx vox_ctx(const uint64_t *rec, const BlockInfo &bi, const GeomInfo &g,
+                                          uint32_t dir, int slot)
+{
+    VoxCtx v;
+    int bx, by, bz, gid;
+    block_pos(bi, &bx, &by, &bz, &gid);
+    const int lx = slot % B, ly = (slot / B) % B, lz = slot / (B * B);
+    v.gx = bx * B + lx;
+    v.gy = by * B + ly;
+    v.gz = bz * B + lz;
+    v.act = own_bit<B>(rec, slot);
+    int nw = 0;
+    v.nbm = v.act ? nb_bits<B>(rec, lx, ly, lz, v.gx, v.gy, v.gz, g.nx, g.ny, g.nz, &nw) : 0u;
+    v.fr = v.act && !on_dirichlet(dir, v.gx, v.gy, v.gz, g.nx, g.ny, g.nz);
+    const int ddx[6] = {-1, 1, 0, 0, 0, 0}, ddy[6] = {0, 0, -1, 1, 0, 0}, ddz[6] = {0, 0, 0, 0, -1, 1};
+    unsigned d = 0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        if (((v.nbm >> k) & 1u) &&
+            on_dirichlet(dir, v.gx + ddx[k], v.gy + ddy[k], v.gz + ddz[k], g.nx, g.ny, g.nz))
+            d |= 1u << k;
+    v.dirnb = d;
+    return v;
+}
+
+// sum over active neighbours of (t_q - t_p), order -x,+x,-y,+y,-z,+z
+template <int B>
+__device__ __forceinline__ float lap_at(const float *ts, int t, unsigned nbm)
+{
+    using K = Blk<B>;
+    const float uc = ts[t];
+    const float nbv[6] = {ts[t - 1], ts[t + 1], ts[t - K::E], ts[t + K::E], ts[t - K::E * K::E],
+                          ts[t + K::E * K::E]};
+    float lap = 0.0f;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) lap = ((nbm >> d) & 1u) ? lap + (nbv[d] - uc) : lap;
+    return lap;
+}
+
+template <int B>
+__device__ __forceinline__ bool geom_live(const CgArgs &a, int gid)
+{
+    return a.scal[gid * CG_NSCAL + CG_DONE] == 0.0;
+}
+
+// r = b - A x (stored in r and p when `store`), partials (r.r, b.b)
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_cg_residual(CgArgs a, int store)
+{
+    using K = Blk<B>;
+    using C = Cfg<B>;
+    __shared__ float tile[C::BPW][1][K::TL];
+    __shared__ uint64_t srec[C::BPW][K::MW];
+    const int sub = threadIdx.x / C::TPB, lt = threadIdx.x % C::TPB;
+    const int b = blockIdx.x * C::BPW + sub;
+    const bool valid = b < a.nb;
+    BlockInfo bi = {};
+    if (valid) {
+        bi = a.info[b];
+        if (lt < K::MW) srec[sub][lt] = a.mask[(int64_t)b * K::MW + lt];
+    }
+    stage_tile<T, B>(tile[sub], (const T *)a.x, 0, 1, b, bi, lt, valid);
+    __syncthreads();
+    double rr = 0.0, bb = 0.0;
+    if (valid) {
+        int bx, by, bz, gid;
+        block_pos(bi, &bx, &by, &bz, &gid);
+        const GeomInfo g = a.geom[gid];
+        for (int k = 0; k < C::VPT; ++k) {
+            const int slot = lt + k * C::TPB;
+            const VoxCtx v = vox_ctx<B>(srec[sub], bi, g, a.dir, slot);
+            const int lx = slot % B, ly = (slot / B) % B, lz = slot / (B * B);
+            const int t = K::tidx(lx, ly, lz);
+            float r = 0.0f;
+            if (v.fr) {
+                r = lap_at<B>(tile[sub][0], t, v.nbm);
+                const int off[6] = {-1, 1, -K::E, K::E, -K::E * K::E, K::E * K::E};
+                double bp = 0.0;
+#pragma unroll
+                for (int d = 0; d < 6; ++d)
+                    if ((v.dirnb >> d) & 1u) bp += (double)tile[sub][0][t + off[d]];
+                rr += (double)r * (double)r;
+                bb += bp * bp;
+            }
+            if (store) {
+                rd_st((T *)a.r, (int64_t)b * K::NS + slot, r);
+                rd_st((T *)a.p, (int64_t)b * K::NS + slot, r);
+            }
+        }
+    }
+    block_sum2<B>(rr, bb, a.partial, b, valid);
+}
+
+// Ap = A p on live geometries, partial (p.Ap, 0)
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_cg_matvec(CgArgs a)
+{
+    using K = Blk<B>;
+    using C = Cfg<B>;
+    __shared__ float tile[C::BPW][1][K::TL];
+    __shared__ uint64_t srec[C::BPW][K::MW];
+    const int sub = threadIdx.x / C::TPB, lt = threadIdx.x % C::TPB;
+    const int b = blockIdx.x * C::BPW + sub;
+    bool valid = b < a.nb;
+    BlockInfo bi = {};
+    if (valid) {
+        bi = a.info[b];
+        int bx, by, bz, gid;
+        block_pos(bi, &bx, &by, &bz, &gid);
+        valid = geom_live<B>(a, gid);
+    }
+    if (valid && lt < K::MW) srec[sub][lt] = a.mask[(int64_t)b * K::MW + lt];
+    stage_tile<T, B>(tile[sub], (const T *)a.p, 0, 1, b, bi, lt, valid);
+    __syncthreads();
+    double pap = 0.0;
+    if (valid) {
+        int bx, by, bz, gid;
+        block_pos(bi, &bx, &by, &bz, &gid);
+        const GeomInfo g = a.geom[gid];
+        for (int k = 0; k < C::VPT; ++k) {
+            const int slot = lt + k * C::TPB;
+            const VoxCtx v = vox_ctx<B>(srec[sub], bi, g, a.dir, slot);
+            const int lx = slot % B, ly = (slot / B) % B, lz = slot / (B * B);
+            const int t = K::tidx(lx, ly, lz);
+            float ap = 0.0f;
+            if (v.fr) {
+                ap = -lap_at<B>(tile[sub][0], t, v.nbm);
+                pap += (double)tile[sub][0][t] * (double)ap;
+            }
+            rd_st((T *)a.ap, (int64_t)b * K::NS + slot, ap);
+        }
+    }
+    block_sum2<B>(pap, 0.0, a.partial, b, b < a.nb);
+}
+
+// x += alpha p, r -= alpha Ap on free voxels of live geometries; partial (r.r, 0)
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_cg_update(CgArgs a)
+{
+    using K = Blk<B>;
+    using C = Cfg<B>;
+    const int sub = threadIdx.x / C::TPB, lt = threadIdx.x % C::TPB;
+    const int b = blockIdx.x * C::BPW + sub;
+    bool valid = b < a.nb;
+    int gid = 0;
+    BlockInfo bi = {};
+    if (valid) {
+        bi = a.info[b];
+        int bx, by, bz;
+        block_pos(bi, &bx, &by, &bz, &gid);
+        valid = geom_live<B>(a, gid);
+    }
+    double rr = 0.0;
+    if (valid) {
+        const float alpha = (float)a.scal[gid * CG_NSCAL + CG_ALPHA];
+        const uint64_t *rec = a.mask + (int64_t)b * K::MW;
+        const GeomInfo g = a.geom[gid];
+        for (int k = 0; k < C::VPT; ++k) {
+            const int slot = lt + k * C::TPB;
+            if (!own_bit<B>(rec, slot)) continue;
+            int bx, by, bz, gg;
+            block_pos(bi, &bx, &by, &bz, &gg);
+            const int gx = bx * B + slot % B, gy = by * B + (slot / B) % B, gz = bz * B + slot / (B * B);
+            if (on_dirichlet(a.dir, gx, gy, gz, g.nx, g.ny, g.nz)) continue;
+            const int64_t i = (int64_t)b * K::NS + slot;
+            const float p = rd_ld((const T *)a.p, i);
+            const float ap = rd_ld((const T *)a.ap, i);
+            const float x = fmaf(alpha, p, rd_ld((const T *)a.x, i));
+            const float r = fmaf(-alpha, ap, rd_ld((const T *)a.r, i));
+            rd_st((T *)a.x, i, x);
+            rd_st((T *)a.r, i, r);
+            const float rs = rd_ld((const T *)a.r, i);  // the stored (rounded) residual
+            rr += (double)rs * (double)rs;
+        }
+    }
+    block_sum2<B>(rr, 0.0, a.partial, b, b < a.nb);
+}
+
+// p = r + beta p on free voxels of live geometries
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_cg_pupdate(CgArgs a)
+{
+    using K = Blk<B>;
+    using C = Cfg<B>;
+    const int sub = threadIdx.x / C::TPB, lt = threadIdx.x % C::TPB;
+    const int b = blockIdx.x * C::BPW + sub;
+    if (b >= a.nb) return;
+    const BlockInfo bi = a.info[b];
+    int bx, by, bz, gid;
+    block_pos(bi, &bx, &by, &bz, &gid);
+    if (!geom_live<B>(a, gid)) return;
+    const float beta = (float)a.scal[gid * CG_NSCAL + CG_BETA];
+    const GeomInfo g = a.geom[gid];
+    const uint64_t *rec = a.mask + (int64_t)b * K::MW;
+    for (int k = 0; k < C::VPT; ++k) {
+        const int slot = lt + k * C::TPB;
+        if (!own_bit<B>(rec, slot)) continue;
+        const int gx = bx * B + slot % B, gy = by * B + (slot / B) % B, gz = bz * B + slot / (B * B);
+        if (on_dirichlet(a.dir, gx, gy, gz, g.nx, g.ny, g.nz)) continue;
+        const int64_t i = (int64_t)b * K::NS + slot;
+        rd_st((T *)a.p, i, fmaf(beta, rd_ld((const T *)a.p, i), rd_ld((const T *)a.r, i)));
+    }
+}
+
+// Steady flux at the Dirichlet planes: partial (inflow at the inlet face, inflow at
+// the outlet face) = sum over Dirichlet voxels q and free neighbours p of (x_q - x_p)
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_cg_flux(CgArgs a, int inlet_face)
+{
+    using K = Blk<B>;
+    using C = Cfg<B>;
+    __shared__ float tile[C::BPW][1][K::TL];
+    __shared__ uint64_t srec[C::BPW][K::MW];
+    const int sub = threadIdx.x / C::TPB, lt = threadIdx.x % C::TPB;
+    const int b = blockIdx.x * C::BPW + sub;
+    const bool valid = b < a.nb;
+    BlockInfo bi = {};
+    if (valid) {
+        bi = a.info[b];
+        if (lt < K::MW) srec[sub][lt] = a.mask[(int64_t)b * K::MW + lt];
+    }
+    stage_tile<T, B>(tile[sub], (const T *)a.x, 0, 1, b, bi, lt, valid);
+    __syncthreads();
+    double qin = 0.0, qout = 0.0;
+    if (valid) {
+        int bx, by, bz, gid;
+        block_pos(bi, &bx, &by, &bz, &gid);
+        const GeomInfo g = a.geom[gid];
+        const uint32_t din = 1u << inlet_face, dout = 1u << (inlet_face + 1);
+        for (int k = 0; k < C::VPT; ++k) {
+            const int slot = lt + k * C::TPB;
+            const VoxCtx v = vox_ctx<B>(srec[sub], bi, g, a.dir, slot);
+            if (!v.act || v.fr) continue;
+            const int lx = slot % B, ly = (slot / B) % B, lz = slot / (B * B);
+            const int t = K::tidx(lx, ly, lz);
+            const bool on_in = on_dirichlet(din, v.gx, v.gy, v.gz, g.nx, g.ny, g.nz);
+            const int off[6] = {-1, 1, -K::E, K::E, -K::E * K::E, K::E * K::E};
+            double q = 0.0;
+#pragma unroll
+            for (int d = 0; d < 6; ++d)
+                if (((v.nbm >> d) & 1u) && !((v.dirnb >> d) & 1u))
+                    q += (double)tile[sub][0][t] - (double)tile[sub][0][t + off[d]];
+            if (on_in) qin += q;
+            else if (on_dirichlet(dout, v.gx, v.gy, v.gz, g.nx, g.ny, g.nz)) qout += q;
+        }
+    }
+    block_sum2<B>(qin, qout, a.partial, b, valid);
+}
+
+// Per-geometry sums of the per-block partial pairs: geometry g owns blocks
+// [block0_g, block0_{g+1}); one workgroup per geometry, fixed summation order.
+// dst[g*CG_NSCAL + slot0 + k] = sum (k = 0, 1; slot < 0 skips that lane).
+__global__ __launch_bounds__(256) void k_cg_segsum(const double *part, const GeomInfo *geom,
+                                                   int ngeom, int nb, double *scal, int slot0,
+                                                   int slot1)
+{
+    __shared__ double sh[2][256];
+    const int g = blockIdx.x;
+    if (g >= ngeom) return;
+    const int lo = geom[g].block0;
+    const int hi = g + 1 < ngeom ? geom[g + 1].block0 : nb;
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = lo + (int)threadIdx.x; i < hi; i += 256) {
+        s0 += part[(int64_t)i * 2 + 0];
+        s1 += part[(int64_t)i * 2 + 1];
+    }
+    sh[0][threadIdx.x] = s0;
+    sh[1][threadIdx.x] = s1;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (slot0 >= 0) scal[g * CG_NSCAL + slot0] = sh[0][0];
+        if (slot1 >= 0) scal[g * CG_NSCAL + slot1] = sh[1][0];
+    }
+}
+
+// Scalar recurrences per live geometry.  mode 0: alpha = rr / pAp.  mode 1:
+// beta = rr_new / rr, rr = rr_new.  mode 2: rr = rr_new (start).
+__global__ __launch_bounds__(256) void k_cg_scalars(double *scal, int ngeom, int mode)
+{
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= ngeom) return;
+    double *s = scal + g * CG_NSCAL;
+    if (s[CG_DONE] != 0.0) return;
+    if (mode == 0) {
+        s[CG_ALPHA] = s[CG_PAP] > 0.0 ? s[CG_RR] / s[CG_PAP] : 0.0;
+    } else if (mode == 1) {
+        s[CG_BETA] = s[CG_RR] > 0.0 ? s[CG_RRNEW] / s[CG_RR] : 0.0;
+        s[CG_RR] = s[CG_RRNEW];
+    } else {
+        s[CG_RR] = s[CG_RRNEW];
+    }
+}
+
+template <int B>
+int groups(int nb) { return (nb + Cfg<B>::BPW - 1) / Cfg<B>::BPW; }
+
+}  // namespace
+
+#define CG_DISPATCH(storage, B, KERNEL, grid, stream, ...)                                         \
+    do {                                                                                           \
+        hipStream_t st_ = (hipStream_t)(stream);                                                   \
+        if ((B) == 8) {                                                                            \
+            if ((storage) == 0) hipLaunchKernelGGL((KERNEL<float, 8>), grid, dim3(256), 0, st_, __VA_ARGS__);      \
+            else if ((storage) == 1) hipLaunchKernelGGL((KERNEL<bf16_t, 8>), grid, dim3(256), 0, st_, __VA_ARGS__); \
+            else hipLaunchKernelGGL((KERNEL<_Float16, 8>), grid, dim3(256), 0, st_, __VA_ARGS__);                  \
+        } else {                                                                                   \
+            if ((storage) == 0) hipLaunchKernelGGL((KERNEL<float, 4>), grid, dim3(256), 0, st_, __VA_ARGS__);      \
+            else if ((storage) == 1) hipLaunchKernelGGL((KERNEL<bf16_t, 4>), grid, dim3(256), 0, st_, __VA_ARGS__); \
+            else hipLaunchKernelGGL((KERNEL<_Float16, 4>), grid, dim3(256), 0, st_, __VA_ARGS__);                  \
+        }                                                                                          \
+        return (int)hipGetLastError();                                                             \
+    } while (0)
+
+static dim3 grid_for(int B, int nb)
+{
+    return dim3((unsigned)std::max(1, B == 8 ? groups<8>(nb) : groups<4>(nb)));
+}
+
+int cg_launch_residual(int storage, int B, const CgArgs &a, int store, void *stream)
+{
+    CG_DISPATCH(storage, B, k_cg_residual, grid_for(B, a.nb), stream, a, store);
+}
+int cg_launch_matvec(int storage, int B, const CgArgs &a, void *stream)
+{
+    CG_DISPATCH(storage, B, k_cg_matvec, grid_for(B, a.nb), stream, a);
+}
+int cg_launch_update(int storage, int B, const CgArgs &a, void *stream)
+{
+    CG_DISPATCH(storage, B, k_cg_update, grid_for(B, a.nb), stream, a);
+}
+int cg_launch_pupdate(int storage, int B, const CgArgs &a, void *stream)
+{
+    CG_DISPATCH(storage, B, k_cg_pupdate, grid_for(B, a.nb), stream, a);
+}
+int cg_launch_flux(int storage, int B, const CgArgs &a, int inlet_face, void *stream)
+{
+    CG_DISPATCH(storage, B, k_cg_flux, grid_for(B, a.nb), stream, a, inlet_face);
+}
+int cg_launch_segsum(const CgArgs &a, int slot0, int slot1, void *stream)
+{
+    hipLaunchKernelGGL(k_cg_segsum, dim3((unsigned)a.ngeom), dim3(256), 0, (hipStream_t)stream,
+                       a.partial, a.geom, a.ngeom, a.nb, a.scal, slot0, slot1);
+    return (int)hipGetLastError();
+}
+int cg_launch_scalars(const CgArgs &a, int mode, void *stream)
+{
+    hipLaunchKernelGGL(k_cg_scalars, dim3((unsigned)((a.ngeom + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, a.scal, a.ngeom, mode);
+    return (int)hipGetLastError();
+}

@@ -15,56 +15,28 @@
 
 namespace {
 
-template <int B>
-struct Cfg {
-    static constexpr int BPW = B == 8 ? 1 : 4;  // blocks per workgroup
-    static constexpr int TPB = 256 / BPW;       // threads per block
-    static constexpr int VPT = Blk<B>::NS / TPB;  // voxels per thread
-};
-
-// Map a workgroup id to a group of blocks.  With xcd_chunk > 0 the consecutive
-// workgroups that the dispatcher sends round-robin to the 8 XCDs are remapped so
-// that each XCD walks one contiguous range of the block list (its own L2 then
-// holds the +-x / +-y neighbours it needs).
-__device__ __forceinline__ int map_group(int wg, int xcd_chunk)
+// Store one updated value (round to nearest, or stochastic rounding when enabled).
+template <typename T>
+__device__ __forceinline__ void store_val(const StepArgs &a, T *cout, int s, int64_t idx,
+                                          int64_t slot_id, float r)
 {
-    if (xcd_chunk <= 0) return wg;
-    return (wg & 7) * xcd_chunk + (wg >> 3);
-}
-
-template <typename T, int B>
-__device__ __forceinline__ void stage_tile(float (*tile)[Blk<B>::TL], const T *c, int64_t sstride,
-                                           int S, int b, const BlockInfo &bi, int lt, bool valid)
-{
-    using K = Blk<B>;
-    using C = Cfg<B>;
-    if (!valid) return;
-    const int64_t base = (int64_t)b * K::NS;
-    for (int s = 0; s < S; ++s) {
-#pragma unroll
-        for (int k = 0; k < C::VPT; ++k) {
-            const int slot = lt + k * C::TPB;
-            const int lx = slot % B, ly = (slot / B) % B, lz = slot / (B * B);
-            tile[s][K::tidx(lx, ly, lz)] = rd_ld(c, s * sstride + base + slot);
-        }
-    }
-    for (int h = lt; h < 6 * B * B; h += C::TPB) {
-        const int f = h / (B * B);
-        const int r = h % (B * B);
-        int nslot, tix;
-        halo_slot<B>(f, r % B, r / B, &nslot, &tix);
-        const int n = bi.nbr[f];
-        for (int s = 0; s < S; ++s)
-            tile[s][tix] = n >= 0 ? rd_ld(c, s * sstride + (int64_t)n * K::NS + nslot) : 0.0f;
+    if (a.sround) {
+        const uint32_t step = *a.ctr + a.ctr_off;
+        rd_st_sr(cout, idx, r, sr_bits(slot_id, s, step, a.seed));
+    } else {
+        rd_st(cout, idx, r);
     }
 }
 
-template <typename T, int B>
+// Generic step (used for B = 4): the block's mask record is staged in LDS so the
+// per-thread bit lookups index shared memory instead of a private array.
+template <typename T, int B, int S>
 __global__ __launch_bounds__(256) void k_step(StepArgs a)
 {
     using K = Blk<B>;
     using C = Cfg<B>;
-    __shared__ float tile[C::BPW][RD_MAX_SPECIES][K::TL];
+    __shared__ float tile[C::BPW][S][K::TL];
+    __shared__ uint64_t srec[C::BPW][K::MW];
 
     const int sub = threadIdx.x / C::TPB;
     const int lt = threadIdx.x % C::TPB;
@@ -75,18 +47,14 @@ __global__ __launch_bounds__(256) void k_step(StepArgs a)
     T *cout = (T *)a.cout;
 
     BlockInfo bi = {};
-    uint64_t rec[K::MW];
     if (valid) {
         bi = a.info[b];
-#pragma unroll
-        for (int w = 0; w < K::MW; ++w) rec[w] = a.mask[(int64_t)b * K::MW + w];
-    } else {
-#pragma unroll
-        for (int w = 0; w < K::MW; ++w) rec[w] = 0;
+        if (lt < K::MW) srec[sub][lt] = a.mask[(int64_t)b * K::MW + lt];
     }
-    stage_tile<T, B>(tile[sub], cin, a.sstride, a.S, b, bi, lt, valid);
+    stage_tile<T, B>(tile[sub], cin, a.sstride, S, b, bi, lt, valid);
     __syncthreads();
     if (!valid) return;
+    const uint64_t *rec = srec[sub];
 
     int bx, by, bz, gid;
     block_pos(bi, &bx, &by, &bz, &gid);
@@ -102,9 +70,11 @@ __global__ __launch_bounds__(256) void k_step(StepArgs a)
         const unsigned nbm = act ? nb_bits<B>(rec, lx, ly, lz, gx, gy, gz, g.nx, g.ny, g.nz, &nwall)
                                  : 0u;
         const int t = K::tidx(lx, ly, lz);
-        float cen[RD_MAX_SPECIES];
-        for (int s = 0; s < a.S; ++s) cen[s] = tile[sub][s][t];
-        for (int s = 0; s < a.S; ++s) {
+        float cen[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) cen[s] = tile[sub][s][t];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
             float r;
             if (!act) {
                 r = 0.0f;
@@ -114,16 +84,311 @@ __global__ __launch_bounds__(256) void k_step(StepArgs a)
                 const float *ts = tile[sub][s];
                 const float nbv[6] = {ts[t - 1], ts[t + 1], ts[t - K::E], ts[t + K::E],
                                       ts[t - K::E * K::E], ts[t + K::E * K::E]};
-                r = rd_update(cen[s], nbv, nbm, nwall, a.coef[s], cen, a.S);
+                r = rd_update<S>(cen[s], nbv, nbm, nwall, a.coef[s], cen);
             }
-            if (a.sround) {
-                const uint32_t step = *a.ctr + a.ctr_off;
-                rd_st_sr(cout, s * a.sstride + base + slot, r,
-                         sr_bits(base + slot, s, step, a.seed));
+            store_val(a, cout, s, s * a.sstride + base + slot, voxel_id(g, gx, gy, gz), r);
+        }
+    }
+}
+
+// B = 8 step.  Wave w (0..3) owns the planes lz = w and lz = w + 4 of the block, lane
+// (lx, ly) = (l % 8, l / 8), so every mask word a wave needs (own planes lz-1..lz+1
+// and the six face words) is wave-uniform and read with scalar loads.  Each thread
+// issues all of its global loads (2 own values and 1-2 halo values per species)
+// before the first wait; the halo of face w (x / y faces) and of face 4 + w (z faces,
+// waves 0-1) goes through the wave-uniform neighbour index.
+template <typename T, int S>
+__global__ __launch_bounds__(256) void k_step8(StepArgs a)
+{
+    using K = Blk<8>;
+    __shared__ float tile[S][K::TL];
+    const int b = map_group(blockIdx.x, a.xcd_chunk);
+    if (b >= a.nb) return;  // the whole workgroup leaves together
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int lx = lane & 7, ly = lane >> 3;
+    const T *cin = (const T *)a.cin;
+    T *cout = (T *)a.cout;
+    const int64_t base = (int64_t)b * K::NS;
+    const int32_t *nbr = a.info[b].nbr;
+
+    float c0[S], c1[S], h0[S], h1[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        c0[s] = rd_ld(cin, s * a.sstride + base + w * 64 + lane);
+        c1[s] = rd_ld(cin, s * a.sstride + base + (w + 4) * 64 + lane);
+    }
+    int ns0, tx0, ns1 = 0, tx1 = 0;
+    halo_slot<8>(w, lx, ly, &ns0, &tx0);
+    const int n0 = nbr[w];
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+        h0[s] = n0 >= 0 ? rd_ld(cin, s * a.sstride + (int64_t)n0 * K::NS + ns0) : 0.0f;
+    const bool zf = w < 2;
+    if (zf) {
+        halo_slot<8>(4 + w, lx, ly, &ns1, &tx1);
+        const int n1 = nbr[4 + w];
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+            h1[s] = n1 >= 0 ? rd_ld(cin, s * a.sstride + (int64_t)n1 * K::NS + ns1) : 0.0f;
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        tile[s][K::tidx(lx, ly, w)] = c0[s];
+        tile[s][K::tidx(lx, ly, w + 4)] = c1[s];
+        tile[s][tx0] = h0[s];
+        if (zf) tile[s][tx1] = h1[s];
+    }
+    __syncthreads();
+
+    const uint64_t *rec = a.mask + (int64_t)b * K::MW;
+    const BlockInfo bi = a.info[b];
+    int bx, by, bz, gid;
+    block_pos(bi, &bx, &by, &bz, &gid);
+    const GeomInfo g = a.geom[gid];
+    const uint64_t fx0 = rec[8], fx1 = rec[9], fy0 = rec[10], fy1 = rec[11];
+    const int bit = ly * 8 + lx;
+    const int gx = bx * 8 + lx, gy = by * 8 + ly;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int lz = w + 4 * k;
+        const uint64_t W = rec[lz];
+        const uint64_t Wm = lz > 0 ? rec[lz - 1] : rec[12];
+        const uint64_t Wp = lz < 7 ? rec[lz + 1] : rec[13];
+        const int gz = bz * 8 + lz;
+        const bool act = (W >> bit) & 1ull;
+        unsigned m = 0;
+        m |= (lx > 0 ? (W >> (bit - 1)) & 1ull : (fx0 >> (lz * 8 + ly)) & 1ull) ? 1u : 0u;
+        m |= (lx < 7 ? (W >> (bit + 1)) & 1ull : (fx1 >> (lz * 8 + ly)) & 1ull) ? 2u : 0u;
+        m |= (ly > 0 ? (W >> (bit - 8)) & 1ull : (fy0 >> (lz * 8 + lx)) & 1ull) ? 4u : 0u;
+        m |= (ly < 7 ? (W >> (bit + 8)) & 1ull : (fy1 >> (lz * 8 + lx)) & 1ull) ? 8u : 0u;
+        m |= ((Wm >> bit) & 1ull) ? 16u : 0u;
+        m |= ((Wp >> bit) & 1ull) ? 32u : 0u;
+        unsigned inbox = 0;
+        inbox |= gx > 0 ? 1u : 0u;
+        inbox |= gx < g.nx - 1 ? 2u : 0u;
+        inbox |= gy > 0 ? 4u : 0u;
+        inbox |= gy < g.ny - 1 ? 8u : 0u;
+        inbox |= gz > 0 ? 16u : 0u;
+        inbox |= gz < g.nz - 1 ? 32u : 0u;
+        const int nwall = __popc(inbox & ~m);
+        const int t = K::tidx(lx, ly, lz);
+        const int slot = lz * 64 + lane;
+        float cen[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) cen[s] = k == 0 ? c0[s] : c1[s];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            float r;
+            if (!act) {
+                r = 0.0f;
+            } else if (on_dirichlet(a.coef[s].dir, gx, gy, gz, g.nx, g.ny, g.nz)) {
+                r = cen[s];
             } else {
-                rd_st(cout, s * a.sstride + base + slot, r);
+                const float *ts = tile[s];
+                const float nbv[6] = {ts[t - 1], ts[t + 1], ts[t - K::E], ts[t + K::E],
+                                      ts[t - K::E * K::E], ts[t + K::E * K::E]};
+                r = rd_update<S>(cen[s], nbv, m, nwall, a.coef[s], cen);
+            }
+            store_val(a, cout, s, s * a.sstride + base + slot, voxel_id(g, gx, gy, gz), r);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent B = 8 step.  A fixed grid of workgroups walks the block list; while
+// block k is computed from LDS, the loads of block k+1 (own slots, halos, mask
+// record) are already in flight in registers, so every wave keeps HBM requests
+// outstanding across the barrier-compute-store phase.  Thread mapping: wave w
+// owns planes lz = 2w, 2w+1; lane l holds the x-adjacent pair lx = 2(l%4), +1 at
+// ly = (l/4)%8, lz = 2w + l/32, so own slots move as one 8-byte (FP32) or 4-byte
+// (BF16 / FP16) access.  With xcd_chunk > 0, XCD x (= workgroup id mod 8) walks
+// the x-th eighth of the list, so +-x / +-y halos are mostly hits in its own L2.
+// ---------------------------------------------------------------------------
+namespace p8 {
+constexpr int TX = 12;            // padded x extent of the LDS tile: [pad, -x, 0..7, +x, pad]
+constexpr int TY = 10, TZ = 10;   // y and z extents with halos
+constexpr int TL = TX * TY * TZ;  // 1200 words per species
+__device__ __forceinline__ int tix(int lx, int ly, int lz)
+{
+    return ((lz + 1) * TY + (ly + 1)) * TX + (lx + 2);
+}
+// neighbour-block slot and tile index of face f at face coordinates (u, v)
+__device__ __forceinline__ void halo(int f, int u, int v, int *ns, int *t)
+{
+    switch (f) {
+    case 0: *ns = (v * 8 + u) * 8 + 7; *t = tix(-1, u, v); break;
+    case 1: *ns = (v * 8 + u) * 8 + 0; *t = tix(8, u, v); break;
+    case 2: *ns = (v * 8 + 7) * 8 + u; *t = tix(u, -1, v); break;
+    case 3: *ns = (v * 8 + 0) * 8 + u; *t = tix(u, 8, v); break;
+    case 4: *ns = (7 * 8 + v) * 8 + u; *t = tix(u, v, -1); break;
+    default: *ns = (0 * 8 + v) * 8 + u; *t = tix(u, v, 8); break;
+    }
+}
+__device__ __forceinline__ int pick6(int i, const BlockInfo &bi)
+{
+    int r = bi.nbr[0];
+    r = i == 1 ? bi.nbr[1] : r;
+    r = i == 2 ? bi.nbr[2] : r;
+    r = i == 3 ? bi.nbr[3] : r;
+    r = i == 4 ? bi.nbr[4] : r;
+    r = i == 5 ? bi.nbr[5] : r;
+    return r;
+}
+template <int S>
+struct Regs {
+    float c0[S], c1[S], h0[S], h1[S];
+    uint64_t mw;
+};
+}  // namespace p8
+
+template <typename T, int S>
+__device__ __forceinline__ void p8_load(const StepArgs &a, const T *cin, int b, const BlockInfo &bi,
+                                        int w, int lane, int slot0, int ns0, int ns1,
+                                        p8::Regs<S> &r)
+{
+    const int64_t base = (int64_t)b * 512;
+#pragma unroll
+    for (int s = 0; s < S; ++s) rd_ld2(cin, s * a.sstride + base + slot0, r.c0[s], r.c1[s]);
+    const int n0 = p8::pick6(w, bi);
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+        r.h0[s] = n0 >= 0 ? rd_ld(cin, s * a.sstride + (int64_t)n0 * 512 + ns0) : 0.0f;
+    if (w < 2) {
+        const int n1 = p8::pick6(4 + w, bi);
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+            r.h1[s] = n1 >= 0 ? rd_ld(cin, s * a.sstride + (int64_t)n1 * 512 + ns1) : 0.0f;
+    }
+    if (threadIdx.x < 16) r.mw = a.mask[(int64_t)b * 16 + threadIdx.x];
+}
+
+template <typename T, int S>
+__global__ __launch_bounds__(256) void k_step8p(StepArgs a)
+{
+    __shared__ __align__(16) float tile[S][p8::TL];
+    __shared__ uint64_t srec[16];
+
+    // block range of this workgroup
+    int64_t lo = 0, hi = a.nb;
+    int first = blockIdx.x, stride = gridDim.x;
+    if (a.xcd_chunk > 0) {
+        const int x = blockIdx.x & 7, per = gridDim.x >> 3;
+        lo = (int64_t)a.nb * x / 8;
+        hi = (int64_t)a.nb * (x + 1) / 8;
+        first = (int)lo + (blockIdx.x >> 3);
+        stride = per;
+    }
+    int b = first;
+    if (b >= hi) return;  // uniform: the whole workgroup leaves
+
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int lx2 = lane & 3, ly = (lane >> 2) & 7, lzp = 2 * w + (lane >> 5);
+    const int slot0 = (lzp * 8 + ly) * 8 + 2 * lx2;
+    int ns0, tx0, ns1 = 0, tx1 = 0;
+    p8::halo(w, lane & 7, lane >> 3, &ns0, &tx0);
+    if (w < 2) p8::halo(4 + w, lane & 7, lane >> 3, &ns1, &tx1);
+    const T *cin = (const T *)a.cin;
+    T *cout = (T *)a.cout;
+    const bool sr = a.sround != 0;
+    const uint32_t step = sr ? *a.ctr + a.ctr_off : 0u;
+
+    BlockInfo bi = a.info[b];
+    p8::Regs<S> cur;
+    p8_load<T, S>(a, cin, b, bi, w, lane, slot0, ns0, ns1, cur);
+    int bn = b + stride;
+    BlockInfo bin = bn < hi ? a.info[bn] : bi;
+
+    for (;;) {
+        // stage block b
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            *reinterpret_cast<float2 *>(&tile[s][p8::tix(2 * lx2, ly, lzp)]) =
+                make_float2(cur.c0[s], cur.c1[s]);
+            tile[s][tx0] = cur.h0[s];
+            if (w < 2) tile[s][tx1] = cur.h1[s];
+        }
+        if (threadIdx.x < 16) srec[threadIdx.x] = cur.mw;
+        __syncthreads();
+
+        // prefetch block bn (and the neighbour list of the one after)
+        const bool more = bn < hi;
+        p8::Regs<S> nxt;
+        if (more) p8_load<T, S>(a, cin, bn, bin, w, lane, slot0, ns0, ns1, nxt);
+        const int bnn = bn + stride;
+        const BlockInfo binn = (more && bnn < hi) ? a.info[bnn] : bin;
+
+        // compute block b
+        int bx, by, bz, gid;
+        block_pos(bi, &bx, &by, &bz, &gid);
+        const GeomInfo g = a.geom[gid];
+        const uint64_t W = srec[lzp];
+        const uint64_t Wm = lzp > 0 ? srec[lzp - 1] : srec[12];
+        const uint64_t Wp = lzp < 7 ? srec[lzp + 1] : srec[13];
+        const uint64_t fx0 = srec[8], fx1 = srec[9], fy0 = srec[10], fy1 = srec[11];
+        const int gy = by * 8 + ly, gz = bz * 8 + lzp;
+        const int64_t base = (int64_t)b * 512;
+        float res[2][S];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int lx = 2 * lx2 + j;
+            const int gx = bx * 8 + lx;
+            const int bit = ly * 8 + lx;
+            const bool act = (W >> bit) & 1ull;
+            unsigned m = 0;
+            m |= (lx > 0 ? (W >> (bit - 1)) & 1ull : (fx0 >> (lzp * 8 + ly)) & 1ull) ? 1u : 0u;
+            m |= (lx < 7 ? (W >> (bit + 1)) & 1ull : (fx1 >> (lzp * 8 + ly)) & 1ull) ? 2u : 0u;
+            m |= (ly > 0 ? (W >> (bit - 8)) & 1ull : (fy0 >> (lzp * 8 + lx)) & 1ull) ? 4u : 0u;
+            m |= (ly < 7 ? (W >> (bit + 8)) & 1ull : (fy1 >> (lzp * 8 + lx)) & 1ull) ? 8u : 0u;
+            m |= ((Wm >> bit) & 1ull) ? 16u : 0u;
+            m |= ((Wp >> bit) & 1ull) ? 32u : 0u;
+            unsigned inbox = 0;
+            inbox |= gx > 0 ? 1u : 0u;
+            inbox |= gx < g.nx - 1 ? 2u : 0u;
+            inbox |= gy > 0 ? 4u : 0u;
+            inbox |= gy < g.ny - 1 ? 8u : 0u;
+            inbox |= gz > 0 ? 16u : 0u;
+            inbox |= gz < g.nz - 1 ? 32u : 0u;
+            const int nwall = __popc(inbox & ~m);
+            const int t = p8::tix(lx, ly, lzp);
+            float cen[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) cen[s] = j == 0 ? cur.c0[s] : cur.c1[s];
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                float r;
+                if (!act) {
+                    r = 0.0f;
+                } else if (on_dirichlet(a.coef[s].dir, gx, gy, gz, g.nx, g.ny, g.nz)) {
+                    r = cen[s];
+                } else {
+                    const float *ts = tile[s];
+                    const float nbv[6] = {ts[t - 1], ts[t + 1], ts[t - p8::TX], ts[t + p8::TX],
+                                          ts[t - p8::TX * p8::TY], ts[t + p8::TX * p8::TY]};
+                    r = rd_update<S>(cen[s], nbv, m, nwall, a.coef[s], cen);
+                }
+                res[j][s] = r;
             }
         }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int64_t idx = s * a.sstride + base + slot0;
+            uint32_t r0 = 0, r1 = 0;
+            if (sr) {
+                const int64_t v0 = voxel_id(g, bx * 8 + 2 * lx2, gy, gz);
+                r0 = sr_bits(v0, s, step, a.seed);
+                r1 = sr_bits(v0 + 1, s, step, a.seed);
+            }
+            rd_st2(cout, idx, res[0][s], res[1][s], sr, r0, r1);
+        }
+        if (!more) break;
+        __syncthreads();  // every wave is done with the tile before it is refilled
+        cur = nxt;
+        b = bn;
+        bi = bin;
+        bn = bnn;
+        bin = binn;
     }
 }
 
@@ -136,6 +401,7 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a)
     using K = Blk<B>;
     using C = Cfg<B>;
     __shared__ float tile[C::BPW][1][K::TL];
+    __shared__ uint64_t srec[C::BPW][K::MW];
     __shared__ double wsum[4][RD_NRED];
 
     const int sub = threadIdx.x / C::TPB;
@@ -145,18 +411,14 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a)
     const T *c = (const T *)a.c;
 
     BlockInfo bi = {};
-    uint64_t rec[K::MW];
     if (valid) {
         bi = a.info[b];
-#pragma unroll
-        for (int w = 0; w < K::MW; ++w) rec[w] = a.mask[(int64_t)b * K::MW + w];
-    } else {
-#pragma unroll
-        for (int w = 0; w < K::MW; ++w) rec[w] = 0;
+        if (lt < K::MW) srec[sub][lt] = a.mask[(int64_t)b * K::MW + lt];
     }
     const T *cs = c + a.s * a.sstride;
     stage_tile<T, B>(tile[sub], cs, 0, 1, b, bi, lt, valid);
     __syncthreads();
+    const uint64_t *rec = srec[sub];
 
     double acc[RD_NRED];
 #pragma unroll
@@ -188,12 +450,17 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a)
                 const int off[6] = {-1, 1, -K::E, K::E, -K::E * K::E, K::E * K::E};
                 const int ddx[6] = {-1, 1, 0, 0, 0, 0}, ddy[6] = {0, 0, -1, 1, 0, 0},
                           ddz[6] = {0, 0, 0, 0, -1, 1};
+                double fin = 0.0;
+#pragma unroll
                 for (int d = 0; d < 6; ++d) {
                     if (!((nbm >> d) & 1u)) continue;
                     if (on_dirichlet(a.dir, gx + ddx[d], gy + ddy[d], gz + ddz[d], g.nx, g.ny, g.nz))
                         continue;
-                    acc[1 + fq] += a.D * (u - (double)ts[t + off[d]]) * dx;
+                    fin += a.D * (u - (double)ts[t + off[d]]) * dx;
                 }
+#pragma unroll
+                for (int f = 0; f < 6; ++f)
+                    if (f == fq) acc[1 + f] += fin;
                 continue;
             }
             acc[0] += u * dx3;
@@ -336,12 +603,29 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, uint32_t v, int64
 template <int B>
 int groups_for(int nb) { return (nb + Cfg<B>::BPW - 1) / Cfg<B>::BPW; }
 
+template <typename T, int B, int S>
+void launch_step_s(const StepArgs &a, int groups, hipStream_t st)
+{
+    if constexpr (B == 8) {
+        if (a.persist)
+            hipLaunchKernelGGL((k_step8p<T, S>), dim3(a.grid), dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_step8<T, S>), dim3(groups), dim3(256), 0, st, a);
+    } else
+        hipLaunchKernelGGL((k_step<T, B, S>), dim3(groups), dim3(256), 0, st, a);
+}
+
 template <typename T, int B>
 int launch_step_t(const StepArgs &a, hipStream_t st)
 {
     int groups = groups_for<B>(a.nb);
     if (a.xcd_chunk > 0) groups = 8 * a.xcd_chunk;
-    hipLaunchKernelGGL((k_step<T, B>), dim3(groups), dim3(256), 0, st, a);
+    switch (a.S) {
+    case 1: launch_step_s<T, B, 1>(a, groups, st); break;
+    case 2: launch_step_s<T, B, 2>(a, groups, st); break;
+    case 3: launch_step_s<T, B, 3>(a, groups, st); break;
+    default: launch_step_s<T, B, 4>(a, groups, st); break;
+    }
     return (int)hipGetLastError();
 }
 

@@ -18,20 +18,6 @@ rd_status rd_fail(rd_status s, const std::string &msg)
     return s;
 }
 
-#define HIPCHK(expr)                                                                         \
-    do {                                                                                     \
-        hipError_t e_ = (expr);                                                              \
-        if (e_ != hipSuccess)                                                                \
-            return rd_fail(RD_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));   \
-    } while (0)
-#define LAUNCHCHK(expr)                                                                      \
-    do {                                                                                     \
-        int e_ = (expr);                                                                     \
-        if (e_ != 0)                                                                         \
-            return rd_fail(RD_ERR_HIP, std::string(#expr) + ": " +                           \
-                                           hipGetErrorString((hipError_t)e_));               \
-    } while (0)
-
 extern "C" const char *rd_status_string(rd_status s)
 {
     switch (s) {
@@ -207,12 +193,23 @@ extern "C" rd_status rd_sim_clear_dirichlet(rd_sim *sim, int species)
     return RD_OK;
 }
 
-extern "C" rd_status rd_sim_set_launch(rd_sim *sim, int graph_steps, int use_graph)
+extern "C" rd_status rd_sim_set_launch(rd_sim *sim, int graph_steps, int use_graph, int xcd_map)
 {
     if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
     if (graph_steps < 1 || graph_steps > 4096) return rd_fail(RD_ERR_ARG, "graph_steps in 1..4096");
     sim->graph_steps = graph_steps;
     sim->use_graph = use_graph != 0;
+    sim->xcd_map = xcd_map != 0;
+    sim->invalidate_graphs();
+    return RD_OK;
+}
+
+extern "C" rd_status rd_sim_set_kernel(rd_sim *sim, int persistent, int wg_per_cu)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    if (wg_per_cu < 1 || wg_per_cu > 32) return rd_fail(RD_ERR_ARG, "wg_per_cu in 1..32");
+    sim->persist = persistent != 0;
+    sim->wg_per_cu = wg_per_cu;
     sim->invalidate_graphs();
     return RD_OK;
 }
@@ -321,6 +318,10 @@ rd_status rd_sim::upload()
 {
     const rd_geometry &G = *g;
     const int64_t nb = G.nb();
+    int dev = 0, ncu = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    if (ncu > 0) n_cu = ncu;
     HIPCHK(hipMemcpyAsync(ws + L.info, G.info.data(), sizeof(BlockInfo) * nb, hipMemcpyHostToDevice, stream));
     HIPCHK(hipMemcpyAsync(ws + L.mask, G.mask.data(), 8 * mask_words(G.B) * nb, hipMemcpyHostToDevice, stream));
     GeomInfo gi{(int32_t)G.nx, (int32_t)G.ny, (int32_t)G.nz, 0};
@@ -417,12 +418,25 @@ rd_status rd_sim::check_dt(double dt) const
 
 uint32_t *rd_sim::step_counter() const { return (uint32_t *)(ws + L.res + 384); }
 
+void rd_sim::launch_shape(StepArgs &a) const
+{
+    a.xcd_chunk = xcd_chunk(a.nb);
+    a.persist = (persist && g->B == 8) ? 1 : 0;
+    if (a.persist) {
+        // a multiple of 8 (one share per XCD), no more workgroups than blocks need
+        int grid = n_cu * wg_per_cu;
+        const int need = ((a.nb + 7) / 8) * 8;
+        if (grid > need) grid = need;
+        a.grid = std::max(8, (grid / 8) * 8);
+    }
+}
+
 rd_status rd_sim::launch_steps(double dt, int64_t n)
 {
     const bool sr = sround && storage != RD_FP32;
     for (int64_t i = 0; i < n; ++i) {
         StepArgs a = step_args(dt, cur);
-        a.xcd_chunk = xcd_chunk(a.nb);
+        launch_shape(a);
         a.sround = sr ? 1 : 0;
         a.seed = seed;
         a.ctr = step_counter();

@@ -26,20 +26,17 @@ __device__ __forceinline__ float rd_ld(const bf16_t *p, int64_t i)
 }
 __device__ __forceinline__ float rd_ld(const _Float16 *p, int64_t i) { return (float)p[i]; }
 
-__device__ __forceinline__ void rd_st(float *p, int64_t i, float v) { p[i] = v; }
-__device__ __forceinline__ void rd_st(bf16_t *p, int64_t i, float v)
+// BF16 round to nearest even on the upper 16 bits; NaN stays NaN (quiet bit set).
+__device__ __forceinline__ uint16_t bf16_rne(float v)
 {
-    // round to nearest even on the upper 16 bits; NaN stays NaN (quiet bit set)
     uint32_t u = __float_as_uint(v);
-    uint16_t r;
-    if ((u & 0x7fffffffu) > 0x7f800000u) {
-        r = (uint16_t)((u >> 16) | 0x40u);
-    } else {
-        u += 0x7fffu + ((u >> 16) & 1u);
-        r = (uint16_t)(u >> 16);
-    }
-    p[i].bits = r;
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
 }
+
+__device__ __forceinline__ void rd_st(float *p, int64_t i, float v) { p[i] = v; }
+__device__ __forceinline__ void rd_st(bf16_t *p, int64_t i, float v) { p[i].bits = bf16_rne(v); }
 __device__ __forceinline__ void rd_st(_Float16 *p, int64_t i, float v) { p[i] = (_Float16)v; }
 
 // ---- stochastic rounding --------------------------------------------------
@@ -63,27 +60,21 @@ __device__ __forceinline__ uint32_t sr_bits(int64_t slot, int species, uint32_t 
 
 // Store with stochastic rounding: round up with probability equal to the distance
 // from the lower neighbour, in units of the storage spacing (unbiased on average).
-__device__ __forceinline__ void rd_st_sr(float *p, int64_t i, float v, uint32_t) { p[i] = v; }
-__device__ __forceinline__ void rd_st_sr(bf16_t *p, int64_t i, float v, uint32_t rnd)
+__device__ __forceinline__ uint16_t bf16_sr(float v, uint32_t rnd)
 {
     // BF16 is the upper half of the FP32 pattern: adding 16 random bits below the cut
     // and truncating rounds the magnitude up with probability (low bits) / 2^16
     uint32_t u = __float_as_uint(v);
-    if ((u & 0x7f800000u) == 0x7f800000u) {  // inf / NaN: nearest
-        rd_st(p, i, v);
-        return;
-    }
+    if ((u & 0x7f800000u) == 0x7f800000u) return bf16_rne(v);  // inf / NaN: nearest
     u += rnd & 0xffffu;
-    p[i].bits = (uint16_t)(u >> 16);
+    return (uint16_t)(u >> 16);
 }
-__device__ __forceinline__ void rd_st_sr(_Float16 *p, int64_t i, float v, uint32_t rnd)
+
+__device__ __forceinline__ _Float16 f16_sr(float v, uint32_t rnd)
 {
     const _Float16 h = (_Float16)v;
     const float hf = (float)h;
-    if (hf == v || !isfinite(v) || !isfinite(hf)) {
-        p[i] = h;
-        return;
-    }
+    if (hf == v || !isfinite(v) || !isfinite(hf)) return h;
     // the FP16 neighbour of h on the other side of v
     uint16_t b = __builtin_bit_cast(uint16_t, h);
     const bool neg = (b & 0x8000u) != 0;
@@ -96,7 +87,61 @@ __device__ __forceinline__ void rd_st_sr(_Float16 *p, int64_t i, float v, uint32
     const float lo = fminf(hf, of), hi = fmaxf(hf, of);
     const float prob_up = (v - lo) / (hi - lo);
     const float u01 = (float)(rnd >> 8) * (1.0f / 16777216.0f);
-    p[i] = u01 < prob_up ? (hf > of ? h : o) : (hf > of ? o : h);
+    return u01 < prob_up ? (hf > of ? h : o) : (hf > of ? o : h);
+}
+
+__device__ __forceinline__ void rd_st_sr(float *p, int64_t i, float v, uint32_t) { p[i] = v; }
+__device__ __forceinline__ void rd_st_sr(bf16_t *p, int64_t i, float v, uint32_t rnd)
+{
+    p[i].bits = bf16_sr(v, rnd);
+}
+__device__ __forceinline__ void rd_st_sr(_Float16 *p, int64_t i, float v, uint32_t rnd)
+{
+    p[i] = f16_sr(v, rnd);
+}
+
+// ---- paired access: two x-adjacent slots (index i even) in one 8- or 4-byte access
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void rd_ld2(const float *p, int64_t i, float &a, float &b)
+{
+    const float2 v = *reinterpret_cast<const float2 *>(p + i);
+    a = v.x;
+    b = v.y;
+}
+__device__ __forceinline__ void rd_ld2(const bf16_t *p, int64_t i, float &a, float &b)
+{
+    const uint32_t u = *reinterpret_cast<const uint32_t *>(p + i);
+    a = __uint_as_float(u << 16);
+    b = __uint_as_float(u & 0xffff0000u);
+}
+__device__ __forceinline__ void rd_ld2(const _Float16 *p, int64_t i, float &a, float &b)
+{
+    const half2_t v = *reinterpret_cast<const half2_t *>(p + i);
+    a = (float)v.x;
+    b = (float)v.y;
+}
+
+// Store a pair; sr selects stochastic rounding with the per-slot random words r0, r1.
+__device__ __forceinline__ void rd_st2(float *p, int64_t i, float a, float b, bool, uint32_t,
+                                       uint32_t)
+{
+    *reinterpret_cast<float2 *>(p + i) = make_float2(a, b);
+}
+__device__ __forceinline__ void rd_st2(bf16_t *p, int64_t i, float a, float b, bool sr, uint32_t r0,
+                                       uint32_t r1)
+{
+    const uint32_t lo = sr ? bf16_sr(a, r0) : bf16_rne(a);
+    const uint32_t hi = sr ? bf16_sr(b, r1) : bf16_rne(b);
+    *reinterpret_cast<uint32_t *>(p + i) = lo | (hi << 16);
+}
+__device__ __forceinline__ void rd_st2(_Float16 *p, int64_t i, float a, float b, bool sr,
+                                       uint32_t r0, uint32_t r1)
+{
+    half2_t v;
+    v.x = sr ? f16_sr(a, r0) : (_Float16)a;
+    v.y = sr ? f16_sr(b, r1) : (_Float16)b;
+    *reinterpret_cast<half2_t *>(p + i) = v;
 }
 
 // ---- block geometry helpers -------------------------------------------------
@@ -170,8 +215,9 @@ __device__ __forceinline__ bool on_dirichlet(uint32_t dir, int gx, int gy, int g
 // The FTCS update of one free voxel of one species (see rd.h):
 //   lap = sum over active neighbours, in order -x,+x,-y,+y,-z,+z, of (c_q - c_p)
 //   c'  = c + alpha*lap - (beta + gamma*n_wall)*c + sum_b K_b c_b
+template <int S>
 __device__ __forceinline__ float rd_update(float uc, const float nbv[6], unsigned nbm, int nwall,
-                                           const SpeciesCoef &k, const float *cen, int S)
+                                           const SpeciesCoef &k, const float *cen)
 {
     float lap = 0.0f;
 #pragma unroll
@@ -182,8 +228,16 @@ __device__ __forceinline__ float rd_update(float uc, const float nbv[6], unsigne
     float r = fmaf(k.alpha, lap, uc);
     const float loss = fmaf(k.gamma, (float)nwall, k.beta);
     r = fmaf(-loss, uc, r);
+#pragma unroll
     for (int b = 0; b < S; ++b) r = fmaf(k.K[b], cen[b], r);
     return r;
+}
+
+// Linear index of a voxel in its (nz, ny, nx) box: the key of the stochastic-rounding
+// hash, so the random bits do not depend on the block layout.
+__device__ __forceinline__ int64_t voxel_id(const GeomInfo &g, int gx, int gy, int gz)
+{
+    return ((int64_t)gz * g.ny + gy) * g.nx + gx;
 }
 
 // Block position of list entry b.
@@ -208,6 +262,54 @@ __device__ __forceinline__ void halo_slot(int f, int u, int v, int *nslot, int *
     case 3: *nslot = (v * B + 0) * B + u; *tix = ((v + 1) * K::E + (B + 1)) * K::E + (u + 1); break;
     case 4: *nslot = ((B - 1) * B + v) * B + u; *tix = ((0) * K::E + (v + 1)) * K::E + (u + 1); break;
     default: *nslot = (0 * B + v) * B + u; *tix = ((B + 1) * K::E + (v + 1)) * K::E + (u + 1); break;
+    }
+}
+
+// Generic per-block workgroup shape: B = 8 one block per 256-thread workgroup (two
+// voxels per thread); B = 4 four blocks per workgroup, one wave per block.
+template <int B>
+struct Cfg {
+    static constexpr int BPW = B == 8 ? 1 : 4;    // blocks per workgroup
+    static constexpr int TPB = 256 / BPW;         // threads per block
+    static constexpr int VPT = Blk<B>::NS / TPB;  // voxels per thread
+};
+
+// Map a workgroup id to a group of blocks.  With xcd_chunk > 0 the consecutive
+// workgroups that the dispatcher sends round-robin to the 8 XCDs are remapped so
+// that each XCD walks one contiguous range of the block list (its own L2 then
+// holds the +-x / +-y neighbours it needs).
+__device__ __forceinline__ int map_group(int wg, int xcd_chunk)
+{
+    if (xcd_chunk <= 0) return wg;
+    return (wg & 7) * xcd_chunk + (wg >> 3);
+}
+
+// Stage S fields (species-major, sstride apart) of block b and its six face halos
+// into an LDS tile of (B+2)^3 words per field (FP32).  Missing neighbours give 0.
+template <typename T, int B>
+__device__ __forceinline__ void stage_tile(float (*tile)[Blk<B>::TL], const T *c, int64_t sstride,
+                                           int S, int b, const BlockInfo &bi, int lt, bool valid)
+{
+    using K = Blk<B>;
+    using C = Cfg<B>;
+    if (!valid) return;
+    const int64_t base = (int64_t)b * K::NS;
+    for (int s = 0; s < S; ++s) {
+#pragma unroll
+        for (int k = 0; k < C::VPT; ++k) {
+            const int slot = lt + k * C::TPB;
+            const int lx = slot % B, ly = (slot / B) % B, lz = slot / (B * B);
+            tile[s][K::tidx(lx, ly, lz)] = rd_ld(c, s * sstride + base + slot);
+        }
+    }
+    for (int h = lt; h < 6 * B * B; h += C::TPB) {
+        const int f = h / (B * B);
+        const int r = h % (B * B);
+        int nslot, tix;
+        halo_slot<B>(f, r % B, r / B, &nslot, &tix);
+        const int n = bi.nbr[f];
+        for (int s = 0; s < S; ++s)
+            tile[s][tix] = n >= 0 ? rd_ld(c, s * sstride + (int64_t)n * K::NS + nslot) : 0.0f;
     }
 }
 

@@ -7,6 +7,22 @@
 
 #include "rd_host.h"
 
+#include <string>
+
+#define HIPCHK(expr)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return rd_fail(RD_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+#define LAUNCHCHK(expr)                                                                      \
+    do {                                                                                     \
+        int e_ = (expr);                                                                     \
+        if (e_ != 0)                                                                         \
+            return rd_fail(RD_ERR_HIP, std::string(#expr) + ": " +                           \
+                                           hipGetErrorString((hipError_t)e_));               \
+    } while (0)
+
 struct Reaction {
     int from, to;
     double rate;
@@ -45,7 +61,10 @@ struct rd_sim {
 
     int graph_steps = 32;
     bool use_graph = true;
-    bool xcd_map = false;
+    bool xcd_map = true;
+    bool persist = true;  // B = 8: persistent prefetching kernel
+    int wg_per_cu = 8;    // resident workgroups per CU of the persistent grid
+    int n_cu = 256;       // compute units of the bound device
     bool sround = false;  // stochastic rounding on store (BF16 / FP16 storage)
     uint32_t seed = 0;
 
@@ -73,6 +92,7 @@ struct rd_sim {
     rd_status check_dt(double dt) const;
     int xcd_chunk(int nb) const;
     uint32_t *step_counter() const;
+    void launch_shape(StepArgs &a) const;
     rd_status launch_steps(double dt, int64_t n);
     rd_status step(double dt, int64_t n);
     rd_status balance(int s, double out[RD_NRED]);

@@ -1,43 +1,634 @@
-// rd_solve.cpp -- steady state (conjugate gradients), adjoint and batches.
+// rd_solve.cpp -- steady state and tortuosity by conjugate gradients (one geometry
+// or a batch), and the adjoint driver.
+//
+// Tortuosity (eq. tortuosity: tau = D_f / D_eff) is measured from the steady
+// diffusive flux Q through a box with a unit concentration drop between two
+// opposite face planes: D_eff = Q L / (psi A dT), so tau = psi D dT A / (Q L), with
+// psi the active volume fraction, A the box cross-section and L = (n-1) dx the
+// distance between the Dirichlet planes.  A straight channel gives tau = 1.
 #include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
 
+#include <algorithm>
+#include <limits>
+#include <new>
+#include <vector>
+
+#include "rd_adjoint.h"
 #include "rd_host.h"
 #include "rd_sim.h"
+#include "rd_solve.h"
 
-extern "C" rd_status rd_sim_steady_state(rd_sim *sim, int, double, int64_t, double *, double *,
-                                         int64_t *)
-{
-    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
-    return rd_fail(RD_ERR_STATE, "steady state not available yet");
-}
+namespace {
 
-extern "C" rd_status rd_sim_adjoint(rd_sim *sim, const float *, int64_t, double, int, double *,
-                                    double *, double *)
-{
-    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
-    return rd_fail(RD_ERR_STATE, "adjoint not available yet");
-}
-
-struct rd_batch {
-    int n = 0;
+struct GeomMeta {
+    int64_t nx, ny, nz;
+    double psi;  // active fraction
+    double dx;
+    bool percolates;
 };
 
-extern "C" rd_status rd_batch_create(const rd_geometry *const *, int, rd_storage, rd_batch **out)
+struct CgOut {
+    double tau = 0, rel = 0, qin = 0, qout = 0;
+    int64_t iters = 0;
+    bool converged = false;
+};
+
+constexpr int CHECK_EVERY = 50;   // iterations between true-residual checks
+constexpr int STALL_CHECKS = 20;  // stop after this many checks without a 10% gain
+
+// ---- host labelling of 6-connected active clusters ------------------------
+// Union-find over the active slots (index b * B^3 + slot) of the block grid.
+struct DSU {
+    std::vector<uint32_t> p;
+    uint32_t find(uint32_t x)
+    {
+        while (p[x] != x) {
+            p[x] = p[p[x]];
+            x = p[x];
+        }
+        return x;
+    }
+    void unite(uint32_t a, uint32_t b)
+    {
+        a = find(a);
+        b = find(b);
+        if (a != b) p[a < b ? b : a] = a < b ? a : b;
+    }
+};
+
+inline bool slot_active(const rd_geometry &G, int64_t b, int slot)
 {
-    if (out) *out = nullptr;
-    return rd_fail(RD_ERR_STATE, "batches not available yet");
+    const uint64_t *rec = &G.mask[(size_t)b * mask_words(G.B)];
+    return G.B == 8 ? (rec[slot >> 6] >> (slot & 63)) & 1u : (rec[0] >> slot) & 1u;
 }
-extern "C" rd_status rd_batch_workspace_bytes(const rd_batch *, size_t *)
+
+// Initial guess of the unit-drop steady state along `axis`, in block-major FP32:
+// clusters touching both Dirichlet planes get the linear ramp 1 - c/(n-1); clusters
+// touching only the inlet plane get 1 (their exact solution), all other clusters 0
+// (exact too: a floating cluster's residual is then exactly zero and CG never moves
+// it).  Dirichlet voxels hold 1 (inlet) and 0 (outlet).  Returns whether any
+// cluster touches both planes (otherwise the geometry does not percolate).
+rd_status initial_guess(const rd_geometry &G, int axis, std::vector<float> &x, bool *percolates)
 {
-    return rd_fail(RD_ERR_STATE, "batches not available yet");
+    const int B = G.B, NS = B * B * B;
+    const int64_t nb = G.nb();
+    const int64_t nslots = nb * NS;
+    if (nslots >= (int64_t)UINT32_MAX) return rd_fail(RD_ERR_SHAPE, "too many slots to label");
+    DSU d;
+    try {
+        d.p.resize((size_t)nslots);
+        x.assign((size_t)nslots, 0.0f);
+    } catch (const std::bad_alloc &) {
+        return rd_fail(RD_ERR_ARG, "out of host memory for labelling");
+    }
+    for (int64_t i = 0; i < nslots; ++i) d.p[(size_t)i] = (uint32_t)i;
+    for (int64_t b = 0; b < nb; ++b) {
+        const BlockInfo &bi = G.info[b];
+        for (int slot = 0; slot < NS; ++slot) {
+            if (!slot_active(G, b, slot)) continue;
+            const int lx = slot % B, ly = (slot / B) % B, lz = slot / (B * B);
+            const uint32_t me = (uint32_t)(b * NS + slot);
+            // +x, +y, +z neighbours (each pair is visited once)
+            const int lc[3] = {lx, ly, lz};
+            for (int a = 0; a < 3; ++a) {
+                int64_t nbk = b;
+                int ns;
+                if (lc[a] < B - 1) {
+                    ns = slot + (a == 0 ? 1 : a == 1 ? B : B * B);
+                } else {
+                    nbk = bi.nbr[2 * a + 1];
+                    if (nbk < 0) continue;
+                    ns = slot - (B - 1) * (a == 0 ? 1 : a == 1 ? B : B * B);
+                }
+                if (slot_active(G, nbk, ns)) d.unite(me, (uint32_t)(nbk * NS + ns));
+            }
+        }
+    }
+    const int64_t ext[3] = {G.nx, G.ny, G.nz};
+    const int64_t n = ext[axis];
+    std::vector<uint8_t> touch((size_t)nslots, 0);  // bit 0 inlet, bit 1 outlet (on roots)
+    auto coord = [&](int64_t b, int slot, int a) {
+        const BlockInfo &bi = G.info[b];
+        const int64_t bc = a == 0 ? (bi.xy & 0xffff) : a == 1 ? ((bi.xy >> 16) & 0xffff) : (bi.zg & 0xffff);
+        const int l = a == 0 ? slot % B : a == 1 ? (slot / B) % B : slot / (B * B);
+        return bc * B + l;
+    };
+    for (int64_t b = 0; b < nb; ++b)
+        for (int slot = 0; slot < NS; ++slot) {
+            if (!slot_active(G, b, slot)) continue;
+            const int64_t c = coord(b, slot, axis);
+            const uint32_t r = d.find((uint32_t)(b * NS + slot));
+            if (c == 0) touch[r] |= 1;
+            if (c == n - 1) touch[r] |= 2;
+        }
+    bool perc = false;
+    for (int64_t b = 0; b < nb; ++b)
+        for (int slot = 0; slot < NS; ++slot) {
+            if (!slot_active(G, b, slot)) continue;
+            const int64_t c = coord(b, slot, axis);
+            const uint8_t t = touch[d.find((uint32_t)(b * NS + slot))];
+            float v;
+            if (c == 0) v = 1.0f;
+            else if (c == n - 1) v = 0.0f;
+            else if (t == 3) v = 1.0f - (float)c / (float)(n - 1);
+            else v = t == 1 ? 1.0f : 0.0f;
+            if (t == 3) perc = true;
+            x[(size_t)(b * NS + slot)] = v;
+        }
+    *percolates = perc;
+    return RD_OK;
 }
-extern "C" rd_status rd_batch_bind(rd_batch *, void *, size_t, void *)
+
+// Upload a block-major FP32 field into storage type `storage` at dev (round to nearest).
+rd_status upload_field(const std::vector<float> &x, rd_storage storage, void *dev, hipStream_t st)
 {
-    return rd_fail(RD_ERR_STATE, "batches not available yet");
+    if (x.empty()) return RD_OK;
+    if (storage == RD_FP32) {
+        HIPCHK(hipMemcpyAsync(dev, x.data(), sizeof(float) * x.size(), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return RD_OK;
+    }
+    std::vector<uint16_t> h(x.size());
+    for (size_t i = 0; i < x.size(); ++i) {
+        const float v = x[i];
+        uint32_t u;
+        memcpy(&u, &v, 4);
+        if (storage == RD_BF16) {
+            u += 0x7fffu + ((u >> 16) & 1u);  // the initial values are finite
+            h[i] = (uint16_t)(u >> 16);
+        } else {
+            const _Float16 hv = (_Float16)v;
+            memcpy(&h[i], &hv, 2);
+        }
+    }
+    HIPCHK(hipMemcpyAsync(dev, h.data(), 2 * h.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return RD_OK;
 }
-extern "C" rd_status rd_batch_tortuosity(rd_batch *, int, double, int64_t, double *, double *,
-                                         int64_t *)
+
+rd_status copy_scal(const CgArgs &a, std::vector<double> &hs, hipStream_t st)
 {
-    return rd_fail(RD_ERR_STATE, "batches not available yet");
+    hs.resize((size_t)a.ngeom * CG_NSCAL);
+    HIPCHK(hipMemcpyAsync(hs.data(), a.scal, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return RD_OK;
 }
+
+rd_status push_scal(const CgArgs &a, const std::vector<double> &hs, hipStream_t st)
+{
+    HIPCHK(hipMemcpyAsync(a.scal, hs.data(), sizeof(double) * hs.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return RD_OK;
+}
+
+// Runs CG on every geometry of `a` (Dirichlet values already in x) from a linear
+// ramp, stopping each geometry at rel. residual <= tol, stagnation or max_iters.
+rd_status run_cg(const CgArgs &a, int storage, int B, hipStream_t st, int axis, double tol,
+                 int64_t max_iters, const std::vector<GeomMeta> &meta, std::vector<CgOut> &out)
+{
+    const int n = a.ngeom;
+    out.assign(n, CgOut());
+    LAUNCHCHK(rd_launch_fill_u32(a.scal, 0u, (int64_t)n * CG_NSCAL * 2, st));
+    LAUNCHCHK(cg_launch_residual(storage, B, a, 1, st));
+    LAUNCHCHK(cg_launch_segsum(a, CG_RRNEW, CG_BB, st));
+    LAUNCHCHK(cg_launch_scalars(a, 2, st));
+    std::vector<double> hs;
+    rd_status s = copy_scal(a, hs, st);
+    if (s != RD_OK) return s;
+    std::vector<double> best(n, 0.0);
+    std::vector<int> since(n, 0);
+    int live = 0;
+    for (int g = 0; g < n; ++g) {
+        double *v = &hs[(size_t)g * CG_NSCAL];
+        const double bb = v[CG_BB], rr = v[CG_RR];
+        out[g].rel = bb > 0 ? sqrt(rr / bb) : 0.0;
+        best[g] = out[g].rel;
+        if (!(bb > 0) || out[g].rel <= tol || max_iters <= 0) {
+            v[CG_DONE] = 1.0;
+            out[g].converged = out[g].rel <= tol;
+        } else {
+            ++live;
+        }
+    }
+    if ((s = push_scal(a, hs, st)) != RD_OK) return s;
+    while (live > 0) {
+        for (int k = 0; k < CHECK_EVERY; ++k) {
+            LAUNCHCHK(cg_launch_matvec(storage, B, a, st));
+            LAUNCHCHK(cg_launch_segsum(a, CG_PAP, -1, st));
+            LAUNCHCHK(cg_launch_scalars(a, 0, st));
+            LAUNCHCHK(cg_launch_update(storage, B, a, st));
+            LAUNCHCHK(cg_launch_segsum(a, CG_RRNEW, -1, st));
+            LAUNCHCHK(cg_launch_scalars(a, 1, st));
+            LAUNCHCHK(cg_launch_pupdate(storage, B, a, st));
+        }
+        // true residual b - A x (the recursive one drifts in reduced precision)
+        LAUNCHCHK(cg_launch_residual(storage, B, a, 0, st));
+        LAUNCHCHK(cg_launch_segsum(a, CG_CHECK, -1, st));
+        if ((s = copy_scal(a, hs, st)) != RD_OK) return s;
+        for (int g = 0; g < n; ++g) {
+            double *v = &hs[(size_t)g * CG_NSCAL];
+            if (v[CG_DONE] != 0.0) continue;
+            out[g].iters += CHECK_EVERY;
+            const double rel = sqrt(std::max(0.0, v[CG_CHECK]) / v[CG_BB]);
+            out[g].rel = rel;
+            if (!isfinite(rel)) return rd_fail(RD_ERR_NONFINITE, "CG residual is not finite");
+            if (rel < 0.9 * best[g]) {
+                best[g] = rel;
+                since[g] = 0;
+            } else {
+                ++since[g];
+            }
+            const bool conv = rel <= tol;
+            if (conv || since[g] >= STALL_CHECKS || out[g].iters >= max_iters) {
+                v[CG_DONE] = 1.0;
+                out[g].converged = conv;
+                --live;
+            }
+        }
+        if ((s = push_scal(a, hs, st)) != RD_OK) return s;
+    }
+    // steady flux through the two Dirichlet planes
+    LAUNCHCHK(cg_launch_flux(storage, B, a, 2 * axis, st));
+    LAUNCHCHK(cg_launch_segsum(a, CG_QIN, CG_QOUT, st));
+    if ((s = copy_scal(a, hs, st)) != RD_OK) return s;
+    for (int g = 0; g < n; ++g) {
+        const GeomMeta &m = meta[g];
+        const double *v = &hs[(size_t)g * CG_NSCAL];
+        // the kernel sums (x_q - x_p) over Dirichlet-free pairs; the flux is D*dx times it
+        out[g].qin = v[CG_QIN] * m.dx;
+        out[g].qout = -v[CG_QOUT] * m.dx;
+        const int64_t ext[3] = {m.nx, m.ny, m.nz};
+        const double area = (double)ext[(axis + 1) % 3] * (double)ext[(axis + 2) % 3] * m.dx * m.dx;
+        const double len = (double)(ext[axis] - 1) * m.dx;
+        out[g].tau = (m.percolates && out[g].qin > 0) ? m.psi * area / (out[g].qin * len)
+                                    : std::numeric_limits<double>::infinity();
+    }
+    return RD_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// single geometry
+// ---------------------------------------------------------------------------
+
+extern "C" rd_status rd_sim_steady_state(rd_sim *sim, int axis, double rel_tol, int64_t max_iters,
+                                         double *tau, double *rel_residual, int64_t *iters)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    if (!sim->ws) return rd_fail(RD_ERR_STATE, "bind a workspace first");
+    if (!(sim->features & RD_WS_SOLVER))
+        return rd_fail(RD_ERR_WORKSPACE, "bind with RD_WS_SOLVER for the steady state");
+    if (sim->S != 1 || !sim->reactions.empty() || sim->robin[0] != 0.0)
+        return rd_fail(RD_ERR_STATE, "steady state needs one species without reactions or Robin");
+    if (axis < 0 || axis > 2) return rd_fail(RD_ERR_ARG, "axis must be 0, 1 or 2");
+    if (!(rel_tol >= 0.0) || max_iters < 0) return rd_fail(RD_ERR_ARG, "bad tolerance or max_iters");
+    const rd_geometry &G = *sim->g;
+    const int64_t ext[3] = {G.nx, G.ny, G.nz};
+    if (ext[axis] < 2) return rd_fail(RD_ERR_SHAPE, "need at least 2 voxels along the axis");
+    const int inlet = 2 * axis, outlet = 2 * axis + 1;
+    sim->dir[0] = (1u << inlet) | (1u << outlet);
+    for (int f = 0; f < 6; ++f) sim->dirval[0][f] = 0.0;
+    sim->dirval[0][inlet] = 1.0;
+    sim->invalidate_graphs();
+    CgArgs a{};
+    a.info = (const BlockInfo *)(sim->ws + sim->L.info);
+    a.mask = (const uint64_t *)(sim->ws + sim->L.mask);
+    a.geom = (const GeomInfo *)(sim->ws + sim->L.geom);
+    a.nb = (int)G.nb();
+    a.ngeom = 1;
+    a.dir = sim->dir[0];
+    a.x = sim->field_ptr(sim->cur, 0);
+    a.r = sim->ws + sim->L.solver[0];
+    a.p = sim->ws + sim->L.solver[1];
+    a.ap = sim->ws + sim->L.solver[2];
+    a.partial = (double *)(sim->ws + sim->L.part);
+    a.scal = (double *)(sim->ws + sim->L.scal);
+    std::vector<GeomMeta> meta(1);
+    meta[0] = {G.nx, G.ny, G.nz, (double)G.n_active / ((double)G.nx * G.ny * G.nz), G.dx, false};
+    std::vector<CgOut> out;
+    if (a.nb == 0) {
+        if (tau) *tau = std::numeric_limits<double>::infinity();
+        if (rel_residual) *rel_residual = 0.0;
+        if (iters) *iters = 0;
+        return RD_OK;
+    }
+    {
+        std::vector<float> x0;
+        rd_status s = initial_guess(G, axis, x0, &meta[0].percolates);
+        if (s != RD_OK) return s;
+        if ((s = upload_field(x0, sim->storage, a.x, sim->stream)) != RD_OK) return s;
+    }
+    rd_status s = run_cg(a, (int)sim->storage, G.B, sim->stream, axis, rel_tol, max_iters, meta, out);
+    if (s != RD_OK) return s;
+    if (tau) *tau = out[0].tau;
+    if (rel_residual) *rel_residual = out[0].rel;
+    if (iters) *iters = out[0].iters;
+    sim->steps_taken = 0;
+    if (!out[0].converged)
+        return rd_fail(RD_ERR_NOT_CONVERGED, "stopped at rel. residual " + std::to_string(out[0].rel));
+    return RD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+
+struct rd_batch {
+    std::vector<const rd_geometry *> geoms;
+    rd_storage storage = RD_FP32;
+    int B = 8;
+    int64_t nb = 0;
+    std::vector<BlockInfo> info;
+    std::vector<uint64_t> mask;
+    std::vector<GeomInfo> ginfo;
+    size_t o_info = 0, o_mask = 0, o_geom = 0, o_vec[4] = {0, 0, 0, 0}, o_part = 0, o_scal = 0,
+           total = 0;
+    char *ws = nullptr;
+    hipStream_t stream = nullptr;
+};
+
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+extern "C" rd_status rd_batch_create(const rd_geometry *const *geoms, int n, rd_storage storage,
+                                     rd_batch **out)
+{
+    if (!out) return rd_fail(RD_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!geoms || n <= 0 || n > 65535) return rd_fail(RD_ERR_ARG, "need 1..65535 geometries");
+    if (storage != RD_FP32 && storage != RD_BF16 && storage != RD_FP16)
+        return rd_fail(RD_ERR_ARG, "unknown storage type");
+    const int B = geoms[0] ? geoms[0]->B : 0;
+    int64_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!geoms[i]) return rd_fail(RD_ERR_ARG, "NULL geometry");
+        if (geoms[i]->B != B) return rd_fail(RD_ERR_SHAPE, "all geometries need the same block edge");
+        total += geoms[i]->nb();
+    }
+    if (total >= INT32_MAX) return rd_fail(RD_ERR_SHAPE, "too many blocks in the batch");
+    rd_batch *bt = new (std::nothrow) rd_batch();
+    if (!bt) return rd_fail(RD_ERR_ARG, "out of host memory");
+    bt->geoms.assign(geoms, geoms + n);
+    bt->storage = storage;
+    bt->B = B;
+    bt->nb = total;
+    const int MW = mask_words(B);
+    try {
+        bt->info.reserve(total);
+        bt->mask.reserve((size_t)total * MW);
+        int32_t off = 0;
+        for (int i = 0; i < n; ++i) {
+            const rd_geometry &G = *geoms[i];
+            bt->ginfo.push_back({(int32_t)G.nx, (int32_t)G.ny, (int32_t)G.nz, off});
+            for (int64_t b = 0; b < G.nb(); ++b) {
+                BlockInfo bi = G.info[b];
+                for (int f = 0; f < 6; ++f)
+                    if (bi.nbr[f] >= 0) bi.nbr[f] += off;
+                bi.zg = (bi.zg & 0xffff) | (i << 16);
+                bt->info.push_back(bi);
+            }
+            bt->mask.insert(bt->mask.end(), G.mask.begin(), G.mask.end());
+            off += (int32_t)G.nb();
+        }
+    } catch (const std::bad_alloc &) {
+        delete bt;
+        return rd_fail(RD_ERR_ARG, "out of host memory");
+    }
+    const size_t es = storage == RD_FP32 ? 4 : 2;
+    const size_t nbs = (size_t)std::max<int64_t>(total, 1);
+    size_t o = 0;
+    bt->o_info = o; o = al256(o + sizeof(BlockInfo) * nbs);
+    bt->o_mask = o; o = al256(o + 8 * (size_t)MW * nbs);
+    bt->o_geom = o; o = al256(o + sizeof(GeomInfo) * (size_t)n);
+    for (int v = 0; v < 4; ++v) {
+        bt->o_vec[v] = o;
+        o = al256(o + es * nbs * (size_t)B * B * B);
+    }
+    bt->o_part = o; o = al256(o + sizeof(double) * 2 * nbs);
+    bt->o_scal = o; o = al256(o + sizeof(double) * CG_NSCAL * (size_t)n);
+    bt->total = o;
+    *out = bt;
+    return RD_OK;
+}
+
+extern "C" rd_status rd_batch_workspace_bytes(const rd_batch *b, size_t *bytes)
+{
+    if (!b || !bytes) return rd_fail(RD_ERR_ARG, "NULL argument");
+    *bytes = b->total;
+    return RD_OK;
+}
+
+extern "C" rd_status rd_batch_bind(rd_batch *b, void *dev_ws, size_t bytes, void *stream)
+{
+    if (!b) return rd_fail(RD_ERR_ARG, "batch is NULL");
+    if (!dev_ws) return rd_fail(RD_ERR_WORKSPACE, "workspace is NULL");
+    if (((uintptr_t)dev_ws) % 256) return rd_fail(RD_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    if (bytes < b->total)
+        return rd_fail(RD_ERR_WORKSPACE, "workspace has " + std::to_string(bytes) + " bytes, needs " +
+                                             std::to_string(b->total));
+    b->ws = (char *)dev_ws;
+    b->stream = (hipStream_t)stream;
+    if (b->nb > 0) {
+        HIPCHK(hipMemcpyAsync(b->ws + b->o_info, b->info.data(), sizeof(BlockInfo) * b->nb,
+                              hipMemcpyHostToDevice, b->stream));
+        HIPCHK(hipMemcpyAsync(b->ws + b->o_mask, b->mask.data(), sizeof(uint64_t) * b->mask.size(),
+                              hipMemcpyHostToDevice, b->stream));
+    }
+    HIPCHK(hipMemcpyAsync(b->ws + b->o_geom, b->ginfo.data(), sizeof(GeomInfo) * b->ginfo.size(),
+                          hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return RD_OK;
+}
+
+extern "C" rd_status rd_batch_tortuosity(rd_batch *b, int axis, double rel_tol, int64_t max_iters,
+                                         double *tau, double *rel_residual, int64_t *iters)
+{
+    if (!b) return rd_fail(RD_ERR_ARG, "batch is NULL");
+    if (!b->ws) return rd_fail(RD_ERR_STATE, "bind a workspace first");
+    if (axis < 0 || axis > 2) return rd_fail(RD_ERR_ARG, "axis must be 0, 1 or 2");
+    const int n = (int)b->geoms.size();
+    std::vector<GeomMeta> meta(n);
+    for (int i = 0; i < n; ++i) {
+        const rd_geometry &G = *b->geoms[i];
+        const int64_t ext[3] = {G.nx, G.ny, G.nz};
+        if (ext[axis] < 2) return rd_fail(RD_ERR_SHAPE, "need at least 2 voxels along the axis");
+        meta[i] = {G.nx, G.ny, G.nz, (double)G.n_active / ((double)G.nx * G.ny * G.nz), G.dx, false};
+    }
+    const int inlet = 2 * axis, outlet = 2 * axis + 1;
+    const size_t es = b->storage == RD_FP32 ? 4 : 2;
+    const size_t NS = (size_t)b->B * b->B * b->B;
+    CgArgs a{};
+    a.info = (const BlockInfo *)(b->ws + b->o_info);
+    a.mask = (const uint64_t *)(b->ws + b->o_mask);
+    a.geom = (const GeomInfo *)(b->ws + b->o_geom);
+    a.nb = (int)b->nb;
+    a.ngeom = n;
+    a.dir = (1u << inlet) | (1u << outlet);
+    a.x = b->ws + b->o_vec[0];
+    a.r = b->ws + b->o_vec[1];
+    a.p = b->ws + b->o_vec[2];
+    a.ap = b->ws + b->o_vec[3];
+    a.partial = (double *)(b->ws + b->o_part);
+    a.scal = (double *)(b->ws + b->o_scal);
+    std::vector<CgOut> out;
+    if (b->nb > 0) {
+        for (int i = 0; i < n; ++i) {
+            std::vector<float> x0;
+            rd_status s = initial_guess(*b->geoms[i], axis, x0, &meta[i].percolates);
+            if (s != RD_OK) return s;
+            char *dst = (char *)a.x + es * NS * (size_t)b->ginfo[i].block0;
+            if ((s = upload_field(x0, b->storage, dst, b->stream)) != RD_OK) return s;
+        }
+        rd_status s = run_cg(a, (int)b->storage, b->B, b->stream, axis, rel_tol, max_iters, meta, out);
+        if (s != RD_OK) return s;
+    } else {
+        out.assign(n, CgOut());
+        for (auto &o : out) o.tau = std::numeric_limits<double>::infinity();
+    }
+    bool all = true;
+    for (int i = 0; i < n; ++i) {
+        if (tau) tau[i] = out[i].tau;
+        if (rel_residual) rel_residual[i] = out[i].rel;
+        if (iters) iters[i] = out[i].iters;
+        all = all && out[i].converged;
+    }
+    if (!all) return rd_fail(RD_ERR_NOT_CONVERGED, "some geometries stopped above the tolerance");
+    return RD_OK;
+}
+
 extern "C" void rd_batch_destroy(rd_batch *b) { delete b; }
+
+// ---------------------------------------------------------------------------
+// adjoint
+// ---------------------------------------------------------------------------
+
+// Checkpointed adjoint: a forward sweep stores c^{jk} every k steps; the backward
+// sweep restores each segment's first state, recomputes the segment's states into
+// k-1 spare slots with the same step kernel (bitwise the forward states) and runs
+// the adjoint steps from the segment's end to its start.
+extern "C" rd_status rd_sim_adjoint(rd_sim *sim, const float *dev_seed, int seed_mode,
+                                    int64_t n_steps, double dt, int checkpoint_every,
+                                    double *loss, double *dL_dD, double *dL_drate)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    if (!sim->ws) return rd_fail(RD_ERR_STATE, "bind a workspace first");
+    if (!(sim->features & RD_WS_ADJOINT))
+        return rd_fail(RD_ERR_WORKSPACE, "bind with RD_WS_ADJOINT for the adjoint");
+    if (sim->S != 1) return rd_fail(RD_ERR_STATE, "the adjoint needs a single species");
+    for (const Reaction &r : sim->reactions)
+        if (r.to != -1) return rd_fail(RD_ERR_STATE, "the adjoint supports decay reactions only");
+    if (sim->sround && sim->storage != RD_FP32)
+        return rd_fail(RD_ERR_STATE, "the adjoint needs round-to-nearest storage");
+    if (!dev_seed) return rd_fail(RD_ERR_ARG, "seed field is NULL");
+    if (seed_mode != 0 && seed_mode != 1) return rd_fail(RD_ERR_ARG, "seed_mode must be 0 or 1");
+    if (n_steps < 1 || checkpoint_every < 1) return rd_fail(RD_ERR_ARG, "need n_steps, checkpoint_every >= 1");
+    rd_status s = sim->check_dt(dt);
+    if (s != RD_OK) return s;
+    const int64_t k = checkpoint_every;
+    const int64_t ncp = (n_steps + k - 1) / k;
+    if (ncp + k - 1 > sim->cp_slots)
+        return rd_fail(RD_ERR_WORKSPACE, "need " + std::to_string(ncp + k - 1) +
+                                             " checkpoint slots, the workspace has " +
+                                             std::to_string(sim->cp_slots));
+    const rd_geometry &G = *sim->g;
+    const int B = G.B, nb = (int)G.nb();
+    const int st = (int)sim->storage;
+    hipStream_t stream = sim->stream;
+    const size_t es = sim->storage == RD_FP32 ? 4 : 2;
+    const size_t fbytes = es * (size_t)sim->L.field_elems;
+    char *ws = sim->ws;
+    auto slot = [&](int64_t j) { return (void *)(ws + sim->L.cp + sim->L.cp_stride * (size_t)j); };
+    double *acc = (double *)(ws + sim->L.res) + 16;  // [loss, gD, gk]
+    LAUNCHCHK(rd_launch_fill_u32(acc, 0u, 6, stream));
+    if (nb == 0) {
+        if (loss) *loss = 0;
+        if (dL_dD) *dL_dD = 0;
+        if (dL_drate) *dL_drate = 0;
+        return RD_OK;
+    }
+    // the seed in block-major FP32
+    float zero6[6] = {0, 0, 0, 0, 0, 0};
+    float *seed = (float *)(ws + sim->L.target);
+    LAUNCHCHK(rd_launch_scatter(0, B, (const BlockInfo *)(ws + sim->L.info),
+                                (const uint64_t *)(ws + sim->L.mask), (const GeomInfo *)(ws + sim->L.geom),
+                                nb, dev_seed, seed, 0u, zero6, stream));
+    // forward with checkpoints
+    for (int64_t j = 0; j < ncp; ++j) {
+        HIPCHK(hipMemcpyAsync(slot(j), sim->field_ptr(sim->cur, 0), fbytes, hipMemcpyDeviceToDevice, stream));
+        s = sim->step(dt, std::min<int64_t>(k, n_steps - j * k));
+        if (s != RD_OK) return s;
+    }
+    AdjArgs a{};
+    a.info = (const BlockInfo *)(ws + sim->L.info);
+    a.mask = (const uint64_t *)(ws + sim->L.mask);
+    a.geom = (const GeomInfo *)(ws + sim->L.geom);
+    a.nb = nb;
+    const StepArgs fa = sim->step_args(dt, sim->cur);
+    a.coef = fa.coef[0];
+    a.seed = seed;
+    a.partial = (double *)(ws + sim->L.part);
+    float *lam[2] = {(float *)(ws + sim->L.lam[0]), (float *)(ws + sim->L.lam[1])};
+    int lc = 0;
+    // lambda^N
+    a.c = sim->field_ptr(sim->cur, 0);
+    a.lam_out = lam[lc];
+    LAUNCHCHK(adj_launch_seed(st, B, a, seed_mode, stream));
+    LAUNCHCHK(adj_launch_sum_acc(a.partial, nb, 1, acc, stream));
+    // backward over segments
+    for (int64_t j = ncp - 1; j >= 0; --j) {
+        const int64_t s0 = j * k;
+        const int64_t len = std::min<int64_t>(k, n_steps - s0);
+        // seg[0] = checkpoint j, seg[m] = spare slot ncp + m - 1
+        auto seg = [&](int64_t m) { return m == 0 ? slot(j) : slot(ncp + m - 1); };
+        for (int64_t m = 1; m < len; ++m) {
+            StepArgs sa = fa;
+            sa.cin = seg(m - 1);
+            sa.cout = seg(m);
+            sa.sround = 0;
+            sa.ctr = sim->step_counter();
+            sa.ctr_off = 0;
+            sim->launch_shape(sa);
+            LAUNCHCHK(rd_launch_step(st, B, sa, stream));
+        }
+        for (int64_t m = len - 1; m >= 0; --m) {
+            a.c = seg(m);
+            a.lam_in = lam[lc];
+            a.lam_out = lam[1 - lc];
+            LAUNCHCHK(adj_launch_step(st, B, a, stream));
+            LAUNCHCHK(adj_launch_sum_acc(a.partial, adj_groups(B, nb), 2, acc + 1, stream));
+            lc = 1 - lc;
+        }
+    }
+    double h[3];
+    HIPCHK(hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    const double dx = G.dx;
+    if (loss) *loss = seed_mode == 0 ? h[0] : 0.0;
+    if (dL_dD) *dL_dD = h[1] * dt / (dx * dx);
+    if (dL_drate) *dL_drate = h[2] * dt;
+    if (!isfinite(h[0]) || !isfinite(h[1]) || !isfinite(h[2]))
+        return rd_fail(RD_ERR_NONFINITE, "adjoint produced a non-finite value");
+    return RD_OK;
+}
+
+extern "C" rd_status rd_sim_set_species_D(rd_sim *sim, int species, double D)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    if (species < 0 || species >= sim->S) return rd_fail(RD_ERR_ARG, "bad species");
+    if (!(D >= 0.0) || !isfinite(D)) return rd_fail(RD_ERR_ARG, "D must be finite and >= 0");
+    sim->D[species] = D;
+    sim->invalidate_graphs();
+    return RD_OK;
+}
+
+extern "C" rd_status rd_sim_set_reaction_rate(rd_sim *sim, int index, double rate)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    if (index < 0 || index >= (int)sim->reactions.size()) return rd_fail(RD_ERR_ARG, "bad reaction index");
+    if (!(rate >= 0.0) || !isfinite(rate)) return rd_fail(RD_ERR_ARG, "rate must be finite and >= 0");
+    sim->reactions[index].rate = rate;
+    sim->invalidate_graphs();
+    return RD_OK;
+}

@@ -1,0 +1,41 @@
+// rd_solve.h -- conjugate-gradient steady state (single geometry or batch).
+#pragma once
+
+#include <stdint.h>
+
+#include "rd_internal.h"
+
+// per-geometry scalar slots (doubles) in CgArgs::scal
+enum {
+    CG_ALPHA = 0,
+    CG_BETA = 1,
+    CG_RR = 2,
+    CG_PAP = 3,
+    CG_BB = 4,
+    CG_RRNEW = 5,
+    CG_DONE = 6,
+    CG_CHECK = 7,
+    CG_QIN = 8,
+    CG_QOUT = 9,
+    CG_NSCAL = 10
+};
+
+struct CgArgs {
+    const BlockInfo *info;
+    const uint64_t *mask;
+    const GeomInfo *geom;  // ngeom entries; block ranges via block0
+    int nb;
+    int ngeom;
+    uint32_t dir;          // Dirichlet faces (inlet | outlet)
+    void *x, *r, *p, *ap;  // storage type T, nb * B^3 each
+    double *partial;       // [nb][2]
+    double *scal;          // [ngeom][CG_NSCAL]
+};
+
+int cg_launch_residual(int storage, int B, const CgArgs &a, int store, void *stream);
+int cg_launch_matvec(int storage, int B, const CgArgs &a, void *stream);
+int cg_launch_update(int storage, int B, const CgArgs &a, void *stream);
+int cg_launch_pupdate(int storage, int B, const CgArgs &a, void *stream);
+int cg_launch_flux(int storage, int B, const CgArgs &a, int inlet_face, void *stream);
+int cg_launch_segsum(const CgArgs &a, int slot0, int slot1, void *stream);
+int cg_launch_scalars(const CgArgs &a, int mode, void *stream);

@@ -20,6 +20,11 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run paper_2304_11165_amd.build.build() "
                       "(or __graft_entry__.build()) first")
 
+# torch first: its HIP runtime (soname libamdhip64.so.7) is then the one librd.so
+# binds to, so device pointers and stream handles from torch are valid in the
+# library.  Loading librd.so first would bring in a second HIP runtime.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 P = ctypes.c_void_p
@@ -48,7 +53,8 @@ _SIGS = {
     "rd_sim_set_robin": ([P, ci, f64], ci),
     "rd_sim_set_dirichlet": ([P, ci, ci, f64], ci),
     "rd_sim_clear_dirichlet": ([P, ci], ci),
-    "rd_sim_set_launch": ([P, ci, ci], ci),
+    "rd_sim_set_launch": ([P, ci, ci, ci], ci),
+    "rd_sim_set_kernel": ([P, ci, ci], ci),
     "rd_sim_set_rounding": ([P, ci, ctypes.c_uint64], ci),
     "rd_sim_workspace_bytes": ([P, u32, i64, P], ci),
     "rd_sim_bind": ([P, P, sz, u32, i64, P], ci),
@@ -59,7 +65,9 @@ _SIGS = {
     "rd_sim_reduce": ([P, ci, P, P, P], ci),
     "rd_sim_balance": ([P, ci, P], ci),
     "rd_sim_steady_state": ([P, ci, f64, i64, P, P, P], ci),
-    "rd_sim_adjoint": ([P, P, i64, f64, ci, P, P, P], ci),
+    "rd_sim_adjoint": ([P, P, ci, i64, f64, ci, P, P, P], ci),
+    "rd_sim_set_species_D": ([P, ci, f64], ci),
+    "rd_sim_set_reaction_rate": ([P, ci, f64], ci),
     "rd_sim_destroy": ([P], None),
     "rd_batch_create": ([P, ci, ci, P], ci),
     "rd_batch_workspace_bytes": ([P, P], ci),
@@ -171,10 +179,10 @@ class Geometry:
     def export_masks(self):
         return rd_geometry_export_masks(self.handle, self.block_edge)
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.rd_geometry_destroy):
         h = getattr(self, "handle", None)
         if h:
-            rd_geometry_destroy(h)
+            _destroy(h)
             self.handle = None
 
 
@@ -212,9 +220,13 @@ class Sim:
     def clear_dirichlet(self, species):
         _check(_lib.rd_sim_clear_dirichlet(self.handle, int(species)), "rd_sim_clear_dirichlet")
 
-    def set_launch(self, graph_steps=32, use_graph=True):
-        _check(_lib.rd_sim_set_launch(self.handle, int(graph_steps), int(bool(use_graph))),
-               "rd_sim_set_launch")
+    def set_launch(self, graph_steps=32, use_graph=True, xcd_map=False):
+        _check(_lib.rd_sim_set_launch(self.handle, int(graph_steps), int(bool(use_graph)),
+                                      int(bool(xcd_map))), "rd_sim_set_launch")
+
+    def set_kernel(self, persistent=True, wg_per_cu=8):
+        _check(_lib.rd_sim_set_kernel(self.handle, int(bool(persistent)), int(wg_per_cu)),
+               "rd_sim_set_kernel")
 
     def set_rounding(self, stochastic, seed=0):
         _check(_lib.rd_sim_set_rounding(self.handle, int(bool(stochastic)), int(seed)),
@@ -289,22 +301,32 @@ class Sim:
         return {"tau": tau.value, "rel_residual": rel.value, "iters": it.value,
                 "converged": st == RD_OK}
 
-    def adjoint(self, target, n_steps, dt, checkpoint_every):
+    def set_species_D(self, species, D):
+        _check(_lib.rd_sim_set_species_D(self.handle, int(species), float(D)), "rd_sim_set_species_D")
+
+    def set_reaction_rate(self, index, rate):
+        _check(_lib.rd_sim_set_reaction_rate(self.handle, int(index), float(rate)),
+               "rd_sim_set_reaction_rate")
+
+    def adjoint(self, seed, n_steps, dt, checkpoint_every, seed_is_target=True):
+        """(loss, dL/dD, dL/dk) of the run from the current field.  seed: target field
+        c* (seed_is_target) or dL/dc^N."""
         import torch
 
         nz, ny, nx = self.geometry.shape
-        t = torch.as_tensor(target, dtype=torch.float32, device=self.workspace.device)
+        t = torch.as_tensor(seed, dtype=torch.float32, device=self.workspace.device)
         t = t.reshape(nz, ny, nx).contiguous()
         L, gD, gk = f64(), f64(), f64()
-        _check(_lib.rd_sim_adjoint(self.handle, ctypes.c_void_p(t.data_ptr()), int(n_steps),
-                                   float(dt), int(checkpoint_every), ctypes.byref(L),
-                                   ctypes.byref(gD), ctypes.byref(gk)), "rd_sim_adjoint")
+        _check(_lib.rd_sim_adjoint(self.handle, ctypes.c_void_p(t.data_ptr()),
+                                   0 if seed_is_target else 1, int(n_steps), float(dt),
+                                   int(checkpoint_every), ctypes.byref(L), ctypes.byref(gD),
+                                   ctypes.byref(gk)), "rd_sim_adjoint")
         return L.value, gD.value, gk.value
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.rd_sim_destroy):
         h = getattr(self, "handle", None)
         if h:
-            _lib.rd_sim_destroy(h)
+            _destroy(h)
             self.handle = None
 
 
@@ -341,10 +363,10 @@ class Batch:
             _check(st, "rd_batch_tortuosity")
         return tau, rel, it
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.rd_batch_destroy):
         h = getattr(self, "handle", None)
         if h:
-            _lib.rd_batch_destroy(h)
+            _destroy(h)
             self.handle = None
 
 
@@ -352,3 +374,35 @@ def stability_dt_max(D_max, dx=1.0, rate_max=0.0, robin_max=0.0):
     """2 / lambda_max of the step (the bound rd_sim_step enforces)."""
     lam = 12.0 * D_max / dx ** 2 + rate_max + 6.0 * robin_max / dx
     return math.inf if lam == 0 else 2.0 / lam
+
+
+class DiffusionDecay(torch.autograd.Function):
+    """c^N = FTCS^n(c^0; D, k) for a single-species diffusion-decay simulation, with
+    gradients with respect to the scalars D and k from the library's checkpointed
+    adjoint (rd_sim_adjoint, seed = dL/dc^N).
+
+    Usage: ``cN = DiffusionDecay.apply(D, k, sim, c0, n_steps, dt, checkpoint_every)``
+    with D, k 0-dim float64 tensors, sim a bound single-species Sim whose reaction 0
+    is the decay, c0 a dense float32 device field."""
+
+    @staticmethod
+    def forward(ctx, D, k, sim, c0, n_steps, dt, checkpoint_every):
+        sim.set_species_D(0, float(D))
+        sim.set_reaction_rate(0, float(k))
+        sim.set_field(0, c0)
+        sim.step(dt, n_steps)
+        out = sim.get_field(0)
+        ctx.sim, ctx.c0, ctx.n, ctx.dt, ctx.k = sim, c0, n_steps, dt, checkpoint_every
+        ctx.params = (float(D), float(k))
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        sim = ctx.sim
+        sim.set_species_D(0, ctx.params[0])
+        sim.set_reaction_rate(0, ctx.params[1])
+        sim.set_field(0, ctx.c0)
+        _, gD, gk = sim.adjoint(g.float().contiguous(), ctx.n, ctx.dt, ctx.k, seed_is_target=False)
+        dev = g.device
+        return (torch.tensor(gD, dtype=torch.float64, device=dev),
+                torch.tensor(gk, dtype=torch.float64, device=dev), None, None, None, None, None)

@@ -23,7 +23,7 @@ def rd():
 def _declared_functions():
     text = open(os.path.join(ROOT, "include", "rd.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = set(re.findall(r"\b(rd_[a-z_0-9]+)\s*\(", text))
+    names = set(re.findall(r"\b(rd_[A-Za-z_0-9]+)\s*\(", text))
     return sorted(names)
 
 

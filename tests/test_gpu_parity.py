@@ -71,10 +71,14 @@ def test_spheres64_full_config(rd, oracle_mod):
     print(f"spheres64 rel L2 = {err:.3e}")
     assert err < TOL
     assert np.all(got8[0][~act] == 0)
-    # B = 4, direct launches and graph replay: bitwise identical
-    _, s4 = make_gpu(rd, img, w.species_D, w.dx, dirichlet=w.dirichlet, B=4, graph=False)
-    s4.step(w.dt, w.steps)
-    np.testing.assert_array_equal(fields(s4, 1), got8)
+    # every kernel variant gives the same bits: B = 4, one workgroup per block,
+    # plain or XCD-aware mapping, graph replay or direct launches, grid sizes
+    variants = [dict(B=4, graph=False), dict(persist=False), dict(persist=False, xcd=False),
+                dict(xcd=False, graph=False), dict(wg_per_cu=1), dict(wg_per_cu=3, xcd=False)]
+    for v in variants:
+        _, sv = make_gpu(rd, img, w.species_D, w.dx, dirichlet=w.dirichlet, **v)
+        sv.step(w.dt, w.steps)
+        np.testing.assert_array_equal(fields(sv, 1), got8, err_msg=str(v))
 
 
 def test_soil_reduced_two_species(rd, oracle_mod):
@@ -212,12 +216,46 @@ def test_reduced_storage_error_reported(rd, oracle_mod, storage):
     assert errs[1] < errs[0]
 
 
-def test_stochastic_rounding_graph_equals_direct(rd):
+@pytest.mark.parametrize("storage", ["bf16", "fp16"])
+def test_stochastic_rounding_variants_agree(rd, storage):
+    """Stochastic rounding draws its bits from (slot, species, step, seed), so graph
+    replay, direct launches and every kernel variant round identically."""
     img, _ = W.boolean_spheres(40, 0.5, 3.0, 6.0, seed=3)
     out = []
-    for graph in (True, False):
-        g, s = make_gpu(rd, img, [1.0], dirichlet={(0, 0): 1.0}, storage="bf16", graph=graph)
+    for v in [dict(), dict(graph=False), dict(persist=False), dict(B=4), dict(wg_per_cu=2)]:
+        g, s = make_gpu(rd, img, [1.0, 0.5], dirichlet={(0, 0): 1.0}, reactions=[(0, 1, 0.02)],
+                        storage=storage, **v)
         s.set_rounding(1, seed=99)
         s.step(0.1, 77)
-        out.append(fields(s, 1))
-    np.testing.assert_array_equal(out[0], out[1])
+        out.append(fields(s, 2))
+    for o in out[1:]:
+        np.testing.assert_array_equal(o, out[0])
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16", "fp16"])
+@pytest.mark.parametrize("S", [1, 3, 4])
+def test_species_counts_and_storage_kernels_agree(rd, oracle_mod, storage, S):
+    """Each (storage, species count) instantiation of the persistent B = 8 kernel
+    equals the one-block-per-workgroup kernel and the B = 4 kernel bit for bit, and
+    FP32 matches the oracle."""
+    img, _ = W.boolean_spheres((21, 26, 35), 0.6, 2.0, 4.0, seed=S)
+    rng = np.random.default_rng(S)
+    D = list(rng.uniform(0.2, 1.0, S))
+    reactions = [(i, i + 1, 0.03) for i in range(S - 1)] + [(0, -1, 0.01)]
+    robin = {S - 1: 0.04}
+    dirichlet = {(0, 0): 1.0, (S - 1, 5): 0.5}
+    init = rng.uniform(0, 1, (S,) + img.shape).astype(np.float32)
+    out = []
+    for v in [dict(), dict(persist=False), dict(B=4)]:
+        g, s = make_gpu(rd, img, D, robin=robin, dirichlet=dirichlet, reactions=reactions,
+                        storage=storage, **v)
+        for sp in range(S):
+            s.set_field(sp, init[sp])
+        s.step(0.1, 40)
+        out.append(fields(s, S))
+    for o in out[1:]:
+        np.testing.assert_array_equal(o, out[0])
+    if storage == "fp32":
+        prob = oracle_mod.Problem(img, D, robin=robin, dirichlet=dirichlet, reactions=reactions)
+        ref = prob.run(prob.apply_dirichlet(init.astype(np.float64)), 0.1, 40)
+        assert np.abs(out[0] - ref).max() < 1e-5
