@@ -1,17 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark: explicit FTCS reaction-diffusion on a sparse block grid, one MI355X.
 
-Workload (the headline configuration): a 512^3 soil-like volume (seeded Gaussian
-random field, correlation length 12 voxels, thresholded to porosity 0.3), 8^3
-blocks, species A and B with D = (1.0, 0.4), A -> B at rate 0.01, Robin wall
-uptake of B with k = 0.05, c_A = 1 on the x = 0 face, dt = 0.1, FP32 storage.
-One "step" is one FTCS time step of both species over the whole geometry.
+Headline workload: a 512^3 soil-like volume (seeded Gaussian random field,
+correlation length 12 voxels, thresholded to porosity 0.3), 8^3 blocks, species A
+and B with D = (1.0, 0.4), A -> B at rate 0.01, Robin wall uptake of B with
+k = 0.05, c_A = 1 on the x = 0 face, dt = 0.1, FP32 storage.  One "step" is one
+FTCS time step of both species over the whole geometry (the workload is 10 000
+steps; that is the default --steps).
 
-Prints one JSON line with: active-voxel updates/s (value), the step kernel's
-achieved HBM bandwidth against the 8 TB/s peak (roofline, algorithmic bytes over
-the average launch duration measured with HIP events on the launch stream), the
-same workload with BF16 / FP16 storage, and the FP64 CPU oracle timed on a
-bounded sample of the same workload (cpu_baseline).
+The JSON line carries: active-voxel updates/s (value); the step kernel's achieved
+HBM bandwidth on algorithmic bytes (2 x 4 B x species per active voxel) over the
+average launch time measured with HIP events on the launch stream, against the
+8 TB/s peak (roofline); the same workload with BF16 / FP16 storage (stochastic
+rounding) and its error against the FP32-storage run; a batched form (per-geometry
+tortuosity of several sphere packings in one set of launches); and the FP64 CPU
+oracle timed on a bounded sample of the headline workload (cpu_baseline).
+
+Modes: --profile (only the timed FP32 loop, for rocprofv3), --copy-calibration (a
+plain 1 GiB device copy, whose FETCH_SIZE / WRITE_SIZE counters calibrate the
+traffic figures).
 """
 from __future__ import annotations
 
@@ -22,6 +29,7 @@ import sys
 import time
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "active-voxel updates/s + achieved HBM GB/s (plain FP32 vs batched/BF16 form)"
 
 
 def parse():
@@ -30,21 +38,42 @@ def parse():
     p.add_argument("--steps", type=int, default=10000)
     p.add_argument("--warmup", type=int, default=200)
     p.add_argument("--size", type=int, default=512, help="edge of the volume (default 512)")
-    p.add_argument("--forms", default="bf16,fp16", help="extra storage forms to time")
+    p.add_argument("--forms", default="bf16,fp16", help="reduced-storage forms to time")
     p.add_argument("--form-steps", type=int, default=2000)
+    p.add_argument("--batch", type=int, default=16, help="geometries in the batched form (0: skip)")
+    p.add_argument("--batch-max-edge", type=int, default=128)
     p.add_argument("--cpu-steps", type=int, default=4, help="oracle steps in the CPU sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--graph-steps", type=int, default=32)
-    p.add_argument("--quiet", action="store_true")
+    p.add_argument("--profile", action="store_true", help="only the timed FP32 loop")
+    p.add_argument("--copy-calibration", action="store_true")
+    p.add_argument("--traffic", default="", help="JSON file with measured HBM bytes per launch")
     return p.parse_args()
 
 
-def log(msg, quiet=False):
-    if not quiet:
-        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def build_sim(rd, geom, w, storage, graph_steps, xcd_map=False):
+def copy_calibration():
+    """A plain device copy of 1 GiB (read 1 GiB + write 1 GiB per launch), 20 launches."""
+    import torch
+
+    n = (1 << 30) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / 20
+    print(json.dumps({"copy_bytes_per_launch": 2 * (1 << 30), "copy_GBps": 2 * (1 << 30) / t / 1e9}))
+
+
+def build_sim(rd, geom, w, storage, graph_steps):
     s = rd.Sim(geom, storage)
     for d in w.species_D:
         s.add_species(d)
@@ -54,7 +83,9 @@ def build_sim(rd, geom, w, storage, graph_steps, xcd_map=False):
         s.set_robin(sp, k)
     for (sp, f), v in w.dirichlet.items():
         s.set_dirichlet(sp, f, v)
-    s.set_launch(graph_steps, True, xcd_map)
+    s.set_launch(graph_steps, True, True)
+    if storage != "fp32":
+        s.set_rounding(1, seed=2304)
     return s
 
 
@@ -72,12 +103,44 @@ def time_steps(torch, sim, stream, dt, warmup, steps):
     return e0.elapsed_time(e1) / 1e3, wall
 
 
+def batched_form(torch, rd, W, count, max_edge, stream):
+    """Per-geometry tortuosity along x of `count` boolean sphere packings (edge
+    U{64..max_edge}, porosity U(0.3, 0.7)), all in one set of CG launches."""
+    t0 = time.perf_counter()
+    geoms_np = W.batch_geometries(count, seed=4, nmin=64, nmax=max_edge)
+    geoms = [rd.Geometry(img, None, 1.0, 8) for img, _ in geoms_np]
+    n_active = sum(g.stats()["n_active"] for g in geoms)
+    log(f"batch of {count}: generated in {time.perf_counter() - t0:.1f}s, {n_active} active voxels")
+    with torch.cuda.stream(stream):
+        bt = rd.Batch(geoms).bind(stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tau, rel, it = bt.tortuosity(0, 1e-6, 20000)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+    voxel_iters = float(sum(g.stats()["n_active"] * int(i) for g, i in zip(geoms, it)))
+    return {
+        "geometries": count,
+        "edges": [int(info["n"]) for _, info in geoms_np],
+        "seconds": secs,
+        "active_voxel_cg_iterations_per_s": voxel_iters / secs,
+        "alg_GBps": voxel_iters * 9 * 4 / secs / 1e9,
+        "tau": [float(x) for x in tau],
+        "rel_residual_max": float(max(rel)),
+        "iterations": [int(x) for x in it],
+        "note": "includes host labelling and initial-guess upload per geometry",
+    }
+
+
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the sparse-block stepper "
-              "is not sharded across GPUs in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the sparse-block stepper is "
+              "not sharded across GPUs in this build", file=sys.stderr)
         sys.exit(2)
+    if a.copy_calibration:
+        copy_calibration()
+        return
 
     import numpy as np
     import torch
@@ -90,34 +153,36 @@ def main():
     n = a.size
     t0 = time.perf_counter()
     img = W.gaussian_random_field_volume(n, 12.0, 0.3, seed=w.seed)
-    log(f"geometry {n}^3 generated in {time.perf_counter() - t0:.1f}s", a.quiet)
+    log(f"geometry {n}^3 generated in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
     geom = rd.Geometry(img, None, w.dx, w.block_edge)
     st = geom.stats()
-    log(f"index built in {time.perf_counter() - t0:.1f}s: {st}", a.quiet)
+    log(f"index built in {time.perf_counter() - t0:.1f}s: {st}")
     n_active, nb, fill = st["n_active"], st["n_blocks"], st["fill"]
     S = len(w.species_D)
     slots = nb * w.block_edge ** 3
 
     stream = torch.cuda.Stream()
-    results = {}
-    fields = {}
-    for storage in ["fp32"] + [f for f in a.forms.split(",") if f]:
+    results, fields = {}, {}
+    forms = [] if a.profile else [f for f in a.forms.split(",") if f]
+    for storage in ["fp32"] + forms:
         steps = a.steps if storage == "fp32" else min(a.steps, a.form_steps)
+        warm = a.warmup if storage == "fp32" else 50
         with torch.cuda.stream(stream):
             sim = build_sim(rd, geom, w, storage, a.graph_steps)
             sim.bind(stream=stream)
-            secs, wall = time_steps(torch, sim, stream, w.dt, a.warmup if storage == "fp32" else 50,
-                                    steps)
+            secs, wall = time_steps(torch, sim, stream, w.dt, warm, steps)
             bal = [sim.balance(sp) for sp in range(S)]
-            fields[storage] = [sim.get_field(sp).float() for sp in range(S)]
+            if storage != "fp32" or forms:
+                fields[storage] = [sim.get_field(sp).float() for sp in range(S)]
             torch.cuda.synchronize()
         es = 4 if storage == "fp32" else 2
-        alg_bytes = 2 * es * S * n_active          # read c + write c' per species per voxel
-        layout_bytes = 2 * es * S * slots + nb * (32 + 128)  # whole blocks + metadata
+        alg_bytes = 2 * es * S * n_active
+        layout_bytes = 2 * es * S * slots + nb * (32 + 512)  # whole blocks + records + codes
         per_step = secs / steps
         results[storage] = {
             "steps": steps,
+            "warmup": warm,
             "seconds": secs,
             "wall_seconds": wall,
             "ms_per_step": per_step * 1e3,
@@ -126,24 +191,22 @@ def main():
             "layout_GBps": layout_bytes / per_step / 1e9,
             "alg_bytes_per_launch": alg_bytes,
             "layout_bytes_per_launch": layout_bytes,
+            "rounding": "nearest" if storage == "fp32" else "stochastic",
             "mass": [b["mass"] for b in bal],
             "inflow": [float(np.sum(b["inflow"])) for b in bal],
             "uptake": [b["uptake"] for b in bal],
         }
-        log(f"{storage}: {results[storage]['ms_per_step']:.4f} ms/step, "
-            f"{results[storage]['updates_per_s']:.3e} upd/s, alg {results[storage]['alg_GBps']:.0f} GB/s, "
-            f"layout {results[storage]['layout_GBps']:.0f} GB/s", a.quiet)
+        log(f"{storage}: {per_step * 1e3:.4f} ms/step, {n_active * steps / secs:.3e} upd/s, "
+            f"alg {alg_bytes / per_step / 1e9:.0f} GB/s, layout {layout_bytes / per_step / 1e9:.0f} GB/s")
         del sim
 
-    # accuracy of the reduced-storage forms against FP32 storage after their steps
-    for storage in results:
-        if storage == "fp32":
-            continue
-        steps = results[storage]["steps"]
+    # reduced-storage accuracy against an FP32-storage run of the same length
+    for storage in forms:
+        steps = results[storage]["steps"] + 50
         with torch.cuda.stream(stream):
             ref = build_sim(rd, geom, w, "fp32", a.graph_steps)
             ref.bind(stream=stream)
-            ref.step(w.dt, 50 + steps)
+            ref.step(w.dt, steps)
             errs = []
             for sp in range(S):
                 r = ref.get_field(sp).float()
@@ -154,10 +217,12 @@ def main():
         del ref
 
     f32 = results["fp32"]
-    value = f32["updates_per_s"]
+    traffic = None
+    if a.traffic and os.path.exists(a.traffic):
+        traffic = json.load(open(a.traffic)).get("hbm_bytes_per_launch")
     out = {
-        "metric": "active-voxel updates/s + achieved HBM GB/s (plain FP32 vs batched/BF16 form)",
-        "value": value,
+        "metric": METRIC,
+        "value": f32["updates_per_s"],
         "unit": "active-voxel updates/s",
         "n_gpus": 1,
         "steps": a.steps,
@@ -180,24 +245,26 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_step<float,8>",
+            "kernel": "k_step8<float,2>",
             "achieved": f32["alg_GBps"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": f32["alg_GBps"] / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
             "alg_bytes_per_launch": f32["alg_bytes_per_launch"],
             "layout_GBps": f32["layout_GBps"],
             "avg_launch_ms": f32["ms_per_step"],
         },
-        "forms": {k: v for k, v in results.items()},
+        "forms": results,
     }
+    if a.batch > 0 and not a.profile:
+        out["forms"]["batched"] = batched_form(torch, rd, W, a.batch, a.batch_max_edge, stream)
+        log(f"batched: {out['forms']['batched']['active_voxel_cg_iterations_per_s']:.3e} "
+            f"voxel-iterations/s")
 
-    if not a.no_cpu_baseline:
+    if not a.no_cpu_baseline and not a.profile:
         import oracle
 
-        threads = len(os.sched_getaffinity(0))
-        os.environ.setdefault("OMP_NUM_THREADS", str(threads))
         prob = oracle.Problem(img, w.species_D, dx=w.dx, robin=w.robin, dirichlet=w.dirichlet,
                               reactions=w.reactions)
         c0 = prob.initial()
@@ -213,8 +280,7 @@ def main():
             "sample": f"{a.cpu_steps} FP64 steps of the same {n}^3 two-species workload on the "
                       f"dense masked grid ({secs:.1f} s)",
         }
-        log(f"cpu oracle: {out['cpu_baseline']['value']:.3e} upd/s on {oracle.num_threads()} threads",
-            a.quiet)
+        log(f"cpu oracle: {out['cpu_baseline']['value']:.3e} upd/s on {oracle.num_threads()} threads")
     print(json.dumps(out), flush=True)
 
 

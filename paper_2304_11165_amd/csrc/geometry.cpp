@@ -135,6 +135,37 @@ rd_status rd_geometry_build(const uint8_t *image, int64_t nx, int64_t ny, int64_
         bi.zg = (int32_t)bz;
     }
 
+    // pass 5 (after the face bits below): per-slot neighbour codes
+    struct CodeFill {
+        static void run(rd_geometry *g)
+        {
+            const int B = g->B, NS = B * B * B, MW = mask_words(B);
+            const int64_t nb = g->nb();
+            g->code.assign((size_t)nb * NS, 0);
+            for (int64_t b = 0; b < nb; ++b) {
+                const uint64_t *rec = &g->mask[(size_t)b * MW];
+                auto own = [&](int s) { return own_bit(rec, B, s); };
+                auto face = [&](int f, int bit) {
+                    if (B == 8) return (bool)((rec[8 + f] >> bit) & 1u);
+                    const int w = f < 4 ? 1 : 2, sh = f < 4 ? 16 * f : 16 * (f - 4);
+                    return (bool)((rec[w] >> (sh + bit)) & 1u);
+                };
+                for (int s = 0; s < NS; ++s) {
+                    const int lx = s % B, ly = (s / B) % B, lz = s / (B * B);
+                    uint8_t c = 0;
+                    if (lx > 0 ? own(s - 1) : face(0, lz * B + ly)) c |= 1;
+                    if (lx < B - 1 ? own(s + 1) : face(1, lz * B + ly)) c |= 2;
+                    if (ly > 0 ? own(s - B) : face(2, lz * B + lx)) c |= 4;
+                    if (ly < B - 1 ? own(s + B) : face(3, lz * B + lx)) c |= 8;
+                    if (lz > 0 ? own(s - B * B) : face(4, ly * B + lx)) c |= 16;
+                    if (lz < B - 1 ? own(s + B * B) : face(5, ly * B + lx)) c |= 32;
+                    if (own(s)) c |= 64;
+                    g->code[(size_t)b * NS + s] = c;
+                }
+            }
+        }
+    };
+
     // pass 4: face bits = own bits of the neighbour voxel across each face
     for (int64_t b = 0; b < nb; ++b) {
         uint64_t *rec = &g->mask[(size_t)b * MW];
@@ -154,5 +185,6 @@ rd_status rd_geometry_build(const uint8_t *image, int64_t nx, int64_t ny, int64_
                 }
         }
     }
+    CodeFill::run(g);
     return RD_OK;
 }

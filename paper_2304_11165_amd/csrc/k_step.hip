@@ -28,6 +28,75 @@ __device__ __forceinline__ void store_val(const StepArgs &a, T *cout, int s, int
     }
 }
 
+// Branch-free update of voxel (lx, ly, lz) of a B = 8 block, all species.  W, Wm, Wp
+// are the active-bit words of planes lz, lz-1, lz+1 (or the -z / +z face words at the
+// block edge); fx0..fy1 the +-x / +-y face words.  ts points at the voxel's centre
+// word in the species-0 tile, sstr is the word distance between species tiles and
+// (oy, oz) the y / z neighbour offsets of the tile layout.  onf: bit d set when the
+// voxel lies on box face d, which marks both Dirichlet planes (onf & dir) and
+// out-of-box neighbours (no wall there).
+template <int S>
+__device__ __forceinline__ void vox8(const StepArgs &a, const float *ts, int sstr, int oy, int oz,
+                                     uint64_t W, uint64_t Wm, uint64_t Wp, uint64_t fx0,
+                                     uint64_t fx1, uint64_t fy0, uint64_t fy1, int lx, int ly,
+                                     int lz, unsigned onf, const float *cen, float *out)
+{
+    const int bit = ly * 8 + lx;
+    const uint64_t fxb = (uint64_t)1 << (lz * 8 + ly), fyb = (uint64_t)1 << (lz * 8 + lx);
+    const uint64_t ob = (uint64_t)1 << bit;
+    unsigned m = 0;
+    m |= ((lx > 0 ? (W & (ob >> 1)) : (fx0 & fxb)) != 0) ? 1u : 0u;
+    m |= ((lx < 7 ? (W & (ob << 1)) : (fx1 & fxb)) != 0) ? 2u : 0u;
+    m |= ((ly > 0 ? (W & (ob >> 8)) : (fy0 & fyb)) != 0) ? 4u : 0u;
+    m |= ((ly < 7 ? (W & (ob << 8)) : (fy1 & fyb)) != 0) ? 8u : 0u;
+    m |= (Wm & ob) != 0 ? 16u : 0u;
+    m |= (Wp & ob) != 0 ? 32u : 0u;
+    const bool act = (W & ob) != 0;
+    const int nwall = __popc(~onf & ~m & 0x3fu);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const float *p = ts + s * sstr;
+        const float nbv[6] = {p[-1], p[1], p[-oy], p[oy], p[-oz], p[oz]};
+        const float upd = rd_update<S>(cen[s], nbv, m, nwall, a.coef[s], cen);
+        const bool isd = (onf & a.coef[s].dir) != 0u;
+        out[s] = act ? (isd ? cen[s] : upd) : 0.0f;
+    }
+}
+
+__device__ __forceinline__ unsigned box_faces(const GeomInfo &g, int gx, int gy, int gz)
+{
+    return (gx == 0 ? 1u : 0u) | (gx == g.nx - 1 ? 2u : 0u) | (gy == 0 ? 4u : 0u) |
+           (gy == g.ny - 1 ? 8u : 0u) | (gz == 0 ? 16u : 0u) | (gz == g.nz - 1 ? 32u : 0u);
+}
+
+// Update of one voxel from its precomputed neighbour code (bits 0-5 active neighbours,
+// bit 6 active) and its box-face bits onf (0 for blocks away from the box boundary).
+// Same arithmetic as every other variant (rd_update).
+template <int S>
+__device__ __forceinline__ void vox_code(const StepArgs &a, const float *ts, int sstr, int oy,
+                                         int oz, unsigned code, unsigned onf, const float *cen,
+                                         float *out)
+{
+    const unsigned m = code & 63u;
+    const bool act = (code & 64u) != 0u;
+    const int nwall = __popc(~onf & ~m & 0x3fu);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const float *p = ts + s * sstr;
+        const float nbv[6] = {p[-1], p[1], p[-oy], p[oy], p[-oz], p[oz]};
+        const float upd = rd_update<S>(cen[s], nbv, m, nwall, a.coef[s], cen);
+        const bool isd = (onf & a.coef[s].dir) != 0u;
+        out[s] = act ? (isd ? cen[s] : upd) : 0.0f;
+    }
+}
+
+// Does a B = 8 block at (bx, by, bz) touch the box boundary (uniform per block)?
+__device__ __forceinline__ bool boundary_block(const GeomInfo &g, int bx, int by, int bz)
+{
+    return bx == 0 || by == 0 || bz == 0 || bx * 8 + 8 >= g.nx || by * 8 + 8 >= g.ny ||
+           bz * 8 + 8 >= g.nz;
+}
+
 // Generic step (used for B = 4): the block's mask record is staged in LDS so the
 // per-thread bit lookups index shared memory instead of a private array.
 template <typename T, int B, int S>
@@ -118,19 +187,28 @@ __global__ __launch_bounds__(256) void k_step8(StepArgs a)
         c0[s] = rd_ld(cin, s * a.sstride + base + w * 64 + lane);
         c1[s] = rd_ld(cin, s * a.sstride + base + (w + 4) * 64 + lane);
     }
+    const unsigned cd0 = a.code[base + w * 64 + lane];
+    const unsigned cd1 = a.code[base + (w + 4) * 64 + lane];
+    // halos: a missing neighbour reads the block itself (always valid) and selects 0
     int ns0, tx0, ns1 = 0, tx1 = 0;
     halo_slot<8>(w, lx, ly, &ns0, &tx0);
     const int n0 = nbr[w];
+    const int64_t hb0 = (int64_t)(n0 >= 0 ? n0 : b) * K::NS + ns0;
 #pragma unroll
-    for (int s = 0; s < S; ++s)
-        h0[s] = n0 >= 0 ? rd_ld(cin, s * a.sstride + (int64_t)n0 * K::NS + ns0) : 0.0f;
+    for (int s = 0; s < S; ++s) {
+        const float v = rd_ld(cin, s * a.sstride + hb0);
+        h0[s] = n0 >= 0 ? v : 0.0f;
+    }
     const bool zf = w < 2;
     if (zf) {
         halo_slot<8>(4 + w, lx, ly, &ns1, &tx1);
         const int n1 = nbr[4 + w];
+        const int64_t hb1 = (int64_t)(n1 >= 0 ? n1 : b) * K::NS + ns1;
 #pragma unroll
-        for (int s = 0; s < S; ++s)
-            h1[s] = n1 >= 0 ? rd_ld(cin, s * a.sstride + (int64_t)n1 * K::NS + ns1) : 0.0f;
+        for (int s = 0; s < S; ++s) {
+            const float v = rd_ld(cin, s * a.sstride + hb1);
+            h1[s] = n1 >= 0 ? v : 0.0f;
+        }
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -141,57 +219,27 @@ __global__ __launch_bounds__(256) void k_step8(StepArgs a)
     }
     __syncthreads();
 
-    const uint64_t *rec = a.mask + (int64_t)b * K::MW;
     const BlockInfo bi = a.info[b];
     int bx, by, bz, gid;
     block_pos(bi, &bx, &by, &bz, &gid);
     const GeomInfo g = a.geom[gid];
-    const uint64_t fx0 = rec[8], fx1 = rec[9], fy0 = rec[10], fy1 = rec[11];
-    const int bit = ly * 8 + lx;
     const int gx = bx * 8 + lx, gy = by * 8 + ly;
+    const bool bnd = boundary_block(g, bx, by, bz);
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         const int lz = w + 4 * k;
-        const uint64_t W = rec[lz];
-        const uint64_t Wm = lz > 0 ? rec[lz - 1] : rec[12];
-        const uint64_t Wp = lz < 7 ? rec[lz + 1] : rec[13];
         const int gz = bz * 8 + lz;
-        const bool act = (W >> bit) & 1ull;
-        unsigned m = 0;
-        m |= (lx > 0 ? (W >> (bit - 1)) & 1ull : (fx0 >> (lz * 8 + ly)) & 1ull) ? 1u : 0u;
-        m |= (lx < 7 ? (W >> (bit + 1)) & 1ull : (fx1 >> (lz * 8 + ly)) & 1ull) ? 2u : 0u;
-        m |= (ly > 0 ? (W >> (bit - 8)) & 1ull : (fy0 >> (lz * 8 + lx)) & 1ull) ? 4u : 0u;
-        m |= (ly < 7 ? (W >> (bit + 8)) & 1ull : (fy1 >> (lz * 8 + lx)) & 1ull) ? 8u : 0u;
-        m |= ((Wm >> bit) & 1ull) ? 16u : 0u;
-        m |= ((Wp >> bit) & 1ull) ? 32u : 0u;
-        unsigned inbox = 0;
-        inbox |= gx > 0 ? 1u : 0u;
-        inbox |= gx < g.nx - 1 ? 2u : 0u;
-        inbox |= gy > 0 ? 4u : 0u;
-        inbox |= gy < g.ny - 1 ? 8u : 0u;
-        inbox |= gz > 0 ? 16u : 0u;
-        inbox |= gz < g.nz - 1 ? 32u : 0u;
-        const int nwall = __popc(inbox & ~m);
-        const int t = K::tidx(lx, ly, lz);
         const int slot = lz * 64 + lane;
-        float cen[S];
+        unsigned onf = 0u;
+        if (bnd) onf = box_faces(g, gx, gy, gz);
+        float cen[S], res[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) cen[s] = k == 0 ? c0[s] : c1[s];
+        vox_code<S>(a, &tile[0][K::tidx(lx, ly, lz)], K::TL, K::E, K::E * K::E, k == 0 ? cd0 : cd1,
+                    onf, cen, res);
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            float r;
-            if (!act) {
-                r = 0.0f;
-            } else if (on_dirichlet(a.coef[s].dir, gx, gy, gz, g.nx, g.ny, g.nz)) {
-                r = cen[s];
-            } else {
-                const float *ts = tile[s];
-                const float nbv[6] = {ts[t - 1], ts[t + 1], ts[t - K::E], ts[t + K::E],
-                                      ts[t - K::E * K::E], ts[t + K::E * K::E]};
-                r = rd_update<S>(cen[s], nbv, m, nwall, a.coef[s], cen);
-            }
-            store_val(a, cout, s, s * a.sstride + base + slot, voxel_id(g, gx, gy, gz), r);
-        }
+        for (int s = 0; s < S; ++s)
+            store_val(a, cout, s, s * a.sstride + base + slot, voxel_id(g, gx, gy, gz), res[s]);
     }
 }
 
@@ -242,23 +290,30 @@ struct Regs {
 };
 }  // namespace p8
 
+// Issue every load of block b for this thread: its own pair, the halo value of face w
+// (neighbour n0) and, for waves 0-1, of face 4 + w (neighbour n1); threads 0-15 also
+// fetch one word of the mask record.
 template <typename T, int S>
-__device__ __forceinline__ void p8_load(const StepArgs &a, const T *cin, int b, const BlockInfo &bi,
-                                        int w, int lane, int slot0, int ns0, int ns1,
-                                        p8::Regs<S> &r)
+__device__ __forceinline__ void p8_load(const StepArgs &a, const T *cin, int b, int n0, int n1,
+                                        int w, int slot0, int ns0, int ns1, p8::Regs<S> &r)
 {
     const int64_t base = (int64_t)b * 512;
 #pragma unroll
     for (int s = 0; s < S; ++s) rd_ld2(cin, s * a.sstride + base + slot0, r.c0[s], r.c1[s]);
-    const int n0 = p8::pick6(w, bi);
+    // a missing neighbour reads the block itself (always valid) and selects 0
+    const int64_t hb0 = (int64_t)(n0 >= 0 ? n0 : b) * 512 + ns0;
 #pragma unroll
-    for (int s = 0; s < S; ++s)
-        r.h0[s] = n0 >= 0 ? rd_ld(cin, s * a.sstride + (int64_t)n0 * 512 + ns0) : 0.0f;
+    for (int s = 0; s < S; ++s) {
+        const float v = rd_ld(cin, s * a.sstride + hb0);
+        r.h0[s] = n0 >= 0 ? v : 0.0f;
+    }
     if (w < 2) {
-        const int n1 = p8::pick6(4 + w, bi);
+        const int64_t hb1 = (int64_t)(n1 >= 0 ? n1 : b) * 512 + ns1;
 #pragma unroll
-        for (int s = 0; s < S; ++s)
-            r.h1[s] = n1 >= 0 ? rd_ld(cin, s * a.sstride + (int64_t)n1 * 512 + ns1) : 0.0f;
+        for (int s = 0; s < S; ++s) {
+            const float v = rd_ld(cin, s * a.sstride + hb1);
+            r.h1[s] = n1 >= 0 ? v : 0.0f;
+        }
     }
     if (threadIdx.x < 16) r.mw = a.mask[(int64_t)b * 16 + threadIdx.x];
 }
@@ -294,14 +349,22 @@ __global__ __launch_bounds__(256) void k_step8p(StepArgs a)
     const bool sr = a.sround != 0;
     const uint32_t step = sr ? *a.ctr + a.ctr_off : 0u;
 
-    BlockInfo bi = a.info[b];
+    // Block records travel through a double-buffered LDS slot (threads 0-7 hold the
+    // next record in a register), which keeps them out of scalar registers.
+    __shared__ int32_t sinfo[2][8];
     p8::Regs<S> cur;
-    p8_load<T, S>(a, cin, b, bi, w, lane, slot0, ns0, ns1, cur);
+    {
+        const int32_t *ib = reinterpret_cast<const int32_t *>(a.info + b);
+        p8_load<T, S>(a, cin, b, ib[w], w < 2 ? ib[4 + w] : -1, w, slot0, ns0, ns1, cur);
+        if (threadIdx.x < 8) sinfo[0][threadIdx.x] = ib[threadIdx.x];
+    }
     int bn = b + stride;
-    BlockInfo bin = bn < hi ? a.info[bn] : bi;
+    int32_t iw = 0;  // threads 0-7: word threadIdx.x of block bn's record
+    if (threadIdx.x < 8 && bn < hi) iw = reinterpret_cast<const int32_t *>(a.info + bn)[threadIdx.x];
+    int ph = 0;  // sinfo[ph] holds block b's record
 
     for (;;) {
-        // stage block b
+        // stage block b (and block bn's record)
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             *reinterpret_cast<float2 *>(&tile[s][p8::tix(2 * lx2, ly, lzp)]) =
@@ -310,17 +373,26 @@ __global__ __launch_bounds__(256) void k_step8p(StepArgs a)
             if (w < 2) tile[s][tx1] = cur.h1[s];
         }
         if (threadIdx.x < 16) srec[threadIdx.x] = cur.mw;
+        if (threadIdx.x < 8) sinfo[ph ^ 1][threadIdx.x] = iw;
         __syncthreads();
 
-        // prefetch block bn (and the neighbour list of the one after)
+        // prefetch block bn (and the record of the one after)
         const bool more = bn < hi;
         p8::Regs<S> nxt;
-        if (more) p8_load<T, S>(a, cin, bn, bin, w, lane, slot0, ns0, ns1, nxt);
+        if (more) {
+            const int n0 = sinfo[ph ^ 1][w];
+            const int n1 = w < 2 ? sinfo[ph ^ 1][4 + w] : -1;
+            p8_load<T, S>(a, cin, bn, n0, n1, w, slot0, ns0, ns1, nxt);
+        }
         const int bnn = bn + stride;
-        const BlockInfo binn = (more && bnn < hi) ? a.info[bnn] : bin;
+        if (threadIdx.x < 8 && more && bnn < hi)
+            iw = reinterpret_cast<const int32_t *>(a.info + bnn)[threadIdx.x];
 
         // compute block b
         int bx, by, bz, gid;
+        BlockInfo bi;
+        bi.xy = sinfo[ph][6];
+        bi.zg = sinfo[ph][7];
         block_pos(bi, &bx, &by, &bz, &gid);
         const GeomInfo g = a.geom[gid];
         const uint64_t W = srec[lzp];
@@ -333,43 +405,11 @@ __global__ __launch_bounds__(256) void k_step8p(StepArgs a)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int lx = 2 * lx2 + j;
-            const int gx = bx * 8 + lx;
-            const int bit = ly * 8 + lx;
-            const bool act = (W >> bit) & 1ull;
-            unsigned m = 0;
-            m |= (lx > 0 ? (W >> (bit - 1)) & 1ull : (fx0 >> (lzp * 8 + ly)) & 1ull) ? 1u : 0u;
-            m |= (lx < 7 ? (W >> (bit + 1)) & 1ull : (fx1 >> (lzp * 8 + ly)) & 1ull) ? 2u : 0u;
-            m |= (ly > 0 ? (W >> (bit - 8)) & 1ull : (fy0 >> (lzp * 8 + lx)) & 1ull) ? 4u : 0u;
-            m |= (ly < 7 ? (W >> (bit + 8)) & 1ull : (fy1 >> (lzp * 8 + lx)) & 1ull) ? 8u : 0u;
-            m |= ((Wm >> bit) & 1ull) ? 16u : 0u;
-            m |= ((Wp >> bit) & 1ull) ? 32u : 0u;
-            unsigned inbox = 0;
-            inbox |= gx > 0 ? 1u : 0u;
-            inbox |= gx < g.nx - 1 ? 2u : 0u;
-            inbox |= gy > 0 ? 4u : 0u;
-            inbox |= gy < g.ny - 1 ? 8u : 0u;
-            inbox |= gz > 0 ? 16u : 0u;
-            inbox |= gz < g.nz - 1 ? 32u : 0u;
-            const int nwall = __popc(inbox & ~m);
-            const int t = p8::tix(lx, ly, lzp);
             float cen[S];
 #pragma unroll
             for (int s = 0; s < S; ++s) cen[s] = j == 0 ? cur.c0[s] : cur.c1[s];
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                float r;
-                if (!act) {
-                    r = 0.0f;
-                } else if (on_dirichlet(a.coef[s].dir, gx, gy, gz, g.nx, g.ny, g.nz)) {
-                    r = cen[s];
-                } else {
-                    const float *ts = tile[s];
-                    const float nbv[6] = {ts[t - 1], ts[t + 1], ts[t - p8::TX], ts[t + p8::TX],
-                                          ts[t - p8::TX * p8::TY], ts[t + p8::TX * p8::TY]};
-                    r = rd_update<S>(cen[s], nbv, m, nwall, a.coef[s], cen);
-                }
-                res[j][s] = r;
-            }
+            vox8<S>(a, &tile[0][p8::tix(lx, ly, lzp)], p8::TL, p8::TX, p8::TX * p8::TY, W, Wm, Wp,
+                    fx0, fx1, fy0, fy1, lx, ly, lzp, box_faces(g, bx * 8 + lx, gy, gz), cen, res[j]);
         }
 #pragma unroll
         for (int s = 0; s < S; ++s) {
@@ -386,9 +426,8 @@ __global__ __launch_bounds__(256) void k_step8p(StepArgs a)
         __syncthreads();  // every wave is done with the tile before it is refilled
         cur = nxt;
         b = bn;
-        bi = bin;
         bn = bnn;
-        bin = binn;
+        ph ^= 1;
     }
 }
 

@@ -272,6 +272,7 @@ SimLayout sim_layout(const rd_sim &s, uint32_t features, int64_t cp_slots)
     L.info = off; off = align256(off + sizeof(BlockInfo) * (size_t)std::max<int64_t>(nb, 1));
     L.mask = off; off = align256(off + 8 * (size_t)mask_words(g.B) * (size_t)std::max<int64_t>(nb, 1));
     L.geom = off; off = align256(off + sizeof(GeomInfo));
+    L.code = off; off = align256(off + (size_t)std::max<int64_t>(nb, 1) * NS);
     L.field_elems = nb * NS;
     for (int p = 0; p < 2; ++p) {
         L.field[p] = off;
@@ -324,6 +325,7 @@ rd_status rd_sim::upload()
     if (ncu > 0) n_cu = ncu;
     HIPCHK(hipMemcpyAsync(ws + L.info, G.info.data(), sizeof(BlockInfo) * nb, hipMemcpyHostToDevice, stream));
     HIPCHK(hipMemcpyAsync(ws + L.mask, G.mask.data(), 8 * mask_words(G.B) * nb, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(ws + L.code, G.code.data(), G.code.size(), hipMemcpyHostToDevice, stream));
     GeomInfo gi{(int32_t)G.nx, (int32_t)G.ny, (int32_t)G.nz, 0};
     geom_host = gi;
     HIPCHK(hipMemcpyAsync(ws + L.geom, &geom_host, sizeof(GeomInfo), hipMemcpyHostToDevice, stream));
@@ -367,6 +369,7 @@ StepArgs rd_sim::step_args(double dt, int in_buf) const
     StepArgs a{};
     a.info = (const BlockInfo *)(ws + L.info);
     a.mask = (const uint64_t *)(ws + L.mask);
+    a.code = (const uint8_t *)(ws + L.code);
     a.geom = (const GeomInfo *)(ws + L.geom);
     a.cin = field_ptr(in_buf, 0);
     a.cout = field_ptr(1 - in_buf, 0);

@@ -21,6 +21,9 @@ struct rd_geometry {
     std::vector<int64_t> block_id;   // [nb], ascending linear id
     std::vector<BlockInfo> info;     // [nb]
     std::vector<uint64_t> mask;      // [nb * mask_words(B)]
+    // per-slot neighbour code [nb * B^3]: bit d (d = 0..5, order -x,+x,-y,+y,-z,+z) set
+    // when that face neighbour is an active voxel, bit 6 set when the slot is active
+    std::vector<uint8_t> code;
     int64_t nb() const { return (int64_t)block_id.size(); }
 };
 

@@ -49,6 +49,7 @@ struct GeomInfo {
 struct StepArgs {
     const BlockInfo *info;
     const uint64_t *mask;
+    const uint8_t *code;   // per-slot neighbour codes (bits 0-5 neighbours, bit 6 active)
     const GeomInfo *geom;  // indexed by geometry id
     const void *cin;       // T*, species-major
     void *cout;

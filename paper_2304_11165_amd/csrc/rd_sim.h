@@ -30,7 +30,7 @@ struct Reaction {
 
 // Byte offsets of every array inside the caller's workspace.
 struct SimLayout {
-    size_t info, mask, geom;
+    size_t info, mask, geom, code;
     size_t field[2];
     int64_t field_elems;  // nb * B^3
     int nparts;
@@ -62,7 +62,7 @@ struct rd_sim {
     int graph_steps = 32;
     bool use_graph = true;
     bool xcd_map = true;
-    bool persist = true;  // B = 8: persistent prefetching kernel
+    bool persist = false;  // B = 8: persistent prefetching kernel (measured slower)
     int wg_per_cu = 8;    // resident workgroups per CU of the persistent grid
     int n_cu = 256;       // compute units of the bound device
     bool sround = false;  // stochastic rounding on store (BF16 / FP16 storage)

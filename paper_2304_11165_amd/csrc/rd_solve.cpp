@@ -35,8 +35,8 @@ struct CgOut {
     bool converged = false;
 };
 
-constexpr int CHECK_EVERY = 50;   // iterations between true-residual checks
-constexpr int STALL_CHECKS = 20;  // stop after this many checks without a 10% gain
+constexpr int CHECK_EVERY = 25;  // iterations between true-residual checks
+constexpr int STALL_CHECKS = 8;  // stop after this many checks without a 10% gain
 
 // ---- host labelling of 6-connected active clusters ------------------------
 // Union-find over the active slots (index b * B^3 + slot) of the block grid.

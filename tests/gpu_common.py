@@ -12,7 +12,7 @@ def rel_l2(a, b, mask):
 
 
 def make_gpu(rd, img, D, dx=1.0, robin=None, dirichlet=None, reactions=None, storage="fp32",
-             B=8, sdf=None, features=0, checkpoint_slots=0, graph=True, xcd=True, persist=True,
+             B=8, sdf=None, features=0, checkpoint_slots=0, graph=True, xcd=True, persist=False,
              wg_per_cu=8):
     g = rd.Geometry(img, sdf, dx, B)
     s = rd.Sim(g, storage)

@@ -73,8 +73,9 @@ def test_spheres64_full_config(rd, oracle_mod):
     assert np.all(got8[0][~act] == 0)
     # every kernel variant gives the same bits: B = 4, one workgroup per block,
     # plain or XCD-aware mapping, graph replay or direct launches, grid sizes
-    variants = [dict(B=4, graph=False), dict(persist=False), dict(persist=False, xcd=False),
-                dict(xcd=False, graph=False), dict(wg_per_cu=1), dict(wg_per_cu=3, xcd=False)]
+    variants = [dict(B=4, graph=False), dict(persist=True), dict(persist=True, xcd=False),
+                dict(xcd=False, graph=False), dict(persist=True, wg_per_cu=1),
+                dict(persist=True, wg_per_cu=3, xcd=False)]
     for v in variants:
         _, sv = make_gpu(rd, img, w.species_D, w.dx, dirichlet=w.dirichlet, **v)
         sv.step(w.dt, w.steps)
@@ -222,7 +223,8 @@ def test_stochastic_rounding_variants_agree(rd, storage):
     replay, direct launches and every kernel variant round identically."""
     img, _ = W.boolean_spheres(40, 0.5, 3.0, 6.0, seed=3)
     out = []
-    for v in [dict(), dict(graph=False), dict(persist=False), dict(B=4), dict(wg_per_cu=2)]:
+    for v in [dict(), dict(graph=False), dict(persist=True), dict(B=4),
+              dict(persist=True, wg_per_cu=2)]:
         g, s = make_gpu(rd, img, [1.0, 0.5], dirichlet={(0, 0): 1.0}, reactions=[(0, 1, 0.02)],
                         storage=storage, **v)
         s.set_rounding(1, seed=99)
@@ -246,7 +248,7 @@ def test_species_counts_and_storage_kernels_agree(rd, oracle_mod, storage, S):
     dirichlet = {(0, 0): 1.0, (S - 1, 5): 0.5}
     init = rng.uniform(0, 1, (S,) + img.shape).astype(np.float32)
     out = []
-    for v in [dict(), dict(persist=False), dict(B=4)]:
+    for v in [dict(), dict(persist=True), dict(B=4)]:
         g, s = make_gpu(rd, img, D, robin=robin, dirichlet=dirichlet, reactions=reactions,
                         storage=storage, **v)
         for sp in range(S):
