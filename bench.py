@@ -45,6 +45,7 @@ def parse():
     p.add_argument("--cpu-steps", type=int, default=4, help="oracle steps in the CPU sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--graph-steps", type=int, default=32)
+    p.add_argument("--no-graph", action="store_true", help="direct launches (for profilers)")
     p.add_argument("--profile", action="store_true", help="only the timed FP32 loop")
     p.add_argument("--copy-calibration", action="store_true")
     p.add_argument("--traffic", default="", help="JSON file with measured HBM bytes per launch")
@@ -73,7 +74,7 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_per_launch": 2 * (1 << 30), "copy_GBps": 2 * (1 << 30) / t / 1e9}))
 
 
-def build_sim(rd, geom, w, storage, graph_steps):
+def build_sim(rd, geom, w, storage, graph_steps, use_graph=True):
     s = rd.Sim(geom, storage)
     for d in w.species_D:
         s.add_species(d)
@@ -83,7 +84,7 @@ def build_sim(rd, geom, w, storage, graph_steps):
         s.set_robin(sp, k)
     for (sp, f), v in w.dirichlet.items():
         s.set_dirichlet(sp, f, v)
-    s.set_launch(graph_steps, True, True)
+    s.set_launch(graph_steps, use_graph, True)
     if storage != "fp32":
         s.set_rounding(1, seed=2304)
     return s
@@ -169,8 +170,12 @@ def main():
         steps = a.steps if storage == "fp32" else min(a.steps, a.form_steps)
         warm = a.warmup if storage == "fp32" else 50
         with torch.cuda.stream(stream):
-            sim = build_sim(rd, geom, w, storage, a.graph_steps)
+            sim = build_sim(rd, geom, w, storage, a.graph_steps, not a.no_graph)
             sim.bind(stream=stream)
+            launch = None
+            if not a.profile:
+                sim.autotune(w.dt, 200)  # resets the fields afterwards
+                launch = sim.get_launch()
             secs, wall = time_steps(torch, sim, stream, w.dt, warm, steps)
             bal = [sim.balance(sp) for sp in range(S)]
             if storage != "fp32" or forms:
@@ -192,6 +197,7 @@ def main():
             "alg_bytes_per_launch": alg_bytes,
             "layout_bytes_per_launch": layout_bytes,
             "rounding": "nearest" if storage == "fp32" else "stochastic",
+            "launch": launch,
             "mass": [b["mass"] for b in bal],
             "inflow": [float(np.sum(b["inflow"])) for b in bal],
             "uptake": [b["uptake"] for b in bal],

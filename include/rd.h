@@ -97,6 +97,11 @@ rd_status rd_geometry_export_index(const rd_geometry *g, int64_t *block_id, int3
 /* Copy the active bitmasks out: uint64[nb * ceil(B^3/64)]; slot (lz*B+ly)*B+lx is
  * bit (slot % 64) of word slot/64 of its block. */
 rd_status rd_geometry_export_masks(const rd_geometry *g, uint64_t *masks);
+/* Copy the per-slot neighbour codes out: uint8[nb * B^3]; bit d (d = 0..5 in order
+ * -x,+x,-y,+y,-z,+z) is set when that face neighbour is an active voxel, bit 6 when
+ * the slot itself is active.  The step kernels read these instead of re-deriving
+ * neighbour activity from the masks. */
+rd_status rd_geometry_export_codes(const rd_geometry *g, uint8_t *codes);
 void rd_geometry_destroy(rd_geometry *g);
 
 /* ---- simulation ------------------------------------------------------------ */
@@ -200,6 +205,25 @@ rd_status rd_sim_adjoint(rd_sim *sim, const float *dev_seed, int seed_mode, int6
 rd_status rd_sim_set_species_D(rd_sim *sim, int species, double D);
 rd_status rd_sim_set_reaction_rate(rd_sim *sim, int index, double rate);
 void rd_sim_destroy(rd_sim *sim);
+
+/* ---- autotuning ----------------------------------------------------------- */
+
+/* Time every launch configuration of a bound simulation (steps per captured graph
+ * 16 or 64; plain or XCD-aware block order; for B = 8 also the persistent kernel with
+ * 2, 4 or 8 workgroups per CU) on `trial_steps` steps of size dt, with HIP events on
+ * the bound stream, and keep the fastest.  All configurations give bitwise-identical
+ * fields.  The trials advance the fields, so the simulation is reset afterwards
+ * (fields zero, Dirichlet values applied): call it before rd_sim_set_field.
+ * *best_ms (may be NULL) receives the mean time per step of the chosen setting. */
+rd_status rd_sim_autotune(rd_sim *sim, double dt, int64_t trial_steps, double *best_ms);
+/* Autotune each candidate simulation (for example the same image indexed with 4^3 and
+ * with 8^3 blocks, same species and parameters) and report the fastest:
+ * *best_index, and ms_per_step[n] (may be NULL). */
+rd_status rd_autotune_pick(rd_sim *const *sims, int n, double dt, int64_t trial_steps,
+                           int *best_index, double *ms_per_step);
+/* Current launch configuration (any output may be NULL). */
+rd_status rd_sim_get_launch(const rd_sim *sim, int *graph_steps, int *use_graph, int *xcd_map,
+                            int *persistent, int *wg_per_cu);
 
 /* ---- batches of geometries ------------------------------------------------- */
 

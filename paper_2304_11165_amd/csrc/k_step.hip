@@ -9,7 +9,11 @@
 //     as FP32 in an LDS tile of (B+2)^3 words per species; corners are unused.
 //   * Activity of the six neighbours comes from the block's mask record (own bits
 //     plus the neighbours' face bits), so no neighbour mask is read.
-//   * Inactive slots are written as 0; Dirichlet voxels are copied through.
+//   * Inactive slots are 0 in every field buffer (zero-filled on upload).  The
+//     default kernels predicate every load on the activity of the voxel it reads and
+//     store active voxels only, so sectors without active voxels are never moved;
+//     the persistent kernel stores 0 into inactive slots.  Dirichlet voxels are
+//     copied through.
 // The stencil is HBM-bound (about 2 FLOP per byte), so there is no MFMA here.
 #include "rd_device.h"
 
@@ -97,66 +101,84 @@ __device__ __forceinline__ bool boundary_block(const GeomInfo &g, int bx, int by
            bz * 8 + 8 >= g.nz;
 }
 
-// Generic step (used for B = 4): the block's mask record is staged in LDS so the
-// per-thread bit lookups index shared memory instead of a private array.
-template <typename T, int B, int S>
-__global__ __launch_bounds__(256) void k_step(StepArgs a)
+// B = 4 step: one wave per block (lane = slot), four independent blocks per
+// workgroup.  Each wave stages its block and the 6 x 16 halo values in a private
+// LDS tile of 6^3 words per species, then updates its 64 voxels from the neighbour
+// codes.  Only wave-level ordering is needed (no workgroup barrier).
+template <typename T, int S>
+__global__ __launch_bounds__(256) void k_step4w(StepArgs a)
 {
-    using K = Blk<B>;
-    using C = Cfg<B>;
-    __shared__ float tile[C::BPW][S][K::TL];
-    __shared__ uint64_t srec[C::BPW][K::MW];
-
-    const int sub = threadIdx.x / C::TPB;
-    const int lt = threadIdx.x % C::TPB;
+    constexpr int E = 6, E2 = 36, TLW = 216;
+    __shared__ float tile[4][S][TLW];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int grp = map_group(blockIdx.x, a.xcd_chunk);
-    const int b = grp * C::BPW + sub;
-    const bool valid = b < a.nb;
+    const int b = __builtin_amdgcn_readfirstlane(grp * 4 + wv);
+    if (b >= a.nb) return;  // the whole wave leaves; no workgroup barrier below
     const T *cin = (const T *)a.cin;
     T *cout = (T *)a.cout;
+    const int64_t base = (int64_t)b * 64;
+    const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
+    const int32_t *nbr = a.info[b].nbr;
 
-    BlockInfo bi = {};
-    if (valid) {
-        bi = a.info[b];
-        if (lt < K::MW) srec[sub][lt] = a.mask[(int64_t)b * K::MW + lt];
+    // Wave-uniform mask record: own word, faces 0-3 (16 bits each) and faces 4-5.
+    // Lane l's bit is l in all three (slot l; face l / 16 at (u, v) with bit
+    // v * 4 + u = l % 16), so every load is predicated on the voxel it reads.
+    const uint64_t *rec = a.mask + (int64_t)b * 3;
+    const uint64_t Wo = rec[0], Wf0 = rec[1], Wf1 = rec[2];
+    const bool act = (Wo >> lane) & 1ull;
+    const bool two = lane < 32;
+    const bool e0 = (Wf0 >> lane) & 1ull, e1 = two && ((Wf1 >> lane) & 1ull);
+
+    float c[S], h0[S], h1[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) c[s] = act ? rd_ld(cin, s * a.sstride + base + lane) : 0.0f;
+    const unsigned code = act ? (unsigned)a.code[base + lane] : 0u;
+    // halo: lanes 16f..16f+15 fetch face f (f = 0..3); lanes 0..31 also faces 4, 5.
+    // A face bit is set only when the neighbour block exists; the address still
+    // falls back to the block itself so that it is valid in every lane.
+    const int f0 = lane >> 4, f1 = 4 + (lane >> 4);
+    const int u = lane & 3, v = (lane >> 2) & 3;
+    int ns0, tx0, ns1 = 0, tx1 = 0;
+    halo_slot<4>(f0, u, v, &ns0, &tx0);
+    const int n0 = f0 == 0 ? nbr[0] : f0 == 1 ? nbr[1] : f0 == 2 ? nbr[2] : nbr[3];
+    const int64_t hb0 = (int64_t)(n0 >= 0 ? n0 : b) * 64 + ns0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) h0[s] = e0 ? rd_ld(cin, s * a.sstride + hb0) : 0.0f;
+    if (two) {
+        halo_slot<4>(f1, u, v, &ns1, &tx1);
+        const int n1 = f1 == 4 ? nbr[4] : nbr[5];
+        const int64_t hb1 = (int64_t)(n1 >= 0 ? n1 : b) * 64 + ns1;
+#pragma unroll
+        for (int s = 0; s < S; ++s) h1[s] = e1 ? rd_ld(cin, s * a.sstride + hb1) : 0.0f;
     }
-    stage_tile<T, B>(tile[sub], cin, a.sstride, S, b, bi, lt, valid);
-    __syncthreads();
-    if (!valid) return;
-    const uint64_t *rec = srec[sub];
+    const int t = ((lz + 1) * E + (ly + 1)) * E + (lx + 1);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        tile[wv][s][t] = c[s];
+        tile[wv][s][tx0] = h0[s];
+        if (two) tile[wv][s][tx1] = h1[s];
+    }
+    // the wave's LDS writes complete before its reads of other lanes' words
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
+    const BlockInfo bi = a.info[b];
     int bx, by, bz, gid;
     block_pos(bi, &bx, &by, &bz, &gid);
     const GeomInfo g = a.geom[gid];
-    const int64_t base = (int64_t)b * K::NS;
+    const int gx = bx * 4 + lx, gy = by * 4 + ly, gz = bz * 4 + lz;
+    const bool bnd = bx == 0 || by == 0 || bz == 0 || bx * 4 + 4 >= g.nx || by * 4 + 4 >= g.ny ||
+                     bz * 4 + 4 >= g.nz;
+    unsigned onf = 0u;
+    if (bnd) onf = box_faces(g, gx, gy, gz);
+    float res[S];
+    vox_code<S>(a, &tile[wv][0][t], TLW, E, E2, code, onf, c, res);
+    // inactive slots hold 0 in every field buffer and are never written
+    if (act) {
 #pragma unroll
-    for (int k = 0; k < C::VPT; ++k) {
-        const int slot = lt + k * C::TPB;
-        const int lx = slot % B, ly = (slot / B) % B, lz = slot / (B * B);
-        const int gx = bx * B + lx, gy = by * B + ly, gz = bz * B + lz;
-        const bool act = own_bit<B>(rec, slot);
-        int nwall = 0;
-        const unsigned nbm = act ? nb_bits<B>(rec, lx, ly, lz, gx, gy, gz, g.nx, g.ny, g.nz, &nwall)
-                                 : 0u;
-        const int t = K::tidx(lx, ly, lz);
-        float cen[S];
-#pragma unroll
-        for (int s = 0; s < S; ++s) cen[s] = tile[sub][s][t];
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            float r;
-            if (!act) {
-                r = 0.0f;
-            } else if (on_dirichlet(a.coef[s].dir, gx, gy, gz, g.nx, g.ny, g.nz)) {
-                r = cen[s];
-            } else {
-                const float *ts = tile[sub][s];
-                const float nbv[6] = {ts[t - 1], ts[t + 1], ts[t - K::E], ts[t + K::E],
-                                      ts[t - K::E * K::E], ts[t + K::E * K::E]};
-                r = rd_update<S>(cen[s], nbv, nbm, nwall, a.coef[s], cen);
-            }
-            store_val(a, cout, s, s * a.sstride + base + slot, voxel_id(g, gx, gy, gz), r);
-        }
+        for (int s = 0; s < S; ++s)
+            store_val(a, cout, s, s * a.sstride + base + lane, voxel_id(g, gx, gy, gz), res[s]);
     }
 }
 
@@ -180,35 +202,39 @@ __global__ __launch_bounds__(256) void k_step8(StepArgs a)
     T *cout = (T *)a.cout;
     const int64_t base = (int64_t)b * K::NS;
     const int32_t *nbr = a.info[b].nbr;
+    // Wave-uniform mask words: own planes w and w + 4, face w and (waves 0-1) face
+    // 4 + w.  Lane l's bit is l in each of them (own slot (lx, ly); face coordinates
+    // (u, v) = (lx, ly) with bit v * 8 + u), so every load below is predicated on
+    // the activity of the voxel it reads: only sectors holding active voxels move.
+    const uint64_t *rec = a.mask + (int64_t)b * K::MW;
+    const bool zf = w < 2;
+    const uint64_t Wo0 = rec[w], Wo1 = rec[w + 4], Wf0 = rec[8 + w];
+    const uint64_t Wf1 = zf ? rec[12 + w] : 0ull;
+    const bool a0 = (Wo0 >> lane) & 1ull, a1 = (Wo1 >> lane) & 1ull;
+    const bool e0 = (Wf0 >> lane) & 1ull, e1 = (Wf1 >> lane) & 1ull;
 
     float c0[S], c1[S], h0[S], h1[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        c0[s] = rd_ld(cin, s * a.sstride + base + w * 64 + lane);
-        c1[s] = rd_ld(cin, s * a.sstride + base + (w + 4) * 64 + lane);
+        c0[s] = a0 ? rd_ld(cin, s * a.sstride + base + w * 64 + lane) : 0.0f;
+        c1[s] = a1 ? rd_ld(cin, s * a.sstride + base + (w + 4) * 64 + lane) : 0.0f;
     }
-    const unsigned cd0 = a.code[base + w * 64 + lane];
-    const unsigned cd1 = a.code[base + (w + 4) * 64 + lane];
-    // halos: a missing neighbour reads the block itself (always valid) and selects 0
+    const unsigned cd0 = a0 ? (unsigned)a.code[base + w * 64 + lane] : 0u;
+    const unsigned cd1 = a1 ? (unsigned)a.code[base + (w + 4) * 64 + lane] : 0u;
+    // halos: a face bit is set only when the neighbour block exists; the address
+    // still falls back to the block itself so that it is valid in every lane
     int ns0, tx0, ns1 = 0, tx1 = 0;
     halo_slot<8>(w, lx, ly, &ns0, &tx0);
     const int n0 = nbr[w];
     const int64_t hb0 = (int64_t)(n0 >= 0 ? n0 : b) * K::NS + ns0;
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-        const float v = rd_ld(cin, s * a.sstride + hb0);
-        h0[s] = n0 >= 0 ? v : 0.0f;
-    }
-    const bool zf = w < 2;
+    for (int s = 0; s < S; ++s) h0[s] = e0 ? rd_ld(cin, s * a.sstride + hb0) : 0.0f;
     if (zf) {
         halo_slot<8>(4 + w, lx, ly, &ns1, &tx1);
         const int n1 = nbr[4 + w];
         const int64_t hb1 = (int64_t)(n1 >= 0 ? n1 : b) * K::NS + ns1;
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const float v = rd_ld(cin, s * a.sstride + hb1);
-            h1[s] = n1 >= 0 ? v : 0.0f;
-        }
+        for (int s = 0; s < S; ++s) h1[s] = e1 ? rd_ld(cin, s * a.sstride + hb1) : 0.0f;
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -237,9 +263,12 @@ __global__ __launch_bounds__(256) void k_step8(StepArgs a)
         for (int s = 0; s < S; ++s) cen[s] = k == 0 ? c0[s] : c1[s];
         vox_code<S>(a, &tile[0][K::tidx(lx, ly, lz)], K::TL, K::E, K::E * K::E, k == 0 ? cd0 : cd1,
                     onf, cen, res);
+        // inactive slots hold 0 in every field buffer and are never written
+        if (k == 0 ? a0 : a1) {
 #pragma unroll
-        for (int s = 0; s < S; ++s)
-            store_val(a, cout, s, s * a.sstride + base + slot, voxel_id(g, gx, gy, gz), res[s]);
+            for (int s = 0; s < S; ++s)
+                store_val(a, cout, s, s * a.sstride + base + slot, voxel_id(g, gx, gy, gz), res[s]);
+        }
     }
 }
 
@@ -650,8 +679,9 @@ void launch_step_s(const StepArgs &a, int groups, hipStream_t st)
             hipLaunchKernelGGL((k_step8p<T, S>), dim3(a.grid), dim3(256), 0, st, a);
         else
             hipLaunchKernelGGL((k_step8<T, S>), dim3(groups), dim3(256), 0, st, a);
-    } else
-        hipLaunchKernelGGL((k_step<T, B, S>), dim3(groups), dim3(256), 0, st, a);
+    } else {
+        hipLaunchKernelGGL((k_step4w<T, S>), dim3(groups), dim3(256), 0, st, a);
+    }
 }
 
 template <typename T, int B>

@@ -117,6 +117,13 @@ extern "C" rd_status rd_geometry_export_masks(const rd_geometry *g, uint64_t *ma
     return RD_OK;
 }
 
+extern "C" rd_status rd_geometry_export_codes(const rd_geometry *g, uint8_t *codes)
+{
+    if (!g || !codes) return rd_fail(RD_ERR_ARG, "NULL argument");
+    memcpy(codes, g->code.data(), g->code.size());
+    return RD_OK;
+}
+
 extern "C" void rd_geometry_destroy(rd_geometry *g) { delete g; }
 
 // ---------------------------------------------------------------------------
@@ -332,6 +339,10 @@ rd_status rd_sim::upload()
     const size_t es = storage == RD_FP32 ? 4 : 2;
     for (int p = 0; p < 2; ++p)
         LAUNCHCHK(rd_launch_fill_u32(ws + L.field[p], 0u, (int64_t)(es * L.field_elems * S / 4), stream));
+    // checkpoint / segment slots: the step kernels never write inactive slots, so
+    // every buffer they write must start with zeros there
+    if (L.cp_stride > 0 && cp_slots > 0)
+        LAUNCHCHK(rd_launch_fill_u32(ws + L.cp, 0u, (int64_t)(L.cp_stride * (size_t)cp_slots / 4), stream));
     LAUNCHCHK(rd_launch_fill_u32(ws + L.res, 0u, 64 * 2, stream));  // results + step counter
     if (!host_res) HIPCHK(hipHostMalloc((void **)&host_res, 64 * sizeof(double), hipHostMallocDefault));
     cur = 0;
@@ -624,3 +635,112 @@ extern "C" rd_status rd_sim_reduce(rd_sim *sim, int species, double *mass, doubl
 }
 
 extern "C" void rd_sim_destroy(rd_sim *sim) { delete sim; }
+
+// ---------------------------------------------------------------------------
+// autotuning
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct LaunchCfg {
+    bool persist, xcd, graph;
+    int wg, gsteps;
+};
+
+// Mean time per step of `steps` steps with the current launch configuration,
+// measured with HIP events on the simulation's stream.
+rd_status time_steps(rd_sim *sim, double dt, int64_t steps, double *ms)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    hipError_t er = hipEventCreate(&e1);
+    if (er != hipSuccess) {
+        hipEventDestroy(e0);
+        HIPCHK(er);
+    }
+    rd_status s = sim->step(dt, std::max<int64_t>(1, steps / 4));  // warm-up + graph capture
+    if (s == RD_OK && (er = hipEventRecord(e0, sim->stream)) != hipSuccess) s = rd_fail(RD_ERR_HIP, "event");
+    if (s == RD_OK) s = sim->step(dt, steps);
+    if (s == RD_OK && (er = hipEventRecord(e1, sim->stream)) != hipSuccess) s = rd_fail(RD_ERR_HIP, "event");
+    float msf = 0.0f;
+    if (s == RD_OK && (er = hipEventSynchronize(e1)) != hipSuccess) s = rd_fail(RD_ERR_HIP, "event sync");
+    if (s == RD_OK && (er = hipEventElapsedTime(&msf, e0, e1)) != hipSuccess) s = rd_fail(RD_ERR_HIP, "elapsed");
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (s == RD_OK) *ms = (double)msf / (double)steps;
+    return s;
+}
+
+}  // namespace
+
+extern "C" rd_status rd_sim_autotune(rd_sim *sim, double dt, int64_t trial_steps, double *best_ms)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    if (!sim->ws) return rd_fail(RD_ERR_STATE, "bind a workspace first");
+    if (trial_steps < 1) return rd_fail(RD_ERR_ARG, "trial_steps >= 1");
+    rd_status s = sim->check_dt(dt);
+    if (s != RD_OK) return s;
+    std::vector<LaunchCfg> cands;
+    const int gs[2] = {16, 64};
+    for (int gi = 0; gi < 2; ++gi) {
+        for (int xcd = 0; xcd < 2; ++xcd) cands.push_back({false, xcd != 0, true, 8, gs[gi]});
+        if (sim->g->B == 8)
+            for (int wg : {2, 4, 8}) cands.push_back({true, true, true, wg, gs[gi]});
+    }
+    double best = 1e300;
+    LaunchCfg bc = cands[0];
+    for (const LaunchCfg &c : cands) {
+        sim->persist = c.persist;
+        sim->xcd_map = c.xcd;
+        sim->use_graph = c.graph;
+        sim->wg_per_cu = c.wg;
+        sim->graph_steps = c.gsteps;
+        sim->invalidate_graphs();
+        double ms = 0.0;
+        if ((s = time_steps(sim, dt, trial_steps, &ms)) != RD_OK) return s;
+        if (ms < best) {
+            best = ms;
+            bc = c;
+        }
+    }
+    sim->persist = bc.persist;
+    sim->xcd_map = bc.xcd;
+    sim->use_graph = bc.graph;
+    sim->wg_per_cu = bc.wg;
+    sim->graph_steps = bc.gsteps;
+    sim->invalidate_graphs();
+    if (best_ms) *best_ms = best;
+    // the trials advanced the fields: start again from zero + Dirichlet values
+    return sim->upload();
+}
+
+extern "C" rd_status rd_autotune_pick(rd_sim *const *sims, int n, double dt, int64_t trial_steps,
+                                      int *best_index, double *ms_per_step)
+{
+    if (!sims || n <= 0 || !best_index) return rd_fail(RD_ERR_ARG, "need sims and best_index");
+    double best = 1e300;
+    *best_index = -1;
+    for (int i = 0; i < n; ++i) {
+        double ms = 0.0;
+        rd_status s = rd_sim_autotune(sims[i], dt, trial_steps, &ms);
+        if (s != RD_OK) return s;
+        if (ms_per_step) ms_per_step[i] = ms;
+        if (ms < best) {
+            best = ms;
+            *best_index = i;
+        }
+    }
+    return RD_OK;
+}
+
+extern "C" rd_status rd_sim_get_launch(const rd_sim *sim, int *graph_steps, int *use_graph,
+                                       int *xcd_map, int *persistent, int *wg_per_cu)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    if (graph_steps) *graph_steps = sim->graph_steps;
+    if (use_graph) *use_graph = sim->use_graph;
+    if (xcd_map) *xcd_map = sim->xcd_map;
+    if (persistent) *persistent = sim->persist;
+    if (wg_per_cu) *wg_per_cu = sim->wg_per_cu;
+    return RD_OK;
+}

@@ -46,6 +46,7 @@ _SIGS = {
     "rd_geometry_stats": ([P, P, P, P, P], ci),
     "rd_geometry_export_index": ([P, P, P], ci),
     "rd_geometry_export_masks": ([P, P], ci),
+    "rd_geometry_export_codes": ([P, P], ci),
     "rd_geometry_destroy": ([P], None),
     "rd_sim_create": ([P, ci, P], ci),
     "rd_sim_add_species": ([P, f64, P], ci),
@@ -69,6 +70,9 @@ _SIGS = {
     "rd_sim_set_species_D": ([P, ci, f64], ci),
     "rd_sim_set_reaction_rate": ([P, ci, f64], ci),
     "rd_sim_destroy": ([P], None),
+    "rd_sim_autotune": ([P, f64, i64, P], ci),
+    "rd_autotune_pick": ([P, ci, f64, i64, P, P], ci),
+    "rd_sim_get_launch": ([P, P, P, P, P, P], ci),
     "rd_batch_create": ([P, ci, ci, P], ci),
     "rd_batch_workspace_bytes": ([P, P], ci),
     "rd_batch_bind": ([P, P, sz, P], ci),
@@ -179,6 +183,12 @@ class Geometry:
     def export_masks(self):
         return rd_geometry_export_masks(self.handle, self.block_edge)
 
+    def export_codes(self):
+        nb = rd_geometry_stats(self.handle)[1]
+        c = np.zeros((nb, self.block_edge ** 3), dtype=np.uint8)
+        _check(_lib.rd_geometry_export_codes(self.handle, _np_ptr(c)), "rd_geometry_export_codes")
+        return c
+
     def __del__(self, _destroy=_lib.rd_geometry_destroy):
         h = getattr(self, "handle", None)
         if h:
@@ -223,6 +233,20 @@ class Sim:
     def set_launch(self, graph_steps=32, use_graph=True, xcd_map=False):
         _check(_lib.rd_sim_set_launch(self.handle, int(graph_steps), int(bool(use_graph)),
                                       int(bool(xcd_map))), "rd_sim_set_launch")
+
+    def autotune(self, dt, trial_steps=200):
+        """Pick the fastest launch configuration (resets the fields); returns ms/step."""
+        ms = f64()
+        _check(_lib.rd_sim_autotune(self.handle, float(dt), int(trial_steps), ctypes.byref(ms)),
+               "rd_sim_autotune")
+        return ms.value
+
+    def get_launch(self):
+        vals = [ci() for _ in range(5)]
+        _check(_lib.rd_sim_get_launch(self.handle, *[ctypes.byref(v) for v in vals]),
+               "rd_sim_get_launch")
+        keys = ("graph_steps", "use_graph", "xcd_map", "persistent", "wg_per_cu")
+        return {k: v.value for k, v in zip(keys, vals)}
 
     def set_kernel(self, persistent=True, wg_per_cu=8):
         _check(_lib.rd_sim_set_kernel(self.handle, int(bool(persistent)), int(wg_per_cu)),
@@ -368,6 +392,17 @@ class Batch:
         if h:
             _destroy(h)
             self.handle = None
+
+
+def autotune_pick(sims, dt, trial_steps=200):
+    """Autotune each bound candidate Sim (e.g. the same image with 4^3 and 8^3 blocks)
+    and return (index of the fastest, ms per step of each)."""
+    arr = (P * len(sims))(*[s.handle for s in sims])
+    best = ci()
+    ms = np.zeros(len(sims))
+    _check(_lib.rd_autotune_pick(arr, len(sims), float(dt), int(trial_steps), ctypes.byref(best),
+                                 _np_ptr(ms)), "rd_autotune_pick")
+    return best.value, ms
 
 
 def stability_dt_max(D_max, dx=1.0, rate_max=0.0, robin_max=0.0):

@@ -52,6 +52,38 @@ def test_index_bit_exact_random(rd, oracle_mod, B, seed):
     assert st["n_blocks"] == len(i2)
 
 
+def _codes_numpy(img, ids, B):
+    """Neighbour codes from the image: bit d for an active face neighbour (order
+    -x,+x,-y,+y,-z,+z; outside the box = inactive), bit 6 for an active slot."""
+    act = np.asarray(img) != 0
+    nz, ny, nx = act.shape
+    NBx, NBy = -(-nx // B), -(-ny // B)
+    pad = np.zeros((nz + 2 + B, ny + 2 + B, nx + 2 + B), dtype=bool)
+    pad[1:nz + 1, 1:ny + 1, 1:nx + 1] = act
+    out = np.zeros((len(ids), B ** 3), dtype=np.uint8)
+    lz, ly, lx = np.meshgrid(np.arange(B), np.arange(B), np.arange(B), indexing="ij")
+    lz, ly, lx = lz.ravel(), ly.ravel(), lx.ravel()
+    for i, l in enumerate(ids):
+        bx, by, bz = l % NBx, (l // NBx) % NBy, l // (NBx * NBy)
+        x, y, z = bx * B + lx + 1, by * B + ly + 1, bz * B + lz + 1
+        c = np.zeros(B ** 3, dtype=np.uint8)
+        for d, (dx, dy, dz) in enumerate([(-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0),
+                                          (0, 0, -1), (0, 0, 1)]):
+            c |= pad[z + dz, y + dy, x + dx].astype(np.uint8) << d
+        c |= pad[z, y, x].astype(np.uint8) << 6
+        out[i] = c
+    return out
+
+
+@pytest.mark.parametrize("B", [4, 8])
+@pytest.mark.parametrize("seed", range(6))
+def test_neighbour_codes_bit_exact(rd, oracle_mod, B, seed):
+    img = W.random_tiny_geometry(seed, density=[0.05, 0.5, 0.95][seed % 3])
+    g = rd.Geometry(img, None, 1.0, B)
+    ids, _ = g.export_index()
+    np.testing.assert_array_equal(g.export_codes(), _codes_numpy(img, ids, B))
+
+
 @pytest.mark.parametrize("B", [4, 8])
 def test_index_bit_exact_workloads(rd, oracle_mod, B):
     for name in ("spheres64", "decay256"):

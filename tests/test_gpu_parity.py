@@ -261,3 +261,28 @@ def test_species_counts_and_storage_kernels_agree(rd, oracle_mod, storage, S):
         prob = oracle_mod.Problem(img, D, robin=robin, dirichlet=dirichlet, reactions=reactions)
         ref = prob.run(prob.apply_dirichlet(init.astype(np.float64)), 0.1, 40)
         assert np.abs(out[0] - ref).max() < 1e-5
+
+
+def test_autotune_resets_and_matches(rd):
+    """The autotuner keeps a launch setting that gives the same bits as the default and
+    resets the fields; picking between 4^3 and 8^3 indexings returns a valid choice."""
+    w = W.workload("soil512", small=True)
+    img, _ = W.workload_geometry("soil512", small=True)
+    _, ref = make_gpu(rd, img, w.species_D, robin=w.robin, dirichlet=w.dirichlet,
+                      reactions=w.reactions)
+    ref.step(w.dt, 150)
+    want = fields(ref, 2)
+    sims = []
+    for B in (8, 4):
+        _, s = make_gpu(rd, img, w.species_D, robin=w.robin, dirichlet=w.dirichlet,
+                        reactions=w.reactions, B=B)
+        sims.append(s)
+    best, ms = rd.autotune_pick(sims, w.dt, 40)
+    print(f"autotune: B=8 {ms[0]:.4f} ms/step, B=4 {ms[1]:.4f} ms/step, best index {best}, "
+          f"launch {sims[best].get_launch()}")
+    assert best in (0, 1) and np.all(ms > 0)
+    for s in sims:
+        assert s.steps_taken() == 0
+        assert s.balance(1)["mass"] == 0.0  # reset: B is zero everywhere
+        s.step(w.dt, 150)
+        np.testing.assert_array_equal(fields(s, 2), want)
