@@ -104,6 +104,14 @@ def time_steps(torch, sim, stream, dt, warmup, steps):
     return e0.elapsed_time(e1) / 1e3, wall
 
 
+def step_kernel_name(B, launch, S):
+    """HIP kernel that runs the FP32 step under a launch setting (B = 4 has one)."""
+    if B == 4:
+        return f"k_step4w<float,{S}>"
+    kern = (launch or {}).get("kernel", "block")
+    return {"block": "k_step8", "column": "k_step8z", "persistent": "k_step8p"}[kern] + f"<float,{S}>"
+
+
 def batched_form(torch, rd, W, count, max_edge, stream):
     """Per-geometry tortuosity along x of `count` boolean sphere packings (edge
     U{64..max_edge}, porosity U(0.3, 0.7)), all in one set of CG launches."""
@@ -251,7 +259,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_step8<float,2>",
+            "kernel": step_kernel_name(w.block_edge, f32["launch"], S),
             "achieved": f32["alg_GBps"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -128,11 +128,15 @@ rd_status rd_sim_clear_dirichlet(rd_sim *sim, int species);
  * (xcd_map = 1; its L2 then holds most halo reads).  Results are bitwise
  * identical for every choice. */
 rd_status rd_sim_set_launch(rd_sim *sim, int graph_steps, int use_graph, int xcd_map);
-/* Step kernel for B = 8: persistent = 1 (default) runs a fixed grid of
- * wg_per_cu * (compute units) workgroups that walk the block list and prefetch the
- * next block while computing the current one; persistent = 0 launches one
- * workgroup per block.  Results are bitwise identical. */
-rd_status rd_sim_set_kernel(rd_sim *sim, int persistent, int wg_per_cu);
+/* Step kernel for B = 8 (ignored for B = 4, which always runs one wave per block):
+ *   kernel = 0 (default): one 256-thread workgroup per block;
+ *   kernel = 1: persistent, a fixed grid of wg_per_cu * (compute units) workgroups
+ *               that walk the block list and prefetch the next block while
+ *               computing the current one;
+ *   kernel = 2: one wave per block, each lane walking a z-column of 8 voxels.
+ * Results are bitwise identical.  RD_ERR_ARG for kernel outside 0..2 or wg_per_cu
+ * outside 1..32. */
+rd_status rd_sim_set_kernel(rd_sim *sim, int kernel, int wg_per_cu);
 
 /* Rounding of BF16 / FP16 stores (no effect with FP32 storage).  stochastic = 0:
  * round to nearest even (default).  stochastic = 1: round up with probability equal
@@ -209,8 +213,9 @@ void rd_sim_destroy(rd_sim *sim);
 /* ---- autotuning ----------------------------------------------------------- */
 
 /* Time every launch configuration of a bound simulation (steps per captured graph
- * 16 or 64; plain or XCD-aware block order; for B = 8 also the persistent kernel with
- * 2, 4 or 8 workgroups per CU) on `trial_steps` steps of size dt, with HIP events on
+ * 16 or 64; plain or XCD-aware block order; for B = 8 the workgroup-per-block and
+ * z-column kernels, and the persistent kernel with 2, 4 or 8 workgroups per CU) on
+ * `trial_steps` steps of size dt, with HIP events on
  * the bound stream, and keep the fastest.  All configurations give bitwise-identical
  * fields.  The trials advance the fields, so the simulation is reset afterwards
  * (fields zero, Dirichlet values applied): call it before rd_sim_set_field.
@@ -223,7 +228,7 @@ rd_status rd_autotune_pick(rd_sim *const *sims, int n, double dt, int64_t trial_
                            int *best_index, double *ms_per_step);
 /* Current launch configuration (any output may be NULL). */
 rd_status rd_sim_get_launch(const rd_sim *sim, int *graph_steps, int *use_graph, int *xcd_map,
-                            int *persistent, int *wg_per_cu);
+                            int *kernel, int *wg_per_cu);
 
 /* ---- batches of geometries ------------------------------------------------- */
 

@@ -11,7 +11,8 @@
 //     plus the neighbours' face bits), so no neighbour mask is read.
 //   * Inactive slots are 0 in every field buffer (zero-filled on upload).  The
 //     default kernels predicate every load on the activity of the voxel it reads and
-//     store active voxels only, so sectors without active voxels are never moved;
+//     store whole sectors that hold an active voxel (sector_active), so sectors
+//     without active voxels are never moved;
 //     the persistent kernel stores 0 into inactive slots.  Dirichlet voxels are
 //     copied through.
 // The stencil is HBM-bound (about 2 FLOP per byte), so there is no MFMA here.
@@ -129,34 +130,43 @@ __global__ __launch_bounds__(256) void k_step4w(StepArgs a)
     const bool two = lane < 32;
     const bool e0 = (Wf0 >> lane) & 1ull, e1 = two && ((Wf1 >> lane) & 1ull);
 
-    float c[S], h0[S], h1[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) c[s] = act ? rd_ld(cin, s * a.sstride + base + lane) : 0.0f;
-    const unsigned code = act ? (unsigned)a.code[base + lane] : 0u;
     // halo: lanes 16f..16f+15 fetch face f (f = 0..3); lanes 0..31 also faces 4, 5.
-    // A face bit is set only when the neighbour block exists; the address still
-    // falls back to the block itself so that it is valid in every lane.
+    // The six neighbour indices are loaded once as wave-uniform values and each lane
+    // selects its face's by value (a select between memory reads of nbr[f] was once
+    // lowered to divergent control flow that gave the +y lanes the -y index).  A face
+    // bit is set only when the neighbour block exists; the address still falls back
+    // to the block itself so that it is valid in every lane.
     const int f0 = lane >> 4, f1 = 4 + (lane >> 4);
+    const BlockInfo bi0 = a.info[b];
+    int n0 = bi0.nbr[0];
+    n0 = f0 == 1 ? bi0.nbr[1] : n0;
+    n0 = f0 == 2 ? bi0.nbr[2] : n0;
+    n0 = f0 == 3 ? bi0.nbr[3] : n0;
+    const int n1 = (f1 & 1) ? bi0.nbr[5] : bi0.nbr[4];  // lanes 32..63 never load (e1 = 0)
+    typedef typename RawOf<T>::type R;
+    R rc[S], rh0[S], rh1[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) rc[s] = ld_raw(cin, s * a.sstride + base + lane, act);
+    const unsigned code = act ? (unsigned)a.code[base + lane] : 0u;
     const int u = lane & 3, v = (lane >> 2) & 3;
     int ns0, tx0, ns1 = 0, tx1 = 0;
     halo_slot<4>(f0, u, v, &ns0, &tx0);
-    const int n0 = f0 == 0 ? nbr[0] : f0 == 1 ? nbr[1] : f0 == 2 ? nbr[2] : nbr[3];
+    halo_slot<4>(f1 & 5, u, v, &ns1, &tx1);
     const int64_t hb0 = (int64_t)(n0 >= 0 ? n0 : b) * 64 + ns0;
 #pragma unroll
-    for (int s = 0; s < S; ++s) h0[s] = e0 ? rd_ld(cin, s * a.sstride + hb0) : 0.0f;
-    if (two) {
-        halo_slot<4>(f1, u, v, &ns1, &tx1);
-        const int n1 = f1 == 4 ? nbr[4] : nbr[5];
-        const int64_t hb1 = (int64_t)(n1 >= 0 ? n1 : b) * 64 + ns1;
+    for (int s = 0; s < S; ++s) rh0[s] = ld_raw(cin, s * a.sstride + hb0, e0);
+    const int64_t hb1 = (int64_t)(n1 >= 0 ? n1 : b) * 64 + ns1;
 #pragma unroll
-        for (int s = 0; s < S; ++s) h1[s] = e1 ? rd_ld(cin, s * a.sstride + hb1) : 0.0f;
-    }
+    for (int s = 0; s < S; ++s) rh1[s] = ld_raw(cin, s * a.sstride + hb1, e1);
+    // all loads are issued; convert to FP32
+    float c[S];
     const int t = ((lz + 1) * E + (ly + 1)) * E + (lx + 1);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
+        c[s] = from_raw<T>(rc[s]);
         tile[wv][s][t] = c[s];
-        tile[wv][s][tx0] = h0[s];
-        if (two) tile[wv][s][tx1] = h1[s];
+        tile[wv][s][tx0] = from_raw<T>(rh0[s]);
+        if (two) tile[wv][s][tx1] = from_raw<T>(rh1[s]);
     }
     // the wave's LDS writes complete before its reads of other lanes' words
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -174,8 +184,8 @@ __global__ __launch_bounds__(256) void k_step4w(StepArgs a)
     if (bnd) onf = box_faces(g, gx, gy, gz);
     float res[S];
     vox_code<S>(a, &tile[wv][0][t], TLW, E, E2, code, onf, c, res);
-    // inactive slots hold 0 in every field buffer and are never written
-    if (act) {
+    // whole sectors only; an inactive slot of an active sector stores its 0 again
+    if (sector_active<T>(Wo, lane)) {
 #pragma unroll
         for (int s = 0; s < S; ++s)
             store_val(a, cout, s, s * a.sstride + base + lane, voxel_id(g, gx, gy, gz), res[s]);
@@ -213,11 +223,12 @@ __global__ __launch_bounds__(256) void k_step8(StepArgs a)
     const bool a0 = (Wo0 >> lane) & 1ull, a1 = (Wo1 >> lane) & 1ull;
     const bool e0 = (Wf0 >> lane) & 1ull, e1 = (Wf1 >> lane) & 1ull;
 
-    float c0[S], c1[S], h0[S], h1[S];
+    typedef typename RawOf<T>::type R;
+    R r0[S], r1[S], rh0[S], rh1[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        c0[s] = a0 ? rd_ld(cin, s * a.sstride + base + w * 64 + lane) : 0.0f;
-        c1[s] = a1 ? rd_ld(cin, s * a.sstride + base + (w + 4) * 64 + lane) : 0.0f;
+        r0[s] = ld_raw(cin, s * a.sstride + base + w * 64 + lane, a0);
+        r1[s] = ld_raw(cin, s * a.sstride + base + (w + 4) * 64 + lane, a1);
     }
     const unsigned cd0 = a0 ? (unsigned)a.code[base + w * 64 + lane] : 0u;
     const unsigned cd1 = a1 ? (unsigned)a.code[base + (w + 4) * 64 + lane] : 0u;
@@ -228,20 +239,22 @@ __global__ __launch_bounds__(256) void k_step8(StepArgs a)
     const int n0 = nbr[w];
     const int64_t hb0 = (int64_t)(n0 >= 0 ? n0 : b) * K::NS + ns0;
 #pragma unroll
-    for (int s = 0; s < S; ++s) h0[s] = e0 ? rd_ld(cin, s * a.sstride + hb0) : 0.0f;
-    if (zf) {
-        halo_slot<8>(4 + w, lx, ly, &ns1, &tx1);
-        const int n1 = nbr[4 + w];
-        const int64_t hb1 = (int64_t)(n1 >= 0 ? n1 : b) * K::NS + ns1;
+    for (int s = 0; s < S; ++s) rh0[s] = ld_raw(cin, s * a.sstride + hb0, e0);
+    halo_slot<8>(4 + (w & 1), lx, ly, &ns1, &tx1);  // waves 2-3 have no z face
+    const int n1 = nbr[4 + (w & 1)];
+    const int64_t hb1 = (int64_t)(n1 >= 0 ? n1 : b) * K::NS + ns1;
 #pragma unroll
-        for (int s = 0; s < S; ++s) h1[s] = e1 ? rd_ld(cin, s * a.sstride + hb1) : 0.0f;
-    }
+    for (int s = 0; s < S; ++s) rh1[s] = ld_raw(cin, s * a.sstride + hb1, e1);  // e1 = 0 there
+    // all loads are issued; convert to FP32
+    float c0[S], c1[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
+        c0[s] = from_raw<T>(r0[s]);
+        c1[s] = from_raw<T>(r1[s]);
         tile[s][K::tidx(lx, ly, w)] = c0[s];
         tile[s][K::tidx(lx, ly, w + 4)] = c1[s];
-        tile[s][tx0] = h0[s];
-        if (zf) tile[s][tx1] = h1[s];
+        tile[s][tx0] = from_raw<T>(rh0[s]);
+        if (zf) tile[s][tx1] = from_raw<T>(rh1[s]);
     }
     __syncthreads();
 
@@ -263,11 +276,137 @@ __global__ __launch_bounds__(256) void k_step8(StepArgs a)
         for (int s = 0; s < S; ++s) cen[s] = k == 0 ? c0[s] : c1[s];
         vox_code<S>(a, &tile[0][K::tidx(lx, ly, lz)], K::TL, K::E, K::E * K::E, k == 0 ? cd0 : cd1,
                     onf, cen, res);
-        // inactive slots hold 0 in every field buffer and are never written
-        if (k == 0 ? a0 : a1) {
+        // whole sectors only; an inactive slot of an active sector stores its 0 again
+        if (sector_active<T>(k == 0 ? Wo0 : Wo1, lane)) {
 #pragma unroll
             for (int s = 0; s < S; ++s)
                 store_val(a, cout, s, s * a.sstride + base + slot, voxel_id(g, gx, gy, gz), res[s]);
+        }
+    }
+}
+
+// B = 8 step, one wave per block and four blocks per workgroup.  Lane l = (lx, ly)
+// walks its z-column lz = 0..7: the -z / +z neighbours of a voxel are the values
+// above and below it in the lane's own registers (the -z / +z face halos at the
+// column ends), and only the +-x / +-y neighbours go through a wave-private LDS
+// tile (8 planes of 10 x 10 words per species: the block plus its four side halos).
+// Every per-block cost (mask words, neighbour list, addresses, predicates) is paid
+// once per 8 voxels of a lane.  Only wave-level ordering is needed.
+namespace z8 {
+constexpr int TP = 100;      // words per plane (10 x 10)
+constexpr int TS = 8 * TP;   // words per species
+__device__ __forceinline__ int tix(int x, int y, int lz) { return (lz * 10 + (y + 1)) * 10 + (x + 1); }
+}  // namespace z8
+
+template <typename T, int S>
+__global__ __launch_bounds__(256) void k_step8z(StepArgs a)
+{
+    __shared__ float tile[4][S][z8::TS];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int grp = map_group(blockIdx.x, a.xcd_chunk);
+    const int b = __builtin_amdgcn_readfirstlane(grp * 4 + wv);
+    if (b >= a.nb) return;  // the whole wave leaves; no workgroup barrier below
+    const T *cin = (const T *)a.cin;
+    T *cout = (T *)a.cout;
+    const int64_t base = (int64_t)b * 512;
+    const int lx = lane & 7, ly = lane >> 3;
+    const int32_t *nbr = a.info[b].nbr;
+    // mask record: own plane words 0-7, face words 8-13; lane l's bit is l in each
+    // (own slot (lx, ly) of a plane; face coordinates (u, v) = (lx, ly), bit v*8+u)
+    const uint64_t *rec = a.mask + (int64_t)b * 16;
+    uint64_t Wo[8], Wf[6];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) Wo[z] = rec[z];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) Wf[f] = rec[8 + f];
+
+    typedef typename RawOf<T>::type R;
+    R rc[S][8], rh[6][S];
+    unsigned cd[8];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        const bool act = (Wo[z] >> lane) & 1ull;
+#pragma unroll
+        for (int s = 0; s < S; ++s) rc[s][z] = ld_raw(cin, s * a.sstride + base + z * 64 + lane, act);
+        cd[z] = act ? (unsigned)a.code[base + z * 64 + lane] : 0u;
+    }
+    // face halos, one value per lane and face: lane (u, v) = (lx, ly) reads the
+    // neighbour slot across face f at face coordinates (u, v); a face bit is set only
+    // when the neighbour block exists, the address falls back to the block itself
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        int ns;
+        switch (f) {
+        case 0: ns = (ly * 8 + lx) * 8 + 7; break;  // (x=7, y=u, z=v)
+        case 1: ns = (ly * 8 + lx) * 8 + 0; break;  // (x=0, y=u, z=v)
+        case 2: ns = (ly * 8 + 7) * 8 + lx; break;  // (x=u, y=7, z=v)
+        case 3: ns = (ly * 8 + 0) * 8 + lx; break;  // (x=u, y=0, z=v)
+        case 4: ns = (7 * 8 + ly) * 8 + lx; break;  // (x=u, y=v, z=7)
+        default: ns = (0 * 8 + ly) * 8 + lx; break; // (x=u, y=v, z=0)
+        }
+        const int n = nbr[f];
+        const bool e = (Wf[f] >> lane) & 1ull;
+        const int64_t hb = (int64_t)(n >= 0 ? n : b) * 512 + ns;
+#pragma unroll
+        for (int s = 0; s < S; ++s) rh[f][s] = ld_raw(cin, s * a.sstride + hb, e);
+    }
+    // all loads are issued; convert to FP32.  LDS: the block's planes and the four side
+    // halos (face f < 4 at (u, v) = (lx, ly)); the z halos stay in registers
+    float c[S][8], zlo[S], zhi[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        float *ts = &tile[wv][s][0];
+#pragma unroll
+        for (int z = 0; z < 8; ++z) {
+            c[s][z] = from_raw<T>(rc[s][z]);
+            ts[z8::tix(lx, ly, z)] = c[s][z];
+        }
+        ts[z8::tix(-1, lx, ly)] = from_raw<T>(rh[0][s]);
+        ts[z8::tix(8, lx, ly)] = from_raw<T>(rh[1][s]);
+        ts[z8::tix(lx, -1, ly)] = from_raw<T>(rh[2][s]);
+        ts[z8::tix(lx, 8, ly)] = from_raw<T>(rh[3][s]);
+        zlo[s] = from_raw<T>(rh[4][s]);
+        zhi[s] = from_raw<T>(rh[5][s]);
+    }
+    // the wave's LDS writes complete before its reads of other lanes' words
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    const BlockInfo bi = a.info[b];
+    int bx, by, bz, gid;
+    block_pos(bi, &bx, &by, &bz, &gid);
+    const GeomInfo g = a.geom[gid];
+    const int gx = bx * 8 + lx, gy = by * 8 + ly;
+    const bool bnd = boundary_block(g, bx, by, bz);
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        const int gz = bz * 8 + z;
+        const unsigned code = cd[z];
+        const unsigned m = code & 63u;
+        const bool act = (code & 64u) != 0u;
+        unsigned onf = 0u;
+        if (bnd) onf = box_faces(g, gx, gy, gz);
+        const int nwall = __popc(~onf & ~m & 0x3fu);
+        float cen[S], res[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) cen[s] = c[s][z];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const float *p = &tile[wv][s][z8::tix(lx, ly, z)];
+            const float dn = z == 0 ? zlo[s] : c[s][z > 0 ? z - 1 : 0];
+            const float up = z == 7 ? zhi[s] : c[s][z < 7 ? z + 1 : 7];
+            const float nbv[6] = {p[-1], p[1], p[-10], p[10], dn, up};
+            const float upd = rd_update<S>(cen[s], nbv, m, nwall, a.coef[s], cen);
+            const bool isd = (onf & a.coef[s].dir) != 0u;
+            res[s] = act ? (isd ? cen[s] : upd) : 0.0f;
+        }
+        // whole sectors only; an inactive slot of an active sector stores its 0 again
+        if (sector_active<T>(Wo[z], lane)) {
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                store_val(a, cout, s, s * a.sstride + base + z * 64 + lane, voxel_id(g, gx, gy, gz),
+                          res[s]);
         }
     }
 }
@@ -301,16 +440,6 @@ __device__ __forceinline__ void halo(int f, int u, int v, int *ns, int *t)
     case 4: *ns = (7 * 8 + v) * 8 + u; *t = tix(u, v, -1); break;
     default: *ns = (0 * 8 + v) * 8 + u; *t = tix(u, v, 8); break;
     }
-}
-__device__ __forceinline__ int pick6(int i, const BlockInfo &bi)
-{
-    int r = bi.nbr[0];
-    r = i == 1 ? bi.nbr[1] : r;
-    r = i == 2 ? bi.nbr[2] : r;
-    r = i == 3 ? bi.nbr[3] : r;
-    r = i == 4 ? bi.nbr[4] : r;
-    r = i == 5 ? bi.nbr[5] : r;
-    return r;
 }
 template <int S>
 struct Regs {
@@ -675,8 +804,10 @@ template <typename T, int B, int S>
 void launch_step_s(const StepArgs &a, int groups, hipStream_t st)
 {
     if constexpr (B == 8) {
-        if (a.persist)
+        if (a.kernel == 1)
             hipLaunchKernelGGL((k_step8p<T, S>), dim3(a.grid), dim3(256), 0, st, a);
+        else if (a.kernel == 2)
+            hipLaunchKernelGGL((k_step8z<T, S>), dim3(groups), dim3(256), 0, st, a);
         else
             hipLaunchKernelGGL((k_step8<T, S>), dim3(groups), dim3(256), 0, st, a);
     } else {
@@ -687,7 +818,9 @@ void launch_step_s(const StepArgs &a, int groups, hipStream_t st)
 template <typename T, int B>
 int launch_step_t(const StepArgs &a, hipStream_t st)
 {
-    int groups = groups_for<B>(a.nb);
+    // blocks per workgroup: 1 for the B = 8 workgroup kernel, 4 for the wave kernels
+    const int bpw = (B == 8 && a.kernel != 2) ? 1 : 4;
+    int groups = (a.nb + bpw - 1) / bpw;
     if (a.xcd_chunk > 0) groups = 8 * a.xcd_chunk;
     switch (a.S) {
     case 1: launch_step_s<T, B, 1>(a, groups, st); break;

@@ -211,11 +211,12 @@ extern "C" rd_status rd_sim_set_launch(rd_sim *sim, int graph_steps, int use_gra
     return RD_OK;
 }
 
-extern "C" rd_status rd_sim_set_kernel(rd_sim *sim, int persistent, int wg_per_cu)
+extern "C" rd_status rd_sim_set_kernel(rd_sim *sim, int kernel, int wg_per_cu)
 {
     if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    if (kernel < 0 || kernel > 2) return rd_fail(RD_ERR_ARG, "kernel in 0..2");
     if (wg_per_cu < 1 || wg_per_cu > 32) return rd_fail(RD_ERR_ARG, "wg_per_cu in 1..32");
-    sim->persist = persistent != 0;
+    sim->kernel = kernel;
     sim->wg_per_cu = wg_per_cu;
     sim->invalidate_graphs();
     return RD_OK;
@@ -434,9 +435,9 @@ uint32_t *rd_sim::step_counter() const { return (uint32_t *)(ws + L.res + 384); 
 
 void rd_sim::launch_shape(StepArgs &a) const
 {
+    a.kernel = g->B == 8 ? kernel : 0;
     a.xcd_chunk = xcd_chunk(a.nb);
-    a.persist = (persist && g->B == 8) ? 1 : 0;
-    if (a.persist) {
+    if (a.kernel == 1) {
         // a multiple of 8 (one share per XCD), no more workgroups than blocks need
         int grid = n_cu * wg_per_cu;
         const int need = ((a.nb + 7) / 8) * 8;
@@ -467,7 +468,8 @@ rd_status rd_sim::launch_steps(double dt, int64_t n)
 int rd_sim::xcd_chunk(int nb) const
 {
     if (!xcd_map) return 0;
-    const int bpw = g->B == 8 ? 1 : 4;
+    // blocks per workgroup: 1 for the B = 8 workgroup kernels, 4 for the wave kernels
+    const int bpw = (g->B == 8 && kernel != 2) ? 1 : 4;
     const int groups = (nb + bpw - 1) / bpw;
     if (groups < 64) return 0;
     return (groups + 7) / 8;
@@ -643,7 +645,8 @@ extern "C" void rd_sim_destroy(rd_sim *sim) { delete sim; }
 namespace {
 
 struct LaunchCfg {
-    bool persist, xcd, graph;
+    int kernel;
+    bool xcd, graph;
     int wg, gsteps;
 };
 
@@ -683,14 +686,16 @@ extern "C" rd_status rd_sim_autotune(rd_sim *sim, double dt, int64_t trial_steps
     std::vector<LaunchCfg> cands;
     const int gs[2] = {16, 64};
     for (int gi = 0; gi < 2; ++gi) {
-        for (int xcd = 0; xcd < 2; ++xcd) cands.push_back({false, xcd != 0, true, 8, gs[gi]});
-        if (sim->g->B == 8)
-            for (int wg : {2, 4, 8}) cands.push_back({true, true, true, wg, gs[gi]});
+        for (int xcd = 0; xcd < 2; ++xcd) cands.push_back({0, xcd != 0, true, 8, gs[gi]});
+        if (sim->g->B == 8) {
+            for (int xcd = 0; xcd < 2; ++xcd) cands.push_back({2, xcd != 0, true, 8, gs[gi]});
+            for (int wg : {2, 4, 8}) cands.push_back({1, true, true, wg, gs[gi]});
+        }
     }
     double best = 1e300;
     LaunchCfg bc = cands[0];
     for (const LaunchCfg &c : cands) {
-        sim->persist = c.persist;
+        sim->kernel = c.kernel;
         sim->xcd_map = c.xcd;
         sim->use_graph = c.graph;
         sim->wg_per_cu = c.wg;
@@ -703,7 +708,7 @@ extern "C" rd_status rd_sim_autotune(rd_sim *sim, double dt, int64_t trial_steps
             bc = c;
         }
     }
-    sim->persist = bc.persist;
+    sim->kernel = bc.kernel;
     sim->xcd_map = bc.xcd;
     sim->use_graph = bc.graph;
     sim->wg_per_cu = bc.wg;
@@ -734,13 +739,13 @@ extern "C" rd_status rd_autotune_pick(rd_sim *const *sims, int n, double dt, int
 }
 
 extern "C" rd_status rd_sim_get_launch(const rd_sim *sim, int *graph_steps, int *use_graph,
-                                       int *xcd_map, int *persistent, int *wg_per_cu)
+                                       int *xcd_map, int *kernel, int *wg_per_cu)
 {
     if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
     if (graph_steps) *graph_steps = sim->graph_steps;
     if (use_graph) *use_graph = sim->use_graph;
     if (xcd_map) *xcd_map = sim->xcd_map;
-    if (persistent) *persistent = sim->persist;
+    if (kernel) *kernel = sim->kernel;
     if (wg_per_cu) *wg_per_cu = sim->wg_per_cu;
     return RD_OK;
 }

@@ -35,9 +35,67 @@ __device__ __forceinline__ uint16_t bf16_rne(float v)
     return (uint16_t)(u >> 16);
 }
 
-__device__ __forceinline__ void rd_st(float *p, int64_t i, float v) { p[i] = v; }
+// FP32 fields are streamed (written once per step, read by the next step), so their
+// stores are nontemporal (measured faster on the 512^3 soil volume).
+__device__ __forceinline__ void rd_st(float *p, int64_t i, float v) { __builtin_nontemporal_store(v, p + i); }
 __device__ __forceinline__ void rd_st(bf16_t *p, int64_t i, float v) { p[i].bits = bf16_rne(v); }
 __device__ __forceinline__ void rd_st(_Float16 *p, int64_t i, float v) { p[i] = (_Float16)v; }
+
+// ---- predicated loads ---------------------------------------------------------
+// A kernel that skips inactive voxels loads raw storage words under a predicate
+// (ld_raw, 0 where the predicate is false) and converts them to FP32 only after all of
+// its loads are issued (from_raw).  The conversion of BF16 / FP16 words is opaque
+// inline asm: written as plain C it is folded into each predicated load's branch,
+// which then waits for its own load, so the loads would no longer overlap.
+__device__ __forceinline__ float ld_raw(const float *p, int64_t i, bool pred)
+{
+    return pred ? p[i] : 0.0f;
+}
+__device__ __forceinline__ uint32_t ld_raw(const bf16_t *p, int64_t i, bool pred)
+{
+    return pred ? (uint32_t)p[i].bits : 0u;
+}
+__device__ __forceinline__ uint32_t ld_raw(const _Float16 *p, int64_t i, bool pred)
+{
+    return pred ? (uint32_t)__builtin_bit_cast(uint16_t, p[i]) : 0u;
+}
+template <typename T> struct RawOf { typedef uint32_t type; };
+template <> struct RawOf<float> { typedef float type; };
+
+template <typename T> __device__ __forceinline__ float from_raw(typename RawOf<T>::type r);
+template <> __device__ __forceinline__ float from_raw<float>(float r) { return r; }
+template <> __device__ __forceinline__ float from_raw<bf16_t>(uint32_t r)
+{
+    float f;  // BF16 is the upper half of an FP32 pattern
+    asm("v_lshlrev_b32 %0, 16, %1" : "=v"(f) : "v"(r));
+    return f;
+}
+template <> __device__ __forceinline__ float from_raw<_Float16>(uint32_t r)
+{
+    float f;  // exact FP16 -> FP32 conversion of the low half
+    asm("v_cvt_f32_f16 %0, %1" : "=v"(f) : "v"(r));
+    return f;
+}
+
+// ---- store granularity ------------------------------------------------------
+// The step kernels write a slot when any voxel of its aligned sector of
+// RD_STORE_SECTOR bytes is active; the inactive slots of such a sector store the 0
+// they already hold.  Sectors without an active voxel are never written, and the
+// memory side only ever sees whole sectors (no partially written ones).
+#ifndef RD_STORE_SECTOR
+#define RD_STORE_SECTOR 128
+#endif
+// W: a 64-slot activity word, bit: the slot's bit in it (slots are consecutive in
+// memory within the word).
+template <typename T>
+__device__ __forceinline__ bool sector_active(uint64_t W, int bit)
+{
+    // slots per sector, at most the 64 slots of one activity word
+    constexpr int V = RD_STORE_SECTOR / (int)sizeof(T) < 64 ? RD_STORE_SECTOR / (int)sizeof(T) : 64;
+    static_assert(V >= 1 && (V & (V - 1)) == 0, "sector of 1..64 slots");
+    if constexpr (V == 64) return W != 0ull;
+    else return ((W >> (bit & ~(V - 1))) & ((1ull << V) - 1ull)) != 0ull;
+}
 
 // ---- stochastic rounding --------------------------------------------------
 // 32-bit finaliser of MurmurHash3 (Appleby): a bijective avalanche mix, used as
@@ -90,7 +148,10 @@ __device__ __forceinline__ _Float16 f16_sr(float v, uint32_t rnd)
     return u01 < prob_up ? (hf > of ? h : o) : (hf > of ? o : h);
 }
 
-__device__ __forceinline__ void rd_st_sr(float *p, int64_t i, float v, uint32_t) { p[i] = v; }
+__device__ __forceinline__ void rd_st_sr(float *p, int64_t i, float v, uint32_t)
+{
+    __builtin_nontemporal_store(v, p + i);
+}
 __device__ __forceinline__ void rd_st_sr(bf16_t *p, int64_t i, float v, uint32_t rnd)
 {
     p[i].bits = bf16_sr(v, rnd);

@@ -57,7 +57,8 @@ struct StepArgs {
     int32_t nb;            // blocks in the list
     int32_t S;             // species
     int32_t xcd_chunk;     // blocks per XCD chunk in the XCD-aware mapping (0 = plain)
-    int32_t persist;       // B = 8: 1 = persistent prefetching kernel with `grid` workgroups
+    int32_t kernel;        // B = 8: 0 one workgroup per block, 1 persistent prefetching
+                           // kernel with `grid` workgroups, 2 one wave per block (z-columns)
     int32_t grid;
     // stochastic rounding on store (BF16 / FP16 storage): the random bits of a slot
     // are hash(slot, species, step, seed) with step = *ctr + ctr_off

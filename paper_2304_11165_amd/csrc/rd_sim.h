@@ -62,7 +62,7 @@ struct rd_sim {
     int graph_steps = 32;
     bool use_graph = true;
     bool xcd_map = true;
-    bool persist = false;  // B = 8: persistent prefetching kernel (measured slower)
+    int kernel = 0;       // B = 8 step kernel: 0 workgroup per block, 1 persistent, 2 z-column
     int wg_per_cu = 8;    // resident workgroups per CU of the persistent grid
     int n_cu = 256;       // compute units of the bound device
     bool sround = false;  // stochastic rounding on store (BF16 / FP16 storage)

@@ -38,6 +38,7 @@ STATUS = ["RD_OK", "RD_ERR_ARG", "RD_ERR_SHAPE", "RD_ERR_INCONSISTENT_SDF", "RD_
 STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2}
 RD_WS_SOLVER = 1
 RD_WS_ADJOINT = 2
+KERNELS = ("block", "persistent", "column")  # B = 8 step kernels, by number
 
 _SIGS = {
     "rd_status_string": ([ci], ctypes.c_char_p),
@@ -245,12 +246,16 @@ class Sim:
         vals = [ci() for _ in range(5)]
         _check(_lib.rd_sim_get_launch(self.handle, *[ctypes.byref(v) for v in vals]),
                "rd_sim_get_launch")
-        keys = ("graph_steps", "use_graph", "xcd_map", "persistent", "wg_per_cu")
-        return {k: v.value for k, v in zip(keys, vals)}
+        keys = ("graph_steps", "use_graph", "xcd_map", "kernel", "wg_per_cu")
+        out = {k: v.value for k, v in zip(keys, vals)}
+        out["kernel"] = KERNELS[out["kernel"]]
+        return out
 
-    def set_kernel(self, persistent=True, wg_per_cu=8):
-        _check(_lib.rd_sim_set_kernel(self.handle, int(bool(persistent)), int(wg_per_cu)),
-               "rd_sim_set_kernel")
+    def set_kernel(self, kernel="block", wg_per_cu=8):
+        """B = 8 step kernel: "block" (one workgroup per block), "persistent" or
+        "column" (one wave per block, z-columns); or its number 0, 1, 2."""
+        k = KERNELS.index(kernel) if isinstance(kernel, str) else int(kernel)
+        _check(_lib.rd_sim_set_kernel(self.handle, k, int(wg_per_cu)), "rd_sim_set_kernel")
 
     def set_rounding(self, stochastic, seed=0):
         _check(_lib.rd_sim_set_rounding(self.handle, int(bool(stochastic)), int(seed)),

@@ -12,8 +12,8 @@ def rel_l2(a, b, mask):
 
 
 def make_gpu(rd, img, D, dx=1.0, robin=None, dirichlet=None, reactions=None, storage="fp32",
-             B=8, sdf=None, features=0, checkpoint_slots=0, graph=True, xcd=True, persist=False,
-             wg_per_cu=8):
+             B=8, sdf=None, features=0, checkpoint_slots=0, graph=True, xcd=True,
+             kernel="block", wg_per_cu=8):
     g = rd.Geometry(img, sdf, dx, B)
     s = rd.Sim(g, storage)
     for d in D:
@@ -25,7 +25,7 @@ def make_gpu(rd, img, D, dx=1.0, robin=None, dirichlet=None, reactions=None, sto
     for (sp, f), v in sorted((dirichlet or {}).items(), key=lambda kv: (kv[0][0], kv[0][1])):
         s.set_dirichlet(sp, f, v)
     s.set_launch(32, graph, xcd)
-    s.set_kernel(persist, wg_per_cu)
+    s.set_kernel(kernel, wg_per_cu)
     s.bind(features=features, checkpoint_slots=checkpoint_slots)
     return g, s
 

@@ -27,8 +27,9 @@ def rd():
 
 
 def _run_both(rd, oracle_mod, img, D, dt, n, B=8, dx=1.0, robin=None, dirichlet=None,
-              reactions=None, init=None, storage="fp32", graph=True):
-    g, s = make_gpu(rd, img, D, dx, robin, dirichlet, reactions, storage, B, graph=graph)
+              reactions=None, init=None, storage="fp32", graph=True, kernel="block"):
+    g, s = make_gpu(rd, img, D, dx, robin, dirichlet, reactions, storage, B, graph=graph,
+                    kernel=kernel)
     prob = oracle_mod.Problem(img, D, dx=dx, robin=robin, dirichlet=dirichlet, reactions=reactions)
     c0 = prob.initial()
     if init is not None:
@@ -73,9 +74,10 @@ def test_spheres64_full_config(rd, oracle_mod):
     assert np.all(got8[0][~act] == 0)
     # every kernel variant gives the same bits: B = 4, one workgroup per block,
     # plain or XCD-aware mapping, graph replay or direct launches, grid sizes
-    variants = [dict(B=4, graph=False), dict(persist=True), dict(persist=True, xcd=False),
-                dict(xcd=False, graph=False), dict(persist=True, wg_per_cu=1),
-                dict(persist=True, wg_per_cu=3, xcd=False)]
+    variants = [dict(B=4, graph=False), dict(B=4, xcd=False), dict(kernel="persistent"),
+                dict(kernel="persistent", xcd=False), dict(xcd=False, graph=False),
+                dict(kernel="persistent", wg_per_cu=1), dict(kernel="persistent", wg_per_cu=3, xcd=False),
+                dict(kernel="column"), dict(kernel="column", xcd=False, graph=False)]
     for v in variants:
         _, sv = make_gpu(rd, img, w.species_D, w.dx, dirichlet=w.dirichlet, **v)
         sv.step(w.dt, w.steps)
@@ -120,10 +122,11 @@ def test_random_tiny_geometries(rd, oracle_mod, seed):
     lam = 12 * max(D) / dx ** 2 + sum(r[2] for r in reactions) + 6 * max(robin.values()) / dx
     dt = 1.9 / lam
     init = rng.uniform(0, 1, (S,) + img.shape)
-    for B in (4, 8):
+    for B, kernel in ((4, "block"), (8, "block"), (8, "column")):
         got, ref, _, _ = _run_both(rd, oracle_mod, img, D, dt, 60, B=B, dx=dx, robin=robin,
-                                   dirichlet=dirichlet, reactions=reactions, init=init)
-        assert np.abs(got - ref).max() < 2e-5, (seed, B)
+                                   dirichlet=dirichlet, reactions=reactions, init=init,
+                                   kernel=kernel)
+        assert np.abs(got - ref).max() < 2e-5, (seed, B, kernel)
 
 
 def test_empty_and_single_voxel(rd, oracle_mod):
@@ -223,8 +226,8 @@ def test_stochastic_rounding_variants_agree(rd, storage):
     replay, direct launches and every kernel variant round identically."""
     img, _ = W.boolean_spheres(40, 0.5, 3.0, 6.0, seed=3)
     out = []
-    for v in [dict(), dict(graph=False), dict(persist=True), dict(B=4),
-              dict(persist=True, wg_per_cu=2)]:
+    for v in [dict(), dict(graph=False), dict(kernel="persistent"), dict(B=4),
+              dict(kernel="persistent", wg_per_cu=2), dict(kernel="column")]:
         g, s = make_gpu(rd, img, [1.0, 0.5], dirichlet={(0, 0): 1.0}, reactions=[(0, 1, 0.02)],
                         storage=storage, **v)
         s.set_rounding(1, seed=99)
@@ -248,7 +251,7 @@ def test_species_counts_and_storage_kernels_agree(rd, oracle_mod, storage, S):
     dirichlet = {(0, 0): 1.0, (S - 1, 5): 0.5}
     init = rng.uniform(0, 1, (S,) + img.shape).astype(np.float32)
     out = []
-    for v in [dict(), dict(persist=True), dict(B=4)]:
+    for v in [dict(), dict(kernel="persistent"), dict(B=4), dict(kernel="column")]:
         g, s = make_gpu(rd, img, D, robin=robin, dirichlet=dirichlet, reactions=reactions,
                         storage=storage, **v)
         for sp in range(S):
