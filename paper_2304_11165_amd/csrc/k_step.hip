@@ -3,10 +3,12 @@
 //
 // Step kernel (paper: FTCS with the mirror rule applied inside the stencil,
 // sections "Discretization and numerical methods" and "Parallel implementation"):
-//   * B = 8: one 256-thread workgroup per block, two voxels per thread;
-//     B = 4: one wave per block, four blocks per workgroup, one voxel per thread.
-//   * The block and its six face halos (read through the neighbour list) are staged
-//     as FP32 in an LDS tile of (B+2)^3 words per species; corners are unused.
+//   * B = 8: k_step8z, one wave per block with each lane walking a z-column (the
+//     fastest); k_step8, one 256-thread workgroup per block, two voxels per thread;
+//     k_step8p, a persistent prefetching grid.  B = 4: k_step4w, one wave per block,
+//     four blocks per workgroup, one voxel per thread.
+//   * The block and its face halos (read through the neighbour list) are staged as
+//     FP32 in LDS tiles; inactive and missing neighbours are staged as exact zeros.
 //   * Activity of the six neighbours comes from the block's mask record (own bits
 //     plus the neighbours' face bits), so no neighbour mask is read.
 //   * Inactive slots are 0 in every field buffer (zero-filled on upload).  The
@@ -20,17 +22,25 @@
 
 namespace {
 
-// Store one updated value (round to nearest, or stochastic rounding when enabled).
-template <typename T>
-__device__ __forceinline__ void store_val(const StepArgs &a, T *cout, int s, int64_t idx,
-                                          int64_t slot_id, float r)
+// Stochastic rounding key of this launch (wave-uniform; 0 when rounding to nearest).
+__device__ __forceinline__ uint32_t launch_key(const StepArgs &a)
 {
-    if (a.sround) {
-        const uint32_t step = *a.ctr + a.ctr_off;
-        rd_st_sr(cout, idx, r, sr_bits(slot_id, s, step, a.seed));
-    } else {
-        rd_st(cout, idx, r);
-    }
+    return a.sround ? sr_key(*a.ctr + a.ctr_off, a.seed) : 0u;
+}
+// Random word of one voxel (only used with stochastic rounding).
+__device__ __forceinline__ uint32_t voxel_bits(const StepArgs &a, uint32_t key, int64_t vid)
+{
+    return a.sround ? sr_voxel(vid, key) : 0u;
+}
+
+// Store one updated value of species s (round to nearest, or stochastic rounding
+// with the voxel's random word h when enabled).
+template <typename T>
+__device__ __forceinline__ void store_val(const StepArgs &a, T *cout, int s, int64_t idx, uint32_t h,
+                                          float r)
+{
+    if (a.sround) rd_st_sr(cout, idx, r, sr_species(h, s));
+    else rd_st(cout, idx, r);
 }
 
 // Branch-free update of voxel (lx, ly, lz) of a B = 8 block, all species.  W, Wm, Wp
@@ -119,7 +129,6 @@ __global__ __launch_bounds__(256) void k_step4w(StepArgs a)
     T *cout = (T *)a.cout;
     const int64_t base = (int64_t)b * 64;
     const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
-    const int32_t *nbr = a.info[b].nbr;
 
     // Wave-uniform mask record: own word, faces 0-3 (16 bits each) and faces 4-5.
     // Lane l's bit is l in all three (slot l; face l / 16 at (u, v) with bit
@@ -186,9 +195,9 @@ __global__ __launch_bounds__(256) void k_step4w(StepArgs a)
     vox_code<S>(a, &tile[wv][0][t], TLW, E, E2, code, onf, c, res);
     // whole sectors only; an inactive slot of an active sector stores its 0 again
     if (sector_active<T>(Wo, lane)) {
+        const uint32_t h = voxel_bits(a, launch_key(a), voxel_id(g, gx, gy, gz));
 #pragma unroll
-        for (int s = 0; s < S; ++s)
-            store_val(a, cout, s, s * a.sstride + base + lane, voxel_id(g, gx, gy, gz), res[s]);
+        for (int s = 0; s < S; ++s) store_val(a, cout, s, s * a.sstride + base + lane, h, res[s]);
     }
 }
 
@@ -264,6 +273,7 @@ __global__ __launch_bounds__(256) void k_step8(StepArgs a)
     const GeomInfo g = a.geom[gid];
     const int gx = bx * 8 + lx, gy = by * 8 + ly;
     const bool bnd = boundary_block(g, bx, by, bz);
+    const uint32_t key = launch_key(a);
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         const int lz = w + 4 * k;
@@ -278,9 +288,9 @@ __global__ __launch_bounds__(256) void k_step8(StepArgs a)
                     onf, cen, res);
         // whole sectors only; an inactive slot of an active sector stores its 0 again
         if (sector_active<T>(k == 0 ? Wo0 : Wo1, lane)) {
+            const uint32_t h = voxel_bits(a, key, voxel_id(g, gx, gy, gz));
 #pragma unroll
-            for (int s = 0; s < S; ++s)
-                store_val(a, cout, s, s * a.sstride + base + slot, voxel_id(g, gx, gy, gz), res[s]);
+            for (int s = 0; s < S; ++s) store_val(a, cout, s, s * a.sstride + base + slot, h, res[s]);
         }
     }
 }
@@ -379,6 +389,7 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
     const GeomInfo g = a.geom[gid];
     const int gx = bx * 8 + lx, gy = by * 8 + ly;
     const bool bnd = boundary_block(g, bx, by, bz);
+    const uint32_t key = launch_key(a);
 #pragma unroll
     for (int z = 0; z < 8; ++z) {
         const int gz = bz * 8 + z;
@@ -403,10 +414,9 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
         }
         // whole sectors only; an inactive slot of an active sector stores its 0 again
         if (sector_active<T>(Wo[z], lane)) {
+            const uint32_t h = voxel_bits(a, key, voxel_id(g, gx, gy, gz));
 #pragma unroll
-            for (int s = 0; s < S; ++s)
-                store_val(a, cout, s, s * a.sstride + base + z * 64 + lane, voxel_id(g, gx, gy, gz),
-                          res[s]);
+            for (int s = 0; s < S; ++s) store_val(a, cout, s, s * a.sstride + base + z * 64 + lane, h, res[s]);
         }
     }
 }
@@ -505,7 +515,7 @@ __global__ __launch_bounds__(256) void k_step8p(StepArgs a)
     const T *cin = (const T *)a.cin;
     T *cout = (T *)a.cout;
     const bool sr = a.sround != 0;
-    const uint32_t step = sr ? *a.ctr + a.ctr_off : 0u;
+    const uint32_t key = launch_key(a);
 
     // Block records travel through a double-buffered LDS slot (threads 0-7 hold the
     // next record in a register), which keeps them out of scalar registers.
@@ -569,16 +579,12 @@ __global__ __launch_bounds__(256) void k_step8p(StepArgs a)
             vox8<S>(a, &tile[0][p8::tix(lx, ly, lzp)], p8::TL, p8::TX, p8::TX * p8::TY, W, Wm, Wp,
                     fx0, fx1, fy0, fy1, lx, ly, lzp, box_faces(g, bx * 8 + lx, gy, gz), cen, res[j]);
         }
+        const int64_t v0 = voxel_id(g, bx * 8 + 2 * lx2, gy, gz);
+        const uint32_t h0 = voxel_bits(a, key, v0), h1 = voxel_bits(a, key, v0 + 1);
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const int64_t idx = s * a.sstride + base + slot0;
-            uint32_t r0 = 0, r1 = 0;
-            if (sr) {
-                const int64_t v0 = voxel_id(g, bx * 8 + 2 * lx2, gy, gz);
-                r0 = sr_bits(v0, s, step, a.seed);
-                r1 = sr_bits(v0 + 1, s, step, a.seed);
-            }
-            rd_st2(cout, idx, res[0][s], res[1][s], sr, r0, r1);
+            rd_st2(cout, idx, res[0][s], res[1][s], sr, sr_species(h0, s), sr_species(h1, s));
         }
         if (!more) break;
         __syncthreads();  // every wave is done with the tile before it is refilled

@@ -110,10 +110,22 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x)
     return x;
 }
 
-__device__ __forceinline__ uint32_t sr_bits(int64_t slot, int species, uint32_t step, uint32_t seed)
+// The random bits of a store come in three layers so that a kernel hashes once per
+// voxel: a key per (step, seed), wave-uniform; 32 bits per voxel from the key and the
+// voxel's linear index in its box (independent of the block layout); 16 bits per
+// species out of those (species 2 and 3 mix the voxel word once more).
+__device__ __forceinline__ uint32_t sr_key(uint32_t step, uint32_t seed)
 {
-    uint32_t k = mix32(step * 4u + (uint32_t)species + seed * 0x9e3779b9u);
-    return mix32((uint32_t)slot ^ mix32((uint32_t)(slot >> 32) ^ k));
+    return mix32(step ^ mix32(seed + 0x9e3779b9u));
+}
+__device__ __forceinline__ uint32_t sr_voxel(int64_t vid, uint32_t key)
+{
+    return mix32((uint32_t)vid ^ ((uint32_t)(vid >> 32) * 0x27d4eb2fu) ^ key);
+}
+__device__ __forceinline__ uint32_t sr_species(uint32_t h, int species)
+{
+    const uint32_t w = species < 2 ? h : mix32(h ^ 0x165667b1u);
+    return (species & 1) ? (w >> 16) : (w & 0xffffu);
 }
 
 // Store with stochastic rounding: round up with probability equal to the distance
@@ -144,7 +156,7 @@ __device__ __forceinline__ _Float16 f16_sr(float v, uint32_t rnd)
     const float of = (float)o;
     const float lo = fminf(hf, of), hi = fmaxf(hf, of);
     const float prob_up = (v - lo) / (hi - lo);
-    const float u01 = (float)(rnd >> 8) * (1.0f / 16777216.0f);
+    const float u01 = (float)(rnd & 0xffffu) * (1.0f / 65536.0f);  // 16 random bits
     return u01 < prob_up ? (hf > of ? h : o) : (hf > of ? o : h);
 }
 
@@ -274,18 +286,21 @@ __device__ __forceinline__ bool on_dirichlet(uint32_t dir, int gx, int gy, int g
 }
 
 // The FTCS update of one free voxel of one species (see rd.h):
-//   lap = sum over active neighbours, in order -x,+x,-y,+y,-z,+z, of (c_q - c_p)
+//   lap = sum over active neighbours q of (c_q - c_p)
 //   c'  = c + alpha*lap - (beta + gamma*n_wall)*c + sum_b K_b c_b
+// Every caller stages inactive and missing neighbours as exactly 0 (inactive slots
+// hold 0 in every field buffer), so the sum over the active neighbours is the sum
+// of all six values, and the mirror rule enters through the active count:
+//   lap = (((((n_-x + n_+x) + n_-y) + n_+y) + n_-z) + n_+z) - popc(nbm) * c_p
+// (one rounding order for every kernel; 6 operations instead of 18).
 template <int S>
 __device__ __forceinline__ float rd_update(float uc, const float nbv[6], unsigned nbm, int nwall,
                                            const SpeciesCoef &k, const float *cen)
 {
-    float lap = 0.0f;
+    float sum = nbv[0];
 #pragma unroll
-    for (int d = 0; d < 6; ++d) {
-        const float t = nbv[d] - uc;
-        lap = ((nbm >> d) & 1u) ? lap + t : lap;
-    }
+    for (int d = 1; d < 6; ++d) sum = sum + nbv[d];
+    const float lap = fmaf(-(float)__popc(nbm & 63u), uc, sum);
     float r = fmaf(k.alpha, lap, uc);
     const float loss = fmaf(k.gamma, (float)nwall, k.beta);
     r = fmaf(-loss, uc, r);
