@@ -298,20 +298,20 @@ __global__ __launch_bounds__(256) void k_step8(StepArgs a)
 // B = 8 step, one wave per block and four blocks per workgroup.  Lane l = (lx, ly)
 // walks its z-column lz = 0..7: the -z / +z neighbours of a voxel are the values
 // above and below it in the lane's own registers (the -z / +z face halos at the
-// column ends), and only the +-x / +-y neighbours go through a wave-private LDS
-// tile (8 planes of 10 x 10 words per species: the block plus its four side halos).
-// Every per-block cost (mask words, neighbour list, addresses, predicates) is paid
+// column ends), and only the +-x / +-y neighbours go through LDS, one plane at a
+// time: a wave-private 10 x 10 tile per species holds plane lz and its ring of side
+// halos (800 bytes per wave for two species, so LDS does not limit residency).
+// Every global load of the block is issued before the first plane is computed, and
+// every per-block cost (mask words, neighbour list, addresses, predicates) is paid
 // once per 8 voxels of a lane.  Only wave-level ordering is needed.
 namespace z8 {
-constexpr int TP = 100;      // words per plane (10 x 10)
-constexpr int TS = 8 * TP;   // words per species
-__device__ __forceinline__ int tix(int x, int y, int lz) { return (lz * 10 + (y + 1)) * 10 + (x + 1); }
+__device__ __forceinline__ int pix(int x, int y) { return (y + 1) * 10 + (x + 1); }
 }  // namespace z8
 
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
 {
-    __shared__ float tile[4][S][z8::TS];
+    __shared__ float tile[4][S][100];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int grp = map_group(blockIdx.x, a.xcd_chunk);
     const int b = __builtin_amdgcn_readfirstlane(grp * 4 + wv);
@@ -360,28 +360,17 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
 #pragma unroll
         for (int s = 0; s < S; ++s) rh[f][s] = ld_raw(cin, s * a.sstride + hb, e);
     }
-    // all loads are issued; convert to FP32.  LDS: the block's planes and the four side
-    // halos (face f < 4 at (u, v) = (lx, ly)); the z halos stay in registers
-    float c[S][8], zlo[S], zhi[S];
+    // all loads are issued; convert to FP32
+    float c[S][8], side[4][S], zlo[S], zhi[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        float *ts = &tile[wv][s][0];
 #pragma unroll
-        for (int z = 0; z < 8; ++z) {
-            c[s][z] = from_raw<T>(rc[s][z]);
-            ts[z8::tix(lx, ly, z)] = c[s][z];
-        }
-        ts[z8::tix(-1, lx, ly)] = from_raw<T>(rh[0][s]);
-        ts[z8::tix(8, lx, ly)] = from_raw<T>(rh[1][s]);
-        ts[z8::tix(lx, -1, ly)] = from_raw<T>(rh[2][s]);
-        ts[z8::tix(lx, 8, ly)] = from_raw<T>(rh[3][s]);
+        for (int z = 0; z < 8; ++z) c[s][z] = from_raw<T>(rc[s][z]);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) side[f][s] = from_raw<T>(rh[f][s]);
         zlo[s] = from_raw<T>(rh[4][s]);
         zhi[s] = from_raw<T>(rh[5][s]);
     }
-    // the wave's LDS writes complete before its reads of other lanes' words
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
     const BlockInfo bi = a.info[b];
     int bx, by, bz, gid;
@@ -392,6 +381,24 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
     const uint32_t key = launch_key(a);
 #pragma unroll
     for (int z = 0; z < 8; ++z) {
+        // plane z and its ring into LDS: the side halos of plane z sit at face
+        // coordinate v = z, i.e. in the lanes with ly == z (face coordinate u = lx)
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            float *ts = tile[wv][s];
+            ts[z8::pix(lx, ly)] = c[s][z];
+            if (ly == z) {
+                ts[z8::pix(-1, lx)] = side[0][s];
+                ts[z8::pix(8, lx)] = side[1][s];
+                ts[z8::pix(lx, -1)] = side[2][s];
+                ts[z8::pix(lx, 8)] = side[3][s];
+            }
+        }
+        // the wave's LDS writes complete before its reads of other lanes' words
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
         const int gz = bz * 8 + z;
         const unsigned code = cd[z];
         const unsigned m = code & 63u;
@@ -404,7 +411,7 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
         for (int s = 0; s < S; ++s) cen[s] = c[s][z];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            const float *p = &tile[wv][s][z8::tix(lx, ly, z)];
+            const float *p = &tile[wv][s][z8::pix(lx, ly)];
             const float dn = z == 0 ? zlo[s] : c[s][z > 0 ? z - 1 : 0];
             const float up = z == 7 ? zhi[s] : c[s][z < 7 ? z + 1 : 7];
             const float nbv[6] = {p[-1], p[1], p[-10], p[10], dn, up};
@@ -412,6 +419,10 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
             const bool isd = (onf & a.coef[s].dir) != 0u;
             res[s] = act ? (isd ? cen[s] : upd) : 0.0f;
         }
+        // every lane has read plane z before any lane overwrites it with plane z + 1
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         // whole sectors only; an inactive slot of an active sector stores its 0 again
         if (sector_active<T>(Wo[z], lane)) {
             const uint32_t h = voxel_bits(a, key, voxel_id(g, gx, gy, gz));
