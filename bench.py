@@ -29,6 +29,10 @@ import sys
 import time
 
 HBM_PEAK_GBS = 8000.0
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "step_traffic.json")
+STEP_SOURCES = ["paper_2304_11165_amd/csrc/k_step.hip", "paper_2304_11165_amd/csrc/rd_device.h",
+                "paper_2304_11165_amd/csrc/rd_internal.h"]
 METRIC = "active-voxel updates/s + achieved HBM GB/s (plain FP32 vs batched/BF16 form)"
 
 
@@ -48,8 +52,40 @@ def parse():
     p.add_argument("--no-graph", action="store_true", help="direct launches (for profilers)")
     p.add_argument("--profile", action="store_true", help="only the timed FP32 loop")
     p.add_argument("--copy-calibration", action="store_true")
-    p.add_argument("--traffic", default="", help="JSON file with measured HBM bytes per launch")
+    p.add_argument("--kernel", default="auto", choices=["auto", "block", "column", "column_xch",
+                                                        "persistent"],
+                   help="B = 8 step kernel (auto: autotuned)")
+    p.add_argument("--xcd", default="auto", choices=["auto", "0", "1"],
+                   help="XCD-aware block order (auto: autotuned)")
+    p.add_argument("--traffic", default=TRAFFIC_FILE,
+                   help="JSON record of measured HBM bytes per step launch (rocprofv3 FETCH_SIZE + "
+                        "WRITE_SIZE, copy-calibrated); used only if the kernel sources still match")
     return p.parse_args()
+
+
+def source_hash():
+    """Hash of the sources the step kernel is built from (a traffic record is valid only
+    for the code it was measured on)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in STEP_SOURCES:
+        with open(os.path.join(HERE, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(path, kernel, workload):
+    """HBM bytes per launch from a traffic record, or None if there is none or it was
+    measured on other code, another kernel or another workload."""
+    if not path or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_hash") != source_hash() or rec.get("kernel") != kernel or \
+            rec.get("workload") != workload:
+        log(f"traffic record {path} does not match this build/kernel/workload: traffic = null")
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def log(msg):
@@ -109,7 +145,9 @@ def step_kernel_name(B, launch, S):
     if B == 4:
         return f"k_step4w<float,{S}>"
     kern = (launch or {}).get("kernel", "block")
-    return {"block": "k_step8", "column": "k_step8z", "persistent": "k_step8p"}[kern] + f"<float,{S}>"
+    name = {"block": "k_step8<float,{S}>", "column": "k_step8z<float,{S},false>",
+            "column_xch": "k_step8z<float,{S},true>", "persistent": "k_step8p<float,{S}>"}[kern]
+    return name.format(S=S)
 
 
 def batched_form(torch, rd, W, count, max_edge, stream):
@@ -180,10 +218,13 @@ def main():
         with torch.cuda.stream(stream):
             sim = build_sim(rd, geom, w, storage, a.graph_steps, not a.no_graph)
             sim.bind(stream=stream)
-            launch = None
-            if not a.profile:
+            if a.kernel != "auto":
+                sim.set_kernel(a.kernel)
+            if a.xcd != "auto":
+                sim.set_launch(a.graph_steps, not a.no_graph, a.xcd == "1")
+            if a.kernel == "auto" or a.xcd == "auto":
                 sim.autotune(w.dt, 200)  # resets the fields afterwards
-                launch = sim.get_launch()
+            launch = sim.get_launch()
             secs, wall = time_steps(torch, sim, stream, w.dt, warm, steps)
             bal = [sim.balance(sp) for sp in range(S)]
             if storage != "fp32" or forms:
@@ -231,9 +272,9 @@ def main():
         del ref
 
     f32 = results["fp32"]
-    traffic = None
-    if a.traffic and os.path.exists(a.traffic):
-        traffic = json.load(open(a.traffic)).get("hbm_bytes_per_launch")
+    kname = step_kernel_name(w.block_edge, f32["launch"], S)
+    workload_name = f"soil{n}"
+    traffic = load_traffic(a.traffic, kname, workload_name)
     out = {
         "metric": METRIC,
         "value": f32["updates_per_s"],
@@ -259,7 +300,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": step_kernel_name(w.block_edge, f32["launch"], S),
+            "kernel": kname,
             "achieved": f32["alg_GBps"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -133,8 +133,10 @@ rd_status rd_sim_set_launch(rd_sim *sim, int graph_steps, int use_graph, int xcd
  *   kernel = 1: persistent, a fixed grid of wg_per_cu * (compute units) workgroups
  *               that walk the block list and prefetch the next block while
  *               computing the current one;
- *   kernel = 2: one wave per block, each lane walking a z-column of 8 voxels.
- * Results are bitwise identical.  RD_ERR_ARG for kernel outside 0..2 or wg_per_cu
+ *   kernel = 2: one wave per block, each lane walking a z-column of 8 voxels;
+ *   kernel = 3: as 2, with the x faces of x-adjacent blocks of a workgroup handed
+ *               over through LDS instead of being re-read from memory.
+ * Results are bitwise identical.  RD_ERR_ARG for kernel outside 0..3 or wg_per_cu
  * outside 1..32. */
 rd_status rd_sim_set_kernel(rd_sim *sim, int kernel, int wg_per_cu);
 

@@ -303,24 +303,38 @@ __global__ __launch_bounds__(256) void k_step8(StepArgs a)
 // halos (800 bytes per wave for two species, so LDS does not limit residency).
 // Every global load of the block is issued before the first plane is computed, and
 // every per-block cost (mask words, neighbour list, addresses, predicates) is paid
-// once per 8 voxels of a lane.  Only wave-level ordering is needed.
+// once per 8 voxels of a lane.
+// The four blocks of a workgroup are consecutive list entries, and an existing +x
+// neighbour of entry b is always entry b + 1 (ascending linear ids, x fastest).  So
+// With XCH, x-adjacent blocks of one workgroup hand each other their x = 0 / x = 7
+// planes through LDS (one workgroup barrier) instead of re-reading the neighbour's
+// strided column from L2: an x face touches every 128-byte line of the neighbour
+// block.  It pays with FP32 storage; the barrier costs more than it saves for the
+// latency-bound 16-bit forms, so both are autotuner candidates.
 namespace z8 {
 __device__ __forceinline__ int pix(int x, int y) { return (y + 1) * 10 + (x + 1); }
 }  // namespace z8
 
-template <typename T, int S>
+template <typename T, int S, bool XCH>
 __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
 {
     __shared__ float tile[4][S][100];
+    __shared__ float xch[4][2][S][64];  // x = 0 / x = 7 planes of each wave's block, [z * 8 + y]
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int grp = map_group(blockIdx.x, a.xcd_chunk);
     const int b = __builtin_amdgcn_readfirstlane(grp * 4 + wv);
-    if (b >= a.nb) return;  // the whole wave leaves; no workgroup barrier below
+    if (b >= a.nb) {  // past the end of the list (with XCH: after the one barrier)
+        if (XCH) __syncthreads();
+        return;
+    }
     const T *cin = (const T *)a.cin;
     T *cout = (T *)a.cout;
     const int64_t base = (int64_t)b * 512;
     const int lx = lane & 7, ly = lane >> 3;
     const int32_t *nbr = a.info[b].nbr;
+    // x neighbours inside this workgroup (wave-uniform; only with XCH)
+    const bool xm_in = XCH && wv > 0 && nbr[0] == b - 1;
+    const bool xp_in = XCH && wv < 3 && nbr[1] == b + 1;
     // mask record: own plane words 0-7, face words 8-13; lane l's bit is l in each
     // (own slot (lx, ly) of a plane; face coordinates (u, v) = (lx, ly), bit v*8+u)
     const uint64_t *rec = a.mask + (int64_t)b * 16;
@@ -355,7 +369,7 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
         default: ns = (0 * 8 + ly) * 8 + lx; break; // (x=u, y=v, z=0)
         }
         const int n = nbr[f];
-        const bool e = (Wf[f] >> lane) & 1ull;
+        const bool e = ((Wf[f] >> lane) & 1ull) && !(f == 0 && xm_in) && !(f == 1 && xp_in);
         const int64_t hb = (int64_t)(n >= 0 ? n : b) * 512 + ns;
 #pragma unroll
         for (int s = 0; s < S; ++s) rh[f][s] = ld_raw(cin, s * a.sstride + hb, e);
@@ -370,6 +384,23 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
         for (int f = 0; f < 4; ++f) side[f][s] = from_raw<T>(rh[f][s]);
         zlo[s] = from_raw<T>(rh[4][s]);
         zhi[s] = from_raw<T>(rh[5][s]);
+    }
+    // hand the x = 0 / x = 7 planes to the x neighbours of this workgroup; inactive
+    // slots are 0 already, as a predicated halo load would give
+    if (XCH) {
+        if (lx == 0 || lx == 7) {
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+#pragma unroll
+                for (int z = 0; z < 8; ++z) xch[wv][lx == 7 ? 1 : 0][s][z * 8 + ly] = c[s][z];
+        }
+        __syncthreads();
+        // face coordinates (u, v) = (lx, ly) of an x face are (y, z)
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (xm_in) side[0][s] = xch[wv - 1][1][s][ly * 8 + lx];
+            if (xp_in) side[1][s] = xch[wv + 1][0][s][ly * 8 + lx];
+        }
     }
 
     const BlockInfo bi = a.info[b];
@@ -615,7 +646,6 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a)
     using K = Blk<B>;
     using C = Cfg<B>;
     __shared__ float tile[C::BPW][1][K::TL];
-    __shared__ uint64_t srec[C::BPW][K::MW];
     __shared__ double wsum[4][RD_NRED];
 
     const int sub = threadIdx.x / C::TPB;
@@ -625,31 +655,33 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a)
     const T *c = (const T *)a.c;
 
     BlockInfo bi = {};
-    if (valid) {
-        bi = a.info[b];
-        if (lt < K::MW) srec[sub][lt] = a.mask[(int64_t)b * K::MW + lt];
-    }
+    if (valid) bi = a.info[b];
     const T *cs = c + a.s * a.sstride;
     stage_tile<T, B>(tile[sub], cs, 0, 1, b, bi, lt, valid);
     __syncthreads();
-    const uint64_t *rec = srec[sub];
 
     double acc[RD_NRED];
 #pragma unroll
     for (int l = 0; l < RD_NRED; ++l) acc[l] = 0.0;
+    bool dblock = false;  // the block touches a Dirichlet face of the species
     if (valid) {
         int bx, by, bz, gid;
         block_pos(bi, &bx, &by, &bz, &gid);
         const GeomInfo g = a.geom[gid];
+        const bool at[6] = {bx == 0, bx * B + B >= g.nx, by == 0, by * B + B >= g.ny, bz == 0,
+                            bz * B + B >= g.nz};
+#pragma unroll
+        for (int f = 0; f < 6; ++f) dblock = dblock || (((a.dir >> f) & 1u) && at[f]);
         const double dx = a.dx, dx2 = dx * dx, dx3 = dx2 * dx;
 #pragma unroll
         for (int k = 0; k < C::VPT; ++k) {
             const int slot = lt + k * C::TPB;
             const int lx = slot % B, ly = (slot / B) % B, lz = slot / (B * B);
             const int gx = bx * B + lx, gy = by * B + ly, gz = bz * B + lz;
-            if (!own_bit<B>(rec, slot)) continue;
-            int nwall = 0;
-            const unsigned nbm = nb_bits<B>(rec, lx, ly, lz, gx, gy, gz, g.nx, g.ny, g.nz, &nwall);
+            const unsigned code = a.code[(int64_t)b * K::NS + slot];
+            if (!(code & 64u)) continue;
+            const unsigned nbm = code & 63u;
+            const int nwall = __popc(~box_faces(g, gx, gy, gz) & ~nbm & 0x3fu);
             const int t = K::tidx(lx, ly, lz);
             const float *ts = tile[sub][0];
             const double u = (double)ts[t];
@@ -686,10 +718,16 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a)
             acc[8] += re * dx3;
         }
     }
+    // wave sums of the lanes that can be nonzero (every flag is uniform per wave: a
+    // B = 8 block spans the workgroup, a B = 4 block is one wave); the others are 0
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    bool hasreact = a.rate_out != 0.0;
+    for (int s2 = 0; s2 < a.S; ++s2) hasreact = hasreact || a.rate_in[s2] != 0.0;
 #pragma unroll
     for (int l = 0; l < RD_NRED; ++l) {
-        const double v = wave_sum(acc[l]);
+        const bool need = l == 0 || l == 9 || (l <= 6 && dblock) || (l == 7 && a.kR != 0.0) ||
+                          (l == 8 && hasreact);
+        const double v = need ? wave_sum(acc[l]) : 0.0;
         if (lane == 0) wsum[wave][l] = v;
     }
     __syncthreads();
@@ -700,23 +738,37 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a)
     }
 }
 
-// Second pass: out[l] = sum over parts of partial[part][l], in a fixed order.
-__global__ __launch_bounds__(256) void k_finish(const double *part, int nparts, int nlanes,
-                                                double *out)
+// Row sums of a [nrows][nlanes] FP64 array (nlanes <= RD_FINISH_LANES): workgroup g
+// sums rows [g * chunk, min((g + 1) * chunk, nrows)) into out[g][*].  Thread t adds
+// rows t, t + 256, ... of the range (whole rows, so loads are coalesced), then a
+// fixed tree over the threads; the order depends only on nrows and chunk.
+#define RD_FINISH_LANES 16
+__global__ __launch_bounds__(256) void k_finish_rows(const double *part, int nrows, int nlanes,
+                                                     int chunk, double *out)
 {
-    __shared__ double sh[256];
-    for (int l = 0; l < nlanes; ++l) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < nparts; i += 256) s += part[(int64_t)i * nlanes + l];
-        sh[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-            __syncthreads();
+    __shared__ double sh[RD_FINISH_LANES][257];
+    const int g = blockIdx.x, t = threadIdx.x;
+    const int64_t r0 = (int64_t)g * chunk;
+    const int64_t r1 = r0 + chunk < nrows ? r0 + chunk : nrows;
+    double acc[RD_FINISH_LANES];
+#pragma unroll
+    for (int l = 0; l < RD_FINISH_LANES; ++l) acc[l] = 0.0;
+    for (int64_t r = r0 + t; r < r1; r += 256) {
+#pragma unroll
+        for (int l = 0; l < RD_FINISH_LANES; ++l)
+            if (l < nlanes) acc[l] += part[r * nlanes + l];
+    }
+#pragma unroll
+    for (int l = 0; l < RD_FINISH_LANES; ++l) sh[l][t] = acc[l];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+#pragma unroll
+            for (int l = 0; l < RD_FINISH_LANES; ++l) sh[l][t] += sh[l][t + w];
         }
-        if (threadIdx.x == 0) out[l] = sh[0];
         __syncthreads();
     }
+    if (t < nlanes) out[(int64_t)g * nlanes + t] = sh[t][0];
 }
 
 // Dense float32 -> block-major storage of one species.  Inactive slots get 0 and
@@ -824,7 +876,9 @@ void launch_step_s(const StepArgs &a, int groups, hipStream_t st)
         if (a.kernel == 1)
             hipLaunchKernelGGL((k_step8p<T, S>), dim3(a.grid), dim3(256), 0, st, a);
         else if (a.kernel == 2)
-            hipLaunchKernelGGL((k_step8z<T, S>), dim3(groups), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_step8z<T, S, false>), dim3(groups), dim3(256), 0, st, a);
+        else if (a.kernel == 3)
+            hipLaunchKernelGGL((k_step8z<T, S, true>), dim3(groups), dim3(256), 0, st, a);
         else
             hipLaunchKernelGGL((k_step8<T, S>), dim3(groups), dim3(256), 0, st, a);
     } else {
@@ -836,7 +890,7 @@ template <typename T, int B>
 int launch_step_t(const StepArgs &a, hipStream_t st)
 {
     // blocks per workgroup: 1 for the B = 8 workgroup kernel, 4 for the wave kernels
-    const int bpw = (B == 8 && a.kernel != 2) ? 1 : 4;
+    const int bpw = (B == 8 && a.kernel < 2) ? 1 : 4;
     int groups = (a.nb + bpw - 1) / bpw;
     if (a.xcd_chunk > 0) groups = 8 * a.xcd_chunk;
     switch (a.S) {
@@ -882,11 +936,23 @@ int rd_launch_reduce(int storage, int B, const ReduceArgs &a, int, void *stream)
     RD_DISPATCH(storage, B, launch_reduce_t, a, (hipStream_t)stream);
 }
 
-int rd_launch_finish_reduce(const double *partial, int nparts, int nlanes, double *out,
+int rd_launch_finish_reduce(const double *partial, int nparts, int nlanes, double *mid, double *out,
                             void *stream)
 {
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, (hipStream_t)stream, partial, nparts,
-                       nlanes, out);
+    if (nlanes < 1 || nlanes > RD_FINISH_LANES) return (int)hipErrorInvalidValue;
+    hipStream_t st = (hipStream_t)stream;
+    if (nparts <= 4096) {  // one workgroup in one pass
+        hipLaunchKernelGGL(k_finish_rows, dim3(1), dim3(256), 0, st, partial, nparts, nlanes,
+                           nparts > 0 ? nparts : 1, out);
+        return (int)hipGetLastError();
+    }
+    // RD_FINISH_GROUPS fixed ranges, then their sums in one workgroup
+    const int chunk = (nparts + RD_FINISH_GROUPS - 1) / RD_FINISH_GROUPS;
+    const int groups = (nparts + chunk - 1) / chunk;
+    hipLaunchKernelGGL(k_finish_rows, dim3(groups), dim3(256), 0, st, partial, nparts, nlanes, chunk,
+                       mid);
+    hipLaunchKernelGGL(k_finish_rows, dim3(1), dim3(256), 0, st, (const double *)mid, groups, nlanes,
+                       groups, out);
     return (int)hipGetLastError();
 }
 

@@ -214,7 +214,7 @@ extern "C" rd_status rd_sim_set_launch(rd_sim *sim, int graph_steps, int use_gra
 extern "C" rd_status rd_sim_set_kernel(rd_sim *sim, int kernel, int wg_per_cu)
 {
     if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
-    if (kernel < 0 || kernel > 2) return rd_fail(RD_ERR_ARG, "kernel in 0..2");
+    if (kernel < 0 || kernel > 3) return rd_fail(RD_ERR_ARG, "kernel in 0..3");
     if (wg_per_cu < 1 || wg_per_cu > 32) return rd_fail(RD_ERR_ARG, "wg_per_cu in 1..32");
     sim->kernel = kernel;
     sim->wg_per_cu = wg_per_cu;
@@ -288,6 +288,7 @@ SimLayout sim_layout(const rd_sim &s, uint32_t features, int64_t cp_slots)
     }
     L.nparts = (int)std::max<int64_t>(1, nb);  // one partial row per workgroup (upper bound)
     L.part = off; off = align256(off + sizeof(double) * RD_NRED * (size_t)L.nparts);
+    L.mid = off; off = align256(off + sizeof(double) * 16 * RD_FINISH_GROUPS);
     L.res = off; off = align256(off + sizeof(double) * 64);
     if (features & RD_WS_SOLVER) {
         for (int v = 0; v < 3; ++v) {
@@ -469,7 +470,7 @@ int rd_sim::xcd_chunk(int nb) const
 {
     if (!xcd_map) return 0;
     // blocks per workgroup: 1 for the B = 8 workgroup kernels, 4 for the wave kernels
-    const int bpw = (g->B == 8 && kernel != 2) ? 1 : 4;
+    const int bpw = (g->B == 8 && kernel < 2) ? 1 : 4;
     const int groups = (nb + bpw - 1) / bpw;
     if (groups < 64) return 0;
     return (groups + 7) / 8;
@@ -538,6 +539,7 @@ rd_status rd_sim::balance(int s, double out[RD_NRED])
     ReduceArgs a{};
     a.info = (const BlockInfo *)(ws + L.info);
     a.mask = (const uint64_t *)(ws + L.mask);
+    a.code = (const uint8_t *)(ws + L.code);
     a.geom = (const GeomInfo *)(ws + L.geom);
     a.c = field_ptr(cur, 0);
     a.sstride = L.field_elems;
@@ -557,7 +559,7 @@ rd_status rd_sim::balance(int s, double out[RD_NRED])
     const int nparts = (a.nb + bpw - 1) / bpw;  // 0 for an empty geometry: sums are 0
     double *res = (double *)(ws + L.res);
     LAUNCHCHK(rd_launch_reduce(storage, g->B, a, nparts, stream));
-    LAUNCHCHK(rd_launch_finish_reduce(a.partial, nparts, RD_NRED, res, stream));
+    LAUNCHCHK(rd_launch_finish_reduce(a.partial, nparts, RD_NRED, (double *)(ws + L.mid), res, stream));
     HIPCHK(hipMemcpyAsync(host_res, res, sizeof(double) * RD_NRED, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
     for (int l = 0; l < RD_NRED; ++l) out[l] = host_res[l];
@@ -688,7 +690,8 @@ extern "C" rd_status rd_sim_autotune(rd_sim *sim, double dt, int64_t trial_steps
     for (int gi = 0; gi < 2; ++gi) {
         for (int xcd = 0; xcd < 2; ++xcd) cands.push_back({0, xcd != 0, true, 8, gs[gi]});
         if (sim->g->B == 8) {
-            for (int xcd = 0; xcd < 2; ++xcd) cands.push_back({2, xcd != 0, true, 8, gs[gi]});
+            for (int k = 2; k <= 3; ++k)
+                for (int xcd = 0; xcd < 2; ++xcd) cands.push_back({k, xcd != 0, true, 8, gs[gi]});
             for (int wg : {2, 4, 8}) cands.push_back({1, true, true, wg, gs[gi]});
         }
     }

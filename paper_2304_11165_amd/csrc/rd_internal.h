@@ -58,7 +58,8 @@ struct StepArgs {
     int32_t S;             // species
     int32_t xcd_chunk;     // blocks per XCD chunk in the XCD-aware mapping (0 = plain)
     int32_t kernel;        // B = 8: 0 one workgroup per block, 1 persistent prefetching
-                           // kernel with `grid` workgroups, 2 one wave per block (z-columns)
+                           // kernel with `grid` workgroups, 2 one wave per block (z-columns),
+                           // 3 as 2 with x faces exchanged inside the workgroup
     int32_t grid;
     // stochastic rounding on store (BF16 / FP16 storage): the random bits of a slot
     // are hash(slot, species, step, seed) with step = *ctr + ctr_off
@@ -72,6 +73,7 @@ struct StepArgs {
 struct ReduceArgs {
     const BlockInfo *info;
     const uint64_t *mask;
+    const uint8_t *code;  // per-slot neighbour codes (as in StepArgs)
     const GeomInfo *geom;
     const void *c;      // T*
     int64_t sstride;
@@ -91,7 +93,11 @@ struct ReduceArgs {
 // storage: 0 fp32, 1 bf16, 2 fp16.  All return a hipError_t as int.
 int rd_launch_step(int storage, int B, const StepArgs &a, void *stream);
 int rd_launch_reduce(int storage, int B, const ReduceArgs &a, int nwg, void *stream);
-int rd_launch_finish_reduce(const double *partial, int nparts, int nlanes, double *out, void *stream);
+// Fixed-order sums of partial[nparts][nlanes] (nlanes <= 16) into out[nlanes]; mid is
+// scratch of RD_FINISH_GROUPS * nlanes doubles.
+#define RD_FINISH_GROUPS 256
+int rd_launch_finish_reduce(const double *partial, int nparts, int nlanes, double *mid, double *out,
+                            void *stream);
 int rd_launch_scatter(int storage, int B, const BlockInfo *info, const uint64_t *mask,
                       const GeomInfo *geom, int nb, const float *dense, void *field,
                       uint32_t dir, float dir_value_per_face[6], void *stream);

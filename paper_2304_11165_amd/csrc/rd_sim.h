@@ -34,7 +34,7 @@ struct SimLayout {
     size_t field[2];
     int64_t field_elems;  // nb * B^3
     int nparts;
-    size_t part, res;
+    size_t part, mid, res;  // reduction partials, finish scratch, results
     size_t solver[3], scal;
     size_t lam[2], target, cp, cp_stride;
     size_t total;
@@ -62,7 +62,8 @@ struct rd_sim {
     int graph_steps = 32;
     bool use_graph = true;
     bool xcd_map = true;
-    int kernel = 0;       // B = 8 step kernel: 0 workgroup per block, 1 persistent, 2 z-column
+    int kernel = 0;       // B = 8 step kernel: 0 workgroup per block, 1 persistent, 2 z-column,
+                          // 3 z-column with in-workgroup x-face exchange
     int wg_per_cu = 8;    // resident workgroups per CU of the persistent grid
     int n_cu = 256;       // compute units of the bound device
     bool sround = false;  // stochastic rounding on store (BF16 / FP16 storage)

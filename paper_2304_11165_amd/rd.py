@@ -38,7 +38,7 @@ STATUS = ["RD_OK", "RD_ERR_ARG", "RD_ERR_SHAPE", "RD_ERR_INCONSISTENT_SDF", "RD_
 STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2}
 RD_WS_SOLVER = 1
 RD_WS_ADJOINT = 2
-KERNELS = ("block", "persistent", "column")  # B = 8 step kernels, by number
+KERNELS = ("block", "persistent", "column", "column_xch")  # B = 8 step kernels, by number
 
 _SIGS = {
     "rd_status_string": ([ci], ctypes.c_char_p),
@@ -252,8 +252,9 @@ class Sim:
         return out
 
     def set_kernel(self, kernel="block", wg_per_cu=8):
-        """B = 8 step kernel: "block" (one workgroup per block), "persistent" or
-        "column" (one wave per block, z-columns); or its number 0, 1, 2."""
+        """B = 8 step kernel: "block" (one workgroup per block), "persistent",
+        "column" (one wave per block, z-columns) or "column_xch" (column with x faces
+        exchanged inside the workgroup); or its number 0..3."""
         k = KERNELS.index(kernel) if isinstance(kernel, str) else int(kernel)
         _check(_lib.rd_sim_set_kernel(self.handle, k, int(wg_per_cu)), "rd_sim_set_kernel")
 

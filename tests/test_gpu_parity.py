@@ -77,7 +77,8 @@ def test_spheres64_full_config(rd, oracle_mod):
     variants = [dict(B=4, graph=False), dict(B=4, xcd=False), dict(kernel="persistent"),
                 dict(kernel="persistent", xcd=False), dict(xcd=False, graph=False),
                 dict(kernel="persistent", wg_per_cu=1), dict(kernel="persistent", wg_per_cu=3, xcd=False),
-                dict(kernel="column"), dict(kernel="column", xcd=False, graph=False)]
+                dict(kernel="column"), dict(kernel="column", xcd=False, graph=False),
+                dict(kernel="column_xch"), dict(kernel="column_xch", xcd=False, graph=False)]
     for v in variants:
         _, sv = make_gpu(rd, img, w.species_D, w.dx, dirichlet=w.dirichlet, **v)
         sv.step(w.dt, w.steps)
@@ -122,7 +123,7 @@ def test_random_tiny_geometries(rd, oracle_mod, seed):
     lam = 12 * max(D) / dx ** 2 + sum(r[2] for r in reactions) + 6 * max(robin.values()) / dx
     dt = 1.9 / lam
     init = rng.uniform(0, 1, (S,) + img.shape)
-    for B, kernel in ((4, "block"), (8, "block"), (8, "column")):
+    for B, kernel in ((4, "block"), (8, "block"), (8, "column"), (8, "column_xch")):
         got, ref, _, _ = _run_both(rd, oracle_mod, img, D, dt, 60, B=B, dx=dx, robin=robin,
                                    dirichlet=dirichlet, reactions=reactions, init=init,
                                    kernel=kernel)
@@ -227,7 +228,8 @@ def test_stochastic_rounding_variants_agree(rd, storage):
     img, _ = W.boolean_spheres(40, 0.5, 3.0, 6.0, seed=3)
     out = []
     for v in [dict(), dict(graph=False), dict(kernel="persistent"), dict(B=4),
-              dict(kernel="persistent", wg_per_cu=2), dict(kernel="column")]:
+              dict(kernel="persistent", wg_per_cu=2), dict(kernel="column"),
+              dict(kernel="column_xch")]:
         g, s = make_gpu(rd, img, [1.0, 0.5], dirichlet={(0, 0): 1.0}, reactions=[(0, 1, 0.02)],
                         storage=storage, **v)
         s.set_rounding(1, seed=99)
@@ -251,7 +253,8 @@ def test_species_counts_and_storage_kernels_agree(rd, oracle_mod, storage, S):
     dirichlet = {(0, 0): 1.0, (S - 1, 5): 0.5}
     init = rng.uniform(0, 1, (S,) + img.shape).astype(np.float32)
     out = []
-    for v in [dict(), dict(kernel="persistent"), dict(B=4), dict(kernel="column")]:
+    for v in [dict(), dict(kernel="persistent"), dict(B=4), dict(kernel="column"),
+              dict(kernel="column_xch")]:
         g, s = make_gpu(rd, img, D, robin=robin, dirichlet=dirichlet, reactions=reactions,
                         storage=storage, **v)
         for sp in range(S):
