@@ -136,8 +136,8 @@ __global__ __launch_bounds__(256) void k_cg_residual(CgArgs a, int store)
                 bb += bp * bp;
             }
             if (store) {
-                rd_st((T *)a.r, (int64_t)b * K::NS + slot, r);
-                rd_st((T *)a.p, (int64_t)b * K::NS + slot, r);
+                rd_st_keep((T *)a.r, (int64_t)b * K::NS + slot, r);
+                rd_st_keep((T *)a.p, (int64_t)b * K::NS + slot, r);
             }
         }
     }
@@ -180,10 +180,136 @@ __global__ __launch_bounds__(256) void k_cg_matvec(CgArgs a)
                 ap = -lap_at<B>(tile[sub][0], t, v.nbm);
                 pap += (double)tile[sub][0][t] * (double)ap;
             }
-            rd_st((T *)a.ap, (int64_t)b * K::NS + slot, ap);
+            rd_st_keep((T *)a.ap, (int64_t)b * K::NS + slot, ap);
         }
     }
     block_sum2<B>(pap, 0.0, a.partial, b, b < a.nb);
+}
+
+// Ap = A p for 8^3 blocks in the column form of the step kernel: one wave per block,
+// four blocks per workgroup, lane (lx, ly) walking its z-column, +-x / +-y
+// neighbours through a one-plane LDS tile, every load predicated on the activity of
+// the voxel it reads.  p is 0 on inactive and Dirichlet voxels (the residual and the
+// p update never give them another value), so on a free voxel
+//   (A p)_p = n_active * p_p - (((((p_-x + p_+x) + p_-y) + p_+y) + p_-z) + p_+z),
+// and Ap = 0 elsewhere.  Partial (p.Ap, 0) per block in FP64.
+// FUSE: the p update of the previous iteration is applied on the fly, to the block
+// and to its halos: p_new = fma(beta, p, r) from the stored r and p (the p update's
+// own operation, rounded to the storage type), stored into p2 (the caller swaps the
+// buffers: neighbouring waves still read the old p); Ap = A p_new.  p_new is 0 where
+// r and p are (inactive and Dirichlet voxels).
+template <typename T, bool FUSE>
+__global__ __launch_bounds__(256) void k_cg_matvec8(CgArgs a)
+{
+    __shared__ float tile[4][100];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int b = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + wv);
+    if (b >= a.nb) return;
+    const BlockInfo bi = a.info[b];
+    int bx, by, bz, gid;
+    block_pos(bi, &bx, &by, &bz, &gid);
+    if (!geom_live<8>(a, gid)) {
+        if (lane == 0) {
+            a.partial[(int64_t)b * 2 + 0] = 0.0;
+            a.partial[(int64_t)b * 2 + 1] = 0.0;
+        }
+        return;
+    }
+    const T *pv = (const T *)a.p;
+    const int64_t base = (int64_t)b * 512;
+    const int lx = lane & 7, ly = lane >> 3;
+    const uint64_t *rec = a.mask + (int64_t)b * 16;
+    uint64_t Wo[8], Wf[6];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) Wo[z] = rec[z];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) Wf[f] = rec[8 + f];
+    typedef typename RawOf<T>::type R;
+    const T *rv = (const T *)a.r;
+    R rc[8], rh[6], qc[8], qh[6];  // p (and with FUSE r) raw words
+    unsigned cd[8];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        const bool act = (Wo[z] >> lane) & 1ull;
+        rc[z] = ld_raw(pv, base + z * 64 + lane, act);
+        if (FUSE) qc[z] = ld_raw(rv, base + z * 64 + lane, act);
+        cd[z] = act ? (unsigned)a.code[base + z * 64 + lane] : 0u;
+    }
+    // face halos: lane (u, v) = (lx, ly) reads the neighbour slot across face f
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        int ns;
+        switch (f) {
+        case 0: ns = (ly * 8 + lx) * 8 + 7; break;
+        case 1: ns = (ly * 8 + lx) * 8 + 0; break;
+        case 2: ns = (ly * 8 + 7) * 8 + lx; break;
+        case 3: ns = (ly * 8 + 0) * 8 + lx; break;
+        case 4: ns = (7 * 8 + ly) * 8 + lx; break;
+        default: ns = (0 * 8 + ly) * 8 + lx; break;
+        }
+        const int n = bi.nbr[f];
+        const bool e = (Wf[f] >> lane) & 1ull;
+        rh[f] = ld_raw(pv, (int64_t)(n >= 0 ? n : b) * 512 + ns, e);
+        if (FUSE) qh[f] = ld_raw(rv, (int64_t)(n >= 0 ? n : b) * 512 + ns, e);
+    }
+    const float beta = FUSE ? (float)a.scal[gid * CG_NSCAL + CG_BETA] : 0.0f;
+    // p (FUSE: the updated p, as the p update would have stored it)
+    auto pval = [&](R praw, R rraw) {
+        const float pv_ = from_raw<T>(praw);
+        return FUSE ? rd_round<T>(fmaf(beta, pv_, from_raw<T>(rraw))) : pv_;
+    };
+    float c[8], side[4];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) c[z] = pval(rc[z], FUSE ? qc[z] : rc[z]);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) side[f] = pval(rh[f], FUSE ? qh[f] : rh[f]);
+    const float zlo = pval(rh[4], FUSE ? qh[4] : rh[4]), zhi = pval(rh[5], FUSE ? qh[5] : rh[5]);
+
+    const GeomInfo g = a.geom[gid];
+    const int gx = bx * 8 + lx, gy = by * 8 + ly;
+    const bool bnd = bx == 0 || by == 0 || bz == 0 || bx * 8 + 8 >= g.nx || by * 8 + 8 >= g.ny ||
+                     bz * 8 + 8 >= g.nz;
+    float *ts = tile[wv];
+    double pap = 0.0;
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        ts[(ly + 1) * 10 + (lx + 1)] = c[z];
+        if (ly == z) {  // side halos of plane z (face coordinate v = z)
+            ts[(lx + 1) * 10 + 0] = side[0];
+            ts[(lx + 1) * 10 + 9] = side[1];
+            ts[0 * 10 + (lx + 1)] = side[2];
+            ts[9 * 10 + (lx + 1)] = side[3];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const unsigned code = cd[z];
+        unsigned onf = 0u;
+        if (bnd)
+            onf = (gx == 0 ? 1u : 0u) | (gx == g.nx - 1 ? 2u : 0u) | (gy == 0 ? 4u : 0u) |
+                  (gy == g.ny - 1 ? 8u : 0u) | (bz * 8 + z == 0 ? 16u : 0u) |
+                  (bz * 8 + z == g.nz - 1 ? 32u : 0u);
+        const bool fr = (code & 64u) != 0u && (onf & a.dir) == 0u;
+        const float *q = &ts[(ly + 1) * 10 + (lx + 1)];
+        const float dn = z == 0 ? zlo : c[z > 0 ? z - 1 : 0];
+        const float up = z == 7 ? zhi : c[z < 7 ? z + 1 : 7];
+        const float sum = ((((q[-1] + q[1]) + q[-10]) + q[10]) + dn) + up;
+        const float ap = fr ? fmaf((float)__popc(code & 63u), c[z], -sum) : 0.0f;
+        if (fr) pap += (double)c[z] * (double)ap;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // whole sectors only (Ap and p are read on free voxels and as predicated halos)
+        if (sector_active<T>(Wo[z], lane)) {
+            rd_st_keep((T *)a.ap, base + z * 64 + lane, ap);
+            if (FUSE) rd_st_keep((T *)a.p2, base + z * 64 + lane, c[z]);
+        }
+    }
+    pap = wave_sum(pap);
+    if (lane == 0) {
+        a.partial[(int64_t)b * 2 + 0] = pap;
+        a.partial[(int64_t)b * 2 + 1] = 0.0;
+    }
 }
 
 // x += alpha p, r -= alpha Ap on free voxels of live geometries; partial (r.r, 0)
@@ -220,8 +346,8 @@ __global__ __launch_bounds__(256) void k_cg_update(CgArgs a)
             const float ap = rd_ld((const T *)a.ap, i);
             const float x = fmaf(alpha, p, rd_ld((const T *)a.x, i));
             const float r = fmaf(-alpha, ap, rd_ld((const T *)a.r, i));
-            rd_st((T *)a.x, i, x);
-            rd_st((T *)a.r, i, r);
+            rd_st_keep((T *)a.x, i, x);
+            rd_st_keep((T *)a.r, i, r);
             const float rs = rd_ld((const T *)a.r, i);  // the stored (rounded) residual
             rr += (double)rs * (double)rs;
         }
@@ -251,7 +377,7 @@ __global__ __launch_bounds__(256) void k_cg_pupdate(CgArgs a)
         const int gx = bx * B + slot % B, gy = by * B + (slot / B) % B, gz = bz * B + slot / (B * B);
         if (on_dirichlet(a.dir, gx, gy, gz, g.nx, g.ny, g.nz)) continue;
         const int64_t i = (int64_t)b * K::NS + slot;
-        rd_st((T *)a.p, i, fmaf(beta, rd_ld((const T *)a.p, i), rd_ld((const T *)a.r, i)));
+        rd_st_keep((T *)a.p, i, fmaf(beta, rd_ld((const T *)a.p, i), rd_ld((const T *)a.r, i)));
     }
 }
 
@@ -302,10 +428,12 @@ __global__ __launch_bounds__(256) void k_cg_flux(CgArgs a, int inlet_face)
 
 // Per-geometry sums of the per-block partial pairs: geometry g owns blocks
 // [block0_g, block0_{g+1}); one workgroup per geometry, fixed summation order.
-// dst[g*CG_NSCAL + slot0 + k] = sum (k = 0, 1; slot < 0 skips that lane).
+// dst[g*CG_NSCAL + slot0 + k] = sum (k = 0, 1; slot < 0 skips that lane); then, for a
+// live geometry, the scalar recurrence `mode`: 0 alpha = rr / pAp; 1 beta = rr_new / rr,
+// rr = rr_new; 2 rr = rr_new (start); -1 none.
 __global__ __launch_bounds__(256) void k_cg_segsum(const double *part, const GeomInfo *geom,
                                                    int ngeom, int nb, double *scal, int slot0,
-                                                   int slot1)
+                                                   int slot1, int mode)
 {
     __shared__ double sh[2][256];
     const int g = blockIdx.x;
@@ -328,28 +456,23 @@ __global__ __launch_bounds__(256) void k_cg_segsum(const double *part, const Geo
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        if (slot0 >= 0) scal[g * CG_NSCAL + slot0] = sh[0][0];
-        if (slot1 >= 0) scal[g * CG_NSCAL + slot1] = sh[1][0];
+        double *s = scal + g * CG_NSCAL;
+        if (slot0 >= 0) s[slot0] = sh[0][0];
+        if (slot1 >= 0) s[slot1] = sh[1][0];
+        // then the scalar recurrence of this geometry (live ones only)
+        if (mode >= 0 && s[CG_DONE] == 0.0) {
+            if (mode == 0) {
+                s[CG_ALPHA] = s[CG_PAP] > 0.0 ? s[CG_RR] / s[CG_PAP] : 0.0;
+            } else if (mode == 1) {
+                s[CG_BETA] = s[CG_RR] > 0.0 ? s[CG_RRNEW] / s[CG_RR] : 0.0;
+                s[CG_RR] = s[CG_RRNEW];
+            } else {
+                s[CG_RR] = s[CG_RRNEW];
+            }
+        }
     }
 }
 
-// Scalar recurrences per live geometry.  mode 0: alpha = rr / pAp.  mode 1:
-// beta = rr_new / rr, rr = rr_new.  mode 2: rr = rr_new (start).
-__global__ __launch_bounds__(256) void k_cg_scalars(double *scal, int ngeom, int mode)
-{
-    const int g = blockIdx.x * 256 + threadIdx.x;
-    if (g >= ngeom) return;
-    double *s = scal + g * CG_NSCAL;
-    if (s[CG_DONE] != 0.0) return;
-    if (mode == 0) {
-        s[CG_ALPHA] = s[CG_PAP] > 0.0 ? s[CG_RR] / s[CG_PAP] : 0.0;
-    } else if (mode == 1) {
-        s[CG_BETA] = s[CG_RR] > 0.0 ? s[CG_RRNEW] / s[CG_RR] : 0.0;
-        s[CG_RR] = s[CG_RRNEW];
-    } else {
-        s[CG_RR] = s[CG_RRNEW];
-    }
-}
 
 template <int B>
 int groups(int nb) { return (nb + Cfg<B>::BPW - 1) / Cfg<B>::BPW; }
@@ -382,7 +505,24 @@ int cg_launch_residual(int storage, int B, const CgArgs &a, int store, void *str
 }
 int cg_launch_matvec(int storage, int B, const CgArgs &a, void *stream)
 {
+    if (B == 8) {  // column form, four blocks per workgroup
+        const dim3 grid((unsigned)std::max(1, (a.nb + 3) / 4));
+        hipStream_t st = (hipStream_t)stream;
+        if (storage == 0) hipLaunchKernelGGL((k_cg_matvec8<float, false>), grid, dim3(256), 0, st, a);
+        else if (storage == 1) hipLaunchKernelGGL((k_cg_matvec8<bf16_t, false>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_cg_matvec8<_Float16, false>), grid, dim3(256), 0, st, a);
+        return (int)hipGetLastError();
+    }
     CG_DISPATCH(storage, B, k_cg_matvec, grid_for(B, a.nb), stream, a);
+}
+int cg_launch_matvec_fused(int storage, const CgArgs &a, void *stream)
+{
+    const dim3 grid((unsigned)std::max(1, (a.nb + 3) / 4));
+    hipStream_t st = (hipStream_t)stream;
+    if (storage == 0) hipLaunchKernelGGL((k_cg_matvec8<float, true>), grid, dim3(256), 0, st, a);
+    else if (storage == 1) hipLaunchKernelGGL((k_cg_matvec8<bf16_t, true>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_cg_matvec8<_Float16, true>), grid, dim3(256), 0, st, a);
+    return (int)hipGetLastError();
 }
 int cg_launch_update(int storage, int B, const CgArgs &a, void *stream)
 {
@@ -396,15 +536,9 @@ int cg_launch_flux(int storage, int B, const CgArgs &a, int inlet_face, void *st
 {
     CG_DISPATCH(storage, B, k_cg_flux, grid_for(B, a.nb), stream, a, inlet_face);
 }
-int cg_launch_segsum(const CgArgs &a, int slot0, int slot1, void *stream)
+int cg_launch_segsum(const CgArgs &a, int slot0, int slot1, int mode, void *stream)
 {
     hipLaunchKernelGGL(k_cg_segsum, dim3((unsigned)a.ngeom), dim3(256), 0, (hipStream_t)stream,
-                       a.partial, a.geom, a.ngeom, a.nb, a.scal, slot0, slot1);
-    return (int)hipGetLastError();
-}
-int cg_launch_scalars(const CgArgs &a, int mode, void *stream)
-{
-    hipLaunchKernelGGL(k_cg_scalars, dim3((unsigned)((a.ngeom + 255) / 256)), dim3(256), 0,
-                       (hipStream_t)stream, a.scal, a.ngeom, mode);
+                       (const double *)a.partial, a.geom, a.ngeom, a.nb, a.scal, slot0, slot1, mode);
     return (int)hipGetLastError();
 }

@@ -291,7 +291,7 @@ SimLayout sim_layout(const rd_sim &s, uint32_t features, int64_t cp_slots)
     L.mid = off; off = align256(off + sizeof(double) * 16 * RD_FINISH_GROUPS);
     L.res = off; off = align256(off + sizeof(double) * 64);
     if (features & RD_WS_SOLVER) {
-        for (int v = 0; v < 3; ++v) {
+        for (int v = 0; v < 4; ++v) {  // r, p, Ap, second p
             L.solver[v] = off;
             off = align256(off + es * (size_t)L.field_elems);
         }

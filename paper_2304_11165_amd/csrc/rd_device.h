@@ -40,6 +40,20 @@ __device__ __forceinline__ uint16_t bf16_rne(float v)
 __device__ __forceinline__ void rd_st(float *p, int64_t i, float v) { __builtin_nontemporal_store(v, p + i); }
 __device__ __forceinline__ void rd_st(bf16_t *p, int64_t i, float v) { p[i].bits = bf16_rne(v); }
 __device__ __forceinline__ void rd_st(_Float16 *p, int64_t i, float v) { p[i] = (_Float16)v; }
+// The value a round-to-nearest store into T holds when read back.
+template <typename T> __device__ __forceinline__ float rd_round(float v);
+template <> __device__ __forceinline__ float rd_round<float>(float v) { return v; }
+template <> __device__ __forceinline__ float rd_round<bf16_t>(float v)
+{
+    return __uint_as_float((uint32_t)bf16_rne(v) << 16);
+}
+template <> __device__ __forceinline__ float rd_round<_Float16>(float v) { return (float)(_Float16)v; }
+
+// Plain (cached) store with round to nearest, for vectors that are read again soon
+// (the solver's).
+__device__ __forceinline__ void rd_st_keep(float *p, int64_t i, float v) { p[i] = v; }
+__device__ __forceinline__ void rd_st_keep(bf16_t *p, int64_t i, float v) { p[i].bits = bf16_rne(v); }
+__device__ __forceinline__ void rd_st_keep(_Float16 *p, int64_t i, float v) { p[i] = (_Float16)v; }
 
 // ---- predicated loads ---------------------------------------------------------
 // A kernel that skips inactive voxels loads raw storage words under a predicate

@@ -35,7 +35,7 @@ struct SimLayout {
     int64_t field_elems;  // nb * B^3
     int nparts;
     size_t part, mid, res;  // reduction partials, finish scratch, results
-    size_t solver[3], scal;
+    size_t solver[4], scal;  // CG vectors r, p, Ap, second p
     size_t lam[2], target, cp, cp_stride;
     size_t total;
 };

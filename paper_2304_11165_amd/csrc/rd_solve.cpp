@@ -11,6 +11,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <thread>
 #include <limits>
 #include <new>
 #include <vector>
@@ -185,15 +187,15 @@ rd_status push_scal(const CgArgs &a, const std::vector<double> &hs, hipStream_t 
 
 // Runs CG on every geometry of `a` (Dirichlet values already in x) from a linear
 // ramp, stopping each geometry at rel. residual <= tol, stagnation or max_iters.
-rd_status run_cg(const CgArgs &a, int storage, int B, hipStream_t st, int axis, double tol,
+rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axis, double tol,
                  int64_t max_iters, const std::vector<GeomMeta> &meta, std::vector<CgOut> &out)
 {
+    CgArgs a = args;  // B = 8 swaps the two p buffers every iteration
     const int n = a.ngeom;
     out.assign(n, CgOut());
     LAUNCHCHK(rd_launch_fill_u32(a.scal, 0u, (int64_t)n * CG_NSCAL * 2, st));
     LAUNCHCHK(cg_launch_residual(storage, B, a, 1, st));
-    LAUNCHCHK(cg_launch_segsum(a, CG_RRNEW, CG_BB, st));
-    LAUNCHCHK(cg_launch_scalars(a, 2, st));
+    LAUNCHCHK(cg_launch_segsum(a, CG_RRNEW, CG_BB, 2, st));
     std::vector<double> hs;
     rd_status s = copy_scal(a, hs, st);
     if (s != RD_OK) return s;
@@ -215,17 +217,22 @@ rd_status run_cg(const CgArgs &a, int storage, int B, hipStream_t st, int axis, 
     if ((s = push_scal(a, hs, st)) != RD_OK) return s;
     while (live > 0) {
         for (int k = 0; k < CHECK_EVERY; ++k) {
-            LAUNCHCHK(cg_launch_matvec(storage, B, a, st));
-            LAUNCHCHK(cg_launch_segsum(a, CG_PAP, -1, st));
-            LAUNCHCHK(cg_launch_scalars(a, 0, st));
+            if (B == 8) {
+                // p <- r + beta p fused into the matvec (beta = 0 on the first pass, where
+                // p = r already), written to the other p buffer
+                LAUNCHCHK(cg_launch_matvec_fused(storage, a, st));
+                std::swap(a.p, a.p2);
+            } else {
+                LAUNCHCHK(cg_launch_matvec(storage, B, a, st));
+            }
+            LAUNCHCHK(cg_launch_segsum(a, CG_PAP, -1, 0, st));
             LAUNCHCHK(cg_launch_update(storage, B, a, st));
-            LAUNCHCHK(cg_launch_segsum(a, CG_RRNEW, -1, st));
-            LAUNCHCHK(cg_launch_scalars(a, 1, st));
-            LAUNCHCHK(cg_launch_pupdate(storage, B, a, st));
+            LAUNCHCHK(cg_launch_segsum(a, CG_RRNEW, -1, 1, st));
+            if (B != 8) LAUNCHCHK(cg_launch_pupdate(storage, B, a, st));
         }
         // true residual b - A x (the recursive one drifts in reduced precision)
         LAUNCHCHK(cg_launch_residual(storage, B, a, 0, st));
-        LAUNCHCHK(cg_launch_segsum(a, CG_CHECK, -1, st));
+        LAUNCHCHK(cg_launch_segsum(a, CG_CHECK, -1, -1, st));
         if ((s = copy_scal(a, hs, st)) != RD_OK) return s;
         for (int g = 0; g < n; ++g) {
             double *v = &hs[(size_t)g * CG_NSCAL];
@@ -251,7 +258,7 @@ rd_status run_cg(const CgArgs &a, int storage, int B, hipStream_t st, int axis, 
     }
     // steady flux through the two Dirichlet planes
     LAUNCHCHK(cg_launch_flux(storage, B, a, 2 * axis, st));
-    LAUNCHCHK(cg_launch_segsum(a, CG_QIN, CG_QOUT, st));
+    LAUNCHCHK(cg_launch_segsum(a, CG_QIN, CG_QOUT, -1, st));
     if ((s = copy_scal(a, hs, st)) != RD_OK) return s;
     for (int g = 0; g < n; ++g) {
         const GeomMeta &m = meta[g];
@@ -296,6 +303,7 @@ extern "C" rd_status rd_sim_steady_state(rd_sim *sim, int axis, double rel_tol, 
     CgArgs a{};
     a.info = (const BlockInfo *)(sim->ws + sim->L.info);
     a.mask = (const uint64_t *)(sim->ws + sim->L.mask);
+    a.code = (const uint8_t *)(sim->ws + sim->L.code);
     a.geom = (const GeomInfo *)(sim->ws + sim->L.geom);
     a.nb = (int)G.nb();
     a.ngeom = 1;
@@ -304,6 +312,7 @@ extern "C" rd_status rd_sim_steady_state(rd_sim *sim, int axis, double rel_tol, 
     a.r = sim->ws + sim->L.solver[0];
     a.p = sim->ws + sim->L.solver[1];
     a.ap = sim->ws + sim->L.solver[2];
+    a.p2 = sim->ws + sim->L.solver[3];
     a.partial = (double *)(sim->ws + sim->L.part);
     a.scal = (double *)(sim->ws + sim->L.scal);
     std::vector<GeomMeta> meta(1);
@@ -343,9 +352,10 @@ struct rd_batch {
     int64_t nb = 0;
     std::vector<BlockInfo> info;
     std::vector<uint64_t> mask;
+    std::vector<uint8_t> code;
     std::vector<GeomInfo> ginfo;
-    size_t o_info = 0, o_mask = 0, o_geom = 0, o_vec[4] = {0, 0, 0, 0}, o_part = 0, o_scal = 0,
-           total = 0;
+    size_t o_info = 0, o_mask = 0, o_code = 0, o_geom = 0, o_vec[5] = {0, 0, 0, 0, 0}, o_part = 0,
+           o_scal = 0, total = 0;
     char *ws = nullptr;
     hipStream_t stream = nullptr;
 };
@@ -378,6 +388,7 @@ extern "C" rd_status rd_batch_create(const rd_geometry *const *geoms, int n, rd_
     try {
         bt->info.reserve(total);
         bt->mask.reserve((size_t)total * MW);
+        bt->code.reserve((size_t)total * B * B * B);
         int32_t off = 0;
         for (int i = 0; i < n; ++i) {
             const rd_geometry &G = *geoms[i];
@@ -390,6 +401,7 @@ extern "C" rd_status rd_batch_create(const rd_geometry *const *geoms, int n, rd_
                 bt->info.push_back(bi);
             }
             bt->mask.insert(bt->mask.end(), G.mask.begin(), G.mask.end());
+            bt->code.insert(bt->code.end(), G.code.begin(), G.code.end());
             off += (int32_t)G.nb();
         }
     } catch (const std::bad_alloc &) {
@@ -401,8 +413,9 @@ extern "C" rd_status rd_batch_create(const rd_geometry *const *geoms, int n, rd_
     size_t o = 0;
     bt->o_info = o; o = al256(o + sizeof(BlockInfo) * nbs);
     bt->o_mask = o; o = al256(o + 8 * (size_t)MW * nbs);
+    bt->o_code = o; o = al256(o + nbs * (size_t)B * B * B);
     bt->o_geom = o; o = al256(o + sizeof(GeomInfo) * (size_t)n);
-    for (int v = 0; v < 4; ++v) {
+    for (int v = 0; v < 5; ++v) {  // x, r, p, Ap, second p
         bt->o_vec[v] = o;
         o = al256(o + es * nbs * (size_t)B * B * B);
     }
@@ -435,6 +448,8 @@ extern "C" rd_status rd_batch_bind(rd_batch *b, void *dev_ws, size_t bytes, void
                               hipMemcpyHostToDevice, b->stream));
         HIPCHK(hipMemcpyAsync(b->ws + b->o_mask, b->mask.data(), sizeof(uint64_t) * b->mask.size(),
                               hipMemcpyHostToDevice, b->stream));
+        HIPCHK(hipMemcpyAsync(b->ws + b->o_code, b->code.data(), b->code.size(), hipMemcpyHostToDevice,
+                              b->stream));
     }
     HIPCHK(hipMemcpyAsync(b->ws + b->o_geom, b->ginfo.data(), sizeof(GeomInfo) * b->ginfo.size(),
                           hipMemcpyHostToDevice, b->stream));
@@ -462,6 +477,7 @@ extern "C" rd_status rd_batch_tortuosity(rd_batch *b, int axis, double rel_tol, 
     CgArgs a{};
     a.info = (const BlockInfo *)(b->ws + b->o_info);
     a.mask = (const uint64_t *)(b->ws + b->o_mask);
+    a.code = (const uint8_t *)(b->ws + b->o_code);
     a.geom = (const GeomInfo *)(b->ws + b->o_geom);
     a.nb = (int)b->nb;
     a.ngeom = n;
@@ -470,16 +486,38 @@ extern "C" rd_status rd_batch_tortuosity(rd_batch *b, int axis, double rel_tol, 
     a.r = b->ws + b->o_vec[1];
     a.p = b->ws + b->o_vec[2];
     a.ap = b->ws + b->o_vec[3];
+    a.p2 = b->ws + b->o_vec[4];
     a.partial = (double *)(b->ws + b->o_part);
     a.scal = (double *)(b->ws + b->o_scal);
     std::vector<CgOut> out;
     if (b->nb > 0) {
+        // host labelling and initial guesses of the geometries are independent: compute
+        // them on parallel host threads, then upload in order
+        std::vector<std::vector<float>> x0(n);
+        std::vector<rd_status> st(n, RD_OK);
+        std::vector<char> perc(n, 0);
+        const int nt = (int)std::max(1u, std::min<unsigned>((unsigned)n, std::min(16u, std::thread::hardware_concurrency())));
+        std::atomic<int> next{0};
+        auto work = [&]() {
+            for (int i = next++; i < n; i = next++) {
+                bool pc = false;
+                st[i] = initial_guess(*b->geoms[i], axis, x0[i], &pc);
+                perc[i] = pc ? 1 : 0;
+            }
+        };
+        std::vector<std::thread> pool;
+        for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+        work();
+        for (auto &th : pool) th.join();
         for (int i = 0; i < n; ++i) {
-            std::vector<float> x0;
-            rd_status s = initial_guess(*b->geoms[i], axis, x0, &meta[i].percolates);
-            if (s != RD_OK) return s;
+            // (the worker's message is thread-local: report on this thread)
+            if (st[i] != RD_OK)
+                return rd_fail(st[i], "initial guess of geometry " + std::to_string(i) + " failed");
+            meta[i].percolates = perc[i] != 0;
             char *dst = (char *)a.x + es * NS * (size_t)b->ginfo[i].block0;
-            if ((s = upload_field(x0, b->storage, dst, b->stream)) != RD_OK) return s;
+            rd_status s = upload_field(x0[i], b->storage, dst, b->stream);
+            if (s != RD_OK) return s;
+            std::vector<float>().swap(x0[i]);
         }
         rd_status s = run_cg(a, (int)b->storage, b->B, b->stream, axis, rel_tol, max_iters, meta, out);
         if (s != RD_OK) return s;

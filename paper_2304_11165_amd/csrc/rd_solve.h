@@ -23,19 +23,23 @@ enum {
 struct CgArgs {
     const BlockInfo *info;
     const uint64_t *mask;
+    const uint8_t *code;   // per-slot neighbour codes (bits 0-5 neighbours, bit 6 active)
     const GeomInfo *geom;  // ngeom entries; block ranges via block0
     int nb;
     int ngeom;
     uint32_t dir;          // Dirichlet faces (inlet | outlet)
     void *x, *r, *p, *ap;  // storage type T, nb * B^3 each
+    void *p2;              // second p buffer (B = 8: the fused p update writes here)
     double *partial;       // [nb][2]
     double *scal;          // [ngeom][CG_NSCAL]
 };
 
 int cg_launch_residual(int storage, int B, const CgArgs &a, int store, void *stream);
 int cg_launch_matvec(int storage, int B, const CgArgs &a, void *stream);
+// B = 8: p2 = r + beta p (per live geometry, rounded to the storage type), Ap = A p2,
+// partial (p2.Ap, 0); the caller then swaps p and p2.
+int cg_launch_matvec_fused(int storage, const CgArgs &a, void *stream);
 int cg_launch_update(int storage, int B, const CgArgs &a, void *stream);
 int cg_launch_pupdate(int storage, int B, const CgArgs &a, void *stream);
 int cg_launch_flux(int storage, int B, const CgArgs &a, int inlet_face, void *stream);
-int cg_launch_segsum(const CgArgs &a, int slot0, int slot1, void *stream);
-int cg_launch_scalars(const CgArgs &a, int mode, void *stream);
+int cg_launch_segsum(const CgArgs &a, int slot0, int slot1, int mode, void *stream);
