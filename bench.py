@@ -44,8 +44,13 @@ def parse():
     p.add_argument("--size", type=int, default=512, help="edge of the volume (default 512)")
     p.add_argument("--forms", default="bf16,fp16", help="reduced-storage forms to time")
     p.add_argument("--form-steps", type=int, default=2000)
-    p.add_argument("--batch", type=int, default=16, help="geometries in the batched form (0: skip)")
-    p.add_argument("--batch-max-edge", type=int, default=128)
+    p.add_argument("--batch", type=int, default=64, help="geometries in the batched form (0: skip)")
+    p.add_argument("--batch-max-edge", type=int, default=256)
+    p.add_argument("--steady-axes", type=int, default=0,
+                   help="ceramic-foam steady state: tortuosity along the first K axes (0: skip)")
+    p.add_argument("--steady-size", type=int, default=1024, help="edge of the foam volume")
+    p.add_argument("--steady-forms", default="fp32", help="storage types of the steady form")
+    p.add_argument("--steady-tol", type=float, default=1e-6)
     p.add_argument("--cpu-steps", type=int, default=4, help="oracle steps in the CPU sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--graph-steps", type=int, default=32)
@@ -179,6 +184,44 @@ def batched_form(torch, rd, W, count, max_edge, stream):
         "iterations": [int(x) for x in it],
         "note": "wall time including host labelling and the initial-guess upload",
     }
+
+
+def steady_form(torch, rd, W, size, axes, forms, tol, stream):
+    """Tortuosity of the ceramic-foam volume (solid matrix of overlapping pore spheres
+    r ~ U(10, 30), pore fraction 0.15) along the first `axes` axes by conjugate
+    gradients, per storage type."""
+    t0 = time.perf_counter()
+    w = W.workload("foam1024")
+    img, _ = W.workload_geometry("foam1024") if size == 1024 else \
+        W.boolean_spheres(size, 0.15, 10.0, 30.0, seed=w.seed, active="solid")
+    log(f"foam {size}^3 generated in {time.perf_counter() - t0:.1f}s")
+    geom = rd.Geometry(img, None, 1.0, 8)
+    st = geom.stats()
+    del img
+    out = {"workload": f"foam{size}", "n_active": st["n_active"], "n_blocks": st["n_blocks"],
+           "fill": st["fill"], "tol": tol, "runs": []}
+    for storage in forms:
+        with torch.cuda.stream(stream):
+            sim = rd.Sim(geom, storage)
+            sim.add_species(1.0)
+            sim.bind(features=rd.RD_WS_SOLVER, stream=stream)
+            for axis in range(axes):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = sim.steady_state(axis, tol, 200000)
+                torch.cuda.synchronize()
+                secs = time.perf_counter() - t0
+                vi = float(st["n_active"]) * r["iters"]
+                out["runs"].append({"storage": storage, "axis": axis, "tau": r["tau"],
+                                    "rel_residual": r["rel_residual"], "iters": r["iters"],
+                                    "converged": r["converged"], "seconds": secs,
+                                    "active_voxel_cg_iterations_per_s": vi / secs,
+                                    "alg_GBps": vi * 10 * (4 if storage == "fp32" else 2) / secs / 1e9})
+                log(f"steady {storage} axis {axis}: tau {r['tau']:.5f}, rel {r['rel_residual']:.2e}, "
+                    f"{r['iters']} it, {secs:.1f}s")
+            del sim
+            torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -318,6 +361,11 @@ def main():
         out["forms"]["batched"] = batched_form(torch, rd, W, a.batch, a.batch_max_edge, stream)
         log(f"batched: {out['forms']['batched']['active_voxel_cg_iterations_per_s']:.3e} "
             f"voxel-iterations/s")
+
+    if a.steady_axes > 0 and not a.profile:
+        out["forms"]["steady"] = steady_form(torch, rd, W, a.steady_size, a.steady_axes,
+                                             [f for f in a.steady_forms.split(",") if f],
+                                             a.steady_tol, stream)
 
     if not a.no_cpu_baseline and not a.profile:
         import oracle

@@ -269,8 +269,12 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
         const int64_t ext[3] = {m.nx, m.ny, m.nz};
         const double area = (double)ext[(axis + 1) % 3] * (double)ext[(axis + 2) % 3] * m.dx * m.dx;
         const double len = (double)(ext[axis] - 1) * m.dx;
-        out[g].tau = (m.percolates && out[g].qin > 0) ? m.psi * area / (out[g].qin * len)
-                                    : std::numeric_limits<double>::infinity();
+        // inlet and outlet fluxes agree at an exact steady state; on an iterate their
+        // mean is used (with BF16 / FP16 storage the inlet flux alone can vanish:
+        // values just below 1 round to 1, while values near 0 keep their resolution)
+        const double q = 0.5 * (out[g].qin + out[g].qout);
+        out[g].tau = (m.percolates && q > 0) ? m.psi * area / (q * len)
+                                              : std::numeric_limits<double>::infinity();
     }
     return RD_OK;
 }
