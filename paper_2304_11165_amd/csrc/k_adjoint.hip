@@ -84,9 +84,130 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs a)
         wsum[wave][1] = s1;
     }
     __syncthreads();
-    if (threadIdx.x < 2) {
+    if (threadIdx.x < 2) {  // this workgroup's accumulator, in step order
         const int l = threadIdx.x;
-        a.partial[(int64_t)blockIdx.x * 2 + l] = ((wsum[0][l] + wsum[1][l]) + wsum[2][l]) + wsum[3][l];
+        a.partial[(int64_t)blockIdx.x * 2 + l] += ((wsum[0][l] + wsum[1][l]) + wsum[2][l]) + wsum[3][l];
+    }
+}
+
+// The adjoint step for 8^3 blocks in the column form of the forward step: one wave per
+// block (four per workgroup), lane (lx, ly) walking its z-column; lambda^{n+1} and c^n
+// of the block and of its face halos are loaded under the activity predicates, the
+// +-x / +-y neighbours of both go through one-plane LDS tiles.  lambda^n on free
+// voxels is rd_update on lambda (the forward step with zero Dirichlet data), 0
+// elsewhere; the gradient terms of the block are added, in step order, to its own
+// FP64 accumulators partial[b][0..1] (one wave owns a block, so there is no race):
+//   dL/dD: lambda^{n+1}_p * (sum of the six c^n neighbours - n_active * c^n_p)
+//   dL/dk: -lambda^{n+1}_p * c^n_p                      (scaled on the host)
+template <typename T>
+__global__ __launch_bounds__(256) void k_adjoint8(AdjArgs a)
+{
+    __shared__ float tl[4][100], tc[4][100];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int b = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + wv);
+    if (b >= a.nb) return;
+    const BlockInfo bi = a.info[b];
+    const T *cv = (const T *)a.c;
+    const int64_t base = (int64_t)b * 512;
+    const int lx = lane & 7, ly = lane >> 3;
+    const uint64_t *rec = a.mask + (int64_t)b * 16;
+    uint64_t Wo[8], Wf[6];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) Wo[z] = rec[z];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) Wf[f] = rec[8 + f];
+    typedef typename RawOf<T>::type R;
+    float lc[8], lh[6];
+    R cc[8], ch[6];
+    unsigned cd[8];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        const bool act = (Wo[z] >> lane) & 1ull;
+        lc[z] = ld_raw(a.lam_in, base + z * 64 + lane, act);
+        cc[z] = ld_raw(cv, base + z * 64 + lane, act);
+        cd[z] = act ? (unsigned)a.code[base + z * 64 + lane] : 0u;
+    }
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        int ns;
+        switch (f) {
+        case 0: ns = (ly * 8 + lx) * 8 + 7; break;
+        case 1: ns = (ly * 8 + lx) * 8 + 0; break;
+        case 2: ns = (ly * 8 + 7) * 8 + lx; break;
+        case 3: ns = (ly * 8 + 0) * 8 + lx; break;
+        case 4: ns = (7 * 8 + ly) * 8 + lx; break;
+        default: ns = (0 * 8 + ly) * 8 + lx; break;
+        }
+        const int n = bi.nbr[f];
+        const bool e = (Wf[f] >> lane) & 1ull;
+        const int64_t hb = (int64_t)(n >= 0 ? n : b) * 512 + ns;
+        lh[f] = ld_raw(a.lam_in, hb, e);
+        ch[f] = ld_raw(cv, hb, e);
+    }
+    float c[8], cs[6];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) c[z] = from_raw<T>(cc[z]);
+#pragma unroll
+    for (int f = 0; f < 6; ++f) cs[f] = from_raw<T>(ch[f]);
+
+    int bx, by, bz, gid;
+    block_pos(bi, &bx, &by, &bz, &gid);
+    const GeomInfo g = a.geom[gid];
+    const int gx = bx * 8 + lx, gy = by * 8 + ly;
+    const bool bnd = bx == 0 || by == 0 || bz == 0 || bx * 8 + 8 >= g.nx || by * 8 + 8 >= g.ny ||
+                     bz * 8 + 8 >= g.nz;
+    float *TL = tl[wv], *TC = tc[wv];
+    double gD = 0.0, gk = 0.0;
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        TL[(ly + 1) * 10 + (lx + 1)] = lc[z];
+        TC[(ly + 1) * 10 + (lx + 1)] = c[z];
+        if (ly == z) {  // side halos of plane z (face coordinate v = z)
+            TL[(lx + 1) * 10 + 0] = lh[0];
+            TL[(lx + 1) * 10 + 9] = lh[1];
+            TL[0 * 10 + (lx + 1)] = lh[2];
+            TL[9 * 10 + (lx + 1)] = lh[3];
+            TC[(lx + 1) * 10 + 0] = cs[0];
+            TC[(lx + 1) * 10 + 9] = cs[1];
+            TC[0 * 10 + (lx + 1)] = cs[2];
+            TC[9 * 10 + (lx + 1)] = cs[3];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const unsigned code = cd[z], m = code & 63u;
+        unsigned onf = 0u;
+        if (bnd)
+            onf = (gx == 0 ? 1u : 0u) | (gx == g.nx - 1 ? 2u : 0u) | (gy == 0 ? 4u : 0u) |
+                  (gy == g.ny - 1 ? 8u : 0u) | (bz * 8 + z == 0 ? 16u : 0u) |
+                  (bz * 8 + z == g.nz - 1 ? 32u : 0u);
+        const bool fr = (code & 64u) != 0u && (onf & a.coef.dir) == 0u;
+        const int nwall = __popc(~onf & ~m & 0x3fu);
+        const int o = (ly + 1) * 10 + (lx + 1);
+        const float lp = lc[z];
+        const float nbl[6] = {TL[o - 1], TL[o + 1], TL[o - 10], TL[o + 10], z == 0 ? lh[4] : lc[z > 0 ? z - 1 : 0],
+                              z == 7 ? lh[5] : lc[z < 7 ? z + 1 : 7]};
+        const float cen[1] = {lp};
+        const float lout = fr ? rd_update<1>(lp, nbl, m, nwall, a.coef, cen) : 0.0f;
+        if (fr) {
+            const double sc = (((((double)TC[o - 1] + (double)TC[o + 1]) + (double)TC[o - 10]) +
+                                (double)TC[o + 10]) + (double)(z == 0 ? cs[4] : c[z > 0 ? z - 1 : 0])) +
+                              (double)(z == 7 ? cs[5] : c[z < 7 ? z + 1 : 7]);
+            const double lapc = sc - (double)__popc(m) * (double)c[z];
+            gD += (double)lp * lapc;
+            gk -= (double)lp * (double)c[z];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // lambda is FP32 and read under activity predicates: whole 128-byte sectors
+        if (sector_active<float>(Wo[z], lane)) a.lam_out[base + z * 64 + lane] = lout;
+    }
+    gD = wave_sum(gD);
+    gk = wave_sum(gk);
+    if (lane == 0) {
+        a.partial[(int64_t)b * 2 + 0] += gD;
+        a.partial[(int64_t)b * 2 + 1] += gk;
     }
 }
 
@@ -128,24 +249,6 @@ __global__ __launch_bounds__(256) void k_adj_seed(AdjArgs a, int mode)
     if (threadIdx.x == 0) a.partial[b] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
 }
 
-// out[l] += sum over parts of part[part*nl + l] (fixed order), l < nl
-__global__ __launch_bounds__(256) void k_sum_acc(const double *part, int nparts, int nl, double *out)
-{
-    __shared__ double sh[256];
-    for (int l = 0; l < nl; ++l) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < nparts; i += 256) s += part[(int64_t)i * nl + l];
-        sh[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[l] += sh[0];
-        __syncthreads();
-    }
-}
-
 }  // namespace
 
 #define ADJ_DISPATCH(storage, B, KERNEL, grid, stream, ...)                                        \
@@ -167,16 +270,18 @@ int adj_groups(int B, int nb) { return B == 8 ? nb : (nb + 3) / 4; }
 
 int adj_launch_step(int storage, int B, const AdjArgs &a, void *stream)
 {
+    if (B == 8) {  // column form, four blocks per workgroup, per-block accumulators
+        const dim3 grid((unsigned)((a.nb + 3) / 4));
+        hipStream_t st = (hipStream_t)stream;
+        if (storage == 0) hipLaunchKernelGGL((k_adjoint8<float>), grid, dim3(256), 0, st, a);
+        else if (storage == 1) hipLaunchKernelGGL((k_adjoint8<bf16_t>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_adjoint8<_Float16>), grid, dim3(256), 0, st, a);
+        return (int)hipGetLastError();
+    }
     ADJ_DISPATCH(storage, B, k_adjoint, dim3((unsigned)adj_groups(B, a.nb)), stream, a);
 }
 
 int adj_launch_seed(int storage, int B, const AdjArgs &a, int mode, void *stream)
 {
     ADJ_DISPATCH(storage, B, k_adj_seed, dim3((unsigned)a.nb), stream, a, mode);
-}
-
-int adj_launch_sum_acc(const double *part, int nparts, int nl, double *out, void *stream)
-{
-    hipLaunchKernelGGL(k_sum_acc, dim3(1), dim3(256), 0, (hipStream_t)stream, part, nparts, nl, out);
-    return (int)hipGetLastError();
 }

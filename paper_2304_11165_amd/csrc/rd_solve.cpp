@@ -605,6 +605,7 @@ extern "C" rd_status rd_sim_adjoint(rd_sim *sim, const float *dev_seed, int seed
     AdjArgs a{};
     a.info = (const BlockInfo *)(ws + sim->L.info);
     a.mask = (const uint64_t *)(ws + sim->L.mask);
+    a.code = (const uint8_t *)(ws + sim->L.code);
     a.geom = (const GeomInfo *)(ws + sim->L.geom);
     a.nb = nb;
     const StepArgs fa = sim->step_args(dt, sim->cur);
@@ -617,7 +618,12 @@ extern "C" rd_status rd_sim_adjoint(rd_sim *sim, const float *dev_seed, int seed
     a.c = sim->field_ptr(sim->cur, 0);
     a.lam_out = lam[lc];
     LAUNCHCHK(adj_launch_seed(st, B, a, seed_mode, stream));
-    LAUNCHCHK(adj_launch_sum_acc(a.partial, nb, 1, acc, stream));
+    double *mid = (double *)(ws + sim->L.mid);
+    LAUNCHCHK(rd_launch_finish_reduce(a.partial, nb, 1, mid, acc, stream));
+    // the step kernel adds its gradient terms to its own FP64 rows, in step order; one
+    // fixed-order reduction over the rows after the sweep
+    const int nrows = adj_groups(B, nb);
+    LAUNCHCHK(rd_launch_fill_u32(a.partial, 0u, (int64_t)nrows * 4, stream));
     // backward over segments
     for (int64_t j = ncp - 1; j >= 0; --j) {
         const int64_t s0 = j * k;
@@ -639,10 +645,10 @@ extern "C" rd_status rd_sim_adjoint(rd_sim *sim, const float *dev_seed, int seed
             a.lam_in = lam[lc];
             a.lam_out = lam[1 - lc];
             LAUNCHCHK(adj_launch_step(st, B, a, stream));
-            LAUNCHCHK(adj_launch_sum_acc(a.partial, adj_groups(B, nb), 2, acc + 1, stream));
             lc = 1 - lc;
         }
     }
+    LAUNCHCHK(rd_launch_finish_reduce(a.partial, nrows, 2, mid, acc + 1, stream));
     double h[3];
     HIPCHK(hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
