@@ -178,6 +178,13 @@ rd_status rd_sim_reduce(rd_sim *sim, int species, double *mass, double *dirichle
 /* All balance terms: out[0] mass, out[1..6] inflow per face, out[7] uptake,
  * out[8] reaction total (sum over free voxels of the reaction rate, times dx^3). */
 rd_status rd_sim_balance(rd_sim *sim, int species, double out[9]);
+/* Diffusive flux of a species through the plane between indices i0 and i0 + 1 along
+ * `axis` (0 x, 1 y, 2 z), positive in the +axis direction (the flux from which an
+ * effective diffusivity, and with it the tortuosity of eq. background:tortuosity, is
+ * read):  sum over pairs (p, p + e_axis) of active voxels of D (c_p - c_{p+e}) dx,
+ * accumulated in FP64 in a fixed order (synchronises).  RD_ERR_ARG unless
+ * 0 <= i0 < n_axis - 1; RD_ERR_STATE before bind. */
+rd_status rd_sim_plane_flux(rd_sim *sim, int species, int axis, int64_t i0, double *flux);
 
 /* Steady state of species 0 (single-species, no reactions or Robin) with a unit
  * drop along `axis` (Dirichlet 1 on the low face plane, 0 on the high one,
@@ -185,7 +192,8 @@ rd_status rd_sim_balance(rd_sim *sim, int species, double out[9]);
  * and FP64 dot products.  Stops at rel. residual <= rel_tol, at stagnation (no 10%
  * decrease of the best residual over 20 checks of 50 iterations) or at max_iters.
  * tau = psi D A / (Q L): psi active fraction, A box cross-section, L = (n-1) dx,
- * Q the inflow at the inlet plane (eq. tortuosity, tau = D_f / D_eff); +inf if
+ * Q the mean of the inflow at the inlet plane and the outflow at the outlet plane
+ * (equal at an exact steady state; eq. tortuosity, tau = D_f / D_eff); +inf if
  * Q <= 0.  Needs RD_WS_SOLVER.  Leaves the steady field in species 0. */
 rd_status rd_sim_steady_state(rd_sim *sim, int axis, double rel_tol, int64_t max_iters,
                               double *tau, double *rel_residual, int64_t *iters);

@@ -738,6 +738,167 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a)
     }
 }
 
+// The same reduction for 8^3 blocks in the column form of the step: one wave per block,
+// four blocks per workgroup, lane (lx, ly) walking its z-column, loads under the
+// voxel-activity predicate.  The per-voxel terms are those of k_reduce; a Dirichlet
+// voxel (only in blocks on a flagged box face) reads each of its free neighbours
+// directly.  One row of RD_NRED partials per workgroup: its four wave sums in wave order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_reduce8z(ReduceArgs a)
+{
+    __shared__ double wsum[4][RD_NRED];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int b = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + wv);
+    double acc[RD_NRED];
+#pragma unroll
+    for (int l = 0; l < RD_NRED; ++l) acc[l] = 0.0;
+    bool hasreact = a.rate_out != 0.0;
+    for (int s2 = 0; s2 < a.S; ++s2) hasreact = hasreact || a.rate_in[s2] != 0.0;
+    bool dblock = false;
+    if (b < a.nb) {  // wave-uniform; the barrier below is outside
+        const BlockInfo bi = a.info[b];
+        int bx, by, bz, gid;
+        block_pos(bi, &bx, &by, &bz, &gid);
+        const GeomInfo g = a.geom[gid];
+        const uint64_t *rec = a.mask + (int64_t)b * 16;
+        const int64_t base = (int64_t)b * 512;
+        const T *c = (const T *)a.c;
+        const T *cs = c + a.s * a.sstride;
+        const int lx = lane & 7, ly = lane >> 3;
+        const int gx = bx * 8 + lx, gy = by * 8 + ly;
+        const bool at[6] = {bx == 0, bx * 8 + 8 >= g.nx, by == 0, by * 8 + 8 >= g.ny, bz == 0,
+                            bz * 8 + 8 >= g.nz};
+        bool bnd = false;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            bnd = bnd || at[f];
+            dblock = dblock || (((a.dir >> f) & 1u) && at[f]);
+        }
+        typedef typename RawOf<T>::type R;
+        uint64_t Wo[8];
+        R raw[8];
+        unsigned cd[8];
+#pragma unroll
+        for (int z = 0; z < 8; ++z) {
+            Wo[z] = rec[z];
+            const bool act = (Wo[z] >> lane) & 1ull;
+            raw[z] = ld_raw(cs, base + z * 64 + lane, act);
+            cd[z] = act ? (unsigned)a.code[base + z * 64 + lane] : 0u;
+        }
+        // inflow into this species from the others (0 on inactive slots)
+        double rin[8];
+#pragma unroll
+        for (int z = 0; z < 8; ++z) rin[z] = 0.0;
+        for (int s2 = 0; s2 < a.S; ++s2) {
+            const double k = a.rate_in[s2];
+            if (k == 0.0) continue;
+            R r2[8];
+#pragma unroll
+            for (int z = 0; z < 8; ++z) r2[z] = ld_raw(c + s2 * a.sstride, base + z * 64 + lane, (Wo[z] >> lane) & 1ull);
+#pragma unroll
+            for (int z = 0; z < 8; ++z) rin[z] += k * (double)from_raw<T>(r2[z]);
+        }
+        const double dx = a.dx, dx2 = dx * dx, dx3 = dx2 * dx;
+#pragma unroll
+        for (int z = 0; z < 8; ++z) {
+            const unsigned code = cd[z];
+            if (!(code & 64u)) continue;
+            const float uf = from_raw<T>(raw[z]);
+            const double u = (double)uf;
+            if (!isfinite(uf)) acc[9] += 1.0;
+            const int gz = bz * 8 + z;
+            const unsigned onf = bnd ? box_faces(g, gx, gy, gz) : 0u;
+            if (onf & a.dir) {
+                // Dirichlet voxel: inflow into its free neighbours, booked on the first
+                // flagged face (in face order) it lies on
+                const int fq = __builtin_ctz(onf & a.dir);
+                double fin = 0.0;
+#pragma unroll
+                for (int d = 0; d < 6; ++d) {
+                    if (!((code >> d) & 1u)) continue;
+                    const int ex = d == 0 ? -1 : d == 1 ? 1 : 0;
+                    const int ey = d == 2 ? -1 : d == 3 ? 1 : 0;
+                    const int ez = d == 4 ? -1 : d == 5 ? 1 : 0;
+                    if (on_dirichlet(a.dir, gx + ex, gy + ey, gz + ez, g.nx, g.ny, g.nz)) continue;
+                    const int qx = lx + ex, qy = ly + ey, qz = z + ez;
+                    const bool inside = qx >= 0 && qx < 8 && qy >= 0 && qy < 8 && qz >= 0 && qz < 8;
+                    // an active neighbour outside the block lies in face neighbour d
+                    const int nbk = inside ? b : bi.nbr[d];
+                    const int slot = ((qz & 7) * 8 + (qy & 7)) * 8 + (qx & 7);
+                    const double v = (double)rd_ld(cs, (int64_t)nbk * 512 + slot);
+                    fin += a.D * (u - v) * dx;
+                }
+#pragma unroll
+                for (int f = 0; f < 6; ++f)
+                    if (f == fq) acc[1 + f] += fin;
+                continue;
+            }
+            acc[0] += u * dx3;
+            if (a.kR != 0.0) {
+                const int nwall = __popc(~onf & ~code & 0x3fu);
+                acc[7] += a.kR * (double)nwall * u * dx2;
+            }
+            if (hasreact) acc[8] += (rin[z] - a.rate_out * u) * dx3;
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < RD_NRED; ++l) {
+        const bool need = l == 0 || l == 9 || (l <= 6 && dblock) || (l == 7 && a.kR != 0.0) ||
+                          (l == 8 && hasreact);
+        const double v = need ? wave_sum(acc[l]) : 0.0;
+        if (lane == 0) wsum[wv][l] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < RD_NRED) {
+        const int l = threadIdx.x;
+        a.partial[(int64_t)blockIdx.x * RD_NRED + l] =
+            ((wsum[0][l] + wsum[1][l]) + wsum[2][l]) + wsum[3][l];
+    }
+}
+
+// Diffusive flux of one species through the plane between indices i0 and i0 + 1 along
+// `axis`: sum over pairs (p, p + e_axis) of active voxels of D (c_p - c_{p+e}) dx.  One
+// wave per block, four blocks per workgroup; lane l < B^2 takes in-plane position l of
+// the block's layer i0, if the block holds it.  One FP64 partial per workgroup (its
+// four wave sums in wave order).
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_plane_flux(const BlockInfo *info, const uint8_t *code,
+                                                    const T *c, int nb, int axis, int i0,
+                                                    double D, double dx, double *partial)
+{
+    using K = Blk<B>;
+    __shared__ double wsum[4];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int b = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + wv);
+    double q = 0.0;
+    if (b < nb) {
+        const BlockInfo bi = info[b];
+        int bx, by, bz, gid;
+        block_pos(bi, &bx, &by, &bz, &gid);
+        const int l0 = i0 - (axis == 0 ? bx : axis == 1 ? by : bz) * B;
+        if (l0 >= 0 && l0 < B && lane < B * B) {
+            const int u = lane % B, v = lane / B;
+            const int lx = axis == 0 ? l0 : u, ly = axis == 1 ? l0 : axis == 0 ? u : v,
+                      lz = axis == 2 ? l0 : v;
+            const int slot = (lz * B + ly) * B + lx;
+            const int stride = axis == 0 ? 1 : axis == 1 ? B : B * B;
+            const unsigned cd = code[(int64_t)b * K::NS + slot];
+            if ((cd & 64u) && ((cd >> (2 * axis + 1)) & 1u)) {
+                // the active +axis neighbour is in this block or in face neighbour 2 axis + 1
+                const int nbk = l0 + 1 < B ? b : bi.nbr[2 * axis + 1];
+                const int ns = l0 + 1 < B ? slot + stride : slot - (B - 1) * stride;
+                const double cp = (double)rd_ld(c, (int64_t)b * K::NS + slot);
+                const double cq = (double)rd_ld(c, (int64_t)nbk * K::NS + ns);
+                q = D * (cp - cq) * dx;
+            }
+        }
+    }
+    const double s = wave_sum(q);
+    if (lane == 0) wsum[wv] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+}
+
 // Row sums of a [nrows][nlanes] FP64 array (nlanes <= RD_FINISH_LANES): workgroup g
 // sums rows [g * chunk, min((g + 1) * chunk, nrows)) into out[g][*].  Thread t adds
 // rows t, t + 256, ... of the range (whole rows, so loads are coalesced), then a
@@ -905,7 +1066,10 @@ int launch_step_t(const StepArgs &a, hipStream_t st)
 template <typename T, int B>
 int launch_reduce_t(const ReduceArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_reduce<T, B>), dim3(groups_for<B>(a.nb)), dim3(256), 0, st, a);
+    if (B == 8)  // column form, four blocks per workgroup
+        hipLaunchKernelGGL((k_reduce8z<T>), dim3(rd_reduce_rows(B, a.nb)), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_reduce<T, B>), dim3(rd_reduce_rows(B, a.nb)), dim3(256), 0, st, a);
     return (int)hipGetLastError();
 }
 
@@ -930,7 +1094,28 @@ int rd_launch_step(int storage, int B, const StepArgs &a, void *stream)
     RD_DISPATCH(storage, B, launch_step_t, a, (hipStream_t)stream);
 }
 
-int rd_launch_reduce(int storage, int B, const ReduceArgs &a, int, void *stream)
+int rd_reduce_rows(int, int nb) { return (nb + 3) / 4; }
+
+namespace {
+template <typename T, int B>
+int launch_plane_flux_t(const BlockInfo *info, const uint8_t *code, const void *c, int nb, int axis,
+                        int i0, double D, double dx, double *partial, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_plane_flux<T, B>), dim3(rd_reduce_rows(B, nb)), dim3(256), 0, st, info, code,
+                       (const T *)c, nb, axis, i0, D, dx, partial);
+    return (int)hipGetLastError();
+}
+}  // namespace
+
+int rd_launch_plane_flux(int storage, int B, const BlockInfo *info, const uint8_t *code, const void *c,
+                         int nb, int axis, int i0, double D, double dx, double *partial, void *stream)
+{
+    if (nb <= 0) return 0;
+    RD_DISPATCH(storage, B, launch_plane_flux_t, info, code, c, nb, axis, i0, D, dx, partial,
+                (hipStream_t)stream);
+}
+
+int rd_launch_reduce(int storage, int B, const ReduceArgs &a, void *stream)
 {
     if (a.nb <= 0) return 0;
     RD_DISPATCH(storage, B, launch_reduce_t, a, (hipStream_t)stream);

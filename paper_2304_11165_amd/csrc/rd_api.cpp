@@ -555,10 +555,9 @@ rd_status rd_sim::balance(int s, double out[RD_NRED])
         if (r.to == s) a.rate_in[r.from] += r.rate;
     }
     a.partial = (double *)(ws + L.part);
-    const int bpw = g->B == 8 ? 1 : 4;
-    const int nparts = (a.nb + bpw - 1) / bpw;  // 0 for an empty geometry: sums are 0
+    const int nparts = rd_reduce_rows(g->B, a.nb);  // 0 for an empty geometry: sums are 0
     double *res = (double *)(ws + L.res);
-    LAUNCHCHK(rd_launch_reduce(storage, g->B, a, nparts, stream));
+    LAUNCHCHK(rd_launch_reduce(storage, g->B, a, stream));
     LAUNCHCHK(rd_launch_finish_reduce(a.partial, nparts, RD_NRED, (double *)(ws + L.mid), res, stream));
     HIPCHK(hipMemcpyAsync(host_res, res, sizeof(double) * RD_NRED, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
@@ -636,6 +635,34 @@ extern "C" rd_status rd_sim_reduce(rd_sim *sim, int species, double *mass, doubl
     if (dirichlet_inflow) *dirichlet_inflow = r[1] + r[2] + r[3] + r[4] + r[5] + r[6];
     if (robin_uptake) *robin_uptake = r[7];
     return st;
+}
+
+extern "C" rd_status rd_sim_plane_flux(rd_sim *sim, int species, int axis, int64_t i0, double *flux)
+{
+    if (!sim || !flux) return rd_fail(RD_ERR_ARG, "NULL argument");
+    if (!sim->ws) return rd_fail(RD_ERR_STATE, "bind a workspace first");
+    if (species < 0 || species >= sim->S) return rd_fail(RD_ERR_ARG, "bad species");
+    if (axis < 0 || axis > 2) return rd_fail(RD_ERR_ARG, "axis must be 0, 1 or 2");
+    const rd_geometry &G = *sim->g;
+    const int64_t n = axis == 0 ? G.nx : axis == 1 ? G.ny : G.nz;
+    if (i0 < 0 || i0 + 1 >= n)
+        return rd_fail(RD_ERR_ARG, "plane index must satisfy 0 <= i0 < n - 1 along the axis");
+    const int nb = (int)G.nb();
+    const SimLayout &L = sim->L;
+    char *ws = sim->ws;
+    double *part = (double *)(ws + L.part);
+    double *res = (double *)(ws + L.res) + 32;
+    hipStream_t stream = sim->stream;
+    LAUNCHCHK(rd_launch_plane_flux((int)sim->storage, G.B, (const BlockInfo *)(ws + L.info),
+                                   (const uint8_t *)(ws + L.code), sim->field_ptr(sim->cur, species), nb,
+                                   axis, (int)i0, sim->D[species], G.dx, part, stream));
+    LAUNCHCHK(rd_launch_finish_reduce(part, rd_reduce_rows(G.B, nb), 1, (double *)(ws + L.mid), res,
+                                      stream));
+    double h = 0.0;
+    HIPCHK(hipMemcpyAsync(&h, res, sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    *flux = h;
+    return RD_OK;
 }
 
 extern "C" void rd_sim_destroy(rd_sim *sim) { delete sim; }

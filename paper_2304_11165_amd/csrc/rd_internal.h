@@ -92,7 +92,12 @@ struct ReduceArgs {
 // ---- launchers (k_step.hip) -------------------------------------------------
 // storage: 0 fp32, 1 bf16, 2 fp16.  All return a hipError_t as int.
 int rd_launch_step(int storage, int B, const StepArgs &a, void *stream);
-int rd_launch_reduce(int storage, int B, const ReduceArgs &a, int nwg, void *stream);
+// rows of partials written by rd_launch_reduce (one per workgroup of four blocks)
+int rd_reduce_rows(int B, int nb);
+int rd_launch_reduce(int storage, int B, const ReduceArgs &a, void *stream);
+// one FP64 partial per rd_reduce_rows row: flux of field c through plane i0 | i0 + 1
+int rd_launch_plane_flux(int storage, int B, const BlockInfo *info, const uint8_t *code, const void *c,
+                         int nb, int axis, int i0, double D, double dx, double *partial, void *stream);
 // Fixed-order sums of partial[nparts][nlanes] (nlanes <= 16) into out[nlanes]; mid is
 // scratch of RD_FINISH_GROUPS * nlanes doubles.
 #define RD_FINISH_GROUPS 256

@@ -66,6 +66,7 @@ _SIGS = {
     "rd_sim_steps_taken": ([P, P], ci),
     "rd_sim_reduce": ([P, ci, P, P, P], ci),
     "rd_sim_balance": ([P, ci, P], ci),
+    "rd_sim_plane_flux": ([P, ci, ci, i64, P], ci),
     "rd_sim_steady_state": ([P, ci, f64, i64, P, P, P], ci),
     "rd_sim_adjoint": ([P, P, ci, i64, f64, ci, P, P, P], ci),
     "rd_sim_set_species_D": ([P, ci, f64], ci),
@@ -321,6 +322,14 @@ class Sim:
         out = np.zeros(9)
         _check(_lib.rd_sim_balance(self.handle, int(species), _np_ptr(out)), "rd_sim_balance")
         return {"mass": out[0], "inflow": out[1:7].copy(), "uptake": out[7], "react": out[8]}
+
+    def plane_flux(self, species, axis, i0):
+        """FP64 diffusive flux of `species` through the plane between i0 and i0 + 1 along
+        `axis` (0 x, 1 y, 2 z), positive towards +axis."""
+        q = f64()
+        _check(_lib.rd_sim_plane_flux(self.handle, int(species), int(axis), int(i0), ctypes.byref(q)),
+               "rd_sim_plane_flux")
+        return q.value
 
     def steady_state(self, axis, rel_tol=1e-8, max_iters=100000):
         tau, rel, it = f64(), f64(), i64()

@@ -124,10 +124,53 @@ def test_random_tiny_geometries(rd, oracle_mod, seed):
     dt = 1.9 / lam
     init = rng.uniform(0, 1, (S,) + img.shape)
     for B, kernel in ((4, "block"), (8, "block"), (8, "column"), (8, "column_xch")):
-        got, ref, _, _ = _run_both(rd, oracle_mod, img, D, dt, 60, B=B, dx=dx, robin=robin,
-                                   dirichlet=dirichlet, reactions=reactions, init=init,
-                                   kernel=kernel)
+        got, ref, prob, s = _run_both(rd, oracle_mod, img, D, dt, 60, B=B, dx=dx, robin=robin,
+                                      dirichlet=dirichlet, reactions=reactions, init=init,
+                                      kernel=kernel)
         assert np.abs(got - ref).max() < 2e-5, (seed, B, kernel)
+        _check_balance(s, prob, got, S)
+
+
+def _check_balance(s, prob, got, S):
+    """FP64 balance terms of the GPU field equal the oracle's on the same field."""
+    for sp in range(S):
+        b = s.balance(sp)
+        m, infl, up, re = prob.balance(got, sp)
+        assert b["mass"] == pytest.approx(m, rel=1e-10, abs=1e-12)
+        np.testing.assert_allclose(b["inflow"], infl, rtol=1e-9, atol=1e-12)
+        assert b["uptake"] == pytest.approx(up, rel=1e-10, abs=1e-12)
+        assert b["react"] == pytest.approx(re, rel=1e-10, abs=1e-12)
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+def test_balance_dirichlet_every_face_ragged(rd, oracle_mod, storage):
+    """Dirichlet data on all six faces of a box whose edges are 1 mod 8: the inflow of a
+    + face plane alone in its block comes from the neighbouring block."""
+    img, _ = W.boolean_spheres(49, 0.5, 2.0, 4.0, seed=21)
+    img = np.ascontiguousarray(img[:33, :41, :])  # (nz, ny, nx) = (33, 41, 49)
+    rng = np.random.default_rng(21)
+    dirichlet = {(0, f): float(rng.uniform(0.2, 1.0)) for f in range(6)}
+    dirichlet[(1, 1)] = 0.7
+    dirichlet[(1, 5)] = 0.3
+    reactions = [(0, 1, 0.02), (1, -1, 0.01)]
+    robin = {1: 0.05}
+    init = rng.uniform(0, 1, (2,) + img.shape)
+    for B in (4, 8):
+        got, ref, prob, s = _run_both(rd, oracle_mod, img, [1.0, 0.5], 0.1, 40, B=B,
+                                      robin=robin, dirichlet=dirichlet, reactions=reactions,
+                                      init=init, storage=storage, kernel="column" if B == 8 else "block")
+        assert np.all(np.array(s.balance(0)["inflow"]) != 0.0)
+        _check_balance(s, prob, got, 2)
+        # plane fluxes, including planes on block boundaries (i0 = 7, 15: the +axis
+        # neighbour lies in the next block) and the last plane of each axis
+        for axis, n in ((0, img.shape[2]), (1, img.shape[1]), (2, img.shape[0])):
+            for i0 in (0, 3, 7, 8, 15, n // 2, n - 2):
+                for sp in range(2):
+                    want = prob.plane_flux(got[sp], [1.0, 0.5][sp], axis, i0)
+                    assert s.plane_flux(sp, axis, i0) == pytest.approx(want, rel=1e-10, abs=1e-13), \
+                        (B, storage, axis, i0, sp)
+        with pytest.raises(rd.RDError):
+            s.plane_flux(0, 0, img.shape[2] - 1)
 
 
 def test_empty_and_single_voxel(rd, oracle_mod):

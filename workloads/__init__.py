@@ -152,7 +152,7 @@ def gaussian_random_field_volume(n=512, corr_len=12.0, porosity=0.3, seed=2):
     k2 = (kz * kz + ky * ky + kx * kx) * np.float32((2 * math.pi) ** 2)
     spec *= np.exp(-0.5 * np.float32(sigma * sigma) * k2)
     del k2
-    field_ = np.fft.irfftn(spec, s=(n, n, n)).astype(np.float32)
+    field_ = np.fft.irfftn(spec, s=(n, n, n), axes=(0, 1, 2)).astype(np.float32)
     del spec
     thr = np.quantile(field_[:: 2, :: 2, :: 2] if n > 256 else field_, porosity)
     image = (field_ < thr).astype(np.uint8)
