@@ -16,7 +16,8 @@ rounding) and its error against the FP32-storage run; a batched form (per-geomet
 tortuosity of several sphere packings in one set of launches); and the FP64 CPU
 oracle timed on a bounded sample of the headline workload (cpu_baseline).
 
-Modes: --profile (only the timed FP32 loop, for rocprofv3), --copy-calibration (a
+Modes: --profile (only the timed loop of one storage type, FP32 unless --profile-storage,
+for rocprofv3), --copy-calibration (a
 plain 1 GiB device copy, whose FETCH_SIZE / WRITE_SIZE counters calibrate the
 traffic figures).
 """
@@ -56,6 +57,8 @@ def parse():
     p.add_argument("--graph-steps", type=int, default=32)
     p.add_argument("--no-graph", action="store_true", help="direct launches (for profilers)")
     p.add_argument("--profile", action="store_true", help="only the timed FP32 loop")
+    p.add_argument("--profile-storage", default="fp32", choices=["fp32", "bf16", "fp16"],
+                   help="storage type timed by --profile")
     p.add_argument("--copy-calibration", action="store_true")
     p.add_argument("--kernel", default="auto", choices=["auto", "block", "column", "column_xch",
                                                         "persistent"],
@@ -176,9 +179,10 @@ def batched_form(torch, rd, W, count, max_edge, stream):
         "edges": [int(info["n"]) for _, info in geoms_np],
         "seconds": secs,
         "active_voxel_cg_iterations_per_s": voxel_iters / secs,
-        # per iteration: matvec with the p update fused (reads p, r; writes p, Ap) and the
-        # x, r update (reads x, p, r, Ap; writes x, r): 10 FP32 words per active voxel
-        "alg_GBps": voxel_iters * 10 * 4 / secs / 1e9,
+        # per iteration: matvec with the p update fused (reads p, r; writes p) and the
+        # x, r update with A p recomputed (reads x, p, r; writes x, r): 8 FP32 words per
+        # active voxel
+        "alg_GBps": voxel_iters * 8 * 4 / secs / 1e9,
         "tau": [float(x) for x in tau],
         "rel_residual_max": float(max(rel)),
         "iterations": [int(x) for x in it],
@@ -257,7 +261,7 @@ def main():
     stream = torch.cuda.Stream()
     results, fields = {}, {}
     forms = [] if a.profile else [f for f in a.forms.split(",") if f]
-    for storage in ["fp32"] + forms:
+    for storage in [a.profile_storage] if a.profile else ["fp32"] + forms:
         steps = a.steps if storage == "fp32" else min(a.steps, a.form_steps)
         warm = a.warmup if storage == "fp32" else 50
         with torch.cuda.stream(stream):
@@ -316,6 +320,9 @@ def main():
         results[storage]["rel_l2_vs_fp32_storage"] = errs
         del ref
 
+    if a.profile and a.profile_storage != "fp32":
+        print(json.dumps({"profile": results}), flush=True)
+        return
     f32 = results["fp32"]
     kname = step_kernel_name(w.block_edge, f32["launch"], S)
     workload_name = f"soil{n}"

@@ -193,12 +193,21 @@ __global__ __launch_bounds__(256) void k_cg_matvec(CgArgs a)
 // p update never give them another value), so on a free voxel
 //   (A p)_p = n_active * p_p - (((((p_-x + p_+x) + p_-y) + p_+y) + p_-z) + p_+z),
 // and Ap = 0 elsewhere.  Partial (p.Ap, 0) per block in FP64.
-// FUSE: the p update of the previous iteration is applied on the fly, to the block
-// and to its halos: p_new = fma(beta, p, r) from the stored r and p (the p update's
-// own operation, rounded to the storage type), stored into p2 (the caller swaps the
+// The p update of the previous iteration is applied on the fly, to the block and to
+// its halos: p_new = fma(beta, p, r) from the stored r and p (the p update's own
+// operation, rounded to the storage type), stored into p2 (the caller swaps the
 // buffers: neighbouring waves still read the old p); Ap = A p_new.  p_new is 0 where
-// r and p are (inactive and Dirichlet voxels).
-template <typename T, bool FUSE>
+// r and p are (inactive and Dirichlet voxels).  Ap itself is not stored: the update
+// kernel (k_cg_update8) recomputes it from p_new with the same arithmetic (cg_ap8),
+// which moves fewer bytes than writing and reading it back.
+__device__ __forceinline__ float cg_ap8(const float *q, float dn, float up, float pc, unsigned code,
+                                        bool fr)
+{
+    const float sum = ((((q[-1] + q[1]) + q[-10]) + q[10]) + dn) + up;
+    return fr ? fmaf((float)__popc(code & 63u), pc, -sum) : 0.0f;
+}
+
+template <typename T>
 __global__ __launch_bounds__(256) void k_cg_matvec8(CgArgs a)
 {
     __shared__ float tile[4][100];
@@ -226,13 +235,13 @@ __global__ __launch_bounds__(256) void k_cg_matvec8(CgArgs a)
     for (int f = 0; f < 6; ++f) Wf[f] = rec[8 + f];
     typedef typename RawOf<T>::type R;
     const T *rv = (const T *)a.r;
-    R rc[8], rh[6], qc[8], qh[6];  // p (and with FUSE r) raw words
+    R rc[8], rh[6], qc[8], qh[6];  // p and r raw words
     unsigned cd[8];
 #pragma unroll
     for (int z = 0; z < 8; ++z) {
         const bool act = (Wo[z] >> lane) & 1ull;
         rc[z] = ld_raw(pv, base + z * 64 + lane, act);
-        if (FUSE) qc[z] = ld_raw(rv, base + z * 64 + lane, act);
+        qc[z] = ld_raw(rv, base + z * 64 + lane, act);
         cd[z] = act ? (unsigned)a.code[base + z * 64 + lane] : 0u;
     }
     // face halos: lane (u, v) = (lx, ly) reads the neighbour slot across face f
@@ -250,20 +259,19 @@ __global__ __launch_bounds__(256) void k_cg_matvec8(CgArgs a)
         const int n = bi.nbr[f];
         const bool e = (Wf[f] >> lane) & 1ull;
         rh[f] = ld_raw(pv, (int64_t)(n >= 0 ? n : b) * 512 + ns, e);
-        if (FUSE) qh[f] = ld_raw(rv, (int64_t)(n >= 0 ? n : b) * 512 + ns, e);
+        qh[f] = ld_raw(rv, (int64_t)(n >= 0 ? n : b) * 512 + ns, e);
     }
-    const float beta = FUSE ? (float)a.scal[gid * CG_NSCAL + CG_BETA] : 0.0f;
-    // p (FUSE: the updated p, as the p update would have stored it)
+    const float beta = (float)a.scal[gid * CG_NSCAL + CG_BETA];
+    // the updated p, as the p update would have stored it
     auto pval = [&](R praw, R rraw) {
-        const float pv_ = from_raw<T>(praw);
-        return FUSE ? rd_round<T>(fmaf(beta, pv_, from_raw<T>(rraw))) : pv_;
+        return rd_round<T>(fmaf(beta, from_raw<T>(praw), from_raw<T>(rraw)));
     };
     float c[8], side[4];
 #pragma unroll
-    for (int z = 0; z < 8; ++z) c[z] = pval(rc[z], FUSE ? qc[z] : rc[z]);
+    for (int z = 0; z < 8; ++z) c[z] = pval(rc[z], qc[z]);
 #pragma unroll
-    for (int f = 0; f < 4; ++f) side[f] = pval(rh[f], FUSE ? qh[f] : rh[f]);
-    const float zlo = pval(rh[4], FUSE ? qh[4] : rh[4]), zhi = pval(rh[5], FUSE ? qh[5] : rh[5]);
+    for (int f = 0; f < 4; ++f) side[f] = pval(rh[f], qh[f]);
+    const float zlo = pval(rh[4], qh[4]), zhi = pval(rh[5], qh[5]);
 
     const GeomInfo g = a.geom[gid];
     const int gx = bx * 8 + lx, gy = by * 8 + ly;
@@ -293,21 +301,135 @@ __global__ __launch_bounds__(256) void k_cg_matvec8(CgArgs a)
         const float *q = &ts[(ly + 1) * 10 + (lx + 1)];
         const float dn = z == 0 ? zlo : c[z > 0 ? z - 1 : 0];
         const float up = z == 7 ? zhi : c[z < 7 ? z + 1 : 7];
-        const float sum = ((((q[-1] + q[1]) + q[-10]) + q[10]) + dn) + up;
-        const float ap = fr ? fmaf((float)__popc(code & 63u), c[z], -sum) : 0.0f;
+        const float ap = cg_ap8(q, dn, up, c[z], code, fr);
         if (fr) pap += (double)c[z] * (double)ap;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // whole sectors only (Ap and p are read on free voxels and as predicated halos)
-        if (sector_active<T>(Wo[z], lane)) {
-            rd_st_keep((T *)a.ap, base + z * 64 + lane, ap);
-            if (FUSE) rd_st_keep((T *)a.p2, base + z * 64 + lane, c[z]);
-        }
+        // whole sectors only (p is read on active voxels and as predicated halos)
+        if (sector_active<T>(Wo[z], lane)) rd_st_keep((T *)a.p2, base + z * 64 + lane, c[z]);
     }
     pap = wave_sum(pap);
     if (lane == 0) {
         a.partial[(int64_t)b * 2 + 0] = pap;
+        a.partial[(int64_t)b * 2 + 1] = 0.0;
+    }
+}
+
+// x += alpha p, r -= alpha A p on free voxels of live geometries, for 8^3 blocks in the
+// column form of k_cg_matvec8, which does not store A p: it is recomputed here from p
+// and its face halos with the matvec's arithmetic (cg_ap8), so it equals the A p of
+// the p.Ap partial bit for bit.  Whole sectors are stored: inactive slots keep 0 and
+// Dirichlet voxels their values.  Partial (r.r, 0) per block, of r as stored.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_update8(CgArgs a)
+{
+    __shared__ float tile[4][100];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int b = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + wv);
+    if (b >= a.nb) return;
+    const BlockInfo bi = a.info[b];
+    int bx, by, bz, gid;
+    block_pos(bi, &bx, &by, &bz, &gid);
+    if (!geom_live<8>(a, gid)) {
+        if (lane == 0) {
+            a.partial[(int64_t)b * 2 + 0] = 0.0;
+            a.partial[(int64_t)b * 2 + 1] = 0.0;
+        }
+        return;
+    }
+    const T *pv = (const T *)a.p;
+    T *xv = (T *)a.x;
+    T *rv = (T *)a.r;
+    const int64_t base = (int64_t)b * 512;
+    const int lx = lane & 7, ly = lane >> 3;
+    const uint64_t *rec = a.mask + (int64_t)b * 16;
+    uint64_t Wo[8], Wf[6];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) Wo[z] = rec[z];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) Wf[f] = rec[8 + f];
+    typedef typename RawOf<T>::type R;
+    R pc[8], ph[6], xc[8], rc[8];
+    unsigned cd[8];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        const bool act = (Wo[z] >> lane) & 1ull;
+        pc[z] = ld_raw(pv, base + z * 64 + lane, act);
+        xc[z] = ld_raw((const T *)xv, base + z * 64 + lane, act);
+        rc[z] = ld_raw((const T *)rv, base + z * 64 + lane, act);
+        cd[z] = act ? (unsigned)a.code[base + z * 64 + lane] : 0u;
+    }
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        int ns;
+        switch (f) {
+        case 0: ns = (ly * 8 + lx) * 8 + 7; break;
+        case 1: ns = (ly * 8 + lx) * 8 + 0; break;
+        case 2: ns = (ly * 8 + 7) * 8 + lx; break;
+        case 3: ns = (ly * 8 + 0) * 8 + lx; break;
+        case 4: ns = (7 * 8 + ly) * 8 + lx; break;
+        default: ns = (0 * 8 + ly) * 8 + lx; break;
+        }
+        const int n = bi.nbr[f];
+        const bool e = (Wf[f] >> lane) & 1ull;
+        ph[f] = ld_raw(pv, (int64_t)(n >= 0 ? n : b) * 512 + ns, e);
+    }
+    const float alpha = (float)a.scal[gid * CG_NSCAL + CG_ALPHA];
+    float c[8], side[4];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) c[z] = from_raw<T>(pc[z]);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) side[f] = from_raw<T>(ph[f]);
+    const float zlo = from_raw<T>(ph[4]), zhi = from_raw<T>(ph[5]);
+
+    const GeomInfo g = a.geom[gid];
+    const int gx = bx * 8 + lx, gy = by * 8 + ly;
+    const bool bnd = bx == 0 || by == 0 || bz == 0 || bx * 8 + 8 >= g.nx || by * 8 + 8 >= g.ny ||
+                     bz * 8 + 8 >= g.nz;
+    float *ts = tile[wv];
+    double rr = 0.0;
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        ts[(ly + 1) * 10 + (lx + 1)] = c[z];
+        if (ly == z) {
+            ts[(lx + 1) * 10 + 0] = side[0];
+            ts[(lx + 1) * 10 + 9] = side[1];
+            ts[0 * 10 + (lx + 1)] = side[2];
+            ts[9 * 10 + (lx + 1)] = side[3];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const unsigned code = cd[z];
+        unsigned onf = 0u;
+        if (bnd)
+            onf = (gx == 0 ? 1u : 0u) | (gx == g.nx - 1 ? 2u : 0u) | (gy == 0 ? 4u : 0u) |
+                  (gy == g.ny - 1 ? 8u : 0u) | (bz * 8 + z == 0 ? 16u : 0u) |
+                  (bz * 8 + z == g.nz - 1 ? 32u : 0u);
+        const bool fr = (code & 64u) != 0u && (onf & a.dir) == 0u;
+        const float *q = &ts[(ly + 1) * 10 + (lx + 1)];
+        const float dn = z == 0 ? zlo : c[z > 0 ? z - 1 : 0];
+        const float up = z == 7 ? zhi : c[z < 7 ? z + 1 : 7];
+        const float ap = cg_ap8(q, dn, up, c[z], code, fr);
+        const float x0 = from_raw<T>(xc[z]), r0 = from_raw<T>(rc[z]);
+        const float xn = fr ? fmaf(alpha, c[z], x0) : x0;
+        const float rn = fr ? fmaf(-alpha, ap, r0) : r0;
+        if (fr) {
+            const float rs = rd_round<T>(rn);  // as stored
+            rr += (double)rs * (double)rs;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (sector_active<T>(Wo[z], lane)) {
+            rd_st_keep(xv, base + z * 64 + lane, xn);
+            rd_st_keep(rv, base + z * 64 + lane, rn);
+        }
+    }
+    rr = wave_sum(rr);
+    if (lane == 0) {
+        a.partial[(int64_t)b * 2 + 0] = rr;
         a.partial[(int64_t)b * 2 + 1] = 0.0;
     }
 }
@@ -441,7 +563,23 @@ __global__ __launch_bounds__(256) void k_cg_segsum(const double *part, const Geo
     const int lo = geom[g].block0;
     const int hi = g + 1 < ngeom ? geom[g + 1].block0 : nb;
     double s0 = 0.0, s1 = 0.0;
-    for (int i = lo + (int)threadIdx.x; i < hi; i += 256) {
+    // thread t adds rows t, t + 256, ... in that order; eight rows' loads are issued
+    // before their adds, so a long segment is not one load latency per row
+    int i = lo + (int)threadIdx.x;
+    for (; i + 7 * 256 < hi; i += 8 * 256) {
+        double v0[8], v1[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            v0[k] = part[(int64_t)(i + k * 256) * 2 + 0];
+            v1[k] = part[(int64_t)(i + k * 256) * 2 + 1];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            s0 += v0[k];
+            s1 += v1[k];
+        }
+    }
+    for (; i < hi; i += 256) {
         s0 += part[(int64_t)i * 2 + 0];
         s1 += part[(int64_t)i * 2 + 1];
     }
@@ -505,27 +643,27 @@ int cg_launch_residual(int storage, int B, const CgArgs &a, int store, void *str
 }
 int cg_launch_matvec(int storage, int B, const CgArgs &a, void *stream)
 {
-    if (B == 8) {  // column form, four blocks per workgroup
-        const dim3 grid((unsigned)std::max(1, (a.nb + 3) / 4));
-        hipStream_t st = (hipStream_t)stream;
-        if (storage == 0) hipLaunchKernelGGL((k_cg_matvec8<float, false>), grid, dim3(256), 0, st, a);
-        else if (storage == 1) hipLaunchKernelGGL((k_cg_matvec8<bf16_t, false>), grid, dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((k_cg_matvec8<_Float16, false>), grid, dim3(256), 0, st, a);
-        return (int)hipGetLastError();
-    }
     CG_DISPATCH(storage, B, k_cg_matvec, grid_for(B, a.nb), stream, a);
 }
 int cg_launch_matvec_fused(int storage, const CgArgs &a, void *stream)
 {
     const dim3 grid((unsigned)std::max(1, (a.nb + 3) / 4));
     hipStream_t st = (hipStream_t)stream;
-    if (storage == 0) hipLaunchKernelGGL((k_cg_matvec8<float, true>), grid, dim3(256), 0, st, a);
-    else if (storage == 1) hipLaunchKernelGGL((k_cg_matvec8<bf16_t, true>), grid, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((k_cg_matvec8<_Float16, true>), grid, dim3(256), 0, st, a);
+    if (storage == 0) hipLaunchKernelGGL((k_cg_matvec8<float>), grid, dim3(256), 0, st, a);
+    else if (storage == 1) hipLaunchKernelGGL((k_cg_matvec8<bf16_t>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_cg_matvec8<_Float16>), grid, dim3(256), 0, st, a);
     return (int)hipGetLastError();
 }
 int cg_launch_update(int storage, int B, const CgArgs &a, void *stream)
 {
+    if (B == 8) {  // column form with A p recomputed (the fused matvec does not store it)
+        const dim3 grid((unsigned)std::max(1, (a.nb + 3) / 4));
+        hipStream_t st = (hipStream_t)stream;
+        if (storage == 0) hipLaunchKernelGGL((k_cg_update8<float>), grid, dim3(256), 0, st, a);
+        else if (storage == 1) hipLaunchKernelGGL((k_cg_update8<bf16_t>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_cg_update8<_Float16>), grid, dim3(256), 0, st, a);
+        return (int)hipGetLastError();
+    }
     CG_DISPATCH(storage, B, k_cg_update, grid_for(B, a.nb), stream, a);
 }
 int cg_launch_pupdate(int storage, int B, const CgArgs &a, void *stream)

@@ -28,7 +28,7 @@ struct CgArgs {
     int nb;
     int ngeom;
     uint32_t dir;          // Dirichlet faces (inlet | outlet)
-    void *x, *r, *p, *ap;  // storage type T, nb * B^3 each
+    void *x, *r, *p, *ap;  // storage type T, nb * B^3 each (ap: B = 4 only)
     void *p2;              // second p buffer (B = 8: the fused p update writes here)
     double *partial;       // [nb][2]
     double *scal;          // [ngeom][CG_NSCAL]
@@ -36,9 +36,11 @@ struct CgArgs {
 
 int cg_launch_residual(int storage, int B, const CgArgs &a, int store, void *stream);
 int cg_launch_matvec(int storage, int B, const CgArgs &a, void *stream);
-// B = 8: p2 = r + beta p (per live geometry, rounded to the storage type), Ap = A p2,
-// partial (p2.Ap, 0); the caller then swaps p and p2.
+// B = 8: p2 = r + beta p (per live geometry, rounded to the storage type) and the
+// partial (p2.A p2, 0); A p2 is not stored.  The caller then swaps p and p2.
 int cg_launch_matvec_fused(int storage, const CgArgs &a, void *stream);
+// x += alpha p, r -= alpha A p, partial (r.r, 0); B = 4 reads the stored A p, B = 8
+// recomputes it from p.
 int cg_launch_update(int storage, int B, const CgArgs &a, void *stream);
 int cg_launch_pupdate(int storage, int B, const CgArgs &a, void *stream);
 int cg_launch_flux(int storage, int B, const CgArgs &a, int inlet_face, void *stream);
