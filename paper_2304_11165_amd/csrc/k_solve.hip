@@ -90,6 +90,16 @@ __device__ __forceinline__ float lap_at(const float *ts, int t, unsigned nbm)
     return lap;
 }
 
+// (A p)_p on a free voxel of an 8^3 column kernel: n_active p_p minus the sum of the
+// six neighbour values (0 where inactive) in the order -x, +x, -y, +y, -z, +z; q points
+// at p_p in the one-plane LDS tile, dn / up are the -z / +z values.  0 elsewhere.
+__device__ __forceinline__ float cg_ap8(const float *q, float dn, float up, float pc, unsigned code,
+                                        bool fr)
+{
+    const float sum = ((((q[-1] + q[1]) + q[-10]) + q[10]) + dn) + up;
+    return fr ? fmaf((float)__popc(code & 63u), pc, -sum) : 0.0f;
+}
+
 template <int B>
 __device__ __forceinline__ bool geom_live(const CgArgs &a, int gid)
 {
@@ -142,6 +152,122 @@ __global__ __launch_bounds__(256) void k_cg_residual(CgArgs a, int store)
         }
     }
     block_sum2<B>(rr, bb, a.partial, b, valid);
+}
+
+// The same residual for 8^3 blocks in the column form of k_cg_matvec8 (one wave per
+// block, four per workgroup): r = sum of the active neighbours' x - n_active x_p, in
+// the matvec's order; b_p (only in blocks on a Dirichlet face) adds the neighbours that
+// lie on a Dirichlet face plane, in face order.  Whole sectors are stored.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_residual8(CgArgs a, int store)
+{
+    __shared__ float tile[4][100];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int b = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + wv);
+    if (b >= a.nb) return;
+    const BlockInfo bi = a.info[b];
+    int bx, by, bz, gid;
+    block_pos(bi, &bx, &by, &bz, &gid);
+    const T *xv = (const T *)a.x;
+    const int64_t base = (int64_t)b * 512;
+    const int lx = lane & 7, ly = lane >> 3;
+    const uint64_t *rec = a.mask + (int64_t)b * 16;
+    uint64_t Wo[8], Wf[6];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) Wo[z] = rec[z];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) Wf[f] = rec[8 + f];
+    typedef typename RawOf<T>::type R;
+    R xc[8], xh[6];
+    unsigned cd[8];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        const bool act = (Wo[z] >> lane) & 1ull;
+        xc[z] = ld_raw(xv, base + z * 64 + lane, act);
+        cd[z] = act ? (unsigned)a.code[base + z * 64 + lane] : 0u;
+    }
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        int ns;
+        switch (f) {
+        case 0: ns = (ly * 8 + lx) * 8 + 7; break;
+        case 1: ns = (ly * 8 + lx) * 8 + 0; break;
+        case 2: ns = (ly * 8 + 7) * 8 + lx; break;
+        case 3: ns = (ly * 8 + 0) * 8 + lx; break;
+        case 4: ns = (7 * 8 + ly) * 8 + lx; break;
+        default: ns = (0 * 8 + ly) * 8 + lx; break;
+        }
+        const int n = bi.nbr[f];
+        const bool e = (Wf[f] >> lane) & 1ull;
+        xh[f] = ld_raw(xv, (int64_t)(n >= 0 ? n : b) * 512 + ns, e);
+    }
+    float c[8], side[4];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) c[z] = from_raw<T>(xc[z]);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) side[f] = from_raw<T>(xh[f]);
+    const float zlo = from_raw<T>(xh[4]), zhi = from_raw<T>(xh[5]);
+
+    const GeomInfo g = a.geom[gid];
+    const int gx = bx * 8 + lx, gy = by * 8 + ly;
+    const bool bnd = bx == 0 || by == 0 || bz == 0 || bx * 8 + 8 >= g.nx || by * 8 + 8 >= g.ny ||
+                     bz * 8 + 8 >= g.nz;
+    float *ts = tile[wv];
+    double rr = 0.0, bb = 0.0;
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        ts[(ly + 1) * 10 + (lx + 1)] = c[z];
+        if (ly == z) {
+            ts[(lx + 1) * 10 + 0] = side[0];
+            ts[(lx + 1) * 10 + 9] = side[1];
+            ts[0 * 10 + (lx + 1)] = side[2];
+            ts[9 * 10 + (lx + 1)] = side[3];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const unsigned code = cd[z];
+        const int gz = bz * 8 + z;
+        unsigned onf = 0u;
+        if (bnd)
+            onf = (gx == 0 ? 1u : 0u) | (gx == g.nx - 1 ? 2u : 0u) | (gy == 0 ? 4u : 0u) |
+                  (gy == g.ny - 1 ? 8u : 0u) | (gz == 0 ? 16u : 0u) | (gz == g.nz - 1 ? 32u : 0u);
+        const bool fr = (code & 64u) != 0u && (onf & a.dir) == 0u;
+        const float *q = &ts[(ly + 1) * 10 + (lx + 1)];
+        const float dn = z == 0 ? zlo : c[z > 0 ? z - 1 : 0];
+        const float up = z == 7 ? zhi : c[z < 7 ? z + 1 : 7];
+        const float r = fr ? -cg_ap8(q, dn, up, c[z], code, fr) : 0.0f;
+        if (fr) {
+            rr += (double)r * (double)r;
+            if (bnd) {  // b_p: active neighbours on a Dirichlet face plane
+                const float nv[6] = {q[-1], q[1], q[-10], q[10], dn, up};
+                double bp = 0.0;
+#pragma unroll
+                for (int d = 0; d < 6; ++d) {
+                    const int ex = d == 0 ? -1 : d == 1 ? 1 : 0;
+                    const int ey = d == 2 ? -1 : d == 3 ? 1 : 0;
+                    const int ez = d == 4 ? -1 : d == 5 ? 1 : 0;
+                    if (((code >> d) & 1u) &&
+                        on_dirichlet(a.dir, gx + ex, gy + ey, gz + ez, g.nx, g.ny, g.nz))
+                        bp += (double)nv[d];
+                }
+                bb += bp * bp;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (store && sector_active<T>(Wo[z], lane)) {
+            rd_st_keep((T *)a.r, base + z * 64 + lane, r);
+            rd_st_keep((T *)a.p, base + z * 64 + lane, r);
+        }
+    }
+    rr = wave_sum(rr);
+    bb = wave_sum(bb);
+    if (lane == 0) {
+        a.partial[(int64_t)b * 2 + 0] = rr;
+        a.partial[(int64_t)b * 2 + 1] = bb;
+    }
 }
 
 // Ap = A p on live geometries, partial (p.Ap, 0)
@@ -200,12 +326,6 @@ __global__ __launch_bounds__(256) void k_cg_matvec(CgArgs a)
 // r and p are (inactive and Dirichlet voxels).  Ap itself is not stored: the update
 // kernel (k_cg_update8) recomputes it from p_new with the same arithmetic (cg_ap8),
 // which moves fewer bytes than writing and reading it back.
-__device__ __forceinline__ float cg_ap8(const float *q, float dn, float up, float pc, unsigned code,
-                                        bool fr)
-{
-    const float sum = ((((q[-1] + q[1]) + q[-10]) + q[10]) + dn) + up;
-    return fr ? fmaf((float)__popc(code & 63u), pc, -sum) : 0.0f;
-}
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_cg_matvec8(CgArgs a)
@@ -639,6 +759,14 @@ static dim3 grid_for(int B, int nb)
 
 int cg_launch_residual(int storage, int B, const CgArgs &a, int store, void *stream)
 {
+    if (B == 8) {  // column form
+        const dim3 grid((unsigned)std::max(1, (a.nb + 3) / 4));
+        hipStream_t st = (hipStream_t)stream;
+        if (storage == 0) hipLaunchKernelGGL((k_cg_residual8<float>), grid, dim3(256), 0, st, a, store);
+        else if (storage == 1) hipLaunchKernelGGL((k_cg_residual8<bf16_t>), grid, dim3(256), 0, st, a, store);
+        else hipLaunchKernelGGL((k_cg_residual8<_Float16>), grid, dim3(256), 0, st, a, store);
+        return (int)hipGetLastError();
+    }
     CG_DISPATCH(storage, B, k_cg_residual, grid_for(B, a.nb), stream, a, store);
 }
 int cg_launch_matvec(int storage, int B, const CgArgs &a, void *stream)

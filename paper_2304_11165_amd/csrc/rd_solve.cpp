@@ -501,9 +501,15 @@ extern "C" rd_status rd_batch_tortuosity(rd_batch *b, int axis, double rel_tol, 
         std::vector<rd_status> st(n, RD_OK);
         std::vector<char> perc(n, 0);
         const int nt = (int)std::max(1u, std::min<unsigned>((unsigned)n, std::min(16u, std::thread::hardware_concurrency())));
+        // largest geometries first (the labelling time grows with the slot count)
+        std::vector<int> order(n);
+        for (int i = 0; i < n; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int u, int v) { return b->geoms[u]->nb() > b->geoms[v]->nb(); });
         std::atomic<int> next{0};
         auto work = [&]() {
-            for (int i = next++; i < n; i = next++) {
+            for (int k = next++; k < n; k = next++) {
+                const int i = order[k];
                 bool pc = false;
                 st[i] = initial_guess(*b->geoms[i], axis, x0[i], &pc);
                 perc[i] = pc ? 1 : 0;
