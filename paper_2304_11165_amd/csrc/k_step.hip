@@ -349,10 +349,15 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
     unsigned cd[8];
 #pragma unroll
     for (int z = 0; z < 8; ++z) {
-        const bool act = (Wo[z] >> lane) & 1ull;
+        // the plane's loads under one predicate (0 where the voxel is inactive)
 #pragma unroll
-        for (int s = 0; s < S; ++s) rc[s][z] = ld_raw(cin, s * a.sstride + base + z * 64 + lane, act);
-        cd[z] = act ? (unsigned)a.code[base + z * 64 + lane] : 0u;
+        for (int s = 0; s < S; ++s) rc[s][z] = (R)0;
+        cd[z] = 0u;
+        if (lane_bit(Wo[z])) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) rc[s][z] = ld_raw(cin, s * a.sstride + base + z * 64 + lane);
+            cd[z] = (unsigned)a.code[base + z * 64 + lane];
+        }
     }
     // face halos, one value per lane and face: lane (u, v) = (lx, ly) reads the
     // neighbour slot across face f at face coordinates (u, v); a face bit is set only
@@ -369,10 +374,13 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
         default: ns = (0 * 8 + ly) * 8 + lx; break; // (x=u, y=v, z=0)
         }
         const int n = nbr[f];
-        const bool e = ((Wf[f] >> lane) & 1ull) && !(f == 0 && xm_in) && !(f == 1 && xp_in);
         const int64_t hb = (int64_t)(n >= 0 ? n : b) * 512 + ns;
 #pragma unroll
-        for (int s = 0; s < S; ++s) rh[f][s] = ld_raw(cin, s * a.sstride + hb, e);
+        for (int s = 0; s < S; ++s) rh[f][s] = (R)0;
+        if (lane_bit((f == 0 && xm_in) || (f == 1 && xp_in) ? 0ull : Wf[f])) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) rh[f][s] = ld_raw(cin, s * a.sstride + hb);
+        }
     }
     // all loads are issued; convert to FP32
     float c[S][8], side[4][S], zlo[S], zhi[S];
@@ -455,7 +463,7 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         // whole sectors only; an inactive slot of an active sector stores its 0 again
-        if (sector_active<T>(Wo[z], lane)) {
+        if (lane_bit(sector_lanes<T>(Wo[z]))) {
             const uint32_t h = voxel_bits(a, key, voxel_id(g, gx, gy, gz));
 #pragma unroll
             for (int s = 0; s < S; ++s) store_val(a, cout, s, s * a.sstride + base + z * 64 + lane, h, res[s]);

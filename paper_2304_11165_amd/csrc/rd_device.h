@@ -73,6 +73,13 @@ __device__ __forceinline__ uint32_t ld_raw(const _Float16 *p, int64_t i, bool pr
 {
     return pred ? (uint32_t)__builtin_bit_cast(uint16_t, p[i]) : 0u;
 }
+// unpredicated forms, for several loads under one predicate
+__device__ __forceinline__ float ld_raw(const float *p, int64_t i) { return p[i]; }
+__device__ __forceinline__ uint32_t ld_raw(const bf16_t *p, int64_t i) { return (uint32_t)p[i].bits; }
+__device__ __forceinline__ uint32_t ld_raw(const _Float16 *p, int64_t i)
+{
+    return (uint32_t)__builtin_bit_cast(uint16_t, p[i]);
+}
 template <typename T> struct RawOf { typedef uint32_t type; };
 template <> struct RawOf<float> { typedef float type; };
 
@@ -109,6 +116,26 @@ __device__ __forceinline__ bool sector_active(uint64_t W, int bit)
     static_assert(V >= 1 && (V & (V - 1)) == 0, "sector of 1..64 slots");
     if constexpr (V == 64) return W != 0ull;
     else return ((W >> (bit & ~(V - 1))) & ((1ull << V) - 1ull)) != 0ull;
+}
+
+// Wave-level forms for the one-wave-per-block kernels, where slot bit l of a plane
+// word belongs to lane l and the word is wave-uniform: lane_bit gives lane l bit l of
+// W (the word becomes the execution mask; no per-lane shift), sector_lanes the
+// uniform mask of the lanes whose sector holds an active slot (scalar ops only).
+__device__ __forceinline__ bool lane_bit(uint64_t W) { return __builtin_amdgcn_inverse_ballot_w64(W); }
+template <typename T>
+__device__ __forceinline__ uint64_t sector_lanes(uint64_t W)
+{
+    constexpr int V = RD_STORE_SECTOR / (int)sizeof(T) < 64 ? RD_STORE_SECTOR / (int)sizeof(T) : 64;
+    if constexpr (V == 64) {
+        return W != 0ull ? ~0ull : 0ull;
+    } else {
+        constexpr uint64_t ONE = (1ull << V) - 1ull;
+        uint64_t m = 0ull;
+#pragma unroll
+        for (int s = 0; s < 64; s += V) m |= ((W >> s) & ONE) != 0ull ? ONE << s : 0ull;
+        return m;
+    }
 }
 
 // ---- stochastic rounding --------------------------------------------------
