@@ -52,7 +52,10 @@ def parse():
     p.add_argument("--steady-size", type=int, default=1024, help="edge of the foam volume")
     p.add_argument("--steady-forms", default="fp32", help="storage types of the steady form")
     p.add_argument("--steady-tol", type=float, default=1e-6)
-    p.add_argument("--cpu-steps", type=int, default=4, help="oracle steps in the CPU sample")
+    p.add_argument("--cpu-steps", type=int, default=0,
+                   help="oracle steps in the CPU sample (0: as many as fit in --cpu-seconds)")
+    p.add_argument("--cpu-seconds", type=float, default=12.0,
+                   help="target length of the CPU sample when --cpu-steps is 0")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--graph-steps", type=int, default=32)
     p.add_argument("--no-graph", action="store_true", help="direct launches (for profilers)")
@@ -382,14 +385,19 @@ def main():
         c0 = prob.initial()
         prob.run(c0, w.dt, 1)  # page in
         t0 = time.perf_counter()
-        prob.run(c0, w.dt, a.cpu_steps)
+        prob.run(c0, w.dt, 2)  # sizes the sample
+        done = a.cpu_steps
+        if done <= 0:
+            done = max(2, min(5000, int(a.cpu_seconds / ((time.perf_counter() - t0) / 2))))
+        t0 = time.perf_counter()
+        prob.run(c0, w.dt, done)
         secs = time.perf_counter() - t0
         out["cpu_baseline"] = {
-            "value": n_active * a.cpu_steps / secs,
+            "value": n_active * done / secs,
             "unit": "active-voxel updates/s",
             "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"{a.cpu_steps} FP64 steps of the same {n}^3 two-species workload on the "
+            "sample": f"{done} FP64 steps of the same {n}^3 two-species workload on the "
                       f"dense masked grid ({secs:.1f} s)",
         }
         log(f"cpu oracle: {out['cpu_baseline']['value']:.3e} upd/s on {oracle.num_threads()} threads")
