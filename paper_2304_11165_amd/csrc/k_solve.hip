@@ -732,6 +732,136 @@ __global__ __launch_bounds__(256) void k_cg_segsum(const double *part, const Geo
 }
 
 
+// ---- initial guess of the unit-drop problem: 6-connected clusters on the GPU ----
+// Lock-free union-find over the slots, after the hooking and pointer-jumping scheme of
+// ECL-CC (Jaiganesh and Burtscher, 2018): par[i] starts at i; every active voxel unites
+// with its active +x, +y, +z neighbours by hooking the larger of the two roots under
+// the smaller with a compare-and-swap.  Every parent index is therefore below its
+// child's, each chain strictly decreases (every loop ends), and each cluster ends up
+// rooted at its smallest slot index whatever the order of the unions.  All accesses to
+// par while unions run are device-scope atomics, so workgroups on different XCDs agree
+// on one order of updates per slot.
+__device__ __forceinline__ uint32_t uf_load(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t uf_find(uint32_t *par, uint32_t x)
+{
+    uint32_t cur = uf_load(par + x);
+    if (cur == x) return x;
+    uint32_t prev = x, next;
+    while (cur > (next = uf_load(par + cur))) {
+        atomicMin(par + prev, next);  // path halving: a closer ancestor (a smaller index)
+        prev = cur;
+        cur = next;
+    }
+    return cur;
+}
+
+__device__ __forceinline__ void uf_unite(uint32_t *par, uint32_t a, uint32_t b)
+{
+    uint32_t ra = uf_find(par, a), rb = uf_find(par, b);
+    while (ra != rb) {
+        if (ra < rb) {
+            const uint32_t t = ra;
+            ra = rb;
+            rb = t;
+        }
+        const uint32_t old = atomicCAS(par + ra, ra, rb);  // hook ra under rb if ra is a root
+        if (old == ra) return;
+        ra = old;  // ra was hooked meanwhile: go on from its parent (ra + rb decreases)
+    }
+}
+
+__global__ __launch_bounds__(256) void k_lab_init(uint32_t *par, int64_t nslots)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < nslots) par[i] = (uint32_t)i;
+}
+
+// every active slot unites with its active +x, +y, +z neighbours (each pair once)
+template <int B>
+__global__ __launch_bounds__(256) void k_lab_unite(const BlockInfo *info, const uint8_t *code,
+                                                   int64_t nslots, uint32_t *par)
+{
+    constexpr int NS = B * B * B;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nslots) return;
+    const unsigned cd = code[i];
+    if (!(cd & 64u)) return;
+    const int64_t b = i / NS;
+    const int slot = (int)(i % NS);
+    const int lc[3] = {slot % B, (slot / B) % B, slot / (B * B)};
+    const int stride[3] = {1, B, B * B};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (!((cd >> (2 * d + 1)) & 1u)) continue;  // active neighbour in the box: its block exists
+        const int64_t j = lc[d] < B - 1 ? i + stride[d]
+                                        : (int64_t)info[b].nbr[2 * d + 1] * NS + slot - (B - 1) * stride[d];
+        uf_unite(par, (uint32_t)i, (uint32_t)j);
+    }
+}
+
+// coordinate of slot i along `axis` and the extent of its geometry along it
+template <int B>
+__device__ __forceinline__ void lab_coord(const BlockInfo *info, const GeomInfo *geom, int64_t i, int axis,
+                                          int *c, int *n, int *gid)
+{
+    constexpr int NS = B * B * B;
+    const int slot = (int)(i % NS);
+    int bx, by, bz;
+    block_pos(info[i / NS], &bx, &by, &bz, gid);
+    const GeomInfo g = geom[*gid];
+    *c = axis == 0 ? bx * B + slot % B : axis == 1 ? by * B + (slot / B) % B : bz * B + slot / (B * B);
+    *n = axis == 0 ? g.nx : axis == 1 ? g.ny : g.nz;
+}
+
+// par[i] = root of i (active slots); flags of the roots whose cluster touches the
+// inlet plane (fin) or the outlet plane (fout)
+template <int B>
+__global__ __launch_bounds__(256) void k_lab_touch(const BlockInfo *info, const uint8_t *code,
+                                                   const GeomInfo *geom, int64_t nslots, int axis,
+                                                   uint32_t *par, uint8_t *fin, uint8_t *fout)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nslots || !(code[i] & 64u)) return;
+    const uint32_t r = uf_find(par, (uint32_t)i);
+    __hip_atomic_store(par + i, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int c, n, gid;
+    lab_coord<B>(info, geom, i, axis, &c, &n, &gid);
+    if (c == 0) fin[r] = 1;  // every writer stores the same byte value
+    if (c == n - 1) fout[r] = 1;
+}
+
+// x on every slot: the inlet plane 1, the outlet plane 0; inside, the linear ramp
+// 1 - c/(n-1) on clusters touching both planes, 1 on clusters touching only the inlet
+// (their exact solution), 0 on the others (exact too: a floating cluster's residual
+// is zero, so CG never moves it); inactive slots 0.  perc[g] = 1 when a cluster of
+// geometry g touches both planes.
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_lab_guess(const BlockInfo *info, const uint8_t *code,
+                                                   const GeomInfo *geom, int64_t nslots, int axis,
+                                                   const uint32_t *par, const uint8_t *fin,
+                                                   const uint8_t *fout, T *x, uint32_t *perc)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nslots) return;
+    float v = 0.0f;
+    if (code[i] & 64u) {
+        int c, n, gid;
+        lab_coord<B>(info, geom, i, axis, &c, &n, &gid);
+        const uint32_t r = par[i];
+        const int t = (int)fin[r] | ((int)fout[r] << 1);
+        if (c == 0) v = 1.0f;
+        else if (c == n - 1) v = 0.0f;
+        else if (t == 3) v = 1.0f - (float)c / (float)(n - 1);
+        else v = t == 1 ? 1.0f : 0.0f;
+        if (t == 3) perc[gid] = 1u;
+    }
+    rd_st_keep(x, i, v);
+}
+
 template <int B>
 int groups(int nb) { return (nb + Cfg<B>::BPW - 1) / Cfg<B>::BPW; }
 
@@ -801,6 +931,41 @@ int cg_launch_pupdate(int storage, int B, const CgArgs &a, void *stream)
 int cg_launch_flux(int storage, int B, const CgArgs &a, int inlet_face, void *stream)
 {
     CG_DISPATCH(storage, B, k_cg_flux, grid_for(B, a.nb), stream, a, inlet_face);
+}
+int cg_launch_initial_guess(int storage, int B, const CgArgs &a, int axis, int64_t nslots, uint32_t *par,
+                            uint8_t *flags, uint32_t *perc, void *stream)
+{
+    if (nslots <= 0) return 0;
+    hipStream_t st = (hipStream_t)stream;
+    const dim3 grid((unsigned)((nslots + 255) / 256));
+    uint8_t *fin = flags, *fout = flags + nslots;
+    hipLaunchKernelGGL(k_lab_init, grid, dim3(256), 0, st, par, nslots);
+    if (B == 8) {
+        hipLaunchKernelGGL(k_lab_unite<8>, grid, dim3(256), 0, st, a.info, a.code, nslots, par);
+        hipLaunchKernelGGL(k_lab_touch<8>, grid, dim3(256), 0, st, a.info, a.code, a.geom, nslots, axis, par, fin, fout);
+        if (storage == 0)
+            hipLaunchKernelGGL((k_lab_guess<float, 8>), grid, dim3(256), 0, st, a.info, a.code, a.geom, nslots, axis,
+                               par, fin, fout, (float *)a.x, perc);
+        else if (storage == 1)
+            hipLaunchKernelGGL((k_lab_guess<bf16_t, 8>), grid, dim3(256), 0, st, a.info, a.code, a.geom, nslots, axis,
+                               par, fin, fout, (bf16_t *)a.x, perc);
+        else
+            hipLaunchKernelGGL((k_lab_guess<_Float16, 8>), grid, dim3(256), 0, st, a.info, a.code, a.geom, nslots, axis,
+                               par, fin, fout, (_Float16 *)a.x, perc);
+    } else {
+        hipLaunchKernelGGL(k_lab_unite<4>, grid, dim3(256), 0, st, a.info, a.code, nslots, par);
+        hipLaunchKernelGGL(k_lab_touch<4>, grid, dim3(256), 0, st, a.info, a.code, a.geom, nslots, axis, par, fin, fout);
+        if (storage == 0)
+            hipLaunchKernelGGL((k_lab_guess<float, 4>), grid, dim3(256), 0, st, a.info, a.code, a.geom, nslots, axis,
+                               par, fin, fout, (float *)a.x, perc);
+        else if (storage == 1)
+            hipLaunchKernelGGL((k_lab_guess<bf16_t, 4>), grid, dim3(256), 0, st, a.info, a.code, a.geom, nslots, axis,
+                               par, fin, fout, (bf16_t *)a.x, perc);
+        else
+            hipLaunchKernelGGL((k_lab_guess<_Float16, 4>), grid, dim3(256), 0, st, a.info, a.code, a.geom, nslots, axis,
+                               par, fin, fout, (_Float16 *)a.x, perc);
+    }
+    return (int)hipGetLastError();
 }
 int cg_launch_segsum(const CgArgs &a, int slot0, int slot1, int mode, void *stream)
 {

@@ -11,8 +11,6 @@
 #include <string.h>
 
 #include <algorithm>
-#include <atomic>
-#include <thread>
 #include <limits>
 #include <new>
 #include <vector>
@@ -40,133 +38,30 @@ struct CgOut {
 constexpr int CHECK_EVERY = 25;  // iterations between true-residual checks
 constexpr int STALL_CHECKS = 8;  // stop after this many checks without a 10% gain
 
-// ---- host labelling of 6-connected active clusters ------------------------
-// Union-find over the active slots (index b * B^3 + slot) of the block grid.
-struct DSU {
-    std::vector<uint32_t> p;
-    uint32_t find(uint32_t x)
-    {
-        while (p[x] != x) {
-            p[x] = p[p[x]];
-            x = p[x];
-        }
-        return x;
-    }
-    void unite(uint32_t a, uint32_t b)
-    {
-        a = find(a);
-        b = find(b);
-        if (a != b) p[a < b ? b : a] = a < b ? a : b;
-    }
-};
-
-inline bool slot_active(const rd_geometry &G, int64_t b, int slot)
+// Initial guess on the GPU (cg_launch_initial_guess).  Its scratch lives in solver
+// vectors that CG has not used yet: the parent array in the Ap and second-p buffers,
+// which are adjacent in every workspace layout (together at least 4 bytes per slot:
+// `pair_bytes` from the start of Ap to the end of the second p), the cluster flags in
+// r (`r_bytes`, at least 2 bytes per slot, rounded up to 256), the per-geometry
+// percolation flags in the scalar area.
+rd_status gpu_initial_guess(const CgArgs &a, int storage, int B, int axis, int64_t nslots, size_t pair_bytes,
+                            size_t r_bytes, hipStream_t st, std::vector<char> &perc)
 {
-    const uint64_t *rec = &G.mask[(size_t)b * mask_words(G.B)];
-    return G.B == 8 ? (rec[slot >> 6] >> (slot & 63)) & 1u : (rec[0] >> slot) & 1u;
-}
-
-// Initial guess of the unit-drop steady state along `axis`, in block-major FP32:
-// clusters touching both Dirichlet planes get the linear ramp 1 - c/(n-1); clusters
-// touching only the inlet plane get 1 (their exact solution), all other clusters 0
-// (exact too: a floating cluster's residual is then exactly zero and CG never moves
-// it).  Dirichlet voxels hold 1 (inlet) and 0 (outlet).  Returns whether any
-// cluster touches both planes (otherwise the geometry does not percolate).
-rd_status initial_guess(const rd_geometry &G, int axis, std::vector<float> &x, bool *percolates)
-{
-    const int B = G.B, NS = B * B * B;
-    const int64_t nb = G.nb();
-    const int64_t nslots = nb * NS;
+    perc.assign((size_t)a.ngeom, 0);
+    if (nslots <= 0) return RD_OK;
     if (nslots >= (int64_t)UINT32_MAX) return rd_fail(RD_ERR_SHAPE, "too many slots to label");
-    DSU d;
-    try {
-        d.p.resize((size_t)nslots);
-        x.assign((size_t)nslots, 0.0f);
-    } catch (const std::bad_alloc &) {
-        return rd_fail(RD_ERR_ARG, "out of host memory for labelling");
-    }
-    for (int64_t i = 0; i < nslots; ++i) d.p[(size_t)i] = (uint32_t)i;
-    for (int64_t b = 0; b < nb; ++b) {
-        const BlockInfo &bi = G.info[b];
-        for (int slot = 0; slot < NS; ++slot) {
-            if (!slot_active(G, b, slot)) continue;
-            const int lx = slot % B, ly = (slot / B) % B, lz = slot / (B * B);
-            const uint32_t me = (uint32_t)(b * NS + slot);
-            // +x, +y, +z neighbours (each pair is visited once)
-            const int lc[3] = {lx, ly, lz};
-            for (int a = 0; a < 3; ++a) {
-                int64_t nbk = b;
-                int ns;
-                if (lc[a] < B - 1) {
-                    ns = slot + (a == 0 ? 1 : a == 1 ? B : B * B);
-                } else {
-                    nbk = bi.nbr[2 * a + 1];
-                    if (nbk < 0) continue;
-                    ns = slot - (B - 1) * (a == 0 ? 1 : a == 1 ? B : B * B);
-                }
-                if (slot_active(G, nbk, ns)) d.unite(me, (uint32_t)(nbk * NS + ns));
-            }
-        }
-    }
-    const int64_t ext[3] = {G.nx, G.ny, G.nz};
-    const int64_t n = ext[axis];
-    std::vector<uint8_t> touch((size_t)nslots, 0);  // bit 0 inlet, bit 1 outlet (on roots)
-    auto coord = [&](int64_t b, int slot, int a) {
-        const BlockInfo &bi = G.info[b];
-        const int64_t bc = a == 0 ? (bi.xy & 0xffff) : a == 1 ? ((bi.xy >> 16) & 0xffff) : (bi.zg & 0xffff);
-        const int l = a == 0 ? slot % B : a == 1 ? (slot / B) % B : slot / (B * B);
-        return bc * B + l;
-    };
-    for (int64_t b = 0; b < nb; ++b)
-        for (int slot = 0; slot < NS; ++slot) {
-            if (!slot_active(G, b, slot)) continue;
-            const int64_t c = coord(b, slot, axis);
-            const uint32_t r = d.find((uint32_t)(b * NS + slot));
-            if (c == 0) touch[r] |= 1;
-            if (c == n - 1) touch[r] |= 2;
-        }
-    bool perc = false;
-    for (int64_t b = 0; b < nb; ++b)
-        for (int slot = 0; slot < NS; ++slot) {
-            if (!slot_active(G, b, slot)) continue;
-            const int64_t c = coord(b, slot, axis);
-            const uint8_t t = touch[d.find((uint32_t)(b * NS + slot))];
-            float v;
-            if (c == 0) v = 1.0f;
-            else if (c == n - 1) v = 0.0f;
-            else if (t == 3) v = 1.0f - (float)c / (float)(n - 1);
-            else v = t == 1 ? 1.0f : 0.0f;
-            if (t == 3) perc = true;
-            x[(size_t)(b * NS + slot)] = v;
-        }
-    *percolates = perc;
-    return RD_OK;
-}
-
-// Upload a block-major FP32 field into storage type `storage` at dev (round to nearest).
-rd_status upload_field(const std::vector<float> &x, rd_storage storage, void *dev, hipStream_t st)
-{
-    if (x.empty()) return RD_OK;
-    if (storage == RD_FP32) {
-        HIPCHK(hipMemcpyAsync(dev, x.data(), sizeof(float) * x.size(), hipMemcpyHostToDevice, st));
-        HIPCHK(hipStreamSynchronize(st));
-        return RD_OK;
-    }
-    std::vector<uint16_t> h(x.size());
-    for (size_t i = 0; i < x.size(); ++i) {
-        const float v = x[i];
-        uint32_t u;
-        memcpy(&u, &v, 4);
-        if (storage == RD_BF16) {
-            u += 0x7fffu + ((u >> 16) & 1u);  // the initial values are finite
-            h[i] = (uint16_t)(u >> 16);
-        } else {
-            const _Float16 hv = (_Float16)v;
-            memcpy(&h[i], &hv, 2);
-        }
-    }
-    HIPCHK(hipMemcpyAsync(dev, h.data(), 2 * h.size(), hipMemcpyHostToDevice, st));
+    if (pair_bytes < 4 * (size_t)nslots || r_bytes < 2 * (size_t)nslots || r_bytes % 4 != 0)
+        return rd_fail(RD_ERR_WORKSPACE, "solver vectors too small for the labelling scratch");
+    uint32_t *par = (uint32_t *)a.ap;
+    uint8_t *flags = (uint8_t *)a.r;
+    uint32_t *pc = (uint32_t *)a.scal;
+    LAUNCHCHK(rd_launch_fill_u32(flags, 0u, (int64_t)((2 * (size_t)nslots + 3) / 4), st));
+    LAUNCHCHK(rd_launch_fill_u32(pc, 0u, a.ngeom, st));
+    LAUNCHCHK(cg_launch_initial_guess(storage, B, a, axis, nslots, par, flags, pc, st));
+    std::vector<uint32_t> h((size_t)a.ngeom);
+    HIPCHK(hipMemcpyAsync(h.data(), pc, sizeof(uint32_t) * h.size(), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    for (int g = 0; g < a.ngeom; ++g) perc[(size_t)g] = h[(size_t)g] != 0u ? 1 : 0;
     return RD_OK;
 }
 
@@ -329,10 +224,14 @@ extern "C" rd_status rd_sim_steady_state(rd_sim *sim, int axis, double rel_tol, 
         return RD_OK;
     }
     {
-        std::vector<float> x0;
-        rd_status s = initial_guess(G, axis, x0, &meta[0].percolates);
+        const size_t es = sim->storage == RD_FP32 ? 4 : 2;
+        const SimLayout &L = sim->L;
+        std::vector<char> perc;
+        rd_status s = gpu_initial_guess(a, (int)sim->storage, G.B, axis, L.field_elems,
+                                        L.solver[3] - L.solver[2] + es * (size_t)L.field_elems,
+                                        L.solver[1] - L.solver[0], sim->stream, perc);
         if (s != RD_OK) return s;
-        if ((s = upload_field(x0, sim->storage, a.x, sim->stream)) != RD_OK) return s;
+        meta[0].percolates = perc[0] != 0;
     }
     rd_status s = run_cg(a, (int)sim->storage, G.B, sim->stream, axis, rel_tol, max_iters, meta, out);
     if (s != RD_OK) return s;
@@ -495,40 +394,13 @@ extern "C" rd_status rd_batch_tortuosity(rd_batch *b, int axis, double rel_tol, 
     a.scal = (double *)(b->ws + b->o_scal);
     std::vector<CgOut> out;
     if (b->nb > 0) {
-        // host labelling and initial guesses of the geometries are independent: compute
-        // them on parallel host threads, then upload in order
-        std::vector<std::vector<float>> x0(n);
-        std::vector<rd_status> st(n, RD_OK);
-        std::vector<char> perc(n, 0);
-        const int nt = (int)std::max(1u, std::min<unsigned>((unsigned)n, std::min(16u, std::thread::hardware_concurrency())));
-        // largest geometries first (the labelling time grows with the slot count)
-        std::vector<int> order(n);
-        for (int i = 0; i < n; ++i) order[i] = i;
-        std::stable_sort(order.begin(), order.end(),
-                         [&](int u, int v) { return b->geoms[u]->nb() > b->geoms[v]->nb(); });
-        std::atomic<int> next{0};
-        auto work = [&]() {
-            for (int k = next++; k < n; k = next++) {
-                const int i = order[k];
-                bool pc = false;
-                st[i] = initial_guess(*b->geoms[i], axis, x0[i], &pc);
-                perc[i] = pc ? 1 : 0;
-            }
-        };
-        std::vector<std::thread> pool;
-        for (int t = 1; t < nt; ++t) pool.emplace_back(work);
-        work();
-        for (auto &th : pool) th.join();
-        for (int i = 0; i < n; ++i) {
-            // (the worker's message is thread-local: report on this thread)
-            if (st[i] != RD_OK)
-                return rd_fail(st[i], "initial guess of geometry " + std::to_string(i) + " failed");
-            meta[i].percolates = perc[i] != 0;
-            char *dst = (char *)a.x + es * NS * (size_t)b->ginfo[i].block0;
-            rd_status s = upload_field(x0[i], b->storage, dst, b->stream);
-            if (s != RD_OK) return s;
-            std::vector<float>().swap(x0[i]);
-        }
+        std::vector<char> perc;
+        const int64_t nslots = b->nb * (int64_t)NS;
+        rd_status s0 = gpu_initial_guess(a, (int)b->storage, b->B, axis, nslots,
+                                         b->o_vec[4] - b->o_vec[3] + es * (size_t)nslots,
+                                         b->o_vec[2] - b->o_vec[1], b->stream, perc);
+        if (s0 != RD_OK) return s0;
+        for (int i = 0; i < n; ++i) meta[i].percolates = perc[(size_t)i] != 0;
         rd_status s = run_cg(a, (int)b->storage, b->B, b->stream, axis, rel_tol, max_iters, meta, out);
         if (s != RD_OK) return s;
     } else {

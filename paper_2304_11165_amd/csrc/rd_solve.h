@@ -45,3 +45,9 @@ int cg_launch_update(int storage, int B, const CgArgs &a, void *stream);
 int cg_launch_pupdate(int storage, int B, const CgArgs &a, void *stream);
 int cg_launch_flux(int storage, int B, const CgArgs &a, int inlet_face, void *stream);
 int cg_launch_segsum(const CgArgs &a, int slot0, int slot1, int mode, void *stream);
+// Initial guess of the unit-drop problem along `axis` into a.x (every slot), from the
+// 6-connected clusters of active voxels labelled on the GPU.  Scratch: par[nslots]
+// (uint32), flags[2 * nslots] (bytes, zeroed by the caller), perc[ngeom] (uint32,
+// zeroed by the caller; set to 1 for geometries with a cluster touching both planes).
+int cg_launch_initial_guess(int storage, int B, const CgArgs &a, int axis, int64_t nslots, uint32_t *par,
+                            uint8_t *flags, uint32_t *perc, void *stream);

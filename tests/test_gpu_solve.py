@@ -108,3 +108,54 @@ def test_batch_matches_single_and_oracle(rd, oracle_mod):
         assert tau[i] == pytest.approx(tau_o, rel=1e-4)
         assert tau[i] == pytest.approx(res["tau"], rel=1e-5)
     assert tau[-1] == pytest.approx(1.0, rel=1e-5)
+
+
+def _expected_guess(img, axis):
+    """The cluster rule of the initial guess, from scipy's 6-connected labelling (an
+    independent implementation): inlet plane 1, outlet plane 0; inside, the ramp
+    1 - c/(n-1) on clusters touching both planes, 1 on clusters touching only the
+    inlet, 0 elsewhere (FP32 arithmetic, as on the GPU)."""
+    from scipy import ndimage
+
+    act = img != 0
+    lab, _ = ndimage.label(act, structure=ndimage.generate_binary_structure(3, 1))
+    ax = 2 - axis  # array axes are (z, y, x)
+    n = img.shape[ax]
+    c = np.indices(img.shape)[ax]
+    lo = np.take(lab, 0, axis=ax)
+    hi = np.take(lab, n - 1, axis=ax)
+    tin = np.isin(lab, lo[lo > 0])
+    tout = np.isin(lab, hi[hi > 0])
+    ramp = np.float32(1) - c.astype(np.float32) / np.float32(n - 1)
+    g = np.where(tin & tout, ramp, np.where(tin, np.float32(1), np.float32(0))).astype(np.float32)
+    g[c == 0] = 1.0
+    g[c == n - 1] = 0.0
+    g[~act] = 0.0
+    return g, bool(np.any(tin & tout))
+
+
+@pytest.mark.parametrize("B", [4, 8])
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_initial_guess_cluster_rule(rd, B, storage, axis):
+    """The GPU labelling gives the cluster rule exactly (max_iters = 0 leaves the guess
+    in the field): a random packing with floating and inlet-only clusters, plus a
+    floating block of voxels and an inlet-only bar added by hand."""
+    from gpu_common import round_to_storage
+
+    img, _ = W.boolean_spheres(30, 0.35, 2.0, 4.0, seed=7)
+    img = np.ascontiguousarray(img[:27, :25, :])  # ragged: (nz, ny, nx) = (27, 25, 30)
+    img[10:13, 10:13, 10:13] = 1
+    img[9:14, 9:14, 9] = 0; img[9:14, 9:14, 13] = 0  # isolate a 3^3 cube
+    img[9:14, 9, 9:14] = 0; img[9:14, 13, 9:14] = 0
+    img[9, 9:14, 9:14] = 0; img[13, 9:14, 9:14] = 0
+    img[0:3, 0:3, 0:3] = 1  # a corner cube on every inlet plane, cut off from the rest
+    img[0:4, 0:4, 3] = 0; img[0:4, 3, 0:4] = 0; img[3, 0:4, 0:4] = 0
+    want, perc = _expected_guess(img, axis)
+    c = np.indices(img.shape)[2 - axis]
+    assert np.any((want == 1.0) & (c > 0)) and np.any((want == 0.0) & (img != 0) & (c < c.max()))
+    g, s = make_gpu(rd, img, [1.0], storage=storage, B=B, features=rd.RD_WS_SOLVER)
+    res = s.steady_state(axis, 1e-6, 0)
+    got = fields(s, 1)[0]
+    np.testing.assert_array_equal(got, round_to_storage(want, storage))
+    assert math.isinf(res["tau"]) != perc
