@@ -189,7 +189,7 @@ def batched_form(torch, rd, W, count, max_edge, stream):
         "tau": [float(x) for x in tau],
         "rel_residual_max": float(max(rel)),
         "iterations": [int(x) for x in it],
-        "note": "wall time including host labelling and the initial-guess upload",
+        "note": "wall time of the tortuosity call: cluster labelling, initial guess and CG",
     }
 
 
