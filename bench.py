@@ -223,7 +223,7 @@ def steady_form(torch, rd, W, size, axes, forms, tol, stream):
                                     "rel_residual": r["rel_residual"], "iters": r["iters"],
                                     "converged": r["converged"], "seconds": secs,
                                     "active_voxel_cg_iterations_per_s": vi / secs,
-                                    "alg_GBps": vi * 10 * (4 if storage == "fp32" else 2) / secs / 1e9})
+                                    "alg_GBps": vi * 8 * (4 if storage == "fp32" else 2) / secs / 1e9})
                 log(f"steady {storage} axis {axis}: tau {r['tau']:.5f}, rel {r['rel_residual']:.2e}, "
                     f"{r['iters']} it, {secs:.1f}s")
             del sim
