@@ -51,7 +51,7 @@ def parse():
                    help="ceramic-foam steady state: tortuosity along the first K axes (0: skip)")
     p.add_argument("--steady-size", type=int, default=1024, help="edge of the foam volume")
     p.add_argument("--steady-forms", default="fp32", help="storage types of the steady form")
-    p.add_argument("--steady-tol", type=float, default=1e-6)
+    p.add_argument("--steady-tol", type=float, default=1e-8)
     p.add_argument("--cpu-steps", type=int, default=0,
                    help="oracle steps in the CPU sample (0: as many as fit in --cpu-seconds)")
     p.add_argument("--cpu-seconds", type=float, default=12.0,

@@ -90,14 +90,20 @@ __device__ __forceinline__ float lap_at(const float *ts, int t, unsigned nbm)
     return lap;
 }
 
-// (A p)_p on a free voxel of an 8^3 column kernel: n_active p_p minus the sum of the
-// six neighbour values (0 where inactive) in the order -x, +x, -y, +y, -z, +z; q points
-// at p_p in the one-plane LDS tile, dn / up are the -z / +z values.  0 elsewhere.
+// (A p)_p on a free voxel of an 8^3 column kernel: the sum over active neighbours q of
+// (p_p - p_q), in the order -x, +x, -y, +y, -z, +z; q points at p_p in the one-plane
+// LDS tile, dn / up are the -z / +z values, `code` holds the active-neighbour bits.  0
+// elsewhere.  The difference form keeps the rounding error proportional to the local
+// differences, not to |p|: CG corrections are smooth fields far larger than their
+// right-hand side, where n p_p - sum p_q would cancel catastrophically in FP32.
 __device__ __forceinline__ float cg_ap8(const float *q, float dn, float up, float pc, unsigned code,
                                         bool fr)
 {
-    const float sum = ((((q[-1] + q[1]) + q[-10]) + q[10]) + dn) + up;
-    return fr ? fmaf((float)__popc(code & 63u), pc, -sum) : 0.0f;
+    const float nv[6] = {q[-1], q[1], q[-10], q[10], dn, up};
+    float ap = 0.0f;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) ap = ((code >> d) & 1u) ? ap + (pc - nv[d]) : ap;
+    return fr ? ap : 0.0f;
 }
 
 template <int B>
@@ -441,7 +447,7 @@ __global__ __launch_bounds__(256) void k_cg_matvec8(CgArgs a)
 // and its face halos with the matvec's arithmetic (cg_ap8), so it equals the A p of
 // the p.Ap partial bit for bit.  Whole sectors are stored: inactive slots keep 0 and
 // Dirichlet voxels their values.  Partial (r.r, 0) per block, of r as stored.
-template <typename T>
+template <typename T, bool X64>
 __global__ __launch_bounds__(256) void k_cg_update8(CgArgs a)
 {
     __shared__ float tile[4][100];
@@ -471,12 +477,14 @@ __global__ __launch_bounds__(256) void k_cg_update8(CgArgs a)
     for (int f = 0; f < 6; ++f) Wf[f] = rec[8 + f];
     typedef typename RawOf<T>::type R;
     R pc[8], ph[6], xc[8], rc[8];
+    double xd[8];
     unsigned cd[8];
 #pragma unroll
     for (int z = 0; z < 8; ++z) {
         const bool act = (Wo[z] >> lane) & 1ull;
         pc[z] = ld_raw(pv, base + z * 64 + lane, act);
-        xc[z] = ld_raw((const T *)xv, base + z * 64 + lane, act);
+        if (X64) xd[z] = act ? a.x64[base + z * 64 + lane] : 0.0;
+        else xc[z] = ld_raw((const T *)xv, base + z * 64 + lane, act);
         rc[z] = ld_raw((const T *)rv, base + z * 64 + lane, act);
         cd[z] = act ? (unsigned)a.code[base + z * 64 + lane] : 0u;
     }
@@ -495,7 +503,9 @@ __global__ __launch_bounds__(256) void k_cg_update8(CgArgs a)
         const bool e = (Wf[f] >> lane) & 1ull;
         ph[f] = ld_raw(pv, (int64_t)(n >= 0 ? n : b) * 512 + ns, e);
     }
-    const float alpha = (float)a.scal[gid * CG_NSCAL + CG_ALPHA];
+    const double alpha_d = a.scal[gid * CG_NSCAL + CG_ALPHA];
+    const float alpha = (float)alpha_d;
+    const double alpha_x = X64 ? alpha_d / a.scal[gid * CG_NSCAL + CG_SIGMA] : 0.0;  // p holds sigma p
     float c[8], side[4];
 #pragma unroll
     for (int z = 0; z < 8; ++z) c[z] = from_raw<T>(pc[z]);
@@ -532,9 +542,12 @@ __global__ __launch_bounds__(256) void k_cg_update8(CgArgs a)
         const float dn = z == 0 ? zlo : c[z > 0 ? z - 1 : 0];
         const float up = z == 7 ? zhi : c[z < 7 ? z + 1 : 7];
         const float ap = cg_ap8(q, dn, up, c[z], code, fr);
-        const float x0 = from_raw<T>(xc[z]), r0 = from_raw<T>(rc[z]);
-        const float xn = fr ? fmaf(alpha, c[z], x0) : x0;
+        const float r0 = from_raw<T>(rc[z]);
         const float rn = fr ? fmaf(-alpha, ap, r0) : r0;
+        float xn = 0.0f;
+        double xdn = 0.0;
+        if (X64) xdn = fr ? fma(alpha_x, (double)c[z], xd[z]) : xd[z];
+        else xn = fr ? fmaf(alpha, c[z], from_raw<T>(xc[z])) : from_raw<T>(xc[z]);
         if (fr) {
             const float rs = rd_round<T>(rn);  // as stored
             rr += (double)rs * (double)rs;
@@ -543,9 +556,10 @@ __global__ __launch_bounds__(256) void k_cg_update8(CgArgs a)
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (sector_active<T>(Wo[z], lane)) {
-            rd_st_keep(xv, base + z * 64 + lane, xn);
+            if (!X64) rd_st_keep(xv, base + z * 64 + lane, xn);
             rd_st_keep(rv, base + z * 64 + lane, rn);
         }
+        if (X64 && sector_active<double>(Wo[z], lane)) a.x64[base + z * 64 + lane] = xdn;
     }
     rr = wave_sum(rr);
     if (lane == 0) {
@@ -586,9 +600,13 @@ __global__ __launch_bounds__(256) void k_cg_update(CgArgs a)
             const int64_t i = (int64_t)b * K::NS + slot;
             const float p = rd_ld((const T *)a.p, i);
             const float ap = rd_ld((const T *)a.ap, i);
-            const float x = fmaf(alpha, p, rd_ld((const T *)a.x, i));
             const float r = fmaf(-alpha, ap, rd_ld((const T *)a.r, i));
-            rd_st_keep((T *)a.x, i, x);
+            if (a.x64) {  // p holds sigma p
+                a.x64[i] = fma(a.scal[gid * CG_NSCAL + CG_ALPHA] / a.scal[gid * CG_NSCAL + CG_SIGMA], (double)p,
+                               a.x64[i]);
+            } else {
+                rd_st_keep((T *)a.x, i, fmaf(alpha, p, rd_ld((const T *)a.x, i)));
+            }
             rd_st_keep((T *)a.r, i, r);
             const float rs = rd_ld((const T *)a.r, i);  // the stored (rounded) residual
             rr += (double)rs * (double)rs;
@@ -862,6 +880,170 @@ __global__ __launch_bounds__(256) void k_lab_guess(const BlockInfo *info, const 
     rd_st_keep(x, i, v);
 }
 
+// ---- mixed-precision iterative refinement of the steady state ----------------
+// The refinement scheme of Wilkinson in the mixed-precision form analysed by Carson
+// and Higham (2018): the solution X and the residual R = b - A X are FP64; every
+// correction A d = R / s is solved by the CG above in the storage type (FP32
+// arithmetic) from the scaled right-hand side, then X += s d.  These kernels take one
+// thread per slot and read neighbours directly (they run a few times per solve).
+
+// slot index of the neighbour of slot i across direction d (order -x,+x,-y,+y,-z,+z);
+// the caller has checked that the neighbour is active (so its block exists)
+template <int B>
+__device__ __forceinline__ int64_t ir_nbr(const BlockInfo *info, int64_t i, int d)
+{
+    constexpr int NS = B * B * B;
+    const int64_t b = i / NS;
+    const int slot = (int)(i % NS);
+    const int l = d < 2 ? slot % B : d < 4 ? (slot / B) % B : slot / (B * B);
+    const int st = d < 2 ? 1 : d < 4 ? B : B * B;
+    if (d & 1) return l < B - 1 ? i + st : (int64_t)info[b].nbr[d] * NS + slot - (B - 1) * st;
+    return l > 0 ? i - st : (int64_t)info[b].nbr[d] * NS + slot + (B - 1) * st;
+}
+
+template <int B>
+__device__ __forceinline__ void ir_pos(const BlockInfo *info, const GeomInfo *geom, int64_t i, int *gx, int *gy,
+                                       int *gz, GeomInfo *g)
+{
+    constexpr int NS = B * B * B;
+    const int slot = (int)(i % NS);
+    int bx, by, bz, gid;
+    block_pos(info[i / NS], &bx, &by, &bz, &gid);
+    *g = geom[gid];
+    *gx = bx * B + slot % B;
+    *gy = by * B + (slot / B) % B;
+    *gz = bz * B + slot / (B * B);
+}
+
+// sum of two FP64 values over the workgroup, written to part[blockIdx.x * 2 + k]
+__device__ __forceinline__ void wg_sum2(double v0, double v1, double *part)
+{
+    __shared__ double sh[4][2];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    v0 = wave_sum(v0);
+    v1 = wave_sum(v1);
+    if (lane == 0) {
+        sh[wave][0] = v0;
+        sh[wave][1] = v1;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2)
+        part[(int64_t)blockIdx.x * 2 + threadIdx.x] =
+            ((sh[0][threadIdx.x] + sh[1][threadIdx.x]) + sh[2][threadIdx.x]) + sh[3][threadIdx.x];
+}
+
+// r = b - A X on free voxels in FP64 from the FP64 iterate X, with the Dirichlet values
+// held in X: r_p = sum over active neighbours q of (X_q - X_p) (difference form, order
+// -x,+x,-y,+y,-z,+z); b_p = sum of the Dirichlet neighbours' X_q.  Per-block FP64
+// partials (r.r, b.b) as the other CG kernels write them.  store 1: r rounded to the
+// storage type becomes the CG residual and direction (r and p; 0 off the free voxels);
+// store 2: sigma_new r replaces the residual (residual replacement) and p is rescaled
+// from sigma to sigma_new (powers of 2: exact), so that 16-bit vectors stay in range
+// as the residual shrinks; store 3: r and p are only rescaled.  With store 2 or 3 the
+// first partial is that of the stored r.
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_res64(CgArgs a, int store)
+{
+    using C = Cfg<B>;
+    constexpr int NS = B * B * B;
+    const int sub = threadIdx.x / C::TPB, lt = threadIdx.x % C::TPB;
+    const int b = blockIdx.x * C::BPW + sub;
+    double rr = 0.0, bb = 0.0;
+    if (b < a.nb) {
+        int bx, by, bz, gid;
+        block_pos(a.info[b], &bx, &by, &bz, &gid);
+        const double sig = store >= 2 ? a.scal[gid * CG_NSCAL + CG_SIGMA_NEW] : 1.0;
+        const float pscale = store >= 2 ? (float)(sig / a.scal[gid * CG_NSCAL + CG_SIGMA]) : 1.0f;
+        for (int k = 0; k < C::VPT; ++k) {
+            const int64_t i = (int64_t)b * NS + lt + k * C::TPB;
+            const unsigned cd = a.code[i];
+            if (store == 3) {  // rescale only
+                const float rs = rd_round<T>(pscale * rd_ld((const T *)a.r, i));
+                rr += (double)rs * (double)rs;
+                rd_st_keep((T *)a.r, i, rs);
+                rd_st_keep((T *)a.p, i, pscale * rd_ld((const T *)a.p, i));
+                continue;
+            }
+            float out = 0.0f;
+            if (cd & 64u) {
+                int gx, gy, gz;
+                GeomInfo g;
+                ir_pos<B>(a.info, a.geom, i, &gx, &gy, &gz, &g);
+                if (!on_dirichlet(a.dir, gx, gy, gz, g.nx, g.ny, g.nz)) {
+                    const double xp = a.x64[i];
+                    double s = 0.0, bp = 0.0;
+#pragma unroll
+                    for (int d = 0; d < 6; ++d) {
+                        if (!((cd >> d) & 1u)) continue;
+                        const double xq = a.x64[ir_nbr<B>(a.info, i, d)];
+                        s += xq - xp;
+                        const int ex = d == 0 ? -1 : d == 1 ? 1 : 0, ey = d == 2 ? -1 : d == 3 ? 1 : 0,
+                                  ez = d == 4 ? -1 : d == 5 ? 1 : 0;
+                        if (on_dirichlet(a.dir, gx + ex, gy + ey, gz + ez, g.nx, g.ny, g.nz)) bp += xq;
+                    }
+                    out = (float)(sig * s);
+                    if (store == 2) {
+                        const double rs = (double)rd_round<T>(out);
+                        rr += rs * rs;
+                    } else {
+                        rr += s * s;
+                    }
+                    bb += bp * bp;
+                }
+            }
+            if (store == 1 || store == 2) rd_st_keep((T *)a.r, i, out);
+            if (store == 1) rd_st_keep((T *)a.p, i, out);
+            if (store == 2 && pscale != 1.0f) rd_st_keep((T *)a.p, i, pscale * rd_ld((const T *)a.p, i));
+        }
+    }
+    block_sum2<B>(rr, bb, a.partial, b, b < a.nb);
+}
+
+// X = x (mode 0), X += s d (mode 1), x = X rounded to the storage type (mode 2); every slot
+template <typename T>
+__global__ __launch_bounds__(256) void k_ir_axpy(int64_t nslots, int mode, double s, double *X, T *x)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nslots) return;
+    if (mode == 0) X[i] = (double)rd_ld((const T *)x, i);
+    else if (mode == 1) X[i] += s * (double)rd_ld((const T *)x, i);
+    else rd_st_keep(x, i, (float)X[i]);
+}
+
+// FP64 flux through the two Dirichlet planes of X: partials (sum over inlet Dirichlet
+// voxels p and their free neighbours q of X_p - X_q, the same over the outlet)
+template <int B>
+__global__ __launch_bounds__(256) void k_ir_flux(const BlockInfo *info, const uint8_t *code, const GeomInfo *geom,
+                                                 int64_t nslots, uint32_t dir, int inlet_face, const double *X,
+                                                 double *partial)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double qin = 0.0, qout = 0.0;
+    if (i < nslots && (code[i] & 64u)) {
+        const unsigned cd = code[i];
+        int gx, gy, gz;
+        GeomInfo g;
+        ir_pos<B>(info, geom, i, &gx, &gy, &gz, &g);
+        const bool on_in = on_dirichlet(1u << inlet_face, gx, gy, gz, g.nx, g.ny, g.nz);
+        const bool on_out = !on_in && on_dirichlet(1u << (inlet_face + 1), gx, gy, gz, g.nx, g.ny, g.nz);
+        if (on_in || on_out) {
+            const double xp = X[i];
+            double q = 0.0;
+#pragma unroll
+            for (int d = 0; d < 6; ++d) {
+                if (!((cd >> d) & 1u)) continue;
+                const int ex = d == 0 ? -1 : d == 1 ? 1 : 0, ey = d == 2 ? -1 : d == 3 ? 1 : 0,
+                          ez = d == 4 ? -1 : d == 5 ? 1 : 0;
+                if (on_dirichlet(dir, gx + ex, gy + ey, gz + ez, g.nx, g.ny, g.nz)) continue;
+                q += xp - X[ir_nbr<B>(info, i, d)];
+            }
+            if (on_in) qin = q;
+            else qout = q;
+        }
+    }
+    wg_sum2(qin, qout, partial);
+}
+
 template <int B>
 int groups(int nb) { return (nb + Cfg<B>::BPW - 1) / Cfg<B>::BPW; }
 
@@ -917,9 +1099,15 @@ int cg_launch_update(int storage, int B, const CgArgs &a, void *stream)
     if (B == 8) {  // column form with A p recomputed (the fused matvec does not store it)
         const dim3 grid((unsigned)std::max(1, (a.nb + 3) / 4));
         hipStream_t st = (hipStream_t)stream;
-        if (storage == 0) hipLaunchKernelGGL((k_cg_update8<float>), grid, dim3(256), 0, st, a);
-        else if (storage == 1) hipLaunchKernelGGL((k_cg_update8<bf16_t>), grid, dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((k_cg_update8<_Float16>), grid, dim3(256), 0, st, a);
+        if (a.x64) {
+            if (storage == 0) hipLaunchKernelGGL((k_cg_update8<float, true>), grid, dim3(256), 0, st, a);
+            else if (storage == 1) hipLaunchKernelGGL((k_cg_update8<bf16_t, true>), grid, dim3(256), 0, st, a);
+            else hipLaunchKernelGGL((k_cg_update8<_Float16, true>), grid, dim3(256), 0, st, a);
+        } else {
+            if (storage == 0) hipLaunchKernelGGL((k_cg_update8<float, false>), grid, dim3(256), 0, st, a);
+            else if (storage == 1) hipLaunchKernelGGL((k_cg_update8<bf16_t, false>), grid, dim3(256), 0, st, a);
+            else hipLaunchKernelGGL((k_cg_update8<_Float16, false>), grid, dim3(256), 0, st, a);
+        }
         return (int)hipGetLastError();
     }
     CG_DISPATCH(storage, B, k_cg_update, grid_for(B, a.nb), stream, a);
@@ -965,6 +1153,31 @@ int cg_launch_initial_guess(int storage, int B, const CgArgs &a, int axis, int64
             hipLaunchKernelGGL((k_lab_guess<_Float16, 4>), grid, dim3(256), 0, st, a.info, a.code, a.geom, nslots, axis,
                                par, fin, fout, (_Float16 *)a.x, perc);
     }
+    return (int)hipGetLastError();
+}
+int ir_rows(int64_t nslots) { return (int)((nslots + 255) / 256); }
+int cg_launch_res64(int storage, int B, const CgArgs &a, int store, void *stream)
+{
+    CG_DISPATCH(storage, B, k_res64, grid_for(B, a.nb), stream, a, store);
+}
+int ir_launch_axpy(int storage, int64_t nslots, int mode, double s, double *X, void *x, void *stream)
+{
+    if (nslots <= 0) return 0;
+    hipStream_t st = (hipStream_t)stream;
+    const dim3 grid((unsigned)ir_rows(nslots));
+    if (storage == 0) hipLaunchKernelGGL((k_ir_axpy<float>), grid, dim3(256), 0, st, nslots, mode, s, X, (float *)x);
+    else if (storage == 1) hipLaunchKernelGGL((k_ir_axpy<bf16_t>), grid, dim3(256), 0, st, nslots, mode, s, X, (bf16_t *)x);
+    else hipLaunchKernelGGL((k_ir_axpy<_Float16>), grid, dim3(256), 0, st, nslots, mode, s, X, (_Float16 *)x);
+    return (int)hipGetLastError();
+}
+int ir_launch_flux(int B, const CgArgs &a, int64_t nslots, int inlet_face, const double *X, double *partial,
+                   void *stream)
+{
+    if (nslots <= 0) return 0;
+    hipStream_t st = (hipStream_t)stream;
+    const dim3 grid((unsigned)ir_rows(nslots));
+    if (B == 8) hipLaunchKernelGGL(k_ir_flux<8>, grid, dim3(256), 0, st, a.info, a.code, a.geom, nslots, a.dir, inlet_face, X, partial);
+    else hipLaunchKernelGGL(k_ir_flux<4>, grid, dim3(256), 0, st, a.info, a.code, a.geom, nslots, a.dir, inlet_face, X, partial);
     return (int)hipGetLastError();
 }
 int cg_launch_segsum(const CgArgs &a, int slot0, int slot1, int mode, void *stream)

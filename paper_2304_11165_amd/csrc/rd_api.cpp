@@ -296,6 +296,7 @@ SimLayout sim_layout(const rd_sim &s, uint32_t features, int64_t cp_slots)
             off = align256(off + es * (size_t)L.field_elems);
         }
         L.scal = off; off = align256(off + sizeof(double) * 64);
+        L.irx = off; off = align256(off + 8 * (size_t)L.field_elems);
     }
     if (features & RD_WS_ADJOINT) {
         for (int v = 0; v < 2; ++v) {

@@ -36,6 +36,7 @@ struct SimLayout {
     int nparts;
     size_t part, mid, res;  // reduction partials, finish scratch, results
     size_t solver[4], scal;  // CG vectors r, p, Ap, second p
+    size_t irx;              // FP64 iterate of the steady state
     size_t lam[2], target, cp, cp_stride;
     size_t total;
 };

@@ -29,6 +29,8 @@ struct GeomMeta {
     bool percolates;
 };
 
+inline double m_active(const GeomMeta &m) { return m.psi * (double)m.nx * (double)m.ny * (double)m.nz; }
+
 struct CgOut {
     double tau = 0, rel = 0, qin = 0, qout = 0;
     int64_t iters = 0;
@@ -83,13 +85,15 @@ rd_status push_scal(const CgArgs &a, const std::vector<double> &hs, hipStream_t 
 // Runs CG on every geometry of `a` (Dirichlet values already in x) from a linear
 // ramp, stopping each geometry at rel. residual <= tol, stagnation or max_iters.
 rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axis, double tol,
-                 int64_t max_iters, const std::vector<GeomMeta> &meta, std::vector<CgOut> &out)
+                 int64_t max_iters, const std::vector<GeomMeta> &meta, std::vector<CgOut> &out,
+                 int stall_checks = STALL_CHECKS, bool want_tau = true)
 {
     CgArgs a = args;  // B = 8 swaps the two p buffers every iteration
     const int n = a.ngeom;
     out.assign(n, CgOut());
     LAUNCHCHK(rd_launch_fill_u32(a.scal, 0u, (int64_t)n * CG_NSCAL * 2, st));
-    LAUNCHCHK(cg_launch_residual(storage, B, a, 1, st));
+    if (a.x64) LAUNCHCHK(cg_launch_res64(storage, B, a, 1, st));
+    else LAUNCHCHK(cg_launch_residual(storage, B, a, 1, st));
     LAUNCHCHK(cg_launch_segsum(a, CG_RRNEW, CG_BB, 2, st));
     std::vector<double> hs;
     rd_status s = copy_scal(a, hs, st);
@@ -102,6 +106,8 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
         const double bb = v[CG_BB], rr = v[CG_RR];
         out[g].rel = bb > 0 ? sqrt(rr / bb) : 0.0;
         best[g] = out[g].rel;
+        v[CG_SIGMA] = 1.0;
+        v[CG_SIGMA_NEW] = 1.0;
         if (!(bb > 0) || out[g].rel <= tol || max_iters <= 0) {
             v[CG_DONE] = 1.0;
             out[g].converged = out[g].rel <= tol;
@@ -118,16 +124,27 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
                 LAUNCHCHK(cg_launch_matvec_fused(storage, a, st));
                 std::swap(a.p, a.p2);
             } else {
+                // the same order: p <- r + beta p first (so that between iterations p is
+                // the last direction and r the newest residual, as with B = 8)
+                LAUNCHCHK(cg_launch_pupdate(storage, B, a, st));
                 LAUNCHCHK(cg_launch_matvec(storage, B, a, st));
             }
             LAUNCHCHK(cg_launch_segsum(a, CG_PAP, -1, 0, st));
             LAUNCHCHK(cg_launch_update(storage, B, a, st));
             LAUNCHCHK(cg_launch_segsum(a, CG_RRNEW, -1, 1, st));
-            if (B != 8) LAUNCHCHK(cg_launch_pupdate(storage, B, a, st));
         }
-        // true residual b - A x (the recursive one drifts in reduced precision)
-        LAUNCHCHK(cg_launch_residual(storage, B, a, 0, st));
-        LAUNCHCHK(cg_launch_segsum(a, CG_CHECK, -1, -1, st));
+        bool replace = false, rescale = false;
+        // true residual b - A x (the recursive one drifts in reduced precision); with an
+        // FP64 iterate it is computed in FP64 and, once the recursive residual has
+        // drifted from it, replaces it (residual replacement, van der Vorst and Ye 2000),
+        // so the iteration is not held at the storage type's floor
+        if (a.x64) {
+            LAUNCHCHK(cg_launch_res64(storage, B, a, 0, st));
+            LAUNCHCHK(cg_launch_segsum(a, CG_CHECK, -1, -1, st));
+        } else {
+            LAUNCHCHK(cg_launch_residual(storage, B, a, 0, st));
+            LAUNCHCHK(cg_launch_segsum(a, CG_CHECK, -1, -1, st));
+        }
         if ((s = copy_scal(a, hs, st)) != RD_OK) return s;
         for (int g = 0; g < n; ++g) {
             double *v = &hs[(size_t)g * CG_NSCAL];
@@ -143,14 +160,40 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
                 ++since[g];
             }
             const bool conv = rel <= tol;
-            if (conv || since[g] >= STALL_CHECKS || out[g].iters >= max_iters) {
+            if (conv || since[g] >= stall_checks || out[g].iters >= max_iters) {
                 v[CG_DONE] = 1.0;
                 out[g].converged = conv;
                 --live;
+            } else if (a.x64) {
+                // next scale: a power of 2 that brings the residual's RMS near 1
+                const double n_act = std::max(1.0, m_active(meta[g]));
+                const double rms = sqrt(std::max(v[CG_CHECK], 1e-300) / n_act);
+                v[CG_SIGMA_NEW] = ldexp(1.0, std::max(-60, std::min(60, (int)lround(-log2(rms)))));
+                // replace the recursive residual once it has drifted from the true one by
+                // more than a quarter (van der Vorst and Ye replace only where the gap
+                // grows: every replacement costs the recursion some of its conjugacy)
+                const double rec = sqrt(std::max(v[CG_RR], 0.0)) / v[CG_SIGMA];
+                const double tru = sqrt(std::max(v[CG_CHECK], 0.0));
+                replace = replace || fabs(rec - tru) > 0.25 * tru;
+                rescale = rescale || v[CG_SIGMA_NEW] != v[CG_SIGMA];
             }
         }
         if ((s = push_scal(a, hs, st)) != RD_OK) return s;
+        if (a.x64 && live > 0 && (replace || rescale)) {
+            // residual replacement: r = sigma_new (b - A X) in FP64 and p rescaled, or only
+            // the rescaling of r and p; then rr of the stored r
+            LAUNCHCHK(cg_launch_res64(storage, B, a, replace ? 2 : 3, st));
+            LAUNCHCHK(cg_launch_segsum(a, CG_RR, -1, -1, st));
+            for (int g = 0; g < n; ++g) {
+                double *v = &hs[(size_t)g * CG_NSCAL];
+                v[CG_SIGMA] = v[CG_SIGMA_NEW];
+                HIPCHK(hipMemcpyAsync(a.scal + (size_t)g * CG_NSCAL + CG_SIGMA, &v[CG_SIGMA], sizeof(double),
+                                      hipMemcpyHostToDevice, st));
+            }
+            HIPCHK(hipStreamSynchronize(st));
+        }
     }
+    if (!want_tau) return RD_OK;
     // steady flux through the two Dirichlet planes
     LAUNCHCHK(cg_launch_flux(storage, B, a, 2 * axis, st));
     LAUNCHCHK(cg_launch_segsum(a, CG_QIN, CG_QOUT, -1, st));
@@ -233,14 +276,40 @@ extern "C" rd_status rd_sim_steady_state(rd_sim *sim, int axis, double rel_tol, 
         if (s != RD_OK) return s;
         meta[0].percolates = perc[0] != 0;
     }
-    rd_status s = run_cg(a, (int)sim->storage, G.B, sim->stream, axis, rel_tol, max_iters, meta, out);
+    // CG with an FP64 iterate X (starting at the guess) and FP64 residual replacement at
+    // every check: direction and residual vectors stay in the storage type
+    const int st_ = (int)sim->storage;
+    const SimLayout &L = sim->L;
+    const int64_t nslots = L.field_elems;
+    hipStream_t stream = sim->stream;
+    double *X = (double *)(sim->ws + L.irx);
+    double *part = (double *)(sim->ws + L.part);
+    double *mid = (double *)(sim->ws + L.mid);
+    double *res = (double *)(sim->ws + L.res) + 40;
+    LAUNCHCHK(ir_launch_axpy(st_, nslots, 0, 0.0, X, a.x, stream));
+    a.x64 = X;
+    rd_status s = run_cg(a, st_, G.B, stream, axis, rel_tol, max_iters, meta, out, 2 * STALL_CHECKS, false);
     if (s != RD_OK) return s;
-    if (tau) *tau = out[0].tau;
-    if (rel_residual) *rel_residual = out[0].rel;
-    if (iters) *iters = out[0].iters;
+    const double rel = out[0].rel;
+    const int64_t total = out[0].iters;
+    // the field holds X; tau from the FP64 flux of X through both Dirichlet planes
+    LAUNCHCHK(ir_launch_axpy(st_, nslots, 2, 0.0, X, a.x, stream));
+    LAUNCHCHK(ir_launch_flux(G.B, a, nslots, inlet, X, part, stream));
+    LAUNCHCHK(rd_launch_finish_reduce(part, ir_rows(nslots), 2, mid, res, stream));
+    double q2[2];
+    HIPCHK(hipMemcpyAsync(q2, res, sizeof(q2), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    const double area = (double)ext[(axis + 1) % 3] * (double)ext[(axis + 2) % 3] * G.dx * G.dx;
+    const double len = (double)(ext[axis] - 1) * G.dx;
+    const double q = 0.5 * (q2[0] * G.dx - q2[1] * G.dx);  // mean of inlet inflow and outlet outflow
+    const double t = (meta[0].percolates && q > 0) ? meta[0].psi * area / (q * len)
+                                                     : std::numeric_limits<double>::infinity();
+    if (tau) *tau = t;
+    if (rel_residual) *rel_residual = rel;
+    if (iters) *iters = total;
     sim->steps_taken = 0;
     if (!out[0].converged)
-        return rd_fail(RD_ERR_NOT_CONVERGED, "stopped at rel. residual " + std::to_string(out[0].rel));
+        return rd_fail(RD_ERR_NOT_CONVERGED, "stopped at rel. residual " + std::to_string(rel));
     return RD_OK;
 }
 

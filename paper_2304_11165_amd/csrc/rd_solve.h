@@ -17,7 +17,9 @@ enum {
     CG_CHECK = 7,
     CG_QIN = 8,
     CG_QOUT = 9,
-    CG_NSCAL = 10
+    CG_SIGMA = 10,      // FP64 iterate: r and p hold sigma times the true residual / direction
+    CG_SIGMA_NEW = 11,  // the scale the next residual replacement switches to (a power of 2)
+    CG_NSCAL = 12
 };
 
 struct CgArgs {
@@ -29,6 +31,7 @@ struct CgArgs {
     int ngeom;
     uint32_t dir;          // Dirichlet faces (inlet | outlet)
     void *x, *r, *p, *ap;  // storage type T, nb * B^3 each (ap: B = 4 only)
+    double *x64;           // FP64 iterate (single geometry), or NULL: the iterate is x
     void *p2;              // second p buffer (B = 8: the fused p update writes here)
     double *partial;       // [nb][2]
     double *scal;          // [ngeom][CG_NSCAL]
@@ -49,5 +52,15 @@ int cg_launch_segsum(const CgArgs &a, int slot0, int slot1, int mode, void *stre
 // 6-connected clusters of active voxels labelled on the GPU.  Scratch: par[nslots]
 // (uint32), flags[2 * nslots] (bytes, zeroed by the caller), perc[ngeom] (uint32,
 // zeroed by the caller; set to 1 for geometries with a cluster touching both planes).
+// FP64 iterate helpers (single geometry), partial rows of ir_rows(nslots) x 2 doubles.
+// axpy mode 0: X = x; 1: X += s x; 2: x = X (rounded).  flux: (inlet, outlet) sums of
+// X_p - X_q over Dirichlet voxels p and their free neighbours q.
+int ir_rows(int64_t nslots);
+// r = b - A x64 in FP64 (per-block partials (r.r, b.b)); store 1 writes it to r and p;
+// store 2 writes sigma_new r to r and rescales p; store 3 only rescales r and p
+int cg_launch_res64(int storage, int B, const CgArgs &a, int store, void *stream);
+int ir_launch_axpy(int storage, int64_t nslots, int mode, double s, double *X, void *x, void *stream);
+int ir_launch_flux(int B, const CgArgs &a, int64_t nslots, int inlet_face, const double *X, double *partial,
+                   void *stream);
 int cg_launch_initial_guess(int storage, int B, const CgArgs &a, int axis, int64_t nslots, uint32_t *par,
                             uint8_t *flags, uint32_t *perc, void *stream);
