@@ -384,11 +384,17 @@ def main():
                               reactions=w.reactions)
         c0 = prob.initial()
         prob.run(c0, w.dt, 1)  # page in
-        t0 = time.perf_counter()
-        prob.run(c0, w.dt, 2)  # sizes the sample
         done = a.cpu_steps
-        if done <= 0:
-            done = max(2, min(5000, int(a.cpu_seconds / ((time.perf_counter() - t0) / 2))))
+        if done <= 0:  # size the sample from two short runs (their difference drops the
+            # per-call cost of copying the field in and out)
+            t0 = time.perf_counter()
+            prob.run(c0, w.dt, 2)
+            t2 = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            prob.run(c0, w.dt, 6)
+            t6 = time.perf_counter() - t0
+            per = max((t6 - t2) / 4, 1e-6)
+            done = max(2, min(5000, int((a.cpu_seconds - t2 + 2 * per) / per)))
         t0 = time.perf_counter()
         prob.run(c0, w.dt, done)
         secs = time.perf_counter() - t0
