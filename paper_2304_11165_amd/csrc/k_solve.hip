@@ -601,7 +601,7 @@ __global__ __launch_bounds__(256) void k_cg_update(CgArgs a)
             const float p = rd_ld((const T *)a.p, i);
             const float ap = rd_ld((const T *)a.ap, i);
             const float r = fmaf(-alpha, ap, rd_ld((const T *)a.r, i));
-            if (a.x64) {  // p holds sigma p
+            if (a.x64 && a.x64_direct) {  // p holds sigma p
                 a.x64[i] = fma(a.scal[gid * CG_NSCAL + CG_ALPHA] / a.scal[gid * CG_NSCAL + CG_SIGMA], (double)p,
                                a.x64[i]);
             } else {
@@ -937,10 +937,10 @@ __device__ __forceinline__ void wg_sum2(double v0, double v1, double *part)
 // -x,+x,-y,+y,-z,+z); b_p = sum of the Dirichlet neighbours' X_q.  Per-block FP64
 // partials (r.r, b.b) as the other CG kernels write them.  store 1: r rounded to the
 // storage type becomes the CG residual and direction (r and p; 0 off the free voxels);
-// store 2: sigma_new r replaces the residual (residual replacement) and p is rescaled
-// from sigma to sigma_new (powers of 2: exact), so that 16-bit vectors stay in range
-// as the residual shrinks; store 3: r and p are only rescaled.  With store 2 or 3 the
-// first partial is that of the stored r.
+// store 2: sigma r replaces the residual (residual replacement) and p is rescaled from
+// sigma_prev to sigma (powers of 2: exact), so that 16-bit vectors stay in range as the
+// residual shrinks; store 3: r and p are only rescaled.  With store 2 or 3 the first
+// partial is that of the stored r.
 template <typename T, int B>
 __global__ __launch_bounds__(256) void k_res64(CgArgs a, int store)
 {
@@ -952,8 +952,8 @@ __global__ __launch_bounds__(256) void k_res64(CgArgs a, int store)
     if (b < a.nb) {
         int bx, by, bz, gid;
         block_pos(a.info[b], &bx, &by, &bz, &gid);
-        const double sig = store >= 2 ? a.scal[gid * CG_NSCAL + CG_SIGMA_NEW] : 1.0;
-        const float pscale = store >= 2 ? (float)(sig / a.scal[gid * CG_NSCAL + CG_SIGMA]) : 1.0f;
+        const double sig = store >= 2 ? a.scal[gid * CG_NSCAL + CG_SIGMA] : 1.0;
+        const float pscale = store >= 2 ? (float)(sig / a.scal[gid * CG_NSCAL + CG_SIGMA_PREV]) : 1.0f;
         for (int k = 0; k < C::VPT; ++k) {
             const int64_t i = (int64_t)b * NS + lt + k * C::TPB;
             const unsigned cd = a.code[i];
@@ -997,6 +997,23 @@ __global__ __launch_bounds__(256) void k_res64(CgArgs a, int store)
         }
     }
     block_sum2<B>(rr, bb, a.partial, b, b < a.nb);
+}
+
+// X += x / sigma of the slot's geometry, then x = 0 (every slot): the updates that x
+// accumulated since the last check join the FP64 iterate
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_ir_fold(const BlockInfo *info, const double *scal, int64_t nslots,
+                                                 double *X, T *x)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nslots) return;
+    const float v = rd_ld((const T *)x, i);
+    if (v != 0.0f) {
+        int bx, by, bz, gid;
+        block_pos(info[i / (B * B * B)], &bx, &by, &bz, &gid);
+        X[i] += (double)v / scal[gid * CG_NSCAL + CG_SIGMA];
+        rd_st_keep(x, i, 0.0f);
+    }
 }
 
 // X = x (mode 0), X += s d (mode 1), x = X rounded to the storage type (mode 2); every slot
@@ -1099,7 +1116,7 @@ int cg_launch_update(int storage, int B, const CgArgs &a, void *stream)
     if (B == 8) {  // column form with A p recomputed (the fused matvec does not store it)
         const dim3 grid((unsigned)std::max(1, (a.nb + 3) / 4));
         hipStream_t st = (hipStream_t)stream;
-        if (a.x64) {
+        if (a.x64 && a.x64_direct) {
             if (storage == 0) hipLaunchKernelGGL((k_cg_update8<float, true>), grid, dim3(256), 0, st, a);
             else if (storage == 1) hipLaunchKernelGGL((k_cg_update8<bf16_t, true>), grid, dim3(256), 0, st, a);
             else hipLaunchKernelGGL((k_cg_update8<_Float16, true>), grid, dim3(256), 0, st, a);
@@ -1168,6 +1185,26 @@ int ir_launch_axpy(int storage, int64_t nslots, int mode, double s, double *X, v
     if (storage == 0) hipLaunchKernelGGL((k_ir_axpy<float>), grid, dim3(256), 0, st, nslots, mode, s, X, (float *)x);
     else if (storage == 1) hipLaunchKernelGGL((k_ir_axpy<bf16_t>), grid, dim3(256), 0, st, nslots, mode, s, X, (bf16_t *)x);
     else hipLaunchKernelGGL((k_ir_axpy<_Float16>), grid, dim3(256), 0, st, nslots, mode, s, X, (_Float16 *)x);
+    return (int)hipGetLastError();
+}
+int ir_launch_fold(int storage, int B, const CgArgs &a, int64_t nslots, void *stream)
+{
+    if (nslots <= 0) return 0;
+    hipStream_t st = (hipStream_t)stream;
+    const dim3 grid((unsigned)ir_rows(nslots));
+#define IR_FOLD(T_, B_)                                                                             \
+    hipLaunchKernelGGL((k_ir_fold<T_, B_>), grid, dim3(256), 0, st, a.info, (const double *)a.scal, nslots, a.x64, \
+                       (T_ *)a.x)
+    if (B == 8) {
+        if (storage == 0) IR_FOLD(float, 8);
+        else if (storage == 1) IR_FOLD(bf16_t, 8);
+        else IR_FOLD(_Float16, 8);
+    } else {
+        if (storage == 0) IR_FOLD(float, 4);
+        else if (storage == 1) IR_FOLD(bf16_t, 4);
+        else IR_FOLD(_Float16, 4);
+    }
+#undef IR_FOLD
     return (int)hipGetLastError();
 }
 int ir_launch_flux(int B, const CgArgs &a, int64_t nslots, int inlet_face, const double *X, double *partial,

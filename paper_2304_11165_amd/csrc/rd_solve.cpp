@@ -107,7 +107,7 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
         out[g].rel = bb > 0 ? sqrt(rr / bb) : 0.0;
         best[g] = out[g].rel;
         v[CG_SIGMA] = 1.0;
-        v[CG_SIGMA_NEW] = 1.0;
+        v[CG_SIGMA_PREV] = 1.0;
         if (!(bb > 0) || out[g].rel <= tol || max_iters <= 0) {
             v[CG_DONE] = 1.0;
             out[g].converged = out[g].rel <= tol;
@@ -139,6 +139,7 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
         // drifted from it, replaces it (residual replacement, van der Vorst and Ye 2000),
         // so the iteration is not held at the storage type's floor
         if (a.x64) {
+            if (!a.x64_direct) LAUNCHCHK(ir_launch_fold(storage, B, a, a.nb * (int64_t)B * B * B, st));
             LAUNCHCHK(cg_launch_res64(storage, B, a, 0, st));
             LAUNCHCHK(cg_launch_segsum(a, CG_CHECK, -1, -1, st));
         } else {
@@ -168,33 +169,29 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
                 // next scale: a power of 2 that brings the residual's RMS near 1
                 const double n_act = std::max(1.0, m_active(meta[g]));
                 const double rms = sqrt(std::max(v[CG_CHECK], 1e-300) / n_act);
-                v[CG_SIGMA_NEW] = ldexp(1.0, std::max(-60, std::min(60, (int)lround(-log2(rms)))));
+                const double sig = ldexp(1.0, std::max(-60, std::min(60, (int)lround(-log2(rms)))));
                 // replace the recursive residual once it has drifted from the true one by
                 // more than a quarter (van der Vorst and Ye replace only where the gap
                 // grows: every replacement costs the recursion some of its conjugacy)
                 const double rec = sqrt(std::max(v[CG_RR], 0.0)) / v[CG_SIGMA];
                 const double tru = sqrt(std::max(v[CG_CHECK], 0.0));
                 replace = replace || fabs(rec - tru) > 0.25 * tru;
-                rescale = rescale || v[CG_SIGMA_NEW] != v[CG_SIGMA];
+                rescale = rescale || sig != v[CG_SIGMA];
+                v[CG_SIGMA_PREV] = v[CG_SIGMA];  // what r and p hold until the kernel below
+                v[CG_SIGMA] = sig;
             }
         }
         if ((s = push_scal(a, hs, st)) != RD_OK) return s;
         if (a.x64 && live > 0 && (replace || rescale)) {
-            // residual replacement: r = sigma_new (b - A X) in FP64 and p rescaled, or only
+            // residual replacement: r = sigma (b - A X) in FP64 and p rescaled, or only
             // the rescaling of r and p; then rr of the stored r
             LAUNCHCHK(cg_launch_res64(storage, B, a, replace ? 2 : 3, st));
             LAUNCHCHK(cg_launch_segsum(a, CG_RR, -1, -1, st));
-            for (int g = 0; g < n; ++g) {
-                double *v = &hs[(size_t)g * CG_NSCAL];
-                v[CG_SIGMA] = v[CG_SIGMA_NEW];
-                HIPCHK(hipMemcpyAsync(a.scal + (size_t)g * CG_NSCAL + CG_SIGMA, &v[CG_SIGMA], sizeof(double),
-                                      hipMemcpyHostToDevice, st));
-            }
-            HIPCHK(hipStreamSynchronize(st));
         }
     }
     if (!want_tau) return RD_OK;
-    // steady flux through the two Dirichlet planes
+    // steady flux through the two Dirichlet planes (of the FP64 iterate rounded to x)
+    if (a.x64) LAUNCHCHK(ir_launch_axpy(storage, a.nb * (int64_t)B * B * B, 2, 0.0, a.x64, a.x, st));
     LAUNCHCHK(cg_launch_flux(storage, B, a, 2 * axis, st));
     LAUNCHCHK(cg_launch_segsum(a, CG_QIN, CG_QOUT, -1, st));
     if ((s = copy_scal(a, hs, st)) != RD_OK) return s;
@@ -288,6 +285,10 @@ extern "C" rd_status rd_sim_steady_state(rd_sim *sim, int axis, double rel_tol, 
     double *res = (double *)(sim->ws + L.res) + 40;
     LAUNCHCHK(ir_launch_axpy(st_, nslots, 0, 0.0, X, a.x, stream));
     a.x64 = X;
+    // FP32 storage: x accumulates the updates between checks (no FP64 traffic per
+    // iteration); 16-bit storage is too coarse for that and updates X directly
+    a.x64_direct = sim->storage == RD_FP32 ? 0 : 1;
+    if (!a.x64_direct) LAUNCHCHK(rd_launch_fill_u32(a.x, 0u, nslots, stream));  // FP32: one word a slot
     rd_status s = run_cg(a, st_, G.B, stream, axis, rel_tol, max_iters, meta, out, 2 * STALL_CHECKS, false);
     if (s != RD_OK) return s;
     const double rel = out[0].rel;
@@ -326,7 +327,7 @@ struct rd_batch {
     std::vector<uint64_t> mask;
     std::vector<uint8_t> code;
     std::vector<GeomInfo> ginfo;
-    size_t o_info = 0, o_mask = 0, o_code = 0, o_geom = 0, o_vec[5] = {0, 0, 0, 0, 0}, o_part = 0,
+    size_t o_info = 0, o_mask = 0, o_code = 0, o_geom = 0, o_vec[5] = {0, 0, 0, 0, 0}, o_x64 = 0, o_part = 0,
            o_scal = 0, total = 0;
     char *ws = nullptr;
     hipStream_t stream = nullptr;
@@ -391,6 +392,7 @@ extern "C" rd_status rd_batch_create(const rd_geometry *const *geoms, int n, rd_
         bt->o_vec[v] = o;
         o = al256(o + es * nbs * (size_t)B * B * B);
     }
+    bt->o_x64 = o; o = al256(o + sizeof(double) * nbs * (size_t)B * B * B);  // FP64 iterate
     bt->o_part = o; o = al256(o + sizeof(double) * 2 * nbs);
     bt->o_scal = o; o = al256(o + sizeof(double) * CG_NSCAL * (size_t)n);
     bt->total = o;
@@ -470,7 +472,13 @@ extern "C" rd_status rd_batch_tortuosity(rd_batch *b, int axis, double rel_tol, 
                                          b->o_vec[2] - b->o_vec[1], b->stream, perc);
         if (s0 != RD_OK) return s0;
         for (int i = 0; i < n; ++i) meta[i].percolates = perc[(size_t)i] != 0;
-        rd_status s = run_cg(a, (int)b->storage, b->B, b->stream, axis, rel_tol, max_iters, meta, out);
+        // FP64 iterate with residual replacement, as for one geometry
+        a.x64 = (double *)(b->ws + b->o_x64);
+        LAUNCHCHK(ir_launch_axpy((int)b->storage, nslots, 0, 0.0, a.x64, a.x, b->stream));
+        a.x64_direct = b->storage == RD_FP32 ? 0 : 1;
+        if (!a.x64_direct) LAUNCHCHK(rd_launch_fill_u32(a.x, 0u, nslots, b->stream));
+        rd_status s = run_cg(a, (int)b->storage, b->B, b->stream, axis, rel_tol, max_iters, meta, out,
+                             2 * STALL_CHECKS, true);
         if (s != RD_OK) return s;
     } else {
         out.assign(n, CgOut());

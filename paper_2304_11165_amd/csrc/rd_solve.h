@@ -17,8 +17,8 @@ enum {
     CG_CHECK = 7,
     CG_QIN = 8,
     CG_QOUT = 9,
-    CG_SIGMA = 10,      // FP64 iterate: r and p hold sigma times the true residual / direction
-    CG_SIGMA_NEW = 11,  // the scale the next residual replacement switches to (a power of 2)
+    CG_SIGMA = 10,       // FP64 iterate: r and p hold sigma times the true residual / direction
+    CG_SIGMA_PREV = 11,  // the scale r and p hold before a pending rescaling (powers of 2)
     CG_NSCAL = 12
 };
 
@@ -31,7 +31,10 @@ struct CgArgs {
     int ngeom;
     uint32_t dir;          // Dirichlet faces (inlet | outlet)
     void *x, *r, *p, *ap;  // storage type T, nb * B^3 each (ap: B = 4 only)
-    double *x64;           // FP64 iterate (single geometry), or NULL: the iterate is x
+    double *x64;           // FP64 iterate, or NULL: the iterate is x
+    int x64_direct;        // with x64: 1 = every update goes to x64 (16 bytes per voxel);
+                           // 0 = x accumulates the updates and is folded into x64 at
+                           // every check (the iterate is x64 + x / sigma)
     void *p2;              // second p buffer (B = 8: the fused p update writes here)
     double *partial;       // [nb][2]
     double *scal;          // [ngeom][CG_NSCAL]
@@ -60,6 +63,8 @@ int ir_rows(int64_t nslots);
 // store 2 writes sigma_new r to r and rescales p; store 3 only rescales r and p
 int cg_launch_res64(int storage, int B, const CgArgs &a, int store, void *stream);
 int ir_launch_axpy(int storage, int64_t nslots, int mode, double s, double *X, void *x, void *stream);
+// x64 += x / sigma (per geometry), x = 0
+int ir_launch_fold(int storage, int B, const CgArgs &a, int64_t nslots, void *stream);
 int ir_launch_flux(int B, const CgArgs &a, int64_t nslots, int inlet_face, const double *X, double *partial,
                    void *stream);
 int cg_launch_initial_guess(int storage, int B, const CgArgs &a, int axis, int64_t nslots, uint32_t *par,
