@@ -999,6 +999,116 @@ __global__ __launch_bounds__(256) void k_res64(CgArgs a, int store)
     block_sum2<B>(rr, bb, a.partial, b, b < a.nb);
 }
 
+// The FP64 true residual of the iterate X + x / sigma (x: the FP32 updates not yet
+// folded, SPLIT) or X, for 8^3 blocks in the column form: one wave per block, lane
+// (lx, ly) walking its z-column, X staged plane by plane in an FP64 LDS tile.  Same sums
+// as k_res64 (difference form, order -x,+x,-y,+y,-z,+z); read-only; per-block partials
+// (r.r, b.b).
+template <typename T, bool SPLIT>
+__global__ __launch_bounds__(256) void k_res64c(CgArgs a)
+{
+    __shared__ double tile[4][100];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int b = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + wv);
+    if (b >= a.nb) return;
+    const BlockInfo bi = a.info[b];
+    int bx, by, bz, gid;
+    block_pos(bi, &bx, &by, &bz, &gid);
+    const double inv_s = SPLIT ? 1.0 / a.scal[gid * CG_NSCAL + CG_SIGMA] : 0.0;
+    const T *xv = (const T *)a.x;
+    const int64_t base = (int64_t)b * 512;
+    const int lx = lane & 7, ly = lane >> 3;
+    const uint64_t *rec = a.mask + (int64_t)b * 16;
+    uint64_t Wo[8], Wf[6];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) Wo[z] = rec[z];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) Wf[f] = rec[8 + f];
+    double c[8], hv[6];
+    unsigned cd[8];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        const int64_t i = base + z * 64 + lane;
+        c[z] = 0.0;
+        cd[z] = 0u;
+        if (lane_bit(Wo[z])) {
+            c[z] = a.x64[i];
+            if (SPLIT) c[z] += (double)rd_ld(xv, i) * inv_s;
+            cd[z] = (unsigned)a.code[i];
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        int ns;
+        switch (f) {
+        case 0: ns = (ly * 8 + lx) * 8 + 7; break;
+        case 1: ns = (ly * 8 + lx) * 8 + 0; break;
+        case 2: ns = (ly * 8 + 7) * 8 + lx; break;
+        case 3: ns = (ly * 8 + 0) * 8 + lx; break;
+        case 4: ns = (7 * 8 + ly) * 8 + lx; break;
+        default: ns = (0 * 8 + ly) * 8 + lx; break;
+        }
+        const int n = bi.nbr[f];
+        const int64_t hb = (int64_t)(n >= 0 ? n : b) * 512 + ns;
+        hv[f] = 0.0;
+        if (lane_bit(Wf[f])) {
+            hv[f] = a.x64[hb];
+            if (SPLIT) hv[f] += (double)rd_ld(xv, hb) * inv_s;
+        }
+    }
+    const GeomInfo g = a.geom[gid];
+    const int gx = bx * 8 + lx, gy = by * 8 + ly;
+    const bool bnd = bx == 0 || by == 0 || bz == 0 || bx * 8 + 8 >= g.nx || by * 8 + 8 >= g.ny ||
+                     bz * 8 + 8 >= g.nz;
+    double *ts = tile[wv];
+    double rr = 0.0, bb = 0.0;
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        ts[(ly + 1) * 10 + (lx + 1)] = c[z];
+        if (ly == z) {
+            ts[(lx + 1) * 10 + 0] = hv[0];
+            ts[(lx + 1) * 10 + 9] = hv[1];
+            ts[0 * 10 + (lx + 1)] = hv[2];
+            ts[9 * 10 + (lx + 1)] = hv[3];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const unsigned code = cd[z];
+        const int gz = bz * 8 + z;
+        const unsigned onf = bnd ? ((gx == 0 ? 1u : 0u) | (gx == g.nx - 1 ? 2u : 0u) | (gy == 0 ? 4u : 0u) |
+                                    (gy == g.ny - 1 ? 8u : 0u) | (gz == 0 ? 16u : 0u) | (gz == g.nz - 1 ? 32u : 0u))
+                                 : 0u;
+        if ((code & 64u) && !(onf & a.dir)) {
+            const double *q = &ts[(ly + 1) * 10 + (lx + 1)];
+            const double nv[6] = {q[-1], q[1], q[-10], q[10], z == 0 ? hv[4] : c[z > 0 ? z - 1 : 0],
+                                  z == 7 ? hv[5] : c[z < 7 ? z + 1 : 7]};
+            double s = 0.0, bp = 0.0;
+#pragma unroll
+            for (int d = 0; d < 6; ++d) {
+                if (!((code >> d) & 1u)) continue;
+                s += nv[d] - c[z];
+                if (bnd) {
+                    const int ex = d == 0 ? -1 : d == 1 ? 1 : 0, ey = d == 2 ? -1 : d == 3 ? 1 : 0,
+                              ez = d == 4 ? -1 : d == 5 ? 1 : 0;
+                    if (on_dirichlet(a.dir, gx + ex, gy + ey, gz + ez, g.nx, g.ny, g.nz)) bp += nv[d];
+                }
+            }
+            rr += s * s;
+            bb += bp * bp;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    rr = wave_sum(rr);
+    bb = wave_sum(bb);
+    if (lane == 0) {
+        a.partial[(int64_t)b * 2 + 0] = rr;
+        a.partial[(int64_t)b * 2 + 1] = bb;
+    }
+}
+
 // X += x / sigma of the slot's geometry, then x = 0 (every slot): the updates that x
 // accumulated since the last check join the FP64 iterate
 template <typename T, int B>
@@ -1175,6 +1285,21 @@ int cg_launch_initial_guess(int storage, int B, const CgArgs &a, int axis, int64
 int ir_rows(int64_t nslots) { return (int)((nslots + 255) / 256); }
 int cg_launch_res64(int storage, int B, const CgArgs &a, int store, void *stream)
 {
+    if (B == 8 && store == 0) {  // the check: column form, read-only, of X + x / sigma when split
+        const dim3 grid((unsigned)std::max(1, (a.nb + 3) / 4));
+        hipStream_t st = (hipStream_t)stream;
+        const bool split = !a.x64_direct;
+#define RES64C(T_)                                                                                 \
+    do {                                                                                           \
+        if (split) hipLaunchKernelGGL((k_res64c<T_, true>), grid, dim3(256), 0, st, a);              \
+        else hipLaunchKernelGGL((k_res64c<T_, false>), grid, dim3(256), 0, st, a);                  \
+    } while (0)
+        if (storage == 0) RES64C(float);
+        else if (storage == 1) RES64C(bf16_t);
+        else RES64C(_Float16);
+#undef RES64C
+        return (int)hipGetLastError();
+    }
     CG_DISPATCH(storage, B, k_res64, grid_for(B, a.nb), stream, a, store);
 }
 int ir_launch_axpy(int storage, int64_t nslots, int mode, double s, double *X, void *x, void *stream)

@@ -139,9 +139,12 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
         // drifted from it, replaces it (residual replacement, van der Vorst and Ye 2000),
         // so the iteration is not held at the storage type's floor
         if (a.x64) {
-            if (!a.x64_direct) LAUNCHCHK(ir_launch_fold(storage, B, a, a.nb * (int64_t)B * B * B, st));
+            // B = 8 reads the unfolded iterate; B = 4 folds first.  The fold then puts the
+            // updates of the last 25 iterations into X and clears x.
+            if (B != 8 && !a.x64_direct) LAUNCHCHK(ir_launch_fold(storage, B, a, a.nb * (int64_t)B * B * B, st));
             LAUNCHCHK(cg_launch_res64(storage, B, a, 0, st));
             LAUNCHCHK(cg_launch_segsum(a, CG_CHECK, -1, -1, st));
+            if (B == 8 && !a.x64_direct) LAUNCHCHK(ir_launch_fold(storage, B, a, a.nb * (int64_t)B * B * B, st));
         } else {
             LAUNCHCHK(cg_launch_residual(storage, B, a, 0, st));
             LAUNCHCHK(cg_launch_segsum(a, CG_CHECK, -1, -1, st));
@@ -169,7 +172,10 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
                 // next scale: a power of 2 that brings the residual's RMS near 1
                 const double n_act = std::max(1.0, m_active(meta[g]));
                 const double rms = sqrt(std::max(v[CG_CHECK], 1e-300) / n_act);
-                const double sig = ldexp(1.0, std::max(-60, std::min(60, (int)lround(-log2(rms)))));
+                // (only FP16 needs it: FP32 and BF16 have FP32's exponent range)
+                const double sig = storage == RD_FP16
+                                       ? ldexp(1.0, std::max(-60, std::min(60, (int)lround(-log2(rms)))))
+                                       : 1.0;
                 // replace the recursive residual once it has drifted from the true one by
                 // more than a quarter (van der Vorst and Ye replace only where the gap
                 // grows: every replacement costs the recursion some of its conjugacy)

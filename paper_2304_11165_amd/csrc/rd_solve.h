@@ -60,7 +60,8 @@ int cg_launch_segsum(const CgArgs &a, int slot0, int slot1, int mode, void *stre
 // X_p - X_q over Dirichlet voxels p and their free neighbours q.
 int ir_rows(int64_t nslots);
 // r = b - A x64 in FP64 (per-block partials (r.r, b.b)); store 1 writes it to r and p;
-// store 2 writes sigma_new r to r and rescales p; store 3 only rescales r and p
+// store 2 writes sigma r to r and rescales p; store 3 only rescales r and p.  B = 8 with
+// store 0 (the check) evaluates the unfolded iterate x64 + x / sigma when x64_direct is 0.
 int cg_launch_res64(int storage, int B, const CgArgs &a, int store, void *stream);
 int ir_launch_axpy(int storage, int64_t nslots, int mode, double s, double *X, void *x, void *stream);
 // x64 += x / sigma (per geometry), x = 0
