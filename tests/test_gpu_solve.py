@@ -115,6 +115,30 @@ def test_batch_matches_single_and_oracle(rd, oracle_mod):
         assert tau[i] == pytest.approx(tau_o, rel=1e-4)
         assert tau[i] == pytest.approx(res["tau"], rel=1e-5)
     assert tau[-1] == pytest.approx(1.0, rel=1e-5)
+    assert np.all(np.asarray(rel) <= 1e-6)  # every geometry reaches the tolerance
+
+
+@pytest.mark.parametrize("B", [4, 8])
+def test_batch_degenerate_members(rd, oracle_mod, B):
+    """A batch holding an empty geometry, one that does not percolate, a single voxel
+    and a normal packing: the degenerate members give tau = inf without disturbing the
+    others, whose tau equals the oracle's."""
+    empty = np.zeros((9, 10, 11), np.uint8)
+    blocked = W.slab_box(12, 6, 6)
+    blocked[:, :, 5] = 0
+    one = np.zeros((5, 5, 5), np.uint8)
+    one[2, 2, 2] = 1
+    pack, _ = W.boolean_spheres(21, 0.55, 2.0, 4.0, seed=33)
+    imgs = [empty, pack, blocked, one, pack]
+    geoms = [rd.Geometry(im, None, 1.0, B) for im in imgs]
+    bt = rd.Batch(geoms).bind()
+    tau, rel, it = bt.tortuosity(0, 1e-8, 20000)
+    uo, _, _ = oracle_mod.steady_state(pack, 0, "cg", tol=1e-12)
+    tau_o = oracle_mod.tortuosity_from_field(pack, 0, uo)[0]
+    print(f"B={B}: tau {list(tau)}, rel {list(rel)}, iters {list(it)}; oracle {tau_o:.10f}")
+    assert math.isinf(tau[0]) and math.isinf(tau[2]) and math.isinf(tau[3])
+    assert tau[1] == pytest.approx(tau_o, rel=1e-7) and tau[4] == tau[1]
+    assert rel[1] <= 1e-8 and rel[4] <= 1e-8
 
 
 def _expected_guess(img, axis):
