@@ -231,6 +231,17 @@ void rd_sim_destroy(rd_sim *sim);
  * (fields zero, Dirichlet values applied): call it before rd_sim_set_field.
  * *best_ms (may be NULL) receives the mean time per step of the chosen setting. */
 rd_status rd_sim_autotune(rd_sim *sim, double dt, int64_t trial_steps, double *best_ms);
+/* rd_sim_autotune with a result cache, for callers that bind the same geometry again
+ * and should not pay the trials every time.  The key
+ * covers the GPU (architecture and compute units), storage type, species count,
+ * reactions, Robin walls and the geometry (extents, block edge, every activity word).
+ * A cache hit applies the stored launch configuration without trials and leaves the
+ * fields untouched; a miss runs rd_sim_autotune (which resets the fields) and appends
+ * one text line "rdtune1 <key> <kernel> <xcd> <graph> <wg_per_cu> <graph_steps> <ms>" to
+ * cache_path (created if missing; the last line of a key wins).  *from_cache and
+ * *best_ms may be NULL.  RD_ERR_ARG if the file cannot be written. */
+rd_status rd_sim_autotune_cached(rd_sim *sim, double dt, int64_t trial_steps, const char *cache_path,
+                                 int *from_cache, double *best_ms);
 /* Autotune each candidate simulation (for example the same image indexed with 4^3 and
  * with 8^3 blocks, same species and parameters) and report the fastest:
  * *best_index, and ms_per_step[n] (may be NULL). */

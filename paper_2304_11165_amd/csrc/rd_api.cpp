@@ -1,6 +1,7 @@
 // rd_api.cpp -- the C ABI: validation, workspace layout, launch driver, reductions.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -748,6 +749,92 @@ extern "C" rd_status rd_sim_autotune(rd_sim *sim, double dt, int64_t trial_steps
     if (best_ms) *best_ms = best;
     // the trials advanced the fields: start again from zero + Dirichlet values
     return sim->upload();
+}
+
+namespace {
+// Key of an autotuning result: the GPU (architecture name and compute-unit count), the
+// storage type, species, reactions and Robin walls, and the geometry (extents, block edge,
+// every activity mask word), folded with FNV-1a 64.
+uint64_t tune_key(const rd_sim *sim)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void *p, size_t n) {
+        const unsigned char *c = (const unsigned char *)p;
+        for (size_t i = 0; i < n; ++i) {
+            h ^= c[i];
+            h *= 1099511628211ull;
+        }
+    };
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        mix(prop.gcnArchName, strnlen(prop.gcnArchName, sizeof(prop.gcnArchName)));
+        mix(&prop.multiProcessorCount, sizeof(prop.multiProcessorCount));
+    }
+    const rd_geometry &g = *sim->g;
+    const int64_t dims[5] = {g.nx, g.ny, g.nz, (int64_t)g.B, g.nb()};
+    mix(dims, sizeof(dims));
+    const int meta[3] = {(int)sim->storage, sim->S, (int)sim->reactions.size()};
+    mix(meta, sizeof(meta));
+    for (int s = 0; s < sim->S; ++s) {
+        const int robin = sim->robin[s] != 0.0;
+        mix(&robin, sizeof(robin));
+    }
+    if (!g.mask.empty()) mix(g.mask.data(), g.mask.size() * sizeof(uint64_t));
+    return h;
+}
+}  // namespace
+
+extern "C" rd_status rd_sim_autotune_cached(rd_sim *sim, double dt, int64_t trial_steps, const char *cache_path,
+                                            int *from_cache, double *best_ms)
+{
+    if (!sim || !cache_path) return rd_fail(RD_ERR_ARG, "NULL argument");
+    if (!sim->ws) return rd_fail(RD_ERR_STATE, "bind a workspace first");
+    const uint64_t key = tune_key(sim);
+    char want[32];
+    snprintf(want, sizeof(want), "%016llx", (unsigned long long)key);
+    // the last entry with this key wins
+    bool found = false;
+    LaunchCfg c{};
+    double ms = 0.0;
+    if (FILE *f = fopen(cache_path, "r")) {
+        char line[256];
+        while (fgets(line, sizeof(line), f)) {
+            char tag[16], k[32];
+            int kernel, xcd, graph, wg, gsteps;
+            double m;
+            if (sscanf(line, "%15s %31s %d %d %d %d %d %lf", tag, k, &kernel, &xcd, &graph, &wg, &gsteps, &m) == 8 &&
+                strcmp(tag, "rdtune1") == 0 && strcmp(k, want) == 0 && kernel >= 0 && kernel <= 3 && wg >= 1 &&
+                gsteps >= 1 && !(sim->g->B == 4 && kernel != 0)) {
+                c = {kernel, xcd != 0, graph != 0, wg, gsteps};
+                ms = m;
+                found = true;
+            }
+        }
+        fclose(f);
+    }
+    if (found) {
+        sim->kernel = c.kernel;
+        sim->xcd_map = c.xcd;
+        sim->use_graph = c.graph;
+        sim->wg_per_cu = c.wg;
+        sim->graph_steps = c.gsteps;
+        sim->invalidate_graphs();
+        if (from_cache) *from_cache = 1;
+        if (best_ms) *best_ms = ms;
+        return RD_OK;
+    }
+    rd_status s = rd_sim_autotune(sim, dt, trial_steps, &ms);
+    if (s != RD_OK) return s;
+    FILE *f = fopen(cache_path, "a");
+    if (!f) return rd_fail(RD_ERR_ARG, std::string("cannot append to the autotuning cache ") + cache_path);
+    const int ok = fprintf(f, "rdtune1 %s %d %d %d %d %d %.9g\n", want, sim->kernel, sim->xcd_map ? 1 : 0,
+                           sim->use_graph ? 1 : 0, sim->wg_per_cu, sim->graph_steps, ms);
+    if (fclose(f) != 0 || ok < 0)
+        return rd_fail(RD_ERR_ARG, std::string("cannot write the autotuning cache ") + cache_path);
+    if (from_cache) *from_cache = 0;
+    if (best_ms) *best_ms = ms;
+    return RD_OK;
 }
 
 extern "C" rd_status rd_autotune_pick(rd_sim *const *sims, int n, double dt, int64_t trial_steps,

@@ -73,6 +73,7 @@ _SIGS = {
     "rd_sim_set_reaction_rate": ([P, ci, f64], ci),
     "rd_sim_destroy": ([P], None),
     "rd_sim_autotune": ([P, f64, i64, P], ci),
+    "rd_sim_autotune_cached": ([P, f64, i64, ctypes.c_char_p, P, P], ci),
     "rd_autotune_pick": ([P, ci, f64, i64, P, P], ci),
     "rd_sim_get_launch": ([P, P, P, P, P, P], ci),
     "rd_batch_create": ([P, ci, ci, P], ci),
@@ -236,11 +237,21 @@ class Sim:
         _check(_lib.rd_sim_set_launch(self.handle, int(graph_steps), int(bool(use_graph)),
                                       int(bool(xcd_map))), "rd_sim_set_launch")
 
-    def autotune(self, dt, trial_steps=200):
-        """Pick the fastest launch configuration (resets the fields); returns ms/step."""
+    def autotune(self, dt, trial_steps=200, cache_path=None):
+        """Pick the fastest launch configuration; returns ms/step.  Without a cache the
+        trials reset the fields; with `cache_path` a stored result for the same GPU,
+        storage, species and geometry is applied without trials (see
+        rd_sim_autotune_cached), else the trials run and are appended to the file."""
         ms = f64()
-        _check(_lib.rd_sim_autotune(self.handle, float(dt), int(trial_steps), ctypes.byref(ms)),
-               "rd_sim_autotune")
+        if cache_path is None:
+            _check(_lib.rd_sim_autotune(self.handle, float(dt), int(trial_steps), ctypes.byref(ms)),
+                   "rd_sim_autotune")
+            return ms.value
+        hit = ci()
+        _check(_lib.rd_sim_autotune_cached(self.handle, float(dt), int(trial_steps),
+                                           os.fsencode(str(cache_path)), ctypes.byref(hit),
+                                           ctypes.byref(ms)), "rd_sim_autotune_cached")
+        self.last_tune_from_cache = bool(hit.value)
         return ms.value
 
     def get_launch(self):

@@ -335,3 +335,36 @@ def test_autotune_resets_and_matches(rd):
         assert s.balance(1)["mass"] == 0.0  # reset: B is zero everywhere
         s.step(w.dt, 150)
         np.testing.assert_array_equal(fields(s, 2), want)
+
+
+def test_autotune_cache(rd, tmp_path):
+    """A tuned launch is stored under a key of GPU, storage, species and geometry: the
+    same geometry bound again gets it without trials, another geometry does not, and
+    the cached launch still gives the default launch's bits."""
+    w = W.workload("soil512", small=True)
+    img, _ = W.workload_geometry("soil512", small=True)
+    cache = tmp_path / "tune.txt"
+
+    def sim(image):
+        return make_gpu(rd, image, w.species_D, robin=w.robin, dirichlet=w.dirichlet,
+                        reactions=w.reactions)[1]
+
+    s1 = sim(img)
+    ms1 = s1.autotune(w.dt, 30, cache_path=cache)
+    assert not s1.last_tune_from_cache and ms1 > 0
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("rdtune1 ")
+    s2 = sim(img)
+    ms2 = s2.autotune(w.dt, 30, cache_path=cache)
+    assert s2.last_tune_from_cache and ms2 == pytest.approx(ms1, rel=1e-5)
+    assert s2.get_launch() == s1.get_launch()
+    other = img.copy()
+    other[0, 0, 0] = 1 - other[0, 0, 0]
+    s3 = sim(other)
+    s3.autotune(w.dt, 30, cache_path=cache)
+    assert not s3.last_tune_from_cache and len(cache.read_text().splitlines()) == 2
+    _, ref = make_gpu(rd, img, w.species_D, robin=w.robin, dirichlet=w.dirichlet,
+                      reactions=w.reactions)
+    ref.step(w.dt, 100)
+    s2.step(w.dt, 100)
+    np.testing.assert_array_equal(fields(s2, 2), fields(ref, 2))
