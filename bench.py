@@ -52,6 +52,8 @@ def parse():
     p.add_argument("--steady-size", type=int, default=1024, help="edge of the foam volume")
     p.add_argument("--steady-forms", default="fp32", help="storage types of the steady form")
     p.add_argument("--steady-tol", type=float, default=1e-8)
+    p.add_argument("--adjoint", type=int, default=0,
+                   help="1: time the checkpointed adjoint on the 256^3 diffusion-decay packing")
     p.add_argument("--cpu-steps", type=int, default=0,
                    help="oracle steps in the CPU sample (0: as many as fit in --cpu-seconds)")
     p.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -231,6 +233,47 @@ def steady_form(torch, rd, W, size, axes, forms, tol, stream):
     return out
 
 
+def adjoint_form(torch, rd, W, stream):
+    """Checkpointed adjoint on the 256^3 diffusion-decay packing (p = 0.5): the target is
+    the final field of a run with D = 1, k = 0.01; the gradient of the L2 misfit of the
+    run with D = 0.8, k = 0.02 (2000 steps, checkpoints every 100)."""
+    w = W.workload("decay256")
+    img, _ = W.workload_geometry("decay256")
+    geom = rd.Geometry(img, None, w.dx, w.block_edge)
+    st = geom.stats()
+    n, k = w.steps, 100
+    with torch.cuda.stream(stream):
+        sim = rd.Sim(geom, "fp32")
+        sim.add_species(1.0)
+        sim.add_reaction(0, -1, 0.01)
+        sim.set_dirichlet(0, 0, 1.0)
+        sim.bind(features=rd.RD_WS_ADJOINT, checkpoint_slots=(n + k - 1) // k + k - 1, stream=stream)
+        sim.step(w.dt, n)
+        target = sim.get_field(0).clone()
+        sim.set_species_D(0, w.species_D[0])
+        sim.set_reaction_rate(0, 0.02)
+        zero = torch.zeros_like(target)
+        sim.set_field(0, zero)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(w.dt, n)
+        torch.cuda.synchronize()
+        fwd = time.perf_counter() - t0
+        sim.set_field(0, zero)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss, gD, gk = sim.adjoint(target, n, w.dt, k, seed_is_target=True)
+        torch.cuda.synchronize()
+        adj = time.perf_counter() - t0
+    log(f"adjoint: forward {fwd * 1e3:.1f} ms, forward with checkpoints + recompute + backward "
+        f"{adj * 1e3:.1f} ms")
+    return {"workload": "decay256", "n_active": st["n_active"], "steps": n, "checkpoint_every": k,
+            "forward_seconds": fwd, "adjoint_seconds": adj, "adjoint_over_forward": adj / fwd,
+            "loss": loss, "dL_dD": gD, "dL_drate": gk,
+            "note": "adjoint_seconds: forward with checkpoints, recompute of each segment, "
+                    "backward sweep; FP32 fields, FP64 gradient sums"}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -376,6 +419,9 @@ def main():
         out["forms"]["steady"] = steady_form(torch, rd, W, a.steady_size, a.steady_axes,
                                              [f for f in a.steady_forms.split(",") if f],
                                              a.steady_tol, stream)
+
+    if a.adjoint and not a.profile:
+        out["forms"]["adjoint"] = adjoint_form(torch, rd, W, stream)
 
     if not a.no_cpu_baseline and not a.profile:
         import oracle

@@ -129,11 +129,11 @@ rd_status rd_sim_clear_dirichlet(rd_sim *sim, int species);
  * identical for every choice. */
 rd_status rd_sim_set_launch(rd_sim *sim, int graph_steps, int use_graph, int xcd_map);
 /* Step kernel for B = 8 (ignored for B = 4, which always runs one wave per block):
- *   kernel = 0 (default): one 256-thread workgroup per block;
+ *   kernel = 0: one 256-thread workgroup per block;
  *   kernel = 1: persistent, a fixed grid of wg_per_cu * (compute units) workgroups
  *               that walk the block list and prefetch the next block while
  *               computing the current one;
- *   kernel = 2: one wave per block, each lane walking a z-column of 8 voxels;
+ *   kernel = 2 (default): one wave per block, each lane walking a z-column of 8 voxels;
  *   kernel = 3: as 2, with the x faces of x-adjacent blocks of a workgroup handed
  *               over through LDS instead of being re-read from memory.
  * Results are bitwise identical.  RD_ERR_ARG for kernel outside 0..3 or wg_per_cu

@@ -63,7 +63,7 @@ struct rd_sim {
     int graph_steps = 32;
     bool use_graph = true;
     bool xcd_map = true;
-    int kernel = 0;       // B = 8 step kernel: 0 workgroup per block, 1 persistent, 2 z-column,
+    int kernel = 2;       // B = 8 step kernel: 0 workgroup per block, 1 persistent, 2 z-column,
                           // 3 z-column with in-workgroup x-face exchange
     int wg_per_cu = 8;    // resident workgroups per CU of the persistent grid
     int n_cu = 256;       // compute units of the bound device
