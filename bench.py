@@ -168,19 +168,28 @@ def batched_form(torch, rd, W, count, max_edge, stream):
     U{64..max_edge}, porosity U(0.3, 0.7)), all in one set of CG launches."""
     t0 = time.perf_counter()
     geoms_np = W.batch_geometries(count, seed=4, nmin=64, nmax=max_edge)
-    geoms = [rd.Geometry(img, None, 1.0, 8) for img, _ in geoms_np]
-    n_active = sum(g.stats()["n_active"] for g in geoms)
-    log(f"batch of {count}: generated in {time.perf_counter() - t0:.1f}s, {n_active} active voxels")
+    edges = (8, 4)
+    cands = {B: [rd.Geometry(img, None, 1.0, B) for img, _ in geoms_np] for B in edges}
+    n_active = sum(g.stats()["n_active"] for g in cands[8])
+    log(f"batch of {count}: generated and indexed in {time.perf_counter() - t0:.1f}s, {n_active} active voxels")
     with torch.cuda.stream(stream):
-        bt = rd.Batch(geoms).bind(stream=stream)
+        # block edge by the batch autotuner (50 CG iterations per candidate)
+        batches = [rd.Batch(cands[B]).bind(stream=stream) for B in edges]
+        best, trial_ms = rd.batch_autotune_pick(batches, 0, 50)
+        bt, geoms, block_edge = batches[best], cands[edges[best]], edges[best]
+        del batches
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         tau, rel, it = bt.tortuosity(0, 1e-6, 20000)
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
     voxel_iters = float(sum(g.stats()["n_active"] * int(i) for g, i in zip(geoms, it)))
+    log(f"batched: block edge {block_edge} (trial ms per iteration: "
+        f"{', '.join(f'{B}^3 {m:.3f}' for B, m in zip(edges, trial_ms))})")
     return {
         "geometries": count,
+        "block_edge": block_edge,
+        "trial_ms_per_iteration": {f"{B}^3": float(m) for B, m in zip(edges, trial_ms)},
         "edges": [int(info["n"]) for _, info in geoms_np],
         "seconds": secs,
         "active_voxel_cg_iterations_per_s": voxel_iters / secs,

@@ -265,6 +265,13 @@ rd_status rd_batch_bind(rd_batch *b, void *dev_workspace, size_t bytes, void *st
  * tau[n], rel_residual[n], iters[n] are host arrays (any may be NULL). */
 rd_status rd_batch_tortuosity(rd_batch *b, int axis, double rel_tol, int64_t max_iters,
                               double *tau, double *rel_residual, int64_t *iters);
+/* Block-edge autotuning of a batch: bound candidate batches of the same geometries
+ * indexed differently (for example 4^3 and 8^3 blocks) each run trial_iters CG
+ * iterations along `axis` (rounded up to the 25-iteration check interval); the wall time
+ * per iteration, net of labelling and initial guess, goes to ms_per_iter[n] (may be NULL)
+ * and the fastest index to *best_index.  The workspaces' contents are overwritten. */
+rd_status rd_batch_autotune_pick(rd_batch *const *batches, int n, int axis, int64_t trial_iters,
+                                 int *best_index, double *ms_per_iter);
 void rd_batch_destroy(rd_batch *b);
 
 #ifdef __cplusplus

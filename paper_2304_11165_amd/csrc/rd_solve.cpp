@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <limits>
 #include <new>
 #include <vector>
@@ -437,8 +438,11 @@ extern "C" rd_status rd_batch_bind(rd_batch *b, void *dev_ws, size_t bytes, void
     return RD_OK;
 }
 
-extern "C" rd_status rd_batch_tortuosity(rd_batch *b, int axis, double rel_tol, int64_t max_iters,
-                                         double *tau, double *rel_residual, int64_t *iters)
+namespace {
+// Labelling, initial guess and CG of every geometry of a bound batch (want_tau: the flux
+// and tau at the end).
+rd_status batch_cg(rd_batch *b, int axis, double rel_tol, int64_t max_iters, bool want_tau,
+                   std::vector<CgOut> &out)
 {
     if (!b) return rd_fail(RD_ERR_ARG, "batch is NULL");
     if (!b->ws) return rd_fail(RD_ERR_STATE, "bind a workspace first");
@@ -469,7 +473,6 @@ extern "C" rd_status rd_batch_tortuosity(rd_batch *b, int axis, double rel_tol, 
     a.p2 = b->ws + b->o_vec[4];
     a.partial = (double *)(b->ws + b->o_part);
     a.scal = (double *)(b->ws + b->o_scal);
-    std::vector<CgOut> out;
     if (b->nb > 0) {
         std::vector<char> perc;
         const int64_t nslots = b->nb * (int64_t)NS;
@@ -483,13 +486,22 @@ extern "C" rd_status rd_batch_tortuosity(rd_batch *b, int axis, double rel_tol, 
         LAUNCHCHK(ir_launch_axpy((int)b->storage, nslots, 0, 0.0, a.x64, a.x, b->stream));
         a.x64_direct = b->storage == RD_FP32 ? 0 : 1;
         if (!a.x64_direct) LAUNCHCHK(rd_launch_fill_u32(a.x, 0u, nslots, b->stream));
-        rd_status s = run_cg(a, (int)b->storage, b->B, b->stream, axis, rel_tol, max_iters, meta, out,
-                             2 * STALL_CHECKS, true);
-        if (s != RD_OK) return s;
-    } else {
-        out.assign(n, CgOut());
-        for (auto &o : out) o.tau = std::numeric_limits<double>::infinity();
+        return run_cg(a, (int)b->storage, b->B, b->stream, axis, rel_tol, max_iters, meta, out,
+                      2 * STALL_CHECKS, want_tau);
     }
+    out.assign(n, CgOut());
+    for (auto &o : out) o.tau = std::numeric_limits<double>::infinity();
+    return RD_OK;
+}
+}  // namespace
+
+extern "C" rd_status rd_batch_tortuosity(rd_batch *b, int axis, double rel_tol, int64_t max_iters,
+                                         double *tau, double *rel_residual, int64_t *iters)
+{
+    std::vector<CgOut> out;
+    rd_status s = batch_cg(b, axis, rel_tol, max_iters, true, out);
+    if (s != RD_OK) return s;
+    const int n = (int)b->geoms.size();
     bool all = true;
     for (int i = 0; i < n; ++i) {
         if (tau) tau[i] = out[i].tau;
@@ -498,6 +510,40 @@ extern "C" rd_status rd_batch_tortuosity(rd_batch *b, int axis, double rel_tol, 
         all = all && out[i].converged;
     }
     if (!all) return rd_fail(RD_ERR_NOT_CONVERGED, "some geometries stopped above the tolerance");
+    return RD_OK;
+}
+
+extern "C" rd_status rd_batch_autotune_pick(rd_batch *const *batches, int n, int axis, int64_t trial_iters,
+                                            int *best_index, double *ms_per_iter)
+{
+    if (!batches || n <= 0 || !best_index) return rd_fail(RD_ERR_ARG, "need batches and best_index");
+    if (trial_iters < 1) return rd_fail(RD_ERR_ARG, "trial_iters >= 1");
+    *best_index = -1;
+    double best = 1e300;
+    for (int i = 0; i < n; ++i) {
+        // wall time of trial_iters iterations: a run with them minus one without
+        // (labelling, initial guess and the first residual are in both)
+        // (a first run without iterations warms the launch paths up)
+        std::vector<CgOut> out;
+        rd_status s = batch_cg(batches[i], axis, 0.0, 0, false, out);
+        if (s != RD_OK) return s;
+        auto t0 = std::chrono::steady_clock::now();
+        s = batch_cg(batches[i], axis, 0.0, 0, false, out);
+        if (s != RD_OK) return s;
+        auto t1 = std::chrono::steady_clock::now();
+        s = batch_cg(batches[i], axis, 0.0, trial_iters, false, out);
+        if (s != RD_OK) return s;
+        auto t2 = std::chrono::steady_clock::now();
+        int64_t done = 0;
+        for (const CgOut &o : out) done = std::max(done, o.iters);
+        const double ms = std::max(1e-6, std::chrono::duration<double, std::milli>((t2 - t1) - (t1 - t0)).count() /
+                                               (double)std::max<int64_t>(1, done));
+        if (ms_per_iter) ms_per_iter[i] = ms;
+        if (ms < best) {
+            best = ms;
+            *best_index = i;
+        }
+    }
     return RD_OK;
 }
 

@@ -80,6 +80,7 @@ _SIGS = {
     "rd_batch_workspace_bytes": ([P, P], ci),
     "rd_batch_bind": ([P, P, sz, P], ci),
     "rd_batch_tortuosity": ([P, ci, f64, i64, P, P, P], ci),
+    "rd_batch_autotune_pick": ([P, ci, ci, i64, P, P], ci),
     "rd_batch_destroy": ([P], None),
 }
 
@@ -428,6 +429,18 @@ def autotune_pick(sims, dt, trial_steps=200):
     ms = np.zeros(len(sims))
     _check(_lib.rd_autotune_pick(arr, len(sims), float(dt), int(trial_steps), ctypes.byref(best),
                                  _np_ptr(ms)), "rd_autotune_pick")
+    return best.value, ms
+
+
+def batch_autotune_pick(batches, axis=0, trial_iters=50):
+    """Time trial_iters CG iterations of each bound candidate Batch (the same geometries
+    indexed with 4^3 and 8^3 blocks, say) and return (index of the fastest, ms per
+    iteration of each)."""
+    arr = (P * len(batches))(*[b.handle for b in batches])
+    best = ci()
+    ms = np.zeros(len(batches))
+    _check(_lib.rd_batch_autotune_pick(arr, len(batches), int(axis), int(trial_iters), ctypes.byref(best),
+                                       _np_ptr(ms)), "rd_batch_autotune_pick")
     return best.value, ms
 
 

@@ -190,3 +190,19 @@ def test_initial_guess_cluster_rule(rd, B, storage, axis):
     got = fields(s, 1)[0]
     np.testing.assert_array_equal(got, round_to_storage(want, storage))
     assert math.isinf(res["tau"]) != perc
+
+
+def test_batch_autotune_pick(rd, oracle_mod):
+    """The batch autotuner times both block edges and leaves batches that still give the
+    oracle's tau."""
+    imgs = [W.boolean_spheres(n, 0.5, 2.0, 4.0, seed=40 + n)[0] for n in (19, 26, 33)]
+    batches = [rd.Batch([rd.Geometry(im, None, 1.0, B) for im in imgs]).bind() for B in (8, 4)]
+    best, ms = rd.batch_autotune_pick(batches, 0, 30)
+    print(f"batch autotune: 8^3 {ms[0]:.4f} ms/it, 4^3 {ms[1]:.4f} ms/it, best {best}")
+    assert best in (0, 1) and np.all(ms > 0)
+    for bt in batches:
+        tau, rel, _ = bt.tortuosity(0, 1e-8, 20000)
+        for i, im in enumerate(imgs):
+            uo, _, _ = oracle_mod.steady_state(im, 0, "cg", tol=1e-12)
+            tau_o = oracle_mod.tortuosity_from_field(im, 0, uo)[0]
+            assert tau[i] == pytest.approx(tau_o, rel=1e-7)
