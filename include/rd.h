@@ -189,12 +189,19 @@ rd_status rd_sim_plane_flux(rd_sim *sim, int species, int axis, int64_t i0, doub
 /* Steady state of species 0 (single-species, no reactions or Robin) with a unit
  * drop along `axis` (Dirichlet 1 on the low face plane, 0 on the high one,
  * no-flux elsewhere), solved by conjugate gradients with the stencil as operator
- * and FP64 dot products.  Stops at rel. residual <= rel_tol, at stagnation (no 10%
- * decrease of the best residual over 20 checks of 50 iterations) or at max_iters.
+ * (the FTCS step's operator at t -> infinity) and FP64 dot products.  Initial guess:
+ * the linear ramp on 6-connected clusters touching both planes, 1 on clusters touching
+ * only the inlet, 0 on the rest (clusters labelled on the GPU).  The iterate is kept in
+ * FP64; every 25 iterations the FP64 residual b - A x is evaluated (rel_residual is its
+ * norm over ||b||) and replaces the recursive residual when the two have drifted apart,
+ * so 1e-8 is reachable with FP32, BF16 or FP16 vectors.  Stops at rel. residual <=
+ * rel_tol (RD_OK), or at stagnation (no 10% decrease of the best residual over 16
+ * checks) or max_iters (RD_ERR_NOT_CONVERGED, outputs still written).
  * tau = psi D A / (Q L): psi active fraction, A box cross-section, L = (n-1) dx,
- * Q the mean of the inflow at the inlet plane and the outflow at the outlet plane
- * (equal at an exact steady state; eq. tortuosity, tau = D_f / D_eff); +inf if
- * Q <= 0.  Needs RD_WS_SOLVER.  Leaves the steady field in species 0. */
+ * Q the mean of the inflow at the inlet plane and the outflow at the outlet plane of
+ * the FP64 iterate (equal at an exact steady state; eq. tortuosity, tau = D_f / D_eff);
+ * +inf if no cluster touches both planes or Q <= 0.  Needs RD_WS_SOLVER.  Leaves the
+ * steady field (the FP64 iterate rounded to the storage type) in species 0. */
 rd_status rd_sim_steady_state(rd_sim *sim, int axis, double rel_tol, int64_t max_iters,
                               double *tau, double *rel_residual, int64_t *iters);
 
@@ -261,8 +268,11 @@ rd_status rd_batch_create(const rd_geometry *const *geoms, int n, rd_storage sto
 rd_status rd_batch_workspace_bytes(const rd_batch *b, size_t *bytes);
 rd_status rd_batch_bind(rd_batch *b, void *dev_workspace, size_t bytes, void *stream);
 /* Per-geometry tortuosity along `axis` by batched conjugate gradients (one launch
- * per kernel stage for the whole batch); converged geometries stop updating.
- * tau[n], rel_residual[n], iters[n] are host arrays (any may be NULL). */
+ * per kernel stage for the whole batch), with the initial guess, FP64 iterate,
+ * residual replacement and stopping rule of rd_sim_steady_state applied per geometry;
+ * converged geometries stop updating.  tau[n], rel_residual[n], iters[n] are host
+ * arrays (any may be NULL).  RD_ERR_NOT_CONVERGED if any geometry stopped above
+ * rel_tol (outputs still written). */
 rd_status rd_batch_tortuosity(rd_batch *b, int axis, double rel_tol, int64_t max_iters,
                               double *tau, double *rel_residual, int64_t *iters);
 /* Block-edge autotuning of a batch: bound candidate batches of the same geometries
