@@ -112,170 +112,6 @@ __device__ __forceinline__ bool geom_live(const CgArgs &a, int gid)
     return a.scal[gid * CG_NSCAL + CG_DONE] == 0.0;
 }
 
-// r = b - A x (stored in r and p when `store`), partials (r.r, b.b)
-template <typename T, int B>
-__global__ __launch_bounds__(256) void k_cg_residual(CgArgs a, int store)
-{
-    using K = Blk<B>;
-    using C = Cfg<B>;
-    __shared__ float tile[C::BPW][1][K::TL];
-    __shared__ uint64_t srec[C::BPW][K::MW];
-    const int sub = threadIdx.x / C::TPB, lt = threadIdx.x % C::TPB;
-    const int b = blockIdx.x * C::BPW + sub;
-    const bool valid = b < a.nb;
-    BlockInfo bi = {};
-    if (valid) {
-        bi = a.info[b];
-        if (lt < K::MW) srec[sub][lt] = a.mask[(int64_t)b * K::MW + lt];
-    }
-    stage_tile<T, B>(tile[sub], (const T *)a.x, 0, 1, b, bi, lt, valid);
-    __syncthreads();
-    double rr = 0.0, bb = 0.0;
-    if (valid) {
-        int bx, by, bz, gid;
-        block_pos(bi, &bx, &by, &bz, &gid);
-        const GeomInfo g = a.geom[gid];
-        for (int k = 0; k < C::VPT; ++k) {
-            const int slot = lt + k * C::TPB;
-            const VoxCtx v = vox_ctx<B>(srec[sub], bi, g, a.dir, slot);
-            const int lx = slot % B, ly = (slot / B) % B, lz = slot / (B * B);
-            const int t = K::tidx(lx, ly, lz);
-            float r = 0.0f;
-            if (v.fr) {
-                r = lap_at<B>(tile[sub][0], t, v.nbm);
-                const int off[6] = {-1, 1, -K::E, K::E, -K::E * K::E, K::E * K::E};
-                double bp = 0.0;
-#pragma unroll
-                for (int d = 0; d < 6; ++d)
-                    if ((v.dirnb >> d) & 1u) bp += (double)tile[sub][0][t + off[d]];
-                rr += (double)r * (double)r;
-                bb += bp * bp;
-            }
-            if (store) {
-                rd_st_keep((T *)a.r, (int64_t)b * K::NS + slot, r);
-                rd_st_keep((T *)a.p, (int64_t)b * K::NS + slot, r);
-            }
-        }
-    }
-    block_sum2<B>(rr, bb, a.partial, b, valid);
-}
-
-// The same residual for 8^3 blocks in the column form of k_cg_matvec8 (one wave per
-// block, four per workgroup): r = sum of the active neighbours' x - n_active x_p, in
-// the matvec's order; b_p (only in blocks on a Dirichlet face) adds the neighbours that
-// lie on a Dirichlet face plane, in face order.  Whole sectors are stored.
-template <typename T>
-__global__ __launch_bounds__(256) void k_cg_residual8(CgArgs a, int store)
-{
-    __shared__ float tile[4][100];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int b = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + wv);
-    if (b >= a.nb) return;
-    const BlockInfo bi = a.info[b];
-    int bx, by, bz, gid;
-    block_pos(bi, &bx, &by, &bz, &gid);
-    const T *xv = (const T *)a.x;
-    const int64_t base = (int64_t)b * 512;
-    const int lx = lane & 7, ly = lane >> 3;
-    const uint64_t *rec = a.mask + (int64_t)b * 16;
-    uint64_t Wo[8], Wf[6];
-#pragma unroll
-    for (int z = 0; z < 8; ++z) Wo[z] = rec[z];
-#pragma unroll
-    for (int f = 0; f < 6; ++f) Wf[f] = rec[8 + f];
-    typedef typename RawOf<T>::type R;
-    R xc[8], xh[6];
-    unsigned cd[8];
-#pragma unroll
-    for (int z = 0; z < 8; ++z) {
-        const bool act = (Wo[z] >> lane) & 1ull;
-        xc[z] = ld_raw(xv, base + z * 64 + lane, act);
-        cd[z] = act ? (unsigned)a.code[base + z * 64 + lane] : 0u;
-    }
-#pragma unroll
-    for (int f = 0; f < 6; ++f) {
-        int ns;
-        switch (f) {
-        case 0: ns = (ly * 8 + lx) * 8 + 7; break;
-        case 1: ns = (ly * 8 + lx) * 8 + 0; break;
-        case 2: ns = (ly * 8 + 7) * 8 + lx; break;
-        case 3: ns = (ly * 8 + 0) * 8 + lx; break;
-        case 4: ns = (7 * 8 + ly) * 8 + lx; break;
-        default: ns = (0 * 8 + ly) * 8 + lx; break;
-        }
-        const int n = bi.nbr[f];
-        const bool e = (Wf[f] >> lane) & 1ull;
-        xh[f] = ld_raw(xv, (int64_t)(n >= 0 ? n : b) * 512 + ns, e);
-    }
-    float c[8], side[4];
-#pragma unroll
-    for (int z = 0; z < 8; ++z) c[z] = from_raw<T>(xc[z]);
-#pragma unroll
-    for (int f = 0; f < 4; ++f) side[f] = from_raw<T>(xh[f]);
-    const float zlo = from_raw<T>(xh[4]), zhi = from_raw<T>(xh[5]);
-
-    const GeomInfo g = a.geom[gid];
-    const int gx = bx * 8 + lx, gy = by * 8 + ly;
-    const bool bnd = bx == 0 || by == 0 || bz == 0 || bx * 8 + 8 >= g.nx || by * 8 + 8 >= g.ny ||
-                     bz * 8 + 8 >= g.nz;
-    float *ts = tile[wv];
-    double rr = 0.0, bb = 0.0;
-#pragma unroll
-    for (int z = 0; z < 8; ++z) {
-        ts[(ly + 1) * 10 + (lx + 1)] = c[z];
-        if (ly == z) {
-            ts[(lx + 1) * 10 + 0] = side[0];
-            ts[(lx + 1) * 10 + 9] = side[1];
-            ts[0 * 10 + (lx + 1)] = side[2];
-            ts[9 * 10 + (lx + 1)] = side[3];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const unsigned code = cd[z];
-        const int gz = bz * 8 + z;
-        unsigned onf = 0u;
-        if (bnd)
-            onf = (gx == 0 ? 1u : 0u) | (gx == g.nx - 1 ? 2u : 0u) | (gy == 0 ? 4u : 0u) |
-                  (gy == g.ny - 1 ? 8u : 0u) | (gz == 0 ? 16u : 0u) | (gz == g.nz - 1 ? 32u : 0u);
-        const bool fr = (code & 64u) != 0u && (onf & a.dir) == 0u;
-        const float *q = &ts[(ly + 1) * 10 + (lx + 1)];
-        const float dn = z == 0 ? zlo : c[z > 0 ? z - 1 : 0];
-        const float up = z == 7 ? zhi : c[z < 7 ? z + 1 : 7];
-        const float r = fr ? -cg_ap8(q, dn, up, c[z], code, fr) : 0.0f;
-        if (fr) {
-            rr += (double)r * (double)r;
-            if (bnd) {  // b_p: active neighbours on a Dirichlet face plane
-                const float nv[6] = {q[-1], q[1], q[-10], q[10], dn, up};
-                double bp = 0.0;
-#pragma unroll
-                for (int d = 0; d < 6; ++d) {
-                    const int ex = d == 0 ? -1 : d == 1 ? 1 : 0;
-                    const int ey = d == 2 ? -1 : d == 3 ? 1 : 0;
-                    const int ez = d == 4 ? -1 : d == 5 ? 1 : 0;
-                    if (((code >> d) & 1u) &&
-                        on_dirichlet(a.dir, gx + ex, gy + ey, gz + ez, g.nx, g.ny, g.nz))
-                        bp += (double)nv[d];
-                }
-                bb += bp * bp;
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (store && sector_active<T>(Wo[z], lane)) {
-            rd_st_keep((T *)a.r, base + z * 64 + lane, r);
-            rd_st_keep((T *)a.p, base + z * 64 + lane, r);
-        }
-    }
-    rr = wave_sum(rr);
-    bb = wave_sum(bb);
-    if (lane == 0) {
-        a.partial[(int64_t)b * 2 + 0] = rr;
-        a.partial[(int64_t)b * 2 + 1] = bb;
-    }
-}
-
 // Ap = A p on live geometries, partial (p.Ap, 0)
 template <typename T, int B>
 __global__ __launch_bounds__(256) void k_cg_matvec(CgArgs a)
@@ -1126,14 +962,13 @@ __global__ __launch_bounds__(256) void k_ir_fold(const BlockInfo *info, const do
     }
 }
 
-// X = x (mode 0), X += s d (mode 1), x = X rounded to the storage type (mode 2); every slot
+// X = x (mode 0), x = X rounded to the storage type (mode 2); every slot
 template <typename T>
 __global__ __launch_bounds__(256) void k_ir_axpy(int64_t nslots, int mode, double s, double *X, T *x)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= nslots) return;
     if (mode == 0) X[i] = (double)rd_ld((const T *)x, i);
-    else if (mode == 1) X[i] += s * (double)rd_ld((const T *)x, i);
     else rd_st_keep(x, i, (float)X[i]);
 }
 
@@ -1196,18 +1031,6 @@ static dim3 grid_for(int B, int nb)
     return dim3((unsigned)std::max(1, B == 8 ? groups<8>(nb) : groups<4>(nb)));
 }
 
-int cg_launch_residual(int storage, int B, const CgArgs &a, int store, void *stream)
-{
-    if (B == 8) {  // column form
-        const dim3 grid((unsigned)std::max(1, (a.nb + 3) / 4));
-        hipStream_t st = (hipStream_t)stream;
-        if (storage == 0) hipLaunchKernelGGL((k_cg_residual8<float>), grid, dim3(256), 0, st, a, store);
-        else if (storage == 1) hipLaunchKernelGGL((k_cg_residual8<bf16_t>), grid, dim3(256), 0, st, a, store);
-        else hipLaunchKernelGGL((k_cg_residual8<_Float16>), grid, dim3(256), 0, st, a, store);
-        return (int)hipGetLastError();
-    }
-    CG_DISPATCH(storage, B, k_cg_residual, grid_for(B, a.nb), stream, a, store);
-}
 int cg_launch_matvec(int storage, int B, const CgArgs &a, void *stream)
 {
     CG_DISPATCH(storage, B, k_cg_matvec, grid_for(B, a.nb), stream, a);

@@ -93,8 +93,8 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
     const int n = a.ngeom;
     out.assign(n, CgOut());
     LAUNCHCHK(rd_launch_fill_u32(a.scal, 0u, (int64_t)n * CG_NSCAL * 2, st));
-    if (a.x64) LAUNCHCHK(cg_launch_res64(storage, B, a, 1, st));
-    else LAUNCHCHK(cg_launch_residual(storage, B, a, 1, st));
+    if (!a.x64) return rd_fail(RD_ERR_STATE, "CG needs the FP64 iterate");
+    LAUNCHCHK(cg_launch_res64(storage, B, a, 1, st));
     LAUNCHCHK(cg_launch_segsum(a, CG_RRNEW, CG_BB, 2, st));
     std::vector<double> hs;
     rd_status s = copy_scal(a, hs, st);
@@ -135,21 +135,15 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
             LAUNCHCHK(cg_launch_segsum(a, CG_RRNEW, -1, 1, st));
         }
         bool replace = false, rescale = false;
-        // true residual b - A x (the recursive one drifts in reduced precision); with an
-        // FP64 iterate it is computed in FP64 and, once the recursive residual has
-        // drifted from it, replaces it (residual replacement, van der Vorst and Ye 2000),
-        // so the iteration is not held at the storage type's floor
-        if (a.x64) {
-            // B = 8 reads the unfolded iterate; B = 4 folds first.  The fold then puts the
-            // updates of the last 25 iterations into X and clears x.
-            if (B != 8 && !a.x64_direct) LAUNCHCHK(ir_launch_fold(storage, B, a, a.nb * (int64_t)B * B * B, st));
-            LAUNCHCHK(cg_launch_res64(storage, B, a, 0, st));
-            LAUNCHCHK(cg_launch_segsum(a, CG_CHECK, -1, -1, st));
-            if (B == 8 && !a.x64_direct) LAUNCHCHK(ir_launch_fold(storage, B, a, a.nb * (int64_t)B * B * B, st));
-        } else {
-            LAUNCHCHK(cg_launch_residual(storage, B, a, 0, st));
-            LAUNCHCHK(cg_launch_segsum(a, CG_CHECK, -1, -1, st));
-        }
+        // true residual b - A x in FP64 (the recursive one drifts in the storage type's
+        // precision); once the recursive residual has drifted from it, it replaces it
+        // (residual replacement, van der Vorst and Ye 2000), so the iteration is not held
+        // at the storage type's floor.  B = 8 reads the unfolded iterate; B = 4 folds
+        // first.  The fold puts the updates of the last 25 iterations into X, clears x.
+        if (B != 8 && !a.x64_direct) LAUNCHCHK(ir_launch_fold(storage, B, a, a.nb * (int64_t)B * B * B, st));
+        LAUNCHCHK(cg_launch_res64(storage, B, a, 0, st));
+        LAUNCHCHK(cg_launch_segsum(a, CG_CHECK, -1, -1, st));
+        if (B == 8 && !a.x64_direct) LAUNCHCHK(ir_launch_fold(storage, B, a, a.nb * (int64_t)B * B * B, st));
         if ((s = copy_scal(a, hs, st)) != RD_OK) return s;
         for (int g = 0; g < n; ++g) {
             double *v = &hs[(size_t)g * CG_NSCAL];
@@ -169,7 +163,7 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
                 v[CG_DONE] = 1.0;
                 out[g].converged = conv;
                 --live;
-            } else if (a.x64) {
+            } else {
                 // next scale: a power of 2 that brings the residual's RMS near 1
                 const double n_act = std::max(1.0, m_active(meta[g]));
                 const double rms = sqrt(std::max(v[CG_CHECK], 1e-300) / n_act);
@@ -189,7 +183,7 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
             }
         }
         if ((s = push_scal(a, hs, st)) != RD_OK) return s;
-        if (a.x64 && live > 0 && (replace || rescale)) {
+        if (live > 0 && (replace || rescale)) {
             // residual replacement: r = sigma (b - A X) in FP64 and p rescaled, or only
             // the rescaling of r and p; then rr of the stored r
             LAUNCHCHK(cg_launch_res64(storage, B, a, replace ? 2 : 3, st));
@@ -198,7 +192,7 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
     }
     if (!want_tau) return RD_OK;
     // steady flux through the two Dirichlet planes (of the FP64 iterate rounded to x)
-    if (a.x64) LAUNCHCHK(ir_launch_axpy(storage, a.nb * (int64_t)B * B * B, 2, 0.0, a.x64, a.x, st));
+    LAUNCHCHK(ir_launch_axpy(storage, a.nb * (int64_t)B * B * B, 2, 0.0, a.x64, a.x, st));
     LAUNCHCHK(cg_launch_flux(storage, B, a, 2 * axis, st));
     LAUNCHCHK(cg_launch_segsum(a, CG_QIN, CG_QOUT, -1, st));
     if ((s = copy_scal(a, hs, st)) != RD_OK) return s;

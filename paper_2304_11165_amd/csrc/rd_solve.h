@@ -31,7 +31,7 @@ struct CgArgs {
     int ngeom;
     uint32_t dir;          // Dirichlet faces (inlet | outlet)
     void *x, *r, *p, *ap;  // storage type T, nb * B^3 each (ap: B = 4 only)
-    double *x64;           // FP64 iterate, or NULL: the iterate is x
+    double *x64;           // FP64 iterate
     int x64_direct;        // with x64: 1 = every update goes to x64 (16 bytes per voxel);
                            // 0 = x accumulates the updates and is folded into x64 at
                            // every check (the iterate is x64 + x / sigma)
@@ -40,7 +40,6 @@ struct CgArgs {
     double *scal;          // [ngeom][CG_NSCAL]
 };
 
-int cg_launch_residual(int storage, int B, const CgArgs &a, int store, void *stream);
 int cg_launch_matvec(int storage, int B, const CgArgs &a, void *stream);
 // B = 8: p2 = r + beta p (per live geometry, rounded to the storage type) and the
 // partial (p2.A p2, 0); A p2 is not stored.  The caller then swaps p and p2.
@@ -56,7 +55,7 @@ int cg_launch_segsum(const CgArgs &a, int slot0, int slot1, int mode, void *stre
 // (uint32), flags[2 * nslots] (bytes, zeroed by the caller), perc[ngeom] (uint32,
 // zeroed by the caller; set to 1 for geometries with a cluster touching both planes).
 // FP64 iterate helpers (single geometry), partial rows of ir_rows(nslots) x 2 doubles.
-// axpy mode 0: X = x; 1: X += s x; 2: x = X (rounded).  flux: (inlet, outlet) sums of
+// axpy mode 0: X = x; 2: x = X (rounded).  flux: (inlet, outlet) sums of
 // X_p - X_q over Dirichlet voxels p and their free neighbours q.
 int ir_rows(int64_t nslots);
 // r = b - A x64 in FP64 (per-block partials (r.r, b.b)); store 1 writes it to r and p;
