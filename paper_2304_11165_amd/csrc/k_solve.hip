@@ -657,6 +657,76 @@ __global__ __launch_bounds__(256) void k_lab_unite(const BlockInfo *info, const 
     }
 }
 
+// B = 8 in two passes, so that most unions stay inside a workgroup: (1) every block
+// labels its own active voxels in LDS by min-label propagation along its in-block
+// edges (each label ends at the smallest slot of its in-block component) and writes
+// par[i] = block base + that slot (a root's parent is itself; every parent index is at
+// most its child's, as the global unions require); (2) only the pairs across the +x, +y
+// and +z faces of each block are united globally (uf_unite), 192 candidate pairs per
+// block instead of three per voxel.
+__global__ __launch_bounds__(256) void k_lab_local8(const uint8_t *code, uint32_t *par)
+{
+    __shared__ uint16_t lab[512];
+    __shared__ int changed;
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * 512;
+    unsigned cd[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int s = t + 256 * k;
+        cd[k] = code[base + s];
+        lab[s] = (cd[k] & 64u) ? (uint16_t)s : (uint16_t)0xffff;
+    }
+    for (int it = 0; it < 512; ++it) {  // each pass lowers a label or ends the loop
+        if (t == 0) changed = 0;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int s = t + 256 * k;
+            if (!(cd[k] & 64u)) continue;
+            const int l[3] = {s & 7, (s >> 3) & 7, s >> 6};
+            unsigned m = lab[s];
+#pragma unroll
+            for (int d = 0; d < 6; ++d) {
+                const int a = d >> 1;
+                const bool up = d & 1;
+                if (!((cd[k] >> d) & 1u) || (up ? l[a] == 7 : l[a] == 0)) continue;  // not in this block
+                const int st = a == 0 ? 1 : a == 1 ? 8 : 64;
+                const unsigned q = lab[up ? s + st : s - st];
+                m = q < m ? q : m;
+            }
+            if (m < lab[s]) {
+                lab[s] = (uint16_t)m;
+                changed = 1;
+            }
+        }
+        __syncthreads();
+        const int c = changed;
+        __syncthreads();
+        if (!c) break;
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int s = t + 256 * k;
+        par[base + s] = (uint32_t)(base + ((cd[k] & 64u) ? lab[s] : s));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_lab_faces8(const BlockInfo *info, const uint8_t *code, uint32_t *par)
+{
+    const int t = threadIdx.x;
+    if (t >= 192) return;
+    const int64_t b = blockIdx.x;
+    const int a = t >> 6, u = t & 7, v = (t >> 3) & 7;  // face +x (a = 0), +y (1), +z (2)
+    const int s = a == 0 ? (v * 8 + u) * 8 + 7 : a == 1 ? (v * 8 + 7) * 8 + u : (7 * 8 + v) * 8 + u;
+    const int64_t i = b * 512 + s;
+    const unsigned cd = code[i];
+    if (!(cd & 64u) || !((cd >> (2 * a + 1)) & 1u)) return;  // active neighbour across the face
+    const int st = a == 0 ? 1 : a == 1 ? 8 : 64;
+    const int64_t j = (int64_t)info[b].nbr[2 * a + 1] * 512 + s - 7 * st;
+    uf_unite(par, (uint32_t)i, (uint32_t)j);
+}
+
 // coordinate of slot i along `axis` and the extent of its geometry along it
 template <int B>
 __device__ __forceinline__ void lab_coord(const BlockInfo *info, const GeomInfo *geom, int64_t i, int axis,
@@ -1077,9 +1147,10 @@ int cg_launch_initial_guess(int storage, int B, const CgArgs &a, int axis, int64
     hipStream_t st = (hipStream_t)stream;
     const dim3 grid((unsigned)((nslots + 255) / 256));
     uint8_t *fin = flags, *fout = flags + nslots;
-    hipLaunchKernelGGL(k_lab_init, grid, dim3(256), 0, st, par, nslots);
     if (B == 8) {
-        hipLaunchKernelGGL(k_lab_unite<8>, grid, dim3(256), 0, st, a.info, a.code, nslots, par);
+        const dim3 blocks((unsigned)(nslots / 512));
+        hipLaunchKernelGGL(k_lab_local8, blocks, dim3(256), 0, st, a.code, par);
+        hipLaunchKernelGGL(k_lab_faces8, blocks, dim3(256), 0, st, a.info, a.code, par);
         hipLaunchKernelGGL(k_lab_touch<8>, grid, dim3(256), 0, st, a.info, a.code, a.geom, nslots, axis, par, fin, fout);
         if (storage == 0)
             hipLaunchKernelGGL((k_lab_guess<float, 8>), grid, dim3(256), 0, st, a.info, a.code, a.geom, nslots, axis,
@@ -1091,6 +1162,7 @@ int cg_launch_initial_guess(int storage, int B, const CgArgs &a, int axis, int64
             hipLaunchKernelGGL((k_lab_guess<_Float16, 8>), grid, dim3(256), 0, st, a.info, a.code, a.geom, nslots, axis,
                                par, fin, fout, (_Float16 *)a.x, perc);
     } else {
+        hipLaunchKernelGGL(k_lab_init, grid, dim3(256), 0, st, par, nslots);
         hipLaunchKernelGGL(k_lab_unite<4>, grid, dim3(256), 0, st, a.info, a.code, nslots, par);
         hipLaunchKernelGGL(k_lab_touch<4>, grid, dim3(256), 0, st, a.info, a.code, a.geom, nslots, axis, par, fin, fout);
         if (storage == 0)
