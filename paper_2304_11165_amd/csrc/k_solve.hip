@@ -477,51 +477,6 @@ __global__ __launch_bounds__(256) void k_cg_pupdate(CgArgs a)
     }
 }
 
-// Steady flux at the Dirichlet planes: partial (inflow at the inlet face, inflow at
-// the outlet face) = sum over Dirichlet voxels q and free neighbours p of (x_q - x_p)
-template <typename T, int B>
-__global__ __launch_bounds__(256) void k_cg_flux(CgArgs a, int inlet_face)
-{
-    using K = Blk<B>;
-    using C = Cfg<B>;
-    __shared__ float tile[C::BPW][1][K::TL];
-    __shared__ uint64_t srec[C::BPW][K::MW];
-    const int sub = threadIdx.x / C::TPB, lt = threadIdx.x % C::TPB;
-    const int b = blockIdx.x * C::BPW + sub;
-    const bool valid = b < a.nb;
-    BlockInfo bi = {};
-    if (valid) {
-        bi = a.info[b];
-        if (lt < K::MW) srec[sub][lt] = a.mask[(int64_t)b * K::MW + lt];
-    }
-    stage_tile<T, B>(tile[sub], (const T *)a.x, 0, 1, b, bi, lt, valid);
-    __syncthreads();
-    double qin = 0.0, qout = 0.0;
-    if (valid) {
-        int bx, by, bz, gid;
-        block_pos(bi, &bx, &by, &bz, &gid);
-        const GeomInfo g = a.geom[gid];
-        const uint32_t din = 1u << inlet_face, dout = 1u << (inlet_face + 1);
-        for (int k = 0; k < C::VPT; ++k) {
-            const int slot = lt + k * C::TPB;
-            const VoxCtx v = vox_ctx<B>(srec[sub], bi, g, a.dir, slot);
-            if (!v.act || v.fr) continue;
-            const int lx = slot % B, ly = (slot / B) % B, lz = slot / (B * B);
-            const int t = K::tidx(lx, ly, lz);
-            const bool on_in = on_dirichlet(din, v.gx, v.gy, v.gz, g.nx, g.ny, g.nz);
-            const int off[6] = {-1, 1, -K::E, K::E, -K::E * K::E, K::E * K::E};
-            double q = 0.0;
-#pragma unroll
-            for (int d = 0; d < 6; ++d)
-                if (((v.nbm >> d) & 1u) && !((v.dirnb >> d) & 1u))
-                    q += (double)tile[sub][0][t] - (double)tile[sub][0][t + off[d]];
-            if (on_in) qin += q;
-            else if (on_dirichlet(dout, v.gx, v.gy, v.gz, g.nx, g.ny, g.nz)) qout += q;
-        }
-    }
-    block_sum2<B>(qin, qout, a.partial, b, valid);
-}
-
 // Per-geometry sums of the per-block partial pairs: geometry g owns blocks
 // [block0_g, block0_{g+1}); one workgroup per geometry, fixed summation order.
 // dst[g*CG_NSCAL + slot0 + k] = sum (k = 0, 1; slot < 0 skips that lane); then, for a
@@ -767,31 +722,31 @@ template <typename T, int B>
 __global__ __launch_bounds__(256) void k_lab_guess(const BlockInfo *info, const uint8_t *code,
                                                    const GeomInfo *geom, int64_t nslots, int axis,
                                                    const uint32_t *par, const uint8_t *fin,
-                                                   const uint8_t *fout, T *x, uint32_t *perc)
+                                                   const uint8_t *fout, T *x, double *X, uint32_t *perc)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= nslots) return;
-    float v = 0.0f;
+    double v = 0.0;
     if (code[i] & 64u) {
         int c, n, gid;
         lab_coord<B>(info, geom, i, axis, &c, &n, &gid);
         const uint32_t r = par[i];
         const int t = (int)fin[r] | ((int)fout[r] << 1);
-        if (c == 0) v = 1.0f;
-        else if (c == n - 1) v = 0.0f;
-        else if (t == 3) v = 1.0f - (float)c / (float)(n - 1);
-        else v = t == 1 ? 1.0f : 0.0f;
+        if (c == 0) v = 1.0;
+        else if (c == n - 1) v = 0.0;
+        else if (t == 3) v = 1.0 - (double)c / (double)(n - 1);
+        else v = t == 1 ? 1.0 : 0.0;
         if (t == 3) perc[gid] = 1u;
     }
-    rd_st_keep(x, i, v);
+    X[i] = v;  // the FP64 iterate starts at the exact ramp
+    rd_st_keep(x, i, (float)v);
 }
 
-// ---- mixed-precision iterative refinement of the steady state ----------------
-// The refinement scheme of Wilkinson in the mixed-precision form analysed by Carson
-// and Higham (2018): the solution X and the residual R = b - A X are FP64; every
-// correction A d = R / s is solved by the CG above in the storage type (FP32
-// arithmetic) from the scaled right-hand side, then X += s d.  These kernels take one
-// thread per slot and read neighbours directly (they run a few times per solve).
+// ---- FP64 iterate of the steady state -------------------------------------
+// CG keeps its iterate X in FP64 (the vectors r, p stay in the storage type): the true
+// residual b - A X is evaluated in FP64 at every check and replaces the recursive one
+// when they drift apart.  The generic kernels below take one thread per slot and read
+// neighbours directly (they run a few times per solve).
 
 // slot index of the neighbour of slot i across direction d (order -x,+x,-y,+y,-z,+z);
 // the caller has checked that the neighbour is active (so its block exists)
@@ -1032,48 +987,51 @@ __global__ __launch_bounds__(256) void k_ir_fold(const BlockInfo *info, const do
     }
 }
 
-// X = x (mode 0), x = X rounded to the storage type (mode 2); every slot
+// x = X rounded to the storage type, every slot
 template <typename T>
-__global__ __launch_bounds__(256) void k_ir_axpy(int64_t nslots, int mode, double s, double *X, T *x)
+__global__ __launch_bounds__(256) void k_ir_store(int64_t nslots, const double *X, T *x)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= nslots) return;
-    if (mode == 0) X[i] = (double)rd_ld((const T *)x, i);
-    else rd_st_keep(x, i, (float)X[i]);
+    if (i < nslots) rd_st_keep(x, i, (float)X[i]);
 }
 
-// FP64 flux through the two Dirichlet planes of X: partials (sum over inlet Dirichlet
-// voxels p and their free neighbours q of X_p - X_q, the same over the outlet)
+// FP64 flux through the two Dirichlet planes of the FP64 iterate: per-block partials
+// (sum over inlet Dirichlet voxels p and their free neighbours q of X_p - X_q, the same
+// over the outlet), in the block layout of the other CG partials.
 template <int B>
-__global__ __launch_bounds__(256) void k_ir_flux(const BlockInfo *info, const uint8_t *code, const GeomInfo *geom,
-                                                 int64_t nslots, uint32_t dir, int inlet_face, const double *X,
-                                                 double *partial)
+__global__ __launch_bounds__(256) void k_flux64(CgArgs a, int inlet_face)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    using C = Cfg<B>;
+    constexpr int NS = B * B * B;
+    const int sub = threadIdx.x / C::TPB, lt = threadIdx.x % C::TPB;
+    const int b = blockIdx.x * C::BPW + sub;
     double qin = 0.0, qout = 0.0;
-    if (i < nslots && (code[i] & 64u)) {
-        const unsigned cd = code[i];
-        int gx, gy, gz;
-        GeomInfo g;
-        ir_pos<B>(info, geom, i, &gx, &gy, &gz, &g);
-        const bool on_in = on_dirichlet(1u << inlet_face, gx, gy, gz, g.nx, g.ny, g.nz);
-        const bool on_out = !on_in && on_dirichlet(1u << (inlet_face + 1), gx, gy, gz, g.nx, g.ny, g.nz);
-        if (on_in || on_out) {
-            const double xp = X[i];
+    if (b < a.nb) {
+        for (int k = 0; k < C::VPT; ++k) {
+            const int64_t i = (int64_t)b * NS + lt + k * C::TPB;
+            const unsigned cd = a.code[i];
+            if (!(cd & 64u)) continue;
+            int gx, gy, gz;
+            GeomInfo g;
+            ir_pos<B>(a.info, a.geom, i, &gx, &gy, &gz, &g);
+            const bool on_in = on_dirichlet(1u << inlet_face, gx, gy, gz, g.nx, g.ny, g.nz);
+            const bool on_out = !on_in && on_dirichlet(1u << (inlet_face + 1), gx, gy, gz, g.nx, g.ny, g.nz);
+            if (!on_in && !on_out) continue;
+            const double xp = a.x64[i];
             double q = 0.0;
 #pragma unroll
             for (int d = 0; d < 6; ++d) {
                 if (!((cd >> d) & 1u)) continue;
                 const int ex = d == 0 ? -1 : d == 1 ? 1 : 0, ey = d == 2 ? -1 : d == 3 ? 1 : 0,
                           ez = d == 4 ? -1 : d == 5 ? 1 : 0;
-                if (on_dirichlet(dir, gx + ex, gy + ey, gz + ez, g.nx, g.ny, g.nz)) continue;
-                q += xp - X[ir_nbr<B>(info, i, d)];
+                if (on_dirichlet(a.dir, gx + ex, gy + ey, gz + ez, g.nx, g.ny, g.nz)) continue;
+                q += xp - a.x64[ir_nbr<B>(a.info, i, d)];
             }
-            if (on_in) qin = q;
-            else qout = q;
+            if (on_in) qin += q;
+            else qout += q;
         }
     }
-    wg_sum2(qin, qout, partial);
+    block_sum2<B>(qin, qout, a.partial, b, b < a.nb);
 }
 
 template <int B>
@@ -1136,9 +1094,12 @@ int cg_launch_pupdate(int storage, int B, const CgArgs &a, void *stream)
 {
     CG_DISPATCH(storage, B, k_cg_pupdate, grid_for(B, a.nb), stream, a);
 }
-int cg_launch_flux(int storage, int B, const CgArgs &a, int inlet_face, void *stream)
+int cg_launch_flux(int B, const CgArgs &a, int inlet_face, void *stream)
 {
-    CG_DISPATCH(storage, B, k_cg_flux, grid_for(B, a.nb), stream, a, inlet_face);
+    hipStream_t st = (hipStream_t)stream;
+    if (B == 8) hipLaunchKernelGGL(k_flux64<8>, grid_for(8, a.nb), dim3(256), 0, st, a, inlet_face);
+    else hipLaunchKernelGGL(k_flux64<4>, grid_for(4, a.nb), dim3(256), 0, st, a, inlet_face);
+    return (int)hipGetLastError();
 }
 int cg_launch_initial_guess(int storage, int B, const CgArgs &a, int axis, int64_t nslots, uint32_t *par,
                             uint8_t *flags, uint32_t *perc, void *stream)
@@ -1154,26 +1115,26 @@ int cg_launch_initial_guess(int storage, int B, const CgArgs &a, int axis, int64
         hipLaunchKernelGGL(k_lab_touch<8>, grid, dim3(256), 0, st, a.info, a.code, a.geom, nslots, axis, par, fin, fout);
         if (storage == 0)
             hipLaunchKernelGGL((k_lab_guess<float, 8>), grid, dim3(256), 0, st, a.info, a.code, a.geom, nslots, axis,
-                               par, fin, fout, (float *)a.x, perc);
+                               par, fin, fout, (float *)a.x, a.x64, perc);
         else if (storage == 1)
             hipLaunchKernelGGL((k_lab_guess<bf16_t, 8>), grid, dim3(256), 0, st, a.info, a.code, a.geom, nslots, axis,
-                               par, fin, fout, (bf16_t *)a.x, perc);
+                               par, fin, fout, (bf16_t *)a.x, a.x64, perc);
         else
             hipLaunchKernelGGL((k_lab_guess<_Float16, 8>), grid, dim3(256), 0, st, a.info, a.code, a.geom, nslots, axis,
-                               par, fin, fout, (_Float16 *)a.x, perc);
+                               par, fin, fout, (_Float16 *)a.x, a.x64, perc);
     } else {
         hipLaunchKernelGGL(k_lab_init, grid, dim3(256), 0, st, par, nslots);
         hipLaunchKernelGGL(k_lab_unite<4>, grid, dim3(256), 0, st, a.info, a.code, nslots, par);
         hipLaunchKernelGGL(k_lab_touch<4>, grid, dim3(256), 0, st, a.info, a.code, a.geom, nslots, axis, par, fin, fout);
         if (storage == 0)
             hipLaunchKernelGGL((k_lab_guess<float, 4>), grid, dim3(256), 0, st, a.info, a.code, a.geom, nslots, axis,
-                               par, fin, fout, (float *)a.x, perc);
+                               par, fin, fout, (float *)a.x, a.x64, perc);
         else if (storage == 1)
             hipLaunchKernelGGL((k_lab_guess<bf16_t, 4>), grid, dim3(256), 0, st, a.info, a.code, a.geom, nslots, axis,
-                               par, fin, fout, (bf16_t *)a.x, perc);
+                               par, fin, fout, (bf16_t *)a.x, a.x64, perc);
         else
             hipLaunchKernelGGL((k_lab_guess<_Float16, 4>), grid, dim3(256), 0, st, a.info, a.code, a.geom, nslots, axis,
-                               par, fin, fout, (_Float16 *)a.x, perc);
+                               par, fin, fout, (_Float16 *)a.x, a.x64, perc);
     }
     return (int)hipGetLastError();
 }
@@ -1197,14 +1158,14 @@ int cg_launch_res64(int storage, int B, const CgArgs &a, int store, void *stream
     }
     CG_DISPATCH(storage, B, k_res64, grid_for(B, a.nb), stream, a, store);
 }
-int ir_launch_axpy(int storage, int64_t nslots, int mode, double s, double *X, void *x, void *stream)
+int ir_launch_store(int storage, int64_t nslots, const double *X, void *x, void *stream)
 {
     if (nslots <= 0) return 0;
     hipStream_t st = (hipStream_t)stream;
     const dim3 grid((unsigned)ir_rows(nslots));
-    if (storage == 0) hipLaunchKernelGGL((k_ir_axpy<float>), grid, dim3(256), 0, st, nslots, mode, s, X, (float *)x);
-    else if (storage == 1) hipLaunchKernelGGL((k_ir_axpy<bf16_t>), grid, dim3(256), 0, st, nslots, mode, s, X, (bf16_t *)x);
-    else hipLaunchKernelGGL((k_ir_axpy<_Float16>), grid, dim3(256), 0, st, nslots, mode, s, X, (_Float16 *)x);
+    if (storage == 0) hipLaunchKernelGGL((k_ir_store<float>), grid, dim3(256), 0, st, nslots, X, (float *)x);
+    else if (storage == 1) hipLaunchKernelGGL((k_ir_store<bf16_t>), grid, dim3(256), 0, st, nslots, X, (bf16_t *)x);
+    else hipLaunchKernelGGL((k_ir_store<_Float16>), grid, dim3(256), 0, st, nslots, X, (_Float16 *)x);
     return (int)hipGetLastError();
 }
 int ir_launch_fold(int storage, int B, const CgArgs &a, int64_t nslots, void *stream)
@@ -1225,16 +1186,6 @@ int ir_launch_fold(int storage, int B, const CgArgs &a, int64_t nslots, void *st
         else IR_FOLD(_Float16, 4);
     }
 #undef IR_FOLD
-    return (int)hipGetLastError();
-}
-int ir_launch_flux(int B, const CgArgs &a, int64_t nslots, int inlet_face, const double *X, double *partial,
-                   void *stream)
-{
-    if (nslots <= 0) return 0;
-    hipStream_t st = (hipStream_t)stream;
-    const dim3 grid((unsigned)ir_rows(nslots));
-    if (B == 8) hipLaunchKernelGGL(k_ir_flux<8>, grid, dim3(256), 0, st, a.info, a.code, a.geom, nslots, a.dir, inlet_face, X, partial);
-    else hipLaunchKernelGGL(k_ir_flux<4>, grid, dim3(256), 0, st, a.info, a.code, a.geom, nslots, a.dir, inlet_face, X, partial);
     return (int)hipGetLastError();
 }
 int cg_launch_segsum(const CgArgs &a, int slot0, int slot1, int mode, void *stream)

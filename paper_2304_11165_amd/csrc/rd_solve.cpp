@@ -192,8 +192,8 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
     }
     if (!want_tau) return RD_OK;
     // steady flux through the two Dirichlet planes (of the FP64 iterate rounded to x)
-    LAUNCHCHK(ir_launch_axpy(storage, a.nb * (int64_t)B * B * B, 2, 0.0, a.x64, a.x, st));
-    LAUNCHCHK(cg_launch_flux(storage, B, a, 2 * axis, st));
+    LAUNCHCHK(ir_launch_store(storage, a.nb * (int64_t)B * B * B, a.x64, a.x, st));
+    LAUNCHCHK(cg_launch_flux(B, a, 2 * axis, st));
     LAUNCHCHK(cg_launch_segsum(a, CG_QIN, CG_QOUT, -1, st));
     if ((s = copy_scal(a, hs, st)) != RD_OK) return s;
     for (int g = 0; g < n; ++g) {
@@ -264,6 +264,7 @@ extern "C" rd_status rd_sim_steady_state(rd_sim *sim, int axis, double rel_tol, 
         if (iters) *iters = 0;
         return RD_OK;
     }
+    a.x64 = (double *)(sim->ws + sim->L.irx);  // the FP64 iterate (the guess writes it)
     {
         const size_t es = sim->storage == RD_FP32 ? 4 : 2;
         const SimLayout &L = sim->L;
@@ -280,32 +281,16 @@ extern "C" rd_status rd_sim_steady_state(rd_sim *sim, int axis, double rel_tol, 
     const SimLayout &L = sim->L;
     const int64_t nslots = L.field_elems;
     hipStream_t stream = sim->stream;
-    double *X = (double *)(sim->ws + L.irx);
-    double *part = (double *)(sim->ws + L.part);
-    double *mid = (double *)(sim->ws + L.mid);
-    double *res = (double *)(sim->ws + L.res) + 40;
-    LAUNCHCHK(ir_launch_axpy(st_, nslots, 0, 0.0, X, a.x, stream));
-    a.x64 = X;
     // FP32 storage: x accumulates the updates between checks (no FP64 traffic per
     // iteration); 16-bit storage is too coarse for that and updates X directly
     a.x64_direct = sim->storage == RD_FP32 ? 0 : 1;
     if (!a.x64_direct) LAUNCHCHK(rd_launch_fill_u32(a.x, 0u, nslots, stream));  // FP32: one word a slot
-    rd_status s = run_cg(a, st_, G.B, stream, axis, rel_tol, max_iters, meta, out, 2 * STALL_CHECKS, false);
+    rd_status s = run_cg(a, st_, G.B, stream, axis, rel_tol, max_iters, meta, out, 2 * STALL_CHECKS, true);
     if (s != RD_OK) return s;
+    // (run_cg leaves X rounded to the storage type in the field and tau from its FP64 flux)
     const double rel = out[0].rel;
     const int64_t total = out[0].iters;
-    // the field holds X; tau from the FP64 flux of X through both Dirichlet planes
-    LAUNCHCHK(ir_launch_axpy(st_, nslots, 2, 0.0, X, a.x, stream));
-    LAUNCHCHK(ir_launch_flux(G.B, a, nslots, inlet, X, part, stream));
-    LAUNCHCHK(rd_launch_finish_reduce(part, ir_rows(nslots), 2, mid, res, stream));
-    double q2[2];
-    HIPCHK(hipMemcpyAsync(q2, res, sizeof(q2), hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipStreamSynchronize(stream));
-    const double area = (double)ext[(axis + 1) % 3] * (double)ext[(axis + 2) % 3] * G.dx * G.dx;
-    const double len = (double)(ext[axis] - 1) * G.dx;
-    const double q = 0.5 * (q2[0] * G.dx - q2[1] * G.dx);  // mean of inlet inflow and outlet outflow
-    const double t = (meta[0].percolates && q > 0) ? meta[0].psi * area / (q * len)
-                                                     : std::numeric_limits<double>::infinity();
+    const double t = out[0].tau;
     if (tau) *tau = t;
     if (rel_residual) *rel_residual = rel;
     if (iters) *iters = total;
@@ -470,14 +455,13 @@ rd_status batch_cg(rd_batch *b, int axis, double rel_tol, int64_t max_iters, boo
     if (b->nb > 0) {
         std::vector<char> perc;
         const int64_t nslots = b->nb * (int64_t)NS;
+        a.x64 = (double *)(b->ws + b->o_x64);  // the FP64 iterate (the guess writes it)
         rd_status s0 = gpu_initial_guess(a, (int)b->storage, b->B, axis, nslots,
                                          b->o_vec[4] - b->o_vec[3] + es * (size_t)nslots,
                                          b->o_vec[2] - b->o_vec[1], b->stream, perc);
         if (s0 != RD_OK) return s0;
         for (int i = 0; i < n; ++i) meta[i].percolates = perc[(size_t)i] != 0;
         // FP64 iterate with residual replacement, as for one geometry
-        a.x64 = (double *)(b->ws + b->o_x64);
-        LAUNCHCHK(ir_launch_axpy((int)b->storage, nslots, 0, 0.0, a.x64, a.x, b->stream));
         a.x64_direct = b->storage == RD_FP32 ? 0 : 1;
         if (!a.x64_direct) LAUNCHCHK(rd_launch_fill_u32(a.x, 0u, nslots, b->stream));
         return run_cg(a, (int)b->storage, b->B, b->stream, axis, rel_tol, max_iters, meta, out,

@@ -48,24 +48,22 @@ int cg_launch_matvec_fused(int storage, const CgArgs &a, void *stream);
 // recomputes it from p.
 int cg_launch_update(int storage, int B, const CgArgs &a, void *stream);
 int cg_launch_pupdate(int storage, int B, const CgArgs &a, void *stream);
-int cg_launch_flux(int storage, int B, const CgArgs &a, int inlet_face, void *stream);
+// per-block FP64 partials (inlet, outlet) of the flux of x64 through the Dirichlet planes
+int cg_launch_flux(int B, const CgArgs &a, int inlet_face, void *stream);
 int cg_launch_segsum(const CgArgs &a, int slot0, int slot1, int mode, void *stream);
-// Initial guess of the unit-drop problem along `axis` into a.x (every slot), from the
+// Initial guess of the unit-drop problem along `axis` into a.x (every slot, rounded to
+// the storage type) and a.x64 (FP64), from the
 // 6-connected clusters of active voxels labelled on the GPU.  Scratch: par[nslots]
 // (uint32), flags[2 * nslots] (bytes, zeroed by the caller), perc[ngeom] (uint32,
 // zeroed by the caller; set to 1 for geometries with a cluster touching both planes).
-// FP64 iterate helpers (single geometry), partial rows of ir_rows(nslots) x 2 doubles.
-// axpy mode 0: X = x; 2: x = X (rounded).  flux: (inlet, outlet) sums of
-// X_p - X_q over Dirichlet voxels p and their free neighbours q.
+// FP64 iterate helpers: rows of 256 slots; x = X rounded to the storage type.
 int ir_rows(int64_t nslots);
 // r = b - A x64 in FP64 (per-block partials (r.r, b.b)); store 1 writes it to r and p;
 // store 2 writes sigma r to r and rescales p; store 3 only rescales r and p.  B = 8 with
 // store 0 (the check) evaluates the unfolded iterate x64 + x / sigma when x64_direct is 0.
 int cg_launch_res64(int storage, int B, const CgArgs &a, int store, void *stream);
-int ir_launch_axpy(int storage, int64_t nslots, int mode, double s, double *X, void *x, void *stream);
+int ir_launch_store(int storage, int64_t nslots, const double *X, void *x, void *stream);
 // x64 += x / sigma (per geometry), x = 0
 int ir_launch_fold(int storage, int B, const CgArgs &a, int64_t nslots, void *stream);
-int ir_launch_flux(int B, const CgArgs &a, int64_t nslots, int inlet_face, const double *X, double *partial,
-                   void *stream);
 int cg_launch_initial_guess(int storage, int B, const CgArgs &a, int axis, int64_t nslots, uint32_t *par,
                             uint8_t *flags, uint32_t *perc, void *stream);
