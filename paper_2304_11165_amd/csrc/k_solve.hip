@@ -776,23 +776,6 @@ __device__ __forceinline__ void ir_pos(const BlockInfo *info, const GeomInfo *ge
     *gz = bz * B + slot / (B * B);
 }
 
-// sum of two FP64 values over the workgroup, written to part[blockIdx.x * 2 + k]
-__device__ __forceinline__ void wg_sum2(double v0, double v1, double *part)
-{
-    __shared__ double sh[4][2];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    v0 = wave_sum(v0);
-    v1 = wave_sum(v1);
-    if (lane == 0) {
-        sh[wave][0] = v0;
-        sh[wave][1] = v1;
-    }
-    __syncthreads();
-    if (threadIdx.x < 2)
-        part[(int64_t)blockIdx.x * 2 + threadIdx.x] =
-            ((sh[0][threadIdx.x] + sh[1][threadIdx.x]) + sh[2][threadIdx.x]) + sh[3][threadIdx.x];
-}
-
 // r = b - A X on free voxels in FP64 from the FP64 iterate X, with the Dirichlet values
 // held in X: r_p = sum over active neighbours q of (X_q - X_p) (difference form, order
 // -x,+x,-y,+y,-z,+z); b_p = sum of the Dirichlet neighbours' X_q.  Per-block FP64
