@@ -195,8 +195,10 @@ rd_status rd_sim_plane_flux(rd_sim *sim, int species, int axis, int64_t i0, doub
  * FP64; every 25 iterations the FP64 residual b - A x is evaluated (rel_residual is its
  * norm over ||b||) and replaces the recursive residual when the two have drifted apart,
  * so 1e-8 is reachable with FP32, BF16 or FP16 vectors.  Stops at rel. residual <=
- * rel_tol (RD_OK), or at stagnation (no 10% decrease of the best residual over 16
- * checks) or max_iters (RD_ERR_NOT_CONVERGED, outputs still written).
+ * rel_tol (RD_OK), or at stagnation (no 10% decrease of the best residual over 40
+ * checks, i.e. 1000 iterations: CG's residual is not monotone and plateaus for
+ * hundreds of iterations on large volumes) or max_iters (RD_ERR_NOT_CONVERGED, outputs
+ * still written).
  * tau = psi D A / (Q L): psi active fraction, A box cross-section, L = (n-1) dx,
  * Q the mean of the inflow at the inlet plane and the outflow at the outlet plane of
  * the FP64 iterate (equal at an exact steady state; eq. tortuosity, tau = D_f / D_eff);

@@ -39,7 +39,9 @@ struct CgOut {
 };
 
 constexpr int CHECK_EVERY = 25;  // iterations between true-residual checks
-constexpr int STALL_CHECKS = 8;  // stop after this many checks without a 10% gain
+// stop after this many checks (1000 iterations) without a 10% gain of the best residual:
+// CG's residual is not monotone and plateaus for hundreds of iterations on large volumes
+constexpr int STALL_CHECKS = 40;
 
 // Initial guess on the GPU (cg_launch_initial_guess).  Its scratch lives in solver
 // vectors that CG has not used yet: the parent array in the Ap and second-p buffers,
@@ -285,7 +287,7 @@ extern "C" rd_status rd_sim_steady_state(rd_sim *sim, int axis, double rel_tol, 
     // iteration); 16-bit storage is too coarse for that and updates X directly
     a.x64_direct = sim->storage == RD_FP32 ? 0 : 1;
     if (!a.x64_direct) LAUNCHCHK(rd_launch_fill_u32(a.x, 0u, nslots, stream));  // FP32: one word a slot
-    rd_status s = run_cg(a, st_, G.B, stream, axis, rel_tol, max_iters, meta, out, 2 * STALL_CHECKS, true);
+    rd_status s = run_cg(a, st_, G.B, stream, axis, rel_tol, max_iters, meta, out, STALL_CHECKS, true);
     if (s != RD_OK) return s;
     // (run_cg leaves X rounded to the storage type in the field and tau from its FP64 flux)
     const double rel = out[0].rel;
@@ -465,7 +467,7 @@ rd_status batch_cg(rd_batch *b, int axis, double rel_tol, int64_t max_iters, boo
         a.x64_direct = b->storage == RD_FP32 ? 0 : 1;
         if (!a.x64_direct) LAUNCHCHK(rd_launch_fill_u32(a.x, 0u, nslots, b->stream));
         return run_cg(a, (int)b->storage, b->B, b->stream, axis, rel_tol, max_iters, meta, out,
-                      2 * STALL_CHECKS, want_tau);
+                      STALL_CHECKS, want_tau);
     }
     out.assign(n, CgOut());
     for (auto &o : out) o.tau = std::numeric_limits<double>::infinity();
