@@ -1173,7 +1173,19 @@ int ir_launch_fold(int storage, int B, const CgArgs &a, int64_t nslots, void *st
 }
 int cg_launch_segsum(const CgArgs &a, int slot0, int slot1, int mode, void *stream)
 {
-    hipLaunchKernelGGL(k_cg_segsum, dim3((unsigned)a.ngeom), dim3(256), 0, (hipStream_t)stream,
-                       (const double *)a.partial, a.geom, a.ngeom, a.nb, a.scal, slot0, slot1, mode);
+    hipStream_t st = (hipStream_t)stream;
+    if (a.ngeom == 1 && a.mid && a.nb > 4096) {
+        // one long block list: fixed row ranges over 256 workgroups, then their sums, then
+        // the recurrence on that single row (one workgroup over millions of rows would
+        // take as long as a matvec)
+        double *sum = a.mid + 1024;
+        const int e = rd_launch_finish_reduce(a.partial, a.nb, 2, a.mid, sum, stream);
+        if (e) return e;
+        hipLaunchKernelGGL(k_cg_segsum, dim3(1), dim3(256), 0, st, (const double *)sum, a.geom, 1, 1, a.scal, slot0,
+                           slot1, mode);
+        return (int)hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_cg_segsum, dim3((unsigned)a.ngeom), dim3(256), 0, st, (const double *)a.partial, a.geom,
+                       a.ngeom, a.nb, a.scal, slot0, slot1, mode);
     return (int)hipGetLastError();
 }

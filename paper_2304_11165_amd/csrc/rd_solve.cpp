@@ -257,6 +257,7 @@ extern "C" rd_status rd_sim_steady_state(rd_sim *sim, int axis, double rel_tol, 
     a.p2 = sim->ws + sim->L.solver[3];
     a.partial = (double *)(sim->ws + sim->L.part);
     a.scal = (double *)(sim->ws + sim->L.scal);
+    a.mid = (double *)(sim->ws + sim->L.mid);
     std::vector<GeomMeta> meta(1);
     meta[0] = {G.nx, G.ny, G.nz, (double)G.n_active / ((double)G.nx * G.ny * G.nz), G.dx, false};
     std::vector<CgOut> out;

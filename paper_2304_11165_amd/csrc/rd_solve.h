@@ -38,6 +38,8 @@ struct CgArgs {
     void *p2;              // second p buffer (B = 8: the fused p update writes here)
     double *partial;       // [nb][2]
     double *scal;          // [ngeom][CG_NSCAL]
+    double *mid;           // single geometry: scratch of >= 1040 doubles for two-level sums
+                           // of long block lists (NULL: one workgroup per geometry)
 };
 
 int cg_launch_matvec(int storage, int B, const CgArgs &a, void *stream);
