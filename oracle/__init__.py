@@ -53,6 +53,14 @@ def _load():
     lib.orc_ftcs_run.restype = ci
     lib.orc_balance.argtypes = [i64, i64, i64, f64, P, ci, P, P, P, ci, P, P, P, P, ci, P, P, P, P]
     lib.orc_balance.restype = ci
+    lib.orc_ftcs_run_eps.argtypes = [i64, i64, i64, f64, P, ci, P, P, P, ci, P, P, P, P, P, f64,
+                                     i64, P, P]
+    lib.orc_ftcs_run_eps.restype = ci
+    lib.orc_balance_eps.argtypes = [i64, i64, i64, f64, P, ci, P, P, P, ci, P, P, P, P, P, ci, P,
+                                    P, P, P]
+    lib.orc_balance_eps.restype = ci
+    lib.orc_smooth_diffusivity.argtypes = [i64, P, f64, f64, f64, f64, P]
+    lib.orc_smooth_diffusivity.restype = None
     lib.orc_plane_flux.argtypes = [i64, i64, i64, f64, P, f64, P, ci, i64]
     lib.orc_plane_flux.restype = f64
     lib.orc_steady_jacobi.argtypes = [i64, i64, i64, P, P, P, f64, i64, i64, P, P]
@@ -86,8 +94,11 @@ class Problem:
     reactions [(from, to, rate)], to = -1 for decay
     """
 
-    def __init__(self, image, D, dx=1.0, robin=None, dirichlet=None, reactions=None):
+    def __init__(self, image, D, dx=1.0, robin=None, dirichlet=None, reactions=None, eps=None):
         self.image = np.ascontiguousarray(image, dtype=np.uint8)
+        # per-voxel diffusivity factor: D of species s at voxel p is D[s] * eps[p]
+        self.eps = None if eps is None else np.ascontiguousarray(
+            np.asarray(eps, dtype=np.float64).reshape(self.image.shape))
         assert self.image.ndim == 3
         self.nz, self.ny, self.nx = self.image.shape
         self.N = self.image.size
@@ -149,10 +160,11 @@ class Problem:
         src = None
         if source is not None:
             src = np.ascontiguousarray(np.asarray(source, dtype=np.float64).reshape(c.shape))
-        rc = lib.orc_ftcs_run(self.nx, self.ny, self.nz, self.dx, _ptr(self.image), self.S,
-                              _ptr(self.D), _ptr(self.robin), _ptr(self.dir_face),
-                              len(self.r_rate), _ptr(self.r_from), _ptr(self.r_to),
-                              _ptr(self.r_rate), _ptr(src), float(dt), int(nsteps), _ptr(c), None)
+        rc = lib.orc_ftcs_run_eps(self.nx, self.ny, self.nz, self.dx, _ptr(self.image), self.S,
+                                  _ptr(self.D), _ptr(self.robin), _ptr(self.dir_face),
+                                  len(self.r_rate), _ptr(self.r_from), _ptr(self.r_to),
+                                  _ptr(self.r_rate), _ptr(src), _ptr(self.eps), float(dt),
+                                  int(nsteps), _ptr(c), None)
         if rc != 0:
             raise MemoryError("oracle: allocation failed")
         return c
@@ -164,10 +176,11 @@ class Problem:
             self.S, self.nz, self.ny, self.nx))
         mass, robin, react = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         inflow = np.zeros(6)
-        lib.orc_balance(self.nx, self.ny, self.nz, self.dx, _ptr(self.image), self.S,
-                        _ptr(self.D), _ptr(self.robin), _ptr(self.dir_face), len(self.r_rate),
-                        _ptr(self.r_from), _ptr(self.r_to), _ptr(self.r_rate), _ptr(c), int(s),
-                        ctypes.byref(mass), _ptr(inflow), ctypes.byref(robin), ctypes.byref(react))
+        lib.orc_balance_eps(self.nx, self.ny, self.nz, self.dx, _ptr(self.image), self.S,
+                            _ptr(self.D), _ptr(self.robin), _ptr(self.dir_face), len(self.r_rate),
+                            _ptr(self.r_from), _ptr(self.r_to), _ptr(self.r_rate), _ptr(self.eps),
+                            _ptr(c), int(s), ctypes.byref(mass), _ptr(inflow), ctypes.byref(robin),
+                            ctypes.byref(react))
         return mass.value, inflow, robin.value, react.value
 
     def plane_flux(self, u, D, axis, i0):
@@ -175,6 +188,16 @@ class Problem:
         u = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(self.nz, self.ny, self.nx))
         return lib.orc_plane_flux(self.nx, self.ny, self.nz, self.dx, _ptr(self.image), float(D),
                                   _ptr(u), int(axis), int(i0))
+
+
+def smooth_diffusivity(phi, d_min, d_max, gamma1, gamma2):
+    """D(phi) = d_min + d_max / (1 + exp(-(gamma1 + gamma2 phi))), FP64 (section "Level-set
+    method for image-based geometry reconstruction", eq. inhomog_diffusion_coefficient)."""
+    phi = np.ascontiguousarray(np.asarray(phi, dtype=np.float64))
+    out = np.empty_like(phi)
+    _load().orc_smooth_diffusivity(phi.size, _ptr(phi), float(d_min), float(d_max),
+                                   float(gamma1), float(gamma2), _ptr(out))
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -16,7 +16,10 @@
  *    space (section "Discretization and numerical methods"), written in the
  *    conservative per-axis flux form of the inhomogeneous-diffusion functor of
  *    appendix "Code examples": u' = u + dt/dx^2 * sum_axes [D+(u+ - u) - D-(u - u-)],
- *    D+- the arithmetic mean of D at the two points (constant D per species here);
+ *    D+- the arithmetic mean of D at the two points; D at a point is D_s * e(x) with
+ *    an optional per-voxel factor e (e = 1 without one: constant D per species);
+ *  - the smooth diffusivity D(phi) = D_min + D_max / (1 + exp(-(g1 + g2 phi))) of
+ *    section "Level-set method ...", eq. inhomog_diffusion_coefficient, used as e;
  *  - no-flux walls by the mirror rule of the same section: a neighbour outside
  *    Omega takes the centre's value, so that face's flux is zero;
  *  - reactions evaluated at the old time level (law of mass action, first order);
@@ -99,17 +102,19 @@ static int wall_count(const uint8_t *active, int64_t i, int64_t j, int64_t k,
  *  robin_k[s]  wall-uptake coefficient k_R of species s (0: plain no-flux); may be NULL
  *  reactions   r_from[r] -> r_to[r] (r_to = -1: decay) with first-order rate r_rate[r]
  *  source      optional volumetric source nspec*N (added as dt*source), may be NULL
+ *  eps         optional per-voxel diffusivity factor (N values): D at voxel p is
+ *              D[s] * eps[p]; NULL means eps = 1
  */
 static void ftcs_step(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8_t *active,
                       int nspec, const double *D, const double *robin_k, const uint8_t *dir_face,
                       int nreact, const int32_t *r_from, const int32_t *r_to, const double *r_rate,
-                      const double *source, double dt, const double *cin, double *cout)
+                      const double *source, const double *eps, double dt, const double *cin,
+                      double *cout)
 {
     const int64_t N = nx * ny * nz;
     for (int s = 0; s < nspec; ++s) {
         const double *u = cin + (int64_t)s * N;
         double *uo = cout + (int64_t)s * N;
-        const double Dc = D[s];
         const double kR = robin_k ? robin_k[s] : 0.0;
 #pragma omp parallel for schedule(static)
         for (int64_t k = 0; k < nz; ++k) {
@@ -119,21 +124,30 @@ static void ftcs_step(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8
                     if (!active[p]) { uo[p] = 0.0; continue; }
                     if (is_dirichlet(dir_face, s, i, j, k, nx, ny, nz)) { uo[p] = u[p]; continue; }
                     const double uc = u[p];
-                    /* neighbour values with the mirror rule: outside Omega -> u_c */
-                    double nb[6];
+                    const double Dc = D[s] * (eps ? eps[p] : 1.0);
+                    /* neighbour values and coefficients with the mirror rule: outside
+                     * Omega (or the box) both take the centre's, u -> u_c, D -> D_c */
+                    double nb[6], Dn[6];
                     int nwall = 0;
                     for (int f = 0; f < 6; ++f) {
                         int64_t a = i + DI[f], b = j + DJ[f], c = k + DK[f];
-                        if (!in_box(a, b, c, nx, ny, nz)) { nb[f] = uc; continue; }
+                        nb[f] = uc;
+                        Dn[f] = Dc;
+                        if (!in_box(a, b, c, nx, ny, nz)) continue;
                         int64_t q = IDX(a, b, c);
-                        if (active[q]) nb[f] = u[q];
-                        else { nb[f] = uc; ++nwall; }
+                        if (active[q]) {
+                            nb[f] = u[q];
+                            Dn[f] = D[s] * (eps ? eps[q] : 1.0);
+                        } else {
+                            ++nwall;
+                        }
                     }
-                    /* arithmetic-mean D at the half points; constant D gives D */
-                    const double Dh = 0.5 * (Dc + Dc);
-                    double flux = Dh * (nb[1] - uc) - Dh * (uc - nb[0])   /* x */
-                                + Dh * (nb[3] - uc) - Dh * (uc - nb[2])   /* y */
-                                + Dh * (nb[5] - uc) - Dh * (uc - nb[4]);  /* z */
+                    /* arithmetic-mean D at the half points */
+                    double Dh[6];
+                    for (int f = 0; f < 6; ++f) Dh[f] = 0.5 * (Dc + Dn[f]);
+                    double flux = Dh[1] * (nb[1] - uc) - Dh[0] * (uc - nb[0])   /* x */
+                                + Dh[3] * (nb[3] - uc) - Dh[2] * (uc - nb[2])   /* y */
+                                + Dh[5] * (nb[5] - uc) - Dh[4] * (uc - nb[4]);  /* z */
                     double un = uc + dt * (1.0 / (dx * dx)) * flux;
                     /* reactive wall: flux k_R*u through each wall face of area dx^2 */
                     un -= dt * kR * (double)nwall * uc / dx;
@@ -151,11 +165,13 @@ static void ftcs_step(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8
     }
 }
 
-/* Run nsteps FTCS steps in place on c (nspec*N).  work: nspec*N scratch (may be NULL). */
-int orc_ftcs_run(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8_t *active,
-                 int nspec, const double *D, const double *robin_k, const uint8_t *dir_face,
-                 int nreact, const int32_t *r_from, const int32_t *r_to, const double *r_rate,
-                 const double *source, double dt, int64_t nsteps, double *c, double *work)
+/* Run nsteps FTCS steps in place on c (nspec*N).  work: nspec*N scratch (may be NULL).
+ * eps: per-voxel diffusivity factor (N values) or NULL. */
+int orc_ftcs_run_eps(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8_t *active,
+                     int nspec, const double *D, const double *robin_k, const uint8_t *dir_face,
+                     int nreact, const int32_t *r_from, const int32_t *r_to, const double *r_rate,
+                     const double *source, const double *eps, double dt, int64_t nsteps,
+                     double *c, double *work)
 {
     const int64_t N = nx * ny * nz;
     double *tmp = work;
@@ -168,7 +184,7 @@ int orc_ftcs_run(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8_t *a
     double *a = c, *b = tmp;
     for (int64_t n = 0; n < nsteps; ++n) {
         ftcs_step(nx, ny, nz, dx, active, nspec, D, robin_k, dir_face, nreact, r_from, r_to,
-                  r_rate, source, dt, a, b);
+                  r_rate, source, eps, dt, a, b);
         double *t = a; a = b; b = t;
     }
     if (a != c) memcpy(c, a, sizeof(double) * (size_t)(N * nspec));
@@ -176,20 +192,39 @@ int orc_ftcs_run(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8_t *a
     return 0;
 }
 
+int orc_ftcs_run(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8_t *active,
+                 int nspec, const double *D, const double *robin_k, const uint8_t *dir_face,
+                 int nreact, const int32_t *r_from, const int32_t *r_to, const double *r_rate,
+                 const double *source, double dt, int64_t nsteps, double *c, double *work)
+{
+    return orc_ftcs_run_eps(nx, ny, nz, dx, active, nspec, D, robin_k, dir_face, nreact, r_from,
+                            r_to, r_rate, source, NULL, dt, nsteps, c, work);
+}
+
+/* Smooth diffusivity of eq. inhomog_diffusion_coefficient (section "Level-set method
+ * for image-based geometry reconstruction"): out[i] = d_min + d_max / (1 +
+ * exp(-(g1 + g2 * phi[i]))), FP64. */
+void orc_smooth_diffusivity(int64_t n, const double *phi, double d_min, double d_max, double g1,
+                            double g2, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = d_min + d_max / (1.0 + exp(-(g1 + g2 * phi[i])));
+}
+
 /*
  * Balance terms of species s for the field c (nspec*N):
  *   mass          sum over free voxels of c * dx^3       (paper: total-mass monitor)
  *   inflow[6]     per Dirichlet face f: sum over (q Dirichlet on f, p free active
- *                 neighbour of q) of D*(c_q - c_p)*dx   (diffusive flux into the domain)
+ *                 neighbour of q) of D_h*(c_q - c_p)*dx, D_h the mean of D at q and p
  *   robin         sum over free voxels of k_R * n_wall * c * dx^2
  *   react         sum over free voxels of the reaction rate of s, times dx^3
  * A voxel is "free" for s if it is active and not a Dirichlet voxel of s.  With
  * these terms one FTCS step satisfies M' - M = dt*(sum(inflow) - robin + react).
  */
-int orc_balance(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8_t *active,
-                int nspec, const double *D, const double *robin_k, const uint8_t *dir_face,
-                int nreact, const int32_t *r_from, const int32_t *r_to, const double *r_rate,
-                const double *c, int s, double *mass, double *inflow, double *robin, double *react)
+int orc_balance_eps(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8_t *active,
+                    int nspec, const double *D, const double *robin_k, const uint8_t *dir_face,
+                    int nreact, const int32_t *r_from, const int32_t *r_to, const double *r_rate,
+                    const double *eps, const double *c, int s, double *mass, double *inflow,
+                    double *robin, double *react)
 {
     const int64_t N = nx * ny * nz;
     const double *u = c + (int64_t)s * N;
@@ -210,7 +245,10 @@ int orc_balance(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8_t *ac
                         int64_t q = IDX(a, b, cc);
                         if (!active[q]) continue;
                         if (is_dirichlet(dir_face, s, a, b, cc, nx, ny, nz)) continue;
-                        fl[df] += D[s] * (u[p] - u[q]) * dx;
+                        /* arithmetic mean of D at the two voxels, as in the step */
+                        const double Dh = 0.5 * (D[s] * (eps ? eps[p] : 1.0) +
+                                                 D[s] * (eps ? eps[q] : 1.0));
+                        fl[df] += Dh * (u[p] - u[q]) * dx;
                     }
                     continue;
                 }
@@ -227,6 +265,15 @@ int orc_balance(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8_t *ac
     *react = re;
     for (int f = 0; f < 6; ++f) inflow[f] = fl[f];
     return 0;
+}
+
+int orc_balance(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8_t *active,
+                int nspec, const double *D, const double *robin_k, const uint8_t *dir_face,
+                int nreact, const int32_t *r_from, const int32_t *r_to, const double *r_rate,
+                const double *c, int s, double *mass, double *inflow, double *robin, double *react)
+{
+    return orc_balance_eps(nx, ny, nz, dx, active, nspec, D, robin_k, dir_face, nreact, r_from,
+                           r_to, r_rate, NULL, c, s, mass, inflow, robin, react);
 }
 
 /* Diffusive flux of one species through the plane between index i and i+1 along
@@ -435,7 +482,7 @@ int orc_adjoint_decay(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8
     memcpy(cur, c0, sizeof(double) * (size_t)N);
     memcpy(cps, cur, sizeof(double) * (size_t)N);
     for (int64_t n = 0; n < nsteps; ++n) {
-        ftcs_step(nx, ny, nz, dx, active, 1, &D, NULL, dir_face, 1, &rf, &rt, &k, NULL, dt, cur, tmp);
+        ftcs_step(nx, ny, nz, dx, active, 1, &D, NULL, dir_face, 1, &rf, &rt, &k, NULL, NULL, dt, cur, tmp);
         memcpy(cur, tmp, sizeof(double) * (size_t)N);
         if ((n + 1) % stride == 0)
             memcpy(cps + ((n + 1) / stride) * N, cur, sizeof(double) * (size_t)N);
@@ -456,7 +503,7 @@ int orc_adjoint_decay(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8
         int64_t len = s1 - s0;
         memcpy(seg, cps + (s0 / stride) * N, sizeof(double) * (size_t)N);
         for (int64_t m = 0; m < len - 1; ++m)
-            ftcs_step(nx, ny, nz, dx, active, 1, &D, NULL, dir_face, 1, &rf, &rt, &k, NULL, dt,
+            ftcs_step(nx, ny, nz, dx, active, 1, &D, NULL, dir_face, 1, &rf, &rt, &k, NULL, NULL, dt,
                       seg + m * N, seg + (m + 1) * N);
         for (int64_t m = len - 1; m >= 0; --m) {
             const double *c = seg + m * N; /* c^{s0+m}; lam holds lambda^{s0+m+1} */
