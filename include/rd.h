@@ -63,6 +63,7 @@ typedef enum { RD_FP32 = 0, RD_BF16 = 1, RD_FP16 = 2 } rd_storage;
 /* Workspace features (rd_sim_workspace_bytes). */
 #define RD_WS_SOLVER 1u   /* vectors for rd_sim_steady_state */
 #define RD_WS_ADJOINT 2u  /* adjoint vectors + checkpoint slots for rd_sim_adjoint */
+#define RD_WS_DIFFUSIVITY 4u  /* a per-voxel diffusivity factor (rd_sim_set_diffusivity) */
 
 typedef struct rd_geometry rd_geometry;
 typedef struct rd_sim rd_sim;
@@ -158,6 +159,30 @@ rd_status rd_sim_bind(rd_sim *sim, void *dev_workspace, size_t bytes, uint32_t f
 /* Scatter a dense device field float32 (nz,ny,nx) into species s; inactive voxels are
  * ignored and Dirichlet voxels take their held value. */
 rd_status rd_sim_set_field(rd_sim *sim, int species, const float *dev_dense);
+/* Inhomogeneous diffusion (section "Level-set method for image-based geometry
+ * reconstruction", eq. inhomog_diffusion_coefficient; section "Application example
+ * 1"; the inhomogeneous-diffusion functor of appendix "Code examples").  A per-voxel
+ * factor e makes the diffusion coefficient of species s D_s * e(x); the face between
+ * active voxels p and q uses the arithmetic mean D_s (e_p + e_q) / 2, faces toward
+ * inactive voxels carry no flux.  dev_dense: device float32 (nz,ny,nx), read at the
+ * active voxels only (values there must be finite and >= 0), copied into the
+ * workspace (bind with RD_WS_DIFFUSIVITY); the caller keeps ownership.  Synchronises.
+ * Afterwards rd_sim_step and rd_sim_balance (Dirichlet inflow with the mean
+ * coefficient) use the factor and the stability bound uses D_max * max(e);
+ * rd_sim_steady_state, rd_sim_plane_flux and rd_sim_adjoint return RD_ERR_STATE until
+ * rd_sim_clear_diffusivity.  Errors: RD_ERR_WORKSPACE without the feature,
+ * RD_ERR_STATE before bind, RD_ERR_ARG for a NULL pointer or for invalid values (the
+ * factor is then cleared).  A new bind clears the factor. */
+rd_status rd_sim_set_diffusivity(rd_sim *sim, const float *dev_dense);
+/* As rd_sim_set_diffusivity with e = d_min + d_max / (1 + exp(-(gamma1 + gamma2 phi)))
+ * evaluated on the GPU in FP64 (rounded to FP32) from a dense device float32 signed
+ * distance phi (nz,ny,nx) (eq. inhomog_diffusion_coefficient; the paper's soil example
+ * takes gamma2 = 4h and gamma1 = gamma2 min phi).  RD_ERR_ARG unless d_min, d_max >= 0
+ * and all four parameters are finite. */
+rd_status rd_sim_set_diffusivity_sdf(rd_sim *sim, const float *dev_sdf, double d_min, double d_max,
+                                     double gamma1, double gamma2);
+/* Back to the homogeneous D_s. */
+rd_status rd_sim_clear_diffusivity(rd_sim *sim);
 /* Gather species s into a dense device float32 (nz,ny,nx); inactive voxels -> 0. */
 rd_status rd_sim_get_field(const rd_sim *sim, int species, float *dev_dense);
 /* Advance n_steps FTCS steps of size dt (asynchronous).  RD_ERR_UNSTABLE_DT if

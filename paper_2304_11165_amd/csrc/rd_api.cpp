@@ -5,10 +5,12 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <new>
 #include <string>
 
 #include "rd_host.h"
+#include "rd_diff.h"
 #include "rd_sim.h"
 
 static thread_local std::string g_last_error;
@@ -259,6 +261,7 @@ extern "C" rd_status rd_sim_bind(rd_sim *sim, void *dev_workspace, size_t bytes,
     sim->ws_bytes = bytes;
     sim->L = L;
     sim->features = features;
+    sim->diff_on = false;
     sim->cp_slots = checkpoint_slots;
     sim->stream = (hipStream_t)stream;
     return sim->upload();
@@ -298,6 +301,10 @@ SimLayout sim_layout(const rd_sim &s, uint32_t features, int64_t cp_slots)
         }
         L.scal = off; off = align256(off + sizeof(double) * 64);
         L.irx = off; off = align256(off + 8 * (size_t)L.field_elems);
+    }
+    if (features & RD_WS_DIFFUSIVITY) {
+        L.diff = off; off = align256(off + 4 * (size_t)std::max<int64_t>(L.field_elems, 1));
+        L.diff_stats = off; off = align256(off + 8);
     }
     if (features & RD_WS_ADJOINT) {
         for (int v = 0; v < 2; ++v) {
@@ -414,7 +421,7 @@ double rd_sim::lambda_max() const
     const double dx = g->dx;
     double dmax = 0.0, rmax = 0.0, kmax = 0.0;
     for (int s = 0; s < S; ++s) {
-        dmax = std::max(dmax, D[s]);
+        dmax = std::max(dmax, D[s] * (diff_on ? e_max : 1.0));
         kmax = std::max(kmax, robin[s]);
         double out_rate = 0.0;
         for (const Reaction &r : reactions)
@@ -459,7 +466,17 @@ rd_status rd_sim::launch_steps(double dt, int64_t n)
         a.seed = seed;
         a.ctr = step_counter();
         a.ctr_off = (uint32_t)i;
-        LAUNCHCHK(rd_launch_step(storage, g->B, a, stream));
+        if (diff_on) {
+            // B = 8: the column kernel unless the workgroup-per-block kernel is chosen
+            // (then one thread per slot); B = 4: one thread per slot
+            const int column = g->B == 8 && kernel != 0 ? 1 : 0;
+            const int groups = (a.nb + 3) / 4;
+            a.xcd_chunk = column && xcd_map && groups >= 64 ? (groups + 7) / 8 : 0;
+            DiffArgs da{a, (const float *)(ws + L.diff)};
+            LAUNCHCHK(rd_launch_step_diff(storage, g->B, da, column, stream));
+        } else {
+            LAUNCHCHK(rd_launch_step(storage, g->B, a, stream));
+        }
         cur = 1 - cur;
     }
     // the device step counter advances once per batch of launches, so graph replay
@@ -557,9 +574,11 @@ rd_status rd_sim::balance(int s, double out[RD_NRED])
         if (r.to == s) a.rate_in[r.from] += r.rate;
     }
     a.partial = (double *)(ws + L.part);
-    const int nparts = rd_reduce_rows(g->B, a.nb);  // 0 for an empty geometry: sums are 0
+    // 0 rows for an empty geometry: sums are 0
+    const int nparts = diff_on ? rd_diff_reduce_rows(g->B, a.nb) : rd_reduce_rows(g->B, a.nb);
     double *res = (double *)(ws + L.res);
-    LAUNCHCHK(rd_launch_reduce(storage, g->B, a, stream));
+    if (diff_on) LAUNCHCHK(rd_launch_reduce_diff(storage, g->B, a, (const float *)(ws + L.diff), stream));
+    else LAUNCHCHK(rd_launch_reduce(storage, g->B, a, stream));
     LAUNCHCHK(rd_launch_finish_reduce(a.partial, nparts, RD_NRED, (double *)(ws + L.mid), res, stream));
     HIPCHK(hipMemcpyAsync(host_res, res, sizeof(double) * RD_NRED, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
@@ -587,6 +606,61 @@ extern "C" rd_status rd_sim_set_field(rd_sim *sim, int species, const float *dev
                                 dev_dense, sim->field_ptr(sim->cur, species), sim->dir[species], dv,
                                 sim->stream));
     sim->steps_taken = 0;
+    return RD_OK;
+}
+
+// Fill the diffusivity factor (mode 0: values, mode 1: smooth D(phi)), check it and
+// switch the steps to the inhomogeneous kernels.
+static rd_status set_diffusivity(rd_sim *sim, const float *dev_dense, int mode, double d_min,
+                                 double d_max, double g1, double g2)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    if (!sim->ws) return rd_fail(RD_ERR_STATE, "bind a workspace first");
+    if (!(sim->features & RD_WS_DIFFUSIVITY))
+        return rd_fail(RD_ERR_WORKSPACE, "bind with RD_WS_DIFFUSIVITY for a diffusivity factor");
+    if (!dev_dense) return rd_fail(RD_ERR_ARG, "array pointer is NULL");
+    if (mode == 1 && !(std::isfinite(d_min) && std::isfinite(d_max) && std::isfinite(g1) &&
+                       std::isfinite(g2) && d_min >= 0.0 && d_max >= 0.0))
+        return rd_fail(RD_ERR_ARG, "need finite d_min, d_max >= 0 and finite gamma1, gamma2");
+    char *ws = sim->ws;
+    const SimLayout &L = sim->L;
+    uint32_t *stats = (uint32_t *)(ws + L.diff_stats);
+    LAUNCHCHK(rd_launch_set_diff(sim->g->B, (const BlockInfo *)(ws + L.info), (const uint8_t *)(ws + L.code),
+                                 (const GeomInfo *)(ws + L.geom), (int)sim->g->nb(), dev_dense, mode, d_min,
+                                 d_max, g1, g2, (float *)(ws + L.diff), stats, sim->stream));
+    HIPCHK(hipMemcpyAsync(sim->host_res, stats, 8, hipMemcpyDeviceToHost, sim->stream));
+    HIPCHK(hipStreamSynchronize(sim->stream));
+    uint32_t hs[2];
+    memcpy(hs, sim->host_res, 8);
+    sim->invalidate_graphs();
+    if (hs[0] != 0) {
+        sim->diff_on = false;
+        return rd_fail(RD_ERR_ARG, std::to_string(hs[0]) + " active voxels have a negative or non-finite "
+                                   "diffusivity factor (the factor is cleared)");
+    }
+    float emax;
+    memcpy(&emax, &hs[1], 4);
+    sim->e_max = (double)emax;
+    sim->diff_on = true;
+    return RD_OK;
+}
+
+extern "C" rd_status rd_sim_set_diffusivity(rd_sim *sim, const float *dev_dense)
+{
+    return set_diffusivity(sim, dev_dense, 0, 0.0, 0.0, 0.0, 0.0);
+}
+
+extern "C" rd_status rd_sim_set_diffusivity_sdf(rd_sim *sim, const float *dev_sdf, double d_min, double d_max,
+                                                double gamma1, double gamma2)
+{
+    return set_diffusivity(sim, dev_sdf, 1, d_min, d_max, gamma1, gamma2);
+}
+
+extern "C" rd_status rd_sim_clear_diffusivity(rd_sim *sim)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    if (sim->diff_on) sim->invalidate_graphs();
+    sim->diff_on = false;
     return RD_OK;
 }
 
@@ -645,6 +719,7 @@ extern "C" rd_status rd_sim_plane_flux(rd_sim *sim, int species, int axis, int64
     if (!sim->ws) return rd_fail(RD_ERR_STATE, "bind a workspace first");
     if (species < 0 || species >= sim->S) return rd_fail(RD_ERR_ARG, "bad species");
     if (axis < 0 || axis > 2) return rd_fail(RD_ERR_ARG, "axis must be 0, 1 or 2");
+    if (sim->diff_on) return rd_fail(RD_ERR_STATE, "plane flux needs a homogeneous D (clear the factor)");
     const rd_geometry &G = *sim->g;
     const int64_t n = axis == 0 ? G.nx : axis == 1 ? G.ny : G.nz;
     if (i0 < 0 || i0 + 1 >= n)

@@ -37,6 +37,7 @@ struct SimLayout {
     size_t part, mid, res;  // reduction partials, finish scratch, results
     size_t solver[4], scal;  // CG vectors r, p, Ap, second p
     size_t irx;              // FP64 iterate of the steady state
+    size_t diff, diff_stats; // per-slot diffusivity factor (FP32) and its set-up counters
     size_t lam[2], target, cp, cp_stride;
     size_t total;
 };
@@ -69,6 +70,8 @@ struct rd_sim {
     int n_cu = 256;       // compute units of the bound device
     bool sround = false;  // stochastic rounding on store (BF16 / FP16 storage)
     uint32_t seed = 0;
+    bool diff_on = false;  // a diffusivity factor is set (inhomogeneous diffusion)
+    double e_max = 0.0;    // its largest value over the active voxels
 
     char *ws = nullptr;
     size_t ws_bytes = 0;

@@ -38,6 +38,7 @@ STATUS = ["RD_OK", "RD_ERR_ARG", "RD_ERR_SHAPE", "RD_ERR_INCONSISTENT_SDF", "RD_
 STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2}
 RD_WS_SOLVER = 1
 RD_WS_ADJOINT = 2
+RD_WS_DIFFUSIVITY = 4
 KERNELS = ("block", "persistent", "column", "column_xch")  # B = 8 step kernels, by number
 
 _SIGS = {
@@ -61,6 +62,9 @@ _SIGS = {
     "rd_sim_workspace_bytes": ([P, u32, i64, P], ci),
     "rd_sim_bind": ([P, P, sz, u32, i64, P], ci),
     "rd_sim_set_field": ([P, ci, P], ci),
+    "rd_sim_set_diffusivity": ([P, P], ci),
+    "rd_sim_set_diffusivity_sdf": ([P, P, f64, f64, f64, f64], ci),
+    "rd_sim_clear_diffusivity": ([P], ci),
     "rd_sim_get_field": ([P, ci, P], ci),
     "rd_sim_step": ([P, f64, i64], ci),
     "rd_sim_steps_taken": ([P, P], ci),
@@ -302,6 +306,37 @@ class Sim:
         _check(_lib.rd_sim_set_field(self.handle, int(species), ctypes.c_void_p(t.data_ptr())),
                "rd_sim_set_field")
         self._keep = t  # lives until the stream has consumed it
+        return self
+
+    def set_diffusivity(self, dense):
+        """Per-voxel diffusivity factor e (dense (nz, ny, nx)): species s then diffuses
+        with D_s * e, the mean of the two voxels' coefficients on each face.  Needs a
+        bind with RD_WS_DIFFUSIVITY.  Synchronises."""
+        import torch
+
+        nz, ny, nx = self.geometry.shape
+        t = torch.as_tensor(dense, dtype=torch.float32, device=self.workspace.device)
+        t = t.reshape(nz, ny, nx).contiguous()
+        _check(_lib.rd_sim_set_diffusivity(self.handle, ctypes.c_void_p(t.data_ptr())),
+               "rd_sim_set_diffusivity")
+        return self
+
+    def set_diffusivity_sdf(self, sdf, d_min, d_max, gamma1, gamma2):
+        """e = d_min + d_max / (1 + exp(-(gamma1 + gamma2 phi))) from a dense signed
+        distance phi, evaluated on the GPU.  Synchronises."""
+        import torch
+
+        nz, ny, nx = self.geometry.shape
+        t = torch.as_tensor(sdf, dtype=torch.float32, device=self.workspace.device)
+        t = t.reshape(nz, ny, nx).contiguous()
+        _check(_lib.rd_sim_set_diffusivity_sdf(self.handle, ctypes.c_void_p(t.data_ptr()),
+                                               float(d_min), float(d_max), float(gamma1),
+                                               float(gamma2)),
+               "rd_sim_set_diffusivity_sdf")
+        return self
+
+    def clear_diffusivity(self):
+        _check(_lib.rd_sim_clear_diffusivity(self.handle), "rd_sim_clear_diffusivity")
         return self
 
     def get_field(self, species, out=None):
