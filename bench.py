@@ -54,6 +54,9 @@ def parse():
     p.add_argument("--steady-tol", type=float, default=1e-8)
     p.add_argument("--adjoint", type=int, default=0,
                    help="1: time the checkpointed adjoint on the 256^3 diffusion-decay packing")
+    p.add_argument("--diffusivity-steps", type=int, default=0,
+                   help="FP32 steps of the inhomogeneous-diffusion form (smooth D(phi) on the "
+                        "same volume; 0: skip)")
     p.add_argument("--cpu-steps", type=int, default=0,
                    help="oracle steps in the CPU sample (0: as many as fit in --cpu-seconds)")
     p.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -283,6 +286,53 @@ def adjoint_form(torch, rd, W, stream):
                     "backward sweep; FP32 fields, FP64 gradient sums"}
 
 
+# Smooth diffusivity of the inhomogeneous form: e = D_MIN + D_MAX / (1 + exp(-(G1 + G2 phi)))
+# with phi the distance to the pore wall (voxels): 0.1 at the wall, 1.0 deep in the
+# pores, the transition 1.5 voxels in and about a voxel wide.
+DIFF_PARS = (0.1, 0.9, -6.0, 4.0)
+
+
+def diffusivity_form(torch, rd, np, geom, img, w, n_active, steps, graph_steps, use_graph, stream):
+    """FP32 steps of the soil volume with the smooth D(phi) factor (inhomogeneous step
+    kernel).  Algorithmic bytes per launch: read + write of every species plus the
+    4-byte factor, per active voxel."""
+    from scipy import ndimage
+
+    t0 = time.perf_counter()
+    phi = (ndimage.distance_transform_edt(img.astype(bool)) - 0.5).astype(np.float32)
+    log(f"diffusivity: distance to the wall in {time.perf_counter() - t0:.1f}s")
+    S = len(w.species_D)
+    with torch.cuda.stream(stream):
+        sim = build_sim(rd, geom, w, "fp32", graph_steps, use_graph)
+        sim.set_kernel("column")
+        sim.bind(features=rd.RD_WS_DIFFUSIVITY, stream=stream)
+        sim.set_diffusivity_sdf(torch.from_numpy(phi).to("cuda"), *DIFF_PARS)
+        del phi
+        secs, wall = time_steps(torch, sim, stream, w.dt, 50, steps)
+        bal = [sim.balance(sp) for sp in range(S)]
+        torch.cuda.synchronize()
+    per = secs / steps
+    alg = (2 * 4 * S + 4) * n_active
+    res = {
+        "kernel": f"k_step8e<float,{S}>",
+        "diffusivity": "e = %g + %g / (1 + exp(-(%g + %g phi))), phi = distance to the wall - 1/2"
+                       % DIFF_PARS,
+        "steps": steps,
+        "seconds": secs,
+        "wall_seconds": wall,
+        "ms_per_step": per * 1e3,
+        "updates_per_s": n_active * steps / secs,
+        "alg_bytes_per_launch": alg,
+        "alg_GBps": alg / per / 1e9,
+        "frac_of_hbm_peak": alg / per / 1e9 / HBM_PEAK_GBS,
+        "mass": [b["mass"] for b in bal],
+        "inflow": [float(np.sum(b["inflow"])) for b in bal],
+    }
+    log(f"diffusivity: {per * 1e3:.4f} ms/step, {n_active * steps / secs:.3e} upd/s, "
+        f"alg {alg / per / 1e9:.0f} GB/s")
+    return res
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -428,6 +478,11 @@ def main():
         out["forms"]["steady"] = steady_form(torch, rd, W, a.steady_size, a.steady_axes,
                                              [f for f in a.steady_forms.split(",") if f],
                                              a.steady_tol, stream)
+
+    if a.diffusivity_steps > 0 and not a.profile:
+        out["forms"]["diffusivity"] = diffusivity_form(torch, rd, np, geom, img, w, n_active,
+                                                       a.diffusivity_steps, a.graph_steps,
+                                                       not a.no_graph, stream)
 
     if a.adjoint and not a.profile:
         out["forms"]["adjoint"] = adjoint_form(torch, rd, W, stream)
