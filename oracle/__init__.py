@@ -324,3 +324,69 @@ def active_index(image, B):
         weights = (np.uint64(1) << np.arange(chunk.shape[1], dtype=np.uint64))
         masks[:, w] = (chunk * weights).sum(axis=1, dtype=np.uint64)
     return block_id, nbr, masks
+
+
+# ---------------------------------------------------------------------------
+# simulated FRAP and the effective diffusion coefficient (section "Calculation of
+# effective diffusion coefficient and tortuosity")
+# ---------------------------------------------------------------------------
+
+def region_mass(image, c, region, dx=1.0):
+    """Sum of c dx^3 over the active voxels with x0 <= x < x1, y0 <= y < y1, z0 <= z < z1
+    (region = (x0, x1, y0, y1, z0, z1); arrays are (nz, ny, nx))."""
+    x0, x1, y0, y1, z0, z1 = region
+    act = np.asarray(image)[z0:z1, y0:y1, x0:x1] != 0
+    sub = np.asarray(c, dtype=np.float64)[z0:z1, y0:y1, x0:x1]
+    return float(np.sum(sub[act])) * dx ** 3
+
+
+def frap_curve(prob, c0, region, dt, steps_per_sample, n_samples, species=0):
+    """Region mass of one species after k * steps_per_sample FTCS steps, k = 0..n_samples."""
+    c = np.array(c0, dtype=np.float64, copy=True)
+    out = [region_mass(prob.image, c[species], region, prob.dx)]
+    for _ in range(n_samples):
+        c = prob.run(c, dt, steps_per_sample)
+        out.append(region_mass(prob.image, c[species], region, prob.dx))
+    return np.array(out)
+
+
+def frap_fit(t, f, ds, g, D_ref):
+    """D minimising sum_i (f_i - g(t_i D / D_ref))^2, g sampled at j * ds for coefficient
+    D_ref (free diffusion depends on D t only; linear interpolation), searched over
+    [1e-4, 1] * D_ref s_max / t_max: dense log grid, then a bounded scalar minimiser."""
+    from scipy.optimize import minimize_scalar
+
+    t = np.asarray(t, dtype=np.float64)
+    f = np.asarray(f, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    s = np.arange(len(g)) * ds
+    hi = s[-1] / t.max()
+
+    def err(logsc):
+        return float(np.sum((f - np.interp(t * math.exp(logsc), s, g)) ** 2))
+
+    grid = np.linspace(math.log(hi * 1e-4), math.log(hi), 2001)
+    e = np.array([err(x) for x in grid])
+    k = int(np.argmin(e))
+    lo_b, hi_b = grid[max(k - 1, 0)], grid[min(k + 1, len(grid) - 1)]
+    r = minimize_scalar(err, bounds=(lo_b, hi_b), method="bounded",
+                        options={"xatol": 1e-12})
+    return math.exp(r.x) * D_ref
+
+
+def frap_free_space(t, D, half_widths):
+    """Mass in the bleached box [-a, a]^3 of free diffusion in all of R^3 from
+    c = 1 - indicator(box): the solution factorises over axes,
+    c = 1 - prod_d h_d, h = (erf((a - x)/s) + erf((a + x)/s)) / 2, s = sqrt(4 D t), and
+    the integral of h over [-a, a] is 2a erf(2a/s) + s (exp(-4a^2/s^2) - 1)/sqrt(pi)."""
+    from scipy.special import erf
+
+    t = np.asarray(t, dtype=np.float64)
+    vol = 1.0
+    prod = np.ones_like(t)
+    for a in half_widths:
+        vol *= 2 * a
+        s = np.sqrt(4 * D * np.maximum(t, 1e-300))
+        ia = 2 * a * erf(2 * a / s) + s * (np.exp(-4 * a * a / (s * s)) - 1) / math.sqrt(math.pi)
+        prod = prod * np.where(t > 0, ia, 2 * a)
+    return vol - prod
