@@ -57,6 +57,8 @@ def parse():
     p.add_argument("--diffusivity-steps", type=int, default=0,
                    help="FP32 steps of the inhomogeneous-diffusion form (smooth D(phi) on the "
                         "same volume; 0: skip)")
+    p.add_argument("--frap-size", type=int, default=0,
+                   help="edge of the volume of the simulated-FRAP form (0: skip)")
     p.add_argument("--cpu-steps", type=int, default=0,
                    help="oracle steps in the CPU sample (0: as many as fit in --cpu-seconds)")
     p.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -333,6 +335,71 @@ def diffusivity_form(torch, rd, np, geom, img, w, n_active, steps, graph_steps, 
     return res
 
 
+def frap_form(torch, rd, np, W, n, stream):
+    """Simulated FRAP on a porous volume (pore phase of overlapping balls, porosity 0.5)
+    and on a free-space box of the same size: bleached central box of edge n/4, D = 1,
+    dt = 0.1; D_eff from the least-squares fit, tau_d = 1 / D_eff, and the steady-state
+    tortuosity of the same volume along x beside it."""
+    img, _ = W.boolean_spheres(n, 0.5, 4.0, 8.0, seed=7)
+    q = n // 8
+    reg = (n // 2 - q, n // 2 + q) * 3
+    x0, x1, y0, y1, z0, z1 = reg
+    dt = 0.1
+    runs = {}
+    t0 = time.perf_counter()
+    for name, im, sps, ns in (("porous", img, 50, 60), ("free", np.ones_like(img), 10, 300)):
+        c0 = (im != 0).astype(np.float32)
+        c0[z0:z1, y0:y1, x0:x1] = 0.0
+        cinf = float(c0.sum()) / float((im != 0).sum())
+        m_inf = cinf * float((im[z0:z1, y0:y1, x0:x1] != 0).sum())
+        with torch.cuda.stream(stream):
+            geom = rd.Geometry(im, None, 1.0, 8)
+            sim = rd.Sim(geom, "fp32")
+            sim.add_species(1.0)
+            sim.bind(stream=stream)
+            sim.set_field(0, torch.from_numpy(c0).to("cuda"))
+            ts = time.perf_counter()
+            curve = sim.frap_curve(0, reg, dt, sps, ns)
+            secs = time.perf_counter() - ts
+        runs[name] = {"curve": curve / m_inf, "seconds": secs, "steps": sps * ns,
+                      "samples": ns + 1, "n_active": geom.stats()["n_active"], "dt_sample": sps * dt}
+        del sim, geom
+    por, free = runs["porous"], runs["free"]
+    t = np.arange(por["samples"]) * por["dt_sample"]
+    d_eff, rms = rd.frap_fit(t, por["curve"], free["dt_sample"], free["curve"], 1.0)
+    wall = time.perf_counter() - t0
+    with torch.cuda.stream(stream):
+        geom = rd.Geometry(img, None, 1.0, 8)
+        sim = rd.Sim(geom, "fp32")
+        sim.add_species(1.0)
+        sim.bind(features=rd.RD_WS_SOLVER, stream=stream)
+        ts = time.perf_counter()
+        ss = sim.steady_state(0, 1e-8, 100000)
+        tau_ss, iters = ss["tau"], ss["iters"]
+        t_ss = time.perf_counter() - ts
+        del sim, geom
+    res = {
+        "volume": f"{n}^3 pore phase of overlapping balls (radii 4-8, porosity 0.5), bleached "
+                  f"box {2 * q}^3 at the centre, D = 1, dt = 0.1",
+        "porosity": float((img != 0).mean()),
+        "D_eff": d_eff,
+        "tau_frap": 1.0 / d_eff,
+        "fit_rms": rms,
+        "tau_steady_x": tau_ss,
+        "steady_iterations": iters,
+        "steady_seconds": t_ss,
+        "frap_wall_seconds": wall,
+        "porous_steps": por["steps"],
+        "porous_seconds": por["seconds"],
+        "porous_updates_per_s": por["n_active"] * por["steps"] / por["seconds"],
+        "free_steps": free["steps"],
+        "free_seconds": free["seconds"],
+    }
+    log(f"frap: D_eff {d_eff:.4f} tau {1 / d_eff:.4f} (steady tau_x {tau_ss:.4f}); porous "
+        f"{por['steps']} steps + {por['samples']} samples in {por['seconds']:.2f}s")
+    return res
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -483,6 +550,9 @@ def main():
         out["forms"]["diffusivity"] = diffusivity_form(torch, rd, np, geom, img, w, n_active,
                                                        a.diffusivity_steps, a.graph_steps,
                                                        not a.no_graph, stream)
+
+    if a.frap_size > 0 and not a.profile:
+        out["forms"]["frap"] = frap_form(torch, rd, np, W, a.frap_size, stream)
 
     if a.adjoint and not a.profile:
         out["forms"]["adjoint"] = adjoint_form(torch, rd, W, stream)

@@ -183,6 +183,30 @@ rd_status rd_sim_set_diffusivity_sdf(rd_sim *sim, const float *dev_sdf, double d
                                      double gamma1, double gamma2);
 /* Back to the homogeneous D_s. */
 rd_status rd_sim_clear_diffusivity(rd_sim *sim);
+/* Simulated FRAP (section "Calculation of effective diffusion coefficient and
+ * tortuosity"): the mass of a species inside a box of voxels while the field recovers
+ * from a bleached initial state (set with rd_sim_set_field).
+ * region = {x0, x1, y0, y1, z0, z1}, half-open voxel index ranges with
+ * 0 <= lo < hi <= n on each axis (RD_ERR_ARG otherwise).
+ * rd_sim_region_mass: FP64 sum of c dx^3 over the active voxels of the region for the
+ * current field (synchronises).  RD_ERR_NONFINITE for a NaN or infinity in the region.
+ * rd_sim_frap_curve: curve[k] (host, n_samples + 1 doubles, caller-owned) = the
+ * region mass after k * steps_per_sample steps of size dt, k = 0..n_samples (the steps
+ * are taken; RD_ERR_UNSTABLE_DT as rd_sim_step). */
+rd_status rd_sim_region_mass(rd_sim *sim, int species, const int64_t region[6], double *mass);
+rd_status rd_sim_frap_curve(rd_sim *sim, int species, const int64_t region[6], double dt,
+                            int64_t steps_per_sample, int64_t n_samples, double *curve);
+/* Least-squares effective diffusion coefficient (host only, no GPU): the free-space
+ * recovery g was computed with coefficient D_ref at times s_j = j ds (j = 0..m-1); since
+ * the diffusion equation depends on D t only, the recovery for coefficient D is
+ * g(t D / D_ref), linearly interpolated.  D_eff minimises
+ * sum_i (f_i - g(t_i D / D_ref))^2 over D in [1e-4, 1] * D_ref (m-1) ds / max t (a
+ * 400-point log scan, then golden-section search); rms = sqrt(minimum / n), may be NULL.
+ * Inputs are host arrays: t, f of n samples (t >= 0, one t > 0), g of m.  The
+ * tortuosity of eq. tortuosity is tau_d = D / D_eff.  RD_ERR_ARG for n or m < 2, ds or
+ * D_ref <= 0, non-finite values. */
+rd_status rd_frap_fit(int64_t n, const double *t, const double *f, int64_t m, double ds,
+                      const double *g, double D_ref, double *D_eff, double *rms);
 /* Gather species s into a dense device float32 (nz,ny,nx); inactive voxels -> 0. */
 rd_status rd_sim_get_field(const rd_sim *sim, int species, float *dev_dense);
 /* Advance n_steps FTCS steps of size dt (asynchronous).  RD_ERR_UNSTABLE_DT if

@@ -20,8 +20,8 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-HIP_SOURCES = ["k_step.hip", "k_solve.hip", "k_adjoint.hip", "k_diff.hip"]
-CPP_SOURCES = ["geometry.cpp", "rd_api.cpp", "rd_solve.cpp"]
+HIP_SOURCES = ["k_step.hip", "k_solve.hip", "k_adjoint.hip", "k_diff.hip", "k_frap.hip"]
+CPP_SOURCES = ["geometry.cpp", "rd_api.cpp", "rd_solve.cpp", "frap.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-ffp-contract=off", "-Xclang", "-target-feature",

@@ -65,6 +65,9 @@ _SIGS = {
     "rd_sim_set_diffusivity": ([P, P], ci),
     "rd_sim_set_diffusivity_sdf": ([P, P, f64, f64, f64, f64], ci),
     "rd_sim_clear_diffusivity": ([P], ci),
+    "rd_sim_region_mass": ([P, ci, P, P], ci),
+    "rd_sim_frap_curve": ([P, ci, P, f64, i64, i64, P], ci),
+    "rd_frap_fit": ([i64, P, P, i64, f64, P, f64, P, P], ci),
     "rd_sim_get_field": ([P, ci, P], ci),
     "rd_sim_step": ([P, f64, i64], ci),
     "rd_sim_steps_taken": ([P, P], ci),
@@ -335,6 +338,23 @@ class Sim:
                "rd_sim_set_diffusivity_sdf")
         return self
 
+    def region_mass(self, species, region):
+        """FP64 mass of `species` over the active voxels of region (x0, x1, y0, y1, z0, z1)."""
+        reg = np.ascontiguousarray(region, dtype=np.int64)
+        m = f64()
+        _check(_lib.rd_sim_region_mass(self.handle, int(species), _np_ptr(reg), ctypes.byref(m)),
+               "rd_sim_region_mass")
+        return m.value
+
+    def frap_curve(self, species, region, dt, steps_per_sample, n_samples):
+        """Region mass at k * steps_per_sample steps, k = 0..n_samples (steps are taken)."""
+        reg = np.ascontiguousarray(region, dtype=np.int64)
+        out = np.zeros(int(n_samples) + 1)
+        _check(_lib.rd_sim_frap_curve(self.handle, int(species), _np_ptr(reg), float(dt),
+                                      int(steps_per_sample), int(n_samples), _np_ptr(out)),
+               "rd_sim_frap_curve")
+        return out
+
     def clear_diffusivity(self):
         _check(_lib.rd_sim_clear_diffusivity(self.handle), "rd_sim_clear_diffusivity")
         return self
@@ -515,3 +535,15 @@ class DiffusionDecay(torch.autograd.Function):
         dev = g.device
         return (torch.tensor(gD, dtype=torch.float64, device=dev),
                 torch.tensor(gk, dtype=torch.float64, device=dev), None, None, None, None, None)
+
+
+def frap_fit(t, f, ds, g, D_ref):
+    """(D_eff, rms): the free-space coefficient whose recovery g(t D / D_ref) (g sampled
+    at j * ds for D_ref) best fits f(t) in least squares (host computation)."""
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    d, r = f64(), f64()
+    _check(_lib.rd_frap_fit(len(t), _np_ptr(t), _np_ptr(f), len(g), float(ds), _np_ptr(g),
+                            float(D_ref), ctypes.byref(d), ctypes.byref(r)), "rd_frap_fit")
+    return d.value, r.value
