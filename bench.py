@@ -296,20 +296,25 @@ DIFF_PARS = (0.1, 0.9, -6.0, 4.0)
 
 def diffusivity_form(torch, rd, np, geom, img, w, n_active, steps, graph_steps, use_graph, stream):
     """FP32 steps of the soil volume with the smooth D(phi) factor (inhomogeneous step
-    kernel).  Algorithmic bytes per launch: read + write of every species plus the
-    4-byte factor, per active voxel."""
-    from scipy import ndimage
-
-    t0 = time.perf_counter()
-    phi = (ndimage.distance_transform_edt(img.astype(bool)) - 0.5).astype(np.float32)
-    log(f"diffusivity: distance to the wall in {time.perf_counter() - t0:.1f}s")
+    kernel), phi from the library's GPU distance transform.  Algorithmic bytes per
+    launch: read + write of every species plus the 4-byte factor, per active voxel."""
     S = len(w.species_D)
     with torch.cuda.stream(stream):
+        dimg = torch.from_numpy(img).to("cuda")
+        rd.sdf_from_image(dimg, 1.0, stream)  # warm-up (first launches)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        phi = rd.sdf_from_image(dimg, 1.0, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sdf_ms = e0.elapsed_time(e1)
+        log(f"diffusivity: signed distance of the {img.shape[0]}^3 image on the GPU in {sdf_ms:.1f} ms")
         sim = build_sim(rd, geom, w, "fp32", graph_steps, use_graph)
         sim.set_kernel("column")
         sim.bind(features=rd.RD_WS_DIFFUSIVITY, stream=stream)
-        sim.set_diffusivity_sdf(torch.from_numpy(phi).to("cuda"), *DIFF_PARS)
-        del phi
+        sim.set_diffusivity_sdf(phi, *DIFF_PARS)
+        del phi, dimg
         secs, wall = time_steps(torch, sim, stream, w.dt, 50, steps)
         bal = [sim.balance(sp) for sp in range(S)]
         torch.cuda.synchronize()
@@ -319,6 +324,7 @@ def diffusivity_form(torch, rd, np, geom, img, w, n_active, steps, graph_steps, 
         "kernel": f"k_step8e<float,{S}>",
         "diffusivity": "e = %g + %g / (1 + exp(-(%g + %g phi))), phi = distance to the wall - 1/2"
                        % DIFF_PARS,
+        "sdf_ms": sdf_ms,
         "steps": steps,
         "seconds": secs,
         "wall_seconds": wall,

@@ -105,6 +105,26 @@ rd_status rd_geometry_export_masks(const rd_geometry *g, uint64_t *masks);
 rd_status rd_geometry_export_codes(const rd_geometry *g, uint8_t *codes);
 void rd_geometry_destroy(rd_geometry *g);
 
+/* ---- signed distance on the GPU --------------------------------------------- */
+
+/* Signed distance of a voxel image (section "Level-set method for image-based geometry
+ * reconstruction", eq. SDF; a GPU-built SDF is the future work of section "Discussion
+ * and conclusions"), by an exact Euclidean distance transform:
+ *   active voxel   (image != 0):  phi = (distance to the nearest inactive voxel centre - 1/2) dx
+ *   inactive voxel:               phi = -(distance to the nearest active voxel centre - 1/2) dx
+ * and +-(box diagonal) dx when the other phase is empty.  The sign matches the image,
+ * so the result passes rd_geometry_create's consistency check, and it feeds
+ * rd_sim_set_diffusivity_sdf directly.
+ *   dev_image   device uint8 (nz,ny,nx), x fastest
+ *   dev_sdf     device float32 (nz,ny,nx), written (caller-owned)
+ *   dev_scratch device scratch of rd_sdf_scratch_bytes (20 bytes per voxel, caller-owned)
+ * Asynchronous on `stream` (a hipStream_t, NULL = the null stream).  RD_ERR_ARG for
+ * NULL pointers or dx <= 0; RD_ERR_SHAPE unless 1 <= n <= 32768 on every axis;
+ * RD_ERR_WORKSPACE if the scratch is too small. */
+rd_status rd_sdf_scratch_bytes(int64_t nx, int64_t ny, int64_t nz, size_t *bytes);
+rd_status rd_sdf_from_image(const uint8_t *dev_image, int64_t nx, int64_t ny, int64_t nz, double dx,
+                            float *dev_sdf, void *dev_scratch, size_t scratch_bytes, void *stream);
+
 /* ---- simulation ------------------------------------------------------------ */
 
 /* A simulation on geometry g (g must outlive the simulation).  storage selects the

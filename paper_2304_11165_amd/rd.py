@@ -66,6 +66,8 @@ _SIGS = {
     "rd_sim_set_diffusivity_sdf": ([P, P, f64, f64, f64, f64], ci),
     "rd_sim_clear_diffusivity": ([P], ci),
     "rd_sim_region_mass": ([P, ci, P, P], ci),
+    "rd_sdf_scratch_bytes": ([i64, i64, i64, P], ci),
+    "rd_sdf_from_image": ([P, i64, i64, i64, f64, P, P, ctypes.c_size_t, P], ci),
     "rd_sim_frap_curve": ([P, ci, P, f64, i64, i64, P], ci),
     "rd_frap_fit": ([i64, P, P, i64, f64, P, f64, P, P], ci),
     "rd_sim_get_field": ([P, ci, P], ci),
@@ -547,3 +549,26 @@ def frap_fit(t, f, ds, g, D_ref):
     _check(_lib.rd_frap_fit(len(t), _np_ptr(t), _np_ptr(f), len(g), float(ds), _np_ptr(g),
                             float(D_ref), ctypes.byref(d), ctypes.byref(r)), "rd_frap_fit")
     return d.value, r.value
+
+
+def sdf_from_image(image, dx=1.0, stream=None):
+    """Signed distance (float32 (nz, ny, nx) tensor on the image's GPU) of a uint8 voxel
+    image by the library's exact distance transform: (distance to the other phase - 1/2)
+    dx, positive on active voxels."""
+    import torch
+
+    img = torch.as_tensor(image, dtype=torch.uint8)
+    if not img.is_cuda:
+        img = img.to("cuda")
+    img = img.contiguous()
+    nz, ny, nx = img.shape
+    n = ctypes.c_size_t()
+    _check(_lib.rd_sdf_scratch_bytes(nx, ny, nz, ctypes.byref(n)), "rd_sdf_scratch_bytes")
+    scratch = torch.empty(max(n.value, 256), dtype=torch.uint8, device=img.device)
+    out = torch.empty((nz, ny, nx), dtype=torch.float32, device=img.device)
+    st = stream if stream is not None else torch.cuda.current_stream(img.device)
+    _check(_lib.rd_sdf_from_image(ctypes.c_void_p(img.data_ptr()), nx, ny, nz, float(dx),
+                                  ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(scratch.data_ptr()),
+                                  scratch.numel(), _stream_handle(st)), "rd_sdf_from_image")
+    out._rd_keep = (img, scratch)  # held until the caller drops the result
+    return out
