@@ -53,12 +53,12 @@ def _load():
     lib.orc_ftcs_run.restype = ci
     lib.orc_balance.argtypes = [i64, i64, i64, f64, P, ci, P, P, P, ci, P, P, P, P, ci, P, P, P, P]
     lib.orc_balance.restype = ci
-    lib.orc_ftcs_run_eps.argtypes = [i64, i64, i64, f64, P, ci, P, P, P, ci, P, P, P, P, P, f64,
-                                     i64, P, P]
-    lib.orc_ftcs_run_eps.restype = ci
-    lib.orc_balance_eps.argtypes = [i64, i64, i64, f64, P, ci, P, P, P, ci, P, P, P, P, P, ci, P,
-                                    P, P, P]
-    lib.orc_balance_eps.restype = ci
+    lib.orc_ftcs_run_ext.argtypes = [i64, i64, i64, f64, P, ci, P, P, P, ci, P, P, P, P, P, P, P,
+                                     f64, i64, P, P]
+    lib.orc_ftcs_run_ext.restype = ci
+    lib.orc_balance_ext.argtypes = [i64, i64, i64, f64, P, ci, P, P, P, ci, P, P, P, P, P, P, P, ci,
+                                    P, P, P, P]
+    lib.orc_balance_ext.restype = ci
     lib.orc_smooth_diffusivity.argtypes = [i64, P, f64, f64, f64, f64, P]
     lib.orc_smooth_diffusivity.restype = None
     lib.orc_plane_flux.argtypes = [i64, i64, i64, f64, P, f64, P, ci, i64]
@@ -94,8 +94,18 @@ class Problem:
     reactions [(from, to, rate)], to = -1 for decay
     """
 
-    def __init__(self, image, D, dx=1.0, robin=None, dirichlet=None, reactions=None, eps=None):
+    def __init__(self, image, D, dx=1.0, robin=None, dirichlet=None, reactions=None, eps=None,
+                 sink=None, sink_mask=None):
         self.image = np.ascontiguousarray(image, dtype=np.uint8)
+        # volumetric sink: rate sink[s] on the voxels where sink_mask is set
+        self.sink_k = None
+        self.sink_mask = None
+        if sink:
+            self.sink_k = np.zeros(len(np.atleast_1d(D)))
+            for s, k in sink.items():
+                self.sink_k[s] = k
+            self.sink_mask = np.ascontiguousarray(np.asarray(sink_mask).reshape(self.image.shape),
+                                                  dtype=np.uint8)
         # per-voxel diffusivity factor: D of species s at voxel p is D[s] * eps[p]
         self.eps = None if eps is None else np.ascontiguousarray(
             np.asarray(eps, dtype=np.float64).reshape(self.image.shape))
@@ -160,10 +170,11 @@ class Problem:
         src = None
         if source is not None:
             src = np.ascontiguousarray(np.asarray(source, dtype=np.float64).reshape(c.shape))
-        rc = lib.orc_ftcs_run_eps(self.nx, self.ny, self.nz, self.dx, _ptr(self.image), self.S,
+        rc = lib.orc_ftcs_run_ext(self.nx, self.ny, self.nz, self.dx, _ptr(self.image), self.S,
                                   _ptr(self.D), _ptr(self.robin), _ptr(self.dir_face),
                                   len(self.r_rate), _ptr(self.r_from), _ptr(self.r_to),
-                                  _ptr(self.r_rate), _ptr(src), _ptr(self.eps), float(dt),
+                                  _ptr(self.r_rate), _ptr(src), _ptr(self.eps),
+                                  _ptr(self.sink_k), _ptr(self.sink_mask), float(dt),
                                   int(nsteps), _ptr(c), None)
         if rc != 0:
             raise MemoryError("oracle: allocation failed")
@@ -176,10 +187,11 @@ class Problem:
             self.S, self.nz, self.ny, self.nx))
         mass, robin, react = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         inflow = np.zeros(6)
-        lib.orc_balance_eps(self.nx, self.ny, self.nz, self.dx, _ptr(self.image), self.S,
+        lib.orc_balance_ext(self.nx, self.ny, self.nz, self.dx, _ptr(self.image), self.S,
                             _ptr(self.D), _ptr(self.robin), _ptr(self.dir_face), len(self.r_rate),
                             _ptr(self.r_from), _ptr(self.r_to), _ptr(self.r_rate), _ptr(self.eps),
-                            _ptr(c), int(s), ctypes.byref(mass), _ptr(inflow), ctypes.byref(robin),
+                            _ptr(self.sink_k), _ptr(self.sink_mask), _ptr(c), int(s),
+                            ctypes.byref(mass), _ptr(inflow), ctypes.byref(robin),
                             ctypes.byref(react))
         return mass.value, inflow, robin.value, react.value
 

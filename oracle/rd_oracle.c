@@ -25,6 +25,8 @@
  *  - reactions evaluated at the old time level (law of mass action, first order);
  *  - a reactive wall (Robin) with flux k_R * u per wall face, the per-face form of
  *    the paper's surface-restricted sink (section "Application example 2");
+ *  - or that sink in volumetric form: rate k_s * u on the voxels of a near-surface
+ *    band selected by the level set (the same section);
  *  - a Dirichlet face: the active voxels of a box face plane hold a fixed value
  *    (section "Application example 1": a solute enters from one face).
  *
@@ -104,12 +106,14 @@ static int wall_count(const uint8_t *active, int64_t i, int64_t j, int64_t k,
  *  source      optional volumetric source nspec*N (added as dt*source), may be NULL
  *  eps         optional per-voxel diffusivity factor (N values): D at voxel p is
  *              D[s] * eps[p]; NULL means eps = 1
+ *  sink_k      optional volumetric sink rate per species, applied (as -dt*k_s*u) on the
+ *  sink_mask   voxels with sink_mask[p] != 0; either NULL: no sink
  */
 static void ftcs_step(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8_t *active,
                       int nspec, const double *D, const double *robin_k, const uint8_t *dir_face,
                       int nreact, const int32_t *r_from, const int32_t *r_to, const double *r_rate,
-                      const double *source, const double *eps, double dt, const double *cin,
-                      double *cout)
+                      const double *source, const double *eps, const double *sink_k,
+                      const uint8_t *sink_mask, double dt, const double *cin, double *cout)
 {
     const int64_t N = nx * ny * nz;
     for (int s = 0; s < nspec; ++s) {
@@ -151,6 +155,8 @@ static void ftcs_step(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8
                     double un = uc + dt * (1.0 / (dx * dx)) * flux;
                     /* reactive wall: flux k_R*u through each wall face of area dx^2 */
                     un -= dt * kR * (double)nwall * uc / dx;
+                    /* volumetric near-surface sink */
+                    if (sink_k && sink_mask && sink_mask[p]) un -= dt * sink_k[s] * uc;
                     /* first-order reactions at the old time level */
                     for (int r = 0; r < nreact; ++r) {
                         double rate = r_rate[r] * cin[(int64_t)r_from[r] * N + p];
@@ -167,11 +173,11 @@ static void ftcs_step(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8
 
 /* Run nsteps FTCS steps in place on c (nspec*N).  work: nspec*N scratch (may be NULL).
  * eps: per-voxel diffusivity factor (N values) or NULL. */
-int orc_ftcs_run_eps(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8_t *active,
+int orc_ftcs_run_ext(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8_t *active,
                      int nspec, const double *D, const double *robin_k, const uint8_t *dir_face,
                      int nreact, const int32_t *r_from, const int32_t *r_to, const double *r_rate,
-                     const double *source, const double *eps, double dt, int64_t nsteps,
-                     double *c, double *work)
+                     const double *source, const double *eps, const double *sink_k,
+                     const uint8_t *sink_mask, double dt, int64_t nsteps, double *c, double *work)
 {
     const int64_t N = nx * ny * nz;
     double *tmp = work;
@@ -184,7 +190,7 @@ int orc_ftcs_run_eps(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8_
     double *a = c, *b = tmp;
     for (int64_t n = 0; n < nsteps; ++n) {
         ftcs_step(nx, ny, nz, dx, active, nspec, D, robin_k, dir_face, nreact, r_from, r_to,
-                  r_rate, source, eps, dt, a, b);
+                  r_rate, source, eps, sink_k, sink_mask, dt, a, b);
         double *t = a; a = b; b = t;
     }
     if (a != c) memcpy(c, a, sizeof(double) * (size_t)(N * nspec));
@@ -197,8 +203,8 @@ int orc_ftcs_run(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8_t *a
                  int nreact, const int32_t *r_from, const int32_t *r_to, const double *r_rate,
                  const double *source, double dt, int64_t nsteps, double *c, double *work)
 {
-    return orc_ftcs_run_eps(nx, ny, nz, dx, active, nspec, D, robin_k, dir_face, nreact, r_from,
-                            r_to, r_rate, source, NULL, dt, nsteps, c, work);
+    return orc_ftcs_run_ext(nx, ny, nz, dx, active, nspec, D, robin_k, dir_face, nreact, r_from,
+                            r_to, r_rate, source, NULL, NULL, NULL, dt, nsteps, c, work);
 }
 
 /* Smooth diffusivity of eq. inhomog_diffusion_coefficient (section "Level-set method
@@ -215,16 +221,18 @@ void orc_smooth_diffusivity(int64_t n, const double *phi, double d_min, double d
  *   mass          sum over free voxels of c * dx^3       (paper: total-mass monitor)
  *   inflow[6]     per Dirichlet face f: sum over (q Dirichlet on f, p free active
  *                 neighbour of q) of D_h*(c_q - c_p)*dx, D_h the mean of D at q and p
- *   robin         sum over free voxels of k_R * n_wall * c * dx^2
+ *   robin         sum over free voxels of k_R * n_wall * c * dx^2 (+ k_s * c * dx^3 on the
+ *                 sink band)
  *   react         sum over free voxels of the reaction rate of s, times dx^3
  * A voxel is "free" for s if it is active and not a Dirichlet voxel of s.  With
  * these terms one FTCS step satisfies M' - M = dt*(sum(inflow) - robin + react).
  */
-int orc_balance_eps(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8_t *active,
+int orc_balance_ext(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8_t *active,
                     int nspec, const double *D, const double *robin_k, const uint8_t *dir_face,
                     int nreact, const int32_t *r_from, const int32_t *r_to, const double *r_rate,
-                    const double *eps, const double *c, int s, double *mass, double *inflow,
-                    double *robin, double *react)
+                    const double *eps, const double *sink_k, const uint8_t *sink_mask,
+                    const double *c, int s, double *mass, double *inflow, double *robin,
+                    double *react)
 {
     const int64_t N = nx * ny * nz;
     const double *u = c + (int64_t)s * N;
@@ -254,6 +262,7 @@ int orc_balance_eps(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8_t
                 }
                 m += u[p] * dx * dx * dx;
                 rb += kR * (double)wall_count(active, i, j, k, nx, ny, nz) * u[p] * dx * dx;
+                if (sink_k && sink_mask && sink_mask[p]) rb += sink_k[s] * u[p] * dx * dx * dx;
                 for (int r = 0; r < nreact; ++r) {
                     double rate = r_rate[r] * c[(int64_t)r_from[r] * N + p];
                     if (r_from[r] == s) re -= rate * dx * dx * dx;
@@ -272,8 +281,8 @@ int orc_balance(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8_t *ac
                 int nreact, const int32_t *r_from, const int32_t *r_to, const double *r_rate,
                 const double *c, int s, double *mass, double *inflow, double *robin, double *react)
 {
-    return orc_balance_eps(nx, ny, nz, dx, active, nspec, D, robin_k, dir_face, nreact, r_from,
-                           r_to, r_rate, NULL, c, s, mass, inflow, robin, react);
+    return orc_balance_ext(nx, ny, nz, dx, active, nspec, D, robin_k, dir_face, nreact, r_from,
+                           r_to, r_rate, NULL, NULL, NULL, c, s, mass, inflow, robin, react);
 }
 
 /* Diffusive flux of one species through the plane between index i and i+1 along
@@ -482,7 +491,7 @@ int orc_adjoint_decay(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8
     memcpy(cur, c0, sizeof(double) * (size_t)N);
     memcpy(cps, cur, sizeof(double) * (size_t)N);
     for (int64_t n = 0; n < nsteps; ++n) {
-        ftcs_step(nx, ny, nz, dx, active, 1, &D, NULL, dir_face, 1, &rf, &rt, &k, NULL, NULL, dt, cur, tmp);
+        ftcs_step(nx, ny, nz, dx, active, 1, &D, NULL, dir_face, 1, &rf, &rt, &k, NULL, NULL, NULL, NULL, dt, cur, tmp);
         memcpy(cur, tmp, sizeof(double) * (size_t)N);
         if ((n + 1) % stride == 0)
             memcpy(cps + ((n + 1) / stride) * N, cur, sizeof(double) * (size_t)N);
@@ -503,7 +512,7 @@ int orc_adjoint_decay(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8
         int64_t len = s1 - s0;
         memcpy(seg, cps + (s0 / stride) * N, sizeof(double) * (size_t)N);
         for (int64_t m = 0; m < len - 1; ++m)
-            ftcs_step(nx, ny, nz, dx, active, 1, &D, NULL, dir_face, 1, &rf, &rt, &k, NULL, NULL, dt,
+            ftcs_step(nx, ny, nz, dx, active, 1, &D, NULL, dir_face, 1, &rf, &rt, &k, NULL, NULL, NULL, NULL, dt,
                       seg + m * N, seg + (m + 1) * N);
         for (int64_t m = len - 1; m >= 0; --m) {
             const double *c = seg + m * N; /* c^{s0+m}; lam holds lambda^{s0+m+1} */

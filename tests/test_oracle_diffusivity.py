@@ -134,3 +134,46 @@ def test_smooth_diffusivity(oracle_mod):
     s = got + oracle_mod.smooth_diffusivity(mirror, d_min, d_max, g1, g2)
     assert np.max(np.abs(s - (2 * d_min + d_max))) < 1e-13
     assert np.all(np.diff(oracle_mod.smooth_diffusivity(np.sort(phi), d_min, d_max, g1, g2)) >= 0)
+
+
+# ---------------------------------------------------------------------------
+# volumetric near-surface sink (section "Application example 2": a sink restricted to
+# the surface by the level set)
+# ---------------------------------------------------------------------------
+
+def test_sink_uniform_closed_form(oracle_mod):
+    img = np.ones((6, 7, 8), np.uint8)
+    prob = oracle_mod.Problem(img, [1.0], sink={0: 0.3}, sink_mask=np.ones(img.shape, np.uint8))
+    c = prob.run(np.full((1,) + img.shape, 2.0), 0.1, 25)
+    np.testing.assert_allclose(c, 2.0 * (1 - 0.03) ** 25, rtol=1e-14)
+
+
+def test_sink_only_on_the_band(oracle_mod):
+    rng = np.random.default_rng(21)
+    img, _ = _random_box(21)
+    mask = (rng.random(img.shape) < 0.3).astype(np.uint8)
+    prob = oracle_mod.Problem(img, [0.0, 0.0], sink={1: 0.2}, sink_mask=mask)
+    c0 = prob.apply_dirichlet(rng.random((2,) + img.shape))
+    c = prob.run(c0, 0.5, 7)
+    act = img != 0
+    np.testing.assert_array_equal(c[0], c0[0])
+    want = np.where(mask != 0, c0[1] * (1 - 0.1) ** 7, c0[1])
+    np.testing.assert_allclose(c[1][act], want[act], rtol=1e-14)
+
+
+def test_sink_in_the_step_balance(oracle_mod):
+    img, eps = _random_box(22)
+    rng = np.random.default_rng(22)
+    mask = (rng.random(img.shape) < 0.4).astype(np.uint8)
+    prob = oracle_mod.Problem(img, [0.7], dirichlet={(0, 0): 1.0}, robin={0: 0.03},
+                              reactions=[(0, -1, 0.02)], eps=eps, sink={0: 0.15}, sink_mask=mask)
+    c0 = prob.apply_dirichlet(rng.random((1,) + img.shape))
+    dt = 0.05
+    m0, inflow, uptake, react = prob.balance(c0, 0)
+    m1 = prob.balance(prob.run(c0, dt, 1), 0)[0]
+    assert abs((m1 - m0) - dt * (inflow.sum() - uptake + react)) < 1e-12
+    no_sink = oracle_mod.Problem(img, [0.7], dirichlet={(0, 0): 1.0}, robin={0: 0.03},
+                                 reactions=[(0, -1, 0.02)], eps=eps)
+    act = (img != 0) & (mask != 0)
+    act[:, :, 0] = False  # Dirichlet plane
+    assert uptake - no_sink.balance(c0, 0)[2] == pytest.approx(0.15 * c0[0][act].sum(), rel=1e-12)
