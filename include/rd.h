@@ -203,6 +203,21 @@ rd_status rd_sim_set_diffusivity_sdf(rd_sim *sim, const float *dev_sdf, double d
                                      double gamma1, double gamma2);
 /* Back to the homogeneous D_s. */
 rd_status rd_sim_clear_diffusivity(rd_sim *sim);
+/* Volumetric sink on a near-surface band (section "Application example 2": a sink
+ * restricted to the surface by the level set).  rd_sim_set_sink: rate k_s >= 0 of a
+ * species (default 0); on band voxels each step removes dt k_s c (old time level), and
+ * rd_sim_balance counts k_s c dx^3 there in the uptake term.  rd_sim_set_sink_band:
+ * the band is the set of active voxels with phi < band, phi a dense device float32
+ * (nz,ny,nx) (e.g. from rd_sdf_from_image, where the voxels next to the wall have
+ * phi = dx/2); *n_band (may be NULL) receives its size; band <= 0 empties it.
+ * Needs a bind with RD_WS_DIFFUSIVITY (the band runs through the inhomogeneous
+ * kernels, with e = 1 when no factor is set); a new bind empties the band.
+ * Synchronises.  The stability bound adds max k_s to the rates; rd_sim_steady_state
+ * and rd_sim_adjoint return RD_ERR_STATE while a band with a nonzero rate is set.
+ * Errors: RD_ERR_ARG for a bad species, a negative or non-finite rate or band, NULL
+ * phi; RD_ERR_WORKSPACE without the feature; RD_ERR_STATE before bind. */
+rd_status rd_sim_set_sink(rd_sim *sim, int species, double rate);
+rd_status rd_sim_set_sink_band(rd_sim *sim, const float *dev_phi, double band, int64_t *n_band);
 /* Simulated FRAP (section "Calculation of effective diffusion coefficient and
  * tortuosity"): the mass of a species inside a box of voxels while the field recovers
  * from a bleached initial state (set with rd_sim_set_field).

@@ -17,6 +17,7 @@
 //   * k_set_diff: fills e from a dense array (values or the smooth D(phi)).
 //   * k_reduce_diff: the balance terms, with the mean coefficient on Dirichlet faces.
 // Like the homogeneous step this is HBM-bound: the factor adds 4 bytes per slot read.
+// A volumetric sink on the near-surface band (code bit 7) rides along at no extra bytes.
 #include "rd_device.h"
 #include "rd_diff.h"
 
@@ -52,12 +53,12 @@ __device__ __forceinline__ void diff_store(const StepArgs &a, T *cout, int s, in
 // FTCS update of one free voxel with the factor:
 //   lap = sum over active neighbours q (in -x,+x,-y,+y,-z,+z order) of
 //         ((e_p + e_q) / 2) (c_q - c_p)
-//   c'  = c + alpha lap - (beta + gamma n_wall) c + sum_b K_b c_b
-// alpha = D_s dt / dx^2.  The difference form keeps the error proportional to the
-// local differences.
+//   c'  = c + alpha lap - (beta + gamma n_wall + sk) c + sum_b K_b c_b
+// alpha = D_s dt / dx^2, sk = dt k_s on band slots and 0 elsewhere.  The difference
+// form keeps the error proportional to the local differences.
 template <int S>
 __device__ __forceinline__ float rd_update_e(float uc, const float nbv[6], const float ev[6], float ec,
-                                             unsigned nbm, int nwall, const SpeciesCoef &k,
+                                             unsigned nbm, int nwall, const SpeciesCoef &k, float sk,
                                              const float *cen)
 {
     float lap = 0.0f;
@@ -67,7 +68,7 @@ __device__ __forceinline__ float rd_update_e(float uc, const float nbv[6], const
         lap = ((nbm >> d) & 1u) ? fmaf(w, nbv[d] - uc, lap) : lap;
     }
     float r = fmaf(k.alpha, lap, uc);
-    const float loss = fmaf(k.gamma, (float)nwall, k.beta);
+    const float loss = fmaf(k.gamma, (float)nwall, k.beta) + sk;
     r = fmaf(-loss, uc, r);
 #pragma unroll
     for (int b = 0; b < S; ++b) r = fmaf(k.K[b], cen[b], r);
@@ -131,7 +132,8 @@ __global__ __launch_bounds__(256) void k_step_diff(DiffArgs d)
         float nbv[6];
 #pragma unroll
         for (int dd = 0; dd < 6; ++dd) nbv[dd] = ((m >> dd) & 1u) ? rd_ld(cin, s * a.sstride + q[dd]) : 0.0f;
-        const float upd = rd_update_e<S>(cen[s], nbv, ev, ec, m, nwall, a.coef[s], cen);
+        const float sk = (code & RD_CODE_BAND) ? d.sink[s] : 0.0f;
+        const float upd = rd_update_e<S>(cen[s], nbv, ev, ec, m, nwall, a.coef[s], sk, cen);
         const bool isd = (onf & a.coef[s].dir) != 0u;
         diff_store(a, cout, s, s * a.sstride + i, h, isd ? cen[s] : upd);
     }
@@ -272,7 +274,8 @@ __global__ __launch_bounds__(256) void k_step8e(DiffArgs d)
             const float dn = z == 0 ? zlo[s] : c[s][z > 0 ? z - 1 : 0];
             const float up = z == 7 ? zhi[s] : c[s][z < 7 ? z + 1 : 7];
             const float nbv[6] = {p[-1], p[1], p[-10], p[10], dn, up};
-            const float upd = rd_update_e<S>(cen[s], nbv, ev, ec[z], m, nwall, a.coef[s], cen);
+            const float sk = (code & RD_CODE_BAND) ? d.sink[s] : 0.0f;
+            const float upd = rd_update_e<S>(cen[s], nbv, ev, ec[z], m, nwall, a.coef[s], sk, cen);
             const bool isd = (onf & a.coef[s].dir) != 0u;
             res[s] = act ? (isd ? cen[s] : upd) : 0.0f;
         }
@@ -309,8 +312,8 @@ __global__ __launch_bounds__(256) void k_set_diff(const BlockInfo *info, const u
             block_pos(info[b], &bx, &by, &bz, &gid);
             const GeomInfo g = geom[gid];
             const int gx = bx * B + slot % B, gy = by * B + (slot / B) % B, gz = bz * B + slot / (B * B);
-            const float x = dense[voxel_id(g, gx, gy, gz)];
-            v = mode == 0 ? x : (float)(d_min + d_max / (1.0 + exp(-(g1 + g2 * (double)x))));
+            const float x = mode == 2 ? 1.0f : dense[voxel_id(g, gx, gy, gz)];
+            v = mode != 1 ? x : (float)(d_min + d_max / (1.0 + exp(-(g1 + g2 * (double)x))));
             bad = !(v >= 0.0f) || !isfinite(v);
             if (!bad) mx = __float_as_uint(v);
         }
@@ -330,7 +333,7 @@ __global__ __launch_bounds__(256) void k_set_diff(const BlockInfo *info, const u
 // reduction: mass, inflow[6], uptake, reactions, non-finite count.  One row per
 // workgroup: the wave sums in wave order.
 template <typename T, int B>
-__global__ __launch_bounds__(256) void k_reduce_diff(ReduceArgs a, const float *e)
+__global__ __launch_bounds__(256) void k_reduce_diff(ReduceArgs a, const float *e, double ksink)
 {
     using C = Cfg<B>;
     constexpr int NS = B * B * B;
@@ -383,6 +386,7 @@ __global__ __launch_bounds__(256) void k_reduce_diff(ReduceArgs a, const float *
             }
             acc[0] += u * dx3;
             acc[7] += a.kR * (double)nwall * u * dx2;
+            if (code & RD_CODE_BAND) acc[7] += ksink * u * dx3;
             double re = -a.rate_out * u;
             for (int s2 = 0; s2 < a.S; ++s2)
                 if (a.rate_in[s2] != 0.0) re += a.rate_in[s2] * (double)rd_ld(c, s2 * a.sstride + i);
@@ -400,6 +404,30 @@ __global__ __launch_bounds__(256) void k_reduce_diff(ReduceArgs a, const float *
         const int l = threadIdx.x;
         a.partial[(int64_t)blockIdx.x * RD_NRED + l] = ((wsum[0][l] + wsum[1][l]) + wsum[2][l]) + wsum[3][l];
     }
+}
+
+// Band marking, one thread per slot.
+template <int B>
+__global__ __launch_bounds__(256) void k_set_band(const BlockInfo *info, uint8_t *code, const GeomInfo *geom,
+                                                  int nb, const float *phi, double band, uint32_t *count)
+{
+    constexpr int NS = B * B * B;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool in = false;
+    if (i < (int64_t)nb * NS) {
+        const unsigned c = code[i];
+        if (c & 64u) {
+            const int b = (int)(i / NS), slot = (int)(i % NS);
+            int bx, by, bz, gid;
+            block_pos(info[b], &bx, &by, &bz, &gid);
+            const GeomInfo g = geom[gid];
+            const int gx = bx * B + slot % B, gy = by * B + (slot / B) % B, gz = bz * B + slot / (B * B);
+            in = (double)phi[voxel_id(g, gx, gy, gz)] < band;
+            code[i] = (uint8_t)((c & 0x7fu) | (in ? RD_CODE_BAND : 0u));
+        }
+    }
+    const uint64_t m = __ballot(in);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(count, (uint32_t)__popcll(m));
 }
 
 template <typename T, int B, int S>
@@ -434,11 +462,11 @@ void launch_diff_b(int B, const DiffArgs &a, int column, hipStream_t st)
 }
 
 template <typename T>
-void launch_reduce_b(int B, const ReduceArgs &a, const float *e, hipStream_t st)
+void launch_reduce_b(int B, const ReduceArgs &a, const float *e, double ksink, hipStream_t st)
 {
     const dim3 grid((unsigned)rd_diff_reduce_rows(B, a.nb));
-    if (B == 8) hipLaunchKernelGGL((k_reduce_diff<T, 8>), grid, dim3(256), 0, st, a, e);
-    else hipLaunchKernelGGL((k_reduce_diff<T, 4>), grid, dim3(256), 0, st, a, e);
+    if (B == 8) hipLaunchKernelGGL((k_reduce_diff<T, 8>), grid, dim3(256), 0, st, a, e, ksink);
+    else hipLaunchKernelGGL((k_reduce_diff<T, 4>), grid, dim3(256), 0, st, a, e, ksink);
 }
 
 }  // namespace
@@ -473,12 +501,27 @@ int rd_launch_set_diff(int B, const BlockInfo *info, const uint8_t *code, const 
 
 int rd_diff_reduce_rows(int B, int nb) { return B == 8 ? nb : (nb + 3) / 4; }
 
-int rd_launch_reduce_diff(int storage, int B, const ReduceArgs &a, const float *e, void *stream)
+int rd_launch_reduce_diff(int storage, int B, const ReduceArgs &a, const float *e, double ksink, void *stream)
 {
     if (a.nb <= 0) return 0;
     hipStream_t st = (hipStream_t)stream;
-    if (storage == 0) launch_reduce_b<float>(B, a, e, st);
-    else if (storage == 1) launch_reduce_b<bf16_t>(B, a, e, st);
-    else launch_reduce_b<_Float16>(B, a, e, st);
+    if (storage == 0) launch_reduce_b<float>(B, a, e, ksink, st);
+    else if (storage == 1) launch_reduce_b<bf16_t>(B, a, e, ksink, st);
+    else launch_reduce_b<_Float16>(B, a, e, ksink, st);
+    return (int)hipGetLastError();
+}
+
+int rd_launch_set_band(int B, const BlockInfo *info, uint8_t *code, const GeomInfo *geom, int nb, const float *phi,
+                       double band, uint32_t *count, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    int rc = rd_launch_fill_u32(count, 0u, 1, stream);
+    if (rc != 0 || nb <= 0) return rc;
+    const int64_t n = (int64_t)nb * B * B * B;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (B == 8)
+        hipLaunchKernelGGL((k_set_band<8>), grid, dim3(256), 0, st, info, code, geom, nb, phi, band, count);
+    else
+        hipLaunchKernelGGL((k_set_band<4>), grid, dim3(256), 0, st, info, code, geom, nb, phi, band, count);
     return (int)hipGetLastError();
 }

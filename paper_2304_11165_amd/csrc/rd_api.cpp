@@ -262,6 +262,8 @@ extern "C" rd_status rd_sim_bind(rd_sim *sim, void *dev_workspace, size_t bytes,
     sim->L = L;
     sim->features = features;
     sim->diff_on = false;
+    sim->band_on = false;  // the upload restores the codes
+    sim->e_ones = false;
     sim->cp_slots = checkpoint_slots;
     sim->stream = (hipStream_t)stream;
     return sim->upload();
@@ -423,7 +425,7 @@ double rd_sim::lambda_max() const
     for (int s = 0; s < S; ++s) {
         dmax = std::max(dmax, D[s] * (diff_on ? e_max : 1.0));
         kmax = std::max(kmax, robin[s]);
-        double out_rate = 0.0;
+        double out_rate = band_on ? sink[s] : 0.0;
         for (const Reaction &r : reactions)
             if (r.from == s) out_rate += r.rate;
         rmax = std::max(rmax, out_rate);
@@ -466,13 +468,14 @@ rd_status rd_sim::launch_steps(double dt, int64_t n)
         a.seed = seed;
         a.ctr = step_counter();
         a.ctr_off = (uint32_t)i;
-        if (diff_on) {
+        if (diff_path()) {
             // B = 8: the column kernel unless the workgroup-per-block kernel is chosen
             // (then one thread per slot); B = 4: one thread per slot
             const int column = g->B == 8 && kernel != 0 ? 1 : 0;
             const int groups = (a.nb + 3) / 4;
             a.xcd_chunk = column && xcd_map && groups >= 64 ? (groups + 7) / 8 : 0;
-            DiffArgs da{a, (const float *)(ws + L.diff)};
+            DiffArgs da{a, (const float *)(ws + L.diff), {0.0f, 0.0f, 0.0f, 0.0f}};
+            for (int s = 0; s < S; ++s) da.sink[s] = band_on ? (float)(dt * sink[s]) : 0.0f;
             LAUNCHCHK(rd_launch_step_diff(storage, g->B, da, column, stream));
         } else {
             LAUNCHCHK(rd_launch_step(storage, g->B, a, stream));
@@ -575,9 +578,11 @@ rd_status rd_sim::balance(int s, double out[RD_NRED])
     }
     a.partial = (double *)(ws + L.part);
     // 0 rows for an empty geometry: sums are 0
-    const int nparts = diff_on ? rd_diff_reduce_rows(g->B, a.nb) : rd_reduce_rows(g->B, a.nb);
+    const int nparts = diff_path() ? rd_diff_reduce_rows(g->B, a.nb) : rd_reduce_rows(g->B, a.nb);
     double *res = (double *)(ws + L.res);
-    if (diff_on) LAUNCHCHK(rd_launch_reduce_diff(storage, g->B, a, (const float *)(ws + L.diff), stream));
+    if (diff_path())
+        LAUNCHCHK(rd_launch_reduce_diff(storage, g->B, a, (const float *)(ws + L.diff), band_on ? sink[s] : 0.0,
+                                        stream));
     else LAUNCHCHK(rd_launch_reduce(storage, g->B, a, stream));
     LAUNCHCHK(rd_launch_finish_reduce(a.partial, nparts, RD_NRED, (double *)(ws + L.mid), res, stream));
     HIPCHK(hipMemcpyAsync(host_res, res, sizeof(double) * RD_NRED, hipMemcpyDeviceToHost, stream));
@@ -618,7 +623,7 @@ static rd_status set_diffusivity(rd_sim *sim, const float *dev_dense, int mode, 
     if (!sim->ws) return rd_fail(RD_ERR_STATE, "bind a workspace first");
     if (!(sim->features & RD_WS_DIFFUSIVITY))
         return rd_fail(RD_ERR_WORKSPACE, "bind with RD_WS_DIFFUSIVITY for a diffusivity factor");
-    if (!dev_dense) return rd_fail(RD_ERR_ARG, "array pointer is NULL");
+    if (!dev_dense && mode != 2) return rd_fail(RD_ERR_ARG, "array pointer is NULL");
     if (mode == 1 && !(std::isfinite(d_min) && std::isfinite(d_max) && std::isfinite(g1) &&
                        std::isfinite(g2) && d_min >= 0.0 && d_max >= 0.0))
         return rd_fail(RD_ERR_ARG, "need finite d_min, d_max >= 0 and finite gamma1, gamma2");
@@ -633,8 +638,11 @@ static rd_status set_diffusivity(rd_sim *sim, const float *dev_dense, int mode, 
     uint32_t hs[2];
     memcpy(hs, sim->host_res, 8);
     sim->invalidate_graphs();
+    sim->e_ones = mode == 2;
+    if (mode == 2) return RD_OK;
     if (hs[0] != 0) {
         sim->diff_on = false;
+        if (sim->band_on) set_diffusivity(sim, dev_dense, 2, 0.0, 0.0, 0.0, 0.0);  // back to e = 1
         return rd_fail(RD_ERR_ARG, std::to_string(hs[0]) + " active voxels have a negative or non-finite "
                                    "diffusivity factor (the factor is cleared)");
     }
@@ -661,6 +669,52 @@ extern "C" rd_status rd_sim_clear_diffusivity(rd_sim *sim)
     if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
     if (sim->diff_on) sim->invalidate_graphs();
     sim->diff_on = false;
+    // the band's sink still runs through the factor kernels, with e = 1
+    if (sim->band_on && !sim->e_ones) return set_diffusivity(sim, nullptr, 2, 0.0, 0.0, 0.0, 0.0);
+    return RD_OK;
+}
+
+bool rd_sim::sink_active() const
+{
+    if (!band_on) return false;
+    for (int s = 0; s < S; ++s)
+        if (sink[s] != 0.0) return true;
+    return false;
+}
+
+extern "C" rd_status rd_sim_set_sink(rd_sim *sim, int species, double rate)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    if (species < 0 || species >= sim->S) return rd_fail(RD_ERR_ARG, "bad species");
+    if (!(rate >= 0.0) || !std::isfinite(rate)) return rd_fail(RD_ERR_ARG, "sink rate must be finite and >= 0");
+    sim->sink[species] = rate;
+    sim->invalidate_graphs();
+    return RD_OK;
+}
+
+extern "C" rd_status rd_sim_set_sink_band(rd_sim *sim, const float *dev_phi, double band, int64_t *n_band)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    if (!sim->ws) return rd_fail(RD_ERR_STATE, "bind a workspace first");
+    if (!(sim->features & RD_WS_DIFFUSIVITY))
+        return rd_fail(RD_ERR_WORKSPACE, "bind with RD_WS_DIFFUSIVITY for a sink band");
+    if (!dev_phi) return rd_fail(RD_ERR_ARG, "phi is NULL");
+    if (!std::isfinite(band)) return rd_fail(RD_ERR_ARG, "band must be finite");
+    char *ws = sim->ws;
+    const SimLayout &L = sim->L;
+    uint32_t *cnt = (uint32_t *)(ws + L.diff_stats);
+    LAUNCHCHK(rd_launch_set_band(sim->g->B, (const BlockInfo *)(ws + L.info), (uint8_t *)(ws + L.code),
+                                 (const GeomInfo *)(ws + L.geom), (int)sim->g->nb(), dev_phi, band, cnt,
+                                 sim->stream));
+    HIPCHK(hipMemcpyAsync(sim->host_res, cnt, 4, hipMemcpyDeviceToHost, sim->stream));
+    HIPCHK(hipStreamSynchronize(sim->stream));
+    uint32_t n;
+    memcpy(&n, sim->host_res, 4);
+    sim->invalidate_graphs();
+    sim->band_on = n > 0;
+    if (n_band) *n_band = (int64_t)n;
+    // without a factor the band's sink runs through the factor kernels with e = 1
+    if (sim->band_on && !sim->diff_on && !sim->e_ones) return set_diffusivity(sim, nullptr, 2, 0.0, 0.0, 0.0, 0.0);
     return RD_OK;
 }
 

@@ -5,6 +5,11 @@
 // inactive voxels carry no flux (mirror rule), as in the inhomogeneous-diffusion
 // functor of the paper's appendix "Code examples".  e is FP32, block-major like the
 // fields (nb * B^3 slots), 0 on inactive slots.
+//
+// The same kernels apply a volumetric sink on a near-surface band (paper: section
+// "Application example 2", a sink restricted to the surface by the level set): bit 7 of
+// a slot's code byte marks the band, and species s loses dt k_s c there each step.
+#define RD_CODE_BAND 0x80u
 #pragma once
 
 #include "rd_internal.h"
@@ -12,6 +17,7 @@
 struct DiffArgs {
     StepArgs s;       // the step's own arguments (coef[].alpha = D_s dt / dx^2)
     const float *e;   // diffusivity factor per slot
+    float sink[RD_MAX_SPECIES];  // dt * k_s, applied on band slots
 };
 
 // One step with the factor.  column = 1 (B = 8 only): one wave per block walking
@@ -19,7 +25,8 @@ struct DiffArgs {
 int rd_launch_step_diff(int storage, int B, const DiffArgs &a, int column, void *stream);
 
 // Fill e from a dense float32 (nz, ny, nx) device array: mode 0 copies the values,
-// mode 1 maps a signed distance phi to d_min + d_max / (1 + exp(-(g1 + g2 phi))).
+// mode 1 maps a signed distance phi to d_min + d_max / (1 + exp(-(g1 + g2 phi))),
+// mode 2 sets 1 on every active slot (dense is not read).
 // stats (two uint32 words, cleared here) receive the number of active slots whose
 // value is negative or not finite, and the bit pattern of the largest value.
 int rd_launch_set_diff(int B, const BlockInfo *info, const uint8_t *code, const GeomInfo *geom,
@@ -30,4 +37,11 @@ int rd_launch_set_diff(int B, const BlockInfo *info, const uint8_t *code, const 
 // Dirichlet inflow of a face uses the mean coefficient.  Writes rd_diff_reduce_rows
 // rows of RD_NRED partials.
 int rd_diff_reduce_rows(int B, int nb);
-int rd_launch_reduce_diff(int storage, int B, const ReduceArgs &a, const float *e, void *stream);
+// ksink: the reduced species' sink rate k_s (its band term goes to the uptake lane).
+int rd_launch_reduce_diff(int storage, int B, const ReduceArgs &a, const float *e, double ksink,
+                          void *stream);
+
+// Mark the band: bit 7 of the code byte of active slots set where phi < band, cleared
+// elsewhere; count (one uint32, cleared here) receives the number of band slots.
+int rd_launch_set_band(int B, const BlockInfo *info, uint8_t *code, const GeomInfo *geom, int nb,
+                       const float *phi, double band, uint32_t *count, void *stream);

@@ -72,6 +72,11 @@ struct rd_sim {
     uint32_t seed = 0;
     bool diff_on = false;  // a diffusivity factor is set (inhomogeneous diffusion)
     double e_max = 0.0;    // its largest value over the active voxels
+    double sink[RD_MAX_SPECIES] = {0, 0, 0, 0};  // volumetric sink rate on the band
+    bool band_on = false;  // band slots are marked (code bit 7)
+    bool e_ones = false;   // the factor buffer holds 1 on active slots (band without factor)
+    bool sink_active() const;
+    bool diff_path() const { return diff_on || sink_active(); }
 
     char *ws = nullptr;
     size_t ws_bytes = 0;

@@ -232,7 +232,8 @@ extern "C" rd_status rd_sim_steady_state(rd_sim *sim, int axis, double rel_tol, 
         return rd_fail(RD_ERR_WORKSPACE, "bind with RD_WS_SOLVER for the steady state");
     if (sim->S != 1 || !sim->reactions.empty() || sim->robin[0] != 0.0)
         return rd_fail(RD_ERR_STATE, "steady state needs one species without reactions or Robin");
-    if (sim->diff_on) return rd_fail(RD_ERR_STATE, "steady state needs a homogeneous D (clear the factor)");
+    if (sim->diff_path())
+        return rd_fail(RD_ERR_STATE, "steady state needs a homogeneous D and no sink band (clear them)");
     if (axis < 0 || axis > 2) return rd_fail(RD_ERR_ARG, "axis must be 0, 1 or 2");
     if (!(rel_tol >= 0.0) || max_iters < 0) return rd_fail(RD_ERR_ARG, "bad tolerance or max_iters");
     const rd_geometry &G = *sim->g;
@@ -548,7 +549,8 @@ extern "C" rd_status rd_sim_adjoint(rd_sim *sim, const float *dev_seed, int seed
     if (!(sim->features & RD_WS_ADJOINT))
         return rd_fail(RD_ERR_WORKSPACE, "bind with RD_WS_ADJOINT for the adjoint");
     if (sim->S != 1) return rd_fail(RD_ERR_STATE, "the adjoint needs a single species");
-    if (sim->diff_on) return rd_fail(RD_ERR_STATE, "the adjoint needs a homogeneous D (clear the factor)");
+    if (sim->diff_path())
+        return rd_fail(RD_ERR_STATE, "the adjoint needs a homogeneous D and no sink band (clear them)");
     for (const Reaction &r : sim->reactions)
         if (r.to != -1) return rd_fail(RD_ERR_STATE, "the adjoint supports decay reactions only");
     if (sim->sround && sim->storage != RD_FP32)

@@ -65,6 +65,8 @@ _SIGS = {
     "rd_sim_set_diffusivity": ([P, P], ci),
     "rd_sim_set_diffusivity_sdf": ([P, P, f64, f64, f64, f64], ci),
     "rd_sim_clear_diffusivity": ([P], ci),
+    "rd_sim_set_sink": ([P, ci, f64], ci),
+    "rd_sim_set_sink_band": ([P, P, f64, P], ci),
     "rd_sim_region_mass": ([P, ci, P, P], ci),
     "rd_sdf_scratch_bytes": ([i64, i64, i64, P], ci),
     "rd_sdf_from_image": ([P, i64, i64, i64, f64, P, P, ctypes.c_size_t, P], ci),
@@ -356,6 +358,23 @@ class Sim:
                                       int(steps_per_sample), int(n_samples), _np_ptr(out)),
                "rd_sim_frap_curve")
         return out
+
+    def set_sink(self, species, rate):
+        """Volumetric sink rate of a species on the near-surface band."""
+        _check(_lib.rd_sim_set_sink(self.handle, int(species), float(rate)), "rd_sim_set_sink")
+        return self
+
+    def set_sink_band(self, phi, band):
+        """Mark the active voxels with phi < band as the sink band; returns their number."""
+        import torch
+
+        nz, ny, nx = self.geometry.shape
+        t = torch.as_tensor(phi, dtype=torch.float32, device=self.workspace.device)
+        t = t.reshape(nz, ny, nx).contiguous()
+        n = i64()
+        _check(_lib.rd_sim_set_sink_band(self.handle, ctypes.c_void_p(t.data_ptr()), float(band),
+                                         ctypes.byref(n)), "rd_sim_set_sink_band")
+        return n.value
 
     def clear_diffusivity(self):
         _check(_lib.rd_sim_clear_diffusivity(self.handle), "rd_sim_clear_diffusivity")

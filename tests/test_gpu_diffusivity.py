@@ -205,3 +205,78 @@ def test_mass_conserved_closed_box(rd):
     s.step(0.05, 400)
     m1 = s.balance(0)["mass"]
     assert abs(m1 - m0) < 1e-5 * m0
+
+
+@pytest.mark.parametrize("B,kernel,with_factor", [(8, "column", True), (8, "column", False),
+                                                  (4, "block", True), (8, "block", False)])
+def test_sink_band_parity(rd, oracle_mod, B, kernel, with_factor):
+    """Volumetric sink on the voxels next to the wall (phi < 1 voxel), with and without
+    a diffusivity factor, against the oracle; balance terms on the same field."""
+    img, eps = _problem(seed=41)
+    phi = oracle_mod.signed_distance(img, 1.0)
+    band = (img != 0) & (phi < 1.0)
+    rng = np.random.default_rng(41)
+    init = rng.uniform(0, 1, (2,) + img.shape)
+    D = [1.0, 0.4]
+    sink = {0: 0.2, 1: 0.05}
+    dt = 0.04
+    _, s = make_gpu(rd, img, D, 1.0, CASE["robin"], CASE["dirichlet"], CASE["reactions"], "fp32", B,
+                    kernel=kernel, features=rd.RD_WS_DIFFUSIVITY)
+    for sp, k in sink.items():
+        s.set_sink(sp, k)
+    if with_factor:
+        s.set_diffusivity(eps.astype(np.float32))
+    assert s.set_sink_band(phi, 1.0) == int(band.sum())
+    prob = oracle_mod.Problem(img, D, robin=CASE["robin"], dirichlet=CASE["dirichlet"],
+                              reactions=CASE["reactions"],
+                              eps=eps.astype(np.float32).astype(np.float64) if with_factor else None,
+                              sink=sink, sink_mask=band.astype(np.uint8))
+    c0 = prob.apply_dirichlet(init)
+    for sp in range(2):
+        s.set_field(sp, c0[sp].astype(np.float32))
+    s.step(dt, 60)
+    got = fields(s, 2)
+    ref = prob.run(c0, dt, 60)
+    act = img != 0
+    for sp in range(2):
+        err = rel_l2(got[sp], ref[sp], act)
+        print(f"sink B={B} {kernel} factor={with_factor} species {sp}: rel L2 {err:.3e}")
+        assert err < TOL
+    for sp in range(2):
+        b = s.balance(sp)
+        m, infl, up, re = prob.balance(got, sp)
+        assert b["mass"] == pytest.approx(m, rel=1e-10, abs=1e-12)
+        np.testing.assert_allclose(b["inflow"], infl, rtol=1e-9, atol=1e-12)
+        assert b["uptake"] == pytest.approx(up, rel=1e-10, abs=1e-12)
+
+
+def test_sink_band_kernels_agree_and_clear(rd, oracle_mod):
+    img, _ = _problem(seed=43, shape=(26, 31, 35))
+    phi = oracle_mod.signed_distance(img, 1.0)
+    rng = np.random.default_rng(43)
+    c0 = rng.uniform(0, 1, img.shape).astype(np.float32) * (img != 0)
+    outs = []
+    for kernel in ("column", "block"):
+        _, s = make_gpu(rd, img, [1.0], kernel=kernel, features=rd.RD_WS_DIFFUSIVITY | rd.RD_WS_SOLVER)
+        s.set_sink(0, 0.3)
+        assert s.set_sink_band(phi, 1.6) > 0
+        s.set_field(0, c0)
+        s.step(0.05, 64)
+        outs.append(fields(s, 1))
+        with pytest.raises(rd.RDError) as ex:
+            s.steady_state(0, 1e-6, 100)
+        assert ex.value.name == "RD_ERR_STATE"
+    assert np.array_equal(outs[0], outs[1])
+    # an empty band gives back the constant-D step, bit for bit
+    _, s = make_gpu(rd, img, [1.0], kernel="column", features=rd.RD_WS_DIFFUSIVITY)
+    s.set_sink(0, 0.3)
+    s.set_sink_band(phi, 1.6)
+    assert s.set_sink_band(phi, 0.0) == 0
+    s.set_field(0, c0)
+    s.step(0.05, 64)
+    _, p = make_gpu(rd, img, [1.0], kernel="column")
+    p.set_field(0, c0)
+    p.step(0.05, 64)
+    assert np.array_equal(fields(s, 1), fields(p, 1))
+    with pytest.raises(rd.RDError):
+        s.set_sink(0, -1.0)
