@@ -426,3 +426,79 @@ def signed_distance(image, dx=1.0):
         d_out = ndimage.distance_transform_edt(~img) - 0.5 if img.any() else np.full(img.shape, diag)
         out[~img] = -d_out[~img] * dx
     return out.astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
+# discrete adjoint with a per-voxel diffusivity factor
+# ---------------------------------------------------------------------------
+
+def _neighbours(active):
+    """For each direction (-x,+x,-y,+y,-z,+z): (in-box-and-active mask, index shift)."""
+    nz, ny, nx = active.shape
+    out = []
+    for axis, sgn in ((2, -1), (2, 1), (1, -1), (1, 1), (0, -1), (0, 1)):
+        m = np.zeros(active.shape, dtype=bool)
+        src = [slice(None)] * 3
+        dst = [slice(None)] * 3
+        n = active.shape[axis]
+        if sgn < 0:
+            dst[axis], src[axis] = slice(1, n), slice(0, n - 1)
+        else:
+            dst[axis], src[axis] = slice(0, n - 1), slice(1, n)
+        m[tuple(dst)] = active[tuple(src)]
+        out.append((m & active, tuple(dst), tuple(src)))
+    return out
+
+
+def _shift(u, dst, src):
+    v = np.zeros_like(u)
+    v[dst] = u[src]
+    return v
+
+
+def adjoint_factor(image, D, k, eps, dt, nsteps, c0, target, dir_faces=(0,), dx=1.0):
+    """Discrete adjoint of single-species FTCS with a diffusivity factor e and decay:
+        c'_p = c_p + a sum_{q active nb} w_pq (c_q - c_p) - b c_p   (free p),
+        a = D dt / dx^2, b = k dt, w_pq = (e_p + e_q) / 2;
+    Dirichlet voxels keep c0.  L = 1/2 sum_free (c^N - c*)^2.  With lambda zero off the
+    free voxels, lambda^n = the same operator applied to lambda^{n+1}; the gradients are
+        dL/dD   = sum_n <lambda^{n+1}, dt/dx^2 sum_q w (c_q - c_p)>,
+        dL/dk   = sum_n <lambda^{n+1}, -dt c>,
+        dL/de_p = sum_n a/2 sum_{q active nb of p} (c_q - c_p)(lambda_p - lambda_q).
+    Returns (loss, dL/dD, dL/dk, dL/de, c^N).  All states are kept (small volumes)."""
+    act = np.asarray(image) != 0
+    e = np.asarray(eps, dtype=np.float64).reshape(act.shape)
+    dirm = np.zeros(act.shape, dtype=bool)
+    for f in dir_faces:
+        sl = [slice(None)] * 3
+        axis = 2 - f // 2
+        sl[axis] = 0 if f % 2 == 0 else act.shape[axis] - 1
+        dirm[tuple(sl)] = True
+    dirm &= act
+    free = act & ~dirm
+    nb = _neighbours(act)
+    a, b = D * dt / dx ** 2, k * dt
+    w = [0.5 * (e + _shift(e, dst, src)) * m for (m, dst, src) in nb]
+
+    def lap(u):
+        return sum(wd * (_shift(u, dst, src) - u) for wd, (m, dst, src) in zip(w, nb))
+
+    c = np.where(act, np.asarray(c0, dtype=np.float64).reshape(act.shape), 0.0)
+    states = [c]
+    for _ in range(nsteps):
+        c = np.where(free, c + a * lap(c) - b * c, c)
+        states.append(c)
+    tg = np.asarray(target, dtype=np.float64).reshape(act.shape)
+    r = np.where(free, c - tg, 0.0)
+    loss = 0.5 * float(np.sum(r * r))
+    lam = r
+    gD = gk = 0.0
+    ge = np.zeros(act.shape)
+    for n in range(nsteps - 1, -1, -1):
+        cn = states[n]
+        gD += float(np.sum(lam * lap(cn))) * dt / dx ** 2
+        gk += float(np.sum(lam * cn)) * -dt
+        for (m, dst, src) in nb:
+            ge += np.where(m, 0.5 * a * (_shift(cn, dst, src) - cn) * (lam - _shift(lam, dst, src)), 0.0)
+        lam = np.where(free, lam + a * lap(lam) - b * lam, 0.0)
+    return loss, gD, gk, np.where(act, ge, 0.0), states[-1]
