@@ -307,6 +307,22 @@ rd_status rd_sim_steady_state(rd_sim *sim, int axis, double rel_tol, int64_t max
 rd_status rd_sim_adjoint(rd_sim *sim, const float *dev_seed, int seed_mode, int64_t n_steps,
                          double dt, int checkpoint_every, double *loss, double *dL_dD,
                          double *dL_drate);
+/* rd_sim_adjoint with a diffusivity factor set (rd_sim_set_diffusivity), adding the
+ * gradient of the loss with respect to the factor of every voxel:
+ *   dev_dL_de  device double (nz,ny,nx), caller-owned, written (0 off the active voxels):
+ *              dL/de_p = sum_n (D dt / dx^2) / 2 * sum_{q active nb of p}
+ *                        (c^n_q - c^n_p)(lambda^{n+1}_p - lambda^{n+1}_q),
+ * lambda being 0 on Dirichlet voxels.  The factor's parameters follow by the chain rule;
+ * for e = D_min + D_max s(g1 + g2 phi), s the logistic function,
+ * dL/dg1 = sum_p dL/de_p D_max s (1 - s) and dL/dg2 = sum_p dL/de_p D_max s (1 - s) phi_p
+ * (eq. inhomog_diffusion_coefficient).  dL/dD, dL/drate and the loss as rd_sim_adjoint,
+ * whose recursion with a factor uses the face coefficient (e_p + e_q) / 2.  Needs a bind
+ * with RD_WS_ADJOINT | RD_WS_DIFFUSIVITY (RD_ERR_WORKSPACE), a factor (RD_ERR_STATE),
+ * no active sink band (RD_ERR_STATE); RD_ERR_ARG for NULL dev_dL_de; otherwise the
+ * errors of rd_sim_adjoint. */
+rd_status rd_sim_adjoint_factor(rd_sim *sim, const float *dev_seed, int seed_mode, int64_t n_steps,
+                                double dt, int checkpoint_every, double *loss, double *dL_dD,
+                                double *dL_drate, double *dev_dL_de);
 /* Change a species' D, or the rate of reaction `index` (in order of addition), after
  * binding (used between differentiable runs). */
 rd_status rd_sim_set_species_D(rd_sim *sim, int species, double D);

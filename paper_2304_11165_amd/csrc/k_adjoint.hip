@@ -249,6 +249,95 @@ __global__ __launch_bounds__(256) void k_adj_seed(AdjArgs a, int mode)
     if (threadIdx.x == 0) a.partial[b] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
 }
 
+
+// Adjoint step with a diffusivity factor, one thread per slot (see AdjEArgs).  The
+// lambda update mirrors the inhomogeneous forward step in FP32; the gradient terms are
+// FP64.  Rows as in k_adjoint: one per workgroup (B = 8: one block, B = 4: four).
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_adjoint_e(AdjEArgs x)
+{
+    using C = Cfg<B>;
+    constexpr int NS = B * B * B;
+    const AdjArgs &a = x.a;
+    __shared__ double wsum[4][2];
+    const int sub = threadIdx.x / C::TPB, lt = threadIdx.x % C::TPB;
+    const int b = blockIdx.x * C::BPW + sub;
+    double gD = 0.0, gk = 0.0;
+    if (b < a.nb) {
+        const BlockInfo bi = a.info[b];
+        int bx, by, bz, gid;
+        block_pos(bi, &bx, &by, &bz, &gid);
+        const GeomInfo g = a.geom[gid];
+        const T *c = (const T *)a.c;
+        for (int k = 0; k < C::VPT; ++k) {
+            const int slot = lt + k * C::TPB;
+            const int64_t i = (int64_t)b * NS + slot;
+            const unsigned code = a.code[i];
+            float out = 0.0f;
+            if (code & 64u) {
+                const int lx = slot % B, ly = (slot / B) % B, lz = slot / (B * B);
+                const int gx = bx * B + lx, gy = by * B + ly, gz = bz * B + lz;
+                const unsigned onf = (gx == 0 ? 1u : 0u) | (gx == g.nx - 1 ? 2u : 0u) | (gy == 0 ? 4u : 0u) |
+                                     (gy == g.ny - 1 ? 8u : 0u) | (gz == 0 ? 16u : 0u) |
+                                     (gz == g.nz - 1 ? 32u : 0u);
+                const unsigned m = code & 63u;
+                const int nwall = __popc(~onf & ~m & 0x3fu);
+                const float lp = a.lam_in[i], ep = x.e[i];
+                const double cp = (double)rd_ld(c, i);
+                float laml = 0.0f;
+                double lapc = 0.0, gsum = 0.0;
+                const int stride[3] = {1, B, B * B};
+                for (int d = 0; d < 6; ++d) {
+                    if (!((m >> d) & 1u)) continue;
+                    const int ax = d >> 1, l = ax == 0 ? lx : ax == 1 ? ly : lz;
+                    const bool up = d & 1;
+                    int64_t q;
+                    if (up ? l < B - 1 : l > 0) q = i + (up ? stride[ax] : -stride[ax]);
+                    else q = (int64_t)bi.nbr[d] * NS + slot + (up ? -(B - 1) : (B - 1)) * stride[ax];
+                    const float lq = a.lam_in[q], eq = x.e[q];
+                    const double cq = (double)rd_ld(c, q);
+                    laml = fmaf(0.5f * (ep + eq), lq - lp, laml);
+                    lapc += 0.5 * ((double)ep + (double)eq) * (cq - cp);
+                    gsum += (cq - cp) * ((double)lp - (double)lq);
+                }
+                x.ge[i] += 0.5 * x.alpha * gsum;  // lambda is 0 on Dirichlet voxels
+                if (!(onf & a.coef.dir)) {
+                    gD += (double)lp * lapc;
+                    gk -= (double)lp * cp;
+                    const float r = fmaf(a.coef.alpha, laml, lp);
+                    out = fmaf(-fmaf(a.coef.gamma, (float)nwall, a.coef.beta), lp, r);
+                }
+            }
+            a.lam_out[i] = out;
+        }
+    }
+    const int wave = threadIdx.x >> 6;
+    const double s0 = wave_sum(gD), s1 = wave_sum(gk);
+    if ((threadIdx.x & 63) == 0) {
+        wsum[wave][0] = s0;
+        wsum[wave][1] = s1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a.partial[(int64_t)blockIdx.x * 2 + 0] += ((wsum[0][0] + wsum[1][0]) + wsum[2][0]) + wsum[3][0];
+        a.partial[(int64_t)blockIdx.x * 2 + 1] += ((wsum[0][1] + wsum[1][1]) + wsum[2][1]) + wsum[3][1];
+    }
+}
+
+template <int B>
+__global__ __launch_bounds__(256) void k_dense_f64(const BlockInfo *info, const uint8_t *code, const GeomInfo *geom,
+                                                   int nb, const double *v, double *dense)
+{
+    constexpr int NS = B * B * B;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)nb * NS || !(code[i] & 64u)) return;
+    const int b = (int)(i / NS), slot = (int)(i % NS);
+    int bx, by, bz, gid;
+    block_pos(info[b], &bx, &by, &bz, &gid);
+    const GeomInfo g = geom[gid];
+    dense[voxel_id(g, bx * B + slot % B, by * B + (slot / B) % B, bz * B + slot / (B * B))] = v[i];
+}
+
 }  // namespace
 
 #define ADJ_DISPATCH(storage, B, KERNEL, grid, stream, ...)                                        \
@@ -284,4 +373,34 @@ int adj_launch_step(int storage, int B, const AdjArgs &a, void *stream)
 int adj_launch_seed(int storage, int B, const AdjArgs &a, int mode, void *stream)
 {
     ADJ_DISPATCH(storage, B, k_adj_seed, dim3((unsigned)a.nb), stream, a, mode);
+}
+
+int adj_launch_step_e(int storage, int B, const AdjEArgs &x, void *stream)
+{
+    if (x.a.nb <= 0) return 0;
+    hipStream_t st = (hipStream_t)stream;
+    const dim3 grid((unsigned)adj_groups(B, x.a.nb));
+    if (B == 8) {
+        if (storage == 0) hipLaunchKernelGGL((k_adjoint_e<float, 8>), grid, dim3(256), 0, st, x);
+        else if (storage == 1) hipLaunchKernelGGL((k_adjoint_e<bf16_t, 8>), grid, dim3(256), 0, st, x);
+        else hipLaunchKernelGGL((k_adjoint_e<_Float16, 8>), grid, dim3(256), 0, st, x);
+    } else {
+        if (storage == 0) hipLaunchKernelGGL((k_adjoint_e<float, 4>), grid, dim3(256), 0, st, x);
+        else if (storage == 1) hipLaunchKernelGGL((k_adjoint_e<bf16_t, 4>), grid, dim3(256), 0, st, x);
+        else hipLaunchKernelGGL((k_adjoint_e<_Float16, 4>), grid, dim3(256), 0, st, x);
+    }
+    return (int)hipGetLastError();
+}
+
+int adj_launch_dense_f64(int B, const BlockInfo *info, const uint8_t *code, const GeomInfo *geom, int nb,
+                         const double *v, double *dense, int64_t ndense, void *stream)
+{
+    int rc = rd_launch_fill_u32(dense, 0u, 2 * ndense, stream);
+    if (rc != 0 || nb <= 0) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = (int64_t)nb * B * B * B;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (B == 8) hipLaunchKernelGGL((k_dense_f64<8>), grid, dim3(256), 0, st, info, code, geom, nb, v, dense);
+    else hipLaunchKernelGGL((k_dense_f64<4>), grid, dim3(256), 0, st, info, code, geom, nb, v, dense);
+    return (int)hipGetLastError();
 }

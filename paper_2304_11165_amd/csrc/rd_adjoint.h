@@ -20,6 +20,21 @@ struct AdjArgs {
                           // accumulators [parts][2], added to in step order; seed: [nb]
 };
 
+// The adjoint step with a per-slot diffusivity factor e (face coefficient
+// (e_p + e_q) / 2): lambda^n from lambda^{n+1}, the dL/dD and dL/dk rows as above, and
+// dL/de_p += alpha / 2 * sum_{q active nb} (c_q - c_p)(lambda_p - lambda_q) per slot (FP64,
+// ge, added to in step order).  One thread per slot, any B.
+struct AdjEArgs {
+    AdjArgs a;
+    const float *e;
+    double alpha;  // D dt / dx^2 in FP64
+    double *ge;    // dL/de per slot
+};
+int adj_launch_step_e(int storage, int B, const AdjEArgs &x, void *stream);
+// dense (nz, ny, nx) FP64 copy of a per-slot FP64 array (0 off the active voxels)
+int adj_launch_dense_f64(int B, const BlockInfo *info, const uint8_t *code, const GeomInfo *geom, int nb,
+                         const double *v, double *dense, int64_t ndense, void *stream);
+
 // gradient accumulator rows of the step kernel (B = 8: one per block; B = 4: one per
 // workgroup of four blocks)
 int adj_groups(int B, int nb);

@@ -314,6 +314,10 @@ SimLayout sim_layout(const rd_sim &s, uint32_t features, int64_t cp_slots)
             off = align256(off + 4 * (size_t)L.field_elems);
         }
         L.target = off; off = align256(off + 4 * (size_t)L.field_elems);
+        if (features & RD_WS_DIFFUSIVITY) {
+            L.ge = off;
+            off = align256(off + 8 * (size_t)std::max<int64_t>(L.field_elems, 1));
+        }
         L.cp = off;
         L.cp_stride = align256(es * (size_t)L.field_elems);
         off += L.cp_stride * (size_t)cp_slots;

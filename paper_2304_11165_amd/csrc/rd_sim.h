@@ -39,6 +39,7 @@ struct SimLayout {
     size_t irx;              // FP64 iterate of the steady state
     size_t diff, diff_stats; // per-slot diffusivity factor (FP32) and its set-up counters
     size_t lam[2], target, cp, cp_stride;
+    size_t ge;               // dL/de per slot (FP64), adjoint with a diffusivity factor
     size_t total;
 };
 

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "rd_adjoint.h"
+#include "rd_diff.h"
 #include "rd_host.h"
 #include "rd_sim.h"
 #include "rd_solve.h"
@@ -540,17 +541,18 @@ extern "C" void rd_batch_destroy(rd_batch *b) { delete b; }
 // sweep restores each segment's first state, recomputes the segment's states into
 // k-1 spare slots with the same step kernel (bitwise the forward states) and runs
 // the adjoint steps from the segment's end to its start.
-extern "C" rd_status rd_sim_adjoint(rd_sim *sim, const float *dev_seed, int seed_mode,
-                                    int64_t n_steps, double dt, int checkpoint_every,
-                                    double *loss, double *dL_dD, double *dL_drate)
+static rd_status adjoint_impl(rd_sim *sim, const float *dev_seed, int seed_mode, int64_t n_steps, double dt,
+                              int checkpoint_every, double *loss, double *dL_dD, double *dL_drate,
+                              double *dev_dL_de)
 {
     if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
     if (!sim->ws) return rd_fail(RD_ERR_STATE, "bind a workspace first");
     if (!(sim->features & RD_WS_ADJOINT))
         return rd_fail(RD_ERR_WORKSPACE, "bind with RD_WS_ADJOINT for the adjoint");
     if (sim->S != 1) return rd_fail(RD_ERR_STATE, "the adjoint needs a single species");
-    if (sim->diff_path())
-        return rd_fail(RD_ERR_STATE, "the adjoint needs a homogeneous D and no sink band (clear them)");
+    if (sim->sink_active()) return rd_fail(RD_ERR_STATE, "the adjoint does not cover the sink band (clear it)");
+    const bool fac = sim->diff_on;
+    if (dev_dL_de && !fac) return rd_fail(RD_ERR_STATE, "dL/de needs a diffusivity factor (rd_sim_set_diffusivity)");
     for (const Reaction &r : sim->reactions)
         if (r.to != -1) return rd_fail(RD_ERR_STATE, "the adjoint supports decay reactions only");
     if (sim->sround && sim->storage != RD_FP32)
@@ -576,12 +578,17 @@ extern "C" rd_status rd_sim_adjoint(rd_sim *sim, const float *dev_seed, int seed
     auto slot = [&](int64_t j) { return (void *)(ws + sim->L.cp + sim->L.cp_stride * (size_t)j); };
     double *acc = (double *)(ws + sim->L.res) + 16;  // [loss, gD, gk]
     LAUNCHCHK(rd_launch_fill_u32(acc, 0u, 6, stream));
+    const int64_t ndense = G.nx * G.ny * G.nz;
     if (nb == 0) {
         if (loss) *loss = 0;
         if (dL_dD) *dL_dD = 0;
         if (dL_drate) *dL_drate = 0;
+        if (dev_dL_de) LAUNCHCHK(rd_launch_fill_u32(dev_dL_de, 0u, 2 * ndense, stream));
         return RD_OK;
     }
+    double *ge = fac ? (double *)(ws + sim->L.ge) : nullptr;
+    if (fac) LAUNCHCHK(rd_launch_fill_u32(ge, 0u, 2 * sim->L.field_elems, stream));
+    const float *efac = (const float *)(ws + sim->L.diff);
     // the seed in block-major FP32
     float zero6[6] = {0, 0, 0, 0, 0, 0};
     float *seed = (float *)(ws + sim->L.target);
@@ -630,17 +637,31 @@ extern "C" rd_status rd_sim_adjoint(rd_sim *sim, const float *dev_seed, int seed
             sa.ctr = sim->step_counter();
             sa.ctr_off = 0;
             sim->launch_shape(sa);
-            LAUNCHCHK(rd_launch_step(st, B, sa, stream));
+            if (fac) {  // the inhomogeneous step, as rd_sim_step runs it
+                const int column = B == 8 && sim->kernel != 0 ? 1 : 0;
+                sa.xcd_chunk = 0;
+                DiffArgs da{sa, efac, {0.0f, 0.0f, 0.0f, 0.0f}};
+                LAUNCHCHK(rd_launch_step_diff(st, B, da, column, stream));
+            } else {
+                LAUNCHCHK(rd_launch_step(st, B, sa, stream));
+            }
         }
         for (int64_t m = len - 1; m >= 0; --m) {
             a.c = seg(m);
             a.lam_in = lam[lc];
             a.lam_out = lam[1 - lc];
-            LAUNCHCHK(adj_launch_step(st, B, a, stream));
+            if (fac) {
+                AdjEArgs x{a, efac, sim->D[0] * dt / (G.dx * G.dx), ge};
+                LAUNCHCHK(adj_launch_step_e(st, B, x, stream));
+            } else {
+                LAUNCHCHK(adj_launch_step(st, B, a, stream));
+            }
             lc = 1 - lc;
         }
     }
     LAUNCHCHK(rd_launch_finish_reduce(a.partial, nrows, 2, mid, acc + 1, stream));
+    if (dev_dL_de)
+        LAUNCHCHK(adj_launch_dense_f64(B, a.info, a.code, a.geom, nb, ge, dev_dL_de, ndense, stream));
     double h[3];
     HIPCHK(hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
@@ -651,6 +672,22 @@ extern "C" rd_status rd_sim_adjoint(rd_sim *sim, const float *dev_seed, int seed
     if (!isfinite(h[0]) || !isfinite(h[1]) || !isfinite(h[2]))
         return rd_fail(RD_ERR_NONFINITE, "adjoint produced a non-finite value");
     return RD_OK;
+}
+
+extern "C" rd_status rd_sim_adjoint(rd_sim *sim, const float *dev_seed, int seed_mode, int64_t n_steps, double dt,
+                                    int checkpoint_every, double *loss, double *dL_dD, double *dL_drate)
+{
+    return adjoint_impl(sim, dev_seed, seed_mode, n_steps, dt, checkpoint_every, loss, dL_dD, dL_drate, nullptr);
+}
+
+extern "C" rd_status rd_sim_adjoint_factor(rd_sim *sim, const float *dev_seed, int seed_mode, int64_t n_steps,
+                                           double dt, int checkpoint_every, double *loss, double *dL_dD,
+                                           double *dL_drate, double *dev_dL_de)
+{
+    if (!dev_dL_de) return rd_fail(RD_ERR_ARG, "dL/de output is NULL");
+    if (sim && !(sim->features & RD_WS_DIFFUSIVITY))
+        return rd_fail(RD_ERR_WORKSPACE, "bind with RD_WS_ADJOINT | RD_WS_DIFFUSIVITY for dL/de");
+    return adjoint_impl(sim, dev_seed, seed_mode, n_steps, dt, checkpoint_every, loss, dL_dD, dL_drate, dev_dL_de);
 }
 
 extern "C" rd_status rd_sim_set_species_D(rd_sim *sim, int species, double D)

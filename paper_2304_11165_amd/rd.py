@@ -80,6 +80,7 @@ _SIGS = {
     "rd_sim_plane_flux": ([P, ci, ci, i64, P], ci),
     "rd_sim_steady_state": ([P, ci, f64, i64, P, P, P], ci),
     "rd_sim_adjoint": ([P, P, ci, i64, f64, ci, P, P, P], ci),
+    "rd_sim_adjoint_factor": ([P, P, ci, i64, f64, ci, P, P, P, P], ci),
     "rd_sim_set_species_D": ([P, ci, f64], ci),
     "rd_sim_set_reaction_rate": ([P, ci, f64], ci),
     "rd_sim_destroy": ([P], None),
@@ -449,6 +450,23 @@ class Sim:
                                    int(checkpoint_every), ctypes.byref(L), ctypes.byref(gD),
                                    ctypes.byref(gk)), "rd_sim_adjoint")
         return L.value, gD.value, gk.value
+
+    def adjoint_factor(self, seed, n_steps, dt, checkpoint_every, seed_is_target=True):
+        """(loss, dL/dD, dL/dk, dL/de) with a diffusivity factor set; dL/de is a float64
+        (nz, ny, nx) tensor on the GPU."""
+        import torch
+
+        nz, ny, nx = self.geometry.shape
+        t = torch.as_tensor(seed, dtype=torch.float32, device=self.workspace.device)
+        t = t.reshape(nz, ny, nx).contiguous()
+        ge = torch.empty((nz, ny, nx), dtype=torch.float64, device=self.workspace.device)
+        L, gD, gk = f64(), f64(), f64()
+        _check(_lib.rd_sim_adjoint_factor(self.handle, ctypes.c_void_p(t.data_ptr()),
+                                          0 if seed_is_target else 1, int(n_steps), float(dt),
+                                          int(checkpoint_every), ctypes.byref(L), ctypes.byref(gD),
+                                          ctypes.byref(gk), ctypes.c_void_p(ge.data_ptr())),
+               "rd_sim_adjoint_factor")
+        return L.value, gD.value, gk.value, ge
 
     def __del__(self, _destroy=_lib.rd_sim_destroy):
         h = getattr(self, "handle", None)
