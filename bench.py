@@ -281,9 +281,37 @@ def adjoint_form(torch, rd, W, stream):
         adj = time.perf_counter() - t0
     log(f"adjoint: forward {fwd * 1e3:.1f} ms, forward with checkpoints + recompute + backward "
         f"{adj * 1e3:.1f} ms")
+    # the same run with the smooth D(phi) factor: dL/de per voxel as well
+    with torch.cuda.stream(stream):
+        del sim
+        sim = rd.Sim(geom, "fp32")
+        sim.add_species(w.species_D[0])
+        sim.add_reaction(0, -1, 0.02)
+        sim.set_dirichlet(0, 0, 1.0)
+        sim.bind(features=rd.RD_WS_ADJOINT | rd.RD_WS_DIFFUSIVITY,
+                 checkpoint_slots=(n + k - 1) // k + k - 1, stream=stream)
+        phi = rd.sdf_from_image(torch.from_numpy(img).to("cuda"), 1.0, stream)
+        sim.set_diffusivity_sdf(phi, *DIFF_PARS)
+        sim.set_field(0, zero)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(w.dt, n)
+        torch.cuda.synchronize()
+        ffwd = time.perf_counter() - t0
+        sim.set_field(0, zero)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        floss, fgD, fgk, ge = sim.adjoint_factor(target, n, w.dt, k, seed_is_target=True)
+        torch.cuda.synchronize()
+        fadj = time.perf_counter() - t0
+        ge_norm = float(torch.linalg.vector_norm(ge))
+    log(f"adjoint with a factor: forward {ffwd * 1e3:.1f} ms, adjoint with dL/de {fadj * 1e3:.1f} ms")
+    factor = {"diffusivity": "e = %g + %g / (1 + exp(-(%g + %g phi)))" % DIFF_PARS,
+              "forward_seconds": ffwd, "adjoint_seconds": fadj, "adjoint_over_forward": fadj / ffwd,
+              "loss": floss, "dL_dD": fgD, "dL_drate": fgk, "dL_de_l2": ge_norm}
     return {"workload": "decay256", "n_active": st["n_active"], "steps": n, "checkpoint_every": k,
             "forward_seconds": fwd, "adjoint_seconds": adj, "adjoint_over_forward": adj / fwd,
-            "loss": loss, "dL_dD": gD, "dL_drate": gk,
+            "loss": loss, "dL_dD": gD, "dL_drate": gk, "factor": factor,
             "note": "adjoint_seconds: forward with checkpoints, recompute of each segment, "
                     "backward sweep; FP32 fields, FP64 gradient sums"}
 
