@@ -324,6 +324,131 @@ __global__ __launch_bounds__(256) void k_adjoint_e(AdjEArgs x)
     }
 }
 
+// Column form of k_adjoint_e for 8^3 blocks: one wave per block, lane (lx, ly) walking
+// z, lambda / c / e planes staged in LDS with their side halos, the z neighbours in
+// registers.  Per voxel the same operations in the same order as k_adjoint_e (dL/de and
+// lambda are bitwise equal; the dL/dD and dL/dk rows are summed in another order).
+// One row per block.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adjoint8e(AdjEArgs x)
+{
+    __shared__ float tl[4][100], tc[4][100], te[4][100];
+    const AdjArgs &a = x.a;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int b = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + wv);
+    if (b >= a.nb) return;
+    const BlockInfo bi = a.info[b];
+    const T *cv = (const T *)a.c;
+    const int64_t base = (int64_t)b * 512;
+    const int lx = lane & 7, ly = lane >> 3;
+    const uint64_t *rec = a.mask + (int64_t)b * 16;
+    uint64_t Wo[8], Wf[6];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) Wo[z] = rec[z];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) Wf[f] = rec[8 + f];
+    float lc[8], lh[6], ec[8], eh[6];
+    float cc[8], ch[6];
+    unsigned cd[8];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        const bool act = (Wo[z] >> lane) & 1ull;
+        const int64_t i = base + z * 64 + lane;
+        lc[z] = act ? a.lam_in[i] : 0.0f;
+        cc[z] = act ? rd_ld(cv, i) : 0.0f;
+        ec[z] = act ? x.e[i] : 0.0f;
+        cd[z] = act ? (unsigned)a.code[i] : 0u;
+    }
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        int ns;
+        switch (f) {
+        case 0: ns = (ly * 8 + lx) * 8 + 7; break;
+        case 1: ns = (ly * 8 + lx) * 8 + 0; break;
+        case 2: ns = (ly * 8 + 7) * 8 + lx; break;
+        case 3: ns = (ly * 8 + 0) * 8 + lx; break;
+        case 4: ns = (7 * 8 + ly) * 8 + lx; break;
+        default: ns = (0 * 8 + ly) * 8 + lx; break;
+        }
+        const int n = bi.nbr[f];
+        const bool on = (Wf[f] >> lane) & 1ull;
+        const int64_t h = (int64_t)(n >= 0 ? n : b) * 512 + ns;
+        lh[f] = on ? a.lam_in[h] : 0.0f;
+        ch[f] = on ? rd_ld(cv, h) : 0.0f;
+        eh[f] = on ? x.e[h] : 0.0f;
+    }
+    int bx, by, bz, gid;
+    block_pos(bi, &bx, &by, &bz, &gid);
+    const GeomInfo g = a.geom[gid];
+    const int gx = bx * 8 + lx, gy = by * 8 + ly;
+    auto pix = [](int px, int py) { return (py + 1) * 10 + (px + 1); };
+    double gD = 0.0, gk = 0.0;
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        tl[wv][pix(lx, ly)] = lc[z];
+        tc[wv][pix(lx, ly)] = cc[z];
+        te[wv][pix(lx, ly)] = ec[z];
+        if (ly == z) {
+            tl[wv][pix(-1, lx)] = lh[0]; tl[wv][pix(8, lx)] = lh[1];
+            tl[wv][pix(lx, -1)] = lh[2]; tl[wv][pix(lx, 8)] = lh[3];
+            tc[wv][pix(-1, lx)] = ch[0]; tc[wv][pix(8, lx)] = ch[1];
+            tc[wv][pix(lx, -1)] = ch[2]; tc[wv][pix(lx, 8)] = ch[3];
+            te[wv][pix(-1, lx)] = eh[0]; te[wv][pix(8, lx)] = eh[1];
+            te[wv][pix(lx, -1)] = eh[2]; te[wv][pix(lx, 8)] = eh[3];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const unsigned code = cd[z];
+        float out = 0.0f;
+        if (code & 64u) {
+            const int gz = bz * 8 + z;
+            const unsigned onf = (gx == 0 ? 1u : 0u) | (gx == g.nx - 1 ? 2u : 0u) | (gy == 0 ? 4u : 0u) |
+                                 (gy == g.ny - 1 ? 8u : 0u) | (gz == 0 ? 16u : 0u) | (gz == g.nz - 1 ? 32u : 0u);
+            const unsigned m = code & 63u;
+            const int nwall = __popc(~onf & ~m & 0x3fu);
+            const int t = pix(lx, ly);
+            const float lp = lc[z], ep = ec[z];
+            const double cp = (double)cc[z];
+            const float lnv[6] = {tl[wv][t - 1], tl[wv][t + 1], tl[wv][t - 10], tl[wv][t + 10],
+                                  z == 0 ? lh[4] : lc[z > 0 ? z - 1 : 0], z == 7 ? lh[5] : lc[z < 7 ? z + 1 : 7]};
+            const float cnv[6] = {tc[wv][t - 1], tc[wv][t + 1], tc[wv][t - 10], tc[wv][t + 10],
+                                  z == 0 ? ch[4] : cc[z > 0 ? z - 1 : 0], z == 7 ? ch[5] : cc[z < 7 ? z + 1 : 7]};
+            const float env[6] = {te[wv][t - 1], te[wv][t + 1], te[wv][t - 10], te[wv][t + 10],
+                                  z == 0 ? eh[4] : ec[z > 0 ? z - 1 : 0], z == 7 ? eh[5] : ec[z < 7 ? z + 1 : 7]};
+            float laml = 0.0f;
+            double lapc = 0.0, gsum = 0.0;
+#pragma unroll
+            for (int d = 0; d < 6; ++d) {
+                if (!((m >> d) & 1u)) continue;
+                const float lq = lnv[d], eq = env[d];
+                const double cq = (double)cnv[d];
+                laml = fmaf(0.5f * (ep + eq), lq - lp, laml);
+                lapc += 0.5 * ((double)ep + (double)eq) * (cq - cp);
+                gsum += (cq - cp) * ((double)lp - (double)lq);
+            }
+            const int64_t i = base + z * 64 + lane;
+            x.ge[i] += 0.5 * x.alpha * gsum;
+            if (!(onf & a.coef.dir)) {
+                gD += (double)lp * lapc;
+                gk -= (double)lp * cp;
+                const float r = fmaf(a.coef.alpha, laml, lp);
+                out = fmaf(-fmaf(a.coef.gamma, (float)nwall, a.coef.beta), lp, r);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        a.lam_out[base + z * 64 + lane] = out;
+    }
+    gD = wave_sum(gD);
+    gk = wave_sum(gk);
+    if (lane == 0) {
+        a.partial[(int64_t)b * 2 + 0] += gD;
+        a.partial[(int64_t)b * 2 + 1] += gk;
+    }
+}
+
 template <int B>
 __global__ __launch_bounds__(256) void k_dense_f64(const BlockInfo *info, const uint8_t *code, const GeomInfo *geom,
                                                    int nb, const double *v, double *dense)
@@ -375,12 +500,17 @@ int adj_launch_seed(int storage, int B, const AdjArgs &a, int mode, void *stream
     ADJ_DISPATCH(storage, B, k_adj_seed, dim3((unsigned)a.nb), stream, a, mode);
 }
 
-int adj_launch_step_e(int storage, int B, const AdjEArgs &x, void *stream)
+int adj_launch_step_e(int storage, int B, const AdjEArgs &x, int column, void *stream)
 {
     if (x.a.nb <= 0) return 0;
     hipStream_t st = (hipStream_t)stream;
     const dim3 grid((unsigned)adj_groups(B, x.a.nb));
-    if (B == 8) {
+    if (B == 8 && column) {  // four blocks per workgroup, one row per block
+        const dim3 g8((unsigned)((x.a.nb + 3) / 4));
+        if (storage == 0) hipLaunchKernelGGL((k_adjoint8e<float>), g8, dim3(256), 0, st, x);
+        else if (storage == 1) hipLaunchKernelGGL((k_adjoint8e<bf16_t>), g8, dim3(256), 0, st, x);
+        else hipLaunchKernelGGL((k_adjoint8e<_Float16>), g8, dim3(256), 0, st, x);
+    } else if (B == 8) {
         if (storage == 0) hipLaunchKernelGGL((k_adjoint_e<float, 8>), grid, dim3(256), 0, st, x);
         else if (storage == 1) hipLaunchKernelGGL((k_adjoint_e<bf16_t, 8>), grid, dim3(256), 0, st, x);
         else hipLaunchKernelGGL((k_adjoint_e<_Float16, 8>), grid, dim3(256), 0, st, x);

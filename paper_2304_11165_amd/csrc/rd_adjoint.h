@@ -23,14 +23,15 @@ struct AdjArgs {
 // The adjoint step with a per-slot diffusivity factor e (face coefficient
 // (e_p + e_q) / 2): lambda^n from lambda^{n+1}, the dL/dD and dL/dk rows as above, and
 // dL/de_p += alpha / 2 * sum_{q active nb} (c_q - c_p)(lambda_p - lambda_q) per slot (FP64,
-// ge, added to in step order).  One thread per slot, any B.
+// ge, added to in step order).  column = 1 (B = 8): one wave per block walking
+// z-columns; otherwise one thread per slot.  Rows: one per block for B = 8.
 struct AdjEArgs {
     AdjArgs a;
     const float *e;
     double alpha;  // D dt / dx^2 in FP64
     double *ge;    // dL/de per slot
 };
-int adj_launch_step_e(int storage, int B, const AdjEArgs &x, void *stream);
+int adj_launch_step_e(int storage, int B, const AdjEArgs &x, int column, void *stream);
 // dense (nz, ny, nx) FP64 copy of a per-slot FP64 array (0 off the active voxels)
 int adj_launch_dense_f64(int B, const BlockInfo *info, const uint8_t *code, const GeomInfo *geom, int nb,
                          const double *v, double *dense, int64_t ndense, void *stream);

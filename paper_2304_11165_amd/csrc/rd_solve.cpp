@@ -652,7 +652,7 @@ static rd_status adjoint_impl(rd_sim *sim, const float *dev_seed, int seed_mode,
             a.lam_out = lam[1 - lc];
             if (fac) {
                 AdjEArgs x{a, efac, sim->D[0] * dt / (G.dx * G.dx), ge};
-                LAUNCHCHK(adj_launch_step_e(st, B, x, stream));
+                LAUNCHCHK(adj_launch_step_e(st, B, x, B == 8 && sim->kernel != 0 ? 1 : 0, stream));
             } else {
                 LAUNCHCHK(adj_launch_step(st, B, a, stream));
             }

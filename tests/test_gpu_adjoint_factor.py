@@ -102,3 +102,15 @@ def test_errors(rd, oracle_mod):
     with pytest.raises(rd.RDError) as ex:
         s2.adjoint_factor(target, 5, 0.05, 5)
     assert ex.value.name == "RD_ERR_WORKSPACE"
+
+
+def test_column_and_per_slot_kernels_agree(rd, oracle_mod):
+    """B = 8: the column adjoint kernel and the one-thread-per-slot kernel give the same
+    dL/de bits; the gradient rows are summed in another order."""
+    img, eps, target = _case(oracle_mod, n=26, seed=13, steps=40)
+    col = _gpu(rd, img, eps, target, 0.8, 0.02, 0.06, 40, 10, kernel="column")[0]
+    per = _gpu(rd, img, eps, target, 0.8, 0.02, 0.06, 40, 10, kernel="block")[0]
+    assert np.array_equal(col[3], per[3])
+    assert col[0] == per[0]
+    assert col[1] == pytest.approx(per[1], rel=1e-12)
+    assert col[2] == pytest.approx(per[2], rel=1e-12)
