@@ -369,19 +369,21 @@ def diffusivity_form(torch, rd, np, geom, img, w, n_active, steps, graph_steps, 
     return res
 
 
-def frap_form(torch, rd, np, W, n, stream):
-    """Simulated FRAP on a porous volume (pore phase of overlapping balls, porosity 0.5)
-    and on a free-space box of the same size: bleached central box of edge n/4, D = 1,
-    dt = 0.1; D_eff from the least-squares fit, tau_d = 1 / D_eff, and the steady-state
-    tortuosity of the same volume along x beside it."""
-    img, _ = W.boolean_spheres(n, 0.5, 4.0, 8.0, seed=7)
-    q = n // 8
+def frap_tau(torch, rd, np, img, stream):
+    """Simulated FRAP on one porous volume and on a free-space box of the same size:
+    bleached central box of edge n/4, D = 1, dt = 0.1; D_eff from the least-squares fit,
+    tau_d = 1 / D_eff, and the steady-state tortuosity of the same volume along x."""
+    n = img.shape[0]
+    q = max(1, n // 8)
     reg = (n // 2 - q, n // 2 + q) * 3
     x0, x1, y0, y1, z0, z1 = reg
     dt = 0.1
+    # recovery time scale ~ (n/4)^2 / D: sample the porous run over ~ 1.2 of it
+    t_end = 1.2 * (2 * q) ** 2
+    sps = max(1, int(round(t_end / 60 / dt)))
     runs = {}
     t0 = time.perf_counter()
-    for name, im, sps, ns in (("porous", img, 50, 60), ("free", np.ones_like(img), 10, 300)):
+    for name, im, sp, ns in (("porous", img, sps, 60), ("free", np.ones_like(img), max(1, sps // 5), 300)):
         c0 = (im != 0).astype(np.float32)
         c0[z0:z1, y0:y1, x0:x1] = 0.0
         cinf = float(c0.sum()) / float((im != 0).sum())
@@ -393,10 +395,10 @@ def frap_form(torch, rd, np, W, n, stream):
             sim.bind(stream=stream)
             sim.set_field(0, torch.from_numpy(c0).to("cuda"))
             ts = time.perf_counter()
-            curve = sim.frap_curve(0, reg, dt, sps, ns)
+            curve = sim.frap_curve(0, reg, dt, sp, ns)
             secs = time.perf_counter() - ts
-        runs[name] = {"curve": curve / m_inf, "seconds": secs, "steps": sps * ns,
-                      "samples": ns + 1, "n_active": geom.stats()["n_active"], "dt_sample": sps * dt}
+        runs[name] = {"curve": curve / m_inf, "seconds": secs, "steps": sp * ns, "samples": ns + 1,
+                      "n_active": geom.stats()["n_active"], "dt_sample": sp * dt}
         del sim, geom
     por, free = runs["porous"], runs["free"]
     t = np.arange(por["samples"]) * por["dt_sample"]
@@ -409,28 +411,33 @@ def frap_form(torch, rd, np, W, n, stream):
         sim.bind(features=rd.RD_WS_SOLVER, stream=stream)
         ts = time.perf_counter()
         ss = sim.steady_state(0, 1e-8, 100000)
-        tau_ss, iters = ss["tau"], ss["iters"]
         t_ss = time.perf_counter() - ts
         del sim, geom
-    res = {
-        "volume": f"{n}^3 pore phase of overlapping balls (radii 4-8, porosity 0.5), bleached "
-                  f"box {2 * q}^3 at the centre, D = 1, dt = 0.1",
-        "porosity": float((img != 0).mean()),
-        "D_eff": d_eff,
-        "tau_frap": 1.0 / d_eff,
-        "fit_rms": rms,
-        "tau_steady_x": tau_ss,
-        "steady_iterations": iters,
-        "steady_seconds": t_ss,
-        "frap_wall_seconds": wall,
-        "porous_steps": por["steps"],
-        "porous_seconds": por["seconds"],
-        "porous_updates_per_s": por["n_active"] * por["steps"] / por["seconds"],
-        "free_steps": free["steps"],
-        "free_seconds": free["seconds"],
-    }
-    log(f"frap: D_eff {d_eff:.4f} tau {1 / d_eff:.4f} (steady tau_x {tau_ss:.4f}); porous "
-        f"{por['steps']} steps + {por['samples']} samples in {por['seconds']:.2f}s")
+    return {"n": n, "porosity": float((img != 0).mean()), "D_eff": d_eff, "tau_frap": 1.0 / d_eff,
+            "fit_rms": rms, "tau_steady_x": ss["tau"], "steady_iterations": ss["iters"],
+            "steady_seconds": t_ss, "frap_wall_seconds": wall, "porous_steps": por["steps"],
+            "porous_seconds": por["seconds"],
+            "porous_updates_per_s": por["n_active"] * por["steps"] / por["seconds"],
+            "free_steps": free["steps"], "free_seconds": free["seconds"]}
+
+
+def frap_form(torch, rd, np, W, n, stream):
+    """FRAP tortuosity of an n^3 pore phase of overlapping balls (radii 4-8, porosity 0.5),
+    then of the first eight packings of the batched workload, each beside its
+    steady-state tortuosity along x."""
+    img, _ = W.boolean_spheres(n, 0.5, 4.0, 8.0, seed=7)
+    res = frap_tau(torch, rd, np, img, stream)
+    res["volume"] = (f"{n}^3 pore phase of overlapping balls (radii 4-8, porosity 0.5), bleached "
+                     f"central box of edge n/4, D = 1, dt = 0.1")
+    log(f"frap: D_eff {res['D_eff']:.4f} tau {res['tau_frap']:.4f} (steady tau_x "
+        f"{res['tau_steady_x']:.4f}); porous {res['porous_steps']} steps in {res['porous_seconds']:.2f}s")
+    packs = []
+    for im, info in W.batch_geometries(count=8):
+        r = frap_tau(torch, rd, np, im, stream)
+        packs.append({k: r[k] for k in ("n", "porosity", "tau_frap", "tau_steady_x", "fit_rms")})
+        log(f"frap packing n={r['n']} porosity {r['porosity']:.3f}: tau_frap {r['tau_frap']:.4f} "
+            f"tau_steady_x {r['tau_steady_x']:.4f}")
+    res["batch_packings"] = packs
     return res
 
 
