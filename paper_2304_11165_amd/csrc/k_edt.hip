@@ -10,7 +10,8 @@
 // Felzenszwalb and Huttenlocher ("Distance transforms of sampled functions", Theory of
 // Computing 8, 2012): a scan along x gives the squared distance to the nearest feature
 // of the row, then each line along y and along z is replaced by
-// min_k ((j - k)^2 + f(k)).  One thread per line; the envelope's vertices, heights and
+// min_k ((j - k)^2 + f(k)).  One wave per row for the scan, one thread per line for the
+// envelope passes; the envelope's vertices, heights and
 // interval boundaries live in a global scratch interleaved by line, so that
 // neighbouring threads touch neighbouring words.  HBM-bound: a few bytes per voxel and
 // pass, no arithmetic to speak of.
@@ -28,66 +29,105 @@ constexpr uint32_t EDT_INF = 0xffffffffu;
 
 // Pass along x: g = squared distance to the nearest feature voxel of the row
 // (EDT_INF if the row has none).  feature_inactive = 1: inactive voxels are features.
-__global__ __launch_bounds__(256) void k_edt_x(const uint8_t *img, int nx, int64_t nrows, int feature_inactive,
-                                               uint32_t *g)
+// One wave per row, 64 consecutive voxels per step: the nearest feature to the left is
+// a running prefix maximum of feature indices across the lanes (carried from chunk to
+// chunk), the nearest to the right a suffix minimum taken from the far end.
+__global__ __launch_bounds__(256) void k_edt_x(const uint8_t *__restrict__ img, int nx, int64_t nrows,
+                                               int feature_inactive, uint32_t *__restrict__ g)
 {
-    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;  // y + ny * z
-    if (row >= nrows) return;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= nrows) return;  // whole waves
     const uint8_t *r = img + row * nx;
     uint32_t *out = g + row * nx;
-    int last = -1;  // nearest feature at or left of i
-    for (int i = 0; i < nx; ++i) {
-        if ((r[i] == 0) == (feature_inactive != 0)) last = i;
-        out[i] = last < 0 ? EDT_INF : (uint32_t)(i - last);
+    int carry = -1;
+    for (int c0 = 0; c0 < nx; c0 += 64) {
+        const int i = c0 + lane;
+        const bool f = i < nx && ((r[i] == 0) == (feature_inactive != 0));
+        int v = f ? i : -1;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(v, o, 64);
+            if (lane >= o) v = max(v, u);
+        }
+        v = max(v, carry);
+        carry = __shfl(v, 63, 64);
+        if (i < nx) out[i] = v < 0 ? EDT_INF : (uint32_t)(i - v);
     }
-    last = -1;  // nearest feature at or right of i
-    for (int i = nx - 1; i >= 0; --i) {
-        if ((r[i] == 0) == (feature_inactive != 0)) last = i;
-        uint32_t d = out[i];
-        if (last >= 0 && (uint32_t)(last - i) < d) d = (uint32_t)(last - i);
-        out[i] = d == EDT_INF ? EDT_INF : d * d;
+    int carry2 = 0x7fffffff;
+    for (int c0 = ((nx - 1) / 64) * 64; c0 >= 0; c0 -= 64) {
+        const int i = c0 + lane;
+        const bool f = i < nx && ((r[i] == 0) == (feature_inactive != 0));
+        int v = f ? i : 0x7fffffff;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_down(v, o, 64);
+            if (lane + o < 64) v = min(v, u);
+        }
+        v = min(v, carry2);
+        carry2 = __shfl(v, 0, 64);
+        if (i < nx) {
+            uint32_t d = out[i];
+            if (v != 0x7fffffff && (uint32_t)(v - i) < d) d = (uint32_t)(v - i);
+            out[i] = d == EDT_INF ? EDT_INF : d * d;
+        }
     }
 }
 
 // One line of n samples of g, at stride st from base, replaced by its distance
 // transform min_k ((j - k)^2 + g(k)).  Line `line` of `nl` lines owns the scratch words
 // V[k * nl + line] (vertex), H[...] (its height g(vertex)), Z[...] (left end of its
-// interval).
-__global__ __launch_bounds__(256) void k_edt_lines(uint32_t *g, int n, int64_t st, int64_t nl, int lines_x,
-                                                   int64_t lstride_x, int64_t lstride_y, int32_t *V,
-                                                   uint32_t *H, double *Z)
+// interval).  The top of the envelope is held in registers and written through, so the
+// scratch is read back only when a parabola is dropped or the evaluation moves on.
+__global__ __launch_bounds__(256) void k_edt_lines(uint32_t *__restrict__ g, int n, int64_t st, int64_t nl,
+                                                   int lines_x, int64_t lstride_x, int64_t lstride_y,
+                                                   int32_t *__restrict__ V, uint32_t *__restrict__ H,
+                                                   double *__restrict__ Z)
 {
     const int64_t line = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (line >= nl) return;
     const int64_t base = (line % lines_x) * lstride_x + (line / lines_x) * lstride_y;
     int kk = -1;  // top of the envelope
+    int tv = 0;   // its vertex, height and left end
+    uint32_t th = 0;
+    double tz = -INFINITY;
     for (int q = 0; q < n; ++q) {
         const uint32_t fq = g[base + q * st];
         if (fq == EDT_INF) continue;
         const double hq = (double)fq + (double)q * (double)q;  // exact: below 2^53
         double s = -INFINITY;
         while (kk >= 0) {
-            const int p = V[(int64_t)kk * nl + line];
-            const double hp = (double)H[(int64_t)kk * nl + line] + (double)p * (double)p;
-            s = (hq - hp) / (2.0 * (double)(q - p));  // where the two parabolas cross
-            if (s <= Z[(int64_t)kk * nl + line]) {
-                --kk;
-                s = -INFINITY;
-            } else {
-                break;
+            const double hp = (double)th + (double)tv * (double)tv;
+            s = (hq - hp) / (2.0 * (double)(q - tv));  // where the two parabolas cross
+            if (s > tz) break;
+            --kk;  // the top parabola is nowhere lowest: drop it
+            s = -INFINITY;
+            if (kk >= 0) {
+                tv = V[(int64_t)kk * nl + line];
+                th = H[(int64_t)kk * nl + line];
+                tz = Z[(int64_t)kk * nl + line];
             }
         }
         ++kk;
+        tv = q;
+        th = fq;
+        tz = s;
         V[(int64_t)kk * nl + line] = q;
         H[(int64_t)kk * nl + line] = fq;
         Z[(int64_t)kk * nl + line] = s;
     }
     if (kk < 0) return;  // no finite sample: the line stays EDT_INF
     int k = 0;
+    int cv = V[line];
+    uint32_t ch = H[line];
+    double nzb = kk >= 1 ? Z[nl + line] : INFINITY;  // left end of the next interval
     for (int j = 0; j < n; ++j) {
-        while (k < kk && Z[(int64_t)(k + 1) * nl + line] < (double)j) ++k;
-        const int64_t d = (int64_t)j - V[(int64_t)k * nl + line];
-        g[base + j * st] = (uint32_t)(d * d + (int64_t)H[(int64_t)k * nl + line]);
+        while (nzb < (double)j) {
+            ++k;
+            cv = V[(int64_t)k * nl + line];
+            ch = H[(int64_t)k * nl + line];
+            nzb = k < kk ? Z[(int64_t)(k + 1) * nl + line] : INFINITY;
+        }
+        const int64_t d = (int64_t)j - cv;
+        g[base + j * st] = (uint32_t)(d * d + (int64_t)ch);
     }
 }
 
@@ -139,8 +179,8 @@ extern "C" rd_status rd_sdf_from_image(const uint8_t *dev_image, int64_t nx, int
     const double diag = sqrt((double)nx * nx + (double)ny * ny + (double)nz * nz);
     for (int active = 1; active >= 0; --active) {
         // features: the other phase
-        hipLaunchKernelGGL(k_edt_x, dim3(blocks_for(ny * nz)), dim3(256), 0, st, dev_image, (int)nx, ny * nz,
-                           active, g);
+        hipLaunchKernelGGL(k_edt_x, dim3((unsigned)((ny * nz + 3) / 4)), dim3(256), 0, st, dev_image, (int)nx,
+                           ny * nz, active, g);
         // lines along y: line = x + nx z, base = x + nx ny z, stride nx
         hipLaunchKernelGGL(k_edt_lines, dim3(blocks_for(nx * nz)), dim3(256), 0, st, g, (int)ny, nx, nx * nz,
                            (int)nx, (int64_t)1, nx * ny, V, H, Z);
