@@ -63,6 +63,8 @@ def _load():
     lib.orc_smooth_diffusivity.restype = None
     lib.orc_plane_flux.argtypes = [i64, i64, i64, f64, P, f64, P, ci, i64]
     lib.orc_plane_flux.restype = f64
+    lib.orc_plane_flux_eps.argtypes = [i64, i64, i64, f64, P, f64, P, P, ci, i64]
+    lib.orc_plane_flux_eps.restype = f64
     lib.orc_steady_jacobi.argtypes = [i64, i64, i64, P, P, P, f64, i64, i64, P, P]
     lib.orc_steady_jacobi.restype = ci
     lib.orc_steady_cg.argtypes = [i64, i64, i64, P, P, P, f64, i64, P, P]
@@ -198,6 +200,9 @@ class Problem:
     def plane_flux(self, u, D, axis, i0):
         lib = _load()
         u = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(self.nz, self.ny, self.nx))
+        if self.eps is not None:
+            return lib.orc_plane_flux_eps(self.nx, self.ny, self.nz, self.dx, _ptr(self.image),
+                                          float(D), _ptr(self.eps), _ptr(u), int(axis), int(i0))
         return lib.orc_plane_flux(self.nx, self.ny, self.nz, self.dx, _ptr(self.image), float(D),
                                   _ptr(u), int(axis), int(i0))
 

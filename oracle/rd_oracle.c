@@ -305,6 +305,25 @@ double orc_plane_flux(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8
     return q;
 }
 
+/* The same flux with a per-voxel diffusivity factor: each straddling pair carries
+ * D * (eps_i + eps_{i+1}) / 2 * (u_i - u_{i+1}) * dx (the face coefficient of the step). */
+double orc_plane_flux_eps(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8_t *active,
+                          double D, const double *eps, const double *u, int axis, int64_t i0)
+{
+    double q = 0.0;
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                int64_t c0 = axis == 0 ? i : axis == 1 ? j : k;
+                if (c0 != i0) continue;
+                int64_t a = i + (axis == 0), b = j + (axis == 1), cc = k + (axis == 2);
+                if (!in_box(a, b, cc, nx, ny, nz)) continue;
+                int64_t p = IDX(i, j, k), r = IDX(a, b, cc);
+                if (active[p] && active[r]) q += D * 0.5 * (eps[p] + eps[r]) * (u[p] - u[r]) * dx;
+            }
+    return q;
+}
+
 /* ---------------------------------------------------------------------------
  * Steady state of pure diffusion (no reactions, no Robin) with the Dirichlet data
  * held in u: the discrete Laplace problem on the free voxels,

@@ -177,3 +177,25 @@ def test_sink_in_the_step_balance(oracle_mod):
     act = (img != 0) & (mask != 0)
     act[:, :, 0] = False  # Dirichlet plane
     assert uptake - no_sink.balance(c0, 0)[2] == pytest.approx(0.15 * c0[0][act].sum(), rel=1e-12)
+
+
+def test_plane_flux_with_factor(oracle_mod):
+    """At the series-conductance steady state every plane carries the through-flux; a
+    unit factor gives the constant-D flux."""
+    n, ny, nz = 17, 3, 2
+    rng = np.random.default_rng(30)
+    ex = rng.uniform(0.1, 2.0, size=n)
+    eps = np.broadcast_to(ex, (nz, ny, n)).copy()
+    img = np.ones((nz, ny, n), dtype=np.uint8)
+    D = 0.6
+    prob = oracle_mod.Problem(img, [D], dirichlet={(0, 0): 1.0, (0, 1): 0.0}, eps=eps)
+    cs, J = _series_steady(D * 0.5 * (ex[:-1] + ex[1:]))
+    u = np.broadcast_to(cs, (nz, ny, n)).copy()
+    for i0 in range(n - 1):
+        assert prob.plane_flux(u, D, 0, i0) == pytest.approx(J * ny * nz, rel=1e-12)
+    img2, _ = _random_box(31)
+    u2 = np.random.default_rng(31).random(img2.shape)
+    p1 = oracle_mod.Problem(img2, [0.7], eps=np.ones(img2.shape))
+    p0 = oracle_mod.Problem(img2, [0.7])
+    for axis in range(3):
+        assert p1.plane_flux(u2, 0.7, axis, 4) == pytest.approx(p0.plane_flux(u2, 0.7, axis, 4), rel=1e-14)
