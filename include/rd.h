@@ -189,7 +189,8 @@ rd_status rd_sim_set_field(rd_sim *sim, int species, const float *dev_dense);
  * workspace (bind with RD_WS_DIFFUSIVITY); the caller keeps ownership.  Synchronises.
  * Afterwards rd_sim_step and rd_sim_balance (Dirichlet inflow with the mean
  * coefficient) use the factor and the stability bound uses D_max * max(e);
- * rd_sim_steady_state, rd_sim_plane_flux and rd_sim_adjoint return RD_ERR_STATE until
+ * rd_sim_plane_flux (the mean coefficient on each straddling pair) and rd_sim_adjoint (see
+ * rd_sim_adjoint_factor) use it too; rd_sim_steady_state returns RD_ERR_STATE until
  * rd_sim_clear_diffusivity.  Errors: RD_ERR_WORKSPACE without the feature,
  * RD_ERR_STATE before bind, RD_ERR_ARG for a NULL pointer or for invalid values (the
  * factor is then cleared).  A new bind clears the factor. */

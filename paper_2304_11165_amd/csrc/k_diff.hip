@@ -406,6 +406,45 @@ __global__ __launch_bounds__(256) void k_reduce_diff(ReduceArgs a, const float *
     }
 }
 
+// Flux through the plane i0 | i0 + 1 along axis with the mean face coefficient.  Rows as
+// in k_reduce_diff; blocks that do not hold plane i0 return at once.
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_plane_flux_diff(const BlockInfo *info, const uint8_t *code, const T *c,
+                                                         const float *e, int nb, int axis, int i0, double D,
+                                                         double dx, double *partial)
+{
+    using C = Cfg<B>;
+    constexpr int NS = B * B * B;
+    __shared__ double wsum[4];
+    const int sub = threadIdx.x / C::TPB, lt = threadIdx.x % C::TPB;
+    const int b = blockIdx.x * C::BPW + sub;
+    double acc = 0.0;
+    if (b < nb) {
+        const BlockInfo bi = info[b];
+        int bx, by, bz, gid;
+        block_pos(bi, &bx, &by, &bz, &gid);
+        const int o = (axis == 0 ? bx : axis == 1 ? by : bz) * B;
+        if (i0 >= o && i0 < o + B) {
+            const int l0 = i0 - o;
+            for (int k = 0; k < C::VPT; ++k) {
+                const int slot = lt + k * C::TPB;
+                const int lx = slot % B, ly = (slot / B) % B, lz = slot / (B * B);
+                if ((axis == 0 ? lx : axis == 1 ? ly : lz) != l0) continue;
+                const int64_t i = (int64_t)b * NS + slot;
+                const unsigned cd = code[i];
+                if (!(cd & 64u) || !((cd >> (2 * axis + 1)) & 1u)) continue;
+                const int64_t q = nbr_slot<B>(bi, b, lx, ly, lz, 2 * axis + 1);
+                const double w = 0.5 * ((double)e[i] + (double)e[q]);
+                acc += D * w * ((double)rd_ld(c, i) - (double)rd_ld(c, q)) * dx;
+            }
+        }
+    }
+    const double v = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+}
+
 // Band marking, one thread per slot.
 template <int B>
 __global__ __launch_bounds__(256) void k_set_band(const BlockInfo *info, uint8_t *code, const GeomInfo *geom,
@@ -523,5 +562,28 @@ int rd_launch_set_band(int B, const BlockInfo *info, uint8_t *code, const GeomIn
         hipLaunchKernelGGL((k_set_band<8>), grid, dim3(256), 0, st, info, code, geom, nb, phi, band, count);
     else
         hipLaunchKernelGGL((k_set_band<4>), grid, dim3(256), 0, st, info, code, geom, nb, phi, band, count);
+    return (int)hipGetLastError();
+}
+
+int rd_launch_plane_flux_diff(int storage, int B, const BlockInfo *info, const uint8_t *code, const void *c,
+                              const float *e, int nb, int axis, int i0, double D, double dx, double *partial,
+                              void *stream)
+{
+    if (nb <= 0) return 0;
+    hipStream_t st = (hipStream_t)stream;
+    const dim3 grid((unsigned)rd_diff_reduce_rows(B, nb));
+#define RD_PF(T, BB) \
+    hipLaunchKernelGGL((k_plane_flux_diff<T, BB>), grid, dim3(256), 0, st, info, code, (const T *)c, e, nb, axis, i0, \
+                       D, dx, partial)
+    if (B == 8) {
+        if (storage == 0) RD_PF(float, 8);
+        else if (storage == 1) RD_PF(bf16_t, 8);
+        else RD_PF(_Float16, 8);
+    } else {
+        if (storage == 0) RD_PF(float, 4);
+        else if (storage == 1) RD_PF(bf16_t, 4);
+        else RD_PF(_Float16, 4);
+    }
+#undef RD_PF
     return (int)hipGetLastError();
 }

@@ -777,7 +777,6 @@ extern "C" rd_status rd_sim_plane_flux(rd_sim *sim, int species, int axis, int64
     if (!sim->ws) return rd_fail(RD_ERR_STATE, "bind a workspace first");
     if (species < 0 || species >= sim->S) return rd_fail(RD_ERR_ARG, "bad species");
     if (axis < 0 || axis > 2) return rd_fail(RD_ERR_ARG, "axis must be 0, 1 or 2");
-    if (sim->diff_on) return rd_fail(RD_ERR_STATE, "plane flux needs a homogeneous D (clear the factor)");
     const rd_geometry &G = *sim->g;
     const int64_t n = axis == 0 ? G.nx : axis == 1 ? G.ny : G.nz;
     if (i0 < 0 || i0 + 1 >= n)
@@ -788,11 +787,20 @@ extern "C" rd_status rd_sim_plane_flux(rd_sim *sim, int species, int axis, int64
     double *part = (double *)(ws + L.part);
     double *res = (double *)(ws + L.res) + 32;
     hipStream_t stream = sim->stream;
-    LAUNCHCHK(rd_launch_plane_flux((int)sim->storage, G.B, (const BlockInfo *)(ws + L.info),
-                                   (const uint8_t *)(ws + L.code), sim->field_ptr(sim->cur, species), nb,
-                                   axis, (int)i0, sim->D[species], G.dx, part, stream));
-    LAUNCHCHK(rd_launch_finish_reduce(part, rd_reduce_rows(G.B, nb), 1, (double *)(ws + L.mid), res,
-                                      stream));
+    if (sim->diff_on) {  // mean face coefficient D (e_p + e_q) / 2
+        LAUNCHCHK(rd_launch_plane_flux_diff((int)sim->storage, G.B, (const BlockInfo *)(ws + L.info),
+                                            (const uint8_t *)(ws + L.code), sim->field_ptr(sim->cur, species),
+                                            (const float *)(ws + L.diff), nb, axis, (int)i0, sim->D[species],
+                                            G.dx, part, stream));
+        LAUNCHCHK(rd_launch_finish_reduce(part, rd_diff_reduce_rows(G.B, nb), 1, (double *)(ws + L.mid), res,
+                                          stream));
+    } else {
+        LAUNCHCHK(rd_launch_plane_flux((int)sim->storage, G.B, (const BlockInfo *)(ws + L.info),
+                                       (const uint8_t *)(ws + L.code), sim->field_ptr(sim->cur, species), nb,
+                                       axis, (int)i0, sim->D[species], G.dx, part, stream));
+        LAUNCHCHK(rd_launch_finish_reduce(part, rd_reduce_rows(G.B, nb), 1, (double *)(ws + L.mid), res,
+                                          stream));
+    }
     double h = 0.0;
     HIPCHK(hipMemcpyAsync(&h, res, sizeof(double), hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));

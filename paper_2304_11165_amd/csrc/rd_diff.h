@@ -41,6 +41,12 @@ int rd_diff_reduce_rows(int B, int nb);
 int rd_launch_reduce_diff(int storage, int B, const ReduceArgs &a, const float *e, double ksink,
                           void *stream);
 
+// One FP64 partial per rd_diff_reduce_rows row: D sum over active pairs straddling the
+// plane i0 | i0 + 1 along axis of (e_p + e_q) / 2 (c_p - c_q) dx.
+int rd_launch_plane_flux_diff(int storage, int B, const BlockInfo *info, const uint8_t *code, const void *c,
+                              const float *e, int nb, int axis, int i0, double D, double dx, double *partial,
+                              void *stream);
+
 // Mark the band: bit 7 of the code byte of active slots set where phi < band, cleared
 // elsewhere; count (one uint32, cleared here) receives the number of band slots.
 int rd_launch_set_band(int B, const BlockInfo *info, uint8_t *code, const GeomInfo *geom, int nb,

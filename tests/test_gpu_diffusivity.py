@@ -82,6 +82,13 @@ def test_parity_with_oracle(rd, oracle_mod, B, kernel):
         assert b["uptake"] == pytest.approx(up, rel=1e-10, abs=1e-12)
         assert b["react"] == pytest.approx(re, rel=1e-10, abs=1e-12)
     assert s.balance(0)["inflow"][0] != 0.0
+    # plane fluxes with the mean face coefficient, on and off block boundaries
+    for axis, n in ((0, img.shape[2]), (1, img.shape[1]), (2, img.shape[0])):
+        for i0 in (0, 3, 7, 8, 15, n - 2):
+            for sp in range(2):
+                want = prob.plane_flux(got[sp], CASE["D"][sp], axis, i0)
+                assert s.plane_flux(sp, axis, i0) == pytest.approx(want, rel=1e-10, abs=1e-13), \
+                    (B, axis, i0, sp)
 
 
 @pytest.mark.parametrize("storage,sround", [("fp32", False), ("bf16", True), ("fp16", False)])
@@ -162,9 +169,6 @@ def test_stability_bound_and_errors(rd):
         s.step(0.15, 1)  # the bound is now 1/12
     assert ex.value.name == "RD_ERR_UNSTABLE_DT"
     s.step(0.08, 1)
-    with pytest.raises(rd.RDError) as ex:
-        s.plane_flux(0, 0, 3)
-    assert ex.value.name == "RD_ERR_STATE"
     e[1, 2, 3] = -1.0
     with pytest.raises(rd.RDError) as ex:
         s.set_diffusivity(e)
