@@ -339,7 +339,7 @@ def diffusivity_form(torch, rd, np, geom, img, w, n_active, steps, graph_steps, 
         sdf_ms = e0.elapsed_time(e1)
         log(f"diffusivity: signed distance of the {img.shape[0]}^3 image on the GPU in {sdf_ms:.1f} ms")
         sim = build_sim(rd, geom, w, "fp32", graph_steps, use_graph)
-        sim.set_kernel("column")
+        sim.set_kernel("column_xch")
         sim.bind(features=rd.RD_WS_DIFFUSIVITY, stream=stream)
         sim.set_diffusivity_sdf(phi, *DIFF_PARS)
         del phi, dimg
@@ -349,7 +349,7 @@ def diffusivity_form(torch, rd, np, geom, img, w, n_active, steps, graph_steps, 
     per = secs / steps
     alg = (2 * 4 * S + 4) * n_active
     res = {
-        "kernel": f"k_step8e<float,{S}>",
+        "kernel": f"k_step8e<float,{S},true>",
         "diffusivity": "e = %g + %g / (1 + exp(-(%g + %g phi))), phi = distance to the wall - 1/2"
                        % DIFF_PARS,
         "sdf_ms": sdf_ms,

@@ -145,21 +145,29 @@ __device__ __forceinline__ int pix(int x, int y) { return (y + 1) * 10 + (x + 1)
 // walking z.  Loads are predicated on the activity of the slot they read (inactive
 // slots give 0); plane z of every species and of the factor goes to LDS with its
 // four side halos, the z neighbours stay in registers.  Whole 128-byte sectors that
-// hold an active voxel are stored.
-template <typename T, int S>
+// hold an active voxel are stored.  XCH: the x faces of x-adjacent blocks of one
+// workgroup are handed over through LDS instead of being read again.
+template <typename T, int S, bool XCH>
 __global__ __launch_bounds__(256) void k_step8e(DiffArgs d)
 {
     __shared__ float tile[4][S + 1][100];  // species tiles, then the factor's
+    __shared__ float xch[XCH ? 4 : 1][2][S + 1][64];  // x = 0 / x = 7 planes, [z * 8 + y]
     const StepArgs &a = d.s;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int grp = map_group(blockIdx.x, a.xcd_chunk);
     const int b = __builtin_amdgcn_readfirstlane(grp * 4 + wv);
-    if (b >= a.nb) return;
+    if (b >= a.nb) {  // past the end of the list (with XCH: after the one barrier)
+        if (XCH) __syncthreads();
+        return;
+    }
     const T *cin = (const T *)a.cin;
     T *cout = (T *)a.cout;
     const int64_t base = (int64_t)b * 512;
     const int lx = lane & 7, ly = lane >> 3;
     const int32_t *nbr = a.info[b].nbr;
+    // x neighbours inside this workgroup (wave-uniform; only with XCH)
+    const bool xm_in = XCH && wv > 0 && nbr[0] == b - 1;
+    const bool xp_in = XCH && wv < 3 && nbr[1] == b + 1;
     const uint64_t *rec = a.mask + (int64_t)b * 16;
     uint64_t Wo[8], Wf[6];
 #pragma unroll
@@ -202,7 +210,7 @@ __global__ __launch_bounds__(256) void k_step8e(DiffArgs d)
 #pragma unroll
         for (int s = 0; s < S; ++s) rh[f][s] = (R)0;
         eh[f] = 0.0f;
-        if (lane_bit(Wf[f])) {
+        if (lane_bit((f == 0 && xm_in) || (f == 1 && xp_in) ? 0ull : Wf[f])) {
 #pragma unroll
             for (int s = 0; s < S; ++s) rh[f][s] = ld_raw(cin, s * a.sstride + hb);
             eh[f] = d.e[hb];
@@ -217,6 +225,28 @@ __global__ __launch_bounds__(256) void k_step8e(DiffArgs d)
         for (int f = 0; f < 4; ++f) side[f][s] = from_raw<T>(rh[f][s]);
         zlo[s] = from_raw<T>(rh[4][s]);
         zhi[s] = from_raw<T>(rh[5][s]);
+    }
+    // hand the x = 0 / x = 7 planes (species and factor) to the x neighbours of this
+    // workgroup; inactive slots are 0 already, as a predicated halo load would give
+    if (XCH) {
+        if (lx == 0 || lx == 7) {
+            const int side_ = lx == 7 ? 1 : 0;
+#pragma unroll
+            for (int z = 0; z < 8; ++z) {
+#pragma unroll
+                for (int s = 0; s < S; ++s) xch[wv][side_][s][z * 8 + ly] = c[s][z];
+                xch[wv][side_][S][z * 8 + ly] = ec[z];
+            }
+        }
+        __syncthreads();
+        // face coordinates (u, v) = (lx, ly) of an x face are (y, z)
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (xm_in) side[0][s] = xch[wv - 1][1][s][ly * 8 + lx];
+            if (xp_in) side[1][s] = xch[wv + 1][0][s][ly * 8 + lx];
+        }
+        if (xm_in) eh[0] = xch[wv - 1][1][S][ly * 8 + lx];
+        if (xp_in) eh[1] = xch[wv + 1][0][S][ly * 8 + lx];
     }
 
     const BlockInfo bi = a.info[b];
@@ -475,7 +505,8 @@ void launch_diff_s(const DiffArgs &a, int column, hipStream_t st)
     if (B == 8 && column) {
         int groups = (a.s.nb + 3) / 4;
         if (a.s.xcd_chunk > 0) groups = 8 * a.s.xcd_chunk;
-        hipLaunchKernelGGL((k_step8e<T, S>), dim3(groups), dim3(256), 0, st, a);
+        if (column == 2) hipLaunchKernelGGL((k_step8e<T, S, true>), dim3(groups), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_step8e<T, S, false>), dim3(groups), dim3(256), 0, st, a);
     } else {
         const int64_t n = (int64_t)a.s.nb * B * B * B;
         hipLaunchKernelGGL((k_step_diff<T, B, S>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);

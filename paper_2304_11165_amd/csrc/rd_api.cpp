@@ -473,9 +473,10 @@ rd_status rd_sim::launch_steps(double dt, int64_t n)
         a.ctr = step_counter();
         a.ctr_off = (uint32_t)i;
         if (diff_path()) {
-            // B = 8: the column kernel unless the workgroup-per-block kernel is chosen
-            // (then one thread per slot); B = 4: one thread per slot
-            const int column = g->B == 8 && kernel != 0 ? 1 : 0;
+            // B = 8: the column kernel (with the x-face exchange when kernel 3 is chosen)
+            // unless the workgroup-per-block kernel is chosen (then one thread per slot);
+            // B = 4: one thread per slot
+            const int column = g->B == 8 && kernel != 0 ? (kernel == 3 ? 2 : 1) : 0;
             const int groups = (a.nb + 3) / 4;
             a.xcd_chunk = column && xcd_map && groups >= 64 ? (groups + 7) / 8 : 0;
             DiffArgs da{a, (const float *)(ws + L.diff), {0.0f, 0.0f, 0.0f, 0.0f}};

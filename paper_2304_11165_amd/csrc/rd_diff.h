@@ -21,7 +21,8 @@ struct DiffArgs {
 };
 
 // One step with the factor.  column = 1 (B = 8 only): one wave per block walking
-// z-columns; column = 0: one thread per slot.  Both give bitwise-identical results.
+// z-columns; column = 2: the same with the x faces of x-adjacent blocks of a workgroup
+// handed over through LDS; column = 0: one thread per slot.  All give the same bits.
 int rd_launch_step_diff(int storage, int B, const DiffArgs &a, int column, void *stream);
 
 // Fill e from a dense float32 (nz, ny, nx) device array: mode 0 copies the values,

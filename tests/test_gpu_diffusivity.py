@@ -93,13 +93,15 @@ def test_parity_with_oracle(rd, oracle_mod, B, kernel):
 
 @pytest.mark.parametrize("storage,sround", [("fp32", False), ("bf16", True), ("fp16", False)])
 def test_kernels_agree_bitwise(rd, oracle_mod, storage, sround):
-    """B = 8 column kernel == one thread per slot, graph replay == direct launches."""
+    """B = 8 column kernel == with the x-face exchange == one thread per slot, graph replay ==
+    direct launches."""
     img, eps = _problem(seed=9, shape=(27, 21, 34))
     rng = np.random.default_rng(9)
     init = rng.uniform(0, 1, (2,) + img.shape)
     dt = 0.05
     outs = []
-    for kernel, graph in (("column", True), ("block", False), ("column", False)):
+    for kernel, graph in (("column", True), ("block", False), ("column", False), ("column_xch", True),
+                          ("column_xch", False)):
         got, _, _, _ = _run(rd, oracle_mod, img, eps, CASE["D"], dt, 70, 8, kernel, storage=storage,
                             robin=CASE["robin"], dirichlet=CASE["dirichlet"],
                             reactions=CASE["reactions"], init=init, graph=graph, sround=sround)

@@ -49,7 +49,7 @@ def _sim(rd, w, g, phi, kernel):
 
 def test_full_size_balance(setup):
     rd, w, img, g, phi = setup
-    s = _sim(rd, w, g, phi, "column")
+    s = _sim(rd, w, g, phi, "column_xch")
     s.step(w.dt, 500)
     before = [s.balance(sp) for sp in range(2)]
     s.step(w.dt, 1)
@@ -67,10 +67,11 @@ def test_full_size_balance(setup):
 def test_full_size_kernels_agree(setup):
     rd, w, img, g, phi = setup
     outs = []
-    for kernel in ("column", "block"):
+    for kernel in ("column_xch", "column", "block"):
         s = _sim(rd, w, g, phi, kernel)
         s.step(w.dt, 40)
         outs.append([s.get_field(sp).cpu().numpy() for sp in range(2)])
         del s
-    for sp in range(2):
-        assert np.array_equal(outs[0][sp], outs[1][sp])
+    for o in outs[1:]:
+        for sp in range(2):
+            assert np.array_equal(outs[0][sp], o[sp])
