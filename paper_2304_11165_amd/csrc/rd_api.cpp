@@ -339,20 +339,23 @@ rd_sim::~rd_sim()
     if (host_res) hipHostFree(host_res);
 }
 
-rd_status rd_sim::upload()
+rd_status rd_sim::upload(bool index)
 {
     const rd_geometry &G = *g;
     const int64_t nb = G.nb();
-    int dev = 0, ncu = 0;
-    HIPCHK(hipGetDevice(&dev));
-    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    if (ncu > 0) n_cu = ncu;
-    HIPCHK(hipMemcpyAsync(ws + L.info, G.info.data(), sizeof(BlockInfo) * nb, hipMemcpyHostToDevice, stream));
-    HIPCHK(hipMemcpyAsync(ws + L.mask, G.mask.data(), 8 * mask_words(G.B) * nb, hipMemcpyHostToDevice, stream));
-    HIPCHK(hipMemcpyAsync(ws + L.code, G.code.data(), G.code.size(), hipMemcpyHostToDevice, stream));
-    GeomInfo gi{(int32_t)G.nx, (int32_t)G.ny, (int32_t)G.nz, 0};
-    geom_host = gi;
-    HIPCHK(hipMemcpyAsync(ws + L.geom, &geom_host, sizeof(GeomInfo), hipMemcpyHostToDevice, stream));
+    if (index) {
+        int dev = 0, ncu = 0;
+        HIPCHK(hipGetDevice(&dev));
+        HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        if (ncu > 0) n_cu = ncu;
+        HIPCHK(hipMemcpyAsync(ws + L.info, G.info.data(), sizeof(BlockInfo) * nb, hipMemcpyHostToDevice, stream));
+        HIPCHK(hipMemcpyAsync(ws + L.mask, G.mask.data(), 8 * mask_words(G.B) * nb, hipMemcpyHostToDevice,
+                              stream));
+        HIPCHK(hipMemcpyAsync(ws + L.code, G.code.data(), G.code.size(), hipMemcpyHostToDevice, stream));
+        GeomInfo gi{(int32_t)G.nx, (int32_t)G.ny, (int32_t)G.nz, 0};
+        geom_host = gi;
+        HIPCHK(hipMemcpyAsync(ws + L.geom, &geom_host, sizeof(GeomInfo), hipMemcpyHostToDevice, stream));
+    }
     const size_t es = storage == RD_FP32 ? 4 : 2;
     for (int p = 0; p < 2; ++p)
         LAUNCHCHK(rd_launch_fill_u32(ws + L.field[p], 0u, (int64_t)(es * L.field_elems * S / 4), stream));
@@ -890,7 +893,7 @@ extern "C" rd_status rd_sim_autotune(rd_sim *sim, double dt, int64_t trial_steps
     sim->invalidate_graphs();
     if (best_ms) *best_ms = best;
     // the trials advanced the fields: start again from zero + Dirichlet values
-    return sim->upload();
+    return sim->upload(false);  // reset the fields, keep the index and any band marks
 }
 
 namespace {

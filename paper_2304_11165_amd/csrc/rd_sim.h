@@ -95,7 +95,9 @@ struct rd_sim {
 
     ~rd_sim();
     void invalidate_graphs();
-    rd_status upload();
+    // index = true: copy the block index, masks and codes too (bind); false: only reset
+    // the fields and counters (the codes keep any sink-band marks)
+    rd_status upload(bool index = true);
     rd_status apply_dirichlet(int s);
     void *field_ptr(int buf, int s) const;
     StepArgs step_args(double dt, int in_buf) const;

@@ -286,3 +286,27 @@ def test_sink_band_kernels_agree_and_clear(rd, oracle_mod):
     assert np.array_equal(fields(s, 1), fields(p, 1))
     with pytest.raises(rd.RDError):
         s.set_sink(0, -1.0)
+
+
+def test_autotune_keeps_factor_and_band(rd, oracle_mod):
+    """The autotuner times the factor kernels, resets the fields only (the factor and the
+    band marks stay), and its choice gives the bits of the default launch."""
+    img, eps = _problem(seed=51, shape=(30, 34, 37))
+    phi = oracle_mod.signed_distance(img, 1.0)
+    rng = np.random.default_rng(51)
+    c0 = (rng.uniform(0, 1, img.shape) * (img != 0)).astype(np.float32)
+    outs = []
+    for tune, band in ((False, 1.0), (True, 1.0), (False, 0.0)):
+        _, s = make_gpu(rd, img, [1.0], dirichlet={(0, 0): 1.0}, kernel="column",
+                        features=rd.RD_WS_DIFFUSIVITY)
+        s.set_diffusivity(eps.astype(np.float32))
+        s.set_sink(0, 0.2)
+        s.set_sink_band(phi, band)
+        if tune:
+            s.autotune(0.04, 30)
+            assert s.steps_taken() == 0
+        s.set_field(0, c0)
+        s.step(0.04, 100)
+        outs.append(fields(s, 1))
+    assert np.array_equal(outs[0], outs[1])
+    assert not np.array_equal(outs[0], outs[2])  # the band's sink acts
