@@ -374,11 +374,15 @@ __global__ __launch_bounds__(256) void k_reduce_diff(ReduceArgs a, const float *
     const int sub = threadIdx.x / C::TPB, lt = threadIdx.x % C::TPB;
     const int b = blockIdx.x * C::BPW + sub;
     const T *c = (const T *)a.c;
+    bool dblock = false;  // the block touches a Dirichlet face of the species (wave-uniform)
     if (b < a.nb) {
         const BlockInfo bi = a.info[b];
         int bx, by, bz, gid;
         block_pos(bi, &bx, &by, &bz, &gid);
         const GeomInfo g = a.geom[gid];
+        const bool at[6] = {bx == 0, bx * B + B >= g.nx, by == 0, by * B + B >= g.ny, bz == 0,
+                            bz * B + B >= g.nz};
+        for (int f = 0; f < 6; ++f) dblock = dblock || (((a.dir >> f) & 1u) && at[f]);
         const double dx = a.dx, dx2 = dx * dx, dx3 = dx2 * dx;
         const T *cs = c + a.s * a.sstride;
         for (int k = 0; k < C::VPT; ++k) {
@@ -423,10 +427,15 @@ __global__ __launch_bounds__(256) void k_reduce_diff(ReduceArgs a, const float *
             acc[8] += re * dx3;
         }
     }
+    // wave sums of the lanes that can be nonzero (the others are 0 in every lane)
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    bool hasreact = a.rate_out != 0.0;
+    for (int s2 = 0; s2 < a.S; ++s2) hasreact = hasreact || a.rate_in[s2] != 0.0;
 #pragma unroll
     for (int l = 0; l < RD_NRED; ++l) {
-        const double v = wave_sum(acc[l]);
+        const bool need = l == 0 || l == 9 || (l <= 6 && dblock) || (l == 7 && (a.kR != 0.0 || ksink != 0.0)) ||
+                          (l == 8 && hasreact);
+        const double v = need ? wave_sum(acc[l]) : 0.0;
         if (lane == 0) wsum[wave][l] = v;
     }
     __syncthreads();
