@@ -607,5 +607,7 @@ def sdf_from_image(image, dx=1.0, stream=None):
     _check(_lib.rd_sdf_from_image(ctypes.c_void_p(img.data_ptr()), nx, ny, nz, float(dx),
                                   ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(scratch.data_ptr()),
                                   scratch.numel(), _stream_handle(st)), "rd_sdf_from_image")
-    out._rd_keep = (img, scratch)  # held until the caller drops the result
+    # the allocator must not hand these out again before the stream has used them
+    for t in (img, scratch, out):
+        t.record_stream(st)
     return out
