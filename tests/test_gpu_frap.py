@@ -96,3 +96,24 @@ def test_frap_tortuosity_end_to_end(rd, oracle_mod):
     print(f"FRAP D_eff gpu {d_gpu:.6f} oracle {d_ora:.6f} tau {1 / d_gpu:.4f} rms {rms:.2e}")
     assert d_gpu == pytest.approx(d_ora, rel=1e-4)
     assert 0.2 < d_gpu < 1.0
+
+
+def test_frap_curve_with_factor_and_sink(rd, oracle_mod):
+    """FRAP recovery with the smooth D(phi) factor and a sink band (the paper's two
+    application examples' ingredients) against the oracle."""
+    img = _geom(seed=17, shape=(28, 30, 26))
+    reg = (9, 17, 10, 20, 8, 18)
+    c0 = _bleached(img, reg)
+    phi = oracle_mod.signed_distance(img, 1.0)
+    eps = oracle_mod.smooth_diffusivity(phi.astype(np.float64), 0.1, 0.9, -6.0, 4.0).astype(np.float32)
+    band = (img != 0) & (phi < 1.0)
+    _, s = make_gpu(rd, img, [1.0], kernel="column", features=rd.RD_WS_DIFFUSIVITY)
+    s.set_diffusivity(eps)
+    s.set_sink(0, 0.01)
+    assert s.set_sink_band(phi, 1.0) == int(band.sum())
+    s.set_field(0, c0.astype(np.float32))
+    got = s.frap_curve(0, reg, 0.1, 10, 25)
+    prob = oracle_mod.Problem(img, [1.0], eps=eps.astype(np.float64), sink={0: 0.01},
+                              sink_mask=band.astype(np.uint8))
+    ref = oracle_mod.frap_curve(prob, c0[None], reg, 0.1, 10, 25)
+    np.testing.assert_allclose(got, ref, rtol=1e-5, atol=1e-6)
