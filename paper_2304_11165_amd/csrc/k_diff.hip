@@ -321,9 +321,10 @@ __global__ __launch_bounds__(256) void k_step8e(DiffArgs d)
     }
 }
 
-// e from a dense (nz, ny, nx) array, one thread per slot.  stats[0] counts active
-// slots with a negative or non-finite value, stats[1] holds the largest valid value
-// (FP32 bits; non-negative values order like their bit patterns).
+// e from a dense (nz, ny, nx) array, a grid-stride loop over the slots.  stats[0]
+// counts active slots with a negative or non-finite value, stats[1] holds the largest
+// valid value (FP32 bits; non-negative values order like their bit patterns).  The
+// counts are reduced per workgroup first: one pair of atomics per workgroup.
 template <int B>
 __global__ __launch_bounds__(256) void k_set_diff(const BlockInfo *info, const uint8_t *code,
                                                   const GeomInfo *geom, int nb, const float *dense,
@@ -331,13 +332,14 @@ __global__ __launch_bounds__(256) void k_set_diff(const BlockInfo *info, const u
                                                   double g2, float *e, uint32_t *stats)
 {
     constexpr int NS = B * B * B;
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    bool bad = false;
-    uint32_t mx = 0u;
-    if (i < (int64_t)nb * NS) {
-        const int b = (int)(i / NS), slot = (int)(i % NS);
+    __shared__ uint32_t wbad[4], wmx[4];
+    uint32_t nbad = 0u, mx = 0u;
+    const int64_t n = (int64_t)nb * NS;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         float v = 0.0f;
+        bool bad = false;
         if (code[i] & 64u) {
+            const int b = (int)(i / NS), slot = (int)(i % NS);
             int bx, by, bz, gid;
             block_pos(info[b], &bx, &by, &bz, &gid);
             const GeomInfo g = geom[gid];
@@ -345,16 +347,26 @@ __global__ __launch_bounds__(256) void k_set_diff(const BlockInfo *info, const u
             const float x = mode == 2 ? 1.0f : dense[voxel_id(g, gx, gy, gz)];
             v = mode != 1 ? x : (float)(d_min + d_max / (1.0 + exp(-(g1 + g2 * (double)x))));
             bad = !(v >= 0.0f) || !isfinite(v);
-            if (!bad) mx = __float_as_uint(v);
+            if (!bad) mx = max(mx, __float_as_uint(v));
+            nbad += bad ? 1u : 0u;
         }
         e[i] = bad ? 0.0f : v;
     }
-    const uint64_t badm = __ballot(bad);
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+    for (int o = 32; o > 0; o >>= 1) {
+        mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+        nbad += (uint32_t)__shfl_xor((int)nbad, o, 64);
+    }
     if ((threadIdx.x & 63) == 0) {
-        if (badm) atomicAdd(&stats[0], (uint32_t)__popcll(badm));
-        if (mx) atomicMax(&stats[1], mx);
+        wbad[threadIdx.x >> 6] = nbad;
+        wmx[threadIdx.x >> 6] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t tb = wbad[0] + wbad[1] + wbad[2] + wbad[3];
+        const uint32_t tm = max(max(wmx[0], wmx[1]), max(wmx[2], wmx[3]));
+        if (tb) atomicAdd(&stats[0], tb);
+        if (tm) atomicMax(&stats[1], tm);
     }
 }
 
@@ -568,7 +580,8 @@ int rd_launch_set_diff(int B, const BlockInfo *info, const uint8_t *code, const 
     int rc = rd_launch_fill_u32(stats, 0u, 2, stream);
     if (rc != 0 || nb <= 0) return rc;
     const int64_t n = (int64_t)nb * B * B * B;
-    const dim3 grid((unsigned)((n + 255) / 256));
+    const int64_t blocks = (n + 255) / 256;
+    const dim3 grid((unsigned)(blocks < 4096 ? blocks : 4096));  // grid-stride
     if (B == 8)
         hipLaunchKernelGGL((k_set_diff<8>), grid, dim3(256), 0, st, info, code, geom, nb, dense, mode, d_min,
                            d_max, g1, g2, e, stats);
