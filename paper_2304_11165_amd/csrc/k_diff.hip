@@ -496,15 +496,16 @@ __global__ __launch_bounds__(256) void k_plane_flux_diff(const BlockInfo *info, 
     if (threadIdx.x == 0) partial[blockIdx.x] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
 }
 
-// Band marking, one thread per slot.
+// Band marking, a grid-stride loop over the slots; one atomic per workgroup.
 template <int B>
 __global__ __launch_bounds__(256) void k_set_band(const BlockInfo *info, uint8_t *code, const GeomInfo *geom,
                                                   int nb, const float *phi, double band, uint32_t *count)
 {
     constexpr int NS = B * B * B;
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    bool in = false;
-    if (i < (int64_t)nb * NS) {
+    __shared__ uint32_t wn[4];
+    uint32_t cnt = 0u;
+    const int64_t n = (int64_t)nb * NS;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const unsigned c = code[i];
         if (c & 64u) {
             const int b = (int)(i / NS), slot = (int)(i % NS);
@@ -512,12 +513,19 @@ __global__ __launch_bounds__(256) void k_set_band(const BlockInfo *info, uint8_t
             block_pos(info[b], &bx, &by, &bz, &gid);
             const GeomInfo g = geom[gid];
             const int gx = bx * B + slot % B, gy = by * B + (slot / B) % B, gz = bz * B + slot / (B * B);
-            in = (double)phi[voxel_id(g, gx, gy, gz)] < band;
+            const bool in = (double)phi[voxel_id(g, gx, gy, gz)] < band;
             code[i] = (uint8_t)((c & 0x7fu) | (in ? RD_CODE_BAND : 0u));
+            cnt += in ? 1u : 0u;
         }
     }
-    const uint64_t m = __ballot(in);
-    if ((threadIdx.x & 63) == 0 && m) atomicAdd(count, (uint32_t)__popcll(m));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) cnt += (uint32_t)__shfl_xor((int)cnt, o, 64);
+    if ((threadIdx.x & 63) == 0) wn[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t t = wn[0] + wn[1] + wn[2] + wn[3];
+        if (t) atomicAdd(count, t);
+    }
 }
 
 template <typename T, int B, int S>
@@ -610,7 +618,8 @@ int rd_launch_set_band(int B, const BlockInfo *info, uint8_t *code, const GeomIn
     int rc = rd_launch_fill_u32(count, 0u, 1, stream);
     if (rc != 0 || nb <= 0) return rc;
     const int64_t n = (int64_t)nb * B * B * B;
-    const dim3 grid((unsigned)((n + 255) / 256));
+    const int64_t blocks = (n + 255) / 256;
+    const dim3 grid((unsigned)(blocks < 4096 ? blocks : 4096));  // grid-stride
     if (B == 8)
         hipLaunchKernelGGL((k_set_band<8>), grid, dim3(256), 0, st, info, code, geom, nb, phi, band, count);
     else
