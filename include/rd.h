@@ -304,7 +304,9 @@ rd_status rd_sim_steady_state(rd_sim *sim, int axis, double rel_tol, int64_t max
  * dL/dk = -sum_n dt <lambda^{n+1}, c^n>, accumulated in FP64.  States are
  * checkpointed every `checkpoint_every` = k steps and recomputed per segment:
  * needs RD_WS_ADJOINT with checkpoint_slots >= ceil(n_steps / k) + k - 1, and
- * round-to-nearest storage.  On return species 0 holds c^N. */
+ * round-to-nearest storage.  With a diffusivity factor set, L is the factor-weighted
+ * Laplacian (face coefficient (e_p + e_q) / 2) in both the recursion and dL/dD; an
+ * active sink band (nonzero rate) gives RD_ERR_STATE.  On return species 0 holds c^N. */
 rd_status rd_sim_adjoint(rd_sim *sim, const float *dev_seed, int seed_mode, int64_t n_steps,
                          double dt, int checkpoint_every, double *loss, double *dL_dD,
                          double *dL_drate);
