@@ -181,3 +181,42 @@ def test_storage_halves_field_bytes(rd):
 def test_status_strings(rd):
     for i, name in enumerate(rd.STATUS):
         assert rd._lib.rd_status_string(i).decode()
+
+
+def test_new_entry_points_validate_without_gpu(rd):
+    """Argument and ordering checks of the diffusivity, sink, FRAP and distance-transform
+    entry points run on the host and fail cleanly before any GPU work."""
+    import ctypes
+
+    g = rd.Geometry(np.ones((8, 8, 8), np.uint8), None, 1.0, 8)
+    s = rd.Sim(g, "fp32")
+    s.add_species(1.0)
+    base = s.workspace_bytes()
+    # the factor adds 4 bytes per slot (+ counters); with the adjoint, dL/de adds 8
+    assert s.workspace_bytes(features=rd.RD_WS_DIFFUSIVITY) >= base + 4 * 512
+    assert (s.workspace_bytes(features=rd.RD_WS_DIFFUSIVITY | rd.RD_WS_ADJOINT, checkpoint_slots=4) -
+            s.workspace_bytes(features=rd.RD_WS_ADJOINT, checkpoint_slots=4)) >= 12 * 512
+    with pytest.raises(rd.RDError) as e:
+        s.set_sink(0, -1.0)
+    assert e.value.name == "RD_ERR_ARG"
+    with pytest.raises(rd.RDError) as e:
+        s.set_sink(2, 0.1)
+    assert e.value.name == "RD_ERR_ARG"
+    s.set_sink(0, 0.1)
+    P = ctypes.c_void_p
+    for call in (lambda: rd._lib.rd_sim_set_diffusivity(s.handle, P(8)),
+                 lambda: rd._lib.rd_sim_set_sink_band(s.handle, P(8), ctypes.c_double(1.0), None),
+                 lambda: rd._lib.rd_sim_region_mass(s.handle, 0, P(8), P(8))):
+        with pytest.raises(rd.RDError) as e:
+            rd._check(call(), "call before bind")
+        assert e.value.name == "RD_ERR_STATE"
+    n = ctypes.c_size_t()
+    rd._check(rd._lib.rd_sdf_scratch_bytes(10, 20, 30, ctypes.byref(n)), "rd_sdf_scratch_bytes")
+    assert n.value >= 20 * 10 * 20 * 30
+    with pytest.raises(rd.RDError) as e:
+        rd._check(rd._lib.rd_sdf_scratch_bytes(0, 20, 30, ctypes.byref(n)), "rd_sdf_scratch_bytes")
+    assert e.value.name == "RD_ERR_SHAPE"
+    with pytest.raises(rd.RDError) as e:  # NULL pointers are refused before any launch
+        rd._check(rd._lib.rd_sdf_from_image(None, 4, 4, 4, ctypes.c_double(1.0), None, None, 0, None),
+                  "rd_sdf_from_image")
+    assert e.value.name == "RD_ERR_ARG"
