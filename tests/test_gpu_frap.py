@@ -117,3 +117,31 @@ def test_frap_curve_with_factor_and_sink(rd, oracle_mod):
                               sink_mask=band.astype(np.uint8))
     ref = oracle_mod.frap_curve(prob, c0[None], reg, 0.1, 10, 25)
     np.testing.assert_allclose(got, ref, rtol=1e-5, atol=1e-6)
+
+
+def test_edge_cases(rd, oracle_mod):
+    """The whole box's region mass is the balance's mass; an empty geometry accepts a
+    factor, a band and FRAP calls; a one-voxel region."""
+    img = _geom(seed=23, shape=(21, 18, 27))
+    nz, ny, nx = img.shape
+    _, s = make_gpu(rd, img, [1.0], dirichlet={(0, 0): 0.7}, features=rd.RD_WS_DIFFUSIVITY)
+    rng = np.random.default_rng(23)
+    s.set_field(0, rng.uniform(0, 1, img.shape).astype(np.float32))
+    s.step(0.1, 5)
+    got = fields(s, 1)[0]
+    free = (img != 0).copy()
+    free[:, :, 0] = False  # Dirichlet plane: not part of the balance's mass
+    whole = s.region_mass(0, (0, nx, 0, ny, 0, nz))
+    assert whole == pytest.approx(oracle_mod.region_mass(img, got, (0, nx, 0, ny, 0, nz)), rel=1e-12)
+    assert s.region_mass(0, (1, nx, 0, ny, 0, nz)) == pytest.approx(s.balance(0)["mass"], rel=1e-12)
+    p = tuple(np.argwhere(img != 0)[7])
+    one = (p[2], p[2] + 1, p[1], p[1] + 1, p[0], p[0] + 1)
+    assert s.region_mass(0, one) == pytest.approx(got[p], rel=1e-7)
+    # empty geometry
+    empty = np.zeros((9, 10, 11), np.uint8)
+    _, e = make_gpu(rd, empty, [1.0], features=rd.RD_WS_DIFFUSIVITY)
+    e.set_diffusivity(np.ones(empty.shape, np.float32))
+    assert e.set_sink_band(np.ones(empty.shape, np.float32), 2.0) == 0
+    e.step(0.1, 3)
+    assert e.region_mass(0, (0, 11, 0, 10, 0, 9)) == 0.0
+    assert np.all(e.frap_curve(0, (2, 5, 2, 5, 2, 5), 0.1, 2, 3) == 0.0)
