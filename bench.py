@@ -54,9 +54,9 @@ def parse():
     p.add_argument("--steady-tol", type=float, default=1e-8)
     p.add_argument("--adjoint", type=int, default=0,
                    help="1: time the checkpointed adjoint on the 256^3 diffusion-decay packing")
-    p.add_argument("--diffusivity-steps", type=int, default=0,
+    p.add_argument("--diffusivity-steps", type=int, default=2000,
                    help="FP32 steps of the inhomogeneous-diffusion form (smooth D(phi) on the "
-                        "same volume; 0: skip)")
+                        "same volume, phi built on the GPU; 0: skip)")
     p.add_argument("--frap-size", type=int, default=0,
                    help="edge of the volume of the simulated-FRAP form (0: skip)")
     p.add_argument("--cpu-steps", type=int, default=0,
