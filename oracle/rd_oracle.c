@@ -237,10 +237,15 @@ int orc_balance_ext(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8_t
     const int64_t N = nx * ny * nz;
     const double *u = c + (int64_t)s * N;
     const double kR = robin_k ? robin_k[s] : 0.0;
-    double m = 0.0, rb = 0.0, re = 0.0;
     (void)nspec;
-    double fl[6] = {0, 0, 0, 0, 0, 0};
-    for (int64_t k = 0; k < nz; ++k)
+    /* per-plane partial sums (9 per plane: mass, robin, react, inflow[6]), added in
+     * plane order afterwards, so the result does not depend on the thread count */
+    double *part = (double *)calloc((size_t)nz * 9, sizeof(double));
+    if (!part) return 1;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < nz; ++k) {
+        double m = 0.0, rb = 0.0, re = 0.0;
+        double fl[6] = {0, 0, 0, 0, 0, 0};
         for (int64_t j = 0; j < ny; ++j)
             for (int64_t i = 0; i < nx; ++i) {
                 const int64_t p = IDX(i, j, k);
@@ -269,6 +274,21 @@ int orc_balance_ext(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8_t
                     if (r_to[r] == s) re += rate * dx * dx * dx;
                 }
             }
+        double *pk = part + 9 * k;
+        pk[0] = m;
+        pk[1] = rb;
+        pk[2] = re;
+        for (int f = 0; f < 6; ++f) pk[3 + f] = fl[f];
+    }
+    double m = 0.0, rb = 0.0, re = 0.0;
+    double fl[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t k = 0; k < nz; ++k) {
+        m += part[9 * k];
+        rb += part[9 * k + 1];
+        re += part[9 * k + 2];
+        for (int f = 0; f < 6; ++f) fl[f] += part[9 * k + 3 + f];
+    }
+    free(part);
     *mass = m;
     *robin = rb;
     *react = re;
@@ -336,8 +356,12 @@ double orc_plane_flux_eps(int64_t nx, int64_t ny, int64_t nz, double dx, const u
 static double steady_residual(int64_t nx, int64_t ny, int64_t nz, const uint8_t *active,
                               const uint8_t *free_, const double *u, double *r, double *bb)
 {
-    double rr = 0.0, b2 = 0.0;
-    for (int64_t k = 0; k < nz; ++k)
+    /* per-plane partials, added in plane order (independent of the thread count) */
+    double *part = (double *)calloc((size_t)nz * 2, sizeof(double));
+    if (!part) return NAN;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < nz; ++k) {
+        double rr = 0.0, b2 = 0.0;
         for (int64_t j = 0; j < ny; ++j)
             for (int64_t i = 0; i < nx; ++i) {
                 int64_t p = IDX(i, j, k);
@@ -357,6 +381,15 @@ static double steady_residual(int64_t nx, int64_t ny, int64_t nz, const uint8_t 
                 rr += rp * rp;
                 b2 += bp * bp;
             }
+        part[2 * k] = rr;
+        part[2 * k + 1] = b2;
+    }
+    double rr = 0.0, b2 = 0.0;
+    for (int64_t k = 0; k < nz; ++k) {
+        rr += part[2 * k];
+        b2 += part[2 * k + 1];
+    }
+    free(part);
     if (bb) *bb = b2;
     return rr;
 }
@@ -423,10 +456,15 @@ int orc_steady_cg(int64_t nx, int64_t ny, int64_t nz, const uint8_t *active,
     memcpy(p, r, sizeof(double) * (size_t)N);
     int64_t it = 0;
     double rel = bb > 0 ? sqrt(rr / bb) : 0.0;
+    const int64_t NP = nx * ny; /* voxels per z-plane */
+    double *part = (double *)calloc((size_t)nz, sizeof(double));
+    if (!part) { free(r); free(p); free(ap); return 1; }
     while (rel > tol && it < max_iters) {
-        /* ap = A_ff p (p is zero off the free set) */
-        double pap = 0.0;
-        for (int64_t k = 0; k < nz; ++k)
+        /* ap = A_ff p (p is zero off the free set); p.ap as per-plane partials added
+         * in plane order */
+#pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < nz; ++k) {
+            double pap_k = 0.0;
             for (int64_t j = 0; j < ny; ++j)
                 for (int64_t i = 0; i < nx; ++i) {
                     int64_t q0 = IDX(i, j, k);
@@ -441,24 +479,36 @@ int orc_steady_cg(int64_t nx, int64_t ny, int64_t nz, const uint8_t *active,
                         if (free_[q]) s -= p[q];
                     }
                     ap[q0] = s;
-                    pap += p[q0] * s;
+                    pap_k += p[q0] * s;
                 }
+            part[k] = pap_k;
+        }
+        double pap = 0.0;
+        for (int64_t k = 0; k < nz; ++k) pap += part[k];
         if (pap <= 0.0) break;
         double alpha = rr / pap;
-        double rr_new = 0.0;
-        for (int64_t q = 0; q < N; ++q) {
-            if (!free_[q]) continue;
-            u[q] += alpha * p[q];
-            r[q] -= alpha * ap[q];
-            rr_new += r[q] * r[q];
+#pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < nz; ++k) {
+            double rr_k = 0.0;
+            for (int64_t q = k * NP; q < (k + 1) * NP; ++q) {
+                if (!free_[q]) continue;
+                u[q] += alpha * p[q];
+                r[q] -= alpha * ap[q];
+                rr_k += r[q] * r[q];
+            }
+            part[k] = rr_k;
         }
+        double rr_new = 0.0;
+        for (int64_t k = 0; k < nz; ++k) rr_new += part[k];
         double beta = rr_new / rr;
         rr = rr_new;
+#pragma omp parallel for schedule(static)
         for (int64_t q = 0; q < N; ++q)
             p[q] = free_[q] ? r[q] + beta * p[q] : 0.0;
         ++it;
         rel = bb > 0 ? sqrt(rr / bb) : 0.0;
     }
+    free(part);
     /* report the true residual, not the recursively updated one */
     rr = steady_residual(nx, ny, nz, active, free_, u, NULL, &bb);
     rel = bb > 0 ? sqrt(rr / bb) : 0.0;
@@ -525,6 +575,11 @@ int orc_adjoint_decay(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8
     }
     const double a = D * dt / (dx * dx), b = k * dt;
     double gD = 0.0, gk = 0.0;
+    double *gpart = (double *)calloc((size_t)nz * 2, sizeof(double));
+    if (!gpart) {
+        free(cps); free(seg); free(lam); free(lam2); free(cur); free(tmp); free(free_);
+        return 1;
+    }
     /* backward over segments [s0, s1) */
     for (int64_t s1 = nsteps; s1 > 0;) {
         int64_t s0 = ((s1 - 1) / stride) * stride;
@@ -535,7 +590,10 @@ int orc_adjoint_decay(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8
                       seg + m * N, seg + (m + 1) * N);
         for (int64_t m = len - 1; m >= 0; --m) {
             const double *c = seg + m * N; /* c^{s0+m}; lam holds lambda^{s0+m+1} */
-            for (int64_t kk = 0; kk < nz; ++kk)
+            /* gradient terms as per-plane partials, added in plane order */
+#pragma omp parallel for schedule(static)
+            for (int64_t kk = 0; kk < nz; ++kk) {
+                double gD_k = 0.0, gk_k = 0.0;
                 for (int64_t j = 0; j < ny; ++j)
                     for (int64_t i = 0; i < nx; ++i) {
                         int64_t p = IDX(i, j, kk);
@@ -551,10 +609,17 @@ int orc_adjoint_decay(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8
                             lap += c[q] - c[p];
                             if (free_[q]) lsum += lam[q];
                         }
-                        gD += lam[p] * dt / (dx * dx) * lap;
-                        gk += lam[p] * (-dt) * c[p];
+                        gD_k += lam[p] * dt / (dx * dx) * lap;
+                        gk_k += lam[p] * (-dt) * c[p];
                         lam2[p] = (1.0 - a * (double)nact - b) * lam[p] + a * lsum;
                     }
+                gpart[2 * kk] = gD_k;
+                gpart[2 * kk + 1] = gk_k;
+            }
+            for (int64_t kk = 0; kk < nz; ++kk) {
+                gD += gpart[2 * kk];
+                gk += gpart[2 * kk + 1];
+            }
             double *t = lam; lam = lam2; lam2 = t;
         }
         s1 = s0;
@@ -562,6 +627,7 @@ int orc_adjoint_decay(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8
     *loss = L;
     *dL_dD = gD;
     *dL_dk = gk;
+    free(gpart);
     free(cps); free(seg); free(lam); free(lam2); free(cur); free(tmp); free(free_);
     return 0;
 }
