@@ -139,11 +139,19 @@ rd_status rd_sim_add_reaction(rd_sim *sim, int from, int to, double rate);
 /* Wall uptake of a species: flux k * c out through every wall face (k >= 0); the
  * per-face form of the surface-restricted sink of section "Application example 2". */
 rd_status rd_sim_set_robin(rd_sim *sim, int species, double k);
-/* Hold the active voxels of box face `face` at `value` for a species. */
+/* Hold the active voxels of box face `face` at `value` for a species: the solute
+ * that enters the domain from one face (section "Application example 1"; the unit
+ * drop between two faces of section "Application example 2").  Those voxels are
+ * never updated, act as active neighbours and are left out of the mass.  On edges
+ * shared by two flagged faces the higher face id's value wins.  After bind the values
+ * are written into the field at once.  RD_ERR_ARG for a bad species or face or a
+ * non-finite value. */
 rd_status rd_sim_set_dirichlet(rd_sim *sim, int species, int face, double value);
-/* Remove every Dirichlet face of a species. */
+/* Remove every Dirichlet face of a species (same passages; same errors). */
 rd_status rd_sim_clear_dirichlet(rd_sim *sim, int species);
-/* Launch shape: steps per captured graph (>= 1), whether rd_sim_step
+/* Launch shape of the time loop (forward Euler steps of section "Discretization and
+ * numerical methods"; the paper times one step of its sparse grid, section "Parallel
+ * implementation using OpenFPM"): steps per captured graph (>= 1), whether rd_sim_step
  * replays a captured hipGraph (1) or launches directly (0), and whether workgroups
  * are remapped so each of the 8 XCDs walks one contiguous range of the block list
  * (xcd_map = 1; its L2 then holds most halo reads).  Results are bitwise
@@ -168,16 +176,27 @@ rd_status rd_sim_set_kernel(rd_sim *sim, int kernel, int wg_per_cu);
  * steady states.  Results stay deterministic for a given seed. */
 rd_status rd_sim_set_rounding(rd_sim *sim, int stochastic, uint64_t seed);
 /* Device bytes the caller must provide to rd_sim_bind for the given features
- * (bitwise OR of RD_WS_*) and, with RD_WS_ADJOINT, checkpoint_slots stored states. */
+ * (bitwise OR of RD_WS_*) and, with RD_WS_ADJOINT, checkpoint_slots stored states.
+ * The fields are stored only for the active blocks (section "Parallel implementation
+ * using OpenFPM": only chunks holding an inserted point are allocated), two buffers
+ * per species.  RD_ERR_ARG for NULL bytes or a negative slot count, RD_ERR_STATE
+ * before the first species. */
 rd_status rd_sim_workspace_bytes(const rd_sim *sim, uint32_t features, int64_t checkpoint_slots,
                                  size_t *bytes);
 /* Attach a caller-owned device workspace (>= the size above, 256-byte aligned) and
  * the stream all work goes to.  Uploads the block index, zeroes the fields and
- * synchronises.  May be called again to move to another workspace (fields reset). */
+ * synchronises.  May be called again to move to another workspace (fields reset).
+ * The initial condition of every species is 0 with the Dirichlet values applied
+ * (section "Application example 1": the solute enters an empty domain).  The caller
+ * keeps ownership of the workspace and must keep it alive until the next bind or
+ * rd_sim_destroy.  RD_ERR_WORKSPACE if it is NULL, misaligned or too small. */
 rd_status rd_sim_bind(rd_sim *sim, void *dev_workspace, size_t bytes, uint32_t features,
                       int64_t checkpoint_slots, void *stream);
 /* Scatter a dense device field float32 (nz,ny,nx) into species s; inactive voxels are
- * ignored and Dirichlet voxels take their held value. */
+ * ignored and Dirichlet voxels take their held value.  This sets the initial condition
+ * u(x, 0) of the problem of section "Methods" (eq. reaction_diffusion).  Synchronises;
+ * resets the step count.  RD_ERR_ARG for a bad species or NULL pointer, RD_ERR_STATE
+ * before bind. */
 rd_status rd_sim_set_field(rd_sim *sim, int species, const float *dev_dense);
 /* Inhomogeneous diffusion (section "Level-set method for image-based geometry
  * reconstruction", eq. inhomog_diffusion_coefficient; section "Application example
@@ -365,11 +384,19 @@ rd_status rd_sim_get_launch(const rd_sim *sim, int *graph_steps, int *use_graph,
 
 /* ---- batches of geometries ------------------------------------------------- */
 
-/* Many geometries stepped together: their block lists are concatenated and one
- * launch per step covers every geometry.  Single species, D = 1, pure diffusion;
- * used for per-geometry tortuosity.  The geometries must outlive the batch. */
+/* Many geometries solved together: the tortuosity of eq. tortuosity (section
+ * "Calculation of effective diffusion coefficient and tortuosity") of each geometry,
+ * from the steady unit-drop problem of rd_sim_steady_state.  Their block lists are
+ * concatenated and one launch per kernel stage covers every geometry.  Single
+ * species, D = 1, pure diffusion.  The geometries must outlive the batch.  RD_ERR_ARG
+ * unless 1 <= n <= 65535, for a NULL geometry or an unknown storage type;
+ * RD_ERR_SHAPE if the block edges differ or the batch holds 2^31 blocks or more. */
 rd_status rd_batch_create(const rd_geometry *const *geoms, int n, rd_storage storage,
                           rd_batch **out);
+/* Device bytes of a batch's workspace (same storage rule as rd_sim_workspace_bytes:
+ * active blocks only, plus the solver vectors), and its binding (caller-owned
+ * workspace, 256-byte aligned, kept alive by the caller; the stream as in rd_sim_bind;
+ * RD_ERR_WORKSPACE if NULL, misaligned or too small). */
 rd_status rd_batch_workspace_bytes(const rd_batch *b, size_t *bytes);
 rd_status rd_batch_bind(rd_batch *b, void *dev_workspace, size_t bytes, void *stream);
 /* Per-geometry tortuosity along `axis` by batched conjugate gradients (one launch

@@ -74,6 +74,8 @@ def _load():
     lib.orc_adjoint_decay.restype = ci
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ci
+    lib.orc_set_num_threads.argtypes = [ci]
+    lib.orc_set_num_threads.restype = None
     _lib = lib
     return lib
 
@@ -84,6 +86,11 @@ def _ptr(a):
 
 def num_threads():
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n):
+    """Threads of the oracle's OpenMP loops from now on (results do not depend on it)."""
+    _load().orc_set_num_threads(int(n))
 
 
 class Problem:

@@ -632,6 +632,16 @@ int orc_adjoint_decay(int64_t nx, int64_t ny, int64_t nz, double dx, const uint8
     return 0;
 }
 
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

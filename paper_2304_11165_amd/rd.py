@@ -8,7 +8,6 @@ if librd.so is missing the import fails.
 from __future__ import annotations
 
 import ctypes
-import math
 import os
 
 import numpy as np
@@ -536,12 +535,6 @@ def batch_autotune_pick(batches, axis=0, trial_iters=50):
     _check(_lib.rd_batch_autotune_pick(arr, len(batches), int(axis), int(trial_iters), ctypes.byref(best),
                                        _np_ptr(ms)), "rd_batch_autotune_pick")
     return best.value, ms
-
-
-def stability_dt_max(D_max, dx=1.0, rate_max=0.0, robin_max=0.0):
-    """2 / lambda_max of the step (the bound rd_sim_step enforces)."""
-    lam = 12.0 * D_max / dx ** 2 + rate_max + 6.0 * robin_max / dx
-    return math.inf if lam == 0 else 2.0 / lam
 
 
 class DiffusionDecay(torch.autograd.Function):

@@ -146,12 +146,20 @@ def gaussian_random_field_volume(n=512, corr_len=12.0, porosity=0.3, seed=2):
     spec = np.fft.rfftn(noise)
     del noise
     sigma = corr_len / math.sqrt(2.0)
-    kz = np.fft.fftfreq(n).astype(np.float32)[:, None, None]
-    ky = np.fft.fftfreq(n).astype(np.float32)[None, :, None]
-    kx = np.fft.rfftfreq(n).astype(np.float32)[None, None, :]
-    k2 = (kz * kz + ky * ky + kx * kx) * np.float32((2 * math.pi) ** 2)
-    spec *= np.exp(-0.5 * np.float32(sigma * sigma) * k2)
-    del k2
+    # The Gaussian kernel factorises over the axes; each 1-D factor is evaluated with
+    # the C library's exp (one value per frequency), and the products are plain IEEE
+    # multiplications, so the volume is the same on every host CPU (numpy's vector exp
+    # differs between instruction sets in the last bit, which can move a voxel across
+    # the threshold).
+    def factor(freqs):
+        return np.array([math.exp(-0.5 * sigma * sigma * (2 * math.pi * f) ** 2) for f in freqs],
+                        dtype=np.float32)
+
+    gz = factor(np.fft.fftfreq(n))
+    gy = factor(np.fft.fftfreq(n))[:, None]
+    gx = factor(np.fft.rfftfreq(n))[None, :]
+    for z in range(n):
+        spec[z] *= gz[z] * gy * gx
     field_ = np.fft.irfftn(spec, s=(n, n, n), axes=(0, 1, 2)).astype(np.float32)
     del spec
     thr = np.quantile(field_[:: 2, :: 2, :: 2] if n > 256 else field_, porosity)
