@@ -47,12 +47,12 @@ def parse():
     p.add_argument("--form-steps", type=int, default=2000)
     p.add_argument("--batch", type=int, default=64, help="geometries in the batched form (0: skip)")
     p.add_argument("--batch-max-edge", type=int, default=256)
-    p.add_argument("--steady-axes", type=int, default=0,
+    p.add_argument("--steady-axes", type=int, default=1,
                    help="ceramic-foam steady state: tortuosity along the first K axes (0: skip)")
     p.add_argument("--steady-size", type=int, default=1024, help="edge of the foam volume")
-    p.add_argument("--steady-forms", default="fp32", help="storage types of the steady form")
+    p.add_argument("--steady-forms", default="fp32,fp16", help="storage types of the steady form")
     p.add_argument("--steady-tol", type=float, default=1e-8)
-    p.add_argument("--adjoint", type=int, default=0,
+    p.add_argument("--adjoint", type=int, default=1,
                    help="1: time the checkpointed adjoint on the 256^3 diffusion-decay packing")
     p.add_argument("--diffusivity-steps", type=int, default=2000,
                    help="FP32 steps of the inhomogeneous-diffusion form (smooth D(phi) on the "
@@ -61,8 +61,9 @@ def parse():
                    help="edge of the volume of the simulated-FRAP form (0: skip)")
     p.add_argument("--cpu-steps", type=int, default=0,
                    help="oracle steps in the CPU sample (0: as many as fit in --cpu-seconds)")
-    p.add_argument("--cpu-seconds", type=float, default=12.0,
-                   help="target length of the CPU sample when --cpu-steps is 0")
+    p.add_argument("--cpu-seconds", type=float, default=5.0,
+                   help="target length of each of the three all-thread CPU samples when "
+                        "--cpu-steps is 0")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--graph-steps", type=int, default=32)
     p.add_argument("--no-graph", action="store_true", help="direct launches (for profilers)")
@@ -73,6 +74,8 @@ def parse():
     p.add_argument("--kernel", default="auto", choices=["auto", "block", "column", "column_xch",
                                                         "persistent"],
                    help="B = 8 step kernel (auto: autotuned)")
+    p.add_argument("--layout", default="auto", choices=["auto", "blocks", "compact"],
+                   help="field layout (auto: the faster of the two, each autotuned)")
     p.add_argument("--xcd", default="auto", choices=["auto", "0", "1"],
                    help="XCD-aware block order (auto: autotuned)")
     p.add_argument("--traffic", default=TRAFFIC_FILE,
@@ -145,17 +148,35 @@ def build_sim(rd, geom, w, storage, graph_steps, use_graph=True):
 
 
 def time_steps(torch, sim, stream, dt, warmup, steps):
+    """Warm-up, then exactly `steps` steps timed with HIP events on the launch stream.
+    The steps are issued in chunks with an event between chunks: chunks of one captured
+    graph (the launch's steps per graph) when there are at least ten of them, else
+    single steps launched directly.  Returns (seconds, wall seconds, timing record with
+    the mean and standard error of the per-chunk time per step)."""
+    import math
+
     sim.step(dt, warmup)
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    launch = sim.get_launch()
+    gs = launch["graph_steps"] + (launch["graph_steps"] & 1)
+    chunk = gs if (launch["use_graph"] and steps >= 10 * gs) else 1
+    sizes = [chunk] * (steps // chunk) + ([steps % chunk] if steps % chunk else [])
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(sizes) + 1)]
     t0 = time.perf_counter()
-    e0.record(stream)
-    sim.step(dt, steps)
-    e1.record(stream)
+    ev[0].record(stream)
+    for i, n in enumerate(sizes):
+        sim.step(dt, n)
+        ev[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return e0.elapsed_time(e1) / 1e3, wall
+    secs = ev[0].elapsed_time(ev[-1]) / 1e3
+    per = [ev[i].elapsed_time(ev[i + 1]) / n for i, n in enumerate(sizes) if n == chunk]
+    mean = sum(per) / len(per)
+    se = math.sqrt(sum((x - mean) ** 2 for x in per) / (len(per) - 1) / len(per)) if len(per) > 1 else 0.0
+    timing = {"chunks": len(per), "steps_per_chunk": chunk,
+              "launches": "captured graphs" if chunk > 1 else "direct launches",
+              "ms_per_step_mean": mean, "ms_per_step_stderr": se}
+    return secs, wall, timing
 
 
 def step_kernel_name(B, launch, S):
@@ -163,9 +184,10 @@ def step_kernel_name(B, launch, S):
     if B == 4:
         return f"k_step4w<float,{S}>"
     kern = (launch or {}).get("kernel", "block")
-    name = {"block": "k_step8<float,{S}>", "column": "k_step8z<float,{S},false>",
-            "column_xch": "k_step8z<float,{S},true>", "persistent": "k_step8p<float,{S}>"}[kern]
-    return name.format(S=S)
+    cmp = "true" if (launch or {}).get("layout") == "compact" else "false"
+    name = {"block": "k_step8<float,{S}>", "column": "k_step8z<float,{S},false,{C}>",
+            "column_xch": "k_step8z<float,{S},true,{C}>", "persistent": "k_step8p<float,{S}>"}[kern]
+    return name.format(S=S, C=cmp)
 
 
 def batched_form(torch, rd, W, count, max_edge, stream):
@@ -212,7 +234,10 @@ def batched_form(torch, rd, W, count, max_edge, stream):
 def steady_form(torch, rd, W, size, axes, forms, tol, stream):
     """Tortuosity of the ceramic-foam volume (solid matrix of overlapping pore spheres
     r ~ U(10, 30), pore fraction 0.15) along the first `axes` axes by conjugate
-    gradients, per storage type."""
+    gradients, per storage type; with the full 1024^3 volume, the same solves on its
+    256^3 corner crop are checked against the stored oracle tortuosity."""
+    import numpy as np
+
     t0 = time.perf_counter()
     w = W.workload("foam1024")
     img, _ = W.workload_geometry("foam1024") if size == 1024 else \
@@ -220,6 +245,7 @@ def steady_form(torch, rd, W, size, axes, forms, tol, stream):
     log(f"foam {size}^3 generated in {time.perf_counter() - t0:.1f}s")
     geom = rd.Geometry(img, None, 1.0, 8)
     st = geom.stats()
+    crop = np.ascontiguousarray(img[:FOAM_CROP, :FOAM_CROP, :FOAM_CROP]) if size == 1024 else None
     del img
     out = {"workload": f"foam{size}", "n_active": st["n_active"], "n_blocks": st["n_blocks"],
            "fill": st["fill"], "tol": tol, "runs": []}
@@ -244,7 +270,48 @@ def steady_form(torch, rd, W, size, axes, forms, tol, stream):
                     f"{r['iters']} it, {secs:.1f}s")
             del sim
             torch.cuda.empty_cache()
+    if crop is not None:
+        out["oracle_check"] = foam_crop_check(torch, rd, np, crop, forms, tol, stream)
     return out
+
+
+FOAM_CROP = 256
+GOLDEN = os.path.join(HERE, "tests", "golden")
+
+
+def _sha256(img):
+    import hashlib
+
+    return hashlib.sha256(img.tobytes()).hexdigest()
+
+
+def foam_crop_check(torch, rd, np, crop, forms, tol, stream):
+    """Tortuosity along x of the 256^3 corner crop of the foam, per storage type, against
+    the stored FP64 oracle value (oracle CG to 1e-12, written by
+    tests/golden/make_goldens.py)."""
+    path = os.path.join(GOLDEN, "foam_crop256_tau.json")
+    if not os.path.exists(path):
+        return None
+    ref = json.load(open(path))
+    if ref["sha256"] != _sha256(crop):
+        log("foam crop differs from the stored one: no oracle check")
+        return None
+    tau_o = ref["axes"]["0"]["tau"]
+    res = {"volume": "256^3 corner crop of the 1024^3 foam", "axis": 0, "oracle_tau": tau_o,
+           "runs": []}
+    geom = rd.Geometry(crop, None, 1.0, 8)
+    for storage in forms:
+        with torch.cuda.stream(stream):
+            sim = rd.Sim(geom, storage)
+            sim.add_species(1.0)
+            sim.bind(features=rd.RD_WS_SOLVER, stream=stream)
+            r = sim.steady_state(0, tol, 200000)
+            del sim
+        err = abs(r["tau"] - tau_o) / tau_o
+        res["runs"].append({"storage": storage, "tau": r["tau"], "rel_err_vs_oracle": err,
+                            "rel_residual": r["rel_residual"], "iters": r["iters"]})
+        log(f"foam crop {storage}: tau {r['tau']:.10f} vs oracle {tau_o:.10f} (rel {err:.2e})")
+    return res
 
 
 def adjoint_form(torch, rd, W, stream):
@@ -309,11 +376,28 @@ def adjoint_form(torch, rd, W, stream):
     factor = {"diffusivity": "e = %g + %g / (1 + exp(-(%g + %g phi)))" % DIFF_PARS,
               "forward_seconds": ffwd, "adjoint_seconds": fadj, "adjoint_over_forward": fadj / ffwd,
               "loss": floss, "dL_dD": fgD, "dL_drate": fgk, "dL_de_l2": ge_norm}
-    return {"workload": "decay256", "n_active": st["n_active"], "steps": n, "checkpoint_every": k,
-            "forward_seconds": fwd, "adjoint_seconds": adj, "adjoint_over_forward": adj / fwd,
-            "loss": loss, "dL_dD": gD, "dL_drate": gk, "factor": factor,
-            "note": "adjoint_seconds: forward with checkpoints, recompute of each segment, "
-                    "backward sweep; FP32 fields, FP64 gradient sums"}
+    res = {"workload": "decay256", "n_active": st["n_active"], "steps": n, "checkpoint_every": k,
+           "forward_seconds": fwd, "adjoint_seconds": adj, "adjoint_over_forward": adj / fwd,
+           "loss": loss, "dL_dD": gD, "dL_drate": gk, "factor": factor,
+           "note": "adjoint_seconds: forward with checkpoints, recompute of each segment, "
+                   "backward sweep; FP32 fields, FP64 gradient sums"}
+    path = os.path.join(GOLDEN, "decay256_adjoint.json")
+    if os.path.exists(path):
+        ref = json.load(open(path))
+        if ref["sha256"] == _sha256(img):
+            res["oracle_check"] = {
+                "oracle_dL_dD": ref["dL_dD"], "oracle_dL_drate": ref["dL_dk"],
+                "central_difference_dL_dD": ref["fd"]["D"]["central"],
+                "central_difference_dL_drate": ref["fd"]["k"]["central"],
+                "rel_err_dL_dD": abs(gD - ref["dL_dD"]) / abs(ref["dL_dD"]),
+                "rel_err_dL_drate": abs(gk - ref["dL_dk"]) / abs(ref["dL_dk"]),
+                "note": "stored FP64 oracle adjoint and central differences (h = 1e-3) use the "
+                        "oracle's FP64 target rounded to FP32; the bench's target is the same "
+                        "run on the GPU in FP32, so the differences include that of the targets "
+                        "(the parity test uses the oracle's target on both sides)"}
+            log(f"adjoint vs stored oracle: dL/dD rel {res['oracle_check']['rel_err_dL_dD']:.2e}, "
+                f"dL/dk rel {res['oracle_check']['rel_err_dL_drate']:.2e}")
+    return res
 
 
 # Smooth diffusivity of the inhomogeneous form: e = D_MIN + D_MAX / (1 + exp(-(G1 + G2 phi)))
@@ -343,7 +427,7 @@ def diffusivity_form(torch, rd, np, geom, img, w, n_active, steps, graph_steps, 
         sim.bind(features=rd.RD_WS_DIFFUSIVITY, stream=stream)
         sim.set_diffusivity_sdf(phi, *DIFF_PARS)
         del phi, dimg
-        secs, wall = time_steps(torch, sim, stream, w.dt, 50, steps)
+        secs, wall, timing = time_steps(torch, sim, stream, w.dt, 50, steps)
         bal = [sim.balance(sp) for sp in range(S)]
         torch.cuda.synchronize()
     per = secs / steps
@@ -357,6 +441,7 @@ def diffusivity_form(torch, rd, np, geom, img, w, n_active, steps, graph_steps, 
         "seconds": secs,
         "wall_seconds": wall,
         "ms_per_step": per * 1e3,
+        "timing": timing,
         "updates_per_s": n_active * steps / secs,
         "alg_bytes_per_launch": alg,
         "alg_GBps": alg / per / 1e9,
@@ -476,25 +561,47 @@ def main():
     forms = [] if a.profile else [f for f in a.forms.split(",") if f]
     for storage in [a.profile_storage] if a.profile else ["fp32"] + forms:
         steps = a.steps if storage == "fp32" else min(a.steps, a.form_steps)
-        warm = a.warmup if storage == "fp32" else 50
+        warm = a.warmup
+        layouts = ["blocks", "compact"] if a.layout == "auto" else [a.layout]
+        if a.kernel in ("block", "persistent"):
+            layouts = ["blocks"]  # the compact layout has only the column kernels
         with torch.cuda.stream(stream):
-            sim = build_sim(rd, geom, w, storage, a.graph_steps, not a.no_graph)
-            sim.bind(stream=stream)
-            if a.kernel != "auto":
-                sim.set_kernel(a.kernel)
-            if a.xcd != "auto":
-                sim.set_launch(a.graph_steps, not a.no_graph, a.xcd == "1")
-            if a.kernel == "auto" or a.xcd == "auto":
-                sim.autotune(w.dt, 200)  # resets the fields afterwards
+            cands = []
+            for lay in layouts:
+                sim = build_sim(rd, geom, w, storage, a.graph_steps, not a.no_graph)
+                sim.set_layout(lay)
+                sim.bind(stream=stream)
+                if a.kernel != "auto":
+                    sim.set_kernel(a.kernel)
+                if a.xcd != "auto":
+                    sim.set_launch(a.graph_steps, not a.no_graph, a.xcd == "1")
+                cands.append(sim)
+            tuned = a.kernel == "auto" or a.xcd == "auto"
+            pick_ms = None
+            if tuned and len(cands) > 1:
+                best, pick_ms = rd.autotune_pick(cands, w.dt, 200)  # resets the fields
+            else:
+                best = 0
+                if tuned:
+                    cands[0].autotune(w.dt, 200)
+            sim = cands[best]
+            layout = layouts[best]
+            del cands
             launch = sim.get_launch()
-            secs, wall = time_steps(torch, sim, stream, w.dt, warm, steps)
+            launch["layout"] = layout
+            if pick_ms is not None:
+                launch["trial_ms_per_step"] = {lay: float(m) for lay, m in zip(layouts, pick_ms)}
+            secs, wall, timing = time_steps(torch, sim, stream, w.dt, warm, steps)
             bal = [sim.balance(sp) for sp in range(S)]
             if storage != "fp32" or forms:
                 fields[storage] = [sim.get_field(sp).float() for sp in range(S)]
             torch.cuda.synchronize()
         es = 4 if storage == "fp32" else 2
         alg_bytes = 2 * es * S * n_active
-        layout_bytes = 2 * es * S * slots + nb * (32 + 512)  # whole blocks + records + codes
+        if layout == "compact":  # active voxels + records, block bases and codes
+            layout_bytes = 2 * es * S * n_active + nb * (32 + 128 + 4) + n_active
+        else:  # whole blocks + records + codes
+            layout_bytes = 2 * es * S * slots + nb * (32 + 128 + 512)
         per_step = secs / steps
         results[storage] = {
             "steps": steps,
@@ -502,6 +609,7 @@ def main():
             "seconds": secs,
             "wall_seconds": wall,
             "ms_per_step": per_step * 1e3,
+            "timing": timing,
             "updates_per_s": n_active * steps / secs,
             "alg_GBps": alg_bytes / per_step / 1e9,
             "layout_GBps": layout_bytes / per_step / 1e9,
@@ -513,7 +621,9 @@ def main():
             "inflow": [float(np.sum(b["inflow"])) for b in bal],
             "uptake": [b["uptake"] for b in bal],
         }
-        log(f"{storage}: {per_step * 1e3:.4f} ms/step, {n_active * steps / secs:.3e} upd/s, "
+        log(f"{storage}: {per_step * 1e3:.4f} ms/step ({timing['ms_per_step_mean']:.4f} +- "
+            f"{timing['ms_per_step_stderr']:.4f} over {timing['chunks']} chunks of "
+            f"{timing['steps_per_chunk']}), {n_active * steps / secs:.3e} upd/s, "
             f"alg {alg_bytes / per_step / 1e9:.0f} GB/s, layout {layout_bytes / per_step / 1e9:.0f} GB/s")
         del sim
 
@@ -561,7 +671,10 @@ def main():
             "n_blocks": nb,
             "fill": fill,
             "species": S,
-            "steps_per_graph": a.graph_steps,
+            "steps_per_graph": f32["launch"]["graph_steps"],
+            "launch": f32["launch"],
+            "timed_as": f"{f32['timing']['chunks']} chunks of {f32['timing']['steps_per_chunk']} "
+                        f"step(s), {f32['timing']['launches']}",
         },
         "roofline": {
             "bound": "hbm",
@@ -574,6 +687,7 @@ def main():
             "alg_bytes_per_launch": f32["alg_bytes_per_launch"],
             "layout_GBps": f32["layout_GBps"],
             "avg_launch_ms": f32["ms_per_step"],
+            "avg_launch_ms_stderr": f32["timing"]["ms_per_step_stderr"],
         },
         "forms": results,
     }
@@ -599,36 +713,71 @@ def main():
         out["forms"]["adjoint"] = adjoint_form(torch, rd, W, stream)
 
     if not a.no_cpu_baseline and not a.profile:
-        import oracle
+        out["cpu_baseline"] = cpu_baseline(img, w, n, n_active, a.cpu_steps, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
 
-        prob = oracle.Problem(img, w.species_D, dx=w.dx, robin=w.robin, dirichlet=w.dirichlet,
-                              reactions=w.reactions)
-        c0 = prob.initial()
-        prob.run(c0, w.dt, 1)  # page in
-        done = a.cpu_steps
-        if done <= 0:  # size the sample from two short runs (their difference drops the
-            # per-call cost of copying the field in and out)
-            t0 = time.perf_counter()
-            prob.run(c0, w.dt, 2)
-            t2 = time.perf_counter() - t0
-            t0 = time.perf_counter()
-            prob.run(c0, w.dt, 6)
-            t6 = time.perf_counter() - t0
-            per = max((t6 - t2) / 4, 1e-6)
-            done = max(2, min(5000, int((a.cpu_seconds - t2 + 2 * per) / per)))
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(img, w, n, n_active, cpu_steps, cpu_seconds):
+    """The FP64 oracle on the host cores: three samples with every OpenMP thread (the
+    median is the value), then one sample on a single thread."""
+    import statistics
+
+    import oracle
+
+    prob = oracle.Problem(img, w.species_D, dx=w.dx, robin=w.robin, dirichlet=w.dirichlet,
+                          reactions=w.reactions)
+    threads = oracle.num_threads()
+    c0 = prob.initial()
+    prob.run(c0, w.dt, 1)  # page in
+    done = cpu_steps
+    if done <= 0:  # size a sample from two short runs (their difference drops the
+        # per-call cost of copying the field in and out)
+        t0 = time.perf_counter()
+        prob.run(c0, w.dt, 2)
+        t2 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        prob.run(c0, w.dt, 6)
+        t6 = time.perf_counter() - t0
+        per = max((t6 - t2) / 4, 1e-6)
+        done = max(2, min(5000, int((cpu_seconds - t2 + 2 * per) / per)))
+    rates = []
+    for _ in range(3):
         t0 = time.perf_counter()
         prob.run(c0, w.dt, done)
-        secs = time.perf_counter() - t0
-        out["cpu_baseline"] = {
-            "value": n_active * done / secs,
-            "unit": "active-voxel updates/s",
-            "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{done} FP64 steps of the same {n}^3 two-species workload on the "
-                      f"dense masked grid ({secs:.1f} s)",
-        }
-        log(f"cpu oracle: {out['cpu_baseline']['value']:.3e} upd/s on {oracle.num_threads()} threads")
-    print(json.dumps(out), flush=True)
+        rates.append(n_active * done / (time.perf_counter() - t0))
+    oracle.set_num_threads(1)
+    one = 2
+    t0 = time.perf_counter()
+    prob.run(c0, w.dt, one)
+    rate1 = n_active * one / (time.perf_counter() - t0)
+    oracle.set_num_threads(threads)
+    res = {
+        "value": statistics.median(rates),
+        "unit": "active-voxel updates/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"median of 3 runs of {done} FP64 steps of the same {n}^3 two-species workload "
+                  f"on the dense masked grid, {threads} OpenMP threads",
+        "runs": rates,
+        "value_single_thread": rate1,
+        "single_thread_sample": f"{one} steps on one thread",
+        "cpu_model": cpu_model(),
+        "host_cpus": os.cpu_count(),
+    }
+    log(f"cpu oracle: {res['value']:.3e} upd/s on {threads} threads (runs "
+        f"{', '.join(f'{r:.3e}' for r in rates)}), {rate1:.3e} on one thread; {res['cpu_model']}")
+    return res
 
 
 if __name__ == "__main__":

@@ -60,6 +60,10 @@ typedef enum {
 
 typedef enum { RD_FP32 = 0, RD_BF16 = 1, RD_FP16 = 2 } rd_storage;
 
+/* Field layouts (rd_sim_set_layout). */
+#define RD_LAYOUT_BLOCKS 0   /* every slot of every stored block (default) */
+#define RD_LAYOUT_COMPACT 1  /* only the active voxels of the stored blocks (8^3 blocks) */
+
 /* Workspace features (rd_sim_workspace_bytes). */
 #define RD_WS_SOLVER 1u   /* vectors for rd_sim_steady_state */
 #define RD_WS_ADJOINT 2u  /* adjoint vectors + checkpoint slots for rd_sim_adjoint */
@@ -157,6 +161,18 @@ rd_status rd_sim_clear_dirichlet(rd_sim *sim, int species);
  * (xcd_map = 1; its L2 then holds most halo reads).  Results are bitwise
  * identical for every choice. */
 rd_status rd_sim_set_launch(rd_sim *sim, int graph_steps, int use_graph, int xcd_map);
+/* Field layout in HBM, before rd_sim_bind (RD_ERR_STATE after it).  The paper stores
+ * whole chunks of 8^3 points with an allocation mask (section "Parallel implementation
+ * using OpenFPM"); RD_LAYOUT_BLOCKS does the same.  RD_LAYOUT_COMPACT keeps, for every
+ * stored block, only its active voxels, block after block in slot order, so a step
+ * moves the bytes of the active voxels rather than of whole blocks (the block index,
+ * masks and neighbour list are unchanged).  Results are bitwise identical in both
+ * layouts.  The compact layout runs the column kernels (2 and 3 of rd_sim_set_kernel)
+ * and supports stepping, balances, plane fluxes, region masses and field set/get; a
+ * bind with RD_WS_SOLVER, RD_WS_ADJOINT or RD_WS_DIFFUSIVITY returns RD_ERR_STATE.
+ * RD_ERR_ARG for an unknown layout; RD_ERR_SHAPE for compact with 4^3 blocks or more
+ * than 2^30 - 128 active voxels. */
+rd_status rd_sim_set_layout(rd_sim *sim, int layout);
 /* Step kernel for B = 8 (ignored for B = 4, which always runs one wave per block):
  *   kernel = 0: one 256-thread workgroup per block;
  *   kernel = 1: persistent, a fixed grid of wg_per_cu * (compute units) workgroups
@@ -164,9 +180,14 @@ rd_status rd_sim_set_launch(rd_sim *sim, int graph_steps, int use_graph, int xcd
  *               computing the current one;
  *   kernel = 2 (default): one wave per block, each lane walking a z-column of 8 voxels;
  *   kernel = 3: as 2, with the x faces of x-adjacent blocks of a workgroup handed
- *               over through LDS instead of being re-read from memory.
- * Results are bitwise identical.  RD_ERR_ARG for kernel outside 0..3 or wg_per_cu
- * outside 1..32. */
+ *               over through LDS instead of being re-read from memory;
+ *   kernel = 4: compact layout only: as 2, with buffer accesses (inactive voxels read
+ *               as 0 by range checking, no predicates) and the +-x / +-y neighbours
+ *               exchanged between lanes (DPP row shifts, ds_bpermute) instead of an
+ *               LDS tile.
+ * Results are bitwise identical.  RD_ERR_ARG for kernel outside 0..4 or wg_per_cu
+ * outside 1..32; RD_ERR_STATE for kernel 0 or 1 with the compact layout and for
+ * kernel 4 with the block layout. */
 rd_status rd_sim_set_kernel(rd_sim *sim, int kernel, int wg_per_cu);
 
 /* Rounding of BF16 / FP16 stores (no effect with FP32 storage).  stochastic = 0:

@@ -20,7 +20,8 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-HIP_SOURCES = ["k_step.hip", "k_solve.hip", "k_adjoint.hip", "k_diff.hip", "k_frap.hip", "k_edt.hip"]
+HIP_SOURCES = ["k_step.hip", "k_compact.hip", "k_solve.hip", "k_adjoint.hip", "k_diff.hip", "k_frap.hip",
+               "k_edt.hip"]
 CPP_SOURCES = ["geometry.cpp", "rd_api.cpp", "rd_solve.cpp", "frap.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function"]

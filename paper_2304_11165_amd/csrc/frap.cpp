@@ -24,7 +24,8 @@ static rd_status region_mass(rd_sim *sim, int species, const int32_t reg[6], dou
     double *part = (double *)(ws + L.part);
     double *res = (double *)(ws + L.res) + 40;
     LAUNCHCHK(rd_launch_region_mass((int)sim->storage, G.B, (const BlockInfo *)(ws + L.info),
-                                    (const uint8_t *)(ws + L.code), sim->field_ptr(sim->cur, species), nb, reg,
+                                    (const uint8_t *)(ws + L.code), sim->cbase_ptr(),
+                                    (const uint64_t *)(ws + L.mask), sim->field_ptr(sim->cur, species), nb, reg,
                                     part, sim->stream));
     LAUNCHCHK(rd_launch_finish_reduce(part, rd_region_rows(G.B, nb), 1, (double *)(ws + L.mid), res,
                                       sim->stream));

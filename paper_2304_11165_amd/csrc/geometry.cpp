@@ -185,6 +185,37 @@ rd_status rd_geometry_build(const uint8_t *image, int64_t nx, int64_t ny, int64_
                 }
         }
     }
+    // B = 8: words 14-15 of a record hold the number of active slots below each plane
+    // (16 bits per plane z = 0..7, plane z at bit 16 (z % 4) of word 14 + z / 4), the
+    // offset of the plane's first voxel in the compact layout, where a block stores
+    // only its active voxels in slot order
+    if (B == 8) {
+        for (int64_t b = 0; b < nb; ++b) {
+            uint64_t *rec = &g->mask[(size_t)b * MW];
+            uint64_t pre = 0;
+            rec[14] = rec[15] = 0;
+            for (int z = 0; z < 8; ++z) {
+                rec[14 + z / 4] |= pre << (16 * (z % 4));
+                pre += (uint64_t)__builtin_popcountll(rec[z]);
+            }
+        }
+    }
     CodeFill::run(g);
     return RD_OK;
+}
+
+void rd_geometry_compact_index(const rd_geometry *g, std::vector<uint32_t> &cbase, std::vector<uint8_t> &ccode)
+{
+    const int B = g->B, NS = B * B * B;
+    const int64_t nb = g->nb();
+    cbase.assign((size_t)nb + 1, 0);
+    ccode.clear();
+    ccode.reserve((size_t)g->n_active);
+    for (int64_t b = 0; b < nb; ++b) {
+        cbase[b] = (uint32_t)ccode.size();
+        const uint8_t *cd = &g->code[(size_t)b * NS];
+        for (int s = 0; s < NS; ++s)
+            if (cd[s] & 64u) ccode.push_back(cd[s]);
+    }
+    cbase[nb] = (uint32_t)ccode.size();
 }

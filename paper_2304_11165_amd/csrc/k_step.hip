@@ -315,7 +315,13 @@ namespace z8 {
 __device__ __forceinline__ int pix(int x, int y) { return (y + 1) * 10 + (x + 1); }
 }  // namespace z8
 
-template <typename T, int S, bool XCH>
+// With CMP the fields and neighbour codes hold only the active voxels (compact
+// layout): plane z of block b starts at cbase[b] + (active slots below plane z) and a
+// lane's voxel sits at the number of active lanes below it; a side halo value is found
+// from the neighbour's plane word and prefix count (one record line), a z halo from
+// the face word.  Loads, arithmetic and stored values are those of the block-major
+// layout, so both give the same bits; stores cover the active voxels only.
+template <typename T, int S, bool XCH, bool CMP>
 __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
 {
     __shared__ float tile[4][S][100];
@@ -329,7 +335,6 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
     }
     const T *cin = (const T *)a.cin;
     T *cout = (T *)a.cout;
-    const int64_t base = (int64_t)b * 512;
     const int lx = lane & 7, ly = lane >> 3;
     const int32_t *nbr = a.info[b].nbr;
     // x neighbours inside this workgroup (wave-uniform; only with XCH)
@@ -344,6 +349,20 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
 #pragma unroll
     for (int f = 0; f < 6; ++f) Wf[f] = rec[8 + f];
 
+    // element index of the lane's voxel in plane z (valid where the voxel is active)
+    typename std::conditional<CMP, uint32_t, int64_t>::type oi[8];
+    if constexpr (CMP) {
+        uint32_t acc = a.cbase[b];
+#pragma unroll
+        for (int z = 0; z < 8; ++z) {
+            oi[z] = acc + lanes_below(Wo[z]);
+            acc += (uint32_t)__popcll(Wo[z]);
+        }
+    } else {
+#pragma unroll
+        for (int z = 0; z < 8; ++z) oi[z] = (int64_t)b * 512 + z * 64 + lane;
+    }
+
     typedef typename RawOf<T>::type R;
     R rc[S][8], rh[6][S];
     unsigned cd[8];
@@ -355,8 +374,8 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
         cd[z] = 0u;
         if (lane_bit(Wo[z])) {
 #pragma unroll
-            for (int s = 0; s < S; ++s) rc[s][z] = ld_raw(cin, s * a.sstride + base + z * 64 + lane);
-            cd[z] = (unsigned)a.code[base + z * 64 + lane];
+            for (int s = 0; s < S; ++s) rc[s][z] = ld_raw(cin, s * a.sstride + oi[z]);
+            cd[z] = (unsigned)a.code[oi[z]];
         }
     }
     // face halos, one value per lane and face: lane (u, v) = (lx, ly) reads the
@@ -374,10 +393,24 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
         default: ns = (0 * 8 + ly) * 8 + lx; break; // (x=u, y=v, z=0)
         }
         const int n = nbr[f];
-        const int64_t hb = (int64_t)(n >= 0 ? n : b) * 512 + ns;
+        const int nn = n >= 0 ? n : b;
+        const uint64_t need = (f == 0 && xm_in) || (f == 1 && xp_in) ? 0ull : Wf[f];
 #pragma unroll
         for (int s = 0; s < S; ++s) rh[f][s] = (R)0;
-        if (lane_bit((f == 0 && xm_in) || (f == 1 && xp_in) ? 0ull : Wf[f])) {
+        int64_t hb;
+        if constexpr (CMP) {
+            if (f == 4) {  // plane 7 of the -z neighbour: its last popc(Wf[4]) voxels
+                hb = (int64_t)a.cbase[nn + 1] - __popcll(Wf[4]) + lanes_below(Wf[4]);
+            } else if (f == 5) {  // plane 0 of the +z neighbour
+                hb = (int64_t)a.cbase[nn] + lanes_below(Wf[5]);
+            } else {  // plane v = ly of a side neighbour, slot ns
+                hb = 0;
+                if (lane_bit(need)) hb = slot_index8(a.cbase, a.mask, nn, ns);
+            }
+        } else {
+            hb = (int64_t)nn * 512 + ns;
+        }
+        if (lane_bit(need)) {
 #pragma unroll
             for (int s = 0; s < S; ++s) rh[f][s] = ld_raw(cin, s * a.sstride + hb);
         }
@@ -462,11 +495,12 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // whole sectors only; an inactive slot of an active sector stores its 0 again
-        if (lane_bit(sector_lanes<T>(Wo[z]))) {
+        // block-major: whole sectors only (an inactive slot of an active sector stores
+        // its 0 again); compact: the active voxels, a contiguous run
+        if (lane_bit(CMP ? Wo[z] : sector_lanes<T>(Wo[z]))) {
             const uint32_t h = voxel_bits(a, key, voxel_id(g, gx, gy, gz));
 #pragma unroll
-            for (int s = 0; s < S; ++s) store_val(a, cout, s, s * a.sstride + base + z * 64 + lane, h, res[s]);
+            for (int s = 0; s < S; ++s) store_val(a, cout, s, s * a.sstride + oi[z], h, res[s]);
         }
     }
 }
@@ -786,12 +820,16 @@ __global__ __launch_bounds__(256) void k_reduce8z(ReduceArgs a)
         uint64_t Wo[8];
         R raw[8];
         unsigned cd[8];
+        int64_t oi[8];  // element index of the lane's voxel in plane z (block-major or compact)
+        int64_t acc0 = a.cbase ? (int64_t)a.cbase[b] : 0;
 #pragma unroll
         for (int z = 0; z < 8; ++z) {
             Wo[z] = rec[z];
+            oi[z] = a.cbase ? acc0 + lanes_below(Wo[z]) : base + z * 64 + lane;
+            acc0 += __popcll(Wo[z]);
             const bool act = (Wo[z] >> lane) & 1ull;
-            raw[z] = ld_raw(cs, base + z * 64 + lane, act);
-            cd[z] = act ? (unsigned)a.code[base + z * 64 + lane] : 0u;
+            raw[z] = ld_raw(cs, oi[z], act);
+            cd[z] = act ? (unsigned)a.code[oi[z]] : 0u;
         }
         // inflow into this species from the others (0 on inactive slots)
         double rin[8];
@@ -802,7 +840,7 @@ __global__ __launch_bounds__(256) void k_reduce8z(ReduceArgs a)
             if (k == 0.0) continue;
             R r2[8];
 #pragma unroll
-            for (int z = 0; z < 8; ++z) r2[z] = ld_raw(c + s2 * a.sstride, base + z * 64 + lane, (Wo[z] >> lane) & 1ull);
+            for (int z = 0; z < 8; ++z) r2[z] = ld_raw(c + s2 * a.sstride, oi[z], (Wo[z] >> lane) & 1ull);
 #pragma unroll
             for (int z = 0; z < 8; ++z) rin[z] += k * (double)from_raw<T>(r2[z]);
         }
@@ -833,7 +871,7 @@ __global__ __launch_bounds__(256) void k_reduce8z(ReduceArgs a)
                     // an active neighbour outside the block lies in face neighbour d
                     const int nbk = inside ? b : bi.nbr[d];
                     const int slot = ((qz & 7) * 8 + (qy & 7)) * 8 + (qx & 7);
-                    const double v = (double)rd_ld(cs, (int64_t)nbk * 512 + slot);
+                    const double v = (double)rd_ld(cs, slot_index8(a.cbase, a.mask, nbk, slot));
                     fin += a.D * (u - v) * dx;
                 }
 #pragma unroll
@@ -871,6 +909,7 @@ __global__ __launch_bounds__(256) void k_reduce8z(ReduceArgs a)
 // four wave sums in wave order).
 template <typename T, int B>
 __global__ __launch_bounds__(256) void k_plane_flux(const BlockInfo *info, const uint8_t *code,
+                                                    const uint32_t *cbase, const uint64_t *mask,
                                                     const T *c, int nb, int axis, int i0,
                                                     double D, double dx, double *partial)
 {
@@ -890,13 +929,18 @@ __global__ __launch_bounds__(256) void k_plane_flux(const BlockInfo *info, const
                       lz = axis == 2 ? l0 : v;
             const int slot = (lz * B + ly) * B + lx;
             const int stride = axis == 0 ? 1 : axis == 1 ? B : B * B;
-            const unsigned cd = code[(int64_t)b * K::NS + slot];
+            // compact layout (B = 8 only): the slot's code and value exist only if it is
+            // active
+            const bool own = !cbase || own_bit<B>(mask + (int64_t)b * K::MW, slot);
+            const int64_t ip = cbase ? slot_index8(cbase, mask, b, slot) : (int64_t)b * K::NS + slot;
+            const unsigned cd = own ? code[ip] : 0u;
             if ((cd & 64u) && ((cd >> (2 * axis + 1)) & 1u)) {
                 // the active +axis neighbour is in this block or in face neighbour 2 axis + 1
                 const int nbk = l0 + 1 < B ? b : bi.nbr[2 * axis + 1];
                 const int ns = l0 + 1 < B ? slot + stride : slot - (B - 1) * stride;
-                const double cp = (double)rd_ld(c, (int64_t)b * K::NS + slot);
-                const double cq = (double)rd_ld(c, (int64_t)nbk * K::NS + ns);
+                const int64_t iq = cbase ? slot_index8(cbase, mask, nbk, ns) : (int64_t)nbk * K::NS + ns;
+                const double cp = (double)rd_ld(c, ip);
+                const double cq = (double)rd_ld(c, iq);
                 q = D * (cp - cq) * dx;
             }
         }
@@ -944,9 +988,9 @@ __global__ __launch_bounds__(256) void k_finish_rows(const double *part, int nro
 // Dirichlet voxels their held value (the highest flagged face wins on shared edges).
 template <typename T, int B>
 __global__ __launch_bounds__(256) void k_scatter(const BlockInfo *info, const uint64_t *mask,
-                                                 const GeomInfo *geom, int nb, const float *dense,
-                                                 T *field, uint32_t dir, float d0, float d1,
-                                                 float d2, float d3, float d4, float d5)
+                                                 const uint32_t *cbase, const GeomInfo *geom, int nb,
+                                                 const float *dense, T *field, uint32_t dir, float d0,
+                                                 float d1, float d2, float d3, float d4, float d5)
 {
     using K = Blk<B>;
     const int b = blockIdx.x;
@@ -961,22 +1005,25 @@ __global__ __launch_bounds__(256) void k_scatter(const BlockInfo *info, const ui
         const int lx = slot % B, ly = (slot / B) % B, lz = slot / (B * B);
         const int gx = bx * B + lx, gy = by * B + ly, gz = bz * B + lz;
         float v = 0.0f;
-        if (own_bit<B>(rec, slot)) {
+        const bool own = own_bit<B>(rec, slot);
+        if (own) {
             v = dense[((int64_t)gz * g.ny + gy) * g.nx + gx];
             const int onf[6] = {gx == 0, gx == g.nx - 1, gy == 0, gy == g.ny - 1, gz == 0,
                                 gz == g.nz - 1};
             for (int f = 0; f < 6; ++f)
                 if (((dir >> f) & 1u) && onf[f]) v = dv[f];
         }
-        rd_st(field, (int64_t)b * K::NS + slot, v);
+        // compact layout: only active voxels are stored
+        if (!cbase) rd_st(field, (int64_t)b * K::NS + slot, v);
+        else if (own) rd_st(field, slot_index8(cbase, mask, b, slot), v);
     }
 }
 
 // Block-major storage -> dense float32 (active voxels only; the caller zero-fills).
 template <typename T, int B>
 __global__ __launch_bounds__(256) void k_gather(const BlockInfo *info, const uint64_t *mask,
-                                                const GeomInfo *geom, int nb, const T *field,
-                                                float *dense)
+                                                const uint32_t *cbase, const GeomInfo *geom, int nb,
+                                                const T *field, float *dense)
 {
     using K = Blk<B>;
     const int b = blockIdx.x;
@@ -990,16 +1037,18 @@ __global__ __launch_bounds__(256) void k_gather(const BlockInfo *info, const uin
         if (!own_bit<B>(rec, slot)) continue;
         const int lx = slot % B, ly = (slot / B) % B, lz = slot / (B * B);
         const int gx = bx * B + lx, gy = by * B + ly, gz = bz * B + lz;
-        dense[((int64_t)gz * g.ny + gy) * g.nx + gx] = rd_ld(field, (int64_t)b * K::NS + slot);
+        const int64_t i = cbase ? slot_index8(cbase, mask, b, slot) : (int64_t)b * K::NS + slot;
+        dense[((int64_t)gz * g.ny + gy) * g.nx + gx] = rd_ld(field, i);
     }
 }
 
 // Set the Dirichlet voxels of one species in a block-major field (others untouched).
 template <typename T, int B>
 __global__ __launch_bounds__(256) void k_set_dirichlet(const BlockInfo *info, const uint64_t *mask,
-                                                       const GeomInfo *geom, int nb, T *field,
-                                                       uint32_t dir, float d0, float d1, float d2,
-                                                       float d3, float d4, float d5)
+                                                       const uint32_t *cbase, const GeomInfo *geom,
+                                                       int nb, T *field, uint32_t dir, float d0,
+                                                       float d1, float d2, float d3, float d4,
+                                                       float d5)
 {
     using K = Blk<B>;
     const int b = blockIdx.x;
@@ -1020,7 +1069,7 @@ __global__ __launch_bounds__(256) void k_set_dirichlet(const BlockInfo *info, co
         float v = 0.0f;
         for (int f = 0; f < 6; ++f)
             if (((dir >> f) & 1u) && onf[f]) { v = dv[f]; hit = true; }
-        if (hit) rd_st(field, (int64_t)b * K::NS + slot, v);
+        if (hit) rd_st(field, cbase ? slot_index8(cbase, mask, b, slot) : (int64_t)b * K::NS + slot, v);
     }
 }
 
@@ -1044,10 +1093,14 @@ void launch_step_s(const StepArgs &a, int groups, hipStream_t st)
     if constexpr (B == 8) {
         if (a.kernel == 1)
             hipLaunchKernelGGL((k_step8p<T, S>), dim3(a.grid), dim3(256), 0, st, a);
+        else if (a.kernel == 2 && a.cbase)
+            hipLaunchKernelGGL((k_step8z<T, S, false, true>), dim3(groups), dim3(256), 0, st, a);
+        else if (a.kernel == 3 && a.cbase)
+            hipLaunchKernelGGL((k_step8z<T, S, true, true>), dim3(groups), dim3(256), 0, st, a);
         else if (a.kernel == 2)
-            hipLaunchKernelGGL((k_step8z<T, S, false>), dim3(groups), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_step8z<T, S, false, false>), dim3(groups), dim3(256), 0, st, a);
         else if (a.kernel == 3)
-            hipLaunchKernelGGL((k_step8z<T, S, true>), dim3(groups), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_step8z<T, S, true, false>), dim3(groups), dim3(256), 0, st, a);
         else
             hipLaunchKernelGGL((k_step8<T, S>), dim3(groups), dim3(256), 0, st, a);
     } else {
@@ -1106,20 +1159,22 @@ int rd_reduce_rows(int, int nb) { return (nb + 3) / 4; }
 
 namespace {
 template <typename T, int B>
-int launch_plane_flux_t(const BlockInfo *info, const uint8_t *code, const void *c, int nb, int axis,
-                        int i0, double D, double dx, double *partial, hipStream_t st)
+int launch_plane_flux_t(const BlockInfo *info, const uint8_t *code, const uint32_t *cbase,
+                        const uint64_t *mask, const void *c, int nb, int axis, int i0, double D, double dx,
+                        double *partial, hipStream_t st)
 {
     hipLaunchKernelGGL((k_plane_flux<T, B>), dim3(rd_reduce_rows(B, nb)), dim3(256), 0, st, info, code,
-                       (const T *)c, nb, axis, i0, D, dx, partial);
+                       cbase, mask, (const T *)c, nb, axis, i0, D, dx, partial);
     return (int)hipGetLastError();
 }
 }  // namespace
 
-int rd_launch_plane_flux(int storage, int B, const BlockInfo *info, const uint8_t *code, const void *c,
-                         int nb, int axis, int i0, double D, double dx, double *partial, void *stream)
+int rd_launch_plane_flux(int storage, int B, const BlockInfo *info, const uint8_t *code,
+                         const uint32_t *cbase, const uint64_t *mask, const void *c, int nb, int axis,
+                         int i0, double D, double dx, double *partial, void *stream)
 {
     if (nb <= 0) return 0;
-    RD_DISPATCH(storage, B, launch_plane_flux_t, info, code, c, nb, axis, i0, D, dx, partial,
+    RD_DISPATCH(storage, B, launch_plane_flux_t, info, code, cbase, mask, c, nb, axis, i0, D, dx, partial,
                 (hipStream_t)stream);
 }
 
@@ -1151,59 +1206,59 @@ int rd_launch_finish_reduce(const double *partial, int nparts, int nlanes, doubl
 
 namespace {
 template <typename T, int B>
-int launch_scatter_t(const BlockInfo *info, const uint64_t *mask, const GeomInfo *geom, int nb,
-                     const float *dense, void *field, uint32_t dir, const float *dv, hipStream_t st)
+int launch_scatter_t(const BlockInfo *info, const uint64_t *mask, const uint32_t *cbase, const GeomInfo *geom,
+                     int nb, const float *dense, void *field, uint32_t dir, const float *dv, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_scatter<T, B>), dim3(nb), dim3(256), 0, st, info, mask, geom, nb, dense,
+    hipLaunchKernelGGL((k_scatter<T, B>), dim3(nb), dim3(256), 0, st, info, mask, cbase, geom, nb, dense,
                        (T *)field, dir, dv[0], dv[1], dv[2], dv[3], dv[4], dv[5]);
     return (int)hipGetLastError();
 }
 template <typename T, int B>
-int launch_gather_t(const BlockInfo *info, const uint64_t *mask, const GeomInfo *geom, int nb,
-                    const void *field, float *dense, hipStream_t st)
+int launch_gather_t(const BlockInfo *info, const uint64_t *mask, const uint32_t *cbase, const GeomInfo *geom,
+                    int nb, const void *field, float *dense, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_gather<T, B>), dim3(nb), dim3(256), 0, st, info, mask, geom, nb,
+    hipLaunchKernelGGL((k_gather<T, B>), dim3(nb), dim3(256), 0, st, info, mask, cbase, geom, nb,
                        (const T *)field, dense);
     return (int)hipGetLastError();
 }
 }  // namespace
 
 int rd_launch_scatter(int storage, int B, const BlockInfo *info, const uint64_t *mask,
-                      const GeomInfo *geom, int nb, const float *dense, void *field, uint32_t dir,
-                      float dir_value_per_face[6], void *stream)
+                      const uint32_t *cbase, const GeomInfo *geom, int nb, const float *dense, void *field,
+                      uint32_t dir, float dir_value_per_face[6], void *stream)
 {
     if (nb <= 0) return 0;
-    RD_DISPATCH(storage, B, launch_scatter_t, info, mask, geom, nb, dense, field, dir,
+    RD_DISPATCH(storage, B, launch_scatter_t, info, mask, cbase, geom, nb, dense, field, dir,
                 dir_value_per_face, (hipStream_t)stream);
 }
 
 int rd_launch_gather(int storage, int B, const BlockInfo *info, const uint64_t *mask,
-                     const GeomInfo *geom, int nb, const void *field, float *dense, int64_t ndense,
-                     void *stream)
+                     const uint32_t *cbase, const GeomInfo *geom, int nb, const void *field, float *dense,
+                     int64_t ndense, void *stream)
 {
     int rc = rd_launch_fill_u32(dense, 0u, ndense, stream);
     if (rc || nb <= 0) return rc;
-    RD_DISPATCH(storage, B, launch_gather_t, info, mask, geom, nb, field, dense,
+    RD_DISPATCH(storage, B, launch_gather_t, info, mask, cbase, geom, nb, field, dense,
                 (hipStream_t)stream);
 }
 
 namespace {
 template <typename T, int B>
-int launch_setdir_t(const BlockInfo *info, const uint64_t *mask, const GeomInfo *geom, int nb,
-                    void *field, uint32_t dir, const float *dv, hipStream_t st)
+int launch_setdir_t(const BlockInfo *info, const uint64_t *mask, const uint32_t *cbase, const GeomInfo *geom,
+                    int nb, void *field, uint32_t dir, const float *dv, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_set_dirichlet<T, B>), dim3(nb), dim3(256), 0, st, info, mask, geom, nb,
+    hipLaunchKernelGGL((k_set_dirichlet<T, B>), dim3(nb), dim3(256), 0, st, info, mask, cbase, geom, nb,
                        (T *)field, dir, dv[0], dv[1], dv[2], dv[3], dv[4], dv[5]);
     return (int)hipGetLastError();
 }
 }  // namespace
 
 int rd_launch_set_dirichlet(int storage, int B, const BlockInfo *info, const uint64_t *mask,
-                            const GeomInfo *geom, int nb, void *field, uint32_t dir,
+                            const uint32_t *cbase, const GeomInfo *geom, int nb, void *field, uint32_t dir,
                             const float dv[6], void *stream)
 {
     if (nb <= 0) return 0;
-    RD_DISPATCH(storage, B, launch_setdir_t, info, mask, geom, nb, field, dir, dv,
+    RD_DISPATCH(storage, B, launch_setdir_t, info, mask, cbase, geom, nb, field, dir, dv,
                 (hipStream_t)stream);
 }
 

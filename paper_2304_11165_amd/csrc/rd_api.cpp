@@ -214,11 +214,36 @@ extern "C" rd_status rd_sim_set_launch(rd_sim *sim, int graph_steps, int use_gra
     return RD_OK;
 }
 
+extern "C" rd_status rd_sim_set_layout(rd_sim *sim, int layout)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    if (layout != RD_LAYOUT_BLOCKS && layout != RD_LAYOUT_COMPACT) return rd_fail(RD_ERR_ARG, "unknown layout");
+    if (sim->ws) return rd_fail(RD_ERR_STATE, "set the layout before bind");
+    if (layout == RD_LAYOUT_COMPACT) {
+        if (sim->g->B != 8) return rd_fail(RD_ERR_SHAPE, "the compact layout needs 8^3 blocks");
+        // byte offsets of one species buffer (4 bytes per voxel at most) stay 32-bit
+        if (sim->g->n_active > (int64_t)(0xFFFFFF00u / 4) - 64)
+            return rd_fail(RD_ERR_SHAPE, "the compact layout holds at most 2^30 - 128 active voxels");
+        if (sim->kernel < 2) sim->kernel = 2;
+    } else if (sim->kernel == 4) {
+        sim->kernel = 2;  // the lane-exchange kernel needs the compact layout
+    }
+    sim->compact = layout == RD_LAYOUT_COMPACT;
+    sim->cbase_host.clear();
+    sim->ccode_host.clear();
+    sim->invalidate_graphs();
+    return RD_OK;
+}
+
 extern "C" rd_status rd_sim_set_kernel(rd_sim *sim, int kernel, int wg_per_cu)
 {
     if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
-    if (kernel < 0 || kernel > 3) return rd_fail(RD_ERR_ARG, "kernel in 0..3");
+    if (kernel < 0 || kernel > 4) return rd_fail(RD_ERR_ARG, "kernel in 0..4");
+    if (!sim->compact && kernel == 4)
+        return rd_fail(RD_ERR_STATE, "kernel 4 (lane exchange) runs on the compact layout only");
     if (wg_per_cu < 1 || wg_per_cu > 32) return rd_fail(RD_ERR_ARG, "wg_per_cu in 1..32");
+    if (sim->compact && kernel < 2)
+        return rd_fail(RD_ERR_STATE, "the compact layout runs the column kernels (2 or 3) only");
     sim->kernel = kernel;
     sim->wg_per_cu = wg_per_cu;
     sim->invalidate_graphs();
@@ -252,6 +277,9 @@ extern "C" rd_status rd_sim_bind(rd_sim *sim, void *dev_workspace, size_t bytes,
     if (!dev_workspace) return rd_fail(RD_ERR_WORKSPACE, "workspace is NULL");
     if (((uintptr_t)dev_workspace) % 256) return rd_fail(RD_ERR_WORKSPACE, "workspace not 256-byte aligned");
     if (checkpoint_slots < 0) return rd_fail(RD_ERR_ARG, "checkpoint_slots < 0");
+    if (sim->compact && (features & (RD_WS_SOLVER | RD_WS_ADJOINT | RD_WS_DIFFUSIVITY)))
+        return rd_fail(RD_ERR_STATE, "the compact layout supports stepping, balances, fluxes and region "
+                                     "masses; bind the block layout for the solver, adjoint or a factor");
     const SimLayout L = sim_layout(*sim, features, checkpoint_slots);
     if (bytes < L.total)
         return rd_fail(RD_ERR_WORKSPACE, "workspace has " + std::to_string(bytes) + " bytes, needs " +
@@ -286,8 +314,15 @@ SimLayout sim_layout(const rd_sim &s, uint32_t features, int64_t cp_slots)
     L.info = off; off = align256(off + sizeof(BlockInfo) * (size_t)std::max<int64_t>(nb, 1));
     L.mask = off; off = align256(off + 8 * (size_t)mask_words(g.B) * (size_t)std::max<int64_t>(nb, 1));
     L.geom = off; off = align256(off + sizeof(GeomInfo));
-    L.code = off; off = align256(off + (size_t)std::max<int64_t>(nb, 1) * NS);
-    L.field_elems = nb * NS;
+    if (s.compact) {
+        // only the active voxels: codes and each species' values in list and slot order
+        L.code = off; off = align256(off + (size_t)std::max<int64_t>(g.n_active, 1));
+        L.cbase = off; off = align256(off + 4 * (size_t)(nb + 1));
+        L.field_elems = std::max<int64_t>((g.n_active + 63) / 64 * 64, 64);
+    } else {
+        L.code = off; off = align256(off + (size_t)std::max<int64_t>(nb, 1) * NS);
+        L.field_elems = nb * NS;
+    }
     for (int p = 0; p < 2; ++p) {
         L.field[p] = off;
         off = align256(off + es * (size_t)L.field_elems * s.S);
@@ -351,7 +386,15 @@ rd_status rd_sim::upload(bool index)
         HIPCHK(hipMemcpyAsync(ws + L.info, G.info.data(), sizeof(BlockInfo) * nb, hipMemcpyHostToDevice, stream));
         HIPCHK(hipMemcpyAsync(ws + L.mask, G.mask.data(), 8 * mask_words(G.B) * nb, hipMemcpyHostToDevice,
                               stream));
-        HIPCHK(hipMemcpyAsync(ws + L.code, G.code.data(), G.code.size(), hipMemcpyHostToDevice, stream));
+        if (compact) {
+            if (cbase_host.size() != (size_t)nb + 1) rd_geometry_compact_index(&G, cbase_host, ccode_host);
+            HIPCHK(hipMemcpyAsync(ws + L.code, ccode_host.data(), ccode_host.size(), hipMemcpyHostToDevice,
+                                  stream));
+            HIPCHK(hipMemcpyAsync(ws + L.cbase, cbase_host.data(), 4 * cbase_host.size(), hipMemcpyHostToDevice,
+                                  stream));
+        } else {
+            HIPCHK(hipMemcpyAsync(ws + L.code, G.code.data(), G.code.size(), hipMemcpyHostToDevice, stream));
+        }
         GeomInfo gi{(int32_t)G.nx, (int32_t)G.ny, (int32_t)G.nz, 0};
         geom_host = gi;
         HIPCHK(hipMemcpyAsync(ws + L.geom, &geom_host, sizeof(GeomInfo), hipMemcpyHostToDevice, stream));
@@ -384,8 +427,9 @@ rd_status rd_sim::apply_dirichlet(int s)
     float dv[6];
     for (int f = 0; f < 6; ++f) dv[f] = (float)dirval[s][f];
     LAUNCHCHK(rd_launch_set_dirichlet(storage, g->B, (const BlockInfo *)(ws + L.info),
-                                      (const uint64_t *)(ws + L.mask), (const GeomInfo *)(ws + L.geom),
-                                      (int)g->nb(), field_ptr(cur, s), dir[s], dv, stream));
+                                      (const uint64_t *)(ws + L.mask), cbase_ptr(),
+                                      (const GeomInfo *)(ws + L.geom), (int)g->nb(), field_ptr(cur, s),
+                                      dir[s], dv, stream));
     return RD_OK;
 }
 
@@ -401,6 +445,7 @@ StepArgs rd_sim::step_args(double dt, int in_buf) const
     a.info = (const BlockInfo *)(ws + L.info);
     a.mask = (const uint64_t *)(ws + L.mask);
     a.code = (const uint8_t *)(ws + L.code);
+    a.cbase = cbase_ptr();
     a.geom = (const GeomInfo *)(ws + L.geom);
     a.cin = field_ptr(in_buf, 0);
     a.cout = field_ptr(1 - in_buf, 0);
@@ -485,6 +530,8 @@ rd_status rd_sim::launch_steps(double dt, int64_t n)
             DiffArgs da{a, (const float *)(ws + L.diff), {0.0f, 0.0f, 0.0f, 0.0f}};
             for (int s = 0; s < S; ++s) da.sink[s] = band_on ? (float)(dt * sink[s]) : 0.0f;
             LAUNCHCHK(rd_launch_step_diff(storage, g->B, da, column, stream));
+        } else if (compact && kernel == 4) {
+            LAUNCHCHK(rd_launch_step_lanes(storage, a, stream));
         } else {
             LAUNCHCHK(rd_launch_step(storage, g->B, a, stream));
         }
@@ -570,6 +617,7 @@ rd_status rd_sim::balance(int s, double out[RD_NRED])
     a.info = (const BlockInfo *)(ws + L.info);
     a.mask = (const uint64_t *)(ws + L.mask);
     a.code = (const uint8_t *)(ws + L.code);
+    a.cbase = cbase_ptr();
     a.geom = (const GeomInfo *)(ws + L.geom);
     a.c = field_ptr(cur, 0);
     a.sstride = L.field_elems;
@@ -614,7 +662,7 @@ extern "C" rd_status rd_sim_set_field(rd_sim *sim, int species, const float *dev
     float dv[6];
     for (int f = 0; f < 6; ++f) dv[f] = (float)sim->dirval[species][f];
     LAUNCHCHK(rd_launch_scatter(sim->storage, sim->g->B, (const BlockInfo *)(sim->ws + sim->L.info),
-                                (const uint64_t *)(sim->ws + sim->L.mask),
+                                (const uint64_t *)(sim->ws + sim->L.mask), sim->cbase_ptr(),
                                 (const GeomInfo *)(sim->ws + sim->L.geom), (int)sim->g->nb(),
                                 dev_dense, sim->field_ptr(sim->cur, species), sim->dir[species], dv,
                                 sim->stream));
@@ -734,7 +782,7 @@ extern "C" rd_status rd_sim_get_field(const rd_sim *sim, int species, float *dev
     if (!dev_dense) return rd_fail(RD_ERR_ARG, "field pointer is NULL");
     const rd_geometry &G = *sim->g;
     LAUNCHCHK(rd_launch_gather(sim->storage, G.B, (const BlockInfo *)(sim->ws + sim->L.info),
-                               (const uint64_t *)(sim->ws + sim->L.mask),
+                               (const uint64_t *)(sim->ws + sim->L.mask), sim->cbase_ptr(),
                                (const GeomInfo *)(sim->ws + sim->L.geom), (int)G.nb(),
                                sim->field_ptr(sim->cur, species), dev_dense, G.nx * G.ny * G.nz,
                                sim->stream));
@@ -800,7 +848,8 @@ extern "C" rd_status rd_sim_plane_flux(rd_sim *sim, int species, int axis, int64
                                           stream));
     } else {
         LAUNCHCHK(rd_launch_plane_flux((int)sim->storage, G.B, (const BlockInfo *)(ws + L.info),
-                                       (const uint8_t *)(ws + L.code), sim->field_ptr(sim->cur, species), nb,
+                                       (const uint8_t *)(ws + L.code), sim->cbase_ptr(),
+                                       (const uint64_t *)(ws + L.mask), sim->field_ptr(sim->cur, species), nb,
                                        axis, (int)i0, sim->D[species], G.dx, part, stream));
         LAUNCHCHK(rd_launch_finish_reduce(part, rd_reduce_rows(G.B, nb), 1, (double *)(ws + L.mid), res,
                                           stream));
@@ -862,8 +911,12 @@ extern "C" rd_status rd_sim_autotune(rd_sim *sim, double dt, int64_t trial_steps
     std::vector<LaunchCfg> cands;
     const int gs[2] = {16, 64};
     for (int gi = 0; gi < 2; ++gi) {
-        for (int xcd = 0; xcd < 2; ++xcd) cands.push_back({0, xcd != 0, true, 8, gs[gi]});
-        if (sim->g->B == 8) {
+        if (!sim->compact)  // the compact layout has only the column kernels
+            for (int xcd = 0; xcd < 2; ++xcd) cands.push_back({0, xcd != 0, true, 8, gs[gi]});
+        if (sim->compact) {
+            for (int k = 2; k <= 4; ++k)
+                for (int xcd = 0; xcd < 2; ++xcd) cands.push_back({k, xcd != 0, true, 8, gs[gi]});
+        } else if (sim->g->B == 8) {
             for (int k = 2; k <= 3; ++k)
                 for (int xcd = 0; xcd < 2; ++xcd) cands.push_back({k, xcd != 0, true, 8, gs[gi]});
             for (int wg : {2, 4, 8}) cands.push_back({1, true, true, wg, gs[gi]});
@@ -919,7 +972,7 @@ uint64_t tune_key(const rd_sim *sim)
     const rd_geometry &g = *sim->g;
     const int64_t dims[5] = {g.nx, g.ny, g.nz, (int64_t)g.B, g.nb()};
     mix(dims, sizeof(dims));
-    const int meta[3] = {(int)sim->storage, sim->S, (int)sim->reactions.size()};
+    const int meta[4] = {(int)sim->storage, sim->S, (int)sim->reactions.size(), sim->compact ? 1 : 0};
     mix(meta, sizeof(meta));
     for (int s = 0; s < sim->S; ++s) {
         const int robin = sim->robin[s] != 0.0;
@@ -949,8 +1002,9 @@ extern "C" rd_status rd_sim_autotune_cached(rd_sim *sim, double dt, int64_t tria
             int kernel, xcd, graph, wg, gsteps;
             double m;
             if (sscanf(line, "%15s %31s %d %d %d %d %d %lf", tag, k, &kernel, &xcd, &graph, &wg, &gsteps, &m) == 8 &&
-                strcmp(tag, "rdtune1") == 0 && strcmp(k, want) == 0 && kernel >= 0 && kernel <= 3 && wg >= 1 &&
-                gsteps >= 1 && !(sim->g->B == 4 && kernel != 0)) {
+                strcmp(tag, "rdtune1") == 0 && strcmp(k, want) == 0 && kernel >= 0 && kernel <= 4 && wg >= 1 &&
+                gsteps >= 1 && !(sim->g->B == 4 && kernel != 0) && !(sim->compact && kernel < 2) &&
+                !(!sim->compact && kernel == 4)) {
                 c = {kernel, xcd != 0, graph != 0, wg, gsteps};
                 ms = m;
                 found = true;

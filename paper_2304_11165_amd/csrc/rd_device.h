@@ -258,6 +258,30 @@ __device__ __forceinline__ void rd_st2(_Float16 *p, int64_t i, float a, float b,
     *reinterpret_cast<half2_t *>(p + i) = v;
 }
 
+// ---- compact layout (B = 8) --------------------------------------------------
+// A block stores only its active voxels, in slot order, starting at cbase[b]; the
+// plane prefix counts sit in words 14-15 of the block's mask record.
+// Number of set bits of the wave-uniform word W in the lanes below this one.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t W)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(W >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)W, 0u));
+}
+// Active slots below plane z of a block (from its mask record).
+__device__ __forceinline__ uint32_t plane_prefix(const uint64_t *rec, int z)
+{
+    return (uint32_t)(rec[14 + (z >> 2)] >> (16 * (z & 3))) & 0xffffu;
+}
+// Element index of (active) slot `slot` of block b: block-major (cbase NULL) or compact.
+__device__ __forceinline__ int64_t slot_index8(const uint32_t *cbase, const uint64_t *mask, int64_t b,
+                                               int slot)
+{
+    if (!cbase) return b * 512 + slot;
+    const uint64_t *rec = mask + b * 16;
+    const int z = slot >> 6, bit = slot & 63;
+    const uint64_t below = bit ? (rec[z] & (~0ull >> (64 - bit))) : 0ull;
+    return (int64_t)cbase[b] + plane_prefix(rec, z) + (uint32_t)__popcll(below);
+}
+
 // ---- block geometry helpers -------------------------------------------------
 template <int B>
 struct Blk {

@@ -30,3 +30,7 @@ struct rd_geometry {
 // Builds the index (geometry.cpp).
 rd_status rd_geometry_build(const uint8_t *image, int64_t nx, int64_t ny, int64_t nz, int B,
                             rd_geometry *g);
+// Compact layout (B = 8): cbase[b] = index of block b's first active voxel when only
+// active voxels are stored, in list and slot order (cbase[nb] = active voxels), and the
+// neighbour codes of the active voxels in that order.
+void rd_geometry_compact_index(const rd_geometry *g, std::vector<uint32_t> &cbase, std::vector<uint8_t> &ccode);

@@ -3,7 +3,10 @@
 // Device layout of a bound simulation (all inside the caller's workspace):
 //   info   BlockInfo[nb]            neighbour list indices + block position
 //   mask   uint64[nb * MW(B)]       own active bits, then face bits of the neighbours
-//   fields T[2][S][nb][B^3]         ping-pong buffers, block-major, slot (lz*B+ly)*B+lx
+//   fields T[2][S][nb][B^3]         ping-pong buffers, block-major, slot (lz*B+ly)*B+lx;
+//                                   compact layout (B = 8): T[2][S][n_active'] holding
+//                                   only the active voxels, block by block in slot
+//                                   order, block b starting at cbase[b]
 //   part   double[...]              per-workgroup FP64 partials of reductions
 //   res    double[32]               reduction results
 //   (+ solver / adjoint vectors when requested)
@@ -24,7 +27,8 @@ struct BlockInfo {
 
 // Mask record (uint64 words per block).
 //  B = 8: words 0..7 own bits (word lz holds bit ly*8+lx), words 8..13 face bits of the
-//         six neighbours (f = 0..5), words 14..15 zero.
+//         six neighbours (f = 0..5), words 14..15 the active slots below each plane
+//         (16 bits per plane z, at bit 16 (z % 4) of word 14 + z / 4).
 //  B = 4: word 0 own bits (bit (lz*4+ly)*4+lx); word 1 faces 0..3 (16 bits each, face f
 //         at bit 16*f); word 2 faces 4..5 (face 4 at bit 0, face 5 at bit 16).
 // Face bit index of face f: x faces (f=0,1): lz*B+ly; y faces: lz*B+lx; z faces: ly*B+lx.
@@ -50,6 +54,8 @@ struct StepArgs {
     const BlockInfo *info;
     const uint64_t *mask;
     const uint8_t *code;   // per-slot neighbour codes (bits 0-5 neighbours, bit 6 active)
+    const uint32_t *cbase; // compact layout: first voxel of each block (nb + 1); NULL:
+                           // block-major layout with every slot stored
     const GeomInfo *geom;  // indexed by geometry id
     const void *cin;       // T*, species-major
     void *cout;
@@ -74,6 +80,7 @@ struct ReduceArgs {
     const BlockInfo *info;
     const uint64_t *mask;
     const uint8_t *code;  // per-slot neighbour codes (as in StepArgs)
+    const uint32_t *cbase;  // compact layout (as in StepArgs) or NULL
     const GeomInfo *geom;
     const void *c;      // T*
     int64_t sstride;
@@ -92,22 +99,26 @@ struct ReduceArgs {
 // ---- launchers (k_step.hip) -------------------------------------------------
 // storage: 0 fp32, 1 bf16, 2 fp16.  All return a hipError_t as int.
 int rd_launch_step(int storage, int B, const StepArgs &a, void *stream);
+// Compact layout, B = 8: the column step with lane-exchanged neighbours (k_compact.hip).
+int rd_launch_step_lanes(int storage, const StepArgs &a, void *stream);
 // rows of partials written by rd_launch_reduce (one per workgroup of four blocks)
 int rd_reduce_rows(int B, int nb);
 int rd_launch_reduce(int storage, int B, const ReduceArgs &a, void *stream);
 // one FP64 partial per rd_reduce_rows row: flux of field c through plane i0 | i0 + 1
-int rd_launch_plane_flux(int storage, int B, const BlockInfo *info, const uint8_t *code, const void *c,
-                         int nb, int axis, int i0, double D, double dx, double *partial, void *stream);
+int rd_launch_plane_flux(int storage, int B, const BlockInfo *info, const uint8_t *code,
+                         const uint32_t *cbase, const uint64_t *mask, const void *c, int nb, int axis,
+                         int i0, double D, double dx, double *partial, void *stream);
 // Fixed-order sums of partial[nparts][nlanes] (nlanes <= 16) into out[nlanes]; mid is
 // scratch of RD_FINISH_GROUPS * nlanes doubles.
 #define RD_FINISH_GROUPS 256
 int rd_launch_finish_reduce(const double *partial, int nparts, int nlanes, double *mid, double *out,
                             void *stream);
+// cbase: compact layout (B = 8) or NULL (block-major), as in StepArgs
 int rd_launch_scatter(int storage, int B, const BlockInfo *info, const uint64_t *mask,
-                      const GeomInfo *geom, int nb, const float *dense, void *field,
+                      const uint32_t *cbase, const GeomInfo *geom, int nb, const float *dense, void *field,
                       uint32_t dir, float dir_value_per_face[6], void *stream);
 int rd_launch_gather(int storage, int B, const BlockInfo *info, const uint64_t *mask,
-                     const GeomInfo *geom, int nb, const void *field, float *dense,
+                     const uint32_t *cbase, const GeomInfo *geom, int nb, const void *field, float *dense,
                      int64_t ndense, void *stream);
 int rd_launch_fill_u32(void *ptr, uint32_t value, int64_t n_words, void *stream);
 int rd_launch_add_u32(uint32_t *ptr, uint32_t add, void *stream);

@@ -31,6 +31,7 @@ struct Reaction {
 // Byte offsets of every array inside the caller's workspace.
 struct SimLayout {
     size_t info, mask, geom, code;
+    size_t cbase;         // compact layout: first voxel of each block, uint32[nb + 1]
     size_t field[2];
     int64_t field_elems;  // nb * B^3
     int nparts;
@@ -70,6 +71,9 @@ struct rd_sim {
     int wg_per_cu = 8;    // resident workgroups per CU of the persistent grid
     int n_cu = 256;       // compute units of the bound device
     bool sround = false;  // stochastic rounding on store (BF16 / FP16 storage)
+    bool compact = false; // fields hold only the active voxels (B = 8; rd_sim_set_layout)
+    std::vector<uint32_t> cbase_host;  // compact index, built at bind
+    std::vector<uint8_t> ccode_host;
     uint32_t seed = 0;
     bool diff_on = false;  // a diffusivity factor is set (inhomogeneous diffusion)
     double e_max = 0.0;    // its largest value over the active voxels
@@ -100,6 +104,7 @@ struct rd_sim {
     rd_status upload(bool index = true);
     rd_status apply_dirichlet(int s);
     void *field_ptr(int buf, int s) const;
+    const uint32_t *cbase_ptr() const { return compact ? (const uint32_t *)(ws + L.cbase) : nullptr; }
     StepArgs step_args(double dt, int in_buf) const;
     double lambda_max() const;
     rd_status check_dt(double dt) const;
@@ -112,5 +117,5 @@ struct rd_sim {
 };
 
 int rd_launch_set_dirichlet(int storage, int B, const BlockInfo *info, const uint64_t *mask,
-                            const GeomInfo *geom, int nb, void *field, uint32_t dir,
+                            const uint32_t *cbase, const GeomInfo *geom, int nb, void *field, uint32_t dir,
                             const float dv[6], void *stream);

@@ -86,11 +86,81 @@ rd_status push_scal(const CgArgs &a, const std::vector<double> &hs, hipStream_t 
     return RD_OK;
 }
 
+// The CHECK_EVERY iterations between two checks: every scalar they need (alpha, beta,
+// the live flags) is computed and read on the device, so the segment is one fixed
+// sequence of launches.  B = 8 alternates the two direction buffers; `a` leaves with
+// them in the order the next segment starts from.
+rd_status cg_segment(CgArgs &a, int storage, int B, hipStream_t st)
+{
+    for (int k = 0; k < CHECK_EVERY; ++k) {
+        if (B == 8) {
+            // p <- r + beta p fused into the matvec (beta = 0 on the first pass, where
+            // p = r already), written to the other p buffer
+            LAUNCHCHK(cg_launch_matvec_fused(storage, a, st));
+            std::swap(a.p, a.p2);
+        } else {
+            // the same order: p <- r + beta p first (so that between iterations p is
+            // the last direction and r the newest residual, as with B = 8)
+            LAUNCHCHK(cg_launch_pupdate(storage, B, a, st));
+            LAUNCHCHK(cg_launch_matvec(storage, B, a, st));
+        }
+        LAUNCHCHK(cg_launch_segsum(a, CG_PAP, -1, 0, st));
+        LAUNCHCHK(cg_launch_update(storage, B, a, st));
+        LAUNCHCHK(cg_launch_segsum(a, CG_RRNEW, -1, 1, st));
+    }
+    return RD_OK;
+}
+
+// Segments captured once as hipGraphs (one per order of the two direction buffers) and
+// replayed; kernels only (no memset nodes).
+struct SegmentGraphs {
+    hipStream_t cap = nullptr;
+    struct Entry {
+        void *p;
+        hipGraphExec_t exec;
+    };
+    std::vector<Entry> g;
+    ~SegmentGraphs()
+    {
+        for (auto &e : g) hipGraphExecDestroy(e.exec);
+        if (cap) hipStreamDestroy(cap);
+    }
+    rd_status run(CgArgs &a, int storage, int B, hipStream_t st)
+    {
+        Entry *hit = nullptr;
+        for (auto &e : g)
+            if (e.p == a.p) hit = &e;
+        if (!hit) {
+            if (!cap) HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            CgArgs c = a;
+            HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+            rd_status s = cg_segment(c, storage, B, cap);
+            hipGraph_t graph = nullptr;
+            const hipError_t ce = hipStreamEndCapture(cap, &graph);
+            if (s != RD_OK) {
+                if (graph) hipGraphDestroy(graph);
+                return s;
+            }
+            HIPCHK(ce);
+            Entry e{a.p, nullptr};
+            const hipError_t ie = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            HIPCHK(ie);
+            g.push_back(e);
+            hit = &g.back();
+        }
+        HIPCHK(hipGraphLaunch(hit->exec, st));
+        if (B == 8 && (CHECK_EVERY & 1)) std::swap(a.p, a.p2);
+        return RD_OK;
+    }
+};
+
 // Runs CG on every geometry of `a` (Dirichlet values already in x) from a linear
 // ramp, stopping each geometry at rel. residual <= tol, stagnation or max_iters.
+// use_graph: replay each segment of CHECK_EVERY iterations as a captured graph.
 rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axis, double tol,
                  int64_t max_iters, const std::vector<GeomMeta> &meta, std::vector<CgOut> &out,
-                 int stall_checks = STALL_CHECKS, bool want_tau = true)
+                 int stall_checks = STALL_CHECKS, bool want_tau = true, bool use_graph = true)
 {
     CgArgs a = args;  // B = 8 swaps the two p buffers every iteration
     const int n = a.ngeom;
@@ -120,22 +190,12 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
         }
     }
     if ((s = push_scal(a, hs, st)) != RD_OK) return s;
+    SegmentGraphs graphs;
     while (live > 0) {
-        for (int k = 0; k < CHECK_EVERY; ++k) {
-            if (B == 8) {
-                // p <- r + beta p fused into the matvec (beta = 0 on the first pass, where
-                // p = r already), written to the other p buffer
-                LAUNCHCHK(cg_launch_matvec_fused(storage, a, st));
-                std::swap(a.p, a.p2);
-            } else {
-                // the same order: p <- r + beta p first (so that between iterations p is
-                // the last direction and r the newest residual, as with B = 8)
-                LAUNCHCHK(cg_launch_pupdate(storage, B, a, st));
-                LAUNCHCHK(cg_launch_matvec(storage, B, a, st));
-            }
-            LAUNCHCHK(cg_launch_segsum(a, CG_PAP, -1, 0, st));
-            LAUNCHCHK(cg_launch_update(storage, B, a, st));
-            LAUNCHCHK(cg_launch_segsum(a, CG_RRNEW, -1, 1, st));
+        if (use_graph) {
+            if ((s = graphs.run(a, storage, B, st)) != RD_OK) return s;
+        } else {
+            if ((s = cg_segment(a, storage, B, st)) != RD_OK) return s;
         }
         bool replace = false, rescale = false;
         // true residual b - A x in FP64 (the recursive one drifts in the storage type's
@@ -593,7 +653,7 @@ static rd_status adjoint_impl(rd_sim *sim, const float *dev_seed, int seed_mode,
     float zero6[6] = {0, 0, 0, 0, 0, 0};
     float *seed = (float *)(ws + sim->L.target);
     LAUNCHCHK(rd_launch_scatter(0, B, (const BlockInfo *)(ws + sim->L.info),
-                                (const uint64_t *)(ws + sim->L.mask), (const GeomInfo *)(ws + sim->L.geom),
+                                (const uint64_t *)(ws + sim->L.mask), nullptr, (const GeomInfo *)(ws + sim->L.geom),
                                 nb, dev_seed, seed, 0u, zero6, stream));
     // forward with checkpoints
     for (int64_t j = 0; j < ncp; ++j) {

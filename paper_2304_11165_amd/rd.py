@@ -38,7 +38,8 @@ STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2}
 RD_WS_SOLVER = 1
 RD_WS_ADJOINT = 2
 RD_WS_DIFFUSIVITY = 4
-KERNELS = ("block", "persistent", "column", "column_xch")  # B = 8 step kernels, by number
+# B = 8 step kernels, by number (column_lanes: compact layout only)
+KERNELS = ("block", "persistent", "column", "column_xch", "column_lanes")
 
 _SIGS = {
     "rd_status_string": ([ci], ctypes.c_char_p),
@@ -69,6 +70,7 @@ _SIGS = {
     "rd_sim_region_mass": ([P, ci, P, P], ci),
     "rd_sdf_scratch_bytes": ([i64, i64, i64, P], ci),
     "rd_sdf_from_image": ([P, i64, i64, i64, f64, P, P, ctypes.c_size_t, P], ci),
+    "rd_sim_set_layout": ([P, ci], ci),
     "rd_sim_frap_curve": ([P, ci, P, f64, i64, i64, P], ci),
     "rd_frap_fit": ([i64, P, P, i64, f64, P, f64, P, P], ci),
     "rd_sim_get_field": ([P, ci, P], ci),
@@ -274,6 +276,13 @@ class Sim:
         out = {k: v.value for k, v in zip(keys, vals)}
         out["kernel"] = KERNELS[out["kernel"]]
         return out
+
+    def set_layout(self, layout="blocks"):
+        """Field layout in HBM: "blocks" (every slot of the stored blocks) or "compact"
+        (only the active voxels); before bind."""
+        _check(_lib.rd_sim_set_layout(self.handle, {"blocks": 0, "compact": 1}[layout]),
+               "rd_sim_set_layout")
+        return self
 
     def set_kernel(self, kernel="block", wg_per_cu=8):
         """B = 8 step kernel: "block" (one workgroup per block), "persistent",
@@ -604,3 +613,4 @@ def sdf_from_image(image, dx=1.0, stream=None):
     for t in (img, scratch, out):
         t.record_stream(st)
     return out
+

@@ -220,3 +220,34 @@ def test_new_entry_points_validate_without_gpu(rd):
         rd._check(rd._lib.rd_sdf_from_image(None, 4, 4, 4, ctypes.c_double(1.0), None, None, 0, None),
                   "rd_sdf_from_image")
     assert e.value.name == "RD_ERR_ARG"
+
+
+def test_compact_layout_validation_without_gpu(rd):
+    img, _ = W.boolean_spheres(40, 0.4, 2.0, 5.0, seed=3)
+    g8 = rd.Geometry(img, None, 1.0, 8)
+    blocks, compact = rd.Sim(g8, "fp32"), rd.Sim(g8, "fp32")
+    for s in (blocks, compact):
+        s.add_species(1.0)
+        s.add_species(0.5)
+    with pytest.raises(rd.RDError) as e:
+        rd._check(rd._lib.rd_sim_set_layout(compact.handle, 2), "rd_sim_set_layout")
+    assert e.value.name == "RD_ERR_ARG"
+    compact.set_layout("compact")
+    # the block kernels do not exist for the compact layout
+    with pytest.raises(rd.RDError) as e:
+        compact.set_kernel("block")
+    assert e.value.name == "RD_ERR_STATE"
+    compact.set_kernel("column_xch")
+    # the fields shrink from whole blocks to the active voxels (2 buffers x 2 species x 4 B)
+    st = g8.stats()
+    saved = blocks.workspace_bytes() - compact.workspace_bytes()
+    slots = st["n_blocks"] * 512
+    assert saved >= 2 * 2 * 4 * (slots - st["n_active"]) - 2 * 2 * 4 * 64 - 4096
+    assert saved > 0
+    # 4^3 blocks have no compact form
+    g4 = rd.Geometry(img, None, 1.0, 4)
+    s4 = rd.Sim(g4, "fp32")
+    s4.add_species(1.0)
+    with pytest.raises(rd.RDError) as e:
+        s4.set_layout("compact")
+    assert e.value.name == "RD_ERR_SHAPE"

@@ -43,10 +43,12 @@ def test_adjoint_vs_oracle(rd, oracle_mod, B):
     c0 = prob.initial()[0]
     Lo, gDo, gko, _ = oracle_mod.adjoint_decay(img, D, k, dt, steps, c0, target.astype(np.float64),
                                                stride=50)
-    print(f"B={B}: loss {L:.8e} vs {Lo:.8e}; dL/dD {gD:.8e} vs {gDo:.8e}; dL/dk {gk:.8e} vs {gko:.8e}")
-    assert L == pytest.approx(Lo, rel=1e-4)
-    assert gD == pytest.approx(gDo, rel=1e-4)
-    assert gk == pytest.approx(gko, rel=1e-4)
+    print(f"B={B}: loss {L:.10e} vs {Lo:.10e}; dL/dD {gD:.10e} vs {gDo:.10e}; dL/dk {gk:.10e} vs "
+          f"{gko:.10e}")
+    # measured: loss 4.5e-8, gradients 3e-9 relative (FP32 fields, FP64 sums, 120 steps)
+    assert L == pytest.approx(Lo, rel=5e-7)
+    assert gD == pytest.approx(gDo, rel=1e-7)
+    assert gk == pytest.approx(gko, rel=1e-7)
 
 
 def test_adjoint_checkpoint_stride_bitwise(rd, oracle_mod):
@@ -84,9 +86,11 @@ def test_decay_workload_reduced(rd, oracle_mod):
     prob = oracle_mod.Problem(img, [0.8], dirichlet=w.dirichlet)
     Lo, gDo, gko, _ = oracle_mod.adjoint_decay(img, 0.8, 0.02, w.dt, w.steps, prob.initial()[0],
                                                target.astype(np.float64), stride=50)
-    print(f"decay64: loss {L:.6e}/{Lo:.6e} dD {gD:.6e}/{gDo:.6e} dk {gk:.6e}/{gko:.6e}")
-    assert gD == pytest.approx(gDo, rel=1e-4)
-    assert gk == pytest.approx(gko, rel=1e-4)
+    print(f"decay64: loss {L:.10e}/{Lo:.10e} dD {gD:.10e}/{gDo:.10e} dk {gk:.10e}/{gko:.10e}")
+    # measured: loss 1.2e-6, dL/dD 6e-7, dL/dk < 4e-7 relative after 2000 FP32 steps
+    assert L == pytest.approx(Lo, rel=5e-6)
+    assert gD == pytest.approx(gDo, rel=3e-6)
+    assert gk == pytest.approx(gko, rel=3e-6)
 
 
 def test_autograd_function(rd, oracle_mod):

@@ -50,10 +50,11 @@ def test_vs_oracle(rd, oracle_mod, B, kernel):
     err = rel_l2(ge, geo, img != 0)
     print(f"B={B}: loss {L:.8e} vs {Lo:.8e}; dL/dD {gD:.8e} vs {gDo:.8e}; dL/dk {gk:.8e} vs "
           f"{gko:.8e}; dL/de rel L2 {err:.2e}")
-    assert L == pytest.approx(Lo, rel=1e-4)
-    assert gD == pytest.approx(gDo, rel=1e-4)
-    assert gk == pytest.approx(gko, rel=1e-4)
-    assert err < 1e-3
+    # measured: loss 1.3e-7, dL/dD 8.5e-8, dL/dk 8.2e-8, dL/de 2.35e-7 relative
+    assert L == pytest.approx(Lo, rel=1e-6)
+    assert gD == pytest.approx(gDo, rel=5e-7)
+    assert gk == pytest.approx(gko, rel=5e-7)
+    assert err < 1e-6
     assert np.all(ge[img == 0] == 0)
 
 
@@ -66,30 +67,38 @@ def test_checkpoint_stride_bitwise(rd, oracle_mod):
 
 
 def test_chain_rule_to_smooth_d_parameters(rd, oracle_mod):
-    """dL/dg1 from dL/de and the derivative of D(phi) == central differences of the
-    GPU loss in g1."""
+    """dL/dg1 and dL/dg2 from the GPU's dL/de and the derivative of D(phi) == central
+    differences (h = 1e-3) of the FP64 oracle's loss in g1 and g2."""
     import torch
 
     img, _, target = _case(oracle_mod, n=20, seed=11, steps=60)
     phi = oracle_mod.signed_distance(img, 1.0)
     d_min, d_max, g1, g2 = 0.1, 0.9, -2.0, 2.0
     dt, steps = 0.08, 60
-
-    def run(g1_, want_grad):
-        _, s = make_gpu(rd, img, [1.0], dirichlet={(0, 0): 1.0}, kernel="column",
-                        features=rd.RD_WS_ADJOINT | rd.RD_WS_DIFFUSIVITY, checkpoint_slots=20)
-        s.set_diffusivity_sdf(phi, d_min, d_max, g1_, g2)
-        if want_grad:
-            return s.adjoint_factor(target, steps, dt, 10)
-        return s.adjoint(target, steps, dt, 10)[0]
-
-    _, _, _, ge = run(g1, True)
-    sig = torch.sigmoid(torch.as_tensor(g1 + g2 * phi.astype(np.float64), device=ge.device))
+    _, s = make_gpu(rd, img, [1.0], dirichlet={(0, 0): 1.0}, kernel="column",
+                    features=rd.RD_WS_ADJOINT | rd.RD_WS_DIFFUSIVITY, checkpoint_slots=20)
+    s.set_diffusivity_sdf(phi, d_min, d_max, g1, g2)
+    _, _, _, ge = s.adjoint_factor(target, steps, dt, 10)
+    ph = torch.as_tensor(phi.astype(np.float64), device=ge.device)
+    sig = torch.sigmoid(g1 + g2 * ph)
     dg1 = float(torch.sum(ge * d_max * sig * (1 - sig)))
+    dg2 = float(torch.sum(ge * d_max * sig * (1 - sig) * ph))
+
+    def oracle_loss(g1_, g2_):
+        eps = oracle_mod.smooth_diffusivity(phi.astype(np.float64), d_min, d_max, g1_, g2_)
+        prob = oracle_mod.Problem(img, [1.0], dirichlet={(0, 0): 1.0}, eps=eps)
+        cN = prob.run(prob.initial(), dt, steps)[0]
+        d = (cN - target.astype(np.float64))[prob.free_mask(0)]
+        return 0.5 * float(np.sum(d * d))
+
     h = 1e-3
-    fd = (run(g1 + h, False) - run(g1 - h, False)) / (2 * h)
-    print(f"dL/dg1 adjoint {dg1:.6e} central differences {fd:.6e}")
-    assert dg1 == pytest.approx(fd, rel=2e-2)
+    fd1 = (oracle_loss(g1 + h, g2) - oracle_loss(g1 - h, g2)) / (2 * h)
+    fd2 = (oracle_loss(g1, g2 + h) - oracle_loss(g1, g2 - h)) / (2 * h)
+    print(f"dL/dg1 adjoint {dg1:.10e} FP64 central differences {fd1:.10e} (rel "
+          f"{abs(dg1 - fd1) / abs(fd1):.2e}); dL/dg2 {dg2:.10e} vs {fd2:.10e} (rel "
+          f"{abs(dg2 - fd2) / abs(fd2):.2e})")
+    assert dg1 == pytest.approx(fd1, rel=1e-4)
+    assert dg2 == pytest.approx(fd2, rel=1e-4)
 
 
 def test_errors(rd, oracle_mod):
