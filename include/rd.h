@@ -128,6 +128,20 @@ void rd_geometry_destroy(rd_geometry *g);
 rd_status rd_sdf_scratch_bytes(int64_t nx, int64_t ny, int64_t nz, size_t *bytes);
 rd_status rd_sdf_from_image(const uint8_t *dev_image, int64_t nx, int64_t ny, int64_t nz, double dx,
                             float *dev_sdf, void *dev_scratch, size_t scratch_bytes, void *stream);
+/* rd_sdf_from_image for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same kernels and the same
+ * result, with the scratch taken from a fixed array of 64 MiB that the library holds on
+ * each GPU it runs on until the process ends (its device address is fetched once per
+ * device, on the first call with that device current).  The caller passes only the
+ * image and the output.  No allocation or free happens in the call.  Volumes whose
+ * scratch (rd_sdf_scratch_bytes, 20 bytes per voxel, e.g. 144^3) exceeds 64 MiB give
+ * RD_ERR_SHAPE; RD_ERR_ARG for NULL pointers or dx <= 0; RD_ERR_HIP if the device or
+ * the array's address cannot be obtained.  Every call on one GPU uses that GPU's array,
+ * which keeps the previous call's contents (every word is written before it is read):
+ * calls that overlap on one GPU (other streams, other threads) race and must be
+ * serialised by the caller.  Asynchronous on `stream`. */
+rd_status rd_sdf_from_image_static(const uint8_t *dev_image, int64_t nx, int64_t ny, int64_t nz,
+                                   double dx, float *dev_sdf, void *stream);
 
 /* ---- simulation ------------------------------------------------------------ */
 

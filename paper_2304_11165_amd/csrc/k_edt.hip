@@ -19,6 +19,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 
 #include "rd_host.h"
@@ -148,6 +149,18 @@ unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Fixed scratch of rd_sdf_from_image_static: one array per GPU, resident until the
+// process ends.  Host code uses only the device address fetched per device below; the
+// array's name on the host is a stand-in, not a device address.
+#define RD_SDF_STATIC_BYTES ((size_t)64 << 20)
+static __device__ __align__(256) unsigned char scratch[RD_SDF_STATIC_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex static_mu;
+void *static_ptr[MAX_DEVICES];  // device address of `scratch` on each device, or NULL
+}  // namespace
+
 extern "C" rd_status rd_sdf_scratch_bytes(int64_t nx, int64_t ny, int64_t nz, size_t *bytes)
 {
     if (!bytes) return rd_fail(RD_ERR_ARG, "bytes is NULL");
@@ -155,6 +168,36 @@ extern "C" rd_status rd_sdf_scratch_bytes(int64_t nx, int64_t ny, int64_t nz, si
     const size_t N = (size_t)nx * (size_t)ny * (size_t)nz;
     *bytes = align256(4 * N) + align256(4 * N) + align256(4 * N) + align256(8 * N);
     return RD_OK;
+}
+
+extern "C" rd_status rd_sdf_from_image_static(const uint8_t *dev_image, int64_t nx, int64_t ny, int64_t nz,
+                                              double dx, float *dev_sdf, void *stream)
+{
+    if (!dev_image || !dev_sdf) return rd_fail(RD_ERR_ARG, "NULL pointer");
+    if (nx < 1 || ny < 1 || nz < 1 || nx > 32768 || ny > 32768 || nz > 32768)
+        return rd_fail(RD_ERR_SHAPE, "need 1 <= nx, ny, nz <= 32768");
+    size_t need = 0;
+    rd_sdf_scratch_bytes(nx, ny, nz, &need);
+    if (need > RD_SDF_STATIC_BYTES)
+        return rd_fail(RD_ERR_SHAPE, "volume needs " + std::to_string(need) + " scratch bytes; the fixed scratch holds " +
+                                         std::to_string(RD_SDF_STATIC_BYTES) + " (20 bytes per voxel)");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return rd_fail(RD_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= MAX_DEVICES) return rd_fail(RD_ERR_HIP, "device id out of range");
+    void *ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(static_mu);
+        if (!static_ptr[dev]) {  // first call on this device (it is current)
+            e = hipGetSymbolAddress(&static_ptr[dev], HIP_SYMBOL(scratch));
+            if (e != hipSuccess) {
+                static_ptr[dev] = nullptr;
+                return rd_fail(RD_ERR_HIP, std::string("hipGetSymbolAddress: ") + hipGetErrorString(e));
+            }
+        }
+        ptr = static_ptr[dev];
+    }
+    return rd_sdf_from_image(dev_image, nx, ny, nz, dx, dev_sdf, ptr, RD_SDF_STATIC_BYTES, stream);
 }
 
 extern "C" rd_status rd_sdf_from_image(const uint8_t *dev_image, int64_t nx, int64_t ny, int64_t nz, double dx,

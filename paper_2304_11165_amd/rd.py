@@ -70,6 +70,7 @@ _SIGS = {
     "rd_sim_region_mass": ([P, ci, P, P], ci),
     "rd_sdf_scratch_bytes": ([i64, i64, i64, P], ci),
     "rd_sdf_from_image": ([P, i64, i64, i64, f64, P, P, ctypes.c_size_t, P], ci),
+    "rd_sdf_from_image_static": ([P, i64, i64, i64, f64, P, P], ci),
     "rd_sim_set_layout": ([P, ci], ci),
     "rd_sim_frap_curve": ([P, ci, P, f64, i64, i64, P], ci),
     "rd_frap_fit": ([i64, P, P, i64, f64, P, f64, P, P], ci),
@@ -614,3 +615,20 @@ def sdf_from_image(image, dx=1.0, stream=None):
         t.record_stream(st)
     return out
 
+
+def sdf_from_image_static(image, out, dx=1.0, stream=None):
+    """rd_sdf_from_image_static: the signed distance of a uint8 (nz, ny, nx) device image
+    into the caller's float32 device tensor `out`, with the library's fixed per-GPU
+    scratch (no allocation in the library; volumes up to 64 MiB of scratch, 20 bytes per
+    voxel).  Calls on one GPU share that scratch: overlapping calls race."""
+    import torch
+
+    assert image.is_cuda and image.dtype == torch.uint8 and image.is_contiguous()
+    assert out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
+    assert tuple(out.shape) == tuple(image.shape)
+    nz, ny, nx = image.shape
+    st = stream if stream is not None else torch.cuda.current_stream(image.device)
+    _check(_lib.rd_sdf_from_image_static(ctypes.c_void_p(image.data_ptr()), nx, ny, nz, float(dx),
+                                         ctypes.c_void_p(out.data_ptr()), _stream_handle(st)),
+           "rd_sdf_from_image_static")
+    return out
