@@ -52,6 +52,7 @@ def parse():
     p.add_argument("--steady-size", type=int, default=1024, help="edge of the foam volume")
     p.add_argument("--steady-forms", default="fp32,fp16", help="storage types of the steady form")
     p.add_argument("--steady-tol", type=float, default=1e-8)
+    p.add_argument("--steady-max-iters", type=int, default=200000)
     p.add_argument("--adjoint", type=int, default=1,
                    help="1: time the checkpointed adjoint on the 256^3 diffusion-decay packing")
     p.add_argument("--diffusivity-steps", type=int, default=2000,
@@ -71,8 +72,10 @@ def parse():
     p.add_argument("--profile-storage", default="fp32", choices=["fp32", "bf16", "fp16"],
                    help="storage type timed by --profile")
     p.add_argument("--copy-calibration", action="store_true")
+    p.add_argument("--profile-form", default="", choices=["", "steady", "batch", "adjoint"],
+                   help="run only this form (for rocprofv3) and print its record")
     p.add_argument("--kernel", default="auto", choices=["auto", "block", "column", "column_xch",
-                                                        "persistent"],
+                                                        "persistent", "column_lanes"],
                    help="B = 8 step kernel (auto: autotuned)")
     p.add_argument("--layout", default="auto", choices=["auto", "blocks", "compact"],
                    help="field layout (auto: the faster of the two, each autotuned)")
@@ -142,8 +145,9 @@ def build_sim(rd, geom, w, storage, graph_steps, use_graph=True):
     for (sp, f), v in w.dirichlet.items():
         s.set_dirichlet(sp, f, v)
     s.set_launch(graph_steps, use_graph, True)
-    if storage != "fp32":
-        s.set_rounding(1, seed=2304)
+    # stochastic rounding for every storage type (FP32: a dither of the increment), so
+    # increments below half a storage spacing are not lost as the field settles
+    s.set_rounding(1, seed=2304)
     return s
 
 
@@ -186,7 +190,8 @@ def step_kernel_name(B, launch, S):
     kern = (launch or {}).get("kernel", "block")
     cmp = "true" if (launch or {}).get("layout") == "compact" else "false"
     name = {"block": "k_step8<float,{S}>", "column": "k_step8z<float,{S},false,{C}>",
-            "column_xch": "k_step8z<float,{S},true,{C}>", "persistent": "k_step8p<float,{S}>"}[kern]
+            "column_xch": "k_step8z<float,{S},true,{C}>", "persistent": "k_step8p<float,{S}>",
+            "column_lanes": "k_step8l<float,{S}>"}[kern]
     return name.format(S=S, C=cmp)
 
 
@@ -231,7 +236,7 @@ def batched_form(torch, rd, W, count, max_edge, stream):
     }
 
 
-def steady_form(torch, rd, W, size, axes, forms, tol, stream):
+def steady_form(torch, rd, W, size, axes, forms, tol, stream, max_iters=200000):
     """Tortuosity of the ceramic-foam volume (solid matrix of overlapping pore spheres
     r ~ U(10, 30), pore fraction 0.15) along the first `axes` axes by conjugate
     gradients, per storage type; with the full 1024^3 volume, the same solves on its
@@ -257,7 +262,7 @@ def steady_form(torch, rd, W, size, axes, forms, tol, stream):
             for axis in range(axes):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                r = sim.steady_state(axis, tol, 200000)
+                r = sim.steady_state(axis, tol, max_iters)
                 torch.cuda.synchronize()
                 secs = time.perf_counter() - t0
                 vi = float(st["n_active"]) * r["iters"]
@@ -543,6 +548,18 @@ def main():
     from paper_2304_11165_amd import rd
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if a.profile_form:
+        stream = torch.cuda.Stream()
+        if a.profile_form == "steady":
+            rec = steady_form(torch, rd, W, a.steady_size, a.steady_axes,
+                              [f for f in a.steady_forms.split(",") if f], a.steady_tol, stream,
+                              a.steady_max_iters)
+        elif a.profile_form == "batch":
+            rec = batched_form(torch, rd, W, a.batch, a.batch_max_edge, stream)
+        else:
+            rec = adjoint_form(torch, rd, W, stream)
+        print(json.dumps({"profile_form": a.profile_form, "record": rec}), flush=True)
+        return
     w = W.workload("soil512")
     n = a.size
     t0 = time.perf_counter()
@@ -615,7 +632,7 @@ def main():
             "layout_GBps": layout_bytes / per_step / 1e9,
             "alg_bytes_per_launch": alg_bytes,
             "layout_bytes_per_launch": layout_bytes,
-            "rounding": "nearest" if storage == "fp32" else "stochastic",
+            "rounding": "stochastic",
             "launch": launch,
             "mass": [b["mass"] for b in bal],
             "inflow": [float(np.sum(b["inflow"])) for b in bal],
@@ -666,7 +683,7 @@ def main():
         "config": {
             "workload": f"soil-like {n}^3 Gaussian random field (corr. length 12, porosity 0.3), "
                         f"8^3 blocks, 2 species D=(1.0,0.4), A->B k=0.01, Robin on B k=0.05, "
-                        f"c_A=1 on x=0, dt=0.1, FP32 storage",
+                        f"c_A=1 on x=0, dt=0.1, FP32 storage (stochastic rounding)",
             "n_active_voxels": n_active,
             "n_blocks": nb,
             "fill": fill,

@@ -204,11 +204,16 @@ rd_status rd_sim_set_layout(rd_sim *sim, int layout);
  * kernel 4 with the block layout. */
 rd_status rd_sim_set_kernel(rd_sim *sim, int kernel, int wg_per_cu);
 
-/* Rounding of BF16 / FP16 stores (no effect with FP32 storage).  stochastic = 0:
- * round to nearest even (default).  stochastic = 1: round up with probability equal
- * to the fraction of the storage spacing, drawn from a counter-based hash of (slot,
- * species, step, seed); unbiased, so small increments are not lost near fronts and
- * steady states.  Results stay deterministic for a given seed. */
+/* Rounding of the stored fields.  stochastic = 0: round to nearest even (default).
+ * stochastic = 1: round up with probability equal to the fraction of the storage
+ * spacing, from a counter-based hash of (voxel, species, step, seed): unbiased, so
+ * increments below half a spacing are not lost near fronts and steady states.  BF16 /
+ * FP16 round so when they store; FP32 storage adds a dither of (u - 1/2) ulp(c) to each
+ * voxel's increment before the final addition c + increment is rounded to nearest
+ * (constant-D kernels; with a diffusivity factor FP32 stays round-to-nearest).  Results
+ * stay deterministic for a given seed and identical across kernels and layouts.
+ * Storage precision is this build's addition; the paper computes in FP32 throughout
+ * (section "Parallel implementation using OpenFPM"). */
 rd_status rd_sim_set_rounding(rd_sim *sim, int stochastic, uint64_t seed);
 /* Device bytes the caller must provide to rd_sim_bind for the given features
  * (bitwise OR of RD_WS_*) and, with RD_WS_ADJOINT, checkpoint_slots stored states.

@@ -96,7 +96,7 @@ __device__ __forceinline__ uint32_t side_index(const StepArgs &a, int f, int nn,
     return a.cbase[nn] + plane_prefix(nrec, ly) + (uint32_t)__popcll(below);
 }
 
-template <typename T, int S>
+template <typename T, int S, bool DTH>
 __global__ __launch_bounds__(256) void k_step8l(StepArgs a)
 {
     typedef Buf<T> Bt;
@@ -204,6 +204,7 @@ __global__ __launch_bounds__(256) void k_step8l(StepArgs a)
         // halo sources of plane z: x faces at (u, v) = (y, z), y faces at (x, z)
         const int hx = (z * 8 + ly) * 4, hy = (z * 8 + lx) * 4;
         float res[S];
+        const uint32_t h = a.sround ? sr_voxel(voxel_id(g, gx, gy, gz), key) : 0u;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const float cz = c[s][z];
@@ -221,10 +222,10 @@ __global__ __launch_bounds__(256) void k_step8l(StepArgs a)
             float cen[S];
 #pragma unroll
             for (int q = 0; q < S; ++q) cen[q] = c[q][z];
-            const float upd = rd_update<S>(cz, nbv, m, nwall, a.coef[s], cen);
+            const float dth = DTH ? fp32_dither(cz, sr_species(h, s)) : 0.0f;
+            const float upd = rd_update<S, DTH>(cz, nbv, m, nwall, a.coef[s], cen, dth);
             res[s] = (dblk && (onf & a.coef[s].dir) != 0u) ? cz : upd;
         }
-        const uint32_t h = a.sround ? sr_voxel(voxel_id(g, gx, gy, gz), key) : 0u;
 #pragma unroll
         for (int s = 0; s < S; ++s) Bt::st(rout[s], vo[z], res[s], a.sround != 0, sr_species(h, s));
     }
@@ -233,7 +234,8 @@ __global__ __launch_bounds__(256) void k_step8l(StepArgs a)
 template <typename T, int S>
 void launch_s(const StepArgs &a, int groups, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_step8l<T, S>), dim3(groups), dim3(256), 0, st, a);
+    if (sizeof(T) == 4 && a.sround) hipLaunchKernelGGL((k_step8l<T, S, true>), dim3(groups), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_step8l<T, S, false>), dim3(groups), dim3(256), 0, st, a);
 }
 
 template <typename T>

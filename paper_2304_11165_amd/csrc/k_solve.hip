@@ -169,13 +169,21 @@ __global__ __launch_bounds__(256) void k_cg_matvec(CgArgs a)
 // kernel (k_cg_update8) recomputes it from p_new with the same arithmetic (cg_ap8),
 // which moves fewer bytes than writing and reading it back.
 
+// The four blocks of a workgroup are consecutive list entries; x-adjacent ones hand each
+// other their x = 0 / x = 7 planes through LDS (one barrier) instead of loading the
+// neighbour's strided x face, which touches every line of the neighbour block.  Every
+// wave reaches the barrier, also those past the list or of converged geometries.
 template <typename T>
 __global__ __launch_bounds__(256) void k_cg_matvec8(CgArgs a)
 {
     __shared__ float tile[4][100];
+    __shared__ float xch[4][2][64];  // x = 0 / x = 7 planes of each wave's p_new, [z * 8 + y]
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int b = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + wv);
-    if (b >= a.nb) return;
+    if (b >= a.nb) {
+        __syncthreads();
+        return;
+    }
     const BlockInfo bi = a.info[b];
     int bx, by, bz, gid;
     block_pos(bi, &bx, &by, &bz, &gid);
@@ -184,8 +192,12 @@ __global__ __launch_bounds__(256) void k_cg_matvec8(CgArgs a)
             a.partial[(int64_t)b * 2 + 0] = 0.0;
             a.partial[(int64_t)b * 2 + 1] = 0.0;
         }
+        __syncthreads();
         return;
     }
+    // x neighbours inside this workgroup (same geometry, so live as well)
+    const bool xm_in = wv > 0 && bi.nbr[0] == b - 1;
+    const bool xp_in = wv < 3 && bi.nbr[1] == b + 1;
     const T *pv = (const T *)a.p;
     const int64_t base = (int64_t)b * 512;
     const int lx = lane & 7, ly = lane >> 3;
@@ -219,7 +231,7 @@ __global__ __launch_bounds__(256) void k_cg_matvec8(CgArgs a)
         default: ns = (0 * 8 + ly) * 8 + lx; break;
         }
         const int n = bi.nbr[f];
-        const bool e = (Wf[f] >> lane) & 1ull;
+        const bool e = ((Wf[f] >> lane) & 1ull) && !(f == 0 && xm_in) && !(f == 1 && xp_in);
         rh[f] = ld_raw(pv, (int64_t)(n >= 0 ? n : b) * 512 + ns, e);
         qh[f] = ld_raw(rv, (int64_t)(n >= 0 ? n : b) * 512 + ns, e);
     }
@@ -234,6 +246,14 @@ __global__ __launch_bounds__(256) void k_cg_matvec8(CgArgs a)
 #pragma unroll
     for (int f = 0; f < 4; ++f) side[f] = pval(rh[f], qh[f]);
     const float zlo = pval(rh[4], qh[4]), zhi = pval(rh[5], qh[5]);
+    // the neighbour's p_new on its face: the value this wave would form from the halos
+    if (lx == 0 || lx == 7) {
+#pragma unroll
+        for (int z = 0; z < 8; ++z) xch[wv][lx == 7 ? 1 : 0][z * 8 + ly] = c[z];
+    }
+    __syncthreads();
+    if (xm_in) side[0] = xch[wv - 1][1][ly * 8 + lx];
+    if (xp_in) side[1] = xch[wv + 1][0][ly * 8 + lx];
 
     const GeomInfo g = a.geom[gid];
     const int gx = bx * 8 + lx, gy = by * 8 + ly;
@@ -287,9 +307,13 @@ template <typename T, bool X64>
 __global__ __launch_bounds__(256) void k_cg_update8(CgArgs a)
 {
     __shared__ float tile[4][100];
+    __shared__ float xch[4][2][64];  // x faces of p within the workgroup (as in k_cg_matvec8)
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int b = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + wv);
-    if (b >= a.nb) return;
+    if (b >= a.nb) {
+        __syncthreads();
+        return;
+    }
     const BlockInfo bi = a.info[b];
     int bx, by, bz, gid;
     block_pos(bi, &bx, &by, &bz, &gid);
@@ -298,8 +322,11 @@ __global__ __launch_bounds__(256) void k_cg_update8(CgArgs a)
             a.partial[(int64_t)b * 2 + 0] = 0.0;
             a.partial[(int64_t)b * 2 + 1] = 0.0;
         }
+        __syncthreads();
         return;
     }
+    const bool xm_in = wv > 0 && bi.nbr[0] == b - 1;
+    const bool xp_in = wv < 3 && bi.nbr[1] == b + 1;
     const T *pv = (const T *)a.p;
     T *xv = (T *)a.x;
     T *rv = (T *)a.r;
@@ -336,7 +363,7 @@ __global__ __launch_bounds__(256) void k_cg_update8(CgArgs a)
         default: ns = (0 * 8 + ly) * 8 + lx; break;
         }
         const int n = bi.nbr[f];
-        const bool e = (Wf[f] >> lane) & 1ull;
+        const bool e = ((Wf[f] >> lane) & 1ull) && !(f == 0 && xm_in) && !(f == 1 && xp_in);
         ph[f] = ld_raw(pv, (int64_t)(n >= 0 ? n : b) * 512 + ns, e);
     }
     const double alpha_d = a.scal[gid * CG_NSCAL + CG_ALPHA];
@@ -348,6 +375,13 @@ __global__ __launch_bounds__(256) void k_cg_update8(CgArgs a)
 #pragma unroll
     for (int f = 0; f < 4; ++f) side[f] = from_raw<T>(ph[f]);
     const float zlo = from_raw<T>(ph[4]), zhi = from_raw<T>(ph[5]);
+    if (lx == 0 || lx == 7) {
+#pragma unroll
+        for (int z = 0; z < 8; ++z) xch[wv][lx == 7 ? 1 : 0][z * 8 + ly] = c[z];
+    }
+    __syncthreads();
+    if (xm_in) side[0] = xch[wv - 1][1][ly * 8 + lx];
+    if (xp_in) side[1] = xch[wv + 1][0][ly * 8 + lx];
 
     const GeomInfo g = a.geom[gid];
     const int gx = bx * 8 + lx, gy = by * 8 + ly;

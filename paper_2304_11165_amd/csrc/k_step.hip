@@ -34,12 +34,15 @@ __device__ __forceinline__ uint32_t voxel_bits(const StepArgs &a, uint32_t key, 
 }
 
 // Store one updated value of species s (round to nearest, or stochastic rounding
-// with the voxel's random word h when enabled).
-template <typename T>
+// with the voxel's random word h when enabled).  PLAIN: an ordinary store also for FP32
+// (the compact layout's plane runs share 128-byte lines with their neighbours, which a
+// nontemporal store would send to memory half written).
+template <typename T, bool PLAIN = false>
 __device__ __forceinline__ void store_val(const StepArgs &a, T *cout, int s, int64_t idx, uint32_t h,
                                           float r)
 {
-    if (a.sround) rd_st_sr(cout, idx, r, sr_species(h, s));
+    if constexpr (PLAIN && sizeof(T) == 4) cout[idx] = r;
+    else if (a.sround) rd_st_sr(cout, idx, r, sr_species(h, s));
     else rd_st(cout, idx, r);
 }
 
@@ -50,11 +53,11 @@ __device__ __forceinline__ void store_val(const StepArgs &a, T *cout, int s, int
 // (oy, oz) the y / z neighbour offsets of the tile layout.  onf: bit d set when the
 // voxel lies on box face d, which marks both Dirichlet planes (onf & dir) and
 // out-of-box neighbours (no wall there).
-template <int S>
+template <int S, bool DTH>
 __device__ __forceinline__ void vox8(const StepArgs &a, const float *ts, int sstr, int oy, int oz,
                                      uint64_t W, uint64_t Wm, uint64_t Wp, uint64_t fx0,
                                      uint64_t fx1, uint64_t fy0, uint64_t fy1, int lx, int ly,
-                                     int lz, unsigned onf, const float *cen, float *out)
+                                     int lz, unsigned onf, const float *cen, float *out, uint32_t hd)
 {
     const int bit = ly * 8 + lx;
     const uint64_t fxb = (uint64_t)1 << (lz * 8 + ly), fyb = (uint64_t)1 << (lz * 8 + lx);
@@ -72,7 +75,8 @@ __device__ __forceinline__ void vox8(const StepArgs &a, const float *ts, int sst
     for (int s = 0; s < S; ++s) {
         const float *p = ts + s * sstr;
         const float nbv[6] = {p[-1], p[1], p[-oy], p[oy], p[-oz], p[oz]};
-        const float upd = rd_update<S>(cen[s], nbv, m, nwall, a.coef[s], cen);
+        const float dth = DTH ? fp32_dither(cen[s], sr_species(hd, s)) : 0.0f;
+        const float upd = rd_update<S, DTH>(cen[s], nbv, m, nwall, a.coef[s], cen, dth);
         const bool isd = (onf & a.coef[s].dir) != 0u;
         out[s] = act ? (isd ? cen[s] : upd) : 0.0f;
     }
@@ -87,10 +91,10 @@ __device__ __forceinline__ unsigned box_faces(const GeomInfo &g, int gx, int gy,
 // Update of one voxel from its precomputed neighbour code (bits 0-5 active neighbours,
 // bit 6 active) and its box-face bits onf (0 for blocks away from the box boundary).
 // Same arithmetic as every other variant (rd_update).
-template <int S>
+template <int S, bool DTH>
 __device__ __forceinline__ void vox_code(const StepArgs &a, const float *ts, int sstr, int oy,
                                          int oz, unsigned code, unsigned onf, const float *cen,
-                                         float *out)
+                                         float *out, uint32_t hd)
 {
     const unsigned m = code & 63u;
     const bool act = (code & 64u) != 0u;
@@ -99,7 +103,8 @@ __device__ __forceinline__ void vox_code(const StepArgs &a, const float *ts, int
     for (int s = 0; s < S; ++s) {
         const float *p = ts + s * sstr;
         const float nbv[6] = {p[-1], p[1], p[-oy], p[oy], p[-oz], p[oz]};
-        const float upd = rd_update<S>(cen[s], nbv, m, nwall, a.coef[s], cen);
+        const float dth = DTH ? fp32_dither(cen[s], sr_species(hd, s)) : 0.0f;
+        const float upd = rd_update<S, DTH>(cen[s], nbv, m, nwall, a.coef[s], cen, dth);
         const bool isd = (onf & a.coef[s].dir) != 0u;
         out[s] = act ? (isd ? cen[s] : upd) : 0.0f;
     }
@@ -116,7 +121,8 @@ __device__ __forceinline__ bool boundary_block(const GeomInfo &g, int bx, int by
 // workgroup.  Each wave stages its block and the 6 x 16 halo values in a private
 // LDS tile of 6^3 words per species, then updates its 64 voxels from the neighbour
 // codes.  Only wave-level ordering is needed (no workgroup barrier).
-template <typename T, int S>
+// DTH (FP32 storage with stochastic rounding): the update takes a dither (fp32_dither).
+template <typename T, int S, bool DTH>
 __global__ __launch_bounds__(256) void k_step4w(StepArgs a)
 {
     constexpr int E = 6, E2 = 36, TLW = 216;
@@ -192,10 +198,10 @@ __global__ __launch_bounds__(256) void k_step4w(StepArgs a)
     unsigned onf = 0u;
     if (bnd) onf = box_faces(g, gx, gy, gz);
     float res[S];
-    vox_code<S>(a, &tile[wv][0][t], TLW, E, E2, code, onf, c, res);
+    const uint32_t h = voxel_bits(a, launch_key(a), voxel_id(g, gx, gy, gz));
+    vox_code<S, DTH>(a, &tile[wv][0][t], TLW, E, E2, code, onf, c, res, h);
     // whole sectors only; an inactive slot of an active sector stores its 0 again
     if (sector_active<T>(Wo, lane)) {
-        const uint32_t h = voxel_bits(a, launch_key(a), voxel_id(g, gx, gy, gz));
 #pragma unroll
         for (int s = 0; s < S; ++s) store_val(a, cout, s, s * a.sstride + base + lane, h, res[s]);
     }
@@ -207,7 +213,7 @@ __global__ __launch_bounds__(256) void k_step4w(StepArgs a)
 // issues all of its global loads (2 own values and 1-2 halo values per species)
 // before the first wait; the halo of face w (x / y faces) and of face 4 + w (z faces,
 // waves 0-1) goes through the wave-uniform neighbour index.
-template <typename T, int S>
+template <typename T, int S, bool DTH>
 __global__ __launch_bounds__(256) void k_step8(StepArgs a)
 {
     using K = Blk<8>;
@@ -284,11 +290,11 @@ __global__ __launch_bounds__(256) void k_step8(StepArgs a)
         float cen[S], res[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) cen[s] = k == 0 ? c0[s] : c1[s];
-        vox_code<S>(a, &tile[0][K::tidx(lx, ly, lz)], K::TL, K::E, K::E * K::E, k == 0 ? cd0 : cd1,
-                    onf, cen, res);
+        const uint32_t h = voxel_bits(a, key, voxel_id(g, gx, gy, gz));
+        vox_code<S, DTH>(a, &tile[0][K::tidx(lx, ly, lz)], K::TL, K::E, K::E * K::E, k == 0 ? cd0 : cd1,
+                         onf, cen, res, h);
         // whole sectors only; an inactive slot of an active sector stores its 0 again
         if (sector_active<T>(k == 0 ? Wo0 : Wo1, lane)) {
-            const uint32_t h = voxel_bits(a, key, voxel_id(g, gx, gy, gz));
 #pragma unroll
             for (int s = 0; s < S; ++s) store_val(a, cout, s, s * a.sstride + base + slot, h, res[s]);
         }
@@ -321,7 +327,7 @@ __device__ __forceinline__ int pix(int x, int y) { return (y + 1) * 10 + (x + 1)
 // from the neighbour's plane word and prefix count (one record line), a z halo from
 // the face word.  Loads, arithmetic and stored values are those of the block-major
 // layout, so both give the same bits; stores cover the active voxels only.
-template <typename T, int S, bool XCH, bool CMP>
+template <typename T, int S, bool XCH, bool CMP, bool DTH>
 __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
 {
     __shared__ float tile[4][S][100];
@@ -481,13 +487,15 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
         float cen[S], res[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) cen[s] = c[s][z];
+        const uint32_t h = voxel_bits(a, key, voxel_id(g, gx, gy, gz));
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const float *p = &tile[wv][s][z8::pix(lx, ly)];
             const float dn = z == 0 ? zlo[s] : c[s][z > 0 ? z - 1 : 0];
             const float up = z == 7 ? zhi[s] : c[s][z < 7 ? z + 1 : 7];
             const float nbv[6] = {p[-1], p[1], p[-10], p[10], dn, up};
-            const float upd = rd_update<S>(cen[s], nbv, m, nwall, a.coef[s], cen);
+            const float dth = DTH ? fp32_dither(cen[s], sr_species(h, s)) : 0.0f;
+            const float upd = rd_update<S, DTH>(cen[s], nbv, m, nwall, a.coef[s], cen, dth);
             const bool isd = (onf & a.coef[s].dir) != 0u;
             res[s] = act ? (isd ? cen[s] : upd) : 0.0f;
         }
@@ -498,9 +506,8 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
         // block-major: whole sectors only (an inactive slot of an active sector stores
         // its 0 again); compact: the active voxels, a contiguous run
         if (lane_bit(CMP ? Wo[z] : sector_lanes<T>(Wo[z]))) {
-            const uint32_t h = voxel_bits(a, key, voxel_id(g, gx, gy, gz));
 #pragma unroll
-            for (int s = 0; s < S; ++s) store_val(a, cout, s, s * a.sstride + oi[z], h, res[s]);
+            for (int s = 0; s < S; ++s) store_val<T, CMP>(a, cout, s, s * a.sstride + oi[z], h, res[s]);
         }
     }
 }
@@ -570,7 +577,7 @@ __device__ __forceinline__ void p8_load(const StepArgs &a, const T *cin, int b, 
     if (threadIdx.x < 16) r.mw = a.mask[(int64_t)b * 16 + threadIdx.x];
 }
 
-template <typename T, int S>
+template <typename T, int S, bool DTH>
 __global__ __launch_bounds__(256) void k_step8p(StepArgs a)
 {
     __shared__ __align__(16) float tile[S][p8::TL];
@@ -654,17 +661,18 @@ __global__ __launch_bounds__(256) void k_step8p(StepArgs a)
         const int gy = by * 8 + ly, gz = bz * 8 + lzp;
         const int64_t base = (int64_t)b * 512;
         float res[2][S];
+        const int64_t v0 = voxel_id(g, bx * 8 + 2 * lx2, gy, gz);
+        const uint32_t h0 = voxel_bits(a, key, v0), h1 = voxel_bits(a, key, v0 + 1);
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int lx = 2 * lx2 + j;
             float cen[S];
 #pragma unroll
             for (int s = 0; s < S; ++s) cen[s] = j == 0 ? cur.c0[s] : cur.c1[s];
-            vox8<S>(a, &tile[0][p8::tix(lx, ly, lzp)], p8::TL, p8::TX, p8::TX * p8::TY, W, Wm, Wp,
-                    fx0, fx1, fy0, fy1, lx, ly, lzp, box_faces(g, bx * 8 + lx, gy, gz), cen, res[j]);
+            vox8<S, DTH>(a, &tile[0][p8::tix(lx, ly, lzp)], p8::TL, p8::TX, p8::TX * p8::TY, W, Wm, Wp,
+                         fx0, fx1, fy0, fy1, lx, ly, lzp, box_faces(g, bx * 8 + lx, gy, gz), cen, res[j],
+                         j == 0 ? h0 : h1);
         }
-        const int64_t v0 = voxel_id(g, bx * 8 + 2 * lx2, gy, gz);
-        const uint32_t h0 = voxel_bits(a, key, v0), h1 = voxel_bits(a, key, v0 + 1);
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const int64_t idx = s * a.sstride + base + slot0;
@@ -1087,25 +1095,34 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, uint32_t v, int64
 template <int B>
 int groups_for(int nb) { return (nb + Cfg<B>::BPW - 1) / Cfg<B>::BPW; }
 
-template <typename T, int B, int S>
-void launch_step_s(const StepArgs &a, int groups, hipStream_t st)
+template <typename T, int B, int S, bool DTH>
+void launch_step_d(const StepArgs &a, int groups, hipStream_t st)
 {
     if constexpr (B == 8) {
         if (a.kernel == 1)
-            hipLaunchKernelGGL((k_step8p<T, S>), dim3(a.grid), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_step8p<T, S, DTH>), dim3(a.grid), dim3(256), 0, st, a);
         else if (a.kernel == 2 && a.cbase)
-            hipLaunchKernelGGL((k_step8z<T, S, false, true>), dim3(groups), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_step8z<T, S, false, true, DTH>), dim3(groups), dim3(256), 0, st, a);
         else if (a.kernel == 3 && a.cbase)
-            hipLaunchKernelGGL((k_step8z<T, S, true, true>), dim3(groups), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_step8z<T, S, true, true, DTH>), dim3(groups), dim3(256), 0, st, a);
         else if (a.kernel == 2)
-            hipLaunchKernelGGL((k_step8z<T, S, false, false>), dim3(groups), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_step8z<T, S, false, false, DTH>), dim3(groups), dim3(256), 0, st, a);
         else if (a.kernel == 3)
-            hipLaunchKernelGGL((k_step8z<T, S, true, false>), dim3(groups), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_step8z<T, S, true, false, DTH>), dim3(groups), dim3(256), 0, st, a);
         else
-            hipLaunchKernelGGL((k_step8<T, S>), dim3(groups), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_step8<T, S, DTH>), dim3(groups), dim3(256), 0, st, a);
     } else {
-        hipLaunchKernelGGL((k_step4w<T, S>), dim3(groups), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_step4w<T, S, DTH>), dim3(groups), dim3(256), 0, st, a);
     }
+}
+
+// FP32 storage with stochastic rounding runs the dithered kernels; 16-bit storage rounds
+// stochastically when it stores.
+template <typename T, int B, int S>
+void launch_step_s(const StepArgs &a, int groups, hipStream_t st)
+{
+    if (sizeof(T) == 4 && a.sround) launch_step_d<T, B, S, true>(a, groups, st);
+    else launch_step_d<T, B, S, false>(a, groups, st);
 }
 
 template <typename T, int B>

@@ -512,7 +512,10 @@ void rd_sim::launch_shape(StepArgs &a) const
 
 rd_status rd_sim::launch_steps(double dt, int64_t n)
 {
-    const bool sr = sround && storage != RD_FP32;
+    // stochastic rounding: at the store for 16-bit storage; for FP32 storage a dither of
+    // the increment, in the constant-D kernels only (the kernels with a diffusivity
+    // factor round FP32 to nearest)
+    const bool sr = sround && (storage != RD_FP32 || !diff_path());
     for (int64_t i = 0; i < n; ++i) {
         StepArgs a = step_args(dt, cur);
         launch_shape(a);

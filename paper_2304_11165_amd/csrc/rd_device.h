@@ -358,20 +358,36 @@ __device__ __forceinline__ bool on_dirichlet(uint32_t dir, int gx, int gy, int g
 // of all six values, and the mirror rule enters through the active count:
 //   lap = (((((n_-x + n_+x) + n_-y) + n_+y) + n_-z) + n_+z) - popc(nbm) * c_p
 // (one rounding order for every kernel; 6 operations instead of 18).
-template <int S>
+// The increment  alpha lap - (beta + gamma n_wall) c + sum_b K_b c_b  is formed first and
+// added to c once, so c is rounded once per step (forming c + alpha lap and then applying
+// each term to it rounded c up to four times).  DTH (FP32 storage with stochastic
+// rounding): `dith` (fp32_dither) is added to the increment before that final addition.
+template <int S, bool DTH = false>
 __device__ __forceinline__ float rd_update(float uc, const float nbv[6], unsigned nbm, int nwall,
-                                           const SpeciesCoef &k, const float *cen)
+                                           const SpeciesCoef &k, const float *cen, float dith = 0.0f)
 {
     float sum = nbv[0];
 #pragma unroll
     for (int d = 1; d < 6; ++d) sum = sum + nbv[d];
     const float lap = fmaf(-(float)__popc(nbm & 63u), uc, sum);
-    float r = fmaf(k.alpha, lap, uc);
+    float inc = k.alpha * lap;
     const float loss = fmaf(k.gamma, (float)nwall, k.beta);
-    r = fmaf(-loss, uc, r);
+    inc = fmaf(-loss, uc, inc);
 #pragma unroll
-    for (int b = 0; b < S; ++b) r = fmaf(k.K[b], cen[b], r);
-    return r;
+    for (int b = 0; b < S; ++b) inc = fmaf(k.K[b], cen[b], inc);
+    if constexpr (DTH) inc = inc + dith;
+    return uc + inc;
+}
+
+// Stochastic rounding of FP32 values: a dither (u - 1/2) ulp(c), u in [0, 1) from 16
+// random bits, added to the increment makes the round-to-nearest of c + increment + dither
+// equal c + increment on average.  Without it, increments below half an ulp of c are lost
+// at every step, and a field close to its steady state stops converging about
+// (ulp / 2) / (dt * slowest decay rate) away from it.  0 for zero and subnormal c.
+__device__ __forceinline__ float fp32_dither(float uc, uint32_t bits16)
+{
+    const float ulp = __uint_as_float(__float_as_uint(uc) & 0x7f800000u) * 0x1p-23f;
+    return fmaf((float)bits16, 0x1p-16f * ulp, -0.5f * ulp);
 }
 
 // Linear index of a voxel in its (nz, ny, nx) box: the key of the stochastic-rounding

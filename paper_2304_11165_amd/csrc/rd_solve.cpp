@@ -615,7 +615,7 @@ static rd_status adjoint_impl(rd_sim *sim, const float *dev_seed, int seed_mode,
     if (dev_dL_de && !fac) return rd_fail(RD_ERR_STATE, "dL/de needs a diffusivity factor (rd_sim_set_diffusivity)");
     for (const Reaction &r : sim->reactions)
         if (r.to != -1) return rd_fail(RD_ERR_STATE, "the adjoint supports decay reactions only");
-    if (sim->sround && sim->storage != RD_FP32)
+    if (sim->sround)
         return rd_fail(RD_ERR_STATE, "the adjoint needs round-to-nearest storage");
     if (!dev_seed) return rd_fail(RD_ERR_ARG, "seed field is NULL");
     if (seed_mode != 0 && seed_mode != 1) return rd_fail(RD_ERR_ARG, "seed_mode must be 0 or 1");

@@ -9,6 +9,7 @@ refuse to compare against a file whose volume they cannot regenerate bit for bit
     python tests/golden/make_goldens.py foam_crop256   # steady state, three axes
     python tests/golden/make_goldens.py batch64        # tortuosity of the 64 packings
     python tests/golden/make_goldens.py decay256       # adjoint and central differences
+    python tests/golden/make_goldens.py decay256_fd_half  # central differences at h / 2
     python tests/golden/make_goldens.py soil512        # 512^3 soil, 1000 and 10000 steps
 
 Cost on 8 host cores: foam_crop256 a few minutes, batch64 about 20 minutes, decay256
@@ -151,6 +152,30 @@ def make_decay256():
         "target_sum": float(np.sum(target.astype(np.float64)))})
 
 
+def make_decay256_fd_half():
+    """Central differences with h / 2 added to decay256_adjoint.json: with the ones at h
+    they give the Richardson value (4 D(h/2) - D(h)) / 3, whose truncation error is
+    O(h^4) (the one at h alone is O(h^2): about (h/k)^2 relative in k = 0.02)."""
+    path = os.path.join(HERE, "decay256_adjoint.json")
+    ref = json.load(open(path))
+    w = W.workload("decay256")
+    img, _ = W.workload_geometry("decay256")
+    assert sha(img) == ref["sha256"]
+    target = decay_target(img, w)
+    assert float(np.sum(target.astype(np.float64))) == ref["target_sum"]
+    D, k, h = ref["D"], ref["k"], ref["h"] / 2
+    for name, (dp, dm) in {"D": ((D + h, k), (D - h, k)), "k": ((D, k + h), (D, k - h))}.items():
+        t = time.time()
+        lp = decay_loss(img, w, *dp, target)
+        lm = decay_loss(img, w, *dm, target)
+        half = (lp - lm) / (2 * h)
+        ref["fd"][name].update({"L_plus_half": lp, "L_minus_half": lm, "central_half": half,
+                                "richardson": (4 * half - ref["fd"][name]["central"]) / 3})
+        print(f"central difference d/d{name} with h/2: {half:.12e}, Richardson "
+              f"{ref['fd'][name]['richardson']:.12e} ({time.time() - t:.1f} s)", flush=True)
+    _write_json("decay256_adjoint.json", ref)
+
+
 # ---------------------------------------------------------------------------
 # C2: 512^3 soil volume, two species, 1000 and 10000 steps
 # ---------------------------------------------------------------------------
@@ -198,6 +223,7 @@ def make_soil512():
 
 if __name__ == "__main__":
     jobs = {"foam_crop256": make_foam_crop256, "batch64": make_batch64,
-            "decay256": make_decay256, "soil512": make_soil512}
+            "decay256": make_decay256, "decay256_fd_half": make_decay256_fd_half,
+            "soil512": make_soil512}
     for name in sys.argv[1:] or list(jobs):
         jobs[name]()

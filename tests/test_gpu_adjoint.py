@@ -70,7 +70,9 @@ def test_adjoint_uniform_closed_form(rd):
     L, gD, gk = s.adjoint(target, N, dt, 8)
     nf = int(img.sum())
     cN = c0v * (1 - k * dt) ** N
-    assert gD == 0.0
+    # L c^n = 0 for a uniform field; in FP32 the six-neighbour sum of equal values can be
+    # an ulp off, which the update (increment form) keeps, so dL/dD is round-off
+    assert abs(gD) <= 1e-9 * abs(gk)
     assert gk == pytest.approx(-nf * (cN - 0.3) * c0v * N * dt * (1 - k * dt) ** (N - 1), rel=1e-5)
     assert L == pytest.approx(0.5 * nf * (cN - 0.3) ** 2, rel=1e-5)
 

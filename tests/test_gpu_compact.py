@@ -58,8 +58,8 @@ def _ragged(seed, shape=(45, 38, 51), p=0.45):
     return np.ascontiguousarray(img)
 
 
-@pytest.mark.parametrize("storage,sround", [("fp32", False), ("bf16", False), ("bf16", True),
-                                            ("fp16", True)])
+@pytest.mark.parametrize("storage,sround", [("fp32", False), ("fp32", True), ("bf16", False),
+                                            ("bf16", True), ("fp16", True)])
 @pytest.mark.parametrize("S", [1, 2, 3, 4])
 def test_compact_equals_blocks(rd, storage, sround, S):
     img = _ragged(20 + S)

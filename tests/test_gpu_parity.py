@@ -264,10 +264,11 @@ def test_reduced_storage_error_reported(rd, oracle_mod, storage):
     assert errs[1] < errs[0]
 
 
-@pytest.mark.parametrize("storage", ["bf16", "fp16"])
+@pytest.mark.parametrize("storage", ["fp32", "bf16", "fp16"])
 def test_stochastic_rounding_variants_agree(rd, storage):
     """Stochastic rounding draws its bits from (slot, species, step, seed), so graph
-    replay, direct launches and every kernel variant round identically."""
+    replay, direct launches and every kernel variant round identically (FP32: the
+    dithered increment; BF16 / FP16: the store)."""
     img, _ = W.boolean_spheres(40, 0.5, 3.0, 6.0, seed=3)
     out = []
     for v in [dict(), dict(graph=False), dict(kernel="persistent"), dict(B=4),
