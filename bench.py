@@ -189,10 +189,11 @@ def step_kernel_name(B, launch, S):
         return f"k_step4w<float,{S}>"
     kern = (launch or {}).get("kernel", "block")
     cmp = "true" if (launch or {}).get("layout") == "compact" else "false"
-    name = {"block": "k_step8<float,{S}>", "column": "k_step8z<float,{S},false,{C}>",
-            "column_xch": "k_step8z<float,{S},true,{C}>", "persistent": "k_step8p<float,{S}>",
-            "column_lanes": "k_step8l<float,{S}>"}[kern]
-    return name.format(S=S, C=cmp)
+    d = "true"  # FP32 with stochastic rounding: the dithered instantiation
+    name = {"block": "k_step8<float,{S},{D}>", "column": "k_step8z<float,{S},false,{C},{D}>",
+            "column_xch": "k_step8z<float,{S},true,{C},{D}>", "persistent": "k_step8p<float,{S},{D}>",
+            "column_lanes": "k_step8l<float,{S},{D}>"}[kern]
+    return name.format(S=S, C=cmp, D=d)
 
 
 def batched_form(torch, rd, W, count, max_edge, stream):

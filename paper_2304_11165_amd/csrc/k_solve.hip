@@ -303,17 +303,15 @@ __global__ __launch_bounds__(256) void k_cg_matvec8(CgArgs a)
 // and its face halos with the matvec's arithmetic (cg_ap8), so it equals the A p of
 // the p.Ap partial bit for bit.  Whole sectors are stored: inactive slots keep 0 and
 // Dirichlet voxels their values.  Partial (r.r, 0) per block, of r as stored.
+// (Unlike the matvec, this kernel loads the x faces of one vector only; handing them
+// over through LDS measured slower here: 499 against 486 us per call on a 512^3 foam.)
 template <typename T, bool X64>
 __global__ __launch_bounds__(256) void k_cg_update8(CgArgs a)
 {
     __shared__ float tile[4][100];
-    __shared__ float xch[4][2][64];  // x faces of p within the workgroup (as in k_cg_matvec8)
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int b = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + wv);
-    if (b >= a.nb) {
-        __syncthreads();
-        return;
-    }
+    if (b >= a.nb) return;
     const BlockInfo bi = a.info[b];
     int bx, by, bz, gid;
     block_pos(bi, &bx, &by, &bz, &gid);
@@ -322,11 +320,8 @@ __global__ __launch_bounds__(256) void k_cg_update8(CgArgs a)
             a.partial[(int64_t)b * 2 + 0] = 0.0;
             a.partial[(int64_t)b * 2 + 1] = 0.0;
         }
-        __syncthreads();
         return;
     }
-    const bool xm_in = wv > 0 && bi.nbr[0] == b - 1;
-    const bool xp_in = wv < 3 && bi.nbr[1] == b + 1;
     const T *pv = (const T *)a.p;
     T *xv = (T *)a.x;
     T *rv = (T *)a.r;
@@ -363,7 +358,7 @@ __global__ __launch_bounds__(256) void k_cg_update8(CgArgs a)
         default: ns = (0 * 8 + ly) * 8 + lx; break;
         }
         const int n = bi.nbr[f];
-        const bool e = ((Wf[f] >> lane) & 1ull) && !(f == 0 && xm_in) && !(f == 1 && xp_in);
+        const bool e = (Wf[f] >> lane) & 1ull;
         ph[f] = ld_raw(pv, (int64_t)(n >= 0 ? n : b) * 512 + ns, e);
     }
     const double alpha_d = a.scal[gid * CG_NSCAL + CG_ALPHA];
@@ -375,13 +370,6 @@ __global__ __launch_bounds__(256) void k_cg_update8(CgArgs a)
 #pragma unroll
     for (int f = 0; f < 4; ++f) side[f] = from_raw<T>(ph[f]);
     const float zlo = from_raw<T>(ph[4]), zhi = from_raw<T>(ph[5]);
-    if (lx == 0 || lx == 7) {
-#pragma unroll
-        for (int z = 0; z < 8; ++z) xch[wv][lx == 7 ? 1 : 0][z * 8 + ly] = c[z];
-    }
-    __syncthreads();
-    if (xm_in) side[0] = xch[wv - 1][1][ly * 8 + lx];
-    if (xp_in) side[1] = xch[wv + 1][0][ly * 8 + lx];
 
     const GeomInfo g = a.geom[gid];
     const int gx = bx * 8 + lx, gy = by * 8 + ly;
