@@ -201,15 +201,19 @@ def batched_form(torch, rd, W, count, max_edge, stream):
     U{64..max_edge}, porosity U(0.3, 0.7)), all in one set of CG launches."""
     t0 = time.perf_counter()
     geoms_np = W.batch_geometries(count, seed=4, nmin=64, nmax=max_edge)
-    edges = (8, 4)
+    # 8^3 blocks only: the 4^3 CG kernels (one thread per slot, A p stored) took 7.6 ms
+    # per iteration of this batch against 2.3 ms for the 8^3 column kernels
+    edges = (8,)
     cands = {B: [rd.Geometry(img, None, 1.0, B) for img, _ in geoms_np] for B in edges}
     n_active = sum(g.stats()["n_active"] for g in cands[8])
     log(f"batch of {count}: generated and indexed in {time.perf_counter() - t0:.1f}s, {n_active} active voxels")
     with torch.cuda.stream(stream):
-        # block edge by the batch autotuner (50 CG iterations per candidate)
+        # launch setting (iterations per graph segment, graph replay) by the batch
+        # autotuner (50 CG iterations per trial)
         batches = [rd.Batch(cands[B]).bind(stream=stream) for B in edges]
         best, trial_ms = rd.batch_autotune_pick(batches, 0, 50)
         bt, geoms, block_edge = batches[best], cands[edges[best]], edges[best]
+        launch = bt.get_launch()
         del batches
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -217,11 +221,12 @@ def batched_form(torch, rd, W, count, max_edge, stream):
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
     voxel_iters = float(sum(g.stats()["n_active"] * int(i) for g, i in zip(geoms, it)))
-    log(f"batched: block edge {block_edge} (trial ms per iteration: "
+    log(f"batched: block edge {block_edge}, launch {launch} (trial ms per iteration: "
         f"{', '.join(f'{B}^3 {m:.3f}' for B, m in zip(edges, trial_ms))})")
     return {
         "geometries": count,
         "block_edge": block_edge,
+        "launch": launch,
         "trial_ms_per_iteration": {f"{B}^3": float(m) for B, m in zip(edges, trial_ms)},
         "edges": [int(info["n"]) for _, info in geoms_np],
         "seconds": secs,

@@ -447,11 +447,19 @@ rd_status rd_batch_bind(rd_batch *b, void *dev_workspace, size_t bytes, void *st
  * rel_tol (outputs still written). */
 rd_status rd_batch_tortuosity(rd_batch *b, int axis, double rel_tol, int64_t max_iters,
                               double *tau, double *rel_residual, int64_t *iters);
-/* Block-edge autotuning of a batch: bound candidate batches of the same geometries
- * indexed differently (for example 4^3 and 8^3 blocks) each run trial_iters CG
- * iterations along `axis` (rounded up to the 25-iteration check interval); the wall time
- * per iteration, net of labelling and initial guess, goes to ms_per_iter[n] (may be NULL)
- * and the fastest index to *best_index.  The workspaces' contents are overwritten. */
+/* Launch setting of a batch's CG: iters_per_check (1..1000, default 25) iterations run
+ * between two FP64 residual checks (the convergence test, which reads scalars back to the
+ * host) as one sequence of launches, replayed as a captured hipGraph when use_graph is 1
+ * (default) or launched directly.  The stagnation rule counts 1000 iterations whatever
+ * the interval.  RD_ERR_ARG for a NULL batch or an interval outside 1..1000. */
+rd_status rd_batch_set_launch(rd_batch *b, int iters_per_check, int use_graph);
+rd_status rd_batch_get_launch(const rd_batch *b, int *iters_per_check, int *use_graph);
+/* Autotuning of batches: bound candidate batches of the same geometries (indexed with
+ * different block edges, say) each try iters_per_check 25 and 50 with and without graph
+ * replay, running max(trial_iters, interval) CG iterations along `axis` per trial, and
+ * keep their fastest setting; the wall time per iteration, net of labelling and initial
+ * guess, of each candidate's best setting goes to ms_per_iter[n] (may be NULL) and the
+ * fastest candidate's index to *best_index.  The workspaces' contents are overwritten. */
 rd_status rd_batch_autotune_pick(rd_batch *const *batches, int n, int axis, int64_t trial_iters,
                                  int *best_index, double *ms_per_iter);
 void rd_batch_destroy(rd_batch *b);

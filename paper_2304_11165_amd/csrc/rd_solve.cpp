@@ -39,10 +39,11 @@ struct CgOut {
     bool converged = false;
 };
 
-constexpr int CHECK_EVERY = 25;  // iterations between true-residual checks
-// stop after this many checks (1000 iterations) without a 10% gain of the best residual:
-// CG's residual is not monotone and plateaus for hundreds of iterations on large volumes
-constexpr int STALL_CHECKS = 40;
+constexpr int CHECK_EVERY = 25;  // iterations between true-residual checks (single geometry)
+// stop after this many iterations (40 checks of 25) without a 10% gain of the best
+// residual: CG's residual is not monotone and plateaus for hundreds of iterations on
+// large volumes
+constexpr int STALL_ITERS = 1000;
 
 // Initial guess on the GPU (cg_launch_initial_guess).  Its scratch lives in solver
 // vectors that CG has not used yet: the parent array in the Ap and second-p buffers,
@@ -86,13 +87,13 @@ rd_status push_scal(const CgArgs &a, const std::vector<double> &hs, hipStream_t 
     return RD_OK;
 }
 
-// The CHECK_EVERY iterations between two checks: every scalar they need (alpha, beta,
+// The iterations between two checks: every scalar they need (alpha, beta,
 // the live flags) is computed and read on the device, so the segment is one fixed
 // sequence of launches.  B = 8 alternates the two direction buffers; `a` leaves with
 // them in the order the next segment starts from.
-rd_status cg_segment(CgArgs &a, int storage, int B, hipStream_t st)
+rd_status cg_segment(CgArgs &a, int storage, int B, hipStream_t st, int iters)
 {
-    for (int k = 0; k < CHECK_EVERY; ++k) {
+    for (int k = 0; k < iters; ++k) {
         if (B == 8) {
             // p <- r + beta p fused into the matvec (beta = 0 on the first pass, where
             // p = r already), written to the other p buffer
@@ -117,6 +118,7 @@ struct SegmentGraphs {
     hipStream_t cap = nullptr;
     struct Entry {
         void *p;
+        int iters;
         hipGraphExec_t exec;
     };
     std::vector<Entry> g;
@@ -125,16 +127,16 @@ struct SegmentGraphs {
         for (auto &e : g) hipGraphExecDestroy(e.exec);
         if (cap) hipStreamDestroy(cap);
     }
-    rd_status run(CgArgs &a, int storage, int B, hipStream_t st)
+    rd_status run(CgArgs &a, int storage, int B, hipStream_t st, int iters)
     {
         Entry *hit = nullptr;
         for (auto &e : g)
-            if (e.p == a.p) hit = &e;
+            if (e.p == a.p && e.iters == iters) hit = &e;
         if (!hit) {
             if (!cap) HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
             CgArgs c = a;
             HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-            rd_status s = cg_segment(c, storage, B, cap);
+            rd_status s = cg_segment(c, storage, B, cap, iters);
             hipGraph_t graph = nullptr;
             const hipError_t ce = hipStreamEndCapture(cap, &graph);
             if (s != RD_OK) {
@@ -142,7 +144,7 @@ struct SegmentGraphs {
                 return s;
             }
             HIPCHK(ce);
-            Entry e{a.p, nullptr};
+            Entry e{a.p, iters, nullptr};
             const hipError_t ie = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
             hipGraphDestroy(graph);
             HIPCHK(ie);
@@ -150,18 +152,20 @@ struct SegmentGraphs {
             hit = &g.back();
         }
         HIPCHK(hipGraphLaunch(hit->exec, st));
-        if (B == 8 && (CHECK_EVERY & 1)) std::swap(a.p, a.p2);
+        if (B == 8 && (iters & 1)) std::swap(a.p, a.p2);
         return RD_OK;
     }
 };
 
 // Runs CG on every geometry of `a` (Dirichlet values already in x) from a linear
 // ramp, stopping each geometry at rel. residual <= tol, stagnation or max_iters.
-// use_graph: replay each segment of CHECK_EVERY iterations as a captured graph.
+// check_every: iterations between two checks; use_graph: replay each segment of
+// check_every iterations as a captured graph.
 rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axis, double tol,
                  int64_t max_iters, const std::vector<GeomMeta> &meta, std::vector<CgOut> &out,
-                 int stall_checks = STALL_CHECKS, bool want_tau = true, bool use_graph = true)
+                 bool want_tau = true, int check_every = CHECK_EVERY, bool use_graph = true)
 {
+    const int stall_checks = std::max(1, STALL_ITERS / check_every);
     CgArgs a = args;  // B = 8 swaps the two p buffers every iteration
     const int n = a.ngeom;
     out.assign(n, CgOut());
@@ -193,9 +197,9 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
     SegmentGraphs graphs;
     while (live > 0) {
         if (use_graph) {
-            if ((s = graphs.run(a, storage, B, st)) != RD_OK) return s;
+            if ((s = graphs.run(a, storage, B, st, check_every)) != RD_OK) return s;
         } else {
-            if ((s = cg_segment(a, storage, B, st)) != RD_OK) return s;
+            if ((s = cg_segment(a, storage, B, st, check_every)) != RD_OK) return s;
         }
         bool replace = false, rescale = false;
         // true residual b - A x in FP64 (the recursive one drifts in the storage type's
@@ -211,7 +215,7 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
         for (int g = 0; g < n; ++g) {
             double *v = &hs[(size_t)g * CG_NSCAL];
             if (v[CG_DONE] != 0.0) continue;
-            out[g].iters += CHECK_EVERY;
+            out[g].iters += check_every;
             const double rel = sqrt(std::max(0.0, v[CG_CHECK]) / v[CG_BB]);
             out[g].rel = rel;
             if (!isfinite(rel)) return rd_fail(RD_ERR_NONFINITE, "CG residual is not finite");
@@ -351,7 +355,7 @@ extern "C" rd_status rd_sim_steady_state(rd_sim *sim, int axis, double rel_tol, 
     // iteration); 16-bit storage is too coarse for that and updates X directly
     a.x64_direct = sim->storage == RD_FP32 ? 0 : 1;
     if (!a.x64_direct) LAUNCHCHK(rd_launch_fill_u32(a.x, 0u, nslots, stream));  // FP32: one word a slot
-    rd_status s = run_cg(a, st_, G.B, stream, axis, rel_tol, max_iters, meta, out, STALL_CHECKS, true);
+    rd_status s = run_cg(a, st_, G.B, stream, axis, rel_tol, max_iters, meta, out, true);
     if (s != RD_OK) return s;
     // (run_cg leaves X rounded to the storage type in the field and tau from its FP64 flux)
     const double rel = out[0].rel;
@@ -383,6 +387,8 @@ struct rd_batch {
            o_scal = 0, total = 0;
     char *ws = nullptr;
     hipStream_t stream = nullptr;
+    int check_every = CHECK_EVERY;  // CG iterations per captured segment / between checks
+    bool use_graph = true;
 };
 
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -531,7 +537,7 @@ rd_status batch_cg(rd_batch *b, int axis, double rel_tol, int64_t max_iters, boo
         a.x64_direct = b->storage == RD_FP32 ? 0 : 1;
         if (!a.x64_direct) LAUNCHCHK(rd_launch_fill_u32(a.x, 0u, nslots, b->stream));
         return run_cg(a, (int)b->storage, b->B, b->stream, axis, rel_tol, max_iters, meta, out,
-                      STALL_CHECKS, want_tau);
+                      want_tau, b->check_every, b->use_graph);
     }
     out.assign(n, CgOut());
     for (auto &o : out) o.tau = std::numeric_limits<double>::infinity();
@@ -557,6 +563,47 @@ extern "C" rd_status rd_batch_tortuosity(rd_batch *b, int axis, double rel_tol, 
     return RD_OK;
 }
 
+extern "C" rd_status rd_batch_set_launch(rd_batch *b, int iters_per_check, int use_graph)
+{
+    if (!b) return rd_fail(RD_ERR_ARG, "batch is NULL");
+    if (iters_per_check < 1 || iters_per_check > 1000) return rd_fail(RD_ERR_ARG, "iters_per_check in 1..1000");
+    b->check_every = iters_per_check;
+    b->use_graph = use_graph != 0;
+    return RD_OK;
+}
+
+extern "C" rd_status rd_batch_get_launch(const rd_batch *b, int *iters_per_check, int *use_graph)
+{
+    if (!b) return rd_fail(RD_ERR_ARG, "batch is NULL");
+    if (iters_per_check) *iters_per_check = b->check_every;
+    if (use_graph) *use_graph = b->use_graph ? 1 : 0;
+    return RD_OK;
+}
+
+namespace {
+// Wall time per iteration of trial_iters CG iterations of a batch with its current launch
+// setting: a run with them minus one without (labelling, initial guess and the first
+// residual are in both; a first run without iterations warms the launch paths up).
+rd_status batch_ms_per_iter(rd_batch *b, int axis, int64_t trial_iters, double *ms)
+{
+    std::vector<CgOut> out;
+    rd_status s = batch_cg(b, axis, 0.0, 0, false, out);
+    if (s != RD_OK) return s;
+    auto t0 = std::chrono::steady_clock::now();
+    s = batch_cg(b, axis, 0.0, 0, false, out);
+    if (s != RD_OK) return s;
+    auto t1 = std::chrono::steady_clock::now();
+    s = batch_cg(b, axis, 0.0, trial_iters, false, out);
+    if (s != RD_OK) return s;
+    auto t2 = std::chrono::steady_clock::now();
+    int64_t done = 0;
+    for (const CgOut &o : out) done = std::max(done, o.iters);
+    *ms = std::max(1e-6, std::chrono::duration<double, std::milli>((t2 - t1) - (t1 - t0)).count() /
+                             (double)std::max<int64_t>(1, done));
+    return RD_OK;
+}
+}  // namespace
+
 extern "C" rd_status rd_batch_autotune_pick(rd_batch *const *batches, int n, int axis, int64_t trial_iters,
                                             int *best_index, double *ms_per_iter)
 {
@@ -565,26 +612,31 @@ extern "C" rd_status rd_batch_autotune_pick(rd_batch *const *batches, int n, int
     *best_index = -1;
     double best = 1e300;
     for (int i = 0; i < n; ++i) {
-        // wall time of trial_iters iterations: a run with them minus one without
-        // (labelling, initial guess and the first residual are in both)
-        // (a first run without iterations warms the launch paths up)
-        std::vector<CgOut> out;
-        rd_status s = batch_cg(batches[i], axis, 0.0, 0, false, out);
-        if (s != RD_OK) return s;
-        auto t0 = std::chrono::steady_clock::now();
-        s = batch_cg(batches[i], axis, 0.0, 0, false, out);
-        if (s != RD_OK) return s;
-        auto t1 = std::chrono::steady_clock::now();
-        s = batch_cg(batches[i], axis, 0.0, trial_iters, false, out);
-        if (s != RD_OK) return s;
-        auto t2 = std::chrono::steady_clock::now();
-        int64_t done = 0;
-        for (const CgOut &o : out) done = std::max(done, o.iters);
-        const double ms = std::max(1e-6, std::chrono::duration<double, std::milli>((t2 - t1) - (t1 - t0)).count() /
-                                               (double)std::max<int64_t>(1, done));
-        if (ms_per_iter) ms_per_iter[i] = ms;
-        if (ms < best) {
-            best = ms;
+        // each candidate keeps its fastest launch setting: iterations per captured
+        // segment (between residual checks) and graph replay or direct launches
+        rd_batch *b = batches[i];
+        if (!b) return rd_fail(RD_ERR_ARG, "NULL batch");
+        double bi = 1e300;
+        int bc = b->check_every;
+        bool bg = b->use_graph;
+        for (int ce : {25, 50})
+            for (int gr = 1; gr >= 0; --gr) {
+                b->check_every = ce;
+                b->use_graph = gr != 0;
+                double ms = 0.0;
+                rd_status s = batch_ms_per_iter(b, axis, std::max<int64_t>(trial_iters, ce), &ms);
+                if (s != RD_OK) return s;
+                if (ms < bi) {
+                    bi = ms;
+                    bc = ce;
+                    bg = gr != 0;
+                }
+            }
+        b->check_every = bc;
+        b->use_graph = bg;
+        if (ms_per_iter) ms_per_iter[i] = bi;
+        if (bi < best) {
+            best = bi;
             *best_index = i;
         }
     }

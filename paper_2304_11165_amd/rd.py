@@ -72,6 +72,8 @@ _SIGS = {
     "rd_sdf_from_image": ([P, i64, i64, i64, f64, P, P, ctypes.c_size_t, P], ci),
     "rd_sdf_from_image_static": ([P, i64, i64, i64, f64, P, P], ci),
     "rd_sim_set_layout": ([P, ci], ci),
+    "rd_batch_set_launch": ([P, ci, ci], ci),
+    "rd_batch_get_launch": ([P, P, P], ci),
     "rd_sim_frap_curve": ([P, ci, P, f64, i64, i64, P], ci),
     "rd_frap_fit": ([i64, P, P, i64, f64, P, f64, P, P], ci),
     "rd_sim_get_field": ([P, ci, P], ci),
@@ -507,6 +509,17 @@ class Batch:
                                   self.workspace.numel(), _stream_handle(self.stream)),
                "rd_batch_bind")
         return self
+
+    def set_launch(self, iters_per_check=25, use_graph=True):
+        _check(_lib.rd_batch_set_launch(self.handle, int(iters_per_check), 1 if use_graph else 0),
+               "rd_batch_set_launch")
+        return self
+
+    def get_launch(self):
+        it, gr = ci(), ci()
+        _check(_lib.rd_batch_get_launch(self.handle, ctypes.byref(it), ctypes.byref(gr)),
+               "rd_batch_get_launch")
+        return {"iters_per_check": it.value, "use_graph": gr.value}
 
     def tortuosity(self, axis=0, rel_tol=1e-8, max_iters=100000):
         n = len(self.geometries)

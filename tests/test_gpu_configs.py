@@ -203,6 +203,11 @@ def test_foam_crop256_tau_vs_stored_oracle(rd, foam_crop, storage, axis):
 # ---------------------------------------------------------------------------
 
 def test_batch64_tau_vs_stored_oracle(rd):
+    """All 64 packings in one batch against the oracle's tau (CG to 1e-12).  The batched
+    benchmark solves to a relative residual of 1e-6 with 25 or 50 iterations per check
+    (graph and direct launches give the same bits, test_gpu_solve); at 1e-6 the measured
+    tau error reaches 1e-4 on the largest packings, so each setting is checked there against
+    2e-4, and once more solved to 1e-8, where tau must agree to 1e-5."""
     ref = _json("batch64_tau.json")["members"]
     geoms = W.batch_geometries()
     assert len(geoms) == len(ref) == 64
@@ -210,17 +215,21 @@ def test_batch64_tau_vs_stored_oracle(rd):
         assert _sha(img) == r["sha256"], f"packing {r['i']} differs from the stored one"
     hs = [rd.Geometry(img, None, 1.0, 8) for img, _ in geoms]
     bt = rd.Batch(hs).bind()
-    tau, rel, it = bt.tortuosity(0, 1e-6, 100000)
-    errs = []
-    for i, r in enumerate(ref):
-        if r["tau"] is None:
-            assert math.isinf(tau[i])
-            continue
-        errs.append(abs(tau[i] - r["tau"]) / r["tau"])
-    print(f"batch of 64: max tau rel err {max(errs):.2e}, median {np.median(errs):.2e}; largest "
-          f"final residual {np.max(rel):.2e}; iterations {int(np.min(it))}..{int(np.max(it))}")
-    assert np.all(rel <= 1e-6)
-    assert max(errs) <= 1e-4
+    for every, use_graph, tol, bar in ((50, False, 1e-6, 2e-4), (25, True, 1e-6, 2e-4),
+                                       (25, True, 1e-8, 1e-5)):
+        bt.set_launch(every, use_graph)
+        tau, rel, it = bt.tortuosity(0, tol, 100000)
+        errs = []
+        for i, r in enumerate(ref):
+            if r["tau"] is None:
+                assert math.isinf(tau[i])
+                continue
+            errs.append(abs(tau[i] - r["tau"]) / r["tau"])
+        print(f"batch of 64, {every} iterations per check, tolerance {tol:g}: max tau rel err "
+              f"{max(errs):.2e}, median {np.median(errs):.2e}; largest final residual "
+              f"{np.max(rel):.2e}; iterations {int(np.min(it))}..{int(np.max(it))}")
+        assert np.all(rel <= tol)
+        assert max(errs) <= bar
 
 
 # ---------------------------------------------------------------------------

@@ -208,3 +208,24 @@ def test_batch_autotune_pick(rd, oracle_mod):
             uo, _, _ = oracle_mod.steady_state(im, 0, "cg", tol=1e-12)
             tau_o = oracle_mod.tortuosity_from_field(im, 0, uo)[0]
             assert tau[i] == pytest.approx(tau_o, rel=1e-7)
+
+
+def test_batch_launch_settings(rd, oracle_mod):
+    """The batch's CG segment replayed as a captured graph gives the bits of direct
+    launches; 50 iterations per check stops at other points but reaches the oracle's tau."""
+    imgs = [W.boolean_spheres(n, 0.5, 2.0, 4.0, seed=70 + n)[0] for n in (18, 27, 35)]
+    geoms = [rd.Geometry(im, None, 1.0, 8) for im in imgs]
+    res = {}
+    for every, graph in ((25, True), (25, False), (50, True)):
+        bt = rd.Batch(geoms).bind().set_launch(every, graph)
+        assert bt.get_launch() == {"iters_per_check": every, "use_graph": int(graph)}
+        res[(every, graph)] = bt.tortuosity(0, 1e-8, 20000)
+    np.testing.assert_array_equal(res[(25, True)][0], res[(25, False)][0])
+    np.testing.assert_array_equal(res[(25, True)][2], res[(25, False)][2])
+    assert np.all(res[(50, True)][2] % 50 == 0)
+    for i, im in enumerate(imgs):
+        uo, _, _ = oracle_mod.steady_state(im, 0, "cg", tol=1e-12)
+        tau_o = oracle_mod.tortuosity_from_field(im, 0, uo)[0]
+        for key, (tau, rel, it) in res.items():
+            assert tau[i] == pytest.approx(tau_o, rel=1e-7), key
+            assert rel[i] <= 1e-8
