@@ -212,7 +212,9 @@ def make_soil512():
         print(f"soil512: {n} steps ({time.time() - t:.1f} s)", flush=True)
         flat = c.reshape(c.shape[0], -1)
         rec[f"samples_{n}"] = np.stack([flat[s][idx] for s in range(c.shape[0])])
-        rec[f"xprofile_{n}"] = c.sum(axis=(2, 3))  # (species, nx): mass per x-plane
+        # c is (species, nz, ny, nx): mass per x-plane (along the inflow) and per z-plane
+        rec[f"xprofile_{n}"] = c.sum(axis=(1, 2))
+        rec[f"zprofile_{n}"] = c.sum(axis=(2, 3))
         for s in range(c.shape[0]):
             m, inflow, up, re = prob.balance(c, s)
             rec[f"balance_{n}_{s}"] = np.array([m, *inflow, up, re])
