@@ -204,7 +204,7 @@ __global__ __launch_bounds__(256) void k_step8l(StepArgs a)
         // halo sources of plane z: x faces at (u, v) = (y, z), y faces at (x, z)
         const int hx = (z * 8 + ly) * 4, hy = (z * 8 + lx) * 4;
         float res[S];
-        const uint32_t h = a.sround ? sr_voxel(voxel_id(g, gx, gy, gz), key) : 0u;
+        const uint32_t h = a.sround ? sr_voxel(g, gx, gy, gz, key) : 0u;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const float cz = c[s][z];

@@ -126,7 +126,7 @@ __global__ __launch_bounds__(256) void k_step_diff(DiffArgs d)
     float cen[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) cen[s] = rd_ld(cin, s * a.sstride + i);
-    const uint32_t h = a.sround ? sr_voxel(voxel_id(g, gx, gy, gz), diff_key(a)) : 0u;
+    const uint32_t h = a.sround ? sr_voxel(g, gx, gy, gz, diff_key(a)) : 0u;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         float nbv[6];
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(256) void k_step8e(DiffArgs d)
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (lane_bit(sector_lanes<T>(Wo[z]))) {
-            const uint32_t h = a.sround ? sr_voxel(voxel_id(g, gx, gy, gz), key) : 0u;
+            const uint32_t h = a.sround ? sr_voxel(g, gx, gy, gz, key) : 0u;
 #pragma unroll
             for (int s = 0; s < S; ++s) diff_store(a, cout, s, s * a.sstride + base + z * 64 + lane, h, res[s]);
         }

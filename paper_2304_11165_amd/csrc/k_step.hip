@@ -28,9 +28,10 @@ __device__ __forceinline__ uint32_t launch_key(const StepArgs &a)
     return a.sround ? sr_key(*a.ctr + a.ctr_off, a.seed) : 0u;
 }
 // Random word of one voxel (only used with stochastic rounding).
-__device__ __forceinline__ uint32_t voxel_bits(const StepArgs &a, uint32_t key, int64_t vid)
+__device__ __forceinline__ uint32_t voxel_bits(const StepArgs &a, uint32_t key, const GeomInfo &g, int gx, int gy,
+                                               int gz)
 {
-    return a.sround ? sr_voxel(vid, key) : 0u;
+    return a.sround ? sr_voxel(g, gx, gy, gz, key) : 0u;
 }
 
 // Store one updated value of species s (round to nearest, or stochastic rounding
@@ -198,7 +199,7 @@ __global__ __launch_bounds__(256) void k_step4w(StepArgs a)
     unsigned onf = 0u;
     if (bnd) onf = box_faces(g, gx, gy, gz);
     float res[S];
-    const uint32_t h = voxel_bits(a, launch_key(a), voxel_id(g, gx, gy, gz));
+    const uint32_t h = voxel_bits(a, launch_key(a), g, gx, gy, gz);
     vox_code<S, DTH>(a, &tile[wv][0][t], TLW, E, E2, code, onf, c, res, h);
     // whole sectors only; an inactive slot of an active sector stores its 0 again
     if (sector_active<T>(Wo, lane)) {
@@ -290,7 +291,7 @@ __global__ __launch_bounds__(256) void k_step8(StepArgs a)
         float cen[S], res[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) cen[s] = k == 0 ? c0[s] : c1[s];
-        const uint32_t h = voxel_bits(a, key, voxel_id(g, gx, gy, gz));
+        const uint32_t h = voxel_bits(a, key, g, gx, gy, gz);
         vox_code<S, DTH>(a, &tile[0][K::tidx(lx, ly, lz)], K::TL, K::E, K::E * K::E, k == 0 ? cd0 : cd1,
                          onf, cen, res, h);
         // whole sectors only; an inactive slot of an active sector stores its 0 again
@@ -317,6 +318,63 @@ __global__ __launch_bounds__(256) void k_step8(StepArgs a)
 // strided column from L2: an x face touches every 128-byte line of the neighbour
 // block.  It pays with FP32 storage; the barrier costs more than it saves for the
 // latency-bound 16-bit forms, so both are autotuner candidates.
+// Active-neighbour counts of a B = 8 block, one 32-bit word per lane (x, y) of the
+// column kernel: bits 3z..3z+2 hold the count of voxel (x, y, z) (0..6), equal to the
+// popcount of its code's six neighbour bits.  Built once per geometry from the mask
+// records: for each plane and direction a 64-bit word holds at bit l whether lane l's
+// neighbour in that direction is active (shifts of the plane word inside the block, the
+// neighbours' face words across its faces); three full adders sum the six words
+// bit-sliced, and lane l's count is bit l of the three sums.
+__device__ __forceinline__ uint64_t transpose8x8(uint64_t x)
+{
+    // bit r*8+c -> bit c*8+r: delta swaps of 1x1, 2x2 and 4x4 sub-blocks
+    uint64_t t = (x ^ (x >> 7)) & 0x00AA00AA00AA00AAull;
+    x = x ^ t ^ (t << 7);
+    t = (x ^ (x >> 14)) & 0x0000CCCC0000CCCCull;
+    x = x ^ t ^ (t << 14);
+    t = (x ^ (x >> 28)) & 0x00000000F0F0F0F0ull;
+    x = x ^ t ^ (t << 28);
+    return x;
+}
+__device__ __forceinline__ void full_add64(uint64_t a, uint64_t b, uint64_t c, uint64_t &sum, uint64_t &carry)
+{
+    const uint64_t t = a ^ b;
+    sum = t ^ c;
+    carry = (a & b) | (c & t);
+}
+
+// One thread per (block, lane): the lane's count word.
+__global__ void k_count_words8(const uint64_t *__restrict__ mask, uint32_t *__restrict__ ncnt, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t *rec = mask + (i >> 6) * 16;
+    const int l = (int)(i & 63);
+    constexpr uint64_t COL0 = 0x0101010101010101ull;  // lanes with x = 0
+    // face words: -x, +x, -y, +y, -z, +z at 8..13, face coordinates (u, v), bit v*8+u;
+    // the x faces' (u, v) = (y, z), so their transpose holds column x = 0 of plane z at
+    // bits y*8
+    const uint64_t tx0 = transpose8x8(rec[8]), tx1 = transpose8x8(rec[9]);
+    uint32_t w = 0u;
+    for (int z = 0; z < 8; ++z) {
+        const uint64_t P = rec[z];
+        const uint64_t xm = ((P << 1) & ~COL0) | ((tx0 >> z) & COL0);
+        const uint64_t xp = ((P >> 1) & ~(COL0 << 7)) | (((tx1 >> z) & COL0) << 7);
+        const uint64_t ym = (P << 8) | ((rec[10] >> (8 * z)) & 0xffull);
+        const uint64_t yp = (P >> 8) | (((rec[11] >> (8 * z)) & 0xffull) << 56);
+        const uint64_t zm = z > 0 ? rec[z - 1] : rec[12];
+        const uint64_t zp = z < 7 ? rec[z + 1] : rec[13];
+        uint64_t s1, c1, s2, c2, n1, n2;
+        full_add64(xm, xp, ym, s1, c1);
+        full_add64(yp, zm, zp, s2, c2);
+        full_add64(c1, c2, s1 & s2, n1, n2);
+        const uint32_t cnt = (uint32_t)(((s1 ^ s2) >> l) & 1ull) + 2u * (uint32_t)((n1 >> l) & 1ull) +
+                             4u * (uint32_t)((n2 >> l) & 1ull);
+        w |= cnt << (3 * z);
+    }
+    ncnt[i] = w;
+}
+
 namespace z8 {
 __device__ __forceinline__ int pix(int x, int y) { return (y + 1) * 10 + (x + 1); }
 }  // namespace z8
@@ -371,17 +429,16 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
 
     typedef typename RawOf<T>::type R;
     R rc[S][8], rh[6][S];
-    unsigned cd[8];
+    // the lane's active-neighbour counts of its 8 voxels (3 bits each)
+    const uint32_t ncw = a.ncnt[(int64_t)b * 64 + lane];
 #pragma unroll
     for (int z = 0; z < 8; ++z) {
         // the plane's loads under one predicate (0 where the voxel is inactive)
 #pragma unroll
         for (int s = 0; s < S; ++s) rc[s][z] = (R)0;
-        cd[z] = 0u;
         if (lane_bit(Wo[z])) {
 #pragma unroll
             for (int s = 0; s < S; ++s) rc[s][z] = ld_raw(cin, s * a.sstride + oi[z]);
-            cd[z] = (unsigned)a.code[oi[z]];
         }
     }
     // face halos, one value per lane and face: lane (u, v) = (lx, ly) reads the
@@ -457,6 +514,9 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
     const int gx = bx * 8 + lx, gy = by * 8 + ly;
     const bool bnd = boundary_block(g, bx, by, bz);
     const uint32_t key = launch_key(a);
+    // stochastic rounding: the lane's column word once, a wave-uniform plane word per plane
+    const bool need_h = DTH || !std::is_same<T, float>::value;
+    const uint32_t colw = (need_h && a.sround) ? sr_column(g, gx, gy, key) : 0u;
 #pragma unroll
     for (int z = 0; z < 8; ++z) {
         // plane z and its ring into LDS: the side halos of plane z sit at face
@@ -478,16 +538,17 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
         const int gz = bz * 8 + z;
-        const unsigned code = cd[z];
-        const unsigned m = code & 63u;
-        const bool act = (code & 64u) != 0u;
+        // active-neighbour count; walls are the in-box neighbours that are not active
+        // (out-of-box ones never are)
+        const float nact = (float)((ncw >> (3 * z)) & 7u);
+        const bool act = lane_bit(Wo[z]);
         unsigned onf = 0u;
         if (bnd) onf = box_faces(g, gx, gy, gz);
-        const int nwall = __popc(~onf & ~m & 0x3fu);
+        const float nwall = (6.0f - nact) - (float)__popc(onf);
         float cen[S], res[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) cen[s] = c[s][z];
-        const uint32_t h = voxel_bits(a, key, voxel_id(g, gx, gy, gz));
+        const uint32_t h = (need_h && a.sround) ? sr_combine(colw, sr_plane(gz, key)) : 0u;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const float *p = &tile[wv][s][z8::pix(lx, ly)];
@@ -495,9 +556,12 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
             const float up = z == 7 ? zhi[s] : c[s][z < 7 ? z + 1 : 7];
             const float nbv[6] = {p[-1], p[1], p[-10], p[10], dn, up};
             const float dth = DTH ? fp32_dither(cen[s], sr_species(h, s)) : 0.0f;
-            const float upd = rd_update<S, DTH>(cen[s], nbv, m, nwall, a.coef[s], cen, dth);
-            const bool isd = (onf & a.coef[s].dir) != 0u;
-            res[s] = act ? (isd ? cen[s] : upd) : 0.0f;
+            const float upd = rd_update_n<S, DTH>(cen[s], nbv, nact, nwall, a.coef[s], cen, dth);
+            float r = upd;
+            if (bnd) {  // Dirichlet voxels lie on the box faces: boundary blocks only (uniform)
+                if ((onf & a.coef[s].dir) != 0u) r = cen[s];
+            }
+            res[s] = act ? r : 0.0f;
         }
         // every lane has read plane z before any lane overwrites it with plane z + 1
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -661,8 +725,8 @@ __global__ __launch_bounds__(256) void k_step8p(StepArgs a)
         const int gy = by * 8 + ly, gz = bz * 8 + lzp;
         const int64_t base = (int64_t)b * 512;
         float res[2][S];
-        const int64_t v0 = voxel_id(g, bx * 8 + 2 * lx2, gy, gz);
-        const uint32_t h0 = voxel_bits(a, key, v0), h1 = voxel_bits(a, key, v0 + 1);
+        const uint32_t h0 = voxel_bits(a, key, g, bx * 8 + 2 * lx2, gy, gz),
+                       h1 = voxel_bits(a, key, g, bx * 8 + 2 * lx2 + 1, gy, gz);
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int lx = 2 * lx2 + j;
@@ -1282,6 +1346,15 @@ int rd_launch_set_dirichlet(int storage, int B, const BlockInfo *info, const uin
 int rd_launch_add_u32(uint32_t *ptr, uint32_t add, void *stream)
 {
     hipLaunchKernelGGL(k_add_u32, dim3(1), dim3(64), 0, (hipStream_t)stream, ptr, add);
+    return (int)hipGetLastError();
+}
+
+int rd_launch_count_words8(const uint64_t *mask, uint32_t *ncnt, int nb, void *stream)
+{
+    const int64_t n = (int64_t)nb * 64;
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_count_words8, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, mask,
+                       ncnt, n);
     return (int)hipGetLastError();
 }
 

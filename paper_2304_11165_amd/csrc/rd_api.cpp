@@ -314,6 +314,9 @@ SimLayout sim_layout(const rd_sim &s, uint32_t features, int64_t cp_slots)
     L.info = off; off = align256(off + sizeof(BlockInfo) * (size_t)std::max<int64_t>(nb, 1));
     L.mask = off; off = align256(off + 8 * (size_t)mask_words(g.B) * (size_t)std::max<int64_t>(nb, 1));
     L.geom = off; off = align256(off + sizeof(GeomInfo));
+    if (g.B == 8) {
+        L.ncnt = off; off = align256(off + 4 * 64 * (size_t)std::max<int64_t>(nb, 1));
+    }
     if (s.compact) {
         // only the active voxels: codes and each species' values in list and slot order
         L.code = off; off = align256(off + (size_t)std::max<int64_t>(g.n_active, 1));
@@ -386,6 +389,9 @@ rd_status rd_sim::upload(bool index)
         HIPCHK(hipMemcpyAsync(ws + L.info, G.info.data(), sizeof(BlockInfo) * nb, hipMemcpyHostToDevice, stream));
         HIPCHK(hipMemcpyAsync(ws + L.mask, G.mask.data(), 8 * mask_words(G.B) * nb, hipMemcpyHostToDevice,
                               stream));
+        if (G.B == 8)
+            LAUNCHCHK(rd_launch_count_words8((const uint64_t *)(ws + L.mask), (uint32_t *)(ws + L.ncnt), (int)nb,
+                                             stream));
         if (compact) {
             if (cbase_host.size() != (size_t)nb + 1) rd_geometry_compact_index(&G, cbase_host, ccode_host);
             HIPCHK(hipMemcpyAsync(ws + L.code, ccode_host.data(), ccode_host.size(), hipMemcpyHostToDevice,
@@ -445,6 +451,7 @@ StepArgs rd_sim::step_args(double dt, int in_buf) const
     a.info = (const BlockInfo *)(ws + L.info);
     a.mask = (const uint64_t *)(ws + L.mask);
     a.code = (const uint8_t *)(ws + L.code);
+    a.ncnt = g->B == 8 ? (const uint32_t *)(ws + L.ncnt) : nullptr;
     a.cbase = cbase_ptr();
     a.geom = (const GeomInfo *)(ws + L.geom);
     a.cin = field_ptr(in_buf, 0);

@@ -151,17 +151,38 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x)
     return x;
 }
 
-// The random bits of a store come in three layers so that a kernel hashes once per
-// voxel: a key per (step, seed), wave-uniform; 32 bits per voxel from the key and the
-// voxel's linear index in its box (independent of the block layout); 16 bits per
-// species out of those (species 2 and 3 mix the voxel word once more).
+// The random bits of a store come in layers so that a kernel spends little per voxel:
+// a key per (step, seed), wave-uniform; a column word from the key and the voxel's
+// (x, y) column in its box and a plane word from the key and its z plane (so the bits
+// do not depend on the block layout, and a kernel that walks a z-column hashes the
+// column once and each plane once per wave); their XOR, finalised by one
+// xorshift-multiply-xorshift round (the first half of the MurmurHash3 finaliser), is the
+// voxel's 32-bit word; 16 bits per species out of it (species 2 and 3 mix the voxel word
+// once more).  For a fixed voxel the word is a bijection of the uniformly distributed
+// column-plane XOR, so its bits are uniform over the steps' keys.
 __device__ __forceinline__ uint32_t sr_key(uint32_t step, uint32_t seed)
 {
     return mix32(step ^ mix32(seed + 0x9e3779b9u));
 }
-__device__ __forceinline__ uint32_t sr_voxel(int64_t vid, uint32_t key)
+__device__ __forceinline__ uint32_t sr_column(const GeomInfo &g, int gx, int gy, uint32_t key)
 {
-    return mix32((uint32_t)vid ^ ((uint32_t)(vid >> 32) * 0x27d4eb2fu) ^ key);
+    return mix32(((uint32_t)gy * (uint32_t)g.nx + (uint32_t)gx) ^ key);
+}
+__device__ __forceinline__ uint32_t sr_plane(int gz, uint32_t key)
+{
+    return mix32((uint32_t)gz ^ mix32(key ^ 0x3c6ef372u));
+}
+__device__ __forceinline__ uint32_t sr_combine(uint32_t column, uint32_t plane)
+{
+    uint32_t x = column ^ plane;
+    x ^= x >> 16;
+    x *= 0x85ebca6bu;
+    x ^= x >> 13;
+    return x;
+}
+__device__ __forceinline__ uint32_t sr_voxel(const GeomInfo &g, int gx, int gy, int gz, uint32_t key)
+{
+    return sr_combine(sr_column(g, gx, gy, key), sr_plane(gz, key));
 }
 __device__ __forceinline__ uint32_t sr_species(uint32_t h, int species)
 {
@@ -362,21 +383,29 @@ __device__ __forceinline__ bool on_dirichlet(uint32_t dir, int gx, int gy, int g
 // added to c once, so c is rounded once per step (forming c + alpha lap and then applying
 // each term to it rounded c up to four times).  DTH (FP32 storage with stochastic
 // rounding): `dith` (fp32_dither) is added to the increment before that final addition.
+// rd_update_n takes the active-neighbour count and the wall count as floats (exact small
+// integers), rd_update the neighbour bits; both round identically.
 template <int S, bool DTH = false>
-__device__ __forceinline__ float rd_update(float uc, const float nbv[6], unsigned nbm, int nwall,
-                                           const SpeciesCoef &k, const float *cen, float dith = 0.0f)
+__device__ __forceinline__ float rd_update_n(float uc, const float nbv[6], float nact, float nwall,
+                                             const SpeciesCoef &k, const float *cen, float dith = 0.0f)
 {
     float sum = nbv[0];
 #pragma unroll
     for (int d = 1; d < 6; ++d) sum = sum + nbv[d];
-    const float lap = fmaf(-(float)__popc(nbm & 63u), uc, sum);
+    const float lap = fmaf(-nact, uc, sum);
     float inc = k.alpha * lap;
-    const float loss = fmaf(k.gamma, (float)nwall, k.beta);
+    const float loss = fmaf(k.gamma, nwall, k.beta);
     inc = fmaf(-loss, uc, inc);
 #pragma unroll
     for (int b = 0; b < S; ++b) inc = fmaf(k.K[b], cen[b], inc);
     if constexpr (DTH) inc = inc + dith;
     return uc + inc;
+}
+template <int S, bool DTH = false>
+__device__ __forceinline__ float rd_update(float uc, const float nbv[6], unsigned nbm, int nwall,
+                                           const SpeciesCoef &k, const float *cen, float dith = 0.0f)
+{
+    return rd_update_n<S, DTH>(uc, nbv, (float)__popc(nbm & 63u), (float)nwall, k, cen, dith);
 }
 
 // Stochastic rounding of FP32 values: a dither (u - 1/2) ulp(c), u in [0, 1) from 16
@@ -386,8 +415,11 @@ __device__ __forceinline__ float rd_update(float uc, const float nbv[6], unsigne
 // (ulp / 2) / (dt * slowest decay rate) away from it.  0 for zero and subnormal c.
 __device__ __forceinline__ float fp32_dither(float uc, uint32_t bits16)
 {
-    const float ulp = __uint_as_float(__float_as_uint(uc) & 0x7f800000u) * 0x1p-23f;
-    return fmaf((float)bits16, 0x1p-16f * ulp, -0.5f * ulp);
+    // 2^-23 (1 + u) with the 16 bits as the leading mantissa bits, minus 1.5 * 2^-23, is
+    // (u - 1/2) 2^-23 exactly; times the power of two of c (c's exponent bits) it is
+    // (u - 1/2) ulp(c)
+    const float v = __uint_as_float(0x34000000u | (bits16 << 7)) - 0x1.8p-23f;
+    return v * __uint_as_float(__float_as_uint(uc) & 0x7f800000u);
 }
 
 // Linear index of a voxel in its (nz, ny, nx) box: the key of the stochastic-rounding

@@ -54,6 +54,8 @@ struct StepArgs {
     const BlockInfo *info;
     const uint64_t *mask;
     const uint8_t *code;   // per-slot neighbour codes (bits 0-5 neighbours, bit 6 active)
+    const uint32_t *ncnt;  // B = 8: active-neighbour counts, one word per (block, lane
+                           // (x, y)): bits 3z..3z+2 hold the count of voxel (x, y, z)
     const uint32_t *cbase; // compact layout: first voxel of each block (nb + 1); NULL:
                            // block-major layout with every slot stored
     const GeomInfo *geom;  // indexed by geometry id
@@ -121,4 +123,6 @@ int rd_launch_gather(int storage, int B, const BlockInfo *info, const uint64_t *
                      const uint32_t *cbase, const GeomInfo *geom, int nb, const void *field, float *dense,
                      int64_t ndense, void *stream);
 int rd_launch_fill_u32(void *ptr, uint32_t value, int64_t n_words, void *stream);
+// B = 8: the active-neighbour count words (StepArgs::ncnt) of nb blocks
+int rd_launch_count_words8(const uint64_t *mask, uint32_t *ncnt, int nb, void *stream);
 int rd_launch_add_u32(uint32_t *ptr, uint32_t add, void *stream);
