@@ -46,6 +46,14 @@ __device__ __forceinline__ void store_val(const StepArgs &a, T *cout, int s, int
     else if (a.sround) rd_st_sr(cout, idx, r, sr_species(h, s));
     else rd_st(cout, idx, r);
 }
+// The same with the rounding mode fixed at compile time (SR: stochastic rounding on).
+template <typename T, bool PLAIN, bool SR>
+__device__ __forceinline__ void store_val_ct(T *cout, int s, int64_t idx, uint32_t h, float r)
+{
+    if constexpr (PLAIN && sizeof(T) == 4) cout[idx] = r;
+    else if constexpr (SR) rd_st_sr(cout, idx, r, sr_species(h, s));
+    else rd_st(cout, idx, r);
+}
 
 // Branch-free update of voxel (lx, ly, lz) of a B = 8 block, all species.  W, Wm, Wp
 // are the active-bit words of planes lz, lz-1, lz+1 (or the -z / +z face words at the
@@ -385,6 +393,8 @@ __device__ __forceinline__ int pix(int x, int y) { return (y + 1) * 10 + (x + 1)
 // from the neighbour's plane word and prefix count (one record line), a z halo from
 // the face word.  Loads, arithmetic and stored values are those of the block-major
 // layout, so both give the same bits; stores cover the active voxels only.
+// DTH: stochastic rounding (FP32: the dither added to each increment; 16-bit: the
+// rounding of the stores).
 template <typename T, int S, bool XCH, bool CMP, bool DTH>
 __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
 {
@@ -514,9 +524,10 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
     const int gx = bx * 8 + lx, gy = by * 8 + ly;
     const bool bnd = boundary_block(g, bx, by, bz);
     const uint32_t key = launch_key(a);
-    // stochastic rounding: the lane's column word once, a wave-uniform plane word per plane
-    const bool need_h = DTH || !std::is_same<T, float>::value;
-    const uint32_t colw = (need_h && a.sround) ? sr_column(g, gx, gy, key) : 0u;
+    // stochastic rounding (DTH; FP32: the dither, 16-bit: at the store): the lane's column
+    // word once, a wave-uniform plane word per plane
+    constexpr bool DITHER = DTH && std::is_same<T, float>::value;
+    const uint32_t colw = DTH ? sr_column(g, gx, gy, key) : 0u;
 #pragma unroll
     for (int z = 0; z < 8; ++z) {
         // plane z and its ring into LDS: the side halos of plane z sit at face
@@ -548,15 +559,15 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
         float cen[S], res[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) cen[s] = c[s][z];
-        const uint32_t h = (need_h && a.sround) ? sr_combine(colw, sr_plane(gz, key)) : 0u;
+        const uint32_t h = DTH ? sr_combine(colw, sr_plane(gz, key)) : 0u;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const float *p = &tile[wv][s][z8::pix(lx, ly)];
             const float dn = z == 0 ? zlo[s] : c[s][z > 0 ? z - 1 : 0];
             const float up = z == 7 ? zhi[s] : c[s][z < 7 ? z + 1 : 7];
             const float nbv[6] = {p[-1], p[1], p[-10], p[10], dn, up};
-            const float dth = DTH ? fp32_dither(cen[s], sr_species(h, s)) : 0.0f;
-            const float upd = rd_update_n<S, DTH>(cen[s], nbv, nact, nwall, a.coef[s], cen, dth);
+            const float dth = DITHER ? fp32_dither(cen[s], sr_species(h, s)) : 0.0f;
+            const float upd = rd_update_n<S, DITHER>(cen[s], nbv, nact, nwall, a.coef[s], cen, dth);
             float r = upd;
             if (bnd) {  // Dirichlet voxels lie on the box faces: boundary blocks only (uniform)
                 if ((onf & a.coef[s].dir) != 0u) r = cen[s];
@@ -571,7 +582,7 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
         // its 0 again); compact: the active voxels, a contiguous run
         if (lane_bit(CMP ? Wo[z] : sector_lanes<T>(Wo[z]))) {
 #pragma unroll
-            for (int s = 0; s < S; ++s) store_val<T, CMP>(a, cout, s, s * a.sstride + oi[z], h, res[s]);
+            for (int s = 0; s < S; ++s) store_val_ct<T, CMP, DTH>(cout, s, s * a.sstride + oi[z], h, res[s]);
         }
     }
 }
@@ -1159,20 +1170,24 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, uint32_t v, int64
 template <int B>
 int groups_for(int nb) { return (nb + Cfg<B>::BPW - 1) / Cfg<B>::BPW; }
 
-template <typename T, int B, int S, bool DTH>
+// SR: stochastic rounding on.  The column kernel takes it for every storage type (FP32:
+// the dither; 16-bit: the rounding of its stores, fixed at compile time); the other
+// kernels take it as the FP32 dither only and round 16-bit stores by the run-time flag.
+template <typename T, int B, int S, bool SR>
 void launch_step_d(const StepArgs &a, int groups, hipStream_t st)
 {
+    constexpr bool DTH = SR && std::is_same<T, float>::value;
     if constexpr (B == 8) {
         if (a.kernel == 1)
             hipLaunchKernelGGL((k_step8p<T, S, DTH>), dim3(a.grid), dim3(256), 0, st, a);
         else if (a.kernel == 2 && a.cbase)
-            hipLaunchKernelGGL((k_step8z<T, S, false, true, DTH>), dim3(groups), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_step8z<T, S, false, true, SR>), dim3(groups), dim3(256), 0, st, a);
         else if (a.kernel == 3 && a.cbase)
-            hipLaunchKernelGGL((k_step8z<T, S, true, true, DTH>), dim3(groups), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_step8z<T, S, true, true, SR>), dim3(groups), dim3(256), 0, st, a);
         else if (a.kernel == 2)
-            hipLaunchKernelGGL((k_step8z<T, S, false, false, DTH>), dim3(groups), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_step8z<T, S, false, false, SR>), dim3(groups), dim3(256), 0, st, a);
         else if (a.kernel == 3)
-            hipLaunchKernelGGL((k_step8z<T, S, true, false, DTH>), dim3(groups), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_step8z<T, S, true, false, SR>), dim3(groups), dim3(256), 0, st, a);
         else
             hipLaunchKernelGGL((k_step8<T, S, DTH>), dim3(groups), dim3(256), 0, st, a);
     } else {
@@ -1185,7 +1200,7 @@ void launch_step_d(const StepArgs &a, int groups, hipStream_t st)
 template <typename T, int B, int S>
 void launch_step_s(const StepArgs &a, int groups, hipStream_t st)
 {
-    if (sizeof(T) == 4 && a.sround) launch_step_d<T, B, S, true>(a, groups, st);
+    if (a.sround) launch_step_d<T, B, S, true>(a, groups, st);
     else launch_step_d<T, B, S, false>(a, groups, st);
 }
 

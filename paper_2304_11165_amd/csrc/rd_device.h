@@ -192,34 +192,36 @@ __device__ __forceinline__ uint32_t sr_species(uint32_t h, int species)
 
 // Store with stochastic rounding: round up with probability equal to the distance
 // from the lower neighbour, in units of the storage spacing (unbiased on average).
+// Both forms add random bits below the cut of the FP32 pattern and truncate there, so
+// the magnitude rounds up exactly when the added bits carry across the cut; no branches.
 __device__ __forceinline__ uint16_t bf16_sr(float v, uint32_t rnd)
 {
-    // BF16 is the upper half of the FP32 pattern: adding 16 random bits below the cut
-    // and truncating rounds the magnitude up with probability (low bits) / 2^16
-    uint32_t u = __float_as_uint(v);
-    if ((u & 0x7f800000u) == 0x7f800000u) return bf16_rne(v);  // inf / NaN: nearest
-    u += rnd & 0xffffu;
-    return (uint16_t)(u >> 16);
+    // BF16 is the upper half of the FP32 pattern: 16 random bits below the cut round the
+    // magnitude up with probability (low bits) / 2^16.  Infinities keep their zero low
+    // bits' pattern above the cut; a NaN stays a (quiet) NaN.
+    const uint32_t u = __float_as_uint(v);
+    const bool nan = (u & 0x7fffffffu) > 0x7f800000u;
+    return nan ? (uint16_t)((u >> 16) | 0x40u) : (uint16_t)((u + (rnd & 0xffffu)) >> 16);
 }
 
 __device__ __forceinline__ _Float16 f16_sr(float v, uint32_t rnd)
 {
-    const _Float16 h = (_Float16)v;
-    const float hf = (float)h;
-    if (hf == v || !isfinite(v) || !isfinite(hf)) return h;
-    // the FP16 neighbour of h on the other side of v
-    uint16_t b = __builtin_bit_cast(uint16_t, h);
-    const bool neg = (b & 0x8000u) != 0;
-    const bool mag = (b & 0x7fffu) != 0;
-    uint16_t ob;
-    if (v > hf) ob = neg ? (mag ? (uint16_t)(b - 1) : (uint16_t)0x0001u) : (uint16_t)(b + 1);
-    else ob = neg ? (uint16_t)(b + 1) : (mag ? (uint16_t)(b - 1) : (uint16_t)0x8001u);
-    const _Float16 o = __builtin_bit_cast(_Float16, ob);
-    const float of = (float)o;
-    const float lo = fminf(hf, of), hi = fmaxf(hf, of);
-    const float prob_up = (v - lo) / (hi - lo);
-    const float u01 = (float)(rnd & 0xffffu) * (1.0f / 65536.0f);  // 16 random bits
-    return u01 < prob_up ? (hf > of ? h : o) : (hf > of ? o : h);
+    // FP16 keeps 10 mantissa bits down to 2^-14 (13 FP32 bits below its cut) and a fixed
+    // spacing of 2^-24 below (d = 126 - biased exponent bits below the cut, up to 23);
+    // d random bits (the 16 given, shifted into the top of the d) are added to the
+    // magnitude's pattern and the low d bits cleared, which leaves a multiple of the FP16
+    // spacing (a carry into the exponent is the next power of two).  Below 2^-24 the
+    // result is 2^-24 with probability |v| / 2^-24, else 0.  Infinities and NaNs convert
+    // as they are.
+    const uint32_t u = __float_as_uint(v);
+    const uint32_t ua = u & 0x7fffffffu;
+    const int eb = (int)(ua >> 23);
+    const int d = min(max(126 - eb, 13), 23);
+    const uint32_t r = ((rnd & 0xffffu) << 16) >> (32 - d);
+    uint32_t m = (ua + r) & (0xffffffffu << d);
+    if (eb < 103) m = (float)(rnd & 0xffffu) < __uint_as_float(ua) * 0x1p40f ? 0x33800000u : 0u;
+    const float q = __uint_as_float(m | (u & 0x80000000u));
+    return (_Float16)(eb == 255 ? v : q);
 }
 
 __device__ __forceinline__ void rd_st_sr(float *p, int64_t i, float v, uint32_t)
