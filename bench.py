@@ -650,9 +650,10 @@ def main():
             f"alg {alg_bytes / per_step / 1e9:.0f} GB/s, layout {layout_bytes / per_step / 1e9:.0f} GB/s")
         del sim
 
-    # reduced-storage accuracy against an FP32-storage run of the same length
+    # reduced-storage accuracy against an FP32-storage run of the same length (timed steps
+    # and warm-up steps)
     for storage in forms:
-        steps = results[storage]["steps"] + 50
+        steps = results[storage]["steps"] + results[storage]["warmup"]
         with torch.cuda.stream(stream):
             ref = build_sim(rd, geom, w, "fp32", a.graph_steps)
             ref.bind(stream=stream)
