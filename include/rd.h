@@ -109,6 +109,28 @@ rd_status rd_geometry_export_masks(const rd_geometry *g, uint64_t *masks);
 rd_status rd_geometry_export_codes(const rd_geometry *g, uint8_t *codes);
 void rd_geometry_destroy(rd_geometry *g);
 
+/* Several geometries stepped together: the time stepping of eq. reaction_diffusion
+ * (section "Methods") on many small volumes at once, which then share launches instead
+ * of paying a launch each.  rd_geometry_concat builds one geometry whose block list is
+ * the parts' lists one after another (neighbour indices shifted, each block tagged with
+ * its part); a simulation created on it steps every part in the same kernels, with the same species,
+ * reactions, Robin and Dirichlet settings (Dirichlet faces are each part's own box faces),
+ * and gives each part the bits it would get alone.  Its dense arrays (rd_sim_set_field,
+ * rd_sim_get_field) hold the parts' (nz,ny,nx) boxes one after another, part 0 first.
+ * The parts are copied (they may be destroyed afterwards); all need the same block edge
+ * and dx; at most 65535 parts.  Calls bound to one box (steady state, adjoint,
+ * diffusivity factor, sink band, plane flux, region mass, FRAP) return RD_ERR_STATE on
+ * such a simulation.  Errors: RD_ERR_ARG (NULL, n out of range, a part that is itself a
+ * concatenation), RD_ERR_SHAPE (mixed block edges or dx, more than 2^31 blocks). */
+rd_status rd_geometry_concat(const rd_geometry *const *parts, int n, rd_geometry **out);
+/* Number of parts (1 for a geometry built from one image; 0 for NULL). */
+int rd_geometry_parts(const rd_geometry *g);
+/* Part `part` of a geometry: box shape {nz, ny, nx}, offset of its box in the dense
+ * arrays, and its range of blocks in the list.  Outputs may be NULL.  RD_ERR_ARG for a
+ * bad part. */
+rd_status rd_geometry_part_info(const rd_geometry *g, int part, int64_t shape[3], int64_t *dense_offset,
+                                int64_t *first_block, int64_t *n_blocks);
+
 /* ---- signed distance on the GPU --------------------------------------------- */
 
 /* Signed distance of a voxel image (section "Level-set method for image-based geometry
@@ -302,7 +324,8 @@ rd_status rd_sim_frap_curve(rd_sim *sim, int species, const int64_t region[6], d
  * D_ref <= 0, non-finite values. */
 rd_status rd_frap_fit(int64_t n, const double *t, const double *f, int64_t m, double ds,
                       const double *g, double D_ref, double *D_eff, double *rms);
-/* Gather species s into a dense device float32 (nz,ny,nx); inactive voxels -> 0. */
+/* Gather species s into a dense device float32 (nz,ny,nx) (a concatenated geometry: the
+ * parts' boxes one after another); inactive voxels -> 0. */
 rd_status rd_sim_get_field(const rd_sim *sim, int species, float *dev_dense);
 /* Advance n_steps FTCS steps of size dt (asynchronous).  RD_ERR_UNSTABLE_DT if
  * dt > 2 / lambda_max with the Gershgorin bound
@@ -322,6 +345,10 @@ rd_status rd_sim_reduce(rd_sim *sim, int species, double *mass, double *dirichle
 /* All balance terms: out[0] mass, out[1..6] inflow per face, out[7] uptake,
  * out[8] reaction total (sum over free voxels of the reaction rate, times dx^3). */
 rd_status rd_sim_balance(rd_sim *sim, int species, double out[9]);
+/* rd_sim_balance over the blocks of one part of a concatenated geometry
+ * (rd_geometry_concat); part 0 of a single geometry is the whole.  RD_ERR_ARG for a bad
+ * part. */
+rd_status rd_sim_balance_part(rd_sim *sim, int species, int part, double out[9]);
 /* Diffusive flux of a species through the plane between indices i0 and i0 + 1 along
  * `axis` (0 x, 1 y, 2 z), positive in the +axis direction (the flux from which an
  * effective diffusivity, and with it the tortuosity of eq. background:tortuosity, is

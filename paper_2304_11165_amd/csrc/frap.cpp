@@ -55,6 +55,8 @@ static rd_status check_region(const rd_sim *sim, int species, const int64_t regi
 
 extern "C" rd_status rd_sim_region_mass(rd_sim *sim, int species, const int64_t region[6], double *mass)
 {
+    if (sim && sim->g->nparts() > 1)
+        return rd_fail(RD_ERR_STATE, "rd_sim_region_mass: one geometry per simulation only");
     if (!sim || !mass) return rd_fail(RD_ERR_ARG, "NULL argument");
     int32_t reg[6];
     rd_status st = check_region(sim, species, region, reg);
@@ -65,6 +67,8 @@ extern "C" rd_status rd_sim_region_mass(rd_sim *sim, int species, const int64_t 
 extern "C" rd_status rd_sim_frap_curve(rd_sim *sim, int species, const int64_t region[6], double dt,
                                        int64_t steps_per_sample, int64_t n_samples, double *curve)
 {
+    if (sim && sim->g->nparts() > 1)
+        return rd_fail(RD_ERR_STATE, "rd_sim_frap_curve: one geometry per simulation only");
     if (!sim || !curve) return rd_fail(RD_ERR_ARG, "NULL argument");
     int32_t reg[6];
     rd_status st = check_region(sim, species, region, reg);

@@ -384,10 +384,10 @@ __global__ __launch_bounds__(256) void k_reduce_diff(ReduceArgs a, const float *
 #pragma unroll
     for (int l = 0; l < RD_NRED; ++l) acc[l] = 0.0;
     const int sub = threadIdx.x / C::TPB, lt = threadIdx.x % C::TPB;
-    const int b = blockIdx.x * C::BPW + sub;
+    const int b = a.b0 + (int)blockIdx.x * C::BPW + sub;
     const T *c = (const T *)a.c;
     bool dblock = false;  // the block touches a Dirichlet face of the species (wave-uniform)
-    if (b < a.nb) {
+    if (b < a.b0 + a.nb) {
         const BlockInfo bi = a.info[b];
         int bx, by, bz, gid;
         block_pos(bi, &bx, &by, &bz, &gid);

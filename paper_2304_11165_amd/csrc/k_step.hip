@@ -775,8 +775,8 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a)
 
     const int sub = threadIdx.x / C::TPB;
     const int lt = threadIdx.x % C::TPB;
-    const int b = blockIdx.x * C::BPW + sub;
-    const bool valid = b < a.nb;
+    const int b = a.b0 + (int)blockIdx.x * C::BPW + sub;
+    const bool valid = b < a.b0 + a.nb;
     const T *c = (const T *)a.c;
 
     BlockInfo bi = {};
@@ -873,14 +873,14 @@ __global__ __launch_bounds__(256) void k_reduce8z(ReduceArgs a)
 {
     __shared__ double wsum[4][RD_NRED];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int b = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + wv);
+    const int b = __builtin_amdgcn_readfirstlane(a.b0 + (int)blockIdx.x * 4 + wv);
     double acc[RD_NRED];
 #pragma unroll
     for (int l = 0; l < RD_NRED; ++l) acc[l] = 0.0;
     bool hasreact = a.rate_out != 0.0;
     for (int s2 = 0; s2 < a.S; ++s2) hasreact = hasreact || a.rate_in[s2] != 0.0;
     bool dblock = false;
-    if (b < a.nb) {  // wave-uniform; the barrier below is outside
+    if (b < a.b0 + a.nb) {  // wave-uniform; the barrier below is outside
         const BlockInfo bi = a.info[b];
         int bx, by, bz, gid;
         block_pos(bi, &bx, &by, &bz, &gid);
@@ -1090,7 +1090,7 @@ __global__ __launch_bounds__(256) void k_scatter(const BlockInfo *info, const ui
         float v = 0.0f;
         const bool own = own_bit<B>(rec, slot);
         if (own) {
-            v = dense[((int64_t)gz * g.ny + gy) * g.nx + gx];
+            v = dense[voxel_id(g, gx, gy, gz)];
             const int onf[6] = {gx == 0, gx == g.nx - 1, gy == 0, gy == g.ny - 1, gz == 0,
                                 gz == g.nz - 1};
             for (int f = 0; f < 6; ++f)
@@ -1121,7 +1121,7 @@ __global__ __launch_bounds__(256) void k_gather(const BlockInfo *info, const uin
         const int lx = slot % B, ly = (slot / B) % B, lz = slot / (B * B);
         const int gx = bx * B + lx, gy = by * B + ly, gz = bz * B + lz;
         const int64_t i = cbase ? slot_index8(cbase, mask, b, slot) : (int64_t)b * K::NS + slot;
-        dense[((int64_t)gz * g.ny + gy) * g.nx + gx] = rd_ld(field, i);
+        dense[voxel_id(g, gx, gy, gz)] = rd_ld(field, i);
     }
 }
 

@@ -127,6 +127,81 @@ extern "C" rd_status rd_geometry_export_codes(const rd_geometry *g, uint8_t *cod
     return RD_OK;
 }
 
+extern "C" rd_status rd_geometry_concat(const rd_geometry *const *geoms, int n, rd_geometry **out)
+{
+    if (!out) return rd_fail(RD_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!geoms || n <= 0 || n > 65535) return rd_fail(RD_ERR_ARG, "need 1..65535 geometries");
+    for (int i = 0; i < n; ++i) {
+        if (!geoms[i]) return rd_fail(RD_ERR_ARG, "NULL geometry");
+        if (geoms[i]->nparts() > 1) return rd_fail(RD_ERR_ARG, "a part is itself a concatenation");
+        if (geoms[i]->B != geoms[0]->B) return rd_fail(RD_ERR_SHAPE, "all parts need the same block edge");
+        if (geoms[i]->dx != geoms[0]->dx) return rd_fail(RD_ERR_SHAPE, "all parts need the same dx");
+    }
+    int64_t total = 0, dense = 0;
+    for (int i = 0; i < n; ++i) total += geoms[i]->nb();
+    if (total >= INT32_MAX) return rd_fail(RD_ERR_SHAPE, "too many blocks");
+    rd_geometry *g = new (std::nothrow) rd_geometry();
+    if (!g) return rd_fail(RD_ERR_ARG, "out of host memory");
+    const int B = geoms[0]->B, MW = mask_words(B);
+    g->B = B;
+    g->dx = geoms[0]->dx;
+    try {
+        g->block_id.reserve(total);
+        g->info.reserve(total);
+        g->mask.reserve((size_t)total * MW);
+        g->code.reserve((size_t)total * B * B * B);
+        int32_t off = 0;
+        for (int i = 0; i < n; ++i) {
+            const rd_geometry &G = *geoms[i];
+            g->parts.push_back({(int32_t)G.nx, (int32_t)G.ny, (int32_t)G.nz, off, dense});
+            for (int64_t b = 0; b < G.nb(); ++b) {
+                BlockInfo bi = G.info[b];
+                for (int f = 0; f < 6; ++f)
+                    if (bi.nbr[f] >= 0) bi.nbr[f] += off;
+                bi.zg = (bi.zg & 0xffff) | (i << 16);
+                g->info.push_back(bi);
+            }
+            g->block_id.insert(g->block_id.end(), G.block_id.begin(), G.block_id.end());
+            g->mask.insert(g->mask.end(), G.mask.begin(), G.mask.end());
+            g->code.insert(g->code.end(), G.code.begin(), G.code.end());
+            g->n_active += G.n_active;
+            off += (int32_t)G.nb();
+            dense += G.dense_size();
+        }
+    } catch (const std::bad_alloc &) {
+        delete g;
+        return rd_fail(RD_ERR_ARG, "out of host memory");
+    }
+    g->nx = dense;
+    g->ny = g->nz = 1;
+    *out = g;
+    return RD_OK;
+}
+
+extern "C" rd_status rd_geometry_part_info(const rd_geometry *g, int part, int64_t shape[3], int64_t *dense_offset,
+                                           int64_t *first_block, int64_t *n_blocks)
+{
+    if (!g) return rd_fail(RD_ERR_ARG, "geometry is NULL");
+    if (part < 0 || part >= g->nparts()) return rd_fail(RD_ERR_ARG, "bad part");
+    if (g->parts.empty()) {
+        if (shape) shape[0] = g->nz, shape[1] = g->ny, shape[2] = g->nx;
+        if (dense_offset) *dense_offset = 0;
+        if (first_block) *first_block = 0;
+        if (n_blocks) *n_blocks = g->nb();
+        return RD_OK;
+    }
+    const GeomInfo &p = g->parts[part];
+    const int64_t end = part + 1 < g->nparts() ? g->parts[part + 1].block0 : g->nb();
+    if (shape) shape[0] = p.nz, shape[1] = p.ny, shape[2] = p.nx;
+    if (dense_offset) *dense_offset = p.dense0;
+    if (first_block) *first_block = p.block0;
+    if (n_blocks) *n_blocks = end - p.block0;
+    return RD_OK;
+}
+
+extern "C" int rd_geometry_parts(const rd_geometry *g) { return g ? g->nparts() : 0; }
+
 extern "C" void rd_geometry_destroy(rd_geometry *g) { delete g; }
 
 // ---------------------------------------------------------------------------
@@ -313,7 +388,7 @@ SimLayout sim_layout(const rd_sim &s, uint32_t features, int64_t cp_slots)
     size_t off = 0;
     L.info = off; off = align256(off + sizeof(BlockInfo) * (size_t)std::max<int64_t>(nb, 1));
     L.mask = off; off = align256(off + 8 * (size_t)mask_words(g.B) * (size_t)std::max<int64_t>(nb, 1));
-    L.geom = off; off = align256(off + sizeof(GeomInfo));
+    L.geom = off; off = align256(off + sizeof(GeomInfo) * (size_t)g.nparts());
     if (g.B == 8) {
         L.ncnt = off; off = align256(off + 4 * 64 * (size_t)std::max<int64_t>(nb, 1));
     }
@@ -401,9 +476,10 @@ rd_status rd_sim::upload(bool index)
         } else {
             HIPCHK(hipMemcpyAsync(ws + L.code, G.code.data(), G.code.size(), hipMemcpyHostToDevice, stream));
         }
-        GeomInfo gi{(int32_t)G.nx, (int32_t)G.ny, (int32_t)G.nz, 0};
-        geom_host = gi;
-        HIPCHK(hipMemcpyAsync(ws + L.geom, &geom_host, sizeof(GeomInfo), hipMemcpyHostToDevice, stream));
+        if (G.parts.empty()) geom_host.assign(1, GeomInfo{(int32_t)G.nx, (int32_t)G.ny, (int32_t)G.nz, 0, 0});
+        else geom_host = G.parts;
+        HIPCHK(hipMemcpyAsync(ws + L.geom, geom_host.data(), sizeof(GeomInfo) * geom_host.size(),
+                              hipMemcpyHostToDevice, stream));
     }
     const size_t es = storage == RD_FP32 ? 4 : 2;
     for (int p = 0; p < 2; ++p)
@@ -619,10 +695,11 @@ rd_status rd_sim::step(double dt, int64_t n)
     return st;
 }
 
-rd_status rd_sim::balance(int s, double out[RD_NRED])
+rd_status rd_sim::balance(int s, double out[RD_NRED], int part)
 {
     if (!ws) return rd_fail(RD_ERR_STATE, "bind a workspace first");
     if (s < 0 || s >= S) return rd_fail(RD_ERR_ARG, "bad species");
+    if (part >= g->nparts()) return rd_fail(RD_ERR_ARG, "bad part");
     ReduceArgs a{};
     a.info = (const BlockInfo *)(ws + L.info);
     a.mask = (const uint64_t *)(ws + L.mask);
@@ -631,7 +708,14 @@ rd_status rd_sim::balance(int s, double out[RD_NRED])
     a.geom = (const GeomInfo *)(ws + L.geom);
     a.c = field_ptr(cur, 0);
     a.sstride = L.field_elems;
+    a.b0 = 0;
     a.nb = (int32_t)g->nb();
+    if (part >= 0) {
+        int64_t first = 0, count = 0;
+        rd_geometry_part_info(g, part, nullptr, nullptr, &first, &count);
+        a.b0 = (int32_t)first;
+        a.nb = (int32_t)count;
+    }
     a.S = S;
     a.s = s;
     a.dx = g->dx;
@@ -721,12 +805,16 @@ static rd_status set_diffusivity(rd_sim *sim, const float *dev_dense, int mode, 
 
 extern "C" rd_status rd_sim_set_diffusivity(rd_sim *sim, const float *dev_dense)
 {
+    if (sim && sim->g->nparts() > 1)
+        return rd_fail(RD_ERR_STATE, "rd_sim_set_diffusivity: one geometry per simulation only");
     return set_diffusivity(sim, dev_dense, 0, 0.0, 0.0, 0.0, 0.0);
 }
 
 extern "C" rd_status rd_sim_set_diffusivity_sdf(rd_sim *sim, const float *dev_sdf, double d_min, double d_max,
                                                 double gamma1, double gamma2)
 {
+    if (sim && sim->g->nparts() > 1)
+        return rd_fail(RD_ERR_STATE, "rd_sim_set_diffusivity_sdf: one geometry per simulation only");
     return set_diffusivity(sim, dev_sdf, 1, d_min, d_max, gamma1, gamma2);
 }
 
@@ -760,6 +848,8 @@ extern "C" rd_status rd_sim_set_sink(rd_sim *sim, int species, double rate)
 
 extern "C" rd_status rd_sim_set_sink_band(rd_sim *sim, const float *dev_phi, double band, int64_t *n_band)
 {
+    if (sim && sim->g->nparts() > 1)
+        return rd_fail(RD_ERR_STATE, "rd_sim_set_sink_band: one geometry per simulation only");
     if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
     if (!sim->ws) return rd_fail(RD_ERR_STATE, "bind a workspace first");
     if (!(sim->features & RD_WS_DIFFUSIVITY))
@@ -821,6 +911,16 @@ extern "C" rd_status rd_sim_balance(rd_sim *sim, int species, double out[9])
     return st;
 }
 
+extern "C" rd_status rd_sim_balance_part(rd_sim *sim, int species, int part, double out[9])
+{
+    if (!sim || !out) return rd_fail(RD_ERR_ARG, "NULL argument");
+    if (part < 0) return rd_fail(RD_ERR_ARG, "bad part");
+    double r[RD_NRED];
+    rd_status st = sim->balance(species, r, part);
+    for (int l = 0; l < 9; ++l) out[l] = r[l];
+    return st;
+}
+
 extern "C" rd_status rd_sim_reduce(rd_sim *sim, int species, double *mass, double *dirichlet_inflow,
                                    double *robin_uptake)
 {
@@ -835,6 +935,8 @@ extern "C" rd_status rd_sim_reduce(rd_sim *sim, int species, double *mass, doubl
 
 extern "C" rd_status rd_sim_plane_flux(rd_sim *sim, int species, int axis, int64_t i0, double *flux)
 {
+    if (sim && sim->g->nparts() > 1)
+        return rd_fail(RD_ERR_STATE, "rd_sim_plane_flux: one geometry per simulation only");
     if (!sim || !flux) return rd_fail(RD_ERR_ARG, "NULL argument");
     if (!sim->ws) return rd_fail(RD_ERR_STATE, "bind a workspace first");
     if (species < 0 || species >= sim->S) return rd_fail(RD_ERR_ARG, "bad species");

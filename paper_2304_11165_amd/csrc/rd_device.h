@@ -428,7 +428,7 @@ __device__ __forceinline__ float fp32_dither(float uc, uint32_t bits16)
 // hash, so the random bits do not depend on the block layout.
 __device__ __forceinline__ int64_t voxel_id(const GeomInfo &g, int gx, int gy, int gz)
 {
-    return ((int64_t)gz * g.ny + gy) * g.nx + gx;
+    return g.dense0 + ((int64_t)gz * g.ny + gy) * g.nx + gx;
 }
 
 // Block position of list entry b.

@@ -24,6 +24,13 @@ struct rd_geometry {
     // per-slot neighbour code [nb * B^3]: bit d (d = 0..5, order -x,+x,-y,+y,-z,+z) set
     // when that face neighbour is an active voxel, bit 6 set when the slot is active
     std::vector<uint8_t> code;
+    // Several geometries stepped together (rd_geometry_concat): one entry per part, in list
+    // order (box, first block, offset of its box in the dense array that holds the parts'
+    // boxes one after another); block_id and the block records' geometry ids refer to the
+    // part.  nx holds the dense size and ny = nz = 1 then.  Empty for one geometry.
+    std::vector<GeomInfo> parts;
+    int nparts() const { return parts.empty() ? 1 : (int)parts.size(); }
+    int64_t dense_size() const { return nx * ny * nz; }
     int64_t nb() const { return (int64_t)block_id.size(); }
 };
 

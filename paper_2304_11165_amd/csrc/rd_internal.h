@@ -48,6 +48,8 @@ struct SpeciesCoef {
 struct GeomInfo {
     int32_t nx, ny, nz;
     int32_t block0;  // first list index of this geometry
+    int64_t dense0;  // first element of this geometry's box in a dense array holding the
+                     // boxes of several geometries one after another (0 for one geometry)
 };
 
 struct StepArgs {
@@ -86,7 +88,8 @@ struct ReduceArgs {
     const GeomInfo *geom;
     const void *c;      // T*
     int64_t sstride;
-    int32_t nb;
+    int32_t b0;         // first block of the reduced range (list index)
+    int32_t nb;         // blocks in the range
     int32_t S;
     int32_t s;          // species reduced
     double dx;

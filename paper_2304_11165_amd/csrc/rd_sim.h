@@ -91,7 +91,7 @@ struct rd_sim {
     SimLayout L{};
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
-    GeomInfo geom_host{};
+    std::vector<GeomInfo> geom_host;  // one entry per part (the device copy's source)
     double *host_res = nullptr;  // pinned
     std::vector<GraphEntry> graphs;
 
@@ -114,7 +114,8 @@ struct rd_sim {
     void launch_shape(StepArgs &a) const;
     rd_status launch_steps(double dt, int64_t n);
     rd_status step(double dt, int64_t n);
-    rd_status balance(int s, double out[RD_NRED]);
+    // part < 0: every block; else the blocks of one part of a concatenated geometry
+    rd_status balance(int s, double out[RD_NRED], int part = -1);
 };
 
 int rd_launch_set_dirichlet(int storage, int B, const BlockInfo *info, const uint64_t *mask,

@@ -6,6 +6,7 @@
 // opposite face planes: D_eff = Q L / (psi A dT), so tau = psi D dT A / (Q L), with
 // psi the active volume fraction, A the box cross-section and L = (n-1) dx the
 // distance between the Dirichlet planes.  A straight channel gives tau = 1.
+#include <stdexcept>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
@@ -291,6 +292,8 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
 extern "C" rd_status rd_sim_steady_state(rd_sim *sim, int axis, double rel_tol, int64_t max_iters,
                                          double *tau, double *rel_residual, int64_t *iters)
 {
+    if (sim && sim->g->nparts() > 1)
+        return rd_fail(RD_ERR_STATE, "rd_sim_steady_state: one geometry per simulation only");
     if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
     if (!sim->ws) return rd_fail(RD_ERR_STATE, "bind a workspace first");
     if (!(sim->features & RD_WS_SOLVER))
@@ -421,9 +424,12 @@ extern "C" rd_status rd_batch_create(const rd_geometry *const *geoms, int n, rd_
         bt->mask.reserve((size_t)total * MW);
         bt->code.reserve((size_t)total * B * B * B);
         int32_t off = 0;
+        int64_t dense = 0;
         for (int i = 0; i < n; ++i) {
             const rd_geometry &G = *geoms[i];
-            bt->ginfo.push_back({(int32_t)G.nx, (int32_t)G.ny, (int32_t)G.nz, off});
+            if (G.nparts() > 1) throw std::invalid_argument("a batch member is a concatenation");
+            bt->ginfo.push_back({(int32_t)G.nx, (int32_t)G.ny, (int32_t)G.nz, off, dense});
+            dense += G.dense_size();
             for (int64_t b = 0; b < G.nb(); ++b) {
                 BlockInfo bi = G.info[b];
                 for (int f = 0; f < 6; ++f)
@@ -438,6 +444,9 @@ extern "C" rd_status rd_batch_create(const rd_geometry *const *geoms, int n, rd_
     } catch (const std::bad_alloc &) {
         delete bt;
         return rd_fail(RD_ERR_ARG, "out of host memory");
+    } catch (const std::invalid_argument &e) {
+        delete bt;
+        return rd_fail(RD_ERR_ARG, e.what());
     }
     const size_t es = storage == RD_FP32 ? 4 : 2;
     const size_t nbs = (size_t)std::max<int64_t>(total, 1);
@@ -789,6 +798,8 @@ static rd_status adjoint_impl(rd_sim *sim, const float *dev_seed, int seed_mode,
 extern "C" rd_status rd_sim_adjoint(rd_sim *sim, const float *dev_seed, int seed_mode, int64_t n_steps, double dt,
                                     int checkpoint_every, double *loss, double *dL_dD, double *dL_drate)
 {
+    if (sim && sim->g->nparts() > 1)
+        return rd_fail(RD_ERR_STATE, "rd_sim_adjoint: one geometry per simulation only");
     return adjoint_impl(sim, dev_seed, seed_mode, n_steps, dt, checkpoint_every, loss, dL_dD, dL_drate, nullptr);
 }
 
@@ -796,6 +807,8 @@ extern "C" rd_status rd_sim_adjoint_factor(rd_sim *sim, const float *dev_seed, i
                                            double dt, int checkpoint_every, double *loss, double *dL_dD,
                                            double *dL_drate, double *dev_dL_de)
 {
+    if (sim && sim->g->nparts() > 1)
+        return rd_fail(RD_ERR_STATE, "rd_sim_adjoint_factor: one geometry per simulation only");
     if (!dev_dL_de) return rd_fail(RD_ERR_ARG, "dL/de output is NULL");
     if (sim && !(sim->features & RD_WS_DIFFUSIVITY))
         return rd_fail(RD_ERR_WORKSPACE, "bind with RD_WS_ADJOINT | RD_WS_DIFFUSIVITY for dL/de");

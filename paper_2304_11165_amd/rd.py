@@ -50,6 +50,10 @@ _SIGS = {
     "rd_geometry_export_masks": ([P, P], ci),
     "rd_geometry_export_codes": ([P, P], ci),
     "rd_geometry_destroy": ([P], None),
+    "rd_geometry_concat": ([P, ci, P], ci),
+    "rd_geometry_parts": ([P], ci),
+    "rd_geometry_part_info": ([P, ci, P, P, P, P], ci),
+    "rd_sim_balance_part": ([P, ci, ci, P], ci),
     "rd_sim_create": ([P, ci, P], ci),
     "rd_sim_add_species": ([P, f64, P], ci),
     "rd_sim_add_reaction": ([P, ci, ci, f64], ci),
@@ -208,6 +212,34 @@ class Geometry:
         c = np.zeros((nb, self.block_edge ** 3), dtype=np.uint8)
         _check(_lib.rd_geometry_export_codes(self.handle, _np_ptr(c)), "rd_geometry_export_codes")
         return c
+
+    @classmethod
+    def concat(cls, parts):
+        """One geometry holding several (rd_geometry_concat): a Sim on it steps every part
+        in the same launches; its dense fields hold the parts' boxes one after another
+        (`shape` is (1, 1, total voxels); `parts()` gives each part's box and offset)."""
+        parts = list(parts)
+        arr = (ctypes.c_void_p * len(parts))(*[p.handle for p in parts])
+        h = ctypes.c_void_p()
+        _check(_lib.rd_geometry_concat(arr, len(parts), ctypes.byref(h)), "rd_geometry_concat")
+        g = cls.__new__(cls)
+        g.handle = h.value
+        g.dx = parts[0].dx
+        g.block_edge = parts[0].block_edge
+        g.shape = (1, 1, int(sum(int(np.prod(p.shape)) for p in parts)))
+        return g
+
+    def parts(self):
+        """[{shape, dense_offset, first_block, n_blocks}] per part (one for a plain geometry)."""
+        out = []
+        for i in range(_lib.rd_geometry_parts(self.handle)):
+            shp = np.zeros(3, dtype=np.int64)
+            off, b0, nb = i64(), i64(), i64()
+            _check(_lib.rd_geometry_part_info(self.handle, i, _np_ptr(shp), ctypes.byref(off), ctypes.byref(b0),
+                                              ctypes.byref(nb)), "rd_geometry_part_info")
+            out.append({"shape": tuple(int(v) for v in shp), "dense_offset": off.value,
+                        "first_block": b0.value, "n_blocks": nb.value})
+        return out
 
     def __del__(self, _destroy=_lib.rd_geometry_destroy):
         h = getattr(self, "handle", None)
@@ -418,10 +450,23 @@ class Sim:
                                   ctypes.byref(r)), "rd_sim_reduce")
         return m.value, f.value, r.value
 
-    def balance(self, species):
+    def balance(self, species, part=None):
+        """FP64 balance terms of `species`; `part`: only that part of a concatenated
+        geometry."""
         out = np.zeros(9)
-        _check(_lib.rd_sim_balance(self.handle, int(species), _np_ptr(out)), "rd_sim_balance")
+        if part is None:
+            _check(_lib.rd_sim_balance(self.handle, int(species), _np_ptr(out)), "rd_sim_balance")
+        else:
+            _check(_lib.rd_sim_balance_part(self.handle, int(species), int(part), _np_ptr(out)),
+                   "rd_sim_balance_part")
         return {"mass": out[0], "inflow": out[1:7].copy(), "uptake": out[7], "react": out[8]}
+
+    def get_part_field(self, species, part):
+        """Species `species` of part `part` of a concatenated geometry, (nz, ny, nx)."""
+        info = self.geometry.parts()[part]
+        n = int(np.prod(info["shape"]))
+        flat = self.get_field(species).reshape(-1)
+        return flat[info["dense_offset"]:info["dense_offset"] + n].reshape(info["shape"])
 
     def plane_flux(self, species, axis, i0):
         """FP64 diffusive flux of `species` through the plane between i0 and i0 + 1 along

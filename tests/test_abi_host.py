@@ -251,3 +251,49 @@ def test_compact_layout_validation_without_gpu(rd):
     with pytest.raises(rd.RDError) as e:
         s4.set_layout("compact")
     assert e.value.name == "RD_ERR_SHAPE"
+
+
+def test_concat_geometry_structure(rd):
+    """rd_geometry_concat: the parts' block lists one after another, neighbour indices
+    shifted by the part's first block, masks and codes unchanged, boxes one after another
+    in the dense array; mixed block edges, nested concatenations and batches of
+    concatenations are refused."""
+    rng = np.random.default_rng(4)
+    imgs = [(rng.random(s) < p).astype(np.uint8) for s, p in
+            (((20, 17, 23), 0.6), ((9, 30, 11), 0.5), ((5, 5, 5), 0.0), ((13, 8, 21), 0.7))]
+    for B in (4, 8):
+        gs = [rd.Geometry(img, None, 1.0, B) for img in imgs]
+        cat = rd.Geometry.concat(gs)
+        parts = cat.parts()
+        ids, nbr = cat.export_index()
+        masks, codes = cat.export_masks(), cat.export_codes()
+        off = dense = 0
+        for g, img, p in zip(gs, imgs, parts):
+            i1, n1 = g.export_index()
+            nb = len(i1)
+            assert p == {"shape": img.shape, "dense_offset": dense, "first_block": off, "n_blocks": nb}
+            assert np.array_equal(ids[off:off + nb], i1)
+            assert np.array_equal(nbr[off:off + nb], np.where(n1 >= 0, n1 + off, -1))
+            assert np.array_equal(masks[off:off + nb], g.export_masks())
+            assert np.array_equal(codes[off:off + nb], g.export_codes())
+            off += nb
+            dense += img.size
+        st = cat.stats()
+        assert st["n_blocks"] == off and cat.shape == (1, 1, dense)
+        assert st["n_active"] == sum(int(img.sum()) for img in imgs)
+        # a plain geometry is one part
+        assert gs[0].parts() == [{"shape": imgs[0].shape, "dense_offset": 0, "first_block": 0,
+                                  "n_blocks": gs[0].stats()["n_blocks"]}]
+        with pytest.raises(rd.RDError) as e:
+            rd.Geometry.concat([cat, gs[0]])
+        assert e.value.name == "RD_ERR_ARG"
+        with pytest.raises(rd.RDError) as e:
+            rd.Batch([cat])
+        assert e.value.name == "RD_ERR_ARG"
+    g4, g8 = rd.Geometry(imgs[0], None, 1.0, 4), rd.Geometry(imgs[0], None, 1.0, 8)
+    with pytest.raises(rd.RDError) as e:
+        rd.Geometry.concat([g4, g8])
+    assert e.value.name == "RD_ERR_SHAPE"
+    with pytest.raises(rd.RDError) as e:
+        rd._check(rd._lib.rd_geometry_part_info(g8.handle, 1, None, None, None, None), "rd_geometry_part_info")
+    assert e.value.name == "RD_ERR_ARG"
