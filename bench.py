@@ -47,6 +47,8 @@ def parse():
     p.add_argument("--form-steps", type=int, default=2000)
     p.add_argument("--batch", type=int, default=64, help="geometries in the batched form (0: skip)")
     p.add_argument("--batch-max-edge", type=int, default=256)
+    p.add_argument("--batch-steps", type=int, default=200,
+                   help="time steps of the batched stepping form (0: skip)")
     p.add_argument("--steady-axes", type=int, default=1,
                    help="ceramic-foam steady state: tortuosity along the first K axes (0: skip)")
     p.add_argument("--steady-size", type=int, default=1024, help="edge of the foam volume")
@@ -72,7 +74,7 @@ def parse():
     p.add_argument("--profile-storage", default="fp32", choices=["fp32", "bf16", "fp16"],
                    help="storage type timed by --profile")
     p.add_argument("--copy-calibration", action="store_true")
-    p.add_argument("--profile-form", default="", choices=["", "steady", "batch", "adjoint"],
+    p.add_argument("--profile-form", default="", choices=["", "steady", "batch", "batch_steps", "adjoint"],
                    help="run only this form (for rocprofv3) and print its record")
     p.add_argument("--kernel", default="auto", choices=["auto", "block", "column", "column_xch",
                                                         "persistent", "column_lanes"],
@@ -239,6 +241,60 @@ def batched_form(torch, rd, W, count, max_edge, stream):
         "rel_residual_max": float(max(rel)),
         "iterations": [int(x) for x in it],
         "note": "wall time of the tortuosity call: cluster labelling, initial guess and CG",
+    }
+
+
+def batched_step_form(torch, rd, W, count, max_edge, steps, stream):
+    """Time stepping of `count` sphere packings (the batched form's volumes) with the soil
+    recipe (two species, A -> B, Robin uptake of B, c_A = 1 on each packing's x = 0 face,
+    FP32 with stochastic rounding): one concatenated geometry stepped in shared launches
+    against each packing stepped on its own with the same launch setting."""
+    w = W.workload("soil512")
+    t0 = time.perf_counter()
+    geoms_np = W.batch_geometries(count, seed=4, nmin=64, nmax=max_edge)
+    gs = [rd.Geometry(img, None, w.dx, 8) for img, _ in geoms_np]
+    cat = rd.Geometry.concat(gs)
+    n_active = cat.stats()["n_active"]
+    log(f"batched stepping: {count} packings, {n_active} active voxels, indexed in {time.perf_counter() - t0:.1f}s")
+    warm = 20
+    with torch.cuda.stream(stream):
+        sim = build_sim(rd, cat, w, "fp32", 16)
+        sim.bind(stream=stream)
+        sim.autotune(w.dt, 50)
+        launch = sim.get_launch()
+        secs_b, _, timing_b = time_steps(torch, sim, stream, w.dt, warm, steps)
+        # each packing alone, same launch setting (kernel, order, steps per graph)
+        secs_s = 0.0
+        equal = True
+        for i, g in enumerate(gs):
+            s1 = build_sim(rd, g, w, "fp32", launch["graph_steps"])
+            s1.bind(stream=stream)
+            s1.set_launch(launch["graph_steps"], bool(launch["use_graph"]), bool(launch["xcd_map"]))
+            s1.set_kernel(launch["kernel"], launch["wg_per_cu"])
+            secs, _, _ = time_steps(torch, s1, stream, w.dt, warm, steps)
+            secs_s += secs
+            if i in (0, count // 2, count - 1):  # the same steps give the same bits
+                for sp in range(len(w.species_D)):
+                    equal = equal and bool(torch.equal(sim.get_part_field(sp, i), s1.get_field(sp)))
+            del s1
+        torch.cuda.synchronize()
+        del sim
+    per_b, per_s = secs_b / steps, secs_s / steps
+    log(f"batched stepping: {per_b * 1e3:.3f} ms per step for all {count} in shared launches, "
+        f"{per_s * 1e3:.3f} ms one by one ({per_s / per_b:.2f}x); parts == single runs: {equal}")
+    return {
+        "geometries": count,
+        "n_active_voxels": n_active,
+        "steps": steps,
+        "launch": launch,
+        "ms_per_step_batched": per_b * 1e3,
+        "ms_per_step_one_by_one": per_s * 1e3,
+        "updates_per_s_batched": n_active * steps / secs_b,
+        "updates_per_s_one_by_one": n_active * steps / secs_s,
+        "speedup": per_s / per_b,
+        "timing_batched": timing_b,
+        "parts_equal_single_runs": equal,
+        "note": "HIP events around the timed steps of each run (warm-up and binding excluded)",
     }
 
 
@@ -562,6 +618,8 @@ def main():
                               a.steady_max_iters)
         elif a.profile_form == "batch":
             rec = batched_form(torch, rd, W, a.batch, a.batch_max_edge, stream)
+        elif a.profile_form == "batch_steps":
+            rec = batched_step_form(torch, rd, W, a.batch, a.batch_max_edge, a.batch_steps, stream)
         else:
             rec = adjoint_form(torch, rd, W, stream)
         print(json.dumps({"profile_form": a.profile_form, "record": rec}), flush=True)
@@ -717,6 +775,9 @@ def main():
     }
     if a.batch > 0 and not a.profile:
         out["forms"]["batched"] = batched_form(torch, rd, W, a.batch, a.batch_max_edge, stream)
+        if a.batch_steps > 0:
+            out["forms"]["batched_steps"] = batched_step_form(torch, rd, W, a.batch, a.batch_max_edge,
+                                                              a.batch_steps, stream)
         log(f"batched: {out['forms']['batched']['active_voxel_cg_iterations_per_s']:.3e} "
             f"voxel-iterations/s")
 
