@@ -49,6 +49,8 @@ def parse():
     p.add_argument("--batch-max-edge", type=int, default=256)
     p.add_argument("--batch-steps", type=int, default=200,
                    help="time steps of the batched stepping form (0: skip)")
+    p.add_argument("--fused-steps", type=int, default=16,
+                   help="steps per cooperative launch in the fused form (0: skip the form)")
     p.add_argument("--steady-axes", type=int, default=1,
                    help="ceramic-foam steady state: tortuosity along the first K axes (0: skip)")
     p.add_argument("--steady-size", type=int, default=1024, help="edge of the foam volume")
@@ -74,7 +76,8 @@ def parse():
     p.add_argument("--profile-storage", default="fp32", choices=["fp32", "bf16", "fp16"],
                    help="storage type timed by --profile")
     p.add_argument("--copy-calibration", action="store_true")
-    p.add_argument("--profile-form", default="", choices=["", "steady", "batch", "batch_steps", "adjoint"],
+    p.add_argument("--profile-form", default="",
+                   choices=["", "steady", "batch", "batch_steps", "fused", "adjoint"],
                    help="run only this form (for rocprofv3) and print its record")
     p.add_argument("--kernel", default="auto", choices=["auto", "block", "column", "column_xch",
                                                         "persistent", "column_lanes"],
@@ -296,6 +299,48 @@ def batched_step_form(torch, rd, W, count, max_edge, steps, stream):
         "parts_equal_single_runs": equal,
         "note": "HIP events around the timed steps of each run (warm-up and binding excluded)",
     }
+
+
+def fused_form(torch, rd, W, stream, fused=16, size=512):
+    """Several steps per cooperative launch against one launch per step (captured graphs),
+    same kernel (column with the x-face exchange, XCD-aware order), on the 64^3 sphere
+    packing (a small volume: 512 blocks) and the soil volume; FP32 with stochastic
+    rounding.  Both runs take the same number of steps and must give the same bits."""
+    out = {}
+    for name in ("spheres64", "soil512"):
+        w = W.workload(name)
+        if name == "soil512":
+            img = W.gaussian_random_field_volume(size, 12.0, 0.3, seed=w.seed)
+            steps, warm = 2000, 64
+        else:
+            img, _ = W.workload_geometry(name)
+            steps, warm = w.steps, 64
+        g = rd.Geometry(img, None, w.dx, 8)
+        n_active = g.stats()["n_active"]
+        rec = {"n_active_voxels": n_active, "n_blocks": g.stats()["n_blocks"], "steps": steps,
+               "kernel": "column_xch", "fused_steps": fused}
+        fields = {}
+        with torch.cuda.stream(stream):
+            for t in (1, fused):
+                sim = build_sim(rd, g, w, "fp32", fused)
+                sim.set_kernel("column_xch", 8)
+                sim.set_fused_steps(t)
+                sim.bind(stream=stream)
+                secs, _, timing = time_steps(torch, sim, stream, w.dt, warm, steps)
+                key = "one_launch_per_step" if t == 1 else "fused"
+                rec[key] = {"ms_per_step": secs / steps * 1e3, "updates_per_s": n_active * steps / secs,
+                            "alg_GBps": 2 * 4 * len(w.species_D) * n_active * steps / secs / 1e9,
+                            "timing": timing}
+                fields[t] = [sim.get_field(sp).clone() for sp in range(len(w.species_D))]
+                del sim
+            torch.cuda.synchronize()
+        rec["bitwise_equal"] = all(bool(torch.equal(a, b)) for a, b in zip(fields[1], fields[fused]))
+        rec["speedup"] = rec["one_launch_per_step"]["ms_per_step"] / rec["fused"]["ms_per_step"]
+        log(f"fused {name}: {rec['one_launch_per_step']['ms_per_step']:.4f} ms/step with one launch per step "
+            f"(graphs), {rec['fused']['ms_per_step']:.4f} with {fused} steps per launch "
+            f"({rec['speedup']:.2f}x); same bits: {rec['bitwise_equal']}")
+        out[name] = rec
+    return out
 
 
 def steady_form(torch, rd, W, size, axes, forms, tol, stream, max_iters=200000):
@@ -620,6 +665,8 @@ def main():
             rec = batched_form(torch, rd, W, a.batch, a.batch_max_edge, stream)
         elif a.profile_form == "batch_steps":
             rec = batched_step_form(torch, rd, W, a.batch, a.batch_max_edge, a.batch_steps, stream)
+        elif a.profile_form == "fused":
+            rec = fused_form(torch, rd, W, stream, a.fused_steps, a.size)
         else:
             rec = adjoint_form(torch, rd, W, stream)
         print(json.dumps({"profile_form": a.profile_form, "record": rec}), flush=True)
@@ -778,6 +825,8 @@ def main():
         if a.batch_steps > 0:
             out["forms"]["batched_steps"] = batched_step_form(torch, rd, W, a.batch, a.batch_max_edge,
                                                               a.batch_steps, stream)
+    if a.fused_steps > 1 and not a.profile:
+        out["forms"]["fused"] = fused_form(torch, rd, W, stream, a.fused_steps, a.size)
         log(f"batched: {out['forms']['batched']['active_voxel_cg_iterations_per_s']:.3e} "
             f"voxel-iterations/s")
 

@@ -445,6 +445,16 @@ rd_status rd_sim_autotune_cached(rd_sim *sim, double dt, int64_t trial_steps, co
  * *best_index, and ms_per_step[n] (may be NULL). */
 rd_status rd_autotune_pick(rd_sim *const *sims, int n, double dt, int64_t trial_steps,
                            int *best_index, double *ms_per_step);
+/* Steps per launch (1..256, default 1): with more than one, rd_sim_step issues the steps
+ * in cooperative launches of that many steps each, a grid barrier between the steps
+ * (the explicit steps of eq. reaction_diffusion, section "Methods", unchanged and in
+ * order; what goes is the launch per step, which dominates small volumes).  The fields
+ * are those of one launch per step bit for bit.  Applies to 8^3
+ * blocks in the block layout with a column kernel (rd_sim_set_kernel 2 or 3) and constant
+ * D; other settings keep one launch per step.  Fused launches are not captured in graphs.
+ * RD_ERR_ARG outside 1..256, RD_ERR_STATE for 4^3 blocks or the compact layout. */
+rd_status rd_sim_set_fused_steps(rd_sim *sim, int steps);
+rd_status rd_sim_get_fused_steps(const rd_sim *sim, int *steps);
 /* Current launch configuration (any output may be NULL). */
 rd_status rd_sim_get_launch(const rd_sim *sim, int *graph_steps, int *use_graph, int *xcd_map,
                             int *kernel, int *wg_per_cu);

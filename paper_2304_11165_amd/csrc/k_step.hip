@@ -18,6 +18,8 @@
 //     the persistent kernel stores 0 into inactive slots.  Dirichlet voxels are
 //     copied through.
 // The stencil is HBM-bound (about 2 FLOP per byte), so there is no MFMA here.
+#include <hip/hip_cooperative_groups.h>
+
 #include "rd_device.h"
 
 namespace {
@@ -395,13 +397,13 @@ __device__ __forceinline__ int pix(int x, int y) { return (y + 1) * 10 + (x + 1)
 // layout, so both give the same bits; stores cover the active voxels only.
 // DTH: stochastic rounding (FP32: the dither added to each increment; 16-bit: the
 // rounding of the stores).
+// One workgroup's work: the four blocks of group grp (list entries 4 grp .. 4 grp + 3).
 template <typename T, int S, bool XCH, bool CMP, bool DTH>
-__global__ __launch_bounds__(256) void k_step8z(StepArgs a)
+__device__ __forceinline__ void step8z_group(const StepArgs &a, int grp)
 {
     __shared__ float tile[4][S][100];
     __shared__ float xch[4][2][S][64];  // x = 0 / x = 7 planes of each wave's block, [z * 8 + y]
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int grp = map_group(blockIdx.x, a.xcd_chunk);
     const int b = __builtin_amdgcn_readfirstlane(grp * 4 + wv);
     if (b >= a.nb) {  // past the end of the list (with XCH: after the one barrier)
         if (XCH) __syncthreads();
@@ -584,6 +586,44 @@ __global__ __launch_bounds__(256) void k_step8z(StepArgs a)
 #pragma unroll
             for (int s = 0; s < S; ++s) store_val_ct<T, CMP, DTH>(cout, s, s * a.sstride + oi[z], h, res[s]);
         }
+    }
+}
+
+template <typename T, int S, bool XCH, bool CMP, bool DTH>
+__global__ __launch_bounds__(256) void k_step8z(StepArgs a)
+{
+    step8z_group<T, S, XCH, CMP, DTH>(a, map_group(blockIdx.x, a.xcd_chunk));
+}
+
+// Several steps in one launch: a cooperative grid, every workgroup resident at once,
+// walks the block groups once per step and meets at a grid barrier between steps (a step
+// reads what the previous one wrote, possibly on another XCD; the barrier orders those
+// writes before the reads and makes them visible).  Each step is k_step8z's per-group
+// work with that step's buffers and rounding key, so the fields equal those of one launch
+// per step bit for bit.  The memory traffic per step is the same; what goes is the launch
+// and its ramp-up and drain per step, which dominate small volumes.  XCD-aware: workgroup
+// w runs on XCD w mod 8, and XCD x walks the x-th eighth of the groups.  The grid is a
+// multiple of 8 workgroups.
+template <typename T, int S, bool XCH, bool DTH>
+__global__ __launch_bounds__(256) void k_step8z_fused(StepArgs a, int nsteps)
+{
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    const int ngroups = (a.nb + 3) / 4;
+    const int per_xcd = (ngroups + 7) / 8;
+    const int xcd = (int)blockIdx.x & 7, w = (int)blockIdx.x >> 3, nw = (int)gridDim.x >> 3;
+    const int g0 = xcd * per_xcd, g1 = min(g0 + per_xcd, ngroups);
+    for (int k = 0; k < nsteps; ++k) {
+        StepArgs ak = a;
+        if (k & 1) {  // ping-pong
+            ak.cin = a.cout;
+            ak.cout = const_cast<void *>(a.cin);
+        }
+        ak.ctr_off = a.ctr_off + (uint32_t)k;
+        for (int grp = g0 + w; grp < g1; grp += nw) {
+            step8z_group<T, S, XCH, false, DTH>(ak, grp);
+            if (XCH) __syncthreads();  // the x-face hand-over arrays serve the next group
+        }
+        if (k + 1 < nsteps) grid.sync();
     }
 }
 
@@ -1249,6 +1289,53 @@ int rd_launch_step(int storage, int B, const StepArgs &a, void *stream)
 {
     if (a.nb <= 0) return 0;
     RD_DISPATCH(storage, B, launch_step_t, a, (hipStream_t)stream);
+}
+
+namespace {
+template <typename T, int S, bool XCH, bool DTH>
+int launch_fused_k(const StepArgs &a, int nsteps, int n_cu, hipStream_t st)
+{
+    const void *fn = (const void *)k_step8z_fused<T, S, XCH, DTH>;
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0);
+    if (e != hipSuccess) return (int)e;
+    const int ngroups = (a.nb + 3) / 4;
+    int grid = per_cu * n_cu;                         // every workgroup resident
+    grid = std::min(grid, ((ngroups + 7) / 8) * 8);   // no more than the groups need
+    grid = (grid / 8) * 8;
+    if (grid < 8) return (int)hipErrorCooperativeLaunchTooLarge;
+    StepArgs args = a;
+    int ns = nsteps;
+    void *params[] = {(void *)&args, (void *)&ns};
+    return (int)hipLaunchCooperativeKernel(fn, dim3((unsigned)grid), dim3(256), params, 0, st);
+}
+template <typename T, int S>
+int launch_fused_s(const StepArgs &a, int nsteps, int n_cu, hipStream_t st)
+{
+    const bool xch = a.kernel == 3, sr = a.sround != 0;
+    if (xch) return sr ? launch_fused_k<T, S, true, true>(a, nsteps, n_cu, st)
+                       : launch_fused_k<T, S, true, false>(a, nsteps, n_cu, st);
+    return sr ? launch_fused_k<T, S, false, true>(a, nsteps, n_cu, st)
+              : launch_fused_k<T, S, false, false>(a, nsteps, n_cu, st);
+}
+template <typename T>
+int launch_fused_t(const StepArgs &a, int nsteps, int n_cu, hipStream_t st)
+{
+    switch (a.S) {
+    case 1: return launch_fused_s<T, 1>(a, nsteps, n_cu, st);
+    case 2: return launch_fused_s<T, 2>(a, nsteps, n_cu, st);
+    case 3: return launch_fused_s<T, 3>(a, nsteps, n_cu, st);
+    default: return launch_fused_s<T, 4>(a, nsteps, n_cu, st);
+    }
+}
+}  // namespace
+
+int rd_launch_step_fused(int storage, const StepArgs &a, int nsteps, int n_cu, void *stream)
+{
+    if (a.nb <= 0 || nsteps <= 0) return 0;
+    if (storage == 0) return launch_fused_t<float>(a, nsteps, n_cu, (hipStream_t)stream);
+    if (storage == 1) return launch_fused_t<bf16_t>(a, nsteps, n_cu, (hipStream_t)stream);
+    return launch_fused_t<_Float16>(a, nsteps, n_cu, (hipStream_t)stream);
 }
 
 int rd_reduce_rows(int, int nb) { return (nb + 3) / 4; }

@@ -325,6 +325,24 @@ extern "C" rd_status rd_sim_set_kernel(rd_sim *sim, int kernel, int wg_per_cu)
     return RD_OK;
 }
 
+extern "C" rd_status rd_sim_set_fused_steps(rd_sim *sim, int steps)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    if (steps < 1 || steps > 256) return rd_fail(RD_ERR_ARG, "steps per launch in 1..256");
+    if (steps > 1 && (sim->g->B != 8 || sim->compact))
+        return rd_fail(RD_ERR_STATE, "fused steps need 8^3 blocks and the block layout");
+    sim->fused_steps = steps;
+    sim->invalidate_graphs();
+    return RD_OK;
+}
+
+extern "C" rd_status rd_sim_get_fused_steps(const rd_sim *sim, int *steps)
+{
+    if (!sim || !steps) return rd_fail(RD_ERR_ARG, "NULL argument");
+    *steps = sim->fused_steps;
+    return RD_OK;
+}
+
 extern "C" rd_status rd_sim_set_rounding(rd_sim *sim, int stochastic, uint64_t seed)
 {
     if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
@@ -593,12 +611,32 @@ void rd_sim::launch_shape(StepArgs &a) const
     }
 }
 
+bool rd_sim::fused_ok() const
+{
+    return g->B == 8 && !compact && (kernel == 2 || kernel == 3) && !diff_path();
+}
+
 rd_status rd_sim::launch_steps(double dt, int64_t n)
 {
     // stochastic rounding: at the store for 16-bit storage; for FP32 storage a dither of
     // the increment, in the constant-D kernels only (the kernels with a diffusivity
     // factor round FP32 to nearest)
     const bool sr = sround && (storage != RD_FP32 || !diff_path());
+    if (fused_steps > 1 && fused_ok()) {
+        for (int64_t i = 0; i < n; i += fused_steps) {
+            const int m = (int)std::min<int64_t>(fused_steps, n - i);
+            StepArgs a = step_args(dt, cur);
+            launch_shape(a);
+            a.sround = sr ? 1 : 0;
+            a.seed = seed;
+            a.ctr = step_counter();
+            a.ctr_off = (uint32_t)i;
+            LAUNCHCHK(rd_launch_step_fused(storage, a, m, n_cu, stream));
+            if (m & 1) cur = 1 - cur;
+        }
+        if (sr && n > 0) LAUNCHCHK(rd_launch_add_u32(step_counter(), (uint32_t)n, stream));
+        return RD_OK;
+    }
     for (int64_t i = 0; i < n; ++i) {
         StepArgs a = step_args(dt, cur);
         launch_shape(a);
@@ -652,9 +690,9 @@ rd_status rd_sim::step(double dt, int64_t n)
     }
     int64_t left = n;
     // a graph holds an even number of steps so the buffer parity it was captured for
-    // is the same at every replay
+    // is the same at every replay (fused steps: cooperative launches, not captured)
     const int gs = graph_steps + (graph_steps & 1);
-    if (use_graph && left >= gs) {
+    if (use_graph && left >= gs && !(fused_steps > 1 && fused_ok())) {
         GraphEntry *ge = nullptr;
         for (auto &e : graphs)
             if (e.dt == dt && e.parity == cur && e.steps == gs) ge = &e;

@@ -126,6 +126,10 @@ int rd_launch_gather(int storage, int B, const BlockInfo *info, const uint64_t *
                      const uint32_t *cbase, const GeomInfo *geom, int nb, const void *field, float *dense,
                      int64_t ndense, void *stream);
 int rd_launch_fill_u32(void *ptr, uint32_t value, int64_t n_words, void *stream);
+// B = 8, block layout, column kernels (a.kernel 2 or 3): nsteps steps in one cooperative
+// launch (grid barrier between steps); the buffers swap after each step, as in nsteps
+// single-step launches; a.ctr_off is the first step's offset.  n_cu: compute units.
+int rd_launch_step_fused(int storage, const StepArgs &a, int nsteps, int n_cu, void *stream);
 // B = 8: the active-neighbour count words (StepArgs::ncnt) of nb blocks
 int rd_launch_count_words8(const uint64_t *mask, uint32_t *ncnt, int nb, void *stream);
 int rd_launch_add_u32(uint32_t *ptr, uint32_t add, void *stream);

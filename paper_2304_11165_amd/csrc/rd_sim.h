@@ -73,6 +73,9 @@ struct rd_sim {
     int n_cu = 256;       // compute units of the bound device
     bool sround = false;  // stochastic rounding on store (BF16 / FP16 storage)
     bool compact = false; // fields hold only the active voxels (B = 8; rd_sim_set_layout)
+    int fused_steps = 1;  // steps per cooperative launch (rd_sim_set_fused_steps; 1: off)
+    // the fused launch applies: B = 8, block layout, a column kernel, constant D
+    bool fused_ok() const;
     std::vector<uint32_t> cbase_host;  // compact index, built at bind
     std::vector<uint8_t> ccode_host;
     uint32_t seed = 0;

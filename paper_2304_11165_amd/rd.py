@@ -54,6 +54,8 @@ _SIGS = {
     "rd_geometry_parts": ([P], ci),
     "rd_geometry_part_info": ([P, ci, P, P, P, P], ci),
     "rd_sim_balance_part": ([P, ci, ci, P], ci),
+    "rd_sim_set_fused_steps": ([P, ci], ci),
+    "rd_sim_get_fused_steps": ([P, P], ci),
     "rd_sim_create": ([P, ci, P], ci),
     "rd_sim_add_species": ([P, f64, P], ci),
     "rd_sim_add_reaction": ([P, ci, ci, f64], ci),
@@ -435,6 +437,17 @@ class Sim:
         return out
 
     # time stepping --------------------------------------------------------------
+    def set_fused_steps(self, steps):
+        """Steps per cooperative launch (1: one launch per step); 8^3 blocks, block layout,
+        column kernels, constant D (others keep one launch per step)."""
+        _check(_lib.rd_sim_set_fused_steps(self.handle, int(steps)), "rd_sim_set_fused_steps")
+        return self
+
+    def get_fused_steps(self):
+        n = ctypes.c_int()
+        _check(_lib.rd_sim_get_fused_steps(self.handle, ctypes.byref(n)), "rd_sim_get_fused_steps")
+        return n.value
+
     def step(self, dt, n_steps=1):
         _check(_lib.rd_sim_step(self.handle, float(dt), int(n_steps)), "rd_sim_step")
         return self

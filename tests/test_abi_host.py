@@ -297,3 +297,27 @@ def test_concat_geometry_structure(rd):
     with pytest.raises(rd.RDError) as e:
         rd._check(rd._lib.rd_geometry_part_info(g8.handle, 1, None, None, None, None), "rd_geometry_part_info")
     assert e.value.name == "RD_ERR_ARG"
+
+
+def test_fused_steps_validation_without_gpu(rd):
+    img, _ = W.boolean_spheres(40, 0.4, 2.0, 5.0, seed=3)
+    s8 = rd.Sim(rd.Geometry(img, None, 1.0, 8), "fp32")
+    s8.add_species(1.0)
+    assert s8.get_fused_steps() == 1
+    s8.set_fused_steps(16)
+    assert s8.get_fused_steps() == 16
+    for bad in (0, 257):
+        with pytest.raises(rd.RDError) as e:
+            s8.set_fused_steps(bad)
+        assert e.value.name == "RD_ERR_ARG"
+    s4 = rd.Sim(rd.Geometry(img, None, 1.0, 4), "fp32")
+    s4.add_species(1.0)
+    with pytest.raises(rd.RDError) as e:
+        s4.set_fused_steps(4)
+    assert e.value.name == "RD_ERR_STATE"
+    sc = rd.Sim(rd.Geometry(img, None, 1.0, 8), "fp32")
+    sc.add_species(1.0)
+    sc.set_layout("compact")
+    with pytest.raises(rd.RDError) as e:
+        sc.set_fused_steps(4)
+    assert e.value.name == "RD_ERR_STATE"
