@@ -474,13 +474,25 @@ __device__ __forceinline__ void step8z_group(const StepArgs &a, int grp)
         for (int s = 0; s < S; ++s) rh[f][s] = (R)0;
         int64_t hb;
         if constexpr (CMP) {
+            // every position follows from b alone (no load waits for the neighbour
+            // table): the block's halo record holds the y / z neighbours' plane bounds,
+            // and the x neighbours are list entries b - 1 and b + 1
+            const uint32_t *hr = a.hrec + (int64_t)b * 32;
             if (f == 4) {  // plane 7 of the -z neighbour: its last popc(Wf[4]) voxels
-                hb = (int64_t)a.cbase[nn + 1] - __popcll(Wf[4]) + lanes_below(Wf[4]);
+                hb = (int64_t)hr[16] - __popcll(Wf[4]) + lanes_below(Wf[4]);
             } else if (f == 5) {  // plane 0 of the +z neighbour
-                hb = (int64_t)a.cbase[nn] + lanes_below(Wf[5]);
-            } else {  // plane v = ly of a side neighbour, slot ns
+                hb = (int64_t)hr[17] + lanes_below(Wf[5]);
+            } else if (f < 2) {  // column x = 7 / x = 0 of plane v = ly, slot ns
                 hb = 0;
-                if (lane_bit(need)) hb = slot_index8(a.cbase, a.mask, nn, ns);
+                if (lane_bit(need)) hb = slot_index8(a.cbase, a.mask, f == 0 ? b - 1 : b + 1, ns);
+            } else {  // row y = 7 / y = 0 of plane v = ly at x = u = lx: the end / start of
+                      // that plane less / plus the row's active voxels at or after / before u
+                const uint32_t row = (uint32_t)(Wf[f] >> (8 * ly)) & 0xffu;
+                hb = 0;
+                if (lane_bit(need)) {
+                    if (f == 2) hb = (int64_t)hr[ly] - __popc(row >> lx);
+                    else hb = (int64_t)hr[8 + ly] + __popc(row & ((1u << lx) - 1u));
+                }
             }
         } else {
             hb = (int64_t)nn * 512 + ns;
@@ -1448,6 +1460,36 @@ int rd_launch_set_dirichlet(int storage, int B, const BlockInfo *info, const uin
 int rd_launch_add_u32(uint32_t *ptr, uint32_t add, void *stream)
 {
     hipLaunchKernelGGL(k_add_u32, dim3(1), dim3(64), 0, (hipStream_t)stream, ptr, add);
+    return (int)hipGetLastError();
+}
+
+// Compact layout: the halo record of each block, 32 words: [v] one past the last voxel of
+// plane v of the -y neighbour, [8 + v] the first voxel of plane v of the +y neighbour,
+// [16] one past the last voxel of the -z neighbour, [17] the first voxel of the +z
+// neighbour (0 where there is no neighbour; the rest 0).  One thread per block.
+__global__ void k_halo_rec8(const BlockInfo *__restrict__ info, const uint64_t *__restrict__ mask,
+                            const uint32_t *__restrict__ cbase, uint32_t *__restrict__ hrec, int nb)
+{
+    const int b = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (b >= nb) return;
+    const BlockInfo bi = info[b];
+    const int n2 = bi.nbr[2], n3 = bi.nbr[3], n4 = bi.nbr[4], n5 = bi.nbr[5];
+    uint32_t *out = hrec + (int64_t)b * 32;
+    for (int v = 0; v < 8; ++v) {
+        out[v] = n2 < 0 ? 0u : (v < 7 ? cbase[n2] + plane_prefix(mask + (int64_t)n2 * 16, v + 1) : cbase[n2 + 1]);
+        out[8 + v] = n3 < 0 ? 0u : cbase[n3] + plane_prefix(mask + (int64_t)n3 * 16, v);
+    }
+    out[16] = n4 < 0 ? 0u : cbase[n4 + 1];
+    out[17] = n5 < 0 ? 0u : cbase[n5];
+    for (int i = 18; i < 32; ++i) out[i] = 0u;
+}
+
+int rd_launch_halo_rec8(const BlockInfo *info, const uint64_t *mask, const uint32_t *cbase, uint32_t *hrec,
+                        int nb, void *stream)
+{
+    if (nb <= 0) return 0;
+    hipLaunchKernelGGL(k_halo_rec8, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, (hipStream_t)stream, info,
+                       mask, cbase, hrec, nb);
     return (int)hipGetLastError();
 }
 

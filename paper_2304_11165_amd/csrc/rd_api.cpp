@@ -414,6 +414,7 @@ SimLayout sim_layout(const rd_sim &s, uint32_t features, int64_t cp_slots)
         // only the active voxels: codes and each species' values in list and slot order
         L.code = off; off = align256(off + (size_t)std::max<int64_t>(g.n_active, 1));
         L.cbase = off; off = align256(off + 4 * (size_t)(nb + 1));
+        L.hrec = off; off = align256(off + 4 * 32 * (size_t)std::max<int64_t>(nb, 1));
         L.field_elems = std::max<int64_t>((g.n_active + 63) / 64 * 64, 64);
     } else {
         L.code = off; off = align256(off + (size_t)std::max<int64_t>(nb, 1) * NS);
@@ -491,6 +492,9 @@ rd_status rd_sim::upload(bool index)
                                   stream));
             HIPCHK(hipMemcpyAsync(ws + L.cbase, cbase_host.data(), 4 * cbase_host.size(), hipMemcpyHostToDevice,
                                   stream));
+            LAUNCHCHK(rd_launch_halo_rec8((const BlockInfo *)(ws + L.info), (const uint64_t *)(ws + L.mask),
+                                          (const uint32_t *)(ws + L.cbase), (uint32_t *)(ws + L.hrec), (int)nb,
+                                          stream));
         } else {
             HIPCHK(hipMemcpyAsync(ws + L.code, G.code.data(), G.code.size(), hipMemcpyHostToDevice, stream));
         }
@@ -546,6 +550,7 @@ StepArgs rd_sim::step_args(double dt, int in_buf) const
     a.mask = (const uint64_t *)(ws + L.mask);
     a.code = (const uint8_t *)(ws + L.code);
     a.ncnt = g->B == 8 ? (const uint32_t *)(ws + L.ncnt) : nullptr;
+    a.hrec = compact ? (const uint32_t *)(ws + L.hrec) : nullptr;
     a.cbase = cbase_ptr();
     a.geom = (const GeomInfo *)(ws + L.geom);
     a.cin = field_ptr(in_buf, 0);

@@ -56,6 +56,7 @@ struct StepArgs {
     const BlockInfo *info;
     const uint64_t *mask;
     const uint8_t *code;   // per-slot neighbour codes (bits 0-5 neighbours, bit 6 active)
+    const uint32_t *hrec;  // compact layout: per-block halo record, 32 words (k_halo_rec8)
     const uint32_t *ncnt;  // B = 8: active-neighbour counts, one word per (block, lane
                            // (x, y)): bits 3z..3z+2 hold the count of voxel (x, y, z)
     const uint32_t *cbase; // compact layout: first voxel of each block (nb + 1); NULL:
@@ -130,6 +131,9 @@ int rd_launch_fill_u32(void *ptr, uint32_t value, int64_t n_words, void *stream)
 // launch (grid barrier between steps); the buffers swap after each step, as in nsteps
 // single-step launches; a.ctr_off is the first step's offset.  n_cu: compute units.
 int rd_launch_step_fused(int storage, const StepArgs &a, int nsteps, int n_cu, void *stream);
+// compact layout: the halo records (StepArgs::hrec) of nb blocks
+int rd_launch_halo_rec8(const BlockInfo *info, const uint64_t *mask, const uint32_t *cbase, uint32_t *hrec,
+                        int nb, void *stream);
 // B = 8: the active-neighbour count words (StepArgs::ncnt) of nb blocks
 int rd_launch_count_words8(const uint64_t *mask, uint32_t *ncnt, int nb, void *stream);
 int rd_launch_add_u32(uint32_t *ptr, uint32_t add, void *stream);

@@ -33,6 +33,7 @@ struct SimLayout {
     size_t info, mask, geom, code;
     size_t cbase;         // compact layout: first voxel of each block, uint32[nb + 1]
     size_t ncnt;          // B = 8: active-neighbour counts, uint32[nb][64] (3 bits per plane)
+    size_t hrec;          // compact layout: halo records, uint32[nb][32]
     size_t field[2];
     int64_t field_elems;  // nb * B^3
     int nparts;
