@@ -299,6 +299,13 @@ extern "C" rd_status rd_sim_set_layout(rd_sim *sim, int layout)
         // byte offsets of one species buffer (4 bytes per voxel at most) stay 32-bit
         if (sim->g->n_active > (int64_t)(0xFFFFFF00u / 4) - 64)
             return rd_fail(RD_ERR_SHAPE, "the compact layout holds at most 2^30 - 128 active voxels");
+        // its kernels take a block's x neighbours as list entries b - 1 and b + 1 (the
+        // builder lists blocks x-fastest, and concatenation keeps each part's order)
+        const std::vector<BlockInfo> &info = sim->g->info;
+        for (size_t b = 0; b < info.size(); ++b)
+            if ((info[b].nbr[0] >= 0 && info[b].nbr[0] != (int32_t)b - 1) ||
+                (info[b].nbr[1] >= 0 && info[b].nbr[1] != (int32_t)b + 1))
+                return rd_fail(RD_ERR_STATE, "the compact layout needs x neighbours at adjacent list entries");
         if (sim->kernel < 2) sim->kernel = 2;
     } else if (sim->kernel == 4) {
         sim->kernel = 2;  // the lane-exchange kernel needs the compact layout
