@@ -57,6 +57,8 @@ def parse():
     p.add_argument("--steady-forms", default="fp32,fp16", help="storage types of the steady form")
     p.add_argument("--steady-tol", type=float, default=1e-8)
     p.add_argument("--steady-max-iters", type=int, default=200000)
+    p.add_argument("--cg-precond", type=int, default=4,
+                   help="Jacobi steps of the steady-state CG's block preconditioner (0: plain CG)")
     p.add_argument("--adjoint", type=int, default=1,
                    help="1: time the checkpointed adjoint on the 256^3 diffusion-decay packing")
     p.add_argument("--diffusivity-steps", type=int, default=2000,
@@ -201,7 +203,14 @@ def step_kernel_name(B, launch, S):
     return name.format(S=S, C=cmp, D=d)
 
 
-def batched_form(torch, rd, W, count, max_edge, stream):
+def cg_words(prec):
+    """Vector words per active voxel and CG iteration: the matvec with the p update fused
+    (reads p and z, or r without the preconditioner; writes p) and the x, r update with
+    A p recomputed (reads x, p, r; writes x, r, and z with the preconditioner)."""
+    return 9 if prec > 0 else 8
+
+
+def batched_form(torch, rd, W, count, max_edge, stream, prec=4):
     """Per-geometry tortuosity along x of `count` boolean sphere packings (edge
     U{64..max_edge}, porosity U(0.3, 0.7)), all in one set of CG launches."""
     t0 = time.perf_counter()
@@ -216,6 +225,8 @@ def batched_form(torch, rd, W, count, max_edge, stream):
         # launch setting (iterations per graph segment, graph replay) by the batch
         # autotuner (50 CG iterations per trial)
         batches = [rd.Batch(cands[B]).bind(stream=stream) for B in edges]
+        for bt in batches:
+            bt.set_cg_precond(prec)
         best, trial_ms = rd.batch_autotune_pick(batches, 0, 50)
         bt, geoms, block_edge = batches[best], cands[edges[best]], edges[best]
         launch = bt.get_launch()
@@ -232,14 +243,12 @@ def batched_form(torch, rd, W, count, max_edge, stream):
         "geometries": count,
         "block_edge": block_edge,
         "launch": launch,
+        "cg_precond_jacobi_steps": prec,
         "trial_ms_per_iteration": {f"{B}^3": float(m) for B, m in zip(edges, trial_ms)},
         "edges": [int(info["n"]) for _, info in geoms_np],
         "seconds": secs,
         "active_voxel_cg_iterations_per_s": voxel_iters / secs,
-        # per iteration: matvec with the p update fused (reads p, r; writes p) and the
-        # x, r update with A p recomputed (reads x, p, r; writes x, r): 8 FP32 words per
-        # active voxel
-        "alg_GBps": voxel_iters * 8 * 4 / secs / 1e9,
+        "alg_GBps": voxel_iters * cg_words(prec) * 4 / secs / 1e9,
         "tau": [float(x) for x in tau],
         "rel_residual_max": float(max(rel)),
         "iterations": [int(x) for x in it],
@@ -343,7 +352,7 @@ def fused_form(torch, rd, W, stream, fused=16, size=512):
     return out
 
 
-def steady_form(torch, rd, W, size, axes, forms, tol, stream, max_iters=200000):
+def steady_form(torch, rd, W, size, axes, forms, tol, stream, max_iters=200000, prec=4):
     """Tortuosity of the ceramic-foam volume (solid matrix of overlapping pore spheres
     r ~ U(10, 30), pore fraction 0.15) along the first `axes` axes by conjugate
     gradients, per storage type; with the full 1024^3 volume, the same solves on its
@@ -360,11 +369,12 @@ def steady_form(torch, rd, W, size, axes, forms, tol, stream, max_iters=200000):
     crop = np.ascontiguousarray(img[:FOAM_CROP, :FOAM_CROP, :FOAM_CROP]) if size == 1024 else None
     del img
     out = {"workload": f"foam{size}", "n_active": st["n_active"], "n_blocks": st["n_blocks"],
-           "fill": st["fill"], "tol": tol, "runs": []}
+           "fill": st["fill"], "tol": tol, "cg_precond_jacobi_steps": prec, "runs": []}
     for storage in forms:
         with torch.cuda.stream(stream):
             sim = rd.Sim(geom, storage)
             sim.add_species(1.0)
+            sim.set_cg_precond(prec)
             sim.bind(features=rd.RD_WS_SOLVER, stream=stream)
             for axis in range(axes):
                 torch.cuda.synchronize()
@@ -377,13 +387,13 @@ def steady_form(torch, rd, W, size, axes, forms, tol, stream, max_iters=200000):
                                     "rel_residual": r["rel_residual"], "iters": r["iters"],
                                     "converged": r["converged"], "seconds": secs,
                                     "active_voxel_cg_iterations_per_s": vi / secs,
-                                    "alg_GBps": vi * 8 * (4 if storage == "fp32" else 2) / secs / 1e9})
+                                    "alg_GBps": vi * cg_words(prec) * (4 if storage == "fp32" else 2) / secs / 1e9})
                 log(f"steady {storage} axis {axis}: tau {r['tau']:.5f}, rel {r['rel_residual']:.2e}, "
                     f"{r['iters']} it, {secs:.1f}s")
             del sim
             torch.cuda.empty_cache()
     if crop is not None:
-        out["oracle_check"] = foam_crop_check(torch, rd, np, crop, forms, tol, stream)
+        out["oracle_check"] = foam_crop_check(torch, rd, np, crop, forms, tol, stream, prec)
     return out
 
 
@@ -397,7 +407,7 @@ def _sha256(img):
     return hashlib.sha256(img.tobytes()).hexdigest()
 
 
-def foam_crop_check(torch, rd, np, crop, forms, tol, stream):
+def foam_crop_check(torch, rd, np, crop, forms, tol, stream, prec=4):
     """Tortuosity along x of the 256^3 corner crop of the foam, per storage type, against
     the stored FP64 oracle value (oracle CG to 1e-12, written by
     tests/golden/make_goldens.py)."""
@@ -416,6 +426,7 @@ def foam_crop_check(torch, rd, np, crop, forms, tol, stream):
         with torch.cuda.stream(stream):
             sim = rd.Sim(geom, storage)
             sim.add_species(1.0)
+            sim.set_cg_precond(prec)
             sim.bind(features=rd.RD_WS_SOLVER, stream=stream)
             r = sim.steady_state(0, tol, 200000)
             del sim
@@ -660,9 +671,9 @@ def main():
         if a.profile_form == "steady":
             rec = steady_form(torch, rd, W, a.steady_size, a.steady_axes,
                               [f for f in a.steady_forms.split(",") if f], a.steady_tol, stream,
-                              a.steady_max_iters)
+                              a.steady_max_iters, a.cg_precond)
         elif a.profile_form == "batch":
-            rec = batched_form(torch, rd, W, a.batch, a.batch_max_edge, stream)
+            rec = batched_form(torch, rd, W, a.batch, a.batch_max_edge, stream, a.cg_precond)
         elif a.profile_form == "batch_steps":
             rec = batched_step_form(torch, rd, W, a.batch, a.batch_max_edge, a.batch_steps, stream)
         elif a.profile_form == "fused":
@@ -821,7 +832,7 @@ def main():
         "forms": results,
     }
     if a.batch > 0 and not a.profile:
-        out["forms"]["batched"] = batched_form(torch, rd, W, a.batch, a.batch_max_edge, stream)
+        out["forms"]["batched"] = batched_form(torch, rd, W, a.batch, a.batch_max_edge, stream, a.cg_precond)
         if a.batch_steps > 0:
             out["forms"]["batched_steps"] = batched_step_form(torch, rd, W, a.batch, a.batch_max_edge,
                                                               a.batch_steps, stream)
@@ -833,7 +844,7 @@ def main():
     if a.steady_axes > 0 and not a.profile:
         out["forms"]["steady"] = steady_form(torch, rd, W, a.steady_size, a.steady_axes,
                                              [f for f in a.steady_forms.split(",") if f],
-                                             a.steady_tol, stream)
+                                             a.steady_tol, stream, prec=a.cg_precond)
 
     if a.diffusivity_steps > 0 and not a.profile:
         out["forms"]["diffusivity"] = diffusivity_form(torch, rd, np, geom, img, w, n_active,

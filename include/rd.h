@@ -360,7 +360,8 @@ rd_status rd_sim_plane_flux(rd_sim *sim, int species, int axis, int64_t i0, doub
 /* Steady state of species 0 (single-species, no reactions or Robin) with a unit
  * drop along `axis` (Dirichlet 1 on the low face plane, 0 on the high one,
  * no-flux elsewhere), solved by conjugate gradients with the stencil as operator
- * (the FTCS step's operator at t -> infinity) and FP64 dot products.  Initial guess:
+ * (the FTCS step's operator at t -> infinity), a block-Jacobi preconditioner
+ * (rd_sim_set_cg_precond) and FP64 dot products.  Initial guess:
  * the linear ramp on 6-connected clusters touching both planes, 1 on clusters touching
  * only the inlet, 0 on the rest (clusters labelled on the GPU).  The iterate is kept in
  * FP64; every 25 iterations the FP64 residual b - A x is evaluated (rel_residual is its
@@ -377,6 +378,17 @@ rd_status rd_sim_plane_flux(rd_sim *sim, int species, int axis, int64_t i0, doub
  * steady field (the FP64 iterate rounded to the storage type) in species 0. */
 rd_status rd_sim_steady_state(rd_sim *sim, int axis, double rel_tol, int64_t max_iters,
                               double *tau, double *rel_residual, int64_t *iters);
+
+/* Preconditioner of the steady-state CG (eq. tortuosity needs only the converged field,
+ * so the preconditioner changes the path to it, not the result).  With 8^3 blocks,
+ * jacobi_steps >= 1 runs preconditioned CG with M^-1 r = jacobi_steps Jacobi steps on
+ * each block's own equations (the diagonal of the operator, the block's own free
+ * neighbours; neighbours outside the block count as 0): a symmetric positive definite
+ * polynomial in the block operator, applied in the registers of the update kernel (one
+ * more vector written per iteration).  Even counts condition best; 0 = plain CG.
+ * Default 4; 4^3 blocks always run plain CG.  RD_ERR_ARG for NULL or a count outside
+ * 0..16.  rd_batch_set_cg_precond sets the same for a batch. */
+rd_status rd_sim_set_cg_precond(rd_sim *sim, int jacobi_steps);
 
 /* Discrete adjoint of a single-species diffusion-decay simulation (optionally with
  * Robin walls and Dirichlet faces), run from the current field for n_steps of size
@@ -491,6 +503,8 @@ rd_status rd_batch_tortuosity(rd_batch *b, int axis, double rel_tol, int64_t max
  * the interval.  RD_ERR_ARG for a NULL batch or an interval outside 1..1000. */
 rd_status rd_batch_set_launch(rd_batch *b, int iters_per_check, int use_graph);
 rd_status rd_batch_get_launch(const rd_batch *b, int *iters_per_check, int *use_graph);
+/* The preconditioner of a batch's CG, as rd_sim_set_cg_precond (default 4). */
+rd_status rd_batch_set_cg_precond(rd_batch *b, int jacobi_steps);
 /* Autotuning of batches: bound candidate batches of the same geometries (indexed with
  * different block edges, say) each try iters_per_check 25 and 50 with and without graph
  * replay, running max(trial_iters, interval) CG iterations along `axis` per trial, and

@@ -106,6 +106,63 @@ __device__ __forceinline__ float cg_ap8(const float *q, float dn, float up, floa
     return fr ? ap : 0.0f;
 }
 
+// Block-Jacobi preconditioner of the 8^3 column kernels: z = M^-1 r with
+//   z_0 = V r,  z_{j+1} = V (r + N z_j),  j < steps - 1,
+// V = diag(1 / n_p) over the free voxels (n_p: active neighbours of p, Dirichlet ones
+// included, i.e. the diagonal of A) and N the adjacency of the free voxels of the same
+// block: Jacobi steps on the block's own equations with every neighbour outside the
+// block taken as 0.  M^-1 = sum_j (V N)^j V = V^1/2 (sum_j (V^1/2 N V^1/2)^j) V^1/2 is
+// symmetric, and positive definite on every block component that has a neighbour
+// outside it or a Dirichlet contact (there |eigenvalue of V^1/2 N V^1/2| < 1); an even
+// step count keeps it well conditioned.  The same linear map in every kernel (same
+// operations, same order), so CG sees one fixed preconditioner.
+// ts: the wave's 10 x 10 LDS tile with a zero ring; rk: the lane's residual per plane
+// (0 off free voxels); vk: 1 / n_p on free voxels, 0 elsewhere (z stays 0 there).
+__device__ __forceinline__ void cg_jacobi8(float *ts, int lx, int ly, const float rk[8], const float vk[8],
+                                           int steps, float zk[8])
+{
+#pragma unroll
+    for (int k = 0; k < 8; ++k) zk[k] = rk[k] * vk[k];
+    for (int j = 1; j < steps; ++j) {
+        float zn[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            ts[(ly + 1) * 10 + (lx + 1)] = zk[k];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const float *q = &ts[(ly + 1) * 10 + (lx + 1)];
+            const float dn = k > 0 ? zk[k > 0 ? k - 1 : 0] : 0.0f;
+            const float up = k < 7 ? zk[k < 7 ? k + 1 : 7] : 0.0f;
+            const float sum = ((q[-1] + q[1]) + (q[-10] + q[10])) + (dn + up);
+            zn[k] = (rk[k] + sum) * vk[k];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) zk[k] = zn[k];
+    }
+}
+
+// the ring of a wave's 10 x 10 tile set to 0 (lanes of the first row write it)
+__device__ __forceinline__ void tile_ring_zero(float *ts, int lx, int ly)
+{
+    if (ly == 0) {
+        ts[(lx + 1) * 10 + 0] = 0.0f;
+        ts[(lx + 1) * 10 + 9] = 0.0f;
+        ts[0 * 10 + (lx + 1)] = 0.0f;
+        ts[9 * 10 + (lx + 1)] = 0.0f;
+    }
+}
+
+// 1 / (active neighbours) of a free voxel from its code (0 for a voxel without any)
+__device__ __forceinline__ float cg_inv_count(unsigned code)
+{
+    const unsigned n = (unsigned)__popc(code & 63u);
+    return n ? __builtin_amdgcn_rcpf((float)n) : 0.0f;
+}
+
 template <int B>
 __device__ __forceinline__ bool geom_live(const CgArgs &a, int gid)
 {
@@ -208,8 +265,8 @@ __global__ __launch_bounds__(256) void k_cg_matvec8(CgArgs a)
 #pragma unroll
     for (int f = 0; f < 6; ++f) Wf[f] = rec[8 + f];
     typedef typename RawOf<T>::type R;
-    const T *rv = (const T *)a.r;
-    R rc[8], rh[6], qc[8], qh[6];  // p and r raw words
+    const T *rv = (const T *)(a.prec > 0 ? a.z : a.r);  // p_new = z + beta p
+    R rc[8], rh[6], qc[8], qh[6];  // p and z raw words
     unsigned cd[8];
 #pragma unroll
     for (int z = 0; z < 8; ++z) {
@@ -305,7 +362,10 @@ __global__ __launch_bounds__(256) void k_cg_matvec8(CgArgs a)
 // Dirichlet voxels their values.  Partial (r.r, 0) per block, of r as stored.
 // (Unlike the matvec, this kernel loads the x faces of one vector only; handing them
 // over through LDS measured slower here: 499 against 486 us per call on a 512^3 foam.)
-template <typename T, bool X64>
+// PREC: the block's new residual, as stored, is preconditioned in place (cg_jacobi8:
+// the whole block is in the wave's registers) and z = M^-1 r stored; partial (r.z, r.r).
+// Without it the partial is (r.r, r.r).
+template <typename T, bool X64, bool PREC>
 __global__ __launch_bounds__(256) void k_cg_update8(CgArgs a)
 {
     __shared__ float tile[4][100];
@@ -377,6 +437,7 @@ __global__ __launch_bounds__(256) void k_cg_update8(CgArgs a)
                      bz * 8 + 8 >= g.nz;
     float *ts = tile[wv];
     double rr = 0.0;
+    float rk[8], vk[8];  // PREC: the stored new residual and 1 / n_p (0 off free voxels)
 #pragma unroll
     for (int z = 0; z < 8; ++z) {
         ts[(ly + 1) * 10 + (lx + 1)] = c[z];
@@ -406,9 +467,11 @@ __global__ __launch_bounds__(256) void k_cg_update8(CgArgs a)
         double xdn = 0.0;
         if (X64) xdn = fr ? fma(alpha_x, (double)c[z], xd[z]) : xd[z];
         else xn = fr ? fmaf(alpha, c[z], from_raw<T>(xc[z])) : from_raw<T>(xc[z]);
-        if (fr) {
-            const float rs = rd_round<T>(rn);  // as stored
-            rr += (double)rs * (double)rs;
+        const float rs = rd_round<T>(rn);  // as stored
+        if (fr) rr += (double)rs * (double)rs;
+        if (PREC) {
+            rk[z] = fr ? rs : 0.0f;
+            vk[z] = fr ? cg_inv_count(code) : 0.0f;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -419,14 +482,90 @@ __global__ __launch_bounds__(256) void k_cg_update8(CgArgs a)
         }
         if (X64 && sector_active<double>(Wo[z], lane)) a.x64[base + z * 64 + lane] = xdn;
     }
+    double rz = rr;
+    if (PREC) {
+        tile_ring_zero(ts, lx, ly);
+        float zk[8];
+        cg_jacobi8(ts, lx, ly, rk, vk, a.prec, zk);
+        rz = 0.0;
+#pragma unroll
+        for (int z = 0; z < 8; ++z) {
+            const float zs = rd_round<T>(zk[z]);  // as stored
+            rz += (double)rk[z] * (double)zs;
+            if (sector_active<T>(Wo[z], lane)) rd_st_keep((T *)a.z, base + z * 64 + lane, zk[z]);
+        }
+        rz = wave_sum(rz);
+    }
     rr = wave_sum(rr);
     if (lane == 0) {
-        a.partial[(int64_t)b * 2 + 0] = rr;
-        a.partial[(int64_t)b * 2 + 1] = 0.0;
+        a.partial[(int64_t)b * 2 + 0] = PREC ? rz : rr;
+        a.partial[(int64_t)b * 2 + 1] = rr;
     }
 }
 
-// x += alpha p, r -= alpha Ap on free voxels of live geometries; partial (r.r, 0)
+// z = M^-1 r (cg_jacobi8) of the stored residual of every block of a live geometry, for
+// the start of CG and after a residual replacement or rescaling; partial (r.z, r.r).
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_prec8(CgArgs a)
+{
+    __shared__ float tile[4][100];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int b = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + wv);
+    if (b >= a.nb) return;
+    const BlockInfo bi = a.info[b];
+    int bx, by, bz, gid;
+    block_pos(bi, &bx, &by, &bz, &gid);
+    if (!geom_live<8>(a, gid)) {
+        if (lane == 0) {
+            a.partial[(int64_t)b * 2 + 0] = 0.0;
+            a.partial[(int64_t)b * 2 + 1] = 0.0;
+        }
+        return;
+    }
+    const int64_t base = (int64_t)b * 512;
+    const int lx = lane & 7, ly = lane >> 3;
+    const uint64_t *rec = a.mask + (int64_t)b * 16;
+    const GeomInfo g = a.geom[gid];
+    const int gx = bx * 8 + lx, gy = by * 8 + ly;
+    const bool bnd = bx == 0 || by == 0 || bz == 0 || bx * 8 + 8 >= g.nx || by * 8 + 8 >= g.ny ||
+                     bz * 8 + 8 >= g.nz;
+    float rk[8], vk[8];
+    double rr = 0.0;
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        const bool act = lane_bit(rec[z]);
+        const unsigned code = act ? (unsigned)a.code[base + z * 64 + lane] : 0u;
+        const float r = act ? rd_ld((const T *)a.r, base + z * 64 + lane) : 0.0f;
+        unsigned onf = 0u;
+        if (bnd)
+            onf = (gx == 0 ? 1u : 0u) | (gx == g.nx - 1 ? 2u : 0u) | (gy == 0 ? 4u : 0u) |
+                  (gy == g.ny - 1 ? 8u : 0u) | (bz * 8 + z == 0 ? 16u : 0u) |
+                  (bz * 8 + z == g.nz - 1 ? 32u : 0u);
+        const bool fr = (code & 64u) != 0u && (onf & a.dir) == 0u;
+        rk[z] = fr ? r : 0.0f;
+        vk[z] = fr ? cg_inv_count(code) : 0.0f;
+        rr += (double)rk[z] * (double)rk[z];
+    }
+    float *ts = tile[wv];
+    tile_ring_zero(ts, lx, ly);
+    float zk[8];
+    cg_jacobi8(ts, lx, ly, rk, vk, a.prec, zk);
+    double rz = 0.0;
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        const float zs = rd_round<T>(zk[z]);
+        rz += (double)rk[z] * (double)zs;
+        if (sector_active<T>(rec[z], lane)) rd_st_keep((T *)a.z, base + z * 64 + lane, zk[z]);
+    }
+    rz = wave_sum(rz);
+    rr = wave_sum(rr);
+    if (lane == 0) {
+        a.partial[(int64_t)b * 2 + 0] = rz;
+        a.partial[(int64_t)b * 2 + 1] = rr;
+    }
+}
+
+// x += alpha p, r -= alpha Ap on free voxels of live geometries; partial (r.r, r.r)
 template <typename T, int B>
 __global__ __launch_bounds__(256) void k_cg_update(CgArgs a)
 {
@@ -470,7 +609,7 @@ __global__ __launch_bounds__(256) void k_cg_update(CgArgs a)
             rr += (double)rs * (double)rs;
         }
     }
-    block_sum2<B>(rr, 0.0, a.partial, b, b < a.nb);
+    block_sum2<B>(rr, rr, a.partial, b, b < a.nb);
 }
 
 // p = r + beta p on free voxels of live geometries
@@ -1082,18 +1221,30 @@ int cg_launch_update(int storage, int B, const CgArgs &a, void *stream)
     if (B == 8) {  // column form with A p recomputed (the fused matvec does not store it)
         const dim3 grid((unsigned)std::max(1, (a.nb + 3) / 4));
         hipStream_t st = (hipStream_t)stream;
-        if (a.x64 && a.x64_direct) {
-            if (storage == 0) hipLaunchKernelGGL((k_cg_update8<float, true>), grid, dim3(256), 0, st, a);
-            else if (storage == 1) hipLaunchKernelGGL((k_cg_update8<bf16_t, true>), grid, dim3(256), 0, st, a);
-            else hipLaunchKernelGGL((k_cg_update8<_Float16, true>), grid, dim3(256), 0, st, a);
-        } else {
-            if (storage == 0) hipLaunchKernelGGL((k_cg_update8<float, false>), grid, dim3(256), 0, st, a);
-            else if (storage == 1) hipLaunchKernelGGL((k_cg_update8<bf16_t, false>), grid, dim3(256), 0, st, a);
-            else hipLaunchKernelGGL((k_cg_update8<_Float16, false>), grid, dim3(256), 0, st, a);
-        }
+        const bool x64 = a.x64 && a.x64_direct, prec = a.prec > 0;
+#define UPD8(T_)                                                                                   \
+    do {                                                                                           \
+        if (x64 && prec) hipLaunchKernelGGL((k_cg_update8<T_, true, true>), grid, dim3(256), 0, st, a);    \
+        else if (x64) hipLaunchKernelGGL((k_cg_update8<T_, true, false>), grid, dim3(256), 0, st, a);      \
+        else if (prec) hipLaunchKernelGGL((k_cg_update8<T_, false, true>), grid, dim3(256), 0, st, a);     \
+        else hipLaunchKernelGGL((k_cg_update8<T_, false, false>), grid, dim3(256), 0, st, a);              \
+    } while (0)
+        if (storage == 0) UPD8(float);
+        else if (storage == 1) UPD8(bf16_t);
+        else UPD8(_Float16);
+#undef UPD8
         return (int)hipGetLastError();
     }
     CG_DISPATCH(storage, B, k_cg_update, grid_for(B, a.nb), stream, a);
+}
+int cg_launch_prec(int storage, const CgArgs &a, void *stream)
+{
+    const dim3 grid((unsigned)std::max(1, (a.nb + 3) / 4));
+    hipStream_t st = (hipStream_t)stream;
+    if (storage == 0) hipLaunchKernelGGL((k_cg_prec8<float>), grid, dim3(256), 0, st, a);
+    else if (storage == 1) hipLaunchKernelGGL((k_cg_prec8<bf16_t>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_cg_prec8<_Float16>), grid, dim3(256), 0, st, a);
+    return (int)hipGetLastError();
 }
 int cg_launch_pupdate(int storage, int B, const CgArgs &a, void *stream)
 {

@@ -108,7 +108,7 @@ rd_status cg_segment(CgArgs &a, int storage, int B, hipStream_t st, int iters)
         }
         LAUNCHCHK(cg_launch_segsum(a, CG_PAP, -1, 0, st));
         LAUNCHCHK(cg_launch_update(storage, B, a, st));
-        LAUNCHCHK(cg_launch_segsum(a, CG_RRNEW, -1, 1, st));
+        LAUNCHCHK(cg_launch_segsum(a, CG_RRNEW, CG_RRREC, 1, st));
     }
     return RD_OK;
 }
@@ -172,8 +172,13 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
     out.assign(n, CgOut());
     LAUNCHCHK(rd_launch_fill_u32(a.scal, 0u, (int64_t)n * CG_NSCAL * 2, st));
     if (!a.x64) return rd_fail(RD_ERR_STATE, "CG needs the FP64 iterate");
+    if (B != 8) a.prec = 0;
     LAUNCHCHK(cg_launch_res64(storage, B, a, 1, st));
     LAUNCHCHK(cg_launch_segsum(a, CG_RRNEW, CG_BB, 2, st));
+    if (a.prec > 0) {  // z = M^-1 r; CG_RR becomes r.z
+        LAUNCHCHK(cg_launch_prec(storage, a, st));
+        LAUNCHCHK(cg_launch_segsum(a, CG_RRNEW, CG_RRREC, 2, st));
+    }
     std::vector<double> hs;
     rd_status s = copy_scal(a, hs, st);
     if (s != RD_OK) return s;
@@ -182,7 +187,8 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
     int live = 0;
     for (int g = 0; g < n; ++g) {
         double *v = &hs[(size_t)g * CG_NSCAL];
-        const double bb = v[CG_BB], rr = v[CG_RR];
+        if (a.prec <= 0) v[CG_RRREC] = v[CG_RR];
+        const double bb = v[CG_BB], rr = v[CG_RRREC];
         out[g].rel = bb > 0 ? sqrt(rr / bb) : 0.0;
         best[g] = out[g].rel;
         v[CG_SIGMA] = 1.0;
@@ -242,7 +248,7 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
                 // replace the recursive residual once it has drifted from the true one by
                 // more than a quarter (van der Vorst and Ye replace only where the gap
                 // grows: every replacement costs the recursion some of its conjugacy)
-                const double rec = sqrt(std::max(v[CG_RR], 0.0)) / v[CG_SIGMA];
+                const double rec = sqrt(std::max(v[CG_RRREC], 0.0)) / v[CG_SIGMA];
                 const double tru = sqrt(std::max(v[CG_CHECK], 0.0));
                 replace = replace || fabs(rec - tru) > 0.25 * tru;
                 rescale = rescale || sig != v[CG_SIGMA];
@@ -256,6 +262,10 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
             // the rescaling of r and p; then rr of the stored r
             LAUNCHCHK(cg_launch_res64(storage, B, a, replace ? 2 : 3, st));
             LAUNCHCHK(cg_launch_segsum(a, CG_RR, -1, -1, st));
+            if (a.prec > 0) {  // and z = M^-1 r of the new r; CG_RR = r.z
+                LAUNCHCHK(cg_launch_prec(storage, a, st));
+                LAUNCHCHK(cg_launch_segsum(a, CG_RR, CG_RRREC, -1, st));
+            }
         }
     }
     if (!want_tau) return RD_OK;
@@ -325,6 +335,8 @@ extern "C" rd_status rd_sim_steady_state(rd_sim *sim, int axis, double rel_tol, 
     a.p = sim->ws + sim->L.solver[1];
     a.ap = sim->ws + sim->L.solver[2];
     a.p2 = sim->ws + sim->L.solver[3];
+    a.z = a.ap;  // free during CG with 8^3 blocks (A p is recomputed, never stored)
+    a.prec = G.B == 8 ? sim->cg_prec : 0;
     a.partial = (double *)(sim->ws + sim->L.part);
     a.scal = (double *)(sim->ws + sim->L.scal);
     a.mid = (double *)(sim->ws + sim->L.mid);
@@ -392,6 +404,7 @@ struct rd_batch {
     hipStream_t stream = nullptr;
     int check_every = CHECK_EVERY;  // CG iterations per captured segment / between checks
     bool use_graph = true;
+    int cg_prec = 4;  // Jacobi steps of the block preconditioner (8^3 blocks; 0: plain CG)
 };
 
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -531,6 +544,8 @@ rd_status batch_cg(rd_batch *b, int axis, double rel_tol, int64_t max_iters, boo
     a.p = b->ws + b->o_vec[2];
     a.ap = b->ws + b->o_vec[3];
     a.p2 = b->ws + b->o_vec[4];
+    a.z = a.ap;
+    a.prec = b->B == 8 ? b->cg_prec : 0;
     a.partial = (double *)(b->ws + b->o_part);
     a.scal = (double *)(b->ws + b->o_scal);
     if (b->nb > 0) {
@@ -578,6 +593,22 @@ extern "C" rd_status rd_batch_set_launch(rd_batch *b, int iters_per_check, int u
     if (iters_per_check < 1 || iters_per_check > 1000) return rd_fail(RD_ERR_ARG, "iters_per_check in 1..1000");
     b->check_every = iters_per_check;
     b->use_graph = use_graph != 0;
+    return RD_OK;
+}
+
+extern "C" rd_status rd_sim_set_cg_precond(rd_sim *sim, int jacobi_steps)
+{
+    if (!sim) return rd_fail(RD_ERR_ARG, "sim is NULL");
+    if (jacobi_steps < 0 || jacobi_steps > 16) return rd_fail(RD_ERR_ARG, "jacobi_steps must be 0..16");
+    sim->cg_prec = jacobi_steps;
+    return RD_OK;
+}
+
+extern "C" rd_status rd_batch_set_cg_precond(rd_batch *b, int jacobi_steps)
+{
+    if (!b) return rd_fail(RD_ERR_ARG, "batch is NULL");
+    if (jacobi_steps < 0 || jacobi_steps > 16) return rd_fail(RD_ERR_ARG, "jacobi_steps must be 0..16");
+    b->cg_prec = jacobi_steps;
     return RD_OK;
 }
 

@@ -19,7 +19,9 @@ enum {
     CG_QOUT = 9,
     CG_SIGMA = 10,       // FP64 iterate: r and p hold sigma times the true residual / direction
     CG_SIGMA_PREV = 11,  // the scale r and p hold before a pending rescaling (powers of 2)
-    CG_NSCAL = 12
+    CG_RRREC = 12,       // r.r of the recursive residual (CG_RR / CG_RRNEW hold r.z: with the
+                         // preconditioner z = M^-1 r, without it z = r)
+    CG_NSCAL = 13
 };
 
 struct CgArgs {
@@ -40,15 +42,20 @@ struct CgArgs {
     double *scal;          // [ngeom][CG_NSCAL]
     double *mid;           // single geometry: scratch of >= 1040 doubles for two-level sums
                            // of long block lists (NULL: one workgroup per geometry)
+    void *z;               // B = 8 with prec > 0: the preconditioned residual z = M^-1 r
+    int prec;              // B = 8: Jacobi steps of the block preconditioner (0: plain CG)
 };
 
 int cg_launch_matvec(int storage, int B, const CgArgs &a, void *stream);
-// B = 8: p2 = r + beta p (per live geometry, rounded to the storage type) and the
-// partial (p2.A p2, 0); A p2 is not stored.  The caller then swaps p and p2.
+// B = 8: p2 = z + beta p (per live geometry, rounded to the storage type; z = r when
+// a.prec is 0) and the partial (p2.A p2, 0); A p2 is not stored.  The caller then swaps
+// p and p2.
 int cg_launch_matvec_fused(int storage, const CgArgs &a, void *stream);
-// x += alpha p, r -= alpha A p, partial (r.r, 0); B = 4 reads the stored A p, B = 8
-// recomputes it from p.
+// x += alpha p, r -= alpha A p, partial (r.z, r.r); B = 4 reads the stored A p, B = 8
+// recomputes it from p and, with a.prec > 0, also writes z = M^-1 r.
 int cg_launch_update(int storage, int B, const CgArgs &a, void *stream);
+// B = 8, a.prec > 0: z = M^-1 r of the stored r on live geometries, partial (r.z, r.r)
+int cg_launch_prec(int storage, const CgArgs &a, void *stream);
 int cg_launch_pupdate(int storage, int B, const CgArgs &a, void *stream);
 // per-block FP64 partials (inlet, outlet) of the flux of x64 through the Dirichlet planes
 int cg_launch_flux(int B, const CgArgs &a, int inlet_face, void *stream);

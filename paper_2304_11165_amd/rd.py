@@ -80,6 +80,8 @@ _SIGS = {
     "rd_sim_set_layout": ([P, ci], ci),
     "rd_batch_set_launch": ([P, ci, ci], ci),
     "rd_batch_get_launch": ([P, P, P], ci),
+    "rd_batch_set_cg_precond": ([P, ci], ci),
+    "rd_sim_set_cg_precond": ([P, ci], ci),
     "rd_sim_frap_curve": ([P, ci, P, f64, i64, i64, P], ci),
     "rd_frap_fit": ([i64, P, P, i64, f64, P, f64, P, P], ci),
     "rd_sim_get_field": ([P, ci, P], ci),
@@ -498,6 +500,10 @@ class Sim:
         return {"tau": tau.value, "rel_residual": rel.value, "iters": it.value,
                 "converged": st == RD_OK}
 
+    def set_cg_precond(self, jacobi_steps):
+        """Jacobi steps of the steady-state CG's block preconditioner (0: plain CG)."""
+        _check(_lib.rd_sim_set_cg_precond(self.handle, int(jacobi_steps)), "rd_sim_set_cg_precond")
+
     def set_species_D(self, species, D):
         _check(_lib.rd_sim_set_species_D(self.handle, int(species), float(D)), "rd_sim_set_species_D")
 
@@ -567,6 +573,9 @@ class Batch:
                                   self.workspace.numel(), _stream_handle(self.stream)),
                "rd_batch_bind")
         return self
+
+    def set_cg_precond(self, jacobi_steps):
+        _check(_lib.rd_batch_set_cg_precond(self.handle, int(jacobi_steps)), "rd_batch_set_cg_precond")
 
     def set_launch(self, iters_per_check=25, use_graph=True):
         _check(_lib.rd_batch_set_launch(self.handle, int(iters_per_check), 1 if use_graph else 0),

@@ -96,6 +96,40 @@ def test_refinement_reaches_1e8(rd, oracle_mod, storage, B):
     assert rel_l2(u, uo, _anchored(img, 0)) < 2 * spacing
 
 
+@pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
+def test_block_jacobi_preconditioner(rd, oracle_mod, storage):
+    """CG with the block-Jacobi preconditioner (2 and 4 Jacobi steps per block) and plain
+    CG reach the same steady state as the FP64 oracle, and the preconditioned runs need
+    fewer iterations (the preconditioner changes the path, not the solution)."""
+    img, _ = W.boolean_spheres(48, 0.6, 2.0, 5.0, seed=6)
+    img = np.ascontiguousarray(img[:45, :, :43])  # ragged
+    uo, _, _ = oracle_mod.steady_state(img, 0, "cg", tol=1e-12)
+    tau_o = oracle_mod.tortuosity_from_field(img, 0, uo)[0]
+    it = {}
+    for k in (0, 2, 4):
+        g, s = make_gpu(rd, img, [1.0], storage=storage, B=8, features=rd.RD_WS_SOLVER)
+        s.set_cg_precond(k)
+        res = s.steady_state(0, 1e-8, 20000)
+        u = fields(s, 1)[0]
+        err = abs(res["tau"] - tau_o) / tau_o
+        print(f"{storage} jacobi steps {k}: rel residual {res['rel_residual']:.2e} after "
+              f"{res['iters']} it; tau rel err {err:.2e}")
+        assert res["converged"] and res["rel_residual"] <= 1e-8
+        assert err < 1e-6
+        spacing = {"fp32": 2.0 ** -24, "bf16": 2.0 ** -8, "fp16": 2.0 ** -11}[storage]
+        assert rel_l2(u, uo, _anchored(img, 0)) < 2 * spacing
+        it[k] = res["iters"]
+    assert it[2] < it[0] and it[4] < it[0]
+
+
+def test_precond_setting_checked(rd):
+    img = W.slab_box(12, 6, 6)
+    g, s = make_gpu(rd, img, [1.0], features=rd.RD_WS_SOLVER)
+    for bad in (-1, 17):
+        with pytest.raises(rd.RDError, match="ARG"):
+            s.set_cg_precond(bad)
+
+
 def test_batch_matches_single_and_oracle(rd, oracle_mod):
     imgs = []
     for i, n in enumerate([17, 24, 9, 31, 20]):
