@@ -57,7 +57,7 @@ def parse():
     p.add_argument("--steady-forms", default="fp32,fp16", help="storage types of the steady form")
     p.add_argument("--steady-tol", type=float, default=1e-8)
     p.add_argument("--steady-max-iters", type=int, default=200000)
-    p.add_argument("--cg-precond", type=int, default=4,
+    p.add_argument("--cg-precond", type=int, default=6,
                    help="Jacobi steps of the steady-state CG's block preconditioner (0: plain CG)")
     p.add_argument("--adjoint", type=int, default=1,
                    help="1: time the checkpointed adjoint on the 256^3 diffusion-decay packing")
@@ -210,7 +210,7 @@ def cg_words(prec):
     return 9 if prec > 0 else 8
 
 
-def batched_form(torch, rd, W, count, max_edge, stream, prec=4):
+def batched_form(torch, rd, W, count, max_edge, stream, prec=6):
     """Per-geometry tortuosity along x of `count` boolean sphere packings (edge
     U{64..max_edge}, porosity U(0.3, 0.7)), all in one set of CG launches."""
     t0 = time.perf_counter()
@@ -352,7 +352,7 @@ def fused_form(torch, rd, W, stream, fused=16, size=512):
     return out
 
 
-def steady_form(torch, rd, W, size, axes, forms, tol, stream, max_iters=200000, prec=4):
+def steady_form(torch, rd, W, size, axes, forms, tol, stream, max_iters=200000, prec=6):
     """Tortuosity of the ceramic-foam volume (solid matrix of overlapping pore spheres
     r ~ U(10, 30), pore fraction 0.15) along the first `axes` axes by conjugate
     gradients, per storage type; with the full 1024^3 volume, the same solves on its
@@ -407,7 +407,7 @@ def _sha256(img):
     return hashlib.sha256(img.tobytes()).hexdigest()
 
 
-def foam_crop_check(torch, rd, np, crop, forms, tol, stream, prec=4):
+def foam_crop_check(torch, rd, np, crop, forms, tol, stream, prec=6):
     """Tortuosity along x of the 256^3 corner crop of the foam, per storage type, against
     the stored FP64 oracle value (oracle CG to 1e-12, written by
     tests/golden/make_goldens.py)."""

@@ -386,7 +386,7 @@ rd_status rd_sim_steady_state(rd_sim *sim, int axis, double rel_tol, int64_t max
  * neighbours; neighbours outside the block count as 0): a symmetric positive definite
  * polynomial in the block operator, applied in the registers of the update kernel (one
  * more vector written per iteration).  Even counts condition best; 0 = plain CG.
- * Default 4; 4^3 blocks always run plain CG.  RD_ERR_ARG for NULL or a count outside
+ * Default 6; 4^3 blocks always run plain CG.  RD_ERR_ARG for NULL or a count outside
  * 0..16.  rd_batch_set_cg_precond sets the same for a batch. */
 rd_status rd_sim_set_cg_precond(rd_sim *sim, int jacobi_steps);
 
@@ -503,7 +503,7 @@ rd_status rd_batch_tortuosity(rd_batch *b, int axis, double rel_tol, int64_t max
  * the interval.  RD_ERR_ARG for a NULL batch or an interval outside 1..1000. */
 rd_status rd_batch_set_launch(rd_batch *b, int iters_per_check, int use_graph);
 rd_status rd_batch_get_launch(const rd_batch *b, int *iters_per_check, int *use_graph);
-/* The preconditioner of a batch's CG, as rd_sim_set_cg_precond (default 4). */
+/* The preconditioner of a batch's CG, as rd_sim_set_cg_precond (default 6). */
 rd_status rd_batch_set_cg_precond(rd_batch *b, int jacobi_steps);
 /* Autotuning of batches: bound candidate batches of the same geometries (indexed with
  * different block edges, say) each try iters_per_check 25 and 50 with and without graph

@@ -68,7 +68,7 @@ struct rd_sim {
     int graph_steps = 32;
     bool use_graph = true;
     bool xcd_map = true;
-    int cg_prec = 4;  // steady-state CG: Jacobi steps of the block preconditioner (0: none)
+    int cg_prec = 6;  // steady-state CG: Jacobi steps of the block preconditioner (0: none)
     int kernel = 2;       // B = 8 step kernel: 0 workgroup per block, 1 persistent, 2 z-column,
                           // 3 z-column with in-workgroup x-face exchange
     int wg_per_cu = 8;    // resident workgroups per CU of the persistent grid

@@ -404,7 +404,7 @@ struct rd_batch {
     hipStream_t stream = nullptr;
     int check_every = CHECK_EVERY;  // CG iterations per captured segment / between checks
     bool use_graph = true;
-    int cg_prec = 4;  // Jacobi steps of the block preconditioner (8^3 blocks; 0: plain CG)
+    int cg_prec = 6;  // Jacobi steps of the block preconditioner (8^3 blocks; 0: plain CG)
 };
 
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
