@@ -188,7 +188,9 @@ def foam_crop():
     return img, ref
 
 
-@pytest.mark.parametrize("storage,axis", [("fp32", 0), ("fp32", 1), ("fp32", 2), ("fp16", 0)])
+# BF16 vectors reach 1e-8 on the foam with the block-Jacobi preconditioner (plain CG stalled
+# near 2e-5 on the 1024^3 volume: the 8-bit mantissa of the directions)
+@pytest.mark.parametrize("storage,axis", [("fp32", 0), ("fp32", 1), ("fp32", 2), ("fp16", 0), ("bf16", 0)])
 def test_foam_crop256_tau_vs_stored_oracle(rd, foam_crop, storage, axis):
     img, ref = foam_crop
     res, s, nb = _steady(rd, img, axis, storage)
