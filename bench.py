@@ -54,7 +54,7 @@ def parse():
     p.add_argument("--steady-axes", type=int, default=1,
                    help="ceramic-foam steady state: tortuosity along the first K axes (0: skip)")
     p.add_argument("--steady-size", type=int, default=1024, help="edge of the foam volume")
-    p.add_argument("--steady-forms", default="fp32,fp16", help="storage types of the steady form")
+    p.add_argument("--steady-forms", default="fp32,fp16,bf16", help="storage types of the steady form")
     p.add_argument("--steady-tol", type=float, default=1e-8)
     p.add_argument("--steady-max-iters", type=int, default=200000)
     p.add_argument("--cg-precond", type=int, default=6,
@@ -89,8 +89,9 @@ def parse():
     p.add_argument("--xcd", default="auto", choices=["auto", "0", "1"],
                    help="XCD-aware block order (auto: autotuned)")
     p.add_argument("--traffic", default=TRAFFIC_FILE,
-                   help="JSON record of measured HBM bytes per step launch (rocprofv3 FETCH_SIZE + "
-                        "WRITE_SIZE, copy-calibrated); used only if the kernel sources still match")
+                   help="JSON records of measured HBM bytes per step launch (rocprofv3 FETCH_SIZE + "
+                        "WRITE_SIZE, copy-calibrated), per kernel and block order; used only if the "
+                        "kernel sources still match")
     return p.parse_args()
 
 
@@ -106,17 +107,19 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(path, kernel, workload):
-    """HBM bytes per launch from a traffic record, or None if there is none or it was
-    measured on other code, another kernel or another workload."""
+def load_traffic(path, kernel, workload, xcd_map):
+    """HBM bytes per launch from the traffic records (one per kernel and block order), or
+    None if none was measured on this code, kernel, block order and workload."""
     if not path or not os.path.exists(path):
         return None
-    rec = json.load(open(path))
-    if rec.get("source_hash") != source_hash() or rec.get("kernel") != kernel or \
-            rec.get("workload") != workload:
-        log(f"traffic record {path} does not match this build/kernel/workload: traffic = null")
-        return None
-    return rec.get("hbm_bytes_per_launch")
+    recs = json.load(open(path)).get("records", [])
+    for rec in recs:
+        if rec.get("source_hash") == source_hash() and rec.get("kernel") == kernel and \
+                rec.get("workload") == workload and rec.get("xcd_map") == int(xcd_map):
+            return rec.get("hbm_bytes_per_launch")
+    log(f"no traffic record in {path} for this build, kernel {kernel}, block order {int(xcd_map)} "
+        f"and workload: traffic = null")
+    return None
 
 
 def log(msg):
@@ -789,7 +792,7 @@ def main():
     f32 = results["fp32"]
     kname = step_kernel_name(w.block_edge, f32["launch"], S)
     workload_name = f"soil{n}"
-    traffic = load_traffic(a.traffic, kname, workload_name)
+    traffic = load_traffic(a.traffic, kname, workload_name, f32["launch"]["xcd_map"])
     out = {
         "metric": METRIC,
         "value": f32["updates_per_s"],

@@ -412,10 +412,33 @@ __device__ __forceinline__ void step8z_group(const StepArgs &a, int grp)
     const T *cin = (const T *)a.cin;
     T *cout = (T *)a.cout;
     const int lx = lane & 7, ly = lane >> 3;
-    const int32_t *nbr = a.info[b].nbr;
+    // the block record whole and unconditionally: one scalar load, issued with the mask
+    // record's, instead of a load per neighbour index behind the tests below
+    const BlockInfo bi = a.info[b];
+    const int32_t *nbr = bi.nbr;
     // x neighbours inside this workgroup (wave-uniform; only with XCH)
     const bool xm_in = XCH && wv > 0 && nbr[0] == b - 1;
     const bool xp_in = XCH && wv < 3 && nbr[1] == b + 1;
+    // CMP: what the side-halo positions are made of, loaded first so that their latency
+    // passes under the mask-record and plane loads: the block's halo record (ends / starts
+    // of the y neighbours' plane v = ly, the z neighbours' run bounds) and, for the x
+    // neighbours (list entries b - 1 and b + 1, clamped to the list; read only where the
+    // neighbour exists), plane v's word and start position
+    uint32_t hym = 0u, hyp = 0u, hzm = 0u, hzp = 0u, xmb = 0u, xpb = 0u;
+    uint64_t xmw = 0ull, xpw = 0ull;
+    if constexpr (CMP) {
+        const uint32_t *hr = a.hrec + (int64_t)b * 32;
+        hym = hr[ly];
+        hyp = hr[8 + ly];
+        hzm = hr[16];
+        hzp = hr[17];
+        const int bm = b > 0 ? b - 1 : b, bp = b + 1 < a.nb ? b + 1 : b;
+        const uint64_t *rm = a.mask + (int64_t)bm * 16, *rp = a.mask + (int64_t)bp * 16;
+        xmw = rm[ly];
+        xpw = rp[ly];
+        xmb = a.cbase[bm] + plane_prefix(rm, ly);
+        xpb = a.cbase[bp] + plane_prefix(rp, ly);
+    }
     // mask record: own plane words 0-7, face words 8-13; lane l's bit is l in each
     // (own slot (lx, ly) of a plane; face coordinates (u, v) = (lx, ly), bit v*8+u)
     const uint64_t *rec = a.mask + (int64_t)b * 16;
@@ -475,24 +498,21 @@ __device__ __forceinline__ void step8z_group(const StepArgs &a, int grp)
         int64_t hb;
         if constexpr (CMP) {
             // every position follows from b alone (no load waits for the neighbour
-            // table): the block's halo record holds the y / z neighbours' plane bounds,
-            // and the x neighbours are list entries b - 1 and b + 1
-            const uint32_t *hr = a.hrec + (int64_t)b * 32;
+            // table), from the values loaded at the top
             if (f == 4) {  // plane 7 of the -z neighbour: its last popc(Wf[4]) voxels
-                hb = (int64_t)hr[16] - __popcll(Wf[4]) + lanes_below(Wf[4]);
+                hb = (int64_t)hzm - __popcll(Wf[4]) + lanes_below(Wf[4]);
             } else if (f == 5) {  // plane 0 of the +z neighbour
-                hb = (int64_t)hr[17] + lanes_below(Wf[5]);
-            } else if (f < 2) {  // column x = 7 / x = 0 of plane v = ly, slot ns
-                hb = 0;
-                if (lane_bit(need)) hb = slot_index8(a.cbase, a.mask, f == 0 ? b - 1 : b + 1, ns);
+                hb = (int64_t)hzp + lanes_below(Wf[5]);
+            } else if (f < 2) {  // slot (x = 7 / 0, y = u = lx) of plane v = ly: the plane's
+                                 // start plus its active slots below that one
+                const int bit = lx * 8 + (f == 0 ? 7 : 0);
+                const uint64_t below = ((f == 0 ? xmw : xpw) & ((1ull << bit) - 1ull));
+                hb = (int64_t)(f == 0 ? xmb : xpb) + __popcll(below);
             } else {  // row y = 7 / y = 0 of plane v = ly at x = u = lx: the end / start of
                       // that plane less / plus the row's active voxels at or after / before u
                 const uint32_t row = (uint32_t)(Wf[f] >> (8 * ly)) & 0xffu;
-                hb = 0;
-                if (lane_bit(need)) {
-                    if (f == 2) hb = (int64_t)hr[ly] - __popc(row >> lx);
-                    else hb = (int64_t)hr[8 + ly] + __popc(row & ((1u << lx) - 1u));
-                }
+                if (f == 2) hb = (int64_t)hym - __popc(row >> lx);
+                else hb = (int64_t)hyp + __popc(row & ((1u << lx) - 1u));
             }
         } else {
             hb = (int64_t)nn * 512 + ns;
@@ -531,7 +551,6 @@ __device__ __forceinline__ void step8z_group(const StepArgs &a, int grp)
         }
     }
 
-    const BlockInfo bi = a.info[b];
     int bx, by, bz, gid;
     block_pos(bi, &bx, &by, &bz, &gid);
     const GeomInfo g = a.geom[gid];
