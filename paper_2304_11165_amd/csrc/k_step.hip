@@ -48,6 +48,34 @@ __device__ __forceinline__ void store_val(const StepArgs &a, T *cout, int s, int
     else if (a.sround) rd_st_sr(cout, idx, r, sr_species(h, s));
     else rd_st(cout, idx, r);
 }
+// p advanced by a 32-bit byte offset: a wave-uniform base plus a zero-extended 32-bit
+// offset, the form of a global access with a scalar base and a 32-bit vector offset (no
+// 64-bit address arithmetic per access).  The compact layout's offsets fit: a species
+// buffer holds fewer than 2^30 values.
+template <typename T>
+__device__ __forceinline__ T *at_byte(T *p, uint32_t off)
+{
+    return (T *)((char *)p + (uint64_t)off);
+}
+template <typename T>
+__device__ __forceinline__ const T *at_byte(const T *p, uint32_t off)
+{
+    return (const T *)((const char *)p + (uint64_t)off);
+}
+// A wave-uniform pointer pinned to scalar registers, so that the compiler keeps it as the
+// scalar base of the accesses above instead of folding it into each 64-bit vector address.
+// (The field buffers are device memory: the pointer is rebuilt in the global address
+// space, so the accesses stay global ones.)
+template <typename T>
+__device__ __forceinline__ T *uniform_ptr(T *p)
+{
+    typedef __attribute__((address_space(1))) T GT;
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (T *)(GT *)(((uint64_t)hi << 32) | lo);
+}
+
 // The same with the rounding mode fixed at compile time (SR: stochastic rounding on).
 template <typename T, bool PLAIN, bool SR>
 __device__ __forceinline__ void store_val_ct(T *cout, int s, int64_t idx, uint32_t h, float r)
@@ -411,6 +439,14 @@ __device__ __forceinline__ void step8z_group(const StepArgs &a, int grp)
     }
     const T *cin = (const T *)a.cin;
     T *cout = (T *)a.cout;
+    // CMP: per-species bases of the fields (scalar)
+    const T *cinb[S];
+    T *coutb[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        cinb[s] = CMP ? uniform_ptr(cin + s * a.sstride) : cin;
+        coutb[s] = CMP ? uniform_ptr(cout + s * a.sstride) : cout;
+    }
     const int lx = lane & 7, ly = lane >> 3;
     // the block record whole and unconditionally: one scalar load, issued with the mask
     // record's, instead of a load per neighbour index behind the tests below
@@ -473,7 +509,12 @@ __device__ __forceinline__ void step8z_group(const StepArgs &a, int grp)
         for (int s = 0; s < S; ++s) rc[s][z] = (R)0;
         if (lane_bit(Wo[z])) {
 #pragma unroll
-            for (int s = 0; s < S; ++s) rc[s][z] = ld_raw(cin, s * a.sstride + oi[z]);
+            for (int s = 0; s < S; ++s) {
+                if constexpr (CMP)  // a species base (scalar) plus a 32-bit byte offset
+                    rc[s][z] = ld_raw(at_byte(cinb[s], oi[z] * (uint32_t)sizeof(T)), 0);
+                else
+                    rc[s][z] = ld_raw(cin, s * a.sstride + oi[z]);
+            }
         }
     }
     // face halos, one value per lane and face: lane (u, v) = (lx, ly) reads the
@@ -519,7 +560,12 @@ __device__ __forceinline__ void step8z_group(const StepArgs &a, int grp)
         }
         if (lane_bit(need)) {
 #pragma unroll
-            for (int s = 0; s < S; ++s) rh[f][s] = ld_raw(cin, s * a.sstride + hb);
+            for (int s = 0; s < S; ++s) {
+                if constexpr (CMP)
+                    rh[f][s] = ld_raw(at_byte(cinb[s], (uint32_t)hb * (uint32_t)sizeof(T)), 0);
+                else
+                    rh[f][s] = ld_raw(cin, s * a.sstride + hb);
+            }
         }
     }
     // all loads are issued; convert to FP32
@@ -615,7 +661,12 @@ __device__ __forceinline__ void step8z_group(const StepArgs &a, int grp)
         // its 0 again); compact: the active voxels, a contiguous run
         if (lane_bit(CMP ? Wo[z] : sector_lanes<T>(Wo[z]))) {
 #pragma unroll
-            for (int s = 0; s < S; ++s) store_val_ct<T, CMP, DTH>(cout, s, s * a.sstride + oi[z], h, res[s]);
+            for (int s = 0; s < S; ++s) {
+                if constexpr (CMP)
+                    store_val_ct<T, CMP, DTH>(at_byte(coutb[s], oi[z] * (uint32_t)sizeof(T)), s, 0, h, res[s]);
+                else
+                    store_val_ct<T, CMP, DTH>(cout, s, s * a.sstride + oi[z], h, res[s]);
+            }
         }
     }
 }
