@@ -50,8 +50,8 @@ __device__ __forceinline__ void store_val(const StepArgs &a, T *cout, int s, int
 }
 // p advanced by a 32-bit byte offset: a wave-uniform base plus a zero-extended 32-bit
 // offset, the form of a global access with a scalar base and a 32-bit vector offset (no
-// 64-bit address arithmetic per access).  The compact layout's offsets fit: a species
-// buffer holds fewer than 2^30 values.
+// 64-bit address arithmetic per access).  The offsets fit: a compact species buffer holds
+// fewer than 2^30 values, and block-layout offsets stay inside one block's slab.
 template <typename T>
 __device__ __forceinline__ T *at_byte(T *p, uint32_t off)
 {
@@ -439,13 +439,15 @@ __device__ __forceinline__ void step8z_group(const StepArgs &a, int grp)
     }
     const T *cin = (const T *)a.cin;
     T *cout = (T *)a.cout;
-    // CMP: per-species bases of the fields (scalar)
+    // per-species bases in scalar registers: the species buffer (CMP) or the block's slab
+    // in it; every access below is a base plus a 32-bit byte offset
     const T *cinb[S];
     T *coutb[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        cinb[s] = CMP ? uniform_ptr(cin + s * a.sstride) : cin;
-        coutb[s] = CMP ? uniform_ptr(cout + s * a.sstride) : cout;
+        const int64_t o = s * a.sstride + (CMP ? 0 : (int64_t)b * 512);
+        cinb[s] = uniform_ptr(cin + o);
+        coutb[s] = uniform_ptr(cout + o);
     }
     const int lx = lane & 7, ly = lane >> 3;
     // the block record whole and unconditionally: one scalar load, issued with the mask
@@ -485,7 +487,7 @@ __device__ __forceinline__ void step8z_group(const StepArgs &a, int grp)
     for (int f = 0; f < 6; ++f) Wf[f] = rec[8 + f];
 
     // element index of the lane's voxel in plane z (valid where the voxel is active)
-    typename std::conditional<CMP, uint32_t, int64_t>::type oi[8];
+    uint32_t oi[8];  // from the species base (CMP) or the block's slab
     if constexpr (CMP) {
         uint32_t acc = a.cbase[b];
 #pragma unroll
@@ -495,7 +497,7 @@ __device__ __forceinline__ void step8z_group(const StepArgs &a, int grp)
         }
     } else {
 #pragma unroll
-        for (int z = 0; z < 8; ++z) oi[z] = (int64_t)b * 512 + z * 64 + lane;
+        for (int z = 0; z < 8; ++z) oi[z] = (uint32_t)(z * 64 + lane);
     }
 
     typedef typename RawOf<T>::type R;
@@ -509,12 +511,7 @@ __device__ __forceinline__ void step8z_group(const StepArgs &a, int grp)
         for (int s = 0; s < S; ++s) rc[s][z] = (R)0;
         if (lane_bit(Wo[z])) {
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
-                if constexpr (CMP)  // a species base (scalar) plus a 32-bit byte offset
-                    rc[s][z] = ld_raw(at_byte(cinb[s], oi[z] * (uint32_t)sizeof(T)), 0);
-                else
-                    rc[s][z] = ld_raw(cin, s * a.sstride + oi[z]);
-            }
+            for (int s = 0; s < S; ++s) rc[s][z] = ld_raw(at_byte(cinb[s], oi[z] * (uint32_t)sizeof(T)), 0);
         }
     }
     // face halos, one value per lane and face: lane (u, v) = (lx, ly) reads the
@@ -556,15 +553,13 @@ __device__ __forceinline__ void step8z_group(const StepArgs &a, int grp)
                 else hb = (int64_t)hyp + __popc(row & ((1u << lx) - 1u));
             }
         } else {
-            hb = (int64_t)nn * 512 + ns;
+            hb = ns;  // in the neighbour's slab
         }
         if (lane_bit(need)) {
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                if constexpr (CMP)
-                    rh[f][s] = ld_raw(at_byte(cinb[s], (uint32_t)hb * (uint32_t)sizeof(T)), 0);
-                else
-                    rh[f][s] = ld_raw(cin, s * a.sstride + hb);
+                const T *hbase = CMP ? cinb[s] : uniform_ptr(cin + s * a.sstride + (int64_t)nn * 512);
+                rh[f][s] = ld_raw(at_byte(hbase, (uint32_t)hb * (uint32_t)sizeof(T)), 0);
             }
         }
     }
@@ -661,12 +656,8 @@ __device__ __forceinline__ void step8z_group(const StepArgs &a, int grp)
         // its 0 again); compact: the active voxels, a contiguous run
         if (lane_bit(CMP ? Wo[z] : sector_lanes<T>(Wo[z]))) {
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
-                if constexpr (CMP)
-                    store_val_ct<T, CMP, DTH>(at_byte(coutb[s], oi[z] * (uint32_t)sizeof(T)), s, 0, h, res[s]);
-                else
-                    store_val_ct<T, CMP, DTH>(cout, s, s * a.sstride + oi[z], h, res[s]);
-            }
+            for (int s = 0; s < S; ++s)
+                store_val_ct<T, CMP, DTH>(at_byte(coutb[s], oi[z] * (uint32_t)sizeof(T)), s, 0, h, res[s]);
         }
     }
 }
