@@ -54,7 +54,9 @@ def parse():
     p.add_argument("--steady-axes", type=int, default=1,
                    help="ceramic-foam steady state: tortuosity along the first K axes (0: skip)")
     p.add_argument("--steady-size", type=int, default=1024, help="edge of the foam volume")
-    p.add_argument("--steady-forms", default="fp32,fp16,bf16", help="storage types of the steady form")
+    p.add_argument("--steady-forms", default="fp32,fp16", help="storage types of the steady form")
+    p.add_argument("--steady-crop-forms", default="fp32,fp16,bf16",
+                   help="storage types of the check on the foam's 256^3 crop against the stored oracle tau")
     p.add_argument("--steady-tol", type=float, default=1e-8)
     p.add_argument("--steady-max-iters", type=int, default=200000)
     p.add_argument("--cg-precond", type=int, default=6,
@@ -355,7 +357,7 @@ def fused_form(torch, rd, W, stream, fused=16, size=512):
     return out
 
 
-def steady_form(torch, rd, W, size, axes, forms, tol, stream, max_iters=200000, prec=6):
+def steady_form(torch, rd, W, size, axes, forms, tol, stream, max_iters=200000, prec=6, crop_forms=None):
     """Tortuosity of the ceramic-foam volume (solid matrix of overlapping pore spheres
     r ~ U(10, 30), pore fraction 0.15) along the first `axes` axes by conjugate
     gradients, per storage type; with the full 1024^3 volume, the same solves on its
@@ -396,7 +398,7 @@ def steady_form(torch, rd, W, size, axes, forms, tol, stream, max_iters=200000, 
             del sim
             torch.cuda.empty_cache()
     if crop is not None:
-        out["oracle_check"] = foam_crop_check(torch, rd, np, crop, forms, tol, stream, prec)
+        out["oracle_check"] = foam_crop_check(torch, rd, np, crop, crop_forms or forms, tol, stream, prec)
     return out
 
 
@@ -674,7 +676,8 @@ def main():
         if a.profile_form == "steady":
             rec = steady_form(torch, rd, W, a.steady_size, a.steady_axes,
                               [f for f in a.steady_forms.split(",") if f], a.steady_tol, stream,
-                              a.steady_max_iters, a.cg_precond)
+                              a.steady_max_iters, a.cg_precond,
+                              [f for f in a.steady_crop_forms.split(",") if f])
         elif a.profile_form == "batch":
             rec = batched_form(torch, rd, W, a.batch, a.batch_max_edge, stream, a.cg_precond)
         elif a.profile_form == "batch_steps":
@@ -847,7 +850,8 @@ def main():
     if a.steady_axes > 0 and not a.profile:
         out["forms"]["steady"] = steady_form(torch, rd, W, a.steady_size, a.steady_axes,
                                              [f for f in a.steady_forms.split(",") if f],
-                                             a.steady_tol, stream, prec=a.cg_precond)
+                                             a.steady_tol, stream, prec=a.cg_precond,
+                                             crop_forms=[f for f in a.steady_crop_forms.split(",") if f])
 
     if a.diffusivity_steps > 0 and not a.profile:
         out["forms"]["diffusivity"] = diffusivity_form(torch, rd, np, geom, img, w, n_active,
