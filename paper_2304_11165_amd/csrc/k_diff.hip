@@ -164,7 +164,10 @@ __global__ __launch_bounds__(256) void k_step8e(DiffArgs d)
     T *cout = (T *)a.cout;
     const int64_t base = (int64_t)b * 512;
     const int lx = lane & 7, ly = lane >> 3;
-    const int32_t *nbr = a.info[b].nbr;
+    // the block record whole and unconditionally: one scalar load instead of a load per
+    // neighbour index behind the tests below
+    const BlockInfo bi = a.info[b];
+    const int32_t *nbr = bi.nbr;
     // x neighbours inside this workgroup (wave-uniform; only with XCH)
     const bool xm_in = XCH && wv > 0 && nbr[0] == b - 1;
     const bool xp_in = XCH && wv < 3 && nbr[1] == b + 1;
@@ -249,7 +252,6 @@ __global__ __launch_bounds__(256) void k_step8e(DiffArgs d)
         if (xp_in) eh[1] = xch[wv + 1][0][S][ly * 8 + lx];
     }
 
-    const BlockInfo bi = a.info[b];
     int bx, by, bz, gid;
     block_pos(bi, &bx, &by, &bz, &gid);
     const GeomInfo g = a.geom[gid];
