@@ -642,7 +642,8 @@ __global__ __launch_bounds__(256) void k_cg_pupdate(CgArgs a)
 // [block0_g, block0_{g+1}); one workgroup per geometry, fixed summation order.
 // dst[g*CG_NSCAL + slot0 + k] = sum (k = 0, 1; slot < 0 skips that lane); then, for a
 // live geometry, the scalar recurrence `mode`: 0 alpha = rr / pAp; 1 beta = rr_new / rr,
-// rr = rr_new; 2 rr = rr_new (start); -1 none.
+// rr = rr_new; 2 rr = rr_new (start); -1 none; -2 none, and only geometries whose CG_REPL
+// slot is set are written.
 __global__ __launch_bounds__(256) void k_cg_segsum(const double *part, const GeomInfo *geom,
                                                    int ngeom, int nb, double *scal, int slot0,
                                                    int slot1, int mode)
@@ -685,6 +686,7 @@ __global__ __launch_bounds__(256) void k_cg_segsum(const double *part, const Geo
     }
     if (threadIdx.x == 0) {
         double *s = scal + g * CG_NSCAL;
+        if (mode == -2 && s[CG_REPL] == 0.0) return;  // only the geometries just replaced
         if (slot0 >= 0) s[slot0] = sh[0][0];
         if (slot1 >= 0) s[slot1] = sh[1][0];
         // then the scalar recurrence of this geometry (live ones only)
@@ -944,8 +946,10 @@ __device__ __forceinline__ void ir_pos(const BlockInfo *info, const GeomInfo *ge
 // storage type becomes the CG residual and direction (r and p; 0 off the free voxels);
 // store 2: sigma r replaces the residual (residual replacement) and p is rescaled from
 // sigma_prev to sigma (powers of 2: exact), so that 16-bit vectors stay in range as the
-// residual shrinks; store 3: r and p are only rescaled.  With store 2 or 3 the first
-// partial is that of the stored r.
+// residual shrinks; store 3: r and p are only rescaled.  With store 2 or 3 each geometry
+// takes its own choice from its CG_REPL slot (2, 3, or 0: untouched, partials 0), so a
+// batch replaces only the residuals of the geometries that need it.  With store 2 or 3 the
+// first partial is that of the stored r.
 template <typename T, int B>
 __global__ __launch_bounds__(256) void k_res64(CgArgs a, int store)
 {
@@ -957,12 +961,15 @@ __global__ __launch_bounds__(256) void k_res64(CgArgs a, int store)
     if (b < a.nb) {
         int bx, by, bz, gid;
         block_pos(a.info[b], &bx, &by, &bz, &gid);
-        const double sig = store >= 2 ? a.scal[gid * CG_NSCAL + CG_SIGMA] : 1.0;
-        const float pscale = store >= 2 ? (float)(sig / a.scal[gid * CG_NSCAL + CG_SIGMA_PREV]) : 1.0f;
-        for (int k = 0; k < C::VPT; ++k) {
+        // store >= 2: each geometry's own choice (CG_REPL: 2 replace, 3 rescale, 0 none)
+        const int st = store >= 2 ? (int)a.scal[gid * CG_NSCAL + CG_REPL] : store;
+        const double sig = st >= 2 ? a.scal[gid * CG_NSCAL + CG_SIGMA] : 1.0;
+        const float pscale = st >= 2 ? (float)(sig / a.scal[gid * CG_NSCAL + CG_SIGMA_PREV]) : 1.0f;
+        const bool untouched = store >= 2 && st == 0;
+        for (int k = 0; k < (untouched ? 0 : C::VPT); ++k) {
             const int64_t i = (int64_t)b * NS + lt + k * C::TPB;
             const unsigned cd = a.code[i];
-            if (store == 3) {  // rescale only
+            if (st == 3) {  // rescale only
                 const float rs = rd_round<T>(pscale * rd_ld((const T *)a.r, i));
                 rr += (double)rs * (double)rs;
                 rd_st_keep((T *)a.r, i, rs);
@@ -987,7 +994,7 @@ __global__ __launch_bounds__(256) void k_res64(CgArgs a, int store)
                         if (on_dirichlet(a.dir, gx + ex, gy + ey, gz + ez, g.nx, g.ny, g.nz)) bp += xq;
                     }
                     out = (float)(sig * s);
-                    if (store == 2) {
+                    if (st == 2) {
                         const double rs = (double)rd_round<T>(out);
                         rr += rs * rs;
                     } else {
@@ -996,9 +1003,9 @@ __global__ __launch_bounds__(256) void k_res64(CgArgs a, int store)
                     bb += bp * bp;
                 }
             }
-            if (store == 1 || store == 2) rd_st_keep((T *)a.r, i, out);
-            if (store == 1) rd_st_keep((T *)a.p, i, out);
-            if (store == 2 && pscale != 1.0f) rd_st_keep((T *)a.p, i, pscale * rd_ld((const T *)a.p, i));
+            if (st == 1 || st == 2) rd_st_keep((T *)a.r, i, out);
+            if (st == 1) rd_st_keep((T *)a.p, i, out);
+            if (st == 2 && pscale != 1.0f) rd_st_keep((T *)a.p, i, pscale * rd_ld((const T *)a.p, i));
         }
     }
     block_sum2<B>(rr, bb, a.partial, b, b < a.nb);

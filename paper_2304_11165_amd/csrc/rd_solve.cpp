@@ -208,7 +208,7 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
         } else {
             if ((s = cg_segment(a, storage, B, st, check_every)) != RD_OK) return s;
         }
-        bool replace = false, rescale = false;
+        bool any = false;  // a geometry replaces or rescales its residual (CG_REPL)
         // true residual b - A x in FP64 (the recursive one drifts in the storage type's
         // precision); once the recursive residual has drifted from it, it replaces it
         // (residual replacement, van der Vorst and Ye 2000), so the iteration is not held
@@ -221,6 +221,7 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
         if ((s = copy_scal(a, hs, st)) != RD_OK) return s;
         for (int g = 0; g < n; ++g) {
             double *v = &hs[(size_t)g * CG_NSCAL];
+            v[CG_REPL] = 0.0;
             if (v[CG_DONE] != 0.0) continue;
             out[g].iters += check_every;
             const double rel = sqrt(std::max(0.0, v[CG_CHECK]) / v[CG_BB]);
@@ -250,21 +251,23 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
                 // grows: every replacement costs the recursion some of its conjugacy)
                 const double rec = sqrt(std::max(v[CG_RRREC], 0.0)) / v[CG_SIGMA];
                 const double tru = sqrt(std::max(v[CG_CHECK], 0.0));
-                replace = replace || fabs(rec - tru) > 0.25 * tru;
-                rescale = rescale || sig != v[CG_SIGMA];
+                const bool replace = fabs(rec - tru) > 0.25 * tru, rescale = sig != v[CG_SIGMA];
+                v[CG_REPL] = replace ? 2.0 : rescale ? 3.0 : 0.0;  // this geometry's own choice
+                any = any || replace || rescale;
                 v[CG_SIGMA_PREV] = v[CG_SIGMA];  // what r and p hold until the kernel below
                 v[CG_SIGMA] = sig;
             }
         }
         if ((s = push_scal(a, hs, st)) != RD_OK) return s;
-        if (live > 0 && (replace || rescale)) {
-            // residual replacement: r = sigma (b - A X) in FP64 and p rescaled, or only
-            // the rescaling of r and p; then rr of the stored r
-            LAUNCHCHK(cg_launch_res64(storage, B, a, replace ? 2 : 3, st));
-            LAUNCHCHK(cg_launch_segsum(a, CG_RR, -1, -1, st));
+        if (live > 0 && any) {
+            // per geometry (CG_REPL): residual replacement, r = sigma (b - A X) in FP64 and
+            // p rescaled, or only the rescaling of r and p; then rr of the stored r; the
+            // other geometries of a batch keep their vectors and scalars
+            LAUNCHCHK(cg_launch_res64(storage, B, a, 2, st));
+            LAUNCHCHK(cg_launch_segsum(a, CG_RR, -1, -2, st));
             if (a.prec > 0) {  // and z = M^-1 r of the new r; CG_RR = r.z
                 LAUNCHCHK(cg_launch_prec(storage, a, st));
-                LAUNCHCHK(cg_launch_segsum(a, CG_RR, CG_RRREC, -1, st));
+                LAUNCHCHK(cg_launch_segsum(a, CG_RR, CG_RRREC, -2, st));
             }
         }
     }

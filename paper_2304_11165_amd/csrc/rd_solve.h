@@ -21,7 +21,8 @@ enum {
     CG_SIGMA_PREV = 11,  // the scale r and p hold before a pending rescaling (powers of 2)
     CG_RRREC = 12,       // r.r of the recursive residual (CG_RR / CG_RRNEW hold r.z: with the
                          // preconditioner z = M^-1 r, without it z = r)
-    CG_NSCAL = 13
+    CG_REPL = 13,        // at a check: 2 replace the residual, 3 only rescale, 0 leave it
+    CG_NSCAL = 14
 };
 
 struct CgArgs {

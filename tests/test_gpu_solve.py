@@ -130,6 +130,24 @@ def test_precond_setting_checked(rd):
             s.set_cg_precond(bad)
 
 
+@pytest.mark.parametrize("steps", [0, 2])
+def test_batch_precond_setting_matches_single(rd, steps):
+    """A batch run with a given preconditioner setting gives each geometry the bits of its
+    single-geometry run with the same setting (plain CG and 2 Jacobi steps)."""
+    imgs = [W.boolean_spheres(n, 0.55, 2.0, 4.0, seed=40 + n)[0] for n in (19, 26, 13)]
+    bt = rd.Batch([rd.Geometry(im, None, 1.0, 8) for im in imgs]).bind()
+    bt.set_cg_precond(steps)
+    tau, rel, it = bt.tortuosity(0, 1e-8, 20000)
+    for i, im in enumerate(imgs):
+        g, s = make_gpu(rd, im, [1.0], features=rd.RD_WS_SOLVER)
+        s.set_cg_precond(steps)
+        res = s.steady_state(0, 1e-8, 20000)
+        assert res["converged"] and rel[i] <= 1e-8
+        assert tau[i] == res["tau"] and it[i] == res["iters"]
+    with pytest.raises(rd.RDError, match="ARG"):
+        bt.set_cg_precond(17)
+
+
 def test_batch_matches_single_and_oracle(rd, oracle_mod):
     imgs = []
     for i, n in enumerate([17, 24, 9, 31, 20]):
