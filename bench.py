@@ -54,7 +54,7 @@ def parse():
     p.add_argument("--steady-axes", type=int, default=1,
                    help="ceramic-foam steady state: tortuosity along the first K axes (0: skip)")
     p.add_argument("--steady-size", type=int, default=1024, help="edge of the foam volume")
-    p.add_argument("--steady-forms", default="fp32,fp16", help="storage types of the steady form")
+    p.add_argument("--steady-forms", default="fp32,fp16,bf16", help="storage types of the steady form")
     p.add_argument("--steady-crop-forms", default="fp32,fp16,bf16",
                    help="storage types of the check on the foam's 256^3 crop against the stored oracle tau")
     p.add_argument("--steady-tol", type=float, default=1e-8)
