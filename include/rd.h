@@ -366,7 +366,7 @@ rd_status rd_sim_plane_flux(rd_sim *sim, int species, int axis, int64_t i0, doub
  * only the inlet, 0 on the rest (clusters labelled on the GPU).  The iterate is kept in
  * FP64; every 25 iterations the FP64 residual b - A x is evaluated (rel_residual is its
  * norm over ||b||) and replaces the recursive residual when the two have drifted apart
- * (with BF16 vectors a replacement also restarts the search direction), so 1e-8 is
+ * (with 16-bit vectors a replacement also restarts the search direction), so 1e-8 is
  * reachable with FP32, BF16 or FP16 vectors.  Stops at rel. residual <=
  * rel_tol (RD_OK), or at stagnation (no 10% decrease of the best residual over 40
  * checks, i.e. 1000 iterations: CG's residual is not monotone and plateaus for

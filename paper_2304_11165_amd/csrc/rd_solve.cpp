@@ -253,9 +253,10 @@ rd_status run_cg(const CgArgs &args, int storage, int B, hipStream_t st, int axi
                 const double tru = sqrt(std::max(v[CG_CHECK], 0.0));
                 const bool replace = fabs(rec - tru) > 0.25 * tru, rescale = sig != v[CG_SIGMA];
                 v[CG_REPL] = replace ? 2.0 : rescale ? 3.0 : 0.0;  // this geometry's own choice
-                // BF16 vectors (8-bit mantissa) lose the directions' conjugacy over long
-                // runs: a replacement restarts the direction (beta = 0: p = z next)
-                if (replace && storage == RD_BF16) v[CG_BETA] = 0.0;
+                // 16-bit vectors lose the directions' conjugacy over long runs (BF16 stalled
+                // near 7.5e-7 on the 1024^3 foam without this): a replacement restarts the
+                // direction (beta = 0: p = z next)
+                if (replace && storage != RD_FP32) v[CG_BETA] = 0.0;
                 any = any || replace || rescale;
                 v[CG_SIGMA_PREV] = v[CG_SIGMA];  // what r and p hold until the kernel below
                 v[CG_SIGMA] = sig;
