@@ -119,7 +119,7 @@ def load_traffic(path, kernel, workload, xcd_map):
         if rec.get("source_hash") == source_hash() and rec.get("kernel") == kernel and \
                 rec.get("workload") == workload and rec.get("xcd_map") == int(xcd_map):
             return rec.get("hbm_bytes_per_launch")
-    log(f"no traffic record in {path} for this build, kernel {kernel}, block order {int(xcd_map)} "
+    log(f"no traffic record in {path} for these sources, kernel {kernel}, block order {int(xcd_map)} "
         f"and workload: traffic = null")
     return None
 
@@ -658,7 +658,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the sparse-block stepper is "
-              "not sharded across GPUs in this build", file=sys.stderr)
+              "not sharded across GPUs: the library runs on one GPU", file=sys.stderr)
         sys.exit(2)
     if a.copy_calibration:
         copy_calibration()

@@ -234,7 +234,7 @@ rd_status rd_sim_set_kernel(rd_sim *sim, int kernel, int wg_per_cu);
  * voxel's increment before the final addition c + increment is rounded to nearest
  * (constant-D kernels; with a diffusivity factor FP32 stays round-to-nearest).  Results
  * stay deterministic for a given seed and identical across kernels and layouts.
- * Storage precision is this build's addition; the paper computes in FP32 throughout
+ * Storage precision is an addition of this library; the paper computes in FP32 throughout
  * (section "Parallel implementation using OpenFPM"). */
 rd_status rd_sim_set_rounding(rd_sim *sim, int stochastic, uint64_t seed);
 /* Device bytes the caller must provide to rd_sim_bind for the given features
